@@ -1,0 +1,103 @@
+"""Seeded synthetic inputs shared by the oracle and the GPU library.
+
+This module draws random numbers and nothing else: it holds none of the
+method's arithmetic (no lattice, no Hamiltonian, no recursion).  Both sides
+of every parity test receive the arrays produced here, so that the two
+implementations see bit-identical inputs.
+
+Generator: SplitMix64 (Steele, Lea, Flood, "Fast splittable pseudorandom
+number generators", OOPSLA 2014), used in counter mode: the k-th draw of a
+stream with seed s is mix(s + (k + 1) * 0x9E3779B97F4A7C15).  The top 53 bits
+of a draw give a uniform double in [0, 1).
+
+Site index convention shared with both lattice builders: site (i, j) with
+i in [0, nx) along the zigzag chains and j in [0, ny) across them has index
+n = j * nx + i.
+
+Seed recipe for the standard workloads: on-site disorder 1000 + sample,
+vacancies 2000 + sample, random vectors 3000 + vector index.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed: int, count: int, offset: int = 0) -> np.ndarray:
+    """Draws offset .. offset+count-1 of the SplitMix64 stream ``seed`` (uint64)."""
+    k = np.arange(offset + 1, offset + count + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + k * _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform(seed: int, count: int, offset: int = 0) -> np.ndarray:
+    """Uniform doubles in [0, 1) with 53 random bits each."""
+    return (splitmix64(seed, count, offset) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def anderson_onsite(n_sites: int, w_ev: float, seed: int) -> np.ndarray:
+    """On-site energies uniform in [-W/2, W/2) eV, one per site index (float64)."""
+    if w_ev == 0.0:
+        return np.zeros(n_sites, dtype=np.float64)
+    return w_ev * (uniform(seed, n_sites) - 0.5)
+
+
+def vacancy_mask(n_sites: int, fraction: float, seed: int) -> np.ndarray:
+    """Active-site mask (uint8, 0 = vacancy) with exactly round(fraction*N) vacancies.
+
+    The vacancies are a uniform draw without replacement: the sites holding the
+    N_v smallest keys of an i.i.d. uniform key per site (ties broken by index).
+    """
+    n_vac = int(round(fraction * n_sites))
+    active = np.ones(n_sites, dtype=np.uint8)
+    if n_vac <= 0:
+        return active
+    if n_vac > n_sites:
+        raise ValueError("vacancy fraction above 1")
+    keys = splitmix64(seed, n_sites)
+    order = np.argsort(keys, kind="stable")
+    active[order[:n_vac]] = 0
+    return active
+
+
+def random_phase(n_sites: int, n_vec: int, seeds, active=None) -> np.ndarray:
+    """Random-phase vectors exp(i*theta), theta uniform in [0, 2*pi).
+
+    Returns complex128 of shape [n_sites, n_vec] (vector index fastest), zero
+    on inactive sites, so <phi|phi> equals the number of active sites.
+    ``seeds`` is an int (vector r uses seed + r) or a sequence of n_vec seeds.
+    """
+    if np.isscalar(seeds):
+        seeds = [int(seeds) + r for r in range(n_vec)]
+    if len(seeds) != n_vec:
+        raise ValueError("one seed per vector required")
+    out = np.empty((n_sites, n_vec), dtype=np.complex128)
+    for r, s in enumerate(seeds):
+        theta = 2.0 * np.pi * uniform(int(s), n_sites)
+        out[:, r] = np.cos(theta) + 1j * np.sin(theta)
+    if active is not None:
+        out[np.asarray(active) == 0, :] = 0.0
+    return out
+
+
+def sheet_config(name: str) -> dict:
+    """Parameters of the named synthetic workloads (sizes in sites, energies in eV)."""
+    hbar = 0.6582119569  # eV fs
+    if name == "small":
+        # 32x32 two-atom cells = 64x32 sites, W = 1 eV, no vacancies.
+        return dict(geometry="sheet", nx=64, ny=32, t=-2.7, w=1.0, vac=0.0,
+                    e_scale=1.01 * (3 * 2.7 + 0.5), n_moments=500, n_steps=10,
+                    dt_fs=hbar / 2.7, n_bessel=30, n_vec=1)
+    if name == "paper":
+        # 1414x1414 two-atom cells = 2828x1414 sites, 0.5 % vacancies, W = 0.1 eV.
+        return dict(geometry="sheet", nx=2828, ny=1414, t=-2.7, w=0.1, vac=0.005,
+                    e_scale=1.01 * (3 * 2.7 + 0.05), n_moments=3000, n_steps=20,
+                    dt_fs=hbar / 2.7, n_bessel=40, n_vec=1)
+    raise KeyError(name)
