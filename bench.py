@@ -1,0 +1,170 @@
+#!/usr/bin/env python3
+"""Benchmark of the Chebyshev hot path on one MI355X.
+
+One step = one full pass of the plain FP64 path over the paper-scale sheet:
+periodic graphene of 2828 x 1414 sites (3,998,792 rows; 0.5 % vacancies,
+Anderson disorder W = 0.1 eV), one random-phase vector,
+  * DOS moments: 3000 Chebyshev moments,
+  * VAC: 20 time steps (21 time points) of U(-dt) with 40 Bessel terms on two
+    states plus 3000 moments per time point,
+  * MSD: 20 time steps of the coupled [X, U(dt)] recursion and U(dt) with 40
+    Bessel terms plus 3000 moments per time point,
+dt = hbar/|t|.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line: whole-step throughput in Gsite-updates/s, the roofline
+of the dominant kernel (the fused moment step) from HIP events recorded by
+the library on its stream, and the oracle's CPU rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import kpm_inputs as ki  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_SITE_UPDATE_FP64 = 84      # 4 state accesses x 16 B + 12 B index + 8 B on-site
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "moment_step_fp64_paper_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1307_0288_amd", "csrc", "kpm_kernels.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_sha() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(step_rows: int):
+    """HBM bytes per moment-step launch from committed rocprofv3 counters,
+    or None when they are absent or were taken on another kernel version."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_sha() or t.get("step_rows") != step_rows:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(p, lat_args, n_moments: int):
+    """The oracle's moment recursion on a bounded sample of the same sheet."""
+    import oracle
+    c_ons, c_act = lat_args
+    lat = oracle.graphene(p["nx"], p["ny"], "sheet", p["t"], c_ons, c_act)
+    phi = ki.random_phase(lat.n, 1, 3000, c_act)[:, 0]
+    t0 = time.perf_counter()
+    oracle.moments(lat, p["e_scale"], phi, phi, n_moments)
+    dt = time.perf_counter() - t0
+    ups = (n_moments - 1) * lat.n
+    return {"value": round(ups / dt / 1e9, 5), "unit": "Gsite-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{n_moments} Chebyshev moments (phi_2 = 2H~phi_1 - phi_0 plus the "
+                      f"inner product) on the full {lat.n}-site sheet, one vector, "
+                      f"serial complex128 C, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-moments", type=int, default=800,
+                    help="moments in the oracle's CPU-baseline sample (0 skips it)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1307_0288_amd as kp
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    p = ki.sheet_config("paper")
+    n = p["nx"] * p["ny"]
+    log(f"inputs: {p['nx']}x{p['ny']} sheet, {n} sites")
+    act = ki.vacancy_mask(n, p["vac"], 2000)
+    ons = ki.anderson_onsite(n, p["w"], 1000)
+    phi_h = ki.random_phase(n, 1, 3000, act)
+    sysg = kp.graphene_system(p["nx"], p["ny"], "sheet", p["t"], ons, act, p["e_scale"], "fp64")
+    phi = sysg.upload(phi_h)
+    nm, ns, nb, dt = p["n_moments"], p["n_steps"], p["n_bessel"], p["dt_fs"]
+
+    def step():
+        kp.kpm_moments(sysg, phi, phi, nm)
+        kp.kpm_vac(sysg, phi, ns, dt, nb, nm)
+        kp.kpm_msd(sysg, phi, ns, dt, nb, nm)
+
+    for w in range(args.warmup):
+        step()
+        log(f"warmup {w + 1}/{args.warmup} done")
+    kp.kpm_reset_stats(sysg)
+    kp.kpm_set_timing(sysg, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step()
+        log(f"step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = kp.kpm_get_stats(sysg)
+    kp.kpm_set_timing(sysg, False)
+
+    value = st["site_updates"] / elapsed / 1e9
+    launch_ms = st["step_ms"] / max(st["step_launches"], 1)
+    bytes_launch = BYTES_PER_SITE_UPDATE_FP64 * st["step_rows"]
+    achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
+    traffic = measured_traffic(st["step_rows"])
+
+    cpu = None
+    if args.cpu_moments > 0:
+        log(f"cpu baseline: oracle, {args.cpu_moments} moments")
+        cpu = cpu_baseline(p, (ons, act), args.cpu_moments)
+
+    out = {
+        "metric": "Gsite-updates/s (plain FP64 Chebyshev hot path: DOS + VAC + MSD)",
+        "value": round(value, 4),
+        "unit": "Gsite-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "graphene sheet 2828x1414 sites (3998792), 0.5% vacancies, "
+                               "W=0.1 eV, 1 random-phase vector, 3000 moments, VAC+MSD 20 steps "
+                               "x 40 Bessel terms, dt=hbar/|t|",
+                   "n_sites": n, "n_vec": 1, "n_moments": nm, "n_steps": ns,
+                   "n_bessel": nb, "site_updates_per_step": st["site_updates"] // args.steps},
+        "roofline": {"kernel": "k_moment_step<double2,false>", "bound": "hbm",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "bytes_per_site_update": BYTES_PER_SITE_UPDATE_FP64,
+                     "avg_launch_us": round(launch_ms * 1e3, 3),
+                     "launches": st["step_launches"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,228 @@
+/*
+ * kpm.h -- C ABI of the MI355X library for linear-scaling Kubo-Greenwood
+ * transport (Fan, Uppstu, Siro, Harju, "Efficient linear-scaling quantum
+ * transport calculations on graphics processing units and applications on
+ * electron transport in graphene").
+ *
+ * The library runs the Chebyshev recursion of a sparse tight-binding
+ * Hamiltonian on complex state vectors in three forms -- Chebyshev moments
+ * (Eq. 46), Chebyshev-Bessel time evolution (Eq. 36) and the commutator
+ * propagator (Eq. 37, recursion Eq. 38-41) -- and the two time loops built
+ * from them: the velocity auto-correlation (Alg. 2, Eq. 42-43) and the mean
+ * square displacement (Alg. 3, Eq. 44).  It also performs the host-side
+ * reconstruction (Jackson damping Eq. 35, KPM sums Eq. 29-31, running
+ * conductivities Eq. 6, 9, 11).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units: energies eV, times fs, lengths nm, hbar = 0.6582119569 eV fs.
+ * Scaling: H~ = H / e_scale; e_scale must bound the spectrum (the library
+ *   checks e_scale >= the Gershgorin bound).  No shift is applied.
+ * States: device memory, complex numbers stored as (re, im) pairs,
+ *   layout [n_sites][n_vec] with the vector index fastest; element type
+ *   double for KPM_FP64 systems and float for KPM_FP32_STATES systems.
+ *   n_vec must be 1, 2, 4, 8, 16, 32 or 64.  States must be zero on removed
+ *   (inactive) sites; the library keeps them zero there.
+ * Streams: every call enqueues its work on the system's HIP stream.  Calls
+ *   that return host results synchronise that stream before returning.
+ * Errors: every call returns a kpm_status; kpm_last_error() gives a message
+ *   for the last failing call on the calling thread.  No exception crosses
+ *   the ABI.  On error the output buffers are unspecified.
+ * Threads: one system may be used by one host thread at a time.
+ */
+#ifndef KPM_H
+#define KPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KPM_OK = 0,
+    KPM_ERR_INVALID = 1,     /* bad argument, descriptor or size            */
+    KPM_ERR_OOM = 2,         /* device or host allocation failed            */
+    KPM_ERR_DEVICE = 3,      /* HIP runtime error                           */
+    KPM_ERR_UNSUPPORTED = 4, /* valid request this build does not support   */
+    KPM_ERR_NUMERIC = 5      /* non-finite moments                          */
+} kpm_status;
+
+typedef enum {
+    KPM_FP64 = 0,            /* states and arithmetic in double            */
+    KPM_FP32_STATES = 1      /* states stored as float; recursion arithmetic,
+                                inner products and moments in double       */
+} kpm_precision;
+
+enum { KPM_MAX_WIDTH = 4 };
+
+/* Lattice geometries of the paper's samples (Sec. 2). */
+typedef enum {
+    KPM_SHEET = 0,  /* periodic in x and y, transport along x (zigzag)      */
+    KPM_ZGNR = 1,   /* periodic in x, open in y, transport along x          */
+    KPM_AGNR = 2    /* open in x, periodic in y, transport along y          */
+} kpm_geometry;
+
+typedef struct kpm_system kpm_system;
+
+/*
+ * Sparse Hamiltonian in neighbour-list (ELL) form, the data structure of
+ * Alg. 8: slot k of row n holds the k-th neighbour of site n; arrays are
+ * slot-major ([width][n_sites], index k * n_sites + n) so that consecutive
+ * rows read consecutive memory.  All arrays are host memory owned by the
+ * caller and copied by kpm_system_create.
+ *   n_sites    number of rows N (removed sites included), 1 <= N < 2^31.
+ *   width      slots per row, 1..KPM_MAX_WIDTH (3 for graphene).
+ *   nbr        [width][N] neighbour index m, or -1 for an empty slot.
+ *   hop        [width][N] H_nm in eV, or NULL: every filled slot is t_uniform.
+ *   t_uniform  hopping in eV used when hop is NULL (-2.7 in the paper, Eq. 13).
+ *   onsite     [N] diagonal H_nn in eV, or NULL for zero.
+ *   dx         [width][N] X_n - X_m in nm along the transport axis for the
+ *              bond in that slot (minimum image under periodic boundaries),
+ *              or NULL; the velocity operator V = (i/hbar)[H, X] (Eq. 15)
+ *              needs it, so kpm_vac, kpm_msd and kpm_evolve_x reject a
+ *              system built without it.
+ *   active     [N] 0 marks a removed site (vacancy, Sec. 2), or NULL.
+ *              Removed sites get no bonds and zero on-site energy.
+ *   e_scale    E_s in eV (see Conventions).
+ * Validation: indices in range, H real symmetric (each bond listed from both
+ * ends with equal hopping), dx antisymmetric, e_scale >= Gershgorin bound.
+ */
+typedef struct {
+    int64_t n_sites;
+    int32_t width;
+    const int32_t *nbr;
+    const double *hop;
+    double t_uniform;
+    const double *onsite;
+    const double *dx;
+    const uint8_t *active;
+    double e_scale;
+} kpm_system_desc;
+
+/*
+ * Nearest-neighbour graphene lattice (Sec. 2, Eq. 13-15) in the descriptor's
+ * layout, built on the host.  Site (i, j), i < nx along the zigzag chains,
+ * j < ny across them, has index j*nx + i and sits at x = i sqrt(3) a / 2,
+ * y = 3 j a / 2 + (a/2 if i + j is odd), a = 0.142 nm.  Slots: 0 = (i-1, j),
+ * 1 = (i+1, j), 2 = (i, j+1) if i + j is odd else (i, j-1).  Periodic
+ * directions need an even size (nx >= 4, ny >= 2).
+ *   nbr  [3][nx*ny] output (caller-allocated host memory), -1 = no bond.
+ *   dx   [3][nx*ny] output, X_n - X_m (nm) along the transport axis, or NULL.
+ *   active  [nx*ny] or NULL; bonds to removed sites are left empty.
+ */
+kpm_status kpm_build_graphene(int64_t nx, int64_t ny, kpm_geometry geometry,
+                              const uint8_t *active, int32_t *nbr, double *dx);
+
+/*
+ * Create a system on `device` whose work runs on `hip_stream` (a
+ * hipStream_t, or NULL for the default stream).  Copies the descriptor
+ * arrays to device memory; the system owns them and all recursion scratch.
+ */
+kpm_status kpm_system_create(const kpm_system_desc *desc, kpm_precision precision,
+                             int device, void *hip_stream, kpm_system **out);
+kpm_status kpm_system_destroy(kpm_system *sys);
+kpm_status kpm_system_set_stream(kpm_system *sys, void *hip_stream);
+/* n_sites of the system (rows of every state buffer). */
+int64_t kpm_system_n_sites(const kpm_system *sys);
+
+/*
+ * Chebyshev moments C_m = <phi_L| T_m(H~) |phi_R>, m = 0 .. n_moments-1, for
+ * each of the n_vec vector pairs (Eq. 46, Alg. 5).  phi_l, phi_r: device
+ * states (may be the same buffer).  mu: host output [n_vec][n_moments][2]
+ * (re, im).  n_moments >= 1.  Synchronises the stream.
+ */
+kpm_status kpm_moments(kpm_system *sys, int n_vec, const void *phi_l,
+                       const void *phi_r, int n_moments, double *mu);
+
+/*
+ * phi <- U(sign * dt) phi, U(t) = exp(-i H t / hbar), by the Chebyshev-Bessel
+ * expansion with n_bessel terms (Eq. 36, Alg. 6); sign = +1 or -1 (U(-dt) =
+ * U(dt)^dagger).  phi: device state, in place.  n_bessel >= 2.  Asynchronous.
+ */
+kpm_status kpm_evolve(kpm_system *sys, int n_vec, void *phi, double dt_fs,
+                      int sign, int n_bessel);
+
+/*
+ * out_x <- [X, U(dt)] phi (Eq. 37 with the recursion Eq. 38-41, Alg. 7) and,
+ * if out_u is not NULL, out_u <- U(dt) phi from the same recursion.  Device
+ * states; out_x and out_u must not alias phi or each other.  Asynchronous.
+ */
+kpm_status kpm_evolve_x(kpm_system *sys, int n_vec, const void *phi, void *out_x,
+                        void *out_u, double dt_fs, int n_bessel);
+
+/*
+ * Velocity auto-correlation moments (Alg. 2, Eq. 32 and 42-43):
+ * out[r][k][m] = Re <V U^dagger(t_k) phi_r| T_m(H~) |U^dagger(t_k) V phi_r>
+ * for t_k = k dt, k = 0 .. n_steps, with V = (i/hbar)[H, X].  Units nm^2/fs^2.
+ * phi: device states (unchanged).  out: host [n_vec][n_steps+1][n_moments].
+ * Synchronises the stream.
+ */
+kpm_status kpm_vac(kpm_system *sys, int n_vec, const void *phi, int n_steps,
+                   double dt_fs, int n_bessel, int n_moments, double *out);
+
+/*
+ * Mean-square-displacement moments (Alg. 3, Eq. 33 and 44):
+ * out[r][k][m] = Re <[X, U(t_k)] phi_r| T_m(H~) |[X, U(t_k)] phi_r>, t_k = k dt,
+ * k = 0 .. n_steps ([X, U(0)] = 0 gives zeros at k = 0).  Units nm^2.
+ * phi: device states (unchanged).  out: host [n_vec][n_steps+1][n_moments].
+ * Synchronises the stream.
+ */
+kpm_status kpm_msd(kpm_system *sys, int n_vec, const void *phi, int n_steps,
+                   double dt_fs, int n_bessel, int n_moments, double *out);
+
+/*
+ * KPM sum (Eq. 29-31) on the device:
+ * out[t][k] = 2 / (pi Omega E_s sqrt(1 - e_k^2)) sum_m g_m (2 - delta_m0)
+ *             T_m(e_k) moments[t][m],  e_k = energies[k] / E_s,
+ * with g_m the Jackson factors (Eq. 35) when jackson != 0, else 1.
+ * moments: host [n_rows][n_moments] (real parts); energies: host
+ * [n_energies] eV, |E| < E_s; out: host [n_rows][n_energies].
+ * Runs on `hip_stream` and synchronises it.
+ */
+kpm_status kpm_kpm_sum(int n_rows, int n_moments, const double *moments,
+                       int n_energies, const double *energies, double e_scale,
+                       double area_nm2, int jackson, void *hip_stream, double *out);
+
+/*
+ * Running electrical conductivities in units of e^2/h on the host, from
+ * rows sampled at t_k = k dt (k = 0 .. n_times-1), each of n_energies:
+ *  kpm_sigma_gk: from rho*C_vv (Eq. 6): 2 pi hbar * cumulative trapezoid.
+ *  kpm_sigma_e1: from rho*MSD (Eq. 9): pi hbar * d/dt, centred differences
+ *                (one-sided at both ends).
+ *  kpm_sigma_e2: from rho*MSD (Eq. 11): pi hbar * value / t, 0 at t = 0.
+ * in/out: host [n_times][n_energies]; out may not alias in.
+ */
+kpm_status kpm_sigma_gk(int n_times, int n_energies, const double *rho_vac,
+                        double dt_fs, double *out);
+kpm_status kpm_sigma_e1(int n_times, int n_energies, const double *rho_msd,
+                        double dt_fs, double *out);
+kpm_status kpm_sigma_e2(int n_times, int n_energies, const double *rho_msd,
+                        double dt_fs, double *out);
+
+/*
+ * Timing of the hot recursion kernel.  When enabled, the library brackets
+ * every uninterrupted run of Chebyshev moment steps with HIP events on the
+ * system's stream and accumulates their elapsed time and launch count.
+ */
+typedef struct {
+    double step_ms;           /* summed event time of moment-step runs      */
+    int64_t step_launches;    /* moment-step kernel launches in those runs  */
+    int64_t step_rows;        /* rows x vectors per launch (last run)       */
+    int64_t site_updates;     /* all recursion site-updates issued          */
+} kpm_stats;
+
+kpm_status kpm_set_timing(kpm_system *sys, int enable);
+kpm_status kpm_get_stats(kpm_system *sys, kpm_stats *out);
+kpm_status kpm_reset_stats(kpm_system *sys);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *kpm_last_error(void);
+/* Library version string. */
+const char *kpm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KPM_H */

@@ -1,0 +1,19 @@
+"""MI355X library for the Chebyshev hot path of linear-scaling Kubo-Greenwood
+transport (Fan, Uppstu, Siro, Harju): KPM moments, Chebyshev-Bessel time
+evolution, commutator propagation, and the VAC / MSD time loops, computed by
+hand-written gfx950 kernels behind the C ABI of include/kpm.h.
+
+This package is the Python binding of that ABI.  The shared library
+(libkpm.so, built in-tree by `python -m paper_1307_0288_amd.build`) is loaded
+on first use; every entry point raises ImportError when it is missing.  There
+is no CPU fallback.
+"""
+from .kpm import (ABI_SYMBOLS, HBAR_EV_FS, BOND_NM, KpmError, System, graphene_system,
+                  kpm_build_graphene, kpm_evolve, kpm_evolve_x, kpm_get_stats, kpm_kpm_sum,
+                  kpm_moments, kpm_msd, kpm_reset_stats, kpm_set_timing, kpm_sigma_e1,
+                  kpm_sigma_e2, kpm_sigma_gk, kpm_vac, lib)
+
+__all__ = ["ABI_SYMBOLS", "HBAR_EV_FS", "BOND_NM", "KpmError", "System", "graphene_system",
+           "kpm_build_graphene", "kpm_evolve", "kpm_evolve_x", "kpm_get_stats",
+           "kpm_kpm_sum", "kpm_moments", "kpm_msd", "kpm_reset_stats", "kpm_set_timing",
+           "kpm_sigma_e1", "kpm_sigma_e2", "kpm_sigma_gk", "kpm_vac", "lib"]

@@ -1,0 +1,791 @@
+// Host side of the C ABI declared in include/kpm.h: descriptor validation and
+// packing, device residency of the scaled Hamiltonian, recursion scratch,
+// and the drivers of Alg. 2, 3, 5, 6 and 7 that sequence the gfx950 kernels.
+#include "kpm.h"
+#include "kpm_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace {
+
+constexpr double kHbar = 0.6582119569;   // eV fs
+constexpr double kBond = 0.142;          // nm, carbon-carbon distance (Sec. 2)
+constexpr double kPi = 3.14159265358979323846;
+
+thread_local std::string g_err;
+
+kpm_status fail(kpm_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define KPM_HIP(call)                                                                \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess)                                                        \
+            return fail(e_ == hipErrorOutOfMemory ? KPM_ERR_OOM : KPM_ERR_DEVICE,    \
+                        "%s: %s", #call, hipGetErrorString(e_));                     \
+    } while (0)
+
+#define KPM_TRY(expr)                          \
+    do {                                       \
+        kpm_status s_ = (expr);                \
+        if (s_ != KPM_OK) return s_;           \
+    } while (0)
+
+int vshift_of(int n_vec) {
+    for (int s = 0; s <= 6; ++s)
+        if ((1 << s) == n_vec) return s;
+    return -1;
+}
+
+// Chebyshev-Bessel coefficients of Eq. 36: c_m = (2 - delta_m0) (-i s)^m J_m(x).
+// J_m from the C++17 special functions (std::cyl_bessel_j).
+void bessel_coeffs(int np, double x, int sign, std::vector<double2> &c) {
+    c.resize(np);
+    for (int m = 0; m < np; ++m) {
+        double j = std::cyl_bessel_j((double)m, x);
+        double f = (m == 0 ? 1.0 : 2.0) * j;
+        // (-i s)^m cycles through 1, -i s, -1, i s
+        double re = 0, im = 0;
+        switch (m & 3) {
+            case 0: re = f; break;
+            case 1: im = -sign * f; break;
+            case 2: re = -f; break;
+            case 3: im = sign * f; break;
+        }
+        c[m] = make_double2(re, im);
+    }
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct kpm_system {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    kpm_precision prec = KPM_FP64;
+    int64_t n = 0;
+    int w = 0;
+    double e_scale = 1;
+    bool has_dx = false;
+    int cus = 256;
+    int wg_per_cu = 8;
+    // device Hamiltonian
+    int32_t *d_nbr = nullptr;
+    double *d_hop = nullptr;
+    double *d_xw = nullptr;
+    double *d_ons = nullptr;
+    double t_scaled = 0;
+    // scratch
+    std::vector<void *> vecs;
+    size_t vec_bytes = 0;
+    double2 *partial = nullptr;
+    size_t partial_elems = 0;
+    double2 *dmom = nullptr;
+    size_t dmom_elems = 0;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> events;
+    size_t events_used = 0;
+    kpm_stats stats{};
+
+    size_t elem_bytes() const { return prec == KPM_FP64 ? 16 : 8; }
+
+    kpm::Ell ell() const {
+        kpm::Ell h;
+        h.nbr = d_nbr;
+        h.hop = d_hop;
+        h.xw = d_xw;
+        h.ons = d_ons;
+        h.t = t_scaled;
+        h.n = n;
+        h.w = w;
+        return h;
+    }
+
+    int grid_for(int64_t total) const {
+        int64_t nblk = (total + kpm::kBlock - 1) / kpm::kBlock;
+        int64_t g = (int64_t)cus * wg_per_cu;
+        g = std::min<int64_t>(g, ((nblk + kpm::kXcds - 1) / kpm::kXcds) * kpm::kXcds);
+        g = std::max<int64_t>(g, kpm::kXcds);
+        return (int)(g - g % kpm::kXcds);
+    }
+
+    kpm::Sweep sweep(int vshift) const {
+        return kpm::make_sweep(n, vshift, grid_for(n << vshift));
+    }
+
+    // Makes sure `count` state vectors of n_vec vectors each exist.
+    kpm_status ensure_vecs(int count, int n_vec) {
+        size_t bytes = (size_t)n * n_vec * elem_bytes();
+        if (bytes > vec_bytes) {
+            for (void *p : vecs) (void)hipFree(p);
+            vecs.clear();
+            vec_bytes = bytes;
+        }
+        while ((int)vecs.size() < count) {
+            void *p = nullptr;
+            KPM_HIP(hipMalloc(&p, vec_bytes));
+            KPM_HIP(hipMemsetAsync(p, 0, vec_bytes, stream));
+            vecs.push_back(p);
+        }
+        return KPM_OK;
+    }
+
+    kpm_status ensure_partial(int slots, int nwg, int n_vec) {
+        size_t need = (size_t)slots * nwg * n_vec;
+        if (need > partial_elems) {
+            if (partial) (void)hipFree(partial);
+            partial = nullptr;
+            KPM_HIP(hipMalloc(&partial, need * sizeof(double2)));
+            partial_elems = need;
+        }
+        return KPM_OK;
+    }
+
+    kpm_status ensure_dmom(size_t elems) {
+        if (elems > dmom_elems) {
+            if (dmom) (void)hipFree(dmom);
+            dmom = nullptr;
+            KPM_HIP(hipMalloc(&dmom, elems * sizeof(double2)));
+            dmom_elems = elems;
+        }
+        return KPM_OK;
+    }
+
+    kpm_status event_pair(hipEvent_t *a, hipEvent_t *b) {
+        while (events.size() < events_used + 2) {
+            hipEvent_t e;
+            KPM_HIP(hipEventCreate(&e));
+            events.push_back(e);
+        }
+        *a = events[events_used];
+        *b = events[events_used + 1];
+        events_used += 2;
+        return KPM_OK;
+    }
+
+    // Adds the elapsed time of every recorded event pair to the stats.
+    // The stream must have been synchronised.
+    kpm_status harvest_events() {
+        for (size_t k = 0; k + 1 < events_used; k += 2) {
+            float ms = 0;
+            KPM_HIP(hipEventElapsedTime(&ms, events[k], events[k + 1]));
+            stats.step_ms += ms;
+        }
+        events_used = 0;
+        return KPM_OK;
+    }
+
+    ~kpm_system() {
+        DeviceGuard g(device);
+        for (void *p : vecs) (void)hipFree(p);
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        if (partial) (void)hipFree(partial);
+        if (dmom) (void)hipFree(dmom);
+        if (d_nbr) (void)hipFree(d_nbr);
+        if (d_hop) (void)hipFree(d_hop);
+        if (d_xw) (void)hipFree(d_xw);
+        if (d_ons) (void)hipFree(d_ons);
+    }
+};
+
+namespace {
+
+// ---------------------------------------------------------------- drivers
+// Chebyshev moments of Alg. 5 for n_vec vector pairs, reduced into
+// sys->dmom[r * stride_r + offset + m] (complex).
+template <typename V>
+kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir, int nm,
+                       V *a_buf, V *b_buf, int64_t stride_r, int64_t offset) {
+    const kpm::Ell h = sys->ell();
+    const kpm::Sweep sw = sys->sweep(vshift);
+    const int slots = std::max(nm, 2);
+    KPM_TRY(sys->ensure_partial(slots, sw.nwg, 1 << vshift));
+    hipStream_t s = sys->stream;
+    // C_0 and C_1 (phi_0 = phi_R, phi_1 = H~ phi_0)
+    kpm::launch_moment_step<V>(h, sw, true, phir, nullptr, a_buf, phil, sys->partial, 0, s);
+    sys->stats.site_updates += sw.total;
+    if (nm > 2) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (sys->timing) {
+            KPM_TRY(sys->event_pair(&e0, &e1));
+            KPM_HIP(hipEventRecord(e0, s));
+        }
+        // phi_m = 2 H~ phi_{m-1} - phi_{m-2}, in place after the first step
+        const V *p0 = phir;
+        V *p1 = a_buf;
+        for (int m = 2; m < nm; ++m) {
+            V *out = (m == 2) ? b_buf : const_cast<V *>(p0);
+            kpm::launch_moment_step<V>(h, sw, false, p1, p0, out, phil, sys->partial, m, s);
+            p0 = p1;
+            p1 = out;
+        }
+        if (sys->timing) {
+            KPM_HIP(hipEventRecord(e1, s));
+            sys->stats.step_launches += nm - 2;
+            sys->stats.step_rows = sw.total;
+        }
+        sys->stats.site_updates += (int64_t)(nm - 2) * sw.total;
+    }
+    kpm::launch_reduce(sys->partial, sw.nwg, vshift, nm, sys->dmom, stride_r, offset, s);
+    return KPM_OK;
+}
+
+// acc = [add +] U(sign dt) in  (Alg. 6).  Scratch a_buf, b_buf.
+template <typename V>
+kpm_status run_evolve(kpm_system *sys, int vshift, const V *in, V *acc, const V *add,
+                      double dt, int sign, int np, V *a_buf, V *b_buf) {
+    const kpm::Ell h = sys->ell();
+    const kpm::Sweep sw = sys->sweep(vshift);
+    std::vector<double2> c;
+    bessel_coeffs(np, sys->e_scale * dt / kHbar, sign, c);
+    hipStream_t s = sys->stream;
+    kpm::launch_evolve_step<V>(h, sw, true, in, nullptr, a_buf, acc, add, c[0], c[1], s);
+    const V *p0 = in;
+    V *p1 = a_buf;
+    for (int m = 2; m < np; ++m) {
+        V *out = (m == 2) ? b_buf : const_cast<V *>(p0);
+        kpm::launch_evolve_step<V>(h, sw, false, p1, p0, out, acc, nullptr, c[0], c[m], s);
+        p0 = p1;
+        p1 = out;
+    }
+    sys->stats.site_updates += (int64_t)(np - 1) * sw.total;
+    return KPM_OK;
+}
+
+// accx = [X, U(dt)] in, accu = U(dt) in  (Alg. 7 with Eq. 36 alongside).
+template <typename V>
+kpm_status run_evolve_x(kpm_system *sys, int vshift, const V *in, V *accx, V *accu,
+                        double dt, int np, V *pa, V *pb, V *qa, V *qb) {
+    const kpm::Ell h = sys->ell();
+    const kpm::Sweep sw = sys->sweep(vshift);
+    std::vector<double2> c;
+    bessel_coeffs(np, sys->e_scale * dt / kHbar, +1, c);
+    hipStream_t s = sys->stream;
+    kpm::launch_evolve_x_step<V>(h, sw, true, in, nullptr, pa, nullptr, nullptr, qa, accx,
+                                 accu, c[0], c[1], s);
+    const V *p0 = in, *q0 = nullptr;
+    V *p1 = pa, *q1 = qa;
+    for (int m = 2; m < np; ++m) {
+        V *pout = (m == 2) ? pb : const_cast<V *>(p0);
+        V *qout = (m == 2) ? qb : const_cast<V *>(q0);
+        kpm::launch_evolve_x_step<V>(h, sw, false, p1, p0, pout, q1, q0, qout, accx, accu,
+                                     c[0], c[m], s);
+        p0 = p1;
+        p1 = pout;
+        q0 = q1;
+        q1 = qout;
+    }
+    sys->stats.site_updates += 2 * (int64_t)(np - 1) * sw.total;
+    return KPM_OK;
+}
+
+kpm_status check_common(kpm_system *sys, int n_vec, int *vshift) {
+    if (!sys) return fail(KPM_ERR_INVALID, "null system");
+    *vshift = vshift_of(n_vec);
+    if (*vshift < 0) return fail(KPM_ERR_INVALID, "n_vec must be 1, 2, 4, ..., 64 (got %d)", n_vec);
+    return KPM_OK;
+}
+
+kpm_status finish_moments(kpm_system *sys, size_t elems, double2 *host) {
+    KPM_HIP(hipMemcpyAsync(host, sys->dmom, elems * sizeof(double2), hipMemcpyDeviceToHost,
+                           sys->stream));
+    KPM_HIP(hipStreamSynchronize(sys->stream));
+    KPM_HIP(hipGetLastError());
+    if (sys->timing) KPM_TRY(sys->harvest_events());
+    for (size_t k = 0; k < elems; ++k)
+        if (!std::isfinite(host[k].x) || !std::isfinite(host[k].y))
+            return fail(KPM_ERR_NUMERIC, "non-finite moment at index %zu", k);
+    return KPM_OK;
+}
+
+template <typename V>
+kpm_status moments_impl(kpm_system *sys, int vshift, const void *phil, const void *phir,
+                        int nm, double *mu) {
+    KPM_TRY(sys->ensure_vecs(2, 1 << vshift));
+    const int64_t r = 1 << vshift;
+    KPM_TRY(sys->ensure_dmom((size_t)r * nm));
+    V *a = (V *)sys->vecs[0], *b = (V *)sys->vecs[1];
+    KPM_TRY(run_moments<V>(sys, vshift, (const V *)phil, (const V *)phir, nm, a, b, nm, 0));
+    return finish_moments(sys, (size_t)r * nm, (double2 *)mu);
+}
+
+template <typename V>
+kpm_status evolve_impl(kpm_system *sys, int vshift, void *phi, double dt, int sign, int np) {
+    KPM_TRY(sys->ensure_vecs(3, 1 << vshift));
+    V *a = (V *)sys->vecs[0], *b = (V *)sys->vecs[1], *acc = (V *)sys->vecs[2];
+    KPM_TRY(run_evolve<V>(sys, vshift, (const V *)phi, acc, nullptr, dt, sign, np, a, b));
+    KPM_HIP(hipMemcpyAsync(phi, acc, (size_t)sys->n * (1 << vshift) * sys->elem_bytes(),
+                           hipMemcpyDeviceToDevice, sys->stream));
+    KPM_HIP(hipGetLastError());
+    return KPM_OK;
+}
+
+template <typename V>
+kpm_status evolve_x_impl(kpm_system *sys, int vshift, const void *phi, void *outx, void *outu,
+                         double dt, int np) {
+    KPM_TRY(sys->ensure_vecs(5, 1 << vshift));
+    V *pa = (V *)sys->vecs[0], *pb = (V *)sys->vecs[1], *qa = (V *)sys->vecs[2],
+      *qb = (V *)sys->vecs[3], *u = (V *)sys->vecs[4];
+    KPM_TRY(run_evolve_x<V>(sys, vshift, (const V *)phi, (V *)outx, outu ? (V *)outu : u, dt,
+                            np, pa, pb, qa, qb));
+    KPM_HIP(hipGetLastError());
+    return KPM_OK;
+}
+
+// VAC loop of Alg. 2 (Eq. 42-43).
+template <typename V>
+kpm_status vac_impl(kpm_system *sys, int vshift, const void *phi_v, int nsteps, double dt,
+                    int np, int nm, double *out) {
+    KPM_TRY(sys->ensure_vecs(7, 1 << vshift));
+    const int64_t r = 1 << vshift;
+    const int64_t per_r = (int64_t)(nsteps + 1) * nm;
+    KPM_TRY(sys->ensure_dmom((size_t)r * per_r));
+    V *a = (V *)sys->vecs[0], *b = (V *)sys->vecs[1];
+    V *psi = (V *)sys->vecs[2], *psi2 = (V *)sys->vecs[3];
+    V *rr = (V *)sys->vecs[4], *rr2 = (V *)sys->vecs[5], *ll = (V *)sys->vecs[6];
+    const V *phi = (const V *)phi_v;
+    const kpm::Ell h = sys->ell();
+    const kpm::Sweep sw = sys->sweep(vshift);
+    const double2 alpha = make_double2(0.0, -sys->e_scale / kHbar);   // V = -i (E_s/hbar) D
+    // R_0 = V phi; L_0 = V psi_0 = R_0
+    kpm::launch_apply_d<V>(h, sw, phi, rr, alpha, sys->stream);
+    KPM_TRY(run_moments<V>(sys, vshift, rr, rr, nm, a, b, per_r, 0));
+    const V *cur = phi;
+    for (int k = 1; k <= nsteps; ++k) {
+        KPM_TRY(run_evolve<V>(sys, vshift, cur, psi2, nullptr, dt, -1, np, a, b));
+        std::swap(psi, psi2);
+        cur = psi;
+        KPM_TRY(run_evolve<V>(sys, vshift, rr, rr2, nullptr, dt, -1, np, a, b));
+        std::swap(rr, rr2);
+        kpm::launch_apply_d<V>(h, sw, psi, ll, alpha, sys->stream);
+        KPM_TRY(run_moments<V>(sys, vshift, ll, rr, nm, a, b, per_r, (int64_t)k * nm));
+    }
+    std::vector<double2> host((size_t)r * per_r);
+    KPM_TRY(finish_moments(sys, host.size(), host.data()));
+    for (size_t q = 0; q < host.size(); ++q) out[q] = host[q].x;
+    return KPM_OK;
+}
+
+// MSD loop of Alg. 3 (Eq. 44).
+template <typename V>
+kpm_status msd_impl(kpm_system *sys, int vshift, const void *phi_v, int nsteps, double dt,
+                    int np, int nm, double *out) {
+    KPM_TRY(sys->ensure_vecs(9, 1 << vshift));
+    const int64_t r = 1 << vshift;
+    const int64_t per_r = (int64_t)(nsteps + 1) * nm;
+    KPM_TRY(sys->ensure_dmom((size_t)r * per_r));
+    V *pa = (V *)sys->vecs[0], *pb = (V *)sys->vecs[1], *qa = (V *)sys->vecs[2],
+      *qb = (V *)sys->vecs[3];
+    V *y = (V *)sys->vecs[4], *y2 = (V *)sys->vecs[5], *xu = (V *)sys->vecs[6];
+    V *psi = (V *)sys->vecs[7], *psi2 = (V *)sys->vecs[8];
+    // Y_0 = [X, U(0)] phi = 0: its moments are exactly zero.
+    KPM_HIP(hipMemsetAsync(sys->dmom, 0, (size_t)r * per_r * sizeof(double2), sys->stream));
+    const V *cur = (const V *)phi_v;
+    for (int k = 1; k <= nsteps; ++k) {
+        // [X, U(dt)] psi'_{k-1} and psi'_k = U(dt) psi'_{k-1}
+        KPM_TRY(run_evolve_x<V>(sys, vshift, cur, xu, psi2, dt, np, pa, pb, qa, qb));
+        std::swap(psi, psi2);
+        cur = psi;
+        if (k == 1) {
+            std::swap(y, xu);                     // Y_1 = U(dt) 0 + [X, U(dt)] phi
+        } else {
+            KPM_TRY(run_evolve<V>(sys, vshift, y, y2, xu, dt, +1, np, pa, pb));
+            std::swap(y, y2);                     // Y_k = U(dt) Y_{k-1} + [X, U(dt)] psi'
+        }
+        KPM_TRY(run_moments<V>(sys, vshift, y, y, nm, pa, pb, per_r, (int64_t)k * nm));
+    }
+    // keep the buffer roles stable across calls is not needed: every call
+    // overwrites what it reads before reading it
+    std::vector<double2> host((size_t)r * per_r);
+    KPM_TRY(finish_moments(sys, host.size(), host.data()));
+    for (size_t q = 0; q < host.size(); ++q) out[q] = host[q].x;
+    return KPM_OK;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+const char *kpm_last_error(void) { return g_err.c_str(); }
+
+const char *kpm_version(void) { return "kpm-mi355x 0.1 (gfx950)"; }
+
+kpm_status kpm_build_graphene(int64_t nx, int64_t ny, kpm_geometry geometry,
+                              const uint8_t *active, int32_t *nbr, double *dx) {
+    const bool pbc_x = geometry == KPM_SHEET || geometry == KPM_ZGNR;
+    const bool pbc_y = geometry == KPM_SHEET || geometry == KPM_AGNR;
+    if (geometry < KPM_SHEET || geometry > KPM_AGNR) return fail(KPM_ERR_INVALID, "geometry");
+    if (nx < 2 || ny < 1 || nx * ny >= (int64_t)1 << 31)
+        return fail(KPM_ERR_INVALID, "lattice size %lld x %lld", (long long)nx, (long long)ny);
+    if (pbc_x && (nx % 2 || nx < 4)) return fail(KPM_ERR_INVALID, "periodic x needs even nx >= 4");
+    if (pbc_y && (ny % 2 || ny < 2)) return fail(KPM_ERR_INVALID, "periodic y needs even ny >= 2");
+    if (!nbr) return fail(KPM_ERR_INVALID, "nbr is null");
+    const int64_t n = nx * ny;
+    const double half_zig = std::sqrt(3.0) * kBond / 2.0;
+    for (int64_t j = 0; j < ny; ++j) {
+        for (int64_t i = 0; i < nx; ++i) {
+            const int64_t s = j * nx + i;
+            const bool up = ((i + j) & 1) != 0;             // odd sites bond upwards
+            int64_t li = i - 1, ri = i + 1, vj = up ? j + 1 : j - 1;
+            bool lok = true, rok = true, vok = true;
+            if (li < 0) { lok = pbc_x; li += nx; }
+            if (ri >= nx) { rok = pbc_x; ri -= nx; }
+            if (vj < 0) { vok = pbc_y; vj += ny; }
+            if (vj >= ny) { vok = pbc_y; vj -= ny; }
+            int64_t m[3] = {j * nx + li, j * nx + ri, vj * nx + i};
+            bool ok[3] = {lok, rok, vok};
+            // displacement X_s - X_m of each slot along the transport axis
+            double d[3];
+            if (geometry == KPM_AGNR) {
+                const double dy = up ? kBond / 2 : -kBond / 2;   // chain neighbours
+                d[0] = dy;
+                d[1] = dy;
+                d[2] = up ? -kBond : kBond;
+            } else {
+                d[0] = half_zig;
+                d[1] = -half_zig;
+                d[2] = 0.0;
+            }
+            const bool alive = !active || active[s];
+            for (int k = 0; k < 3; ++k) {
+                bool use = alive && ok[k] && (!active || active[m[k]]);
+                nbr[k * n + s] = use ? (int32_t)m[k] : -1;
+                if (dx) dx[k * n + s] = use ? d[k] : 0.0;
+            }
+        }
+    }
+    return KPM_OK;
+}
+
+kpm_status kpm_system_create(const kpm_system_desc *d, kpm_precision prec, int device,
+                             void *hip_stream, kpm_system **out) {
+    if (!d || !out) return fail(KPM_ERR_INVALID, "null descriptor or output");
+    *out = nullptr;
+    const int64_t n = d->n_sites;
+    const int w = d->width;
+    if (n < 1 || n >= ((int64_t)1 << 31)) return fail(KPM_ERR_INVALID, "n_sites out of range");
+    if (w < 1 || w > KPM_MAX_WIDTH) return fail(KPM_ERR_INVALID, "width must be 1..%d", KPM_MAX_WIDTH);
+    if (!d->nbr) return fail(KPM_ERR_INVALID, "nbr is null");
+    if (prec != KPM_FP64 && prec != KPM_FP32_STATES) return fail(KPM_ERR_INVALID, "precision");
+    if (!(d->e_scale > 0) || !std::isfinite(d->e_scale)) return fail(KPM_ERR_INVALID, "e_scale");
+
+    // Pack: removed sites lose every bond and their on-site energy.
+    std::vector<int32_t> nbr((size_t)w * n);
+    std::vector<double> hop(d->hop ? (size_t)w * n : 0), ons(n, 0.0);
+    std::vector<double> dxs(d->dx ? (size_t)w * n : 0);
+    auto alive = [&](int64_t s) { return !d->active || d->active[s] != 0; };
+    for (int64_t s = 0; s < n; ++s) {
+        ons[s] = (alive(s) && d->onsite) ? d->onsite[s] : 0.0;
+        if (!std::isfinite(ons[s])) return fail(KPM_ERR_INVALID, "non-finite onsite at %lld", (long long)s);
+        for (int k = 0; k < w; ++k) {
+            const size_t q = (size_t)k * n + s;
+            int32_t m = d->nbr[q];
+            if (m < -1 || m >= n) return fail(KPM_ERR_INVALID, "neighbour index %d out of range at row %lld slot %d", m, (long long)s, k);
+            if (m >= 0 && (!alive(s) || !alive(m))) m = -1;
+            nbr[q] = m;
+            if (d->hop) hop[q] = m >= 0 ? d->hop[q] : 0.0;
+            if (d->dx) dxs[q] = m >= 0 ? d->dx[q] : 0.0;
+        }
+    }
+    // Symmetry: every bond listed from both ends with equal H and opposite dx.
+    const double tu = d->t_uniform;
+    double gersh = 0.0;
+    for (int64_t s = 0; s < n; ++s) {
+        double row = std::fabs(ons[s]);
+        for (int k = 0; k < w; ++k) {
+            const size_t q = (size_t)k * n + s;
+            const int32_t m = nbr[q];
+            if (m < 0) continue;
+            const double hv = d->hop ? hop[q] : tu;
+            row += std::fabs(hv);
+            bool found = false;
+            for (int k2 = 0; k2 < w && !found; ++k2) {
+                const size_t q2 = (size_t)k2 * n + m;
+                if (nbr[q2] != s) continue;
+                const double hb = d->hop ? hop[q2] : tu;
+                if (hb != hv) continue;
+                if (d->dx && dxs[q2] != -dxs[q]) continue;
+                found = true;
+            }
+            if (!found)
+                return fail(KPM_ERR_INVALID, "H not symmetric (or dx not antisymmetric) at row %lld slot %d", (long long)s, k);
+        }
+        gersh = std::max(gersh, row);
+    }
+    if (d->e_scale < gersh)
+        return fail(KPM_ERR_INVALID, "e_scale %.6g below the Gershgorin bound %.6g", d->e_scale, gersh);
+
+    kpm_system *sys = new (std::nothrow) kpm_system();
+    if (!sys) return fail(KPM_ERR_OOM, "host allocation");
+    sys->device = device;
+    sys->stream = (hipStream_t)hip_stream;
+    sys->prec = prec;
+    sys->n = n;
+    sys->w = w;
+    sys->e_scale = d->e_scale;
+    sys->has_dx = d->dx != nullptr;
+    sys->t_scaled = tu / d->e_scale;
+    if (const char *env = std::getenv("KPM_WG_PER_CU")) sys->wg_per_cu = std::max(1, atoi(env));
+
+    auto bail = [&](kpm_status st) { delete sys; return st; };
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return bail(fail(KPM_ERR_DEVICE, "no HIP device %d", device));
+    DeviceGuard guard(device);
+    if (hipDeviceGetAttribute(&sys->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        sys->cus = 256;
+
+    std::vector<double> hs, xw;
+    if (d->hop) {
+        hs.resize(hop.size());
+        for (size_t q = 0; q < hop.size(); ++q) hs[q] = hop[q] / d->e_scale;
+    }
+    if (d->dx) {
+        xw.resize(dxs.size());
+        for (size_t q = 0; q < dxs.size(); ++q)
+            xw[q] = nbr[q] >= 0 ? dxs[q] * ((d->hop ? hop[q] : tu) / d->e_scale) : 0.0;
+    }
+    for (auto &o : ons) o /= d->e_scale;
+    auto upload = [&](void **dst, const void *src, size_t bytes) -> kpm_status {
+        hipError_t e = hipMalloc(dst, bytes);
+        if (e != hipSuccess) return fail(KPM_ERR_OOM, "hipMalloc %zu bytes: %s", bytes, hipGetErrorString(e));
+        e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail(KPM_ERR_DEVICE, "upload: %s", hipGetErrorString(e));
+        return KPM_OK;
+    };
+    kpm_status st = upload((void **)&sys->d_nbr, nbr.data(), nbr.size() * sizeof(int32_t));
+    if (st == KPM_OK) st = upload((void **)&sys->d_ons, ons.data(), ons.size() * sizeof(double));
+    if (st == KPM_OK && d->hop) st = upload((void **)&sys->d_hop, hs.data(), hs.size() * sizeof(double));
+    if (st == KPM_OK && d->dx) st = upload((void **)&sys->d_xw, xw.data(), xw.size() * sizeof(double));
+    if (st != KPM_OK) return bail(st);
+    *out = sys;
+    return KPM_OK;
+}
+
+kpm_status kpm_system_destroy(kpm_system *sys) {
+    if (!sys) return KPM_OK;
+    {
+        DeviceGuard g(sys->device);
+        (void)hipStreamSynchronize(sys->stream);
+    }
+    delete sys;
+    return KPM_OK;
+}
+
+kpm_status kpm_system_set_stream(kpm_system *sys, void *hip_stream) {
+    if (!sys) return fail(KPM_ERR_INVALID, "null system");
+    sys->stream = (hipStream_t)hip_stream;
+    return KPM_OK;
+}
+
+int64_t kpm_system_n_sites(const kpm_system *sys) { return sys ? sys->n : -1; }
+
+kpm_status kpm_moments(kpm_system *sys, int n_vec, const void *phil, const void *phir,
+                       int n_moments, double *mu) {
+    int vs;
+    KPM_TRY(check_common(sys, n_vec, &vs));
+    if (!phil || !phir || !mu) return fail(KPM_ERR_INVALID, "null buffer");
+    if (n_moments < 1) return fail(KPM_ERR_INVALID, "n_moments must be >= 1");
+    DeviceGuard g(sys->device);
+    return sys->prec == KPM_FP64 ? moments_impl<double2>(sys, vs, phil, phir, n_moments, mu)
+                                 : moments_impl<float2>(sys, vs, phil, phir, n_moments, mu);
+}
+
+kpm_status kpm_evolve(kpm_system *sys, int n_vec, void *phi, double dt_fs, int sign,
+                      int n_bessel) {
+    int vs;
+    KPM_TRY(check_common(sys, n_vec, &vs));
+    if (!phi) return fail(KPM_ERR_INVALID, "null buffer");
+    if (sign != 1 && sign != -1) return fail(KPM_ERR_INVALID, "sign must be +1 or -1");
+    if (n_bessel < 2) return fail(KPM_ERR_INVALID, "n_bessel must be >= 2");
+    if (!std::isfinite(dt_fs) || dt_fs < 0) return fail(KPM_ERR_INVALID, "dt_fs");
+    DeviceGuard g(sys->device);
+    return sys->prec == KPM_FP64 ? evolve_impl<double2>(sys, vs, phi, dt_fs, sign, n_bessel)
+                                 : evolve_impl<float2>(sys, vs, phi, dt_fs, sign, n_bessel);
+}
+
+kpm_status kpm_evolve_x(kpm_system *sys, int n_vec, const void *phi, void *out_x, void *out_u,
+                        double dt_fs, int n_bessel) {
+    int vs;
+    KPM_TRY(check_common(sys, n_vec, &vs));
+    if (!phi || !out_x) return fail(KPM_ERR_INVALID, "null buffer");
+    if (out_x == phi || out_u == phi || (out_u && out_u == out_x))
+        return fail(KPM_ERR_INVALID, "outputs must not alias the input or each other");
+    if (!sys->has_dx) return fail(KPM_ERR_INVALID, "system has no dx (position operator)");
+    if (n_bessel < 2) return fail(KPM_ERR_INVALID, "n_bessel must be >= 2");
+    if (!std::isfinite(dt_fs) || dt_fs < 0) return fail(KPM_ERR_INVALID, "dt_fs");
+    DeviceGuard g(sys->device);
+    return sys->prec == KPM_FP64
+               ? evolve_x_impl<double2>(sys, vs, phi, out_x, out_u, dt_fs, n_bessel)
+               : evolve_x_impl<float2>(sys, vs, phi, out_x, out_u, dt_fs, n_bessel);
+}
+
+static kpm_status check_loop(kpm_system *sys, int n_vec, const void *phi, int n_steps,
+                             double dt_fs, int n_bessel, int n_moments, double *out, int *vs) {
+    KPM_TRY(check_common(sys, n_vec, vs));
+    if (!phi || !out) return fail(KPM_ERR_INVALID, "null buffer");
+    if (!sys->has_dx) return fail(KPM_ERR_INVALID, "system has no dx (velocity operator)");
+    if (n_steps < 0) return fail(KPM_ERR_INVALID, "n_steps must be >= 0");
+    if (n_bessel < 2) return fail(KPM_ERR_INVALID, "n_bessel must be >= 2");
+    if (n_moments < 1) return fail(KPM_ERR_INVALID, "n_moments must be >= 1");
+    if (!std::isfinite(dt_fs) || dt_fs < 0) return fail(KPM_ERR_INVALID, "dt_fs");
+    return KPM_OK;
+}
+
+kpm_status kpm_vac(kpm_system *sys, int n_vec, const void *phi, int n_steps, double dt_fs,
+                   int n_bessel, int n_moments, double *out) {
+    int vs;
+    KPM_TRY(check_loop(sys, n_vec, phi, n_steps, dt_fs, n_bessel, n_moments, out, &vs));
+    DeviceGuard g(sys->device);
+    return sys->prec == KPM_FP64
+               ? vac_impl<double2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, out)
+               : vac_impl<float2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, out);
+}
+
+kpm_status kpm_msd(kpm_system *sys, int n_vec, const void *phi, int n_steps, double dt_fs,
+                   int n_bessel, int n_moments, double *out) {
+    int vs;
+    KPM_TRY(check_loop(sys, n_vec, phi, n_steps, dt_fs, n_bessel, n_moments, out, &vs));
+    DeviceGuard g(sys->device);
+    return sys->prec == KPM_FP64
+               ? msd_impl<double2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, out)
+               : msd_impl<float2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, out);
+}
+
+kpm_status kpm_kpm_sum(int n_rows, int n_moments, const double *moments, int n_energies,
+                       const double *energies, double e_scale, double area_nm2, int jackson,
+                       void *hip_stream, double *out) {
+    if (n_rows < 1 || n_moments < 1 || n_energies < 1) return fail(KPM_ERR_INVALID, "sizes");
+    if (!moments || !energies || !out) return fail(KPM_ERR_INVALID, "null buffer");
+    if (!(e_scale > 0) || !(area_nm2 > 0)) return fail(KPM_ERR_INVALID, "e_scale / area");
+    std::vector<double> w(n_moments), eps(n_energies), pref(n_energies);
+    const double a = 1.0 / (n_moments + 1);
+    for (int m = 0; m < n_moments; ++m) {
+        // Jackson damping, Eq. 35
+        double g = jackson ? (1 - m * a) * std::cos(kPi * m * a) +
+                                 a * std::sin(kPi * m * a) / std::tan(kPi * a)
+                           : 1.0;
+        w[m] = g * (m == 0 ? 1.0 : 2.0);
+    }
+    for (int k = 0; k < n_energies; ++k) {
+        eps[k] = energies[k] / e_scale;
+        if (!(std::fabs(eps[k]) < 1.0)) return fail(KPM_ERR_INVALID, "energy %d outside (-E_s, E_s)", k);
+        pref[k] = 2.0 / (kPi * area_nm2 * e_scale * std::sqrt(1.0 - eps[k] * eps[k]));
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t nmom = (size_t)n_rows * n_moments, nout = (size_t)n_rows * n_energies;
+    double *buf = nullptr;
+    const size_t total = nmom + n_moments + 2 * (size_t)n_energies + nout;
+    KPM_HIP(hipMalloc(&buf, total * sizeof(double)));
+    double *dm = buf, *dw = dm + nmom, *de = dw + n_moments, *dp = de + n_energies,
+           *dout = dp + n_energies;
+    kpm_status st = KPM_OK;
+    auto chk = [&](hipError_t e) {
+        if (e != hipSuccess && st == KPM_OK) st = fail(KPM_ERR_DEVICE, "kpm_sum: %s", hipGetErrorString(e));
+    };
+    chk(hipMemcpyAsync(dm, moments, nmom * sizeof(double), hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(dw, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(de, eps.data(), eps.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(dp, pref.data(), pref.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    if (st == KPM_OK) {
+        kpm::launch_kpm_sum(dm, n_rows, n_moments, dw, de, dp, n_energies, dout, s);
+        chk(hipGetLastError());
+    }
+    chk(hipMemcpyAsync(out, dout, nout * sizeof(double), hipMemcpyDeviceToHost, s));
+    chk(hipStreamSynchronize(s));
+    (void)hipFree(buf);
+    return st;
+}
+
+kpm_status kpm_sigma_gk(int nt, int ne, const double *in, double dt, double *out) {
+    if (nt < 1 || ne < 1 || !in || !out || in == out || !(dt > 0))
+        return fail(KPM_ERR_INVALID, "sigma_gk arguments");
+    const double f = 2.0 * kPi * kHbar;
+    for (int k = 0; k < ne; ++k) {
+        double acc = 0.0;
+        out[k] = 0.0;
+        for (int t = 1; t < nt; ++t) {
+            acc += 0.5 * (in[(size_t)t * ne + k] + in[(size_t)(t - 1) * ne + k]) * dt;
+            out[(size_t)t * ne + k] = f * acc;
+        }
+    }
+    return KPM_OK;
+}
+
+kpm_status kpm_sigma_e1(int nt, int ne, const double *in, double dt, double *out) {
+    if (nt < 1 || ne < 1 || !in || !out || in == out || !(dt > 0))
+        return fail(KPM_ERR_INVALID, "sigma_e1 arguments");
+    const double f = kPi * kHbar;
+    for (int k = 0; k < ne; ++k) {
+        for (int t = 0; t < nt; ++t) {
+            double d;
+            if (nt == 1) d = 0.0;
+            else if (t == 0) d = (in[(size_t)ne + k] - in[k]) / dt;
+            else if (t == nt - 1) d = (in[(size_t)t * ne + k] - in[(size_t)(t - 1) * ne + k]) / dt;
+            else d = (in[(size_t)(t + 1) * ne + k] - in[(size_t)(t - 1) * ne + k]) / (2.0 * dt);
+            out[(size_t)t * ne + k] = f * d;
+        }
+    }
+    return KPM_OK;
+}
+
+kpm_status kpm_sigma_e2(int nt, int ne, const double *in, double dt, double *out) {
+    if (nt < 1 || ne < 1 || !in || !out || in == out || !(dt > 0))
+        return fail(KPM_ERR_INVALID, "sigma_e2 arguments");
+    const double f = kPi * kHbar;
+    for (int k = 0; k < ne; ++k) out[k] = 0.0;
+    for (int t = 1; t < nt; ++t)
+        for (int k = 0; k < ne; ++k)
+            out[(size_t)t * ne + k] = f * in[(size_t)t * ne + k] / (t * dt);
+    return KPM_OK;
+}
+
+kpm_status kpm_set_timing(kpm_system *sys, int enable) {
+    if (!sys) return fail(KPM_ERR_INVALID, "null system");
+    sys->timing = enable != 0;
+    return KPM_OK;
+}
+
+kpm_status kpm_get_stats(kpm_system *sys, kpm_stats *out) {
+    if (!sys || !out) return fail(KPM_ERR_INVALID, "null argument");
+    *out = sys->stats;
+    return KPM_OK;
+}
+
+kpm_status kpm_reset_stats(kpm_system *sys) {
+    if (!sys) return fail(KPM_ERR_INVALID, "null system");
+    sys->stats = kpm_stats{};
+    return KPM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Internal interface between the host driver (kpm_host.cpp) and the gfx950
+// kernels (kpm_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kpm {
+
+constexpr int kBlock = 256;       // work-group size of the sweep kernels
+constexpr int kWave = 64;         // CDNA wavefront
+constexpr int kXcds = 8;          // MI355X: 8 accelerator complex dies
+constexpr int kMaxWidth = 4;      // neighbour-list slots per row
+
+// Scaled sparse Hamiltonian on the device (neighbour-list layout of Alg. 8).
+struct Ell {
+    const int32_t *nbr;   // [w][n] neighbour row, -1 = empty slot
+    const double *hop;    // [w][n] H_nm / E_s, or nullptr: every slot is t
+    const double *xw;     // [w][n] (X_n - X_m) H_nm / E_s, or nullptr
+    const double *ons;    // [n] H_nn / E_s
+    double t;             // uniform H_nm / E_s
+    int64_t n;            // rows
+    int w;                // slots per row
+};
+
+// Persistent, XCD-aware sweep over `total` = rows * vectors elements.
+// Work-groups are dispatched round-robin over the XCDs, so group g runs on
+// XCD g % 8.  The element blocks are cut into 8 contiguous ranges, one per
+// XCD, and the groups of an XCD stride through its range together: rows
+// that share neighbours are then served by the same L2.
+struct Sweep {
+    int64_t total;        // elements (rows << vshift)
+    int64_t nblk;         // ceil(total / kBlock)
+    int64_t per_xcd;      // blocks per XCD range
+    int nwg;              // work-groups in the grid (multiple of 8)
+    int vshift;           // log2(vectors per row)
+};
+
+Sweep make_sweep(int64_t rows, int vshift, int nwg);
+
+// --- launchers (all asynchronous on `s`) ----------------------------------
+// Chebyshev moment step (Alg. 5 fused with Alg. 8 and the inner product):
+//   first: out = H~ in; partial[slot] = <L|in>, partial[slot+1] = <L|out>.
+//   else : out = 2 H~ p1 - p0 (out may alias p0); partial[slot] = <L|out>.
+// partial: [slots][nwg][vectors] complex.
+template <typename V>
+void launch_moment_step(const Ell &h, const Sweep &sw, bool first, const V *p1,
+                        const V *p0, V *out, const V *phil, double2 *partial,
+                        int slot, hipStream_t s);
+
+// Chebyshev-Bessel propagator step (Alg. 6):
+//   first: out = H~ in; acc = add + c0 in + c out   (add may be nullptr)
+//   else : out = 2 H~ p1 - p0 (out may alias p0); acc += c out
+template <typename V>
+void launch_evolve_step(const Ell &h, const Sweep &sw, bool first, const V *p1,
+                        const V *p0, V *out, V *acc, const V *add, double2 c0,
+                        double2 c, hipStream_t s);
+
+// Coupled T_m / [X, T_m] step (Alg. 7, Eq. 38-41), accumulating both sums:
+//   first: pout = H~ in, qout = D in; accx = c qout; accu = c0 in + c pout
+//   else : pout = 2 H~ p1 - p0; qout = 2 D p1 + 2 H~ q1 - q0 (q0 may be
+//          nullptr = 0); accx += c qout; accu += c pout
+template <typename V>
+void launch_evolve_x_step(const Ell &h, const Sweep &sw, bool first, const V *p1,
+                          const V *p0, V *pout, const V *q1, const V *q0, V *qout,
+                          V *accx, V *accu, double2 c0, double2 c, hipStream_t s);
+
+// y = alpha * D x, D = [X, H~].
+template <typename V>
+void launch_apply_d(const Ell &h, const Sweep &sw, const V *x, V *y, double2 alpha,
+                    hipStream_t s);
+
+// dst[r * stride_r + offset + j] = sum_g partial[j][g][r] for j < slots, in a
+// fixed order (deterministic).
+void launch_reduce(const double2 *partial, int nwg, int vshift, int slots,
+                   double2 *dst, int64_t stride_r, int64_t offset, hipStream_t s);
+
+// out[t][k] = pref_k sum_m w_m T_m(e_k) mom[t][m]  (KPM sum, Eq. 29-31).
+void launch_kpm_sum(const double *mom, int rows, int nm, const double *w,
+                    const double *eps, const double *pref, int ne, double *out,
+                    hipStream_t s);
+
+}  // namespace kpm

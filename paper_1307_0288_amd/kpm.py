@@ -1,0 +1,332 @@
+"""Python binding of the C ABI in include/kpm.h (ctypes; argument marshalling only).
+
+Every computation runs in libkpm.so.  PyTorch provides device memory (state
+tensors) and the stream: each call runs on torch's current HIP stream.
+
+States are torch tensors on the GPU of shape [n_sites, n_vec] and dtype
+complex128 (KPM_FP64 systems) or complex64 (KPM_FP32_STATES systems), or the
+equivalent real view [n_sites, n_vec, 2]; n_vec is a power of two <= 64.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libkpm.so")
+
+KPM_OK, KPM_ERR_INVALID, KPM_ERR_OOM, KPM_ERR_DEVICE, KPM_ERR_UNSUPPORTED, KPM_ERR_NUMERIC = range(6)
+KPM_FP64, KPM_FP32_STATES = 0, 1
+GEOMETRIES = {"sheet": 0, "zgnr": 1, "agnr": 2}
+HBAR_EV_FS = 0.6582119569
+BOND_NM = 0.142
+
+# Every symbol declared in include/kpm.h.
+ABI_SYMBOLS = ("kpm_build_graphene", "kpm_system_create", "kpm_system_destroy",
+               "kpm_system_set_stream", "kpm_system_n_sites", "kpm_moments", "kpm_evolve",
+               "kpm_evolve_x", "kpm_vac", "kpm_msd", "kpm_kpm_sum", "kpm_sigma_gk",
+               "kpm_sigma_e1", "kpm_sigma_e2", "kpm_set_timing", "kpm_get_stats",
+               "kpm_reset_stats", "kpm_last_error", "kpm_version")
+
+
+class KpmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"kpm status {status}: {msg}")
+        self.status = status
+
+
+class _Desc(C.Structure):
+    _fields_ = [("n_sites", C.c_int64), ("width", C.c_int32),
+                ("nbr", C.POINTER(C.c_int32)), ("hop", C.POINTER(C.c_double)),
+                ("t_uniform", C.c_double), ("onsite", C.POINTER(C.c_double)),
+                ("dx", C.POINTER(C.c_double)), ("active", C.POINTER(C.c_uint8)),
+                ("e_scale", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("step_ms", C.c_double), ("step_launches", C.c_int64),
+                ("step_rows", C.c_int64), ("site_updates", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libkpm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1307_0288_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int64
+        sig = {
+            "kpm_build_graphene": [i64, i64, C.c_int, C.POINTER(C.c_uint8), C.POINTER(C.c_int32), dp],
+            "kpm_system_create": [C.POINTER(_Desc), C.c_int, C.c_int, vp, C.POINTER(vp)],
+            "kpm_system_destroy": [vp],
+            "kpm_system_set_stream": [vp, vp],
+            "kpm_moments": [vp, C.c_int, vp, vp, C.c_int, dp],
+            "kpm_evolve": [vp, C.c_int, vp, C.c_double, C.c_int, C.c_int],
+            "kpm_evolve_x": [vp, C.c_int, vp, vp, vp, C.c_double, C.c_int],
+            "kpm_vac": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, C.c_int, dp],
+            "kpm_msd": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, C.c_int, dp],
+            "kpm_kpm_sum": [C.c_int, C.c_int, dp, C.c_int, dp, C.c_double, C.c_double,
+                            C.c_int, vp, dp],
+            "kpm_sigma_gk": [C.c_int, C.c_int, dp, C.c_double, dp],
+            "kpm_sigma_e1": [C.c_int, C.c_int, dp, C.c_double, dp],
+            "kpm_sigma_e2": [C.c_int, C.c_int, dp, C.c_double, dp],
+            "kpm_set_timing": [vp, C.c_int],
+            "kpm_get_stats": [vp, C.POINTER(Stats)],
+            "kpm_reset_stats": [vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.kpm_system_n_sites.argtypes = [vp]
+        L.kpm_system_n_sites.restype = C.c_int64
+        L.kpm_last_error.restype = C.c_char_p
+        L.kpm_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != KPM_OK:
+        raise KpmError(status, lib().kpm_last_error().decode())
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ------------------------------------------------------------------ host helpers
+def kpm_build_graphene(nx: int, ny: int, geometry: str = "sheet", active=None):
+    """Neighbour list [3][nx*ny] (int32, -1 empty) and dx [3][nx*ny] (nm)."""
+    n = nx * ny
+    nbr = np.empty((3, n), dtype=np.int32)
+    dx = np.empty((3, n), dtype=np.float64)
+    act = None if active is None else np.ascontiguousarray(active, dtype=np.uint8)
+    _check(lib().kpm_build_graphene(nx, ny, GEOMETRIES[geometry],
+                                    None if act is None else act.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                    nbr.ctypes.data_as(C.POINTER(C.c_int32)), _dp(dx)))
+    return nbr, dx
+
+
+def kpm_kpm_sum(moments, energies_ev, e_scale: float, area_nm2: float, jackson: bool = True):
+    """KPM sum of Eq. 29-31 on the device: moments [rows, N_m] -> [rows, K]."""
+    mom = np.ascontiguousarray(np.real(moments), dtype=np.float64)
+    squeeze = mom.ndim == 1
+    mom = mom.reshape(-1, mom.shape[-1])
+    en = np.ascontiguousarray(energies_ev, dtype=np.float64).reshape(-1)
+    out = np.empty((mom.shape[0], en.shape[0]))
+    _check(lib().kpm_kpm_sum(mom.shape[0], mom.shape[1], _dp(mom), en.shape[0], _dp(en),
+                             e_scale, area_nm2, int(bool(jackson)), _stream(), _dp(out)))
+    return out[0] if squeeze else out
+
+
+def _sigma(fn, rows, dt_fs):
+    a = np.ascontiguousarray(rows, dtype=np.float64)
+    a2 = a.reshape(a.shape[0], -1)
+    out = np.empty_like(a2)
+    _check(fn(a2.shape[0], a2.shape[1], _dp(a2), dt_fs, _dp(out)))
+    return out.reshape(a.shape)
+
+
+def kpm_sigma_gk(rho_vac, dt_fs):
+    """sigma_GK(E, t_k) / (e^2/h) from rho*C_vv [T, K] (Eq. 6)."""
+    return _sigma(lib().kpm_sigma_gk, rho_vac, dt_fs)
+
+
+def kpm_sigma_e1(rho_msd, dt_fs):
+    """sigma_E1(E, t_k) / (e^2/h) from rho*MSD [T, K] (Eq. 9)."""
+    return _sigma(lib().kpm_sigma_e1, rho_msd, dt_fs)
+
+
+def kpm_sigma_e2(rho_msd, dt_fs):
+    """sigma_E2(E, t_k) / (e^2/h) from rho*MSD [T, K] (Eq. 11)."""
+    return _sigma(lib().kpm_sigma_e2, rho_msd, dt_fs)
+
+
+# ------------------------------------------------------------------ system
+class System:
+    """A Hamiltonian resident on one GPU (wraps kpm_system_create)."""
+
+    def __init__(self, nbr, e_scale: float, t_uniform: float = -2.7, hop=None, onsite=None,
+                 dx=None, active=None, precision: str = "fp64", device: int | None = None):
+        import torch
+        nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+        if nbr.ndim != 2:
+            raise ValueError("nbr must be [width][n_sites]")
+        self.width, self.n_sites = nbr.shape
+        keep = [nbr]
+
+        def arr(a, dt, shape):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(a, dtype=dt)
+            if a.shape != shape:
+                raise ValueError(f"array shape {a.shape} != {shape}")
+            keep.append(a)
+            return a
+
+        hop = arr(hop, np.float64, nbr.shape)
+        onsite = arr(onsite, np.float64, (self.n_sites,))
+        dx = arr(dx, np.float64, nbr.shape)
+        active = arr(active, np.uint8, (self.n_sites,))
+        d = _Desc(self.n_sites, self.width, nbr.ctypes.data_as(C.POINTER(C.c_int32)), _dp(hop),
+                  t_uniform, _dp(onsite), _dp(dx),
+                  None if active is None else active.ctypes.data_as(C.POINTER(C.c_uint8)),
+                  e_scale)
+        self.precision = precision
+        self.e_scale = float(e_scale)
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self._h = C.c_void_p()
+        prec = KPM_FP64 if precision == "fp64" else KPM_FP32_STATES
+        with torch.cuda.device(self.device):
+            _check(lib().kpm_system_create(C.byref(d), prec, self.device, _stream(),
+                                           C.byref(self._h)))
+        self.cdtype = torch.complex128 if precision == "fp64" else torch.complex64
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().kpm_system_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _sync_stream(self):
+        _check(lib().kpm_system_set_stream(self._h, _stream()))
+
+    def _state(self, t, name):
+        """(data pointer, n_vec) of a state tensor, after checking it."""
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a GPU tensor")
+        if t.dtype in (torch.float64, torch.float32):
+            if t.dim() != 3 or t.shape[-1] != 2:
+                raise ValueError(f"{name}: real view must be [n_sites, n_vec, 2]")
+            t = torch.view_as_complex(t)
+        if t.dtype != self.cdtype:
+            raise TypeError(f"{name} must be {self.cdtype} for a {self.precision} system")
+        if t.dim() == 1:
+            t = t.unsqueeze(1)
+        if t.dim() != 2 or t.shape[0] != self.n_sites or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous [n_sites={self.n_sites}, n_vec]")
+        if t.device.index != self.device:
+            raise ValueError(f"{name} is on device {t.device.index}, system on {self.device}")
+        return C.c_void_p(t.data_ptr()), int(t.shape[1])
+
+    def new_state(self, n_vec: int = 1):
+        import torch
+        return torch.zeros((self.n_sites, n_vec), dtype=self.cdtype, device=f"cuda:{self.device}")
+
+    def upload(self, phi):
+        """Host complex array [n_sites] or [n_sites, n_vec] -> device state tensor."""
+        import torch
+        a = np.asarray(phi)
+        if a.ndim == 1:
+            a = a[:, None]
+        npdt = np.complex128 if self.precision == "fp64" else np.complex64
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=npdt)).to(f"cuda:{self.device}")
+
+
+def kpm_moments(sys: System, phi_l, phi_r, n_moments: int) -> np.ndarray:
+    """C_m = <phi_L|T_m(H~)|phi_R>, complex128 [n_vec, n_moments] (Eq. 46)."""
+    pl, nv = sys._state(phi_l, "phi_l")
+    pr, nv2 = sys._state(phi_r, "phi_r")
+    if nv != nv2:
+        raise ValueError("phi_l and phi_r differ in n_vec")
+    out = np.empty((nv, n_moments, 2))
+    sys._sync_stream()
+    _check(lib().kpm_moments(sys.handle, nv, pl, pr, n_moments, _dp(out)))
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def kpm_evolve(sys: System, phi, dt_fs: float, sign: int, n_bessel: int):
+    """phi <- U(sign dt) phi in place (Eq. 36)."""
+    p, nv = sys._state(phi, "phi")
+    sys._sync_stream()
+    _check(lib().kpm_evolve(sys.handle, nv, p, dt_fs, sign, n_bessel))
+    return phi
+
+
+def kpm_evolve_x(sys: System, phi, out_x, out_u, dt_fs: float, n_bessel: int):
+    """out_x <- [X, U(dt)] phi, out_u <- U(dt) phi (Eq. 37); out_u may be None."""
+    p, nv = sys._state(phi, "phi")
+    px, nx_ = sys._state(out_x, "out_x")
+    pu = None
+    if out_u is not None:
+        pu, nu = sys._state(out_u, "out_u")
+        if nu != nv:
+            raise ValueError("n_vec mismatch")
+    if nx_ != nv:
+        raise ValueError("n_vec mismatch")
+    sys._sync_stream()
+    _check(lib().kpm_evolve_x(sys.handle, nv, p, px, pu, dt_fs, n_bessel))
+
+
+def _loop(fn, sys, phi, n_steps, dt_fs, n_bessel, n_moments):
+    p, nv = sys._state(phi, "phi")
+    out = np.empty((nv, n_steps + 1, n_moments))
+    sys._sync_stream()
+    _check(fn(sys.handle, nv, p, n_steps, dt_fs, n_bessel, n_moments, _dp(out)))
+    return out
+
+
+def kpm_vac(sys: System, phi, n_steps: int, dt_fs: float, n_bessel: int, n_moments: int):
+    """VAC moments [n_vec, n_steps+1, n_moments] in nm^2/fs^2 (Alg. 2)."""
+    return _loop(lib().kpm_vac, sys, phi, n_steps, dt_fs, n_bessel, n_moments)
+
+
+def kpm_msd(sys: System, phi, n_steps: int, dt_fs: float, n_bessel: int, n_moments: int):
+    """MSD moments [n_vec, n_steps+1, n_moments] in nm^2 (Alg. 3)."""
+    return _loop(lib().kpm_msd, sys, phi, n_steps, dt_fs, n_bessel, n_moments)
+
+
+def kpm_set_timing(sys: System, enable: bool = True):
+    _check(lib().kpm_set_timing(sys.handle, int(bool(enable))))
+
+
+def kpm_get_stats(sys: System) -> dict:
+    s = Stats()
+    _check(lib().kpm_get_stats(sys.handle, C.byref(s)))
+    return dict(step_ms=s.step_ms, step_launches=s.step_launches, step_rows=s.step_rows,
+                site_updates=s.site_updates)
+
+
+def kpm_reset_stats(sys: System):
+    _check(lib().kpm_reset_stats(sys.handle))
+
+
+def graphene_system(nx: int, ny: int, geometry: str = "sheet", t_ev: float = -2.7,
+                    onsite=None, active=None, e_scale: float | None = None,
+                    precision: str = "fp64", device: int | None = None) -> System:
+    """System for an nx x ny graphene sample (Sec. 2), built with kpm_build_graphene."""
+    nbr, dx = kpm_build_graphene(nx, ny, geometry, active)
+    if e_scale is None:
+        wmax = 0.0 if onsite is None else float(np.max(np.abs(onsite)))
+        e_scale = 1.01 * (3 * abs(t_ev) + wmax)
+    s = System(nbr, e_scale, t_uniform=t_ev, onsite=onsite, dx=dx, active=active,
+               precision=precision, device=device)
+    s.nx, s.ny, s.geometry = nx, ny, geometry
+    lx = np.sqrt(3.0) * nx * BOND_NM / 2.0
+    ly = 3.0 * ny * BOND_NM / 2.0
+    s.area_nm2 = lx * ly
+    s.width_nm = lx if geometry == "agnr" else ly
+    return s

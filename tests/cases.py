@@ -1,0 +1,35 @@
+"""Matched test inputs: one seeded recipe feeds both the oracle and the GPU library."""
+import numpy as np
+
+import kpm_inputs as ki
+import oracle
+
+
+def recipe(geometry, nx, ny, w=0.0, vac=0.0, seed=0, e_scale=None):
+    """Seeded on-site disorder, vacancies and E_s for an nx x ny sample."""
+    n = nx * ny
+    act = ki.vacancy_mask(n, vac, 2000 + seed) if vac else None
+    ons = ki.anderson_onsite(n, w, 1000 + seed)
+    es = 1.01 * (3 * 2.7 + w / 2) if e_scale is None else e_scale
+    return dict(geometry=geometry, nx=nx, ny=ny, onsite=ons, active=act, e_scale=es)
+
+
+def oracle_lattice(c):
+    return oracle.graphene(c["nx"], c["ny"], c["geometry"], -2.7, c["onsite"], c["active"])
+
+
+def gpu_system(c, precision="fp64"):
+    import paper_1307_0288_amd as kp
+    return kp.graphene_system(c["nx"], c["ny"], c["geometry"], -2.7, c["onsite"], c["active"],
+                              c["e_scale"], precision)
+
+
+def phases(c, n_vec=1, seed=3000):
+    act = c["active"]
+    return ki.random_phase(c["nx"] * c["ny"], n_vec, seed, act)
+
+
+def rel_err(got, ref, scale=None):
+    got, ref = np.asarray(got), np.asarray(ref)
+    s = np.max(np.abs(ref)) if scale is None else scale
+    return float(np.max(np.abs(got - ref)) / s) if s > 0 else float(np.max(np.abs(got - ref)))

@@ -1,0 +1,281 @@
+"""Parity of the gfx950 library (through its C ABI) with the CPU oracle.
+
+Tolerances (FP64): moments max|dC| / (|phi_L| |phi_R|) <= 1e-10; VAC/MSD
+moments max|dC| / max|C| <= 1e-10; sigma(E) max|d sigma| / max|sigma| <= 1e-8.
+FP32 states (FP64 arithmetic and dots): sigma error <= 1e-3.
+"""
+import numpy as np
+import pytest
+
+import kpm_inputs as ki
+import oracle
+from cases import gpu_system, oracle_lattice, phases, recipe, rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+kp = pytest.importorskip("paper_1307_0288_amd")
+
+HBAR = oracle.HBAR_EV_FS
+SMALL = ki.sheet_config("small")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def small():
+    _need_gpu()
+    c = recipe("sheet", SMALL["nx"], SMALL["ny"], w=SMALL["w"], e_scale=SMALL["e_scale"])
+    return c, oracle_lattice(c), gpu_system(c)
+
+
+# ------------------------------------------------------------------ moments
+def test_moments_small_config(small):
+    c, lat, sysg = small
+    _log("moments small 2048 sites 500 moments")
+    phi = phases(c)
+    ref = oracle.moments(lat, c["e_scale"], phi[:, 0], phi[:, 0], SMALL["n_moments"])
+    d = sysg.upload(phi)
+    got = kp.kpm_moments(sysg, d, d, SMALL["n_moments"])[0]
+    scale = np.vdot(phi, phi).real
+    assert rel_err(got, ref, scale) < 1e-10
+    assert abs(got[0] - lat.n) < 1e-9
+
+
+@pytest.mark.parametrize("geometry,nx,ny,w,vac,nm", [
+    ("sheet", 64, 32, 1.0, 0.02, 300),    # vacancies
+    ("agnr", 7, 6, 2.0, 0.0, 50),         # 42 rows: one ragged block
+    ("zgnr", 10, 13, 0.5, 0.05, 64),      # 130 rows
+    ("sheet", 100, 50, 0.1, 0.005, 200),  # 5000 rows: several blocks and a ragged tail
+    ("sheet", 8, 4, 1.0, 0.0, 1),         # only C_0
+    ("sheet", 8, 4, 1.0, 0.0, 2),         # C_0 and C_1
+    ("sheet", 8, 4, 1.0, 0.0, 3),
+])
+def test_moments_left_right_ragged(geometry, nx, ny, w, vac, nm):
+    _need_gpu()
+    _log(f"moments {geometry} {nx}x{ny} nm={nm}")
+    c = recipe(geometry, nx, ny, w=w, vac=vac, seed=11)
+    lat = oracle_lattice(c)
+    sysg = gpu_system(c)
+    pl = phases(c, 1, 3000)
+    pr = phases(c, 1, 3500)
+    ref = oracle.moments(lat, c["e_scale"], pl[:, 0], pr[:, 0], nm)
+    got = kp.kpm_moments(sysg, sysg.upload(pl), sysg.upload(pr), nm)[0]
+    scale = np.linalg.norm(pl) * np.linalg.norm(pr)
+    assert rel_err(got, ref, scale) < 1e-10
+
+
+@pytest.mark.parametrize("n_vec", [2, 8, 64])
+def test_moments_batched_vectors(n_vec):
+    _need_gpu()
+    _log(f"moments batched n_vec={n_vec}")
+    c = recipe("sheet", 48, 20, w=1.0, vac=0.01, seed=5)
+    lat = oracle_lattice(c)
+    sysg = gpu_system(c)
+    phi = phases(c, n_vec, 3000)
+    got = kp.kpm_moments(sysg, sysg.upload(phi), sysg.upload(phi), 100)
+    for r in range(n_vec):
+        ref = oracle.moments(lat, c["e_scale"], phi[:, r], phi[:, r], 100)
+        assert rel_err(got[r], ref, np.vdot(phi[:, r], phi[:, r]).real) < 1e-10
+
+
+def test_moments_all_sites_removed():
+    _need_gpu()
+    c = recipe("sheet", 8, 4)
+    c["active"] = np.zeros(32, np.uint8)
+    sysg = gpu_system(c)
+    z = sysg.new_state(1)
+    got = kp.kpm_moments(sysg, z, z, 10)
+    assert np.all(got == 0)
+
+
+def test_moments_deterministic(small):
+    c, lat, sysg = small
+    d = sysg.upload(phases(c, 1, 3001))
+    a = kp.kpm_moments(sysg, d, d, 200)
+    b = kp.kpm_moments(sysg, d, d, 200)
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------ propagators
+@pytest.mark.parametrize("sign,nb,dt", [(1, 30, SMALL["dt_fs"]), (-1, 30, SMALL["dt_fs"]),
+                                        (1, 2, 0.05), (1, 40, 1.0)])
+def test_evolve(small, sign, nb, dt):
+    c, lat, sysg = small
+    _log(f"evolve sign={sign} nb={nb} dt={dt}")
+    phi = phases(c, 1, 3002)
+    ref = oracle.evolve(lat, c["e_scale"], phi[:, 0], dt, sign, nb)
+    d = sysg.upload(phi)
+    kp.kpm_evolve(sysg, d, dt, sign, nb)
+    got = d.cpu().numpy()[:, 0]
+    assert rel_err(got, ref) < 1e-12
+
+
+def test_evolve_zero_time_is_identity(small):
+    c, lat, sysg = small
+    phi = phases(c, 1, 3003)
+    d = sysg.upload(phi)
+    kp.kpm_evolve(sysg, d, 0.0, 1, 10)
+    assert np.array_equal(d.cpu().numpy(), phi)
+
+
+@pytest.mark.parametrize("geometry,nx,ny", [("sheet", 64, 32), ("zgnr", 10, 13), ("agnr", 9, 8)])
+def test_evolve_x(geometry, nx, ny):
+    _need_gpu()
+    _log(f"evolve_x {geometry}")
+    c = recipe(geometry, nx, ny, w=1.0, vac=0.02, seed=7)
+    lat = oracle_lattice(c)
+    sysg = gpu_system(c)
+    phi = phases(c, 1, 3004)
+    rx, ru = oracle.evolve_x(lat, c["e_scale"], phi[:, 0], SMALL["dt_fs"], 30)
+    d = sysg.upload(phi)
+    ox, ou = sysg.new_state(1), sysg.new_state(1)
+    kp.kpm_evolve_x(sysg, d, ox, ou, SMALL["dt_fs"], 30)
+    assert rel_err(ox.cpu().numpy()[:, 0], rx) < 1e-12
+    assert rel_err(ou.cpu().numpy()[:, 0], ru) < 1e-12
+
+
+# ------------------------------------------------------------------ VAC / MSD / sigma
+@pytest.fixture(scope="module")
+def loops(small):
+    c, lat, sysg = small
+    phi = phases(c, 1, 3000)
+    args = (SMALL["n_steps"], SMALL["dt_fs"], SMALL["n_bessel"], SMALL["n_moments"])
+    _log("vac/msd oracle small")
+    rv = oracle.vac(lat, c["e_scale"], phi[:, 0], *args)
+    rm = oracle.msd(lat, c["e_scale"], phi[:, 0], *args)
+    _log("vac/msd gpu small")
+    d = sysg.upload(phi)
+    gv = kp.kpm_vac(sysg, d, *args)[0]
+    gm = kp.kpm_msd(sysg, d, *args)[0]
+    return c, lat, rv, rm, gv, gm
+
+
+def test_vac_small_config(loops):
+    c, lat, rv, rm, gv, gm = loops
+    assert rel_err(gv, rv) < 1e-10
+
+
+def test_msd_small_config(loops):
+    c, lat, rv, rm, gv, gm = loops
+    assert np.all(gm[0] == 0)
+    assert rel_err(gm, rm) < 1e-10
+
+
+def test_sigma_small_config(loops):
+    """DOS, sigma_GK, sigma_E1, sigma_E2 on an energy grid: device KPM sum +
+    library conductivities vs the oracle's reconstruction."""
+    c, lat, rv, rm, gv, gm = loops
+    es, area, dt = c["e_scale"], lat.area_nm2, SMALL["dt_fs"]
+    en = oracle.energies_grid(257, es)
+    r_gk = oracle.sigma_gk(oracle.kpm_sum(rv, en, es, area), dt)
+    r_e1 = oracle.sigma_e1(oracle.kpm_sum(rm, en, es, area), dt)
+    r_e2 = oracle.sigma_e2(oracle.kpm_sum(rm, en, es, area), dt)
+    g_gk = kp.kpm_sigma_gk(kp.kpm_kpm_sum(gv, en, es, area), dt)
+    g_e1 = kp.kpm_sigma_e1(kp.kpm_kpm_sum(gm, en, es, area), dt)
+    g_e2 = kp.kpm_sigma_e2(kp.kpm_kpm_sum(gm, en, es, area), dt)
+    for g, r in ((g_gk, r_gk), (g_e1, r_e1), (g_e2, r_e2)):
+        assert rel_err(g, r) < 1e-8
+
+
+def test_dos_device_sum(small):
+    c, lat, sysg = small
+    phi = phases(c, 1, 3000)
+    mu = oracle.moments(lat, c["e_scale"], phi[:, 0], phi[:, 0], 500).real
+    en = oracle.energies_grid(1001, c["e_scale"])
+    ref = oracle.dos(mu, en, c["e_scale"], lat.area_nm2)
+    got = kp.kpm_kpm_sum(mu, en, c["e_scale"], lat.area_nm2)
+    assert rel_err(got, ref) < 1e-12
+
+
+def test_fp32_states_sigma_within_1e3(small):
+    c, lat, sys64 = small
+    _log("fp32 states small loops")
+    sys32 = gpu_system(c, "fp32")
+    phi = phases(c, 1, 3000)
+    args = (SMALL["n_steps"], SMALL["dt_fs"], SMALL["n_bessel"], SMALL["n_moments"])
+    rv = oracle.vac(lat, c["e_scale"], phi[:, 0], *args)
+    d = sys32.upload(phi)
+    gv = kp.kpm_vac(sys32, d, *args)[0]
+    es, area, dt = c["e_scale"], lat.area_nm2, SMALL["dt_fs"]
+    en = oracle.energies_grid(257, es)
+    r = oracle.sigma_gk(oracle.kpm_sum(rv, en, es, area), dt)
+    g = kp.kpm_sigma_gk(kp.kpm_kpm_sum(gv, en, es, area), dt)
+    assert rel_err(g, r) < 1e-3
+
+
+def test_invalid_calls_raise(small):
+    c, lat, sysg = small
+    d = sysg.upload(phases(c, 1, 3000))
+    with pytest.raises(kp.KpmError):
+        kp.kpm_evolve(sysg, d, 0.1, 0, 10)          # sign must be +-1
+    with pytest.raises(kp.KpmError):
+        kp.kpm_evolve(sysg, d, 0.1, 1, 1)           # n_bessel >= 2
+    with pytest.raises(kp.KpmError):
+        kp.kpm_moments(sysg, d, d, 0)               # n_moments >= 1
+    bad = torch.zeros((sysg.n_sites, 3), dtype=torch.complex128, device="cuda")
+    with pytest.raises(kp.KpmError):
+        kp.kpm_moments(sysg, bad, bad, 4)           # n_vec not a power of two
+
+
+# ------------------------------------------------------------------ paper-scale sheet
+@pytest.fixture(scope="module")
+def paper():
+    _need_gpu()
+    p = ki.sheet_config("paper")
+    c = recipe("sheet", p["nx"], p["ny"], w=p["w"], vac=p["vac"], e_scale=p["e_scale"])
+    _log("paper-scale lattice (3998792 sites)")
+    return p, c, oracle_lattice(c), gpu_system(c)
+
+
+def test_paper_scale_moments_prefix_and_properties(paper):
+    """Full 4M-site sheet in the benchmark's launch configuration: the first
+    64 moments against the oracle; all 3000 checked for properties that hold
+    at any size (C_0 = N_active, real for phi_L = phi_R, |C_m| <= C_0)."""
+    p, c, lat, sysg = paper
+    phi = phases(c, 1, 3000)
+    d = sysg.upload(phi)
+    _log("paper-scale gpu moments 3000")
+    got = kp.kpm_moments(sysg, d, d, p["n_moments"])[0]
+    n_act = int(np.count_nonzero(c["active"]))
+    assert abs(got[0] - n_act) < 1e-6
+    assert np.max(np.abs(got.imag)) < 1e-8 * n_act
+    assert np.all(np.abs(got.real) <= n_act * (1 + 1e-12))
+    _log("paper-scale oracle moments 64")
+    ref = oracle.moments(lat, c["e_scale"], phi[:, 0], phi[:, 0], 64)
+    assert rel_err(got[:64], ref, n_act) < 1e-10
+
+
+def test_paper_scale_vac_msd_one_step(paper):
+    p, c, lat, sysg = paper
+    phi = phases(c, 1, 3000)
+    d = sysg.upload(phi)
+    args = (1, p["dt_fs"], p["n_bessel"], 16)
+    _log("paper-scale gpu vac/msd 1 step")
+    gv = kp.kpm_vac(sysg, d, *args)[0]
+    gm = kp.kpm_msd(sysg, d, *args)[0]
+    _log("paper-scale oracle vac/msd 1 step")
+    rv = oracle.vac(lat, c["e_scale"], phi[:, 0], *args)
+    rm = oracle.msd(lat, c["e_scale"], phi[:, 0], *args)
+    assert rel_err(gv, rv) < 1e-10
+    assert rel_err(gm, rm) < 1e-10
+
+
+def test_paper_scale_evolve_norm(paper):
+    p, c, lat, sysg = paper
+    phi = phases(c, 1, 3005)
+    d = sysg.upload(phi)
+    n0 = float(torch.vdot(d[:, 0], d[:, 0]).real)
+    kp.kpm_evolve(sysg, d, p["dt_fs"], 1, p["n_bessel"])
+    n1 = float(torch.vdot(d[:, 0], d[:, 0]).real)
+    assert abs(n1 - n0) < 1e-10 * n0
+    kp.kpm_evolve(sysg, d, p["dt_fs"], -1, p["n_bessel"])
+    back = d.cpu().numpy()
+    assert np.max(np.abs(back - phi)) < 1e-11
