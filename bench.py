@@ -83,6 +83,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-moments", type=int, default=800,
                     help="moments in the oracle's CPU-baseline sample (0 skips it)")
+    ap.add_argument("--workload", default="paper", choices=["paper", "batched"],
+                    help="paper: plain FP64, one vector (default); batched: 64 vectors, "
+                         "FP32 states vs FP64")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -95,6 +98,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.workload == "batched":
+        return batched(args)
 
     p = ki.sheet_config("paper")
     n = p["nx"] * p["ny"]
@@ -105,6 +110,8 @@ def main():
     sysg = kp.graphene_system(p["nx"], p["ny"], "sheet", p["t"], ons, act, p["e_scale"], "fp64")
     phi = sysg.upload(phi_h)
     nm, ns, nb, dt = p["n_moments"], p["n_steps"], p["n_bessel"], p["dt_fs"]
+    launch = kp.kpm_autotune(sysg, phi, 30)
+    log(f"autotuned launch shape: {launch}")
 
     def step():
         kp.kpm_moments(sysg, phi, phi, nm)
@@ -160,8 +167,88 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_site_update": BYTES_PER_SITE_UPDATE_FP64,
                      "avg_launch_us": round(launch_ms * 1e3, 3),
-                     "launches": st["step_launches"]},
+                     "launches": st["step_launches"], "launch_shape": launch},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def batched(args):
+    """64 random vectors per Chebyshev step on the paper-scale sheet: FP32 states
+    (FP64 arithmetic, inner products and moments) against FP64 states.
+
+    Timed: 3000 moments for all 64 vectors (one sparse-matrix x 64-vector product
+    per step).  Error: sigma_GK (from the VAC) and sigma_E1 (from the MSD) at 2048
+    energies and t = dt, 2 dt, averaged over the 64 vectors, FP32 vs FP64.
+    """
+    import torch
+    import paper_1307_0288_amd as kp
+    p = ki.sheet_config("paper")
+    n = p["nx"] * p["ny"]
+    r = 64
+    log(f"batched inputs: {n} sites x {r} vectors")
+    act = ki.vacancy_mask(n, p["vac"], 2000)
+    ons = ki.anderson_onsite(n, p["w"], 1000)
+    phi_h = ki.random_phase(n, r, 3000, act)
+    nm, nb, dt = p["n_moments"], p["n_bessel"], p["dt_fs"]
+    res = {}
+    sig = {}
+    en = np.linspace(-0.95 * p["e_scale"], 0.95 * p["e_scale"], 2048)
+    for prec in ("fp64", "fp32"):
+        sysg = kp.graphene_system(p["nx"], p["ny"], "sheet", p["t"], ons, act, p["e_scale"], prec)
+        phi = sysg.upload(phi_h)
+        res_launch = kp.kpm_autotune(sysg, phi, 5)
+        log(f"{prec} autotuned launch shape: {res_launch}")
+        kp.kpm_moments(sysg, phi, phi, 64)                      # warm-up
+        kp.kpm_reset_stats(sysg)
+        kp.kpm_set_timing(sysg, True)
+        torch.cuda.synchronize()
+        times = []
+        for k in range(max(args.steps, 1)):
+            t0 = time.perf_counter()
+            kp.kpm_moments(sysg, phi, phi, nm)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            log(f"{prec} moments run {k + 1}: {times[-1]:.3f} s")
+        st = kp.kpm_get_stats(sysg)
+        kp.kpm_set_timing(sysg, False)
+        ups = (nm - 1) * n * r
+        launch_ms = st["step_ms"] / max(st["step_launches"], 1)
+        res[prec] = dict(seconds=min(times), gsu=ups / min(times) / 1e9,
+                         launch_us=launch_ms * 1e3, launch=res_launch)
+        log(f"{prec} sigma runs (VAC + MSD, 2 steps)")
+        vac = kp.kpm_vac(sysg, phi, 2, dt, nb, nm).mean(axis=0)
+        msd = kp.kpm_msd(sysg, phi, 2, dt, nb, nm).mean(axis=0)
+        rho_v = kp.kpm_kpm_sum(vac, en, p["e_scale"], sysg.area_nm2)
+        rho_m = kp.kpm_kpm_sum(msd, en, p["e_scale"], sysg.area_nm2)
+        sig[prec] = (kp.kpm_sigma_gk(rho_v, dt), kp.kpm_sigma_e1(rho_m, dt))
+        sysg.close()
+        del phi
+        torch.cuda.empty_cache()
+    err_gk = float(np.max(np.abs(sig["fp32"][0] - sig["fp64"][0])) / np.max(np.abs(sig["fp64"][0])))
+    err_e1 = float(np.max(np.abs(sig["fp32"][1] - sig["fp64"][1])) / np.max(np.abs(sig["fp64"][1])))
+    bpu = {"fp64": 64 + 20 / r, "fp32": 32 + 20 / r}
+    out = {
+        "metric": "Gsite-updates/s (batched Chebyshev moments, 64 vectors, FP32 states)",
+        "value": round(res["fp32"]["gsu"], 3), "unit": "Gsite-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": round(res["fp32"]["seconds"] * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32-states/f64-dots",
+        "data": "synthetic",
+        "config": {"workload": "graphene sheet 2828x1414 sites, 0.5% vacancies, W=0.1 eV, 64 "
+                               "random-phase vectors per step, 3000 moments", "n_sites": n,
+                   "n_vec": r},
+        "fp64_batched_gsu": round(res["fp64"]["gsu"], 3),
+        "speedup_fp32_vs_fp64": round(res["fp32"]["gsu"] / res["fp64"]["gsu"], 3),
+        "sigma_rel_err_fp32_vs_fp64": {"gk": err_gk, "e1": err_e1,
+                                       "energies": 2048, "times": "dt, 2dt"},
+        "roofline": {prec: {"bound": "hbm", "bytes_per_site_update": round(bpu[prec], 3),
+                            "avg_launch_us": round(res[prec]["launch_us"], 2),
+                            "launch_shape": res[prec]["launch"],
+                            "achieved": round(bpu[prec] * n * r / (res[prec]["launch_us"] * 1e-6) / 1e9, 1),
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": round(bpu[prec] * n * r / (res[prec]["launch_us"] * 1e-6) / 1e9
+                                          / HBM_PEAK_GBS, 4)}
+                     for prec in ("fp64", "fp32")},
     }
     print(json.dumps(out), flush=True)
 

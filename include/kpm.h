@@ -201,6 +201,35 @@ kpm_status kpm_sigma_e2(int n_times, int n_energies, const double *rho_msd,
                         double dt_fs, double *out);
 
 /*
+ * Launch shape of the Chebyshev moment step for a given n_vec: work-groups
+ * per compute unit of the persistent grid (1..32; the grid is rounded to a
+ * multiple of the 8 XCDs), elements per thread per pass (ilp: 1, 2 or 4) and
+ * streaming (non-temporal) access to the operands read or written once per
+ * step (0 or 1).  At a fixed grid size the moments are bit-identical for
+ * every ilp and streaming choice; the grid size changes only the order of
+ * the inner-product partial sums.
+ */
+typedef struct {
+    int32_t groups_per_cu;
+    int32_t ilp;
+    int32_t streaming;
+} kpm_launch;
+
+kpm_status kpm_set_launch(kpm_system *sys, int n_vec, const kpm_launch *launch);
+kpm_status kpm_get_launch(kpm_system *sys, int n_vec, kpm_launch *out);
+
+/*
+ * Autotuner: times `reps` moment steps of every candidate shape
+ * (groups_per_cu in {4, 8, 16} x ilp in {1, 2, 4} x streaming in {0, 1}) on
+ * the device state
+ * `phi` ([n_sites][n_vec], read only; only system scratch is written), keeps
+ * the fastest for this n_vec and returns it in *best (may be NULL).
+ * Synchronises the stream.
+ */
+kpm_status kpm_autotune(kpm_system *sys, int n_vec, const void *phi, int reps,
+                        kpm_launch *best);
+
+/*
  * Timing of the hot recursion kernel.  When enabled, the library brackets
  * every uninterrupted run of Chebyshev moment steps with HIP events on the
  * system's stream and accumulates their elapsed time and launch count.

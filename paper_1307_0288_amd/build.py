@@ -33,7 +33,7 @@ def flags() -> list:
     return [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
             # packed fp32 instructions stay off (build notes)
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wall"]
+            "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wall", "-ffp-contract=off"]
 
 
 def build(verbose: bool = False) -> str:

@@ -21,6 +21,7 @@ namespace {
 constexpr double kHbar = 0.6582119569;   // eV fs
 constexpr double kBond = 0.142;          // nm, carbon-carbon distance (Sec. 2)
 constexpr double kPi = 3.14159265358979323846;
+constexpr int kPartialRing = 256;     // moment slots of group partials kept at once
 
 thread_local std::string g_err;
 
@@ -85,6 +86,22 @@ struct DeviceGuard {
     }
 };
 
+bool valid_launch(const kpm_launch &l) {
+    return l.groups_per_cu >= 1 && l.groups_per_cu <= 32 &&
+           (l.ilp == 1 || l.ilp == 2 || l.ilp == 4) && (l.streaming == 0 || l.streaming == 1);
+}
+
+// Launch shape used until kpm_autotune or kpm_set_launch picks another.
+kpm_launch default_launch(int vshift) {
+    kpm_launch l;
+    // measured on MI355X (paper-scale sheet): one vector favours 4 groups per
+    // CU, many vectors 8; streaming helps every vector count
+    l.groups_per_cu = vshift == 0 ? 4 : 8;
+    l.ilp = vshift >= 6 ? 4 : 1;
+    l.streaming = 1;
+    return l;
+}
+
 }  // namespace
 
 struct kpm_system {
@@ -96,7 +113,7 @@ struct kpm_system {
     double e_scale = 1;
     bool has_dx = false;
     int cus = 256;
-    int wg_per_cu = 8;
+    kpm_launch launch[7];       // launch shape of the moment step per log2(n_vec)
     // device Hamiltonian
     int32_t *d_nbr = nullptr;
     double *d_hop = nullptr;
@@ -130,16 +147,18 @@ struct kpm_system {
         return h;
     }
 
-    int grid_for(int64_t total) const {
+    int grid_for(int64_t total, int groups_per_cu) const {
         int64_t nblk = (total + kpm::kBlock - 1) / kpm::kBlock;
-        int64_t g = (int64_t)cus * wg_per_cu;
+        int64_t g = (int64_t)cus * groups_per_cu;
         g = std::min<int64_t>(g, ((nblk + kpm::kXcds - 1) / kpm::kXcds) * kpm::kXcds);
         g = std::max<int64_t>(g, kpm::kXcds);
         return (int)(g - g % kpm::kXcds);
     }
 
-    kpm::Sweep sweep(int vshift) const {
-        return kpm::make_sweep(n, vshift, grid_for(n << vshift));
+    kpm::Sweep sweep(int vshift) const { return sweep_with(vshift, launch[vshift]); }
+
+    kpm::Sweep sweep_with(int vshift, const kpm_launch &l) const {
+        return kpm::make_sweep(n, vshift, grid_for(n << vshift, l.groups_per_cu), l.ilp, l.streaming);
     }
 
     // Makes sure `count` state vectors of n_vec vectors each exist.
@@ -227,35 +246,42 @@ kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir
                        V *a_buf, V *b_buf, int64_t stride_r, int64_t offset) {
     const kpm::Ell h = sys->ell();
     const kpm::Sweep sw = sys->sweep(vshift);
-    const int slots = std::max(nm, 2);
-    KPM_TRY(sys->ensure_partial(slots, sw.nwg, 1 << vshift));
+    // Group partials live in a ring of kPartialRing moment slots that is
+    // reduced into sys->dmom whenever it fills, bounding its size at any N_m.
+    const int ring = std::min(std::max(nm, 2), kPartialRing);
+    KPM_TRY(sys->ensure_partial(ring, sw.nwg, 1 << vshift));
     hipStream_t s = sys->stream;
     // C_0 and C_1 (phi_0 = phi_R, phi_1 = H~ phi_0)
     kpm::launch_moment_step<V>(h, sw, true, phir, nullptr, a_buf, phil, sys->partial, 0, s);
     sys->stats.site_updates += sw.total;
-    if (nm > 2) {
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (sys->timing) {
-            KPM_TRY(sys->event_pair(&e0, &e1));
-            KPM_HIP(hipEventRecord(e0, s));
+    // phi_m = 2 H~ phi_{m-1} - phi_{m-2}, in place after the first step
+    const V *p0 = phir;
+    V *p1 = a_buf;
+    for (int c0 = 0; c0 < nm; c0 += ring) {
+        const int c1 = std::min(nm, c0 + ring);
+        const int m0 = std::max(c0, 2);
+        if (m0 < c1) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (sys->timing) {
+                KPM_TRY(sys->event_pair(&e0, &e1));
+                KPM_HIP(hipEventRecord(e0, s));
+            }
+            for (int m = m0; m < c1; ++m) {
+                V *out = (m == 2) ? b_buf : const_cast<V *>(p0);
+                kpm::launch_moment_step<V>(h, sw, false, p1, p0, out, phil, sys->partial, m - c0, s);
+                p0 = p1;
+                p1 = out;
+            }
+            if (sys->timing) {
+                KPM_HIP(hipEventRecord(e1, s));
+                sys->stats.step_launches += c1 - m0;
+                sys->stats.step_rows = sw.total;
+            }
+            sys->stats.site_updates += (int64_t)(c1 - m0) * sw.total;
         }
-        // phi_m = 2 H~ phi_{m-1} - phi_{m-2}, in place after the first step
-        const V *p0 = phir;
-        V *p1 = a_buf;
-        for (int m = 2; m < nm; ++m) {
-            V *out = (m == 2) ? b_buf : const_cast<V *>(p0);
-            kpm::launch_moment_step<V>(h, sw, false, p1, p0, out, phil, sys->partial, m, s);
-            p0 = p1;
-            p1 = out;
-        }
-        if (sys->timing) {
-            KPM_HIP(hipEventRecord(e1, s));
-            sys->stats.step_launches += nm - 2;
-            sys->stats.step_rows = sw.total;
-        }
-        sys->stats.site_updates += (int64_t)(nm - 2) * sw.total;
+        kpm::launch_reduce(sys->partial, sw.nwg, vshift, c1 - c0, sys->dmom, stride_r,
+                           offset + c0, s);
     }
-    kpm::launch_reduce(sys->partial, sw.nwg, vshift, nm, sys->dmom, stride_r, offset, s);
     return KPM_OK;
 }
 
@@ -433,6 +459,70 @@ kpm_status msd_impl(kpm_system *sys, int vshift, const void *phi_v, int nsteps, 
 
 }  // namespace
 
+namespace {
+template <typename V>
+kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_launch *best) {
+    KPM_TRY(sys->ensure_vecs(2, 1 << vs));
+    V *a = (V *)sys->vecs[0], *b = (V *)sys->vecs[1];
+    hipStream_t s = sys->stream;
+    const size_t bytes = (size_t)sys->n * ((size_t)1 << vs) * sys->elem_bytes();
+    const kpm::Ell h = sys->ell();
+    static const int groups[] = {4, 8, 16};
+    static const int ilps[] = {1, 2, 4};
+    float best_ms = 1e30f;
+    kpm_launch pick = sys->launch[vs];
+    hipEvent_t e0, e1;
+    KPM_HIP(hipEventCreate(&e0));
+    KPM_HIP(hipEventCreate(&e1));
+    kpm_status st = KPM_OK;
+    // Each candidate runs the real two-buffer recursion (the output of one
+    // step is the gathered input of the next) on copies of phi, twice; the
+    // faster round counts.
+    for (int g : groups) {
+        for (int q = 0; q < 6 && st == KPM_OK; ++q) {
+            kpm_launch l;
+            l.groups_per_cu = g;
+            l.ilp = ilps[q % 3];
+            l.streaming = q / 3;
+            const kpm::Sweep sw = sys->sweep_with(vs, l);
+            if ((st = sys->ensure_partial(1, sw.nwg, 1 << vs)) != KPM_OK) break;
+            for (int round = 0; round < 2; ++round) {
+                if (hipMemcpyAsync(a, phi, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                    hipMemcpyAsync(b, phi, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+                    st = fail(KPM_ERR_DEVICE, "autotune copy");
+                    break;
+                }
+                V *p0 = b, *p1 = a;
+                (void)hipEventRecord(e0, s);
+                for (int k = 0; k < reps; ++k) {
+                    kpm::launch_moment_step<V>(h, sw, false, p1, p0, p0, phi, sys->partial, 0, s);
+                    std::swap(p0, p1);
+                }
+                (void)hipEventRecord(e1, s);
+                if (hipEventSynchronize(e1) != hipSuccess) {
+                    st = fail(KPM_ERR_DEVICE, "autotune: %s", hipGetErrorString(hipGetLastError()));
+                    break;
+                }
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    pick = l;
+                }
+            }
+        }
+        if (st != KPM_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != KPM_OK) return st;
+    KPM_HIP(hipGetLastError());
+    sys->launch[vs] = pick;
+    if (best) *best = pick;
+    return KPM_OK;
+}
+}  // namespace
+
 // ======================================================================= ABI
 extern "C" {
 
@@ -555,7 +645,13 @@ kpm_status kpm_system_create(const kpm_system_desc *d, kpm_precision prec, int d
     sys->e_scale = d->e_scale;
     sys->has_dx = d->dx != nullptr;
     sys->t_scaled = tu / d->e_scale;
-    if (const char *env = std::getenv("KPM_WG_PER_CU")) sys->wg_per_cu = std::max(1, atoi(env));
+    for (int v = 0; v < 7; ++v) sys->launch[v] = default_launch(v);
+    if (const char *env = std::getenv("KPM_GROUPS_PER_CU"))
+        for (auto &l : sys->launch) l.groups_per_cu = std::max(1, atoi(env));
+    if (const char *env = std::getenv("KPM_ILP"))
+        for (auto &l : sys->launch) l.ilp = std::max(1, atoi(env));
+    if (const char *env = std::getenv("KPM_STREAMING"))
+        for (auto &l : sys->launch) l.streaming = atoi(env) != 0;
 
     auto bail = [&](kpm_status st) { delete sys; return st; };
     int ndev = 0;
@@ -768,6 +864,33 @@ kpm_status kpm_sigma_e2(int nt, int ne, const double *in, double dt, double *out
         for (int k = 0; k < ne; ++k)
             out[(size_t)t * ne + k] = f * in[(size_t)t * ne + k] / (t * dt);
     return KPM_OK;
+}
+
+kpm_status kpm_set_launch(kpm_system *sys, int n_vec, const kpm_launch *l) {
+    int vs;
+    KPM_TRY(check_common(sys, n_vec, &vs));
+    if (!l || !valid_launch(*l)) return fail(KPM_ERR_INVALID, "launch shape out of range");
+    sys->launch[vs] = *l;
+    return KPM_OK;
+}
+
+kpm_status kpm_get_launch(kpm_system *sys, int n_vec, kpm_launch *out) {
+    int vs;
+    KPM_TRY(check_common(sys, n_vec, &vs));
+    if (!out) return fail(KPM_ERR_INVALID, "null output");
+    *out = sys->launch[vs];
+    return KPM_OK;
+}
+
+
+kpm_status kpm_autotune(kpm_system *sys, int n_vec, const void *phi, int reps, kpm_launch *best) {
+    int vs;
+    KPM_TRY(check_common(sys, n_vec, &vs));
+    if (!phi) return fail(KPM_ERR_INVALID, "null buffer");
+    if (reps < 1 || reps > 1000) return fail(KPM_ERR_INVALID, "reps must be 1..1000");
+    DeviceGuard g(sys->device);
+    return sys->prec == KPM_FP64 ? autotune_impl<double2>(sys, vs, (const double2 *)phi, reps, best)
+                                 : autotune_impl<float2>(sys, vs, (const float2 *)phi, reps, best);
 }
 
 kpm_status kpm_set_timing(kpm_system *sys, int enable) {

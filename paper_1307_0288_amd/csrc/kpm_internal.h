@@ -34,9 +34,11 @@ struct Sweep {
     int64_t per_xcd;      // blocks per XCD range
     int nwg;              // work-groups in the grid (multiple of 8)
     int vshift;           // log2(vectors per row)
+    int ilp;              // elements per thread per pass in the moment step (1, 2, 4)
+    int nt;               // streaming (non-temporal) access to phi_0, phi_L and the output
 };
 
-Sweep make_sweep(int64_t rows, int vshift, int nwg);
+Sweep make_sweep(int64_t rows, int vshift, int nwg, int ilp, int nt);
 
 // --- launchers (all asynchronous on `s`) ----------------------------------
 // Chebyshev moment step (Alg. 5 fused with Alg. 8 and the inner product):

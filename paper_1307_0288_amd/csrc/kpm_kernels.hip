@@ -26,6 +26,31 @@ __device__ __forceinline__ void st(float2 *p, double2 v) {
     *p = make_float2((float)v.x, (float)v.y);
 }
 
+// Streaming (non-temporal) accesses for operands read or written once per
+// step, so that L2 keeps the gathered vector for the neighbour reads.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_nt(const double2 *p) {
+    d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(p));
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ double2 ld_nt(const float2 *p) {
+    f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v *>(p));
+    return make_double2((double)v.x, (double)v.y);
+}
+__device__ __forceinline__ void st_nt(double2 *p, double2 v) {
+    d2v w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, reinterpret_cast<d2v *>(p));
+}
+__device__ __forceinline__ void st_nt(float2 *p, double2 v) {
+    f2v w;
+    w.x = (float)v.x;
+    w.y = (float)v.y;
+    __builtin_nontemporal_store(w, reinterpret_cast<f2v *>(p));
+}
+
 // The value a store of v into storage type V will hold, back in double.
 template <typename V> __device__ __forceinline__ double2 rounded(double2 v);
 template <> __device__ __forceinline__ double2 rounded<double2>(double2 v) { return v; }
@@ -33,19 +58,30 @@ template <> __device__ __forceinline__ double2 rounded<float2>(double2 v) {
     return make_double2((double)(float)v.x, (double)(float)v.y);
 }
 
+// The library is compiled with -ffp-contract=off: every fused multiply-add
+// below is written out, so all launch shapes round identically.
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
     return make_double2(a.x + b.x, a.y + b.y);
 }
-__device__ __forceinline__ double2 cscale(double s, double2 a) {
-    return make_double2(s * a.x, s * a.y);
+// s + a * b
+__device__ __forceinline__ double2 cmla(double2 s, double2 a, double2 b) {
+    return make_double2(fma(a.x, b.x, fma(-a.y, b.y, s.x)), fma(a.x, b.y, fma(a.y, b.x, s.y)));
 }
 // a * b
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return cmla(make_double2(0.0, 0.0), a, b);
 }
-// conj(a) * b
-__device__ __forceinline__ double2 cdot(double2 a, double2 b) {
-    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+// s + conj(a) * b
+__device__ __forceinline__ double2 cdot_acc(double2 s, double2 a, double2 b) {
+    return make_double2(fma(a.x, b.x, fma(a.y, b.y, s.x)), fma(a.x, b.y, fma(-a.y, b.x, s.y)));
+}
+// s + h * x  (real h)
+__device__ __forceinline__ double2 raxpy(double2 s, double h, double2 x) {
+    return make_double2(fma(h, x.x, s.x), fma(h, x.y, s.y));
+}
+// 2 a - b
+__device__ __forceinline__ double2 two_minus(double2 a, double2 b) {
+    return make_double2(fma(2.0, a.x, -b.x), fma(2.0, a.y, -b.y));
 }
 
 // Sum of H~_im x_m over the filled slots of row i, plus the diagonal term.
@@ -61,8 +97,7 @@ __device__ __forceinline__ double2 row_h(const Ell &h, const V *x, int64_t i,
             double hk = h.hop ? h.hop[k * h.n + i] : h.t;
             double2 xm = ld(x + ((int64_t)(m < 0 ? 0 : m) << vshift) + v);
             hk = m < 0 ? 0.0 : hk;
-            acc.x += hk * xm.x;
-            acc.y += hk * xm.y;
+            acc = raxpy(acc, hk, xm);
         }
     }
     return acc;
@@ -84,10 +119,8 @@ __device__ __forceinline__ void row_hd(const Ell &h, const V *x, int64_t i, int6
             double2 xm = ld(x + ((int64_t)(m < 0 ? 0 : m) << vshift) + v);
             hk = m < 0 ? 0.0 : hk;
             xk = m < 0 ? 0.0 : xk;
-            hx.x += hk * xm.x;
-            hx.y += hk * xm.y;
-            dx.x += xk * xm.x;
-            dx.y += xk * xm.y;
+            hx = raxpy(hx, hk, xm);
+            dx = raxpy(dx, xk, xm);
         }
     }
 }
@@ -104,8 +137,7 @@ __device__ __forceinline__ double2 row_d(const Ell &h, const V *x, int64_t i, in
             double xk = h.xw[k * h.n + i];
             double2 xm = ld(x + ((int64_t)(m < 0 ? 0 : m) << vshift) + v);
             xk = m < 0 ? 0.0 : xk;
-            dx.x += xk * xm.x;
-            dx.y += xk * xm.y;
+            dx = raxpy(dx, xk, xm);
         }
     }
     return dx;
@@ -164,16 +196,14 @@ __global__ __launch_bounds__(kBlock) void k_moment_step(Ell h, Sweep sw, const V
     double2 o;
     if (FIRST) {
         o = hx;
-        double2 d0 = cdot(l, xi);
-        s1 = cadd(s1, d0);
+        s1 = cdot_acc(s1, l, xi);
     } else {
-        double2 q = ld(p0 + e);
-        o = make_double2(2.0 * hx.x - q.x, 2.0 * hx.y - q.y);
+        o = two_minus(hx, ld(p0 + e));
     }
     // the dot uses the stored (rounded) value, which the next step reads
     o = rounded<V>(o);
     st(out + e, o);
-    s0 = cadd(s0, cdot(l, o));
+    s0 = cdot_acc(s0, l, o);
     KPM_SWEEP_END
     const int64_t r = (int64_t)1 << sw.vshift;
     if (FIRST) {
@@ -182,6 +212,82 @@ __global__ __launch_bounds__(kBlock) void k_moment_step(Ell h, Sweep sw, const V
     } else {
         block_sum(s0, sw.vshift, partial + ((int64_t)slot * sw.nwg + blockIdx.x) * r);
     }
+}
+
+// Recursion step of the moments with ILP elements per thread per pass: all
+// loads of the ILP elements are issued before any arithmetic, so a wavefront
+// keeps ILP times more bytes in flight (the gathers depend on the index
+// loads, which would otherwise serialise two memory latencies per element).
+// Elements are visited in the same order as with one element per pass, so
+// every ILP gives bit-identical results.
+template <typename V, int ILP, bool NT>
+__global__ __launch_bounds__(kBlock) void k_moment_step_ilp(Ell h, Sweep sw, const V *p1,
+                                                            const V *p0, V *out,
+                                                            const V *__restrict__ phil,
+                                                            double2 *__restrict__ partial,
+                                                            int slot) {
+    double2 s0 = make_double2(0.0, 0.0);
+    const int xcd = blockIdx.x % kXcds;
+    const int loc = blockIdx.x / kXcds;
+    const int nloc = sw.nwg / kXcds;
+    const int64_t b0 = (int64_t)xcd * sw.per_xcd;
+    const int64_t b1 = min(b0 + sw.per_xcd, sw.nblk);
+    const int64_t vmask = ((int64_t)1 << sw.vshift) - 1;
+    for (int64_t b = b0 + loc; b < b1; b += (int64_t)nloc * ILP) {
+        int64_t e[ILP];
+        bool ok[ILP];
+#pragma unroll
+        for (int u = 0; u < ILP; ++u) {
+            const int64_t bu = b + (int64_t)u * nloc;
+            e[u] = bu * kBlock + threadIdx.x;
+            ok[u] = bu < b1 && e[u] < sw.total;
+            e[u] = ok[u] ? e[u] : 0;          // a safe element; its result is dropped
+        }
+        int32_t m[ILP][kMaxWidth];
+        double hk[ILP][kMaxWidth];
+        double on[ILP];
+        double2 xi[ILP], l[ILP], q[ILP];
+#pragma unroll
+        for (int u = 0; u < ILP; ++u) {
+            const int64_t i = e[u] >> sw.vshift;
+#pragma unroll
+            for (int k = 0; k < kMaxWidth; ++k) {
+                if (k < h.w) {
+                    m[u][k] = h.nbr[k * h.n + i];
+                    hk[u][k] = h.hop ? h.hop[k * h.n + i] : h.t;
+                }
+            }
+            on[u] = h.ons[i];
+            xi[u] = ld(p1 + e[u]);
+            l[u] = NT ? ld_nt(phil + e[u]) : ld(phil + e[u]);
+            q[u] = NT ? ld_nt(p0 + e[u]) : ld(p0 + e[u]);
+        }
+        double2 acc[ILP];
+#pragma unroll
+        for (int u = 0; u < ILP; ++u) {
+            const int64_t v = e[u] & vmask;
+            acc[u] = make_double2(on[u] * xi[u].x, on[u] * xi[u].y);
+#pragma unroll
+            for (int k = 0; k < kMaxWidth; ++k) {
+                if (k < h.w) {
+                    const int32_t mm = m[u][k];
+                    const double2 xm = ld(p1 + ((int64_t)(mm < 0 ? 0 : mm) << sw.vshift) + v);
+                    const double hh = mm < 0 ? 0.0 : hk[u][k];
+                    acc[u] = raxpy(acc[u], hh, xm);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < ILP; ++u) {
+            if (ok[u]) {
+                const double2 o = rounded<V>(two_minus(acc[u], q[u]));
+                if (NT) st_nt(out + e[u], o); else st(out + e[u], o);
+                s0 = cdot_acc(s0, l[u], o);
+            }
+        }
+    }
+    const int64_t r = (int64_t)1 << sw.vshift;
+    block_sum(s0, sw.vshift, partial + ((int64_t)slot * sw.nwg + blockIdx.x) * r);
 }
 
 template <typename V, bool FIRST>
@@ -195,15 +301,14 @@ __global__ __launch_bounds__(kBlock) void k_evolve_step(Ell h, Sweep sw, const V
     double2 o, a;
     if (FIRST) {
         o = rounded<V>(hx);
-        a = cadd(cmul(c0, xi), cmul(c, o));
-        if (add) a = cadd(ld(add + e), a);
+        a = cmla(cmul(c0, xi), c, o);
+        if (add) a = cadd(ld_nt(add + e), a);
     } else {
-        double2 q = ld(p0 + e);
-        o = rounded<V>(make_double2(2.0 * hx.x - q.x, 2.0 * hx.y - q.y));
-        a = cadd(ld(acc + e), cmul(c, o));
+        o = rounded<V>(two_minus(hx, ld_nt(p0 + e)));
+        a = cmla(ld_nt(acc + e), c, o);
     }
-    st(out + e, o);
-    st(acc + e, a);
+    st_nt(out + e, o);
+    st_nt(acc + e, a);
     KPM_SWEEP_END
 }
 
@@ -220,22 +325,21 @@ __global__ __launch_bounds__(kBlock) void k_evolve_x_step(Ell h, Sweep sw, const
     if (FIRST) {
         hp = rounded<V>(hp);
         dp = rounded<V>(dp);
-        st(pout + e, hp);
-        st(qout + e, dp);
-        st(accx + e, cmul(c, dp));
-        st(accu + e, cadd(cmul(c0, xi), cmul(c, hp)));
+        st_nt(pout + e, hp);
+        st_nt(qout + e, dp);
+        st_nt(accx + e, cmul(c, dp));
+        st_nt(accu + e, cmla(cmul(c0, xi), c, hp));
     } else {
         double2 qi = ld(q1 + e);
         double2 hq = row_h(h, q1, i, v, sw.vshift, qi);
-        double2 pp = ld(p0 + e);
-        double2 qq = q0 ? ld(q0 + e) : make_double2(0.0, 0.0);
-        double2 po = rounded<V>(make_double2(2.0 * hp.x - pp.x, 2.0 * hp.y - pp.y));
-        double2 qo = rounded<V>(make_double2(2.0 * dp.x + 2.0 * hq.x - qq.x,
-                                             2.0 * dp.y + 2.0 * hq.y - qq.y));
-        st(pout + e, po);
-        st(qout + e, qo);
-        st(accx + e, cadd(ld(accx + e), cmul(c, qo)));
-        st(accu + e, cadd(ld(accu + e), cmul(c, po)));
+        double2 pp = ld_nt(p0 + e);
+        double2 qq = q0 ? ld_nt(q0 + e) : make_double2(0.0, 0.0);
+        double2 po = rounded<V>(two_minus(hp, pp));
+        double2 qo = rounded<V>(two_minus(cadd(dp, hq), qq));
+        st_nt(pout + e, po);
+        st_nt(qout + e, qo);
+        st_nt(accx + e, cmla(ld_nt(accx + e), c, qo));
+        st_nt(accu + e, cmla(ld_nt(accu + e), c, po));
     }
     KPM_SWEEP_END
 }
@@ -282,10 +386,10 @@ __global__ __launch_bounds__(kBlock) void k_kpm_sum(const double *__restrict__ m
     const double *c = mom + (int64_t)t * nm;
     double tm2 = 1.0, tm1 = x;
     double s = w[0] * c[0];
-    if (nm > 1) s += w[1] * x * c[1];
+    if (nm > 1) s = fma(w[1] * x, c[1], s);
     for (int m = 2; m < nm; ++m) {
-        double tm = 2.0 * x * tm1 - tm2;
-        s += w[m] * tm * c[m];
+        double tm = fma(2.0 * x, tm1, -tm2);
+        s = fma(w[m] * tm, c[m], s);
         tm2 = tm1;
         tm1 = tm;
     }
@@ -293,8 +397,10 @@ __global__ __launch_bounds__(kBlock) void k_kpm_sum(const double *__restrict__ m
 }
 
 // ---------------------------------------------------------------- launchers
-Sweep make_sweep(int64_t rows, int vshift, int nwg) {
+Sweep make_sweep(int64_t rows, int vshift, int nwg, int ilp, int nt) {
     Sweep sw;
+    sw.ilp = ilp;
+    sw.nt = nt;
     sw.total = rows << vshift;
     sw.nblk = (sw.total + kBlock - 1) / kBlock;
     sw.nwg = nwg;
@@ -310,9 +416,27 @@ void launch_moment_step(const Ell &h, const Sweep &sw, bool first, const V *p1,
     if (first)
         hipLaunchKernelGGL((k_moment_step<V, true>), dim3(sw.nwg), dim3(kBlock), 0, s, h, sw,
                            p1, p0, out, phil, partial, slot);
-    else
-        hipLaunchKernelGGL((k_moment_step<V, false>), dim3(sw.nwg), dim3(kBlock), 0, s, h, sw,
-                           p1, p0, out, phil, partial, slot);
+    else if (sw.nt) {
+        if (sw.ilp >= 4)
+            hipLaunchKernelGGL((k_moment_step_ilp<V, 4, true>), dim3(sw.nwg), dim3(kBlock), 0, s,
+                               h, sw, p1, p0, out, phil, partial, slot);
+        else if (sw.ilp == 2)
+            hipLaunchKernelGGL((k_moment_step_ilp<V, 2, true>), dim3(sw.nwg), dim3(kBlock), 0, s,
+                               h, sw, p1, p0, out, phil, partial, slot);
+        else
+            hipLaunchKernelGGL((k_moment_step_ilp<V, 1, true>), dim3(sw.nwg), dim3(kBlock), 0, s,
+                               h, sw, p1, p0, out, phil, partial, slot);
+    } else {
+        if (sw.ilp >= 4)
+            hipLaunchKernelGGL((k_moment_step_ilp<V, 4, false>), dim3(sw.nwg), dim3(kBlock), 0, s,
+                               h, sw, p1, p0, out, phil, partial, slot);
+        else if (sw.ilp == 2)
+            hipLaunchKernelGGL((k_moment_step_ilp<V, 2, false>), dim3(sw.nwg), dim3(kBlock), 0, s,
+                               h, sw, p1, p0, out, phil, partial, slot);
+        else
+            hipLaunchKernelGGL((k_moment_step_ilp<V, 1, false>), dim3(sw.nwg), dim3(kBlock), 0, s,
+                               h, sw, p1, p0, out, phil, partial, slot);
+    }
 }
 
 template <typename V>

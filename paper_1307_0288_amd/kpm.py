@@ -27,8 +27,9 @@ BOND_NM = 0.142
 ABI_SYMBOLS = ("kpm_build_graphene", "kpm_system_create", "kpm_system_destroy",
                "kpm_system_set_stream", "kpm_system_n_sites", "kpm_moments", "kpm_evolve",
                "kpm_evolve_x", "kpm_vac", "kpm_msd", "kpm_kpm_sum", "kpm_sigma_gk",
-               "kpm_sigma_e1", "kpm_sigma_e2", "kpm_set_timing", "kpm_get_stats",
-               "kpm_reset_stats", "kpm_last_error", "kpm_version")
+               "kpm_sigma_e1", "kpm_sigma_e2", "kpm_set_launch", "kpm_get_launch",
+               "kpm_autotune", "kpm_set_timing", "kpm_get_stats", "kpm_reset_stats",
+               "kpm_last_error", "kpm_version")
 
 
 class KpmError(RuntimeError):
@@ -43,6 +44,10 @@ class _Desc(C.Structure):
                 ("t_uniform", C.c_double), ("onsite", C.POINTER(C.c_double)),
                 ("dx", C.POINTER(C.c_double)), ("active", C.POINTER(C.c_uint8)),
                 ("e_scale", C.c_double)]
+
+
+class Launch(C.Structure):
+    _fields_ = [("groups_per_cu", C.c_int32), ("ilp", C.c_int32), ("streaming", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -77,6 +82,9 @@ def lib():
             "kpm_sigma_gk": [C.c_int, C.c_int, dp, C.c_double, dp],
             "kpm_sigma_e1": [C.c_int, C.c_int, dp, C.c_double, dp],
             "kpm_sigma_e2": [C.c_int, C.c_int, dp, C.c_double, dp],
+            "kpm_set_launch": [vp, C.c_int, C.POINTER(Launch)],
+            "kpm_get_launch": [vp, C.c_int, C.POINTER(Launch)],
+            "kpm_autotune": [vp, C.c_int, vp, C.c_int, C.POINTER(Launch)],
             "kpm_set_timing": [vp, C.c_int],
             "kpm_get_stats": [vp, C.POINTER(Stats)],
             "kpm_reset_stats": [vp],
@@ -297,6 +305,27 @@ def kpm_vac(sys: System, phi, n_steps: int, dt_fs: float, n_bessel: int, n_momen
 def kpm_msd(sys: System, phi, n_steps: int, dt_fs: float, n_bessel: int, n_moments: int):
     """MSD moments [n_vec, n_steps+1, n_moments] in nm^2 (Alg. 3)."""
     return _loop(lib().kpm_msd, sys, phi, n_steps, dt_fs, n_bessel, n_moments)
+
+
+def kpm_set_launch(sys: System, n_vec: int, groups_per_cu: int, ilp: int, streaming: int = 0):
+    """Launch shape of the moment step for n_vec vectors (see kpm_launch in kpm.h)."""
+    _check(lib().kpm_set_launch(sys.handle, n_vec,
+                                C.byref(Launch(groups_per_cu, ilp, int(bool(streaming))))))
+
+
+def kpm_get_launch(sys: System, n_vec: int) -> dict:
+    out = Launch()
+    _check(lib().kpm_get_launch(sys.handle, n_vec, C.byref(out)))
+    return dict(groups_per_cu=out.groups_per_cu, ilp=out.ilp, streaming=out.streaming)
+
+
+def kpm_autotune(sys: System, phi, reps: int = 10) -> dict:
+    """Time every candidate launch shape on `phi` and keep the fastest for its n_vec."""
+    p, nv = sys._state(phi, "phi")
+    out = Launch()
+    sys._sync_stream()
+    _check(lib().kpm_autotune(sys.handle, nv, p, reps, C.byref(out)))
+    return dict(groups_per_cu=out.groups_per_cu, ilp=out.ilp, streaming=out.streaming)
 
 
 def kpm_set_timing(sys: System, enable: bool = True):

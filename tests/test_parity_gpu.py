@@ -279,3 +279,31 @@ def test_paper_scale_evolve_norm(paper):
     kp.kpm_evolve(sysg, d, p["dt_fs"], -1, p["n_bessel"])
     back = d.cpu().numpy()
     assert np.max(np.abs(back - phi)) < 1e-11
+
+
+# ------------------------------------------------------------------ launch shapes
+@pytest.mark.parametrize("n_vec,precision", [(1, "fp64"), (8, "fp32"), (64, "fp64")])
+def test_launch_shapes(n_vec, precision):
+    """At a fixed grid every ILP visits each work-group's elements in the same
+    order with the same explicit FMAs, so the moments are bit-identical; another
+    grid size partitions the inner-product sums differently (rounding only).
+    The autotuner keeps one of the candidate shapes."""
+    _need_gpu()
+    c = recipe("sheet", 100, 50, w=1.0, vac=0.01, seed=2)
+    sysg = gpu_system(c, precision)
+    phi = sysg.upload(phases(c, n_vec, 3000))
+    first = None
+    for g in (2, 16):
+        ref = None
+        for ilp in (1, 2, 4):
+            for nt in (0, 1):
+                kp.kpm_set_launch(sysg, n_vec, g, ilp, nt)
+                mu = kp.kpm_moments(sysg, phi, phi, 40)
+                ref = mu if ref is None else ref
+                assert np.array_equal(mu, ref), (g, ilp, nt)
+        first = ref if first is None else first
+        assert rel_err(ref, first, float(np.abs(first[:, 0]).max())) < 1e-13
+    best = kp.kpm_autotune(sysg, phi, 3)
+    assert best["groups_per_cu"] in (4, 8, 16) and best["ilp"] in (1, 2, 4)
+    assert best["streaming"] in (0, 1)
+    assert kp.kpm_get_launch(sysg, n_vec) == best
