@@ -110,7 +110,7 @@ def main():
     sysg = kp.graphene_system(p["nx"], p["ny"], "sheet", p["t"], ons, act, p["e_scale"], "fp64")
     phi = sysg.upload(phi_h)
     nm, ns, nb, dt = p["n_moments"], p["n_steps"], p["n_bessel"], p["dt_fs"]
-    launch = kp.kpm_autotune(sysg, phi, 30)
+    launch = kp.kpm_autotune(sysg, phi, 50)
     log(f"autotuned launch shape: {launch}")
 
     def step():
@@ -162,7 +162,8 @@ def main():
                                "x 40 Bessel terms, dt=hbar/|t|",
                    "n_sites": n, "n_vec": 1, "n_moments": nm, "n_steps": ns,
                    "n_bessel": nb, "site_updates_per_step": st["site_updates"] // args.steps},
-        "roofline": {"kernel": "k_moment_step<double2,false>", "bound": "hbm",
+        "roofline": {"kernel": f"k_moment_step<double2,{launch['ilp']},"
+                               f"{'true' if launch['streaming'] else 'false'}>", "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_site_update": BYTES_PER_SITE_UPDATE_FP64,

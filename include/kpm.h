@@ -127,6 +127,25 @@ kpm_status kpm_system_set_stream(kpm_system *sys, void *hip_stream);
 int64_t kpm_system_n_sites(const kpm_system *sys);
 
 /*
+ * Ragged batch: n_sys independent samples (each its own descriptor, size,
+ * width, disorder and e_scale) laid side by side in one system, so that every
+ * recursion step of all samples is one kernel launch.  Sample s occupies rows
+ * offsets[s] .. offsets[s+1]-1 of every state buffer (offsets from
+ * kpm_system_offsets; n_sites is their total).  Each sample is scaled by its
+ * own e_scale (time steps use each sample's Bessel argument) and gets its own
+ * inner products: host outputs of kpm_moments, kpm_vac and kpm_msd gain a
+ * leading sample dimension ([n_sys][n_vec][...]).  Every entry point that
+ * takes a system accepts a batch.  kpm_system_create is the batch of one.
+ * n_sys <= 4096; the total rows must stay below 2^31.
+ */
+kpm_status kpm_batch_create(int n_sys, const kpm_system_desc *descs, kpm_precision precision,
+                            int device, void *hip_stream, kpm_system **out);
+/* Number of samples (1 for kpm_system_create). */
+int32_t kpm_system_n_samples(const kpm_system *sys);
+/* Row offsets of the samples, offsets[0 .. n_samples] (host output). */
+kpm_status kpm_system_offsets(const kpm_system *sys, int64_t *offsets);
+
+/*
  * Chebyshev moments C_m = <phi_L| T_m(H~) |phi_R>, m = 0 .. n_moments-1, for
  * each of the n_vec vector pairs (Eq. 46, Alg. 5).  phi_l, phi_r: device
  * states (may be the same buffer).  mu: host output [n_vec][n_moments][2]

@@ -87,6 +87,32 @@ def random_phase(n_sites: int, n_vec: int, seeds, active=None) -> np.ndarray:
     return out
 
 
+def ragged_specs(count: int, seed: int, n_min: float = 1e4, n_max: float = 1e6,
+                 w_min: int = 20, w_max: int = 400) -> list:
+    """Sizes of a ragged batch: per sample a geometry (AGNR, ZGNR or sheet), a
+    width in cells (ZGNR: zigzag chains; AGNR: twice as many dimer lines), a
+    length giving a log-uniform site count in [n_min, n_max], and an Anderson
+    strength W in {0.5, 1, 2} eV.  Periodic directions get even sizes."""
+    u = uniform(seed, 4 * count).reshape(count, 4)
+    out = []
+    for s in range(count):
+        geo = ("agnr", "zgnr", "sheet")[int(3 * u[s, 0])]
+        width = w_min + int(u[s, 1] * (w_max - w_min + 1))
+        n_target = float(np.exp(np.log(n_min) + u[s, 2] * (np.log(n_max) - np.log(n_min))))
+        w_ev = (0.5, 1.0, 2.0)[int(3 * u[s, 3])]
+        if geo == "zgnr":
+            ny = width
+            nx = max(4, 2 * int(round(n_target / ny / 2)))
+        elif geo == "agnr":
+            nx = 2 * width
+            ny = max(2, 2 * int(round(n_target / nx / 2)))
+        else:
+            half = max(2, 2 * int(round(np.sqrt(n_target / 2) / 2)))
+            nx, ny = 2 * half, half
+        out.append(dict(geometry=geo, nx=nx, ny=ny, w=w_ev))
+    return out
+
+
 def sheet_config(name: str) -> dict:
     """Parameters of the named synthetic workloads (sizes in sites, energies in eV)."""
     hbar = 0.6582119569  # eV fs
@@ -100,4 +126,8 @@ def sheet_config(name: str) -> dict:
         return dict(geometry="sheet", nx=2828, ny=1414, t=-2.7, w=0.1, vac=0.005,
                     e_scale=1.01 * (3 * 2.7 + 0.05), n_moments=3000, n_steps=20,
                     dt_fs=hbar / 2.7, n_bessel=40, n_vec=1)
+    if name == "ragged":
+        # 32 samples of 1e4..1e6 sites, 8 vectors each, 1000 moments.
+        return dict(count=32, seed=4000, n_min=1e4, n_max=1e6, w_min=20, w_max=400,
+                    n_vec=8, n_moments=1000, t=-2.7)
     raise KeyError(name)

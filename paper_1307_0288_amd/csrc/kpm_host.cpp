@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/kpm.h: descriptor validation and
-// packing, device residency of the scaled Hamiltonian, recursion scratch,
-// and the drivers of Alg. 2, 3, 5, 6 and 7 that sequence the gfx950 kernels.
+// packing, device residency of the scaled Hamiltonian (one sample, or many
+// side by side), recursion scratch, and the drivers of Alg. 2, 3, 5, 6 and 7
+// that sequence the gfx950 kernels.
 #include "kpm.h"
 #include "kpm_internal.h"
 
@@ -21,7 +22,7 @@ namespace {
 constexpr double kHbar = 0.6582119569;   // eV fs
 constexpr double kBond = 0.142;          // nm, carbon-carbon distance (Sec. 2)
 constexpr double kPi = 3.14159265358979323846;
-constexpr int kPartialRing = 256;     // moment slots of group partials kept at once
+constexpr int kPartialRing = 256;        // moment slots of group partials kept at once
 
 thread_local std::string g_err;
 
@@ -57,11 +58,9 @@ int vshift_of(int n_vec) {
 
 // Chebyshev-Bessel coefficients of Eq. 36: c_m = (2 - delta_m0) (-i s)^m J_m(x).
 // J_m from the C++17 special functions (std::cyl_bessel_j).
-void bessel_coeffs(int np, double x, int sign, std::vector<double2> &c) {
-    c.resize(np);
+void bessel_coeffs(int np, double x, int sign, double2 *c) {
     for (int m = 0; m < np; ++m) {
-        double j = std::cyl_bessel_j((double)m, x);
-        double f = (m == 0 ? 1.0 : 2.0) * j;
+        const double f = (m == 0 ? 1.0 : 2.0) * std::cyl_bessel_j((double)m, x);
         // (-i s)^m cycles through 1, -i s, -1, i s
         double re = 0, im = 0;
         switch (m & 3) {
@@ -102,24 +101,123 @@ kpm_launch default_launch(int vshift) {
     return l;
 }
 
+// One validated sample in neighbour-list form, energies in eV.  Removed
+// sites lose every bond and their on-site energy.
+struct Packed {
+    int64_t n = 0;
+    int w = 0;
+    std::vector<int32_t> nbr;   // [w][n], -1 = empty
+    std::vector<double> hop;    // [w][n] or empty (uniform t)
+    std::vector<double> ons;    // [n]
+    std::vector<double> dx;     // [w][n] or empty
+    double t = 0;
+    double e_scale = 1;
+};
+
+kpm_status pack_desc(const kpm_system_desc *d, int index, Packed &p) {
+    const int64_t n = d->n_sites;
+    const int w = d->width;
+    if (n < 1 || n >= ((int64_t)1 << 31)) return fail(KPM_ERR_INVALID, "sample %d: n_sites out of range", index);
+    if (w < 1 || w > KPM_MAX_WIDTH) return fail(KPM_ERR_INVALID, "sample %d: width must be 1..%d", index, KPM_MAX_WIDTH);
+    if (!d->nbr) return fail(KPM_ERR_INVALID, "sample %d: nbr is null", index);
+    if (!(d->e_scale > 0) || !std::isfinite(d->e_scale)) return fail(KPM_ERR_INVALID, "sample %d: e_scale", index);
+    if (!std::isfinite(d->t_uniform)) return fail(KPM_ERR_INVALID, "sample %d: t_uniform", index);
+    p.n = n;
+    p.w = w;
+    p.t = d->t_uniform;
+    p.e_scale = d->e_scale;
+    p.nbr.assign((size_t)w * n, -1);
+    p.ons.assign(n, 0.0);
+    if (d->hop) p.hop.assign((size_t)w * n, 0.0);
+    if (d->dx) p.dx.assign((size_t)w * n, 0.0);
+    auto alive = [&](int64_t s) { return !d->active || d->active[s] != 0; };
+    for (int64_t s = 0; s < n; ++s) {
+        p.ons[s] = (alive(s) && d->onsite) ? d->onsite[s] : 0.0;
+        if (!std::isfinite(p.ons[s])) return fail(KPM_ERR_INVALID, "sample %d: non-finite onsite at %lld", index, (long long)s);
+        for (int k = 0; k < w; ++k) {
+            const size_t q = (size_t)k * n + s;
+            int32_t m = d->nbr[q];
+            if (m < -1 || m >= n)
+                return fail(KPM_ERR_INVALID, "sample %d: neighbour index %d out of range at row %lld slot %d", index, m, (long long)s, k);
+            if (m >= 0 && (!alive(s) || !alive(m))) m = -1;
+            p.nbr[q] = m;
+            if (d->hop) {
+                p.hop[q] = m >= 0 ? d->hop[q] : 0.0;
+                if (!std::isfinite(p.hop[q])) return fail(KPM_ERR_INVALID, "sample %d: non-finite hop", index);
+            }
+            if (d->dx) {
+                p.dx[q] = m >= 0 ? d->dx[q] : 0.0;
+                if (!std::isfinite(p.dx[q])) return fail(KPM_ERR_INVALID, "sample %d: non-finite dx", index);
+            }
+        }
+    }
+    // Symmetry: every bond listed from both ends with equal H and opposite dx.
+    double gersh = 0.0;
+    for (int64_t s = 0; s < n; ++s) {
+        double row = std::fabs(p.ons[s]);
+        for (int k = 0; k < w; ++k) {
+            const size_t q = (size_t)k * n + s;
+            const int32_t m = p.nbr[q];
+            if (m < 0) continue;
+            const double hv = d->hop ? p.hop[q] : p.t;
+            row += std::fabs(hv);
+            bool found = false;
+            for (int k2 = 0; k2 < w && !found; ++k2) {
+                const size_t q2 = (size_t)k2 * n + m;
+                if (p.nbr[q2] != s) continue;
+                const double hb = d->hop ? p.hop[q2] : p.t;
+                if (hb != hv) continue;
+                if (d->dx && p.dx[q2] != -p.dx[q]) continue;
+                found = true;
+            }
+            if (!found)
+                return fail(KPM_ERR_INVALID, "sample %d: H not symmetric (or dx not antisymmetric) at row %lld slot %d", index, (long long)s, k);
+        }
+        gersh = std::max(gersh, row);
+    }
+    if (d->e_scale < gersh)
+        return fail(KPM_ERR_INVALID, "sample %d: e_scale %.6g below the Gershgorin bound %.6g", index, d->e_scale, gersh);
+    return KPM_OK;
+}
+
 }  // namespace
 
 struct kpm_system {
     int device = 0;
     hipStream_t stream = nullptr;
     kpm_precision prec = KPM_FP64;
-    int64_t n = 0;
+    int64_t n = 0;              // rows of all samples
     int w = 0;
-    double e_scale = 1;
     bool has_dx = false;
     int cus = 256;
     kpm_launch launch[7];       // launch shape of the moment step per log2(n_vec)
+    // samples: rows [off[s], off[s+1]) hold sample s, whose scale is es[s]
+    int nseg = 1;
+    std::vector<int64_t> off;
+    std::vector<double> es;
     // device Hamiltonian
     int32_t *d_nbr = nullptr;
     double *d_hop = nullptr;
+    double *d_tsc = nullptr;
     double *d_xw = nullptr;
     double *d_ons = nullptr;
     double t_scaled = 0;
+    double2 *d_alpha = nullptr;  // [nseg] velocity prefactor -i E_s / hbar (batches)
+    // segment tables per (vshift, requested groups); batches only
+    struct SegTab {
+        int vshift, groups;
+        int nwg;
+        kpm::Seg *seg;
+        int32_t *wg;
+    };
+    std::vector<SegTab> segtabs;
+    // Bessel coefficient tables [nseg][np] per (dt, sign, np); batches only
+    struct CoefTab {
+        double dt;
+        int sign, np;
+        double2 *d;
+    };
+    std::vector<CoefTab> coeftabs;
     // scratch
     std::vector<void *> vecs;
     size_t vec_bytes = 0;
@@ -134,11 +232,13 @@ struct kpm_system {
     kpm_stats stats{};
 
     size_t elem_bytes() const { return prec == KPM_FP64 ? 16 : 8; }
+    size_t state_bytes(int vshift) const { return (size_t)n * ((size_t)1 << vshift) * elem_bytes(); }
 
     kpm::Ell ell() const {
         kpm::Ell h;
         h.nbr = d_nbr;
         h.hop = d_hop;
+        h.tsc = d_tsc;
         h.xw = d_xw;
         h.ons = d_ons;
         h.t = t_scaled;
@@ -147,23 +247,98 @@ struct kpm_system {
         return h;
     }
 
-    int grid_for(int64_t total, int groups_per_cu) const {
-        int64_t nblk = (total + kpm::kBlock - 1) / kpm::kBlock;
-        int64_t g = (int64_t)cus * groups_per_cu;
-        g = std::min<int64_t>(g, ((nblk + kpm::kXcds - 1) / kpm::kXcds) * kpm::kXcds);
-        g = std::max<int64_t>(g, kpm::kXcds);
-        return (int)(g - g % kpm::kXcds);
+    // The sweep of the moment step (and every other kernel) for n_vec =
+    // 2^vshift under launch shape l.  Batches give each sample a contiguous
+    // run of work-groups (a multiple of 8) in proportion to its rows.
+    kpm_status sweep_with(int vshift, const kpm_launch &l, kpm::Sweep *out) {
+        kpm::Sweep sw{};
+        sw.total = n << vshift;
+        sw.vshift = vshift;
+        sw.ilp = l.ilp;
+        sw.nt = l.streaming;
+        const int64_t want = std::max<int64_t>(kpm::kXcds, ((int64_t)cus * l.groups_per_cu) / kpm::kXcds * kpm::kXcds);
+        if (nseg == 1) {
+            const int64_t nblk = (sw.total + kpm::kBlock - 1) / kpm::kBlock;
+            const int64_t cap = ((nblk + kpm::kXcds - 1) / kpm::kXcds) * kpm::kXcds;
+            sw.nwg = (int)std::max<int64_t>(kpm::kXcds, std::min(want, cap));
+            sw.nseg = 1;
+            sw.seg = nullptr;
+            sw.wg_seg = nullptr;
+            sw.one = kpm::Seg{0, sw.total, 0, sw.nwg};
+            *out = sw;
+            return KPM_OK;
+        }
+        for (const SegTab &t : segtabs) {
+            if (t.vshift == vshift && t.groups == l.groups_per_cu) {
+                sw.nwg = t.nwg;
+                sw.nseg = nseg;
+                sw.seg = t.seg;
+                sw.wg_seg = t.wg;
+                *out = sw;
+                return KPM_OK;
+            }
+        }
+        const int64_t units = want / kpm::kXcds;
+        std::vector<kpm::Seg> seg(nseg);
+        int64_t g0 = 0;
+        for (int s = 0; s < nseg; ++s) {
+            const int64_t rows = off[s + 1] - off[s];
+            const int64_t nblk = ((rows << vshift) + kpm::kBlock - 1) / kpm::kBlock;
+            int64_t u = (int64_t)std::llround((double)units * rows / (double)n);
+            u = std::max<int64_t>(1, std::min(u, (nblk + kpm::kXcds - 1) / kpm::kXcds));
+            seg[s] = kpm::Seg{off[s] << vshift, off[s + 1] << vshift, (int32_t)g0,
+                              (int32_t)(u * kpm::kXcds)};
+            g0 += u * kpm::kXcds;
+        }
+        if (g0 > (1 << 30)) return fail(KPM_ERR_INVALID, "batch needs too many work-groups");
+        std::vector<int32_t> wg(g0);
+        for (int s = 0; s < nseg; ++s)
+            for (int g = 0; g < seg[s].nwg; ++g) wg[seg[s].g0 + g] = s;
+        SegTab t{vshift, l.groups_per_cu, (int)g0, nullptr, nullptr};
+        KPM_HIP(hipMalloc(&t.seg, seg.size() * sizeof(kpm::Seg)));
+        KPM_HIP(hipMalloc(&t.wg, wg.size() * sizeof(int32_t)));
+        KPM_HIP(hipMemcpy(t.seg, seg.data(), seg.size() * sizeof(kpm::Seg), hipMemcpyHostToDevice));
+        KPM_HIP(hipMemcpy(t.wg, wg.data(), wg.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        segtabs.push_back(t);
+        sw.nwg = t.nwg;
+        sw.nseg = nseg;
+        sw.seg = t.seg;
+        sw.wg_seg = t.wg;
+        *out = sw;
+        return KPM_OK;
     }
 
-    kpm::Sweep sweep(int vshift) const { return sweep_with(vshift, launch[vshift]); }
+    kpm_status sweep(int vshift, kpm::Sweep *out) { return sweep_with(vshift, launch[vshift], out); }
 
-    kpm::Sweep sweep_with(int vshift, const kpm_launch &l) const {
-        return kpm::make_sweep(n, vshift, grid_for(n << vshift, l.groups_per_cu), l.ilp, l.streaming);
+    // Coefficients c_m of Eq. 36 for every sample: host values for a single
+    // sample (kernel arguments), a cached device table [nseg][np] otherwise.
+    kpm_status bessel(double dt, int sign, int np, std::vector<double2> &host,
+                      const double2 **tab) {
+        host.resize((size_t)np * nseg);
+        for (int s = 0; s < nseg; ++s) bessel_coeffs(np, es[s] * dt / kHbar, sign, &host[(size_t)s * np]);
+        *tab = nullptr;
+        if (nseg == 1) return KPM_OK;
+        for (const CoefTab &c : coeftabs)
+            if (c.dt == dt && c.sign == sign && c.np == np) {
+                *tab = c.d;
+                return KPM_OK;
+            }
+        CoefTab c{dt, sign, np, nullptr};
+        KPM_HIP(hipMalloc(&c.d, host.size() * sizeof(double2)));
+        KPM_HIP(hipMemcpy(c.d, host.data(), host.size() * sizeof(double2), hipMemcpyHostToDevice));
+        coeftabs.push_back(c);
+        *tab = c.d;
+        return KPM_OK;
+    }
+
+    kpm::Coef alpha() const {
+        const double2 v = make_double2(0.0, -es[0] / kHbar);   // V = -i (E_s/hbar) D
+        return nseg == 1 ? kpm::coef_val(v) : kpm::coef_tab(d_alpha, 1, 0, v);
     }
 
     // Makes sure `count` state vectors of n_vec vectors each exist.
-    kpm_status ensure_vecs(int count, int n_vec) {
-        size_t bytes = (size_t)n * n_vec * elem_bytes();
+    kpm_status ensure_vecs(int count, int vshift) {
+        const size_t bytes = state_bytes(vshift);
         if (bytes > vec_bytes) {
             for (void *p : vecs) (void)hipFree(p);
             vecs.clear();
@@ -179,7 +354,7 @@ struct kpm_system {
     }
 
     kpm_status ensure_partial(int slots, int nwg, int n_vec) {
-        size_t need = (size_t)slots * nwg * n_vec;
+        const size_t need = (size_t)slots * nwg * n_vec;
         if (need > partial_elems) {
             if (partial) (void)hipFree(partial);
             partial = nullptr;
@@ -227,25 +402,37 @@ struct kpm_system {
         DeviceGuard g(device);
         for (void *p : vecs) (void)hipFree(p);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        for (SegTab &t : segtabs) {
+            (void)hipFree(t.seg);
+            (void)hipFree(t.wg);
+        }
+        for (CoefTab &c : coeftabs) (void)hipFree(c.d);
         if (partial) (void)hipFree(partial);
         if (dmom) (void)hipFree(dmom);
         if (d_nbr) (void)hipFree(d_nbr);
         if (d_hop) (void)hipFree(d_hop);
+        if (d_tsc) (void)hipFree(d_tsc);
         if (d_xw) (void)hipFree(d_xw);
         if (d_ons) (void)hipFree(d_ons);
+        if (d_alpha) (void)hipFree(d_alpha);
     }
 };
 
 namespace {
 
+kpm::Coef step_coef(const std::vector<double2> &host, const double2 *tab, int np, int m) {
+    return tab ? kpm::coef_tab(tab, np, m, host[m]) : kpm::coef_val(host[m]);
+}
+
 // ---------------------------------------------------------------- drivers
-// Chebyshev moments of Alg. 5 for n_vec vector pairs, reduced into
-// sys->dmom[r * stride_r + offset + m] (complex).
+// Chebyshev moments of Alg. 5 for n_vec vector pairs (every sample), reduced
+// into sys->dmom[(s * R + r) * stride_r + offset + m] (complex).
 template <typename V>
 kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir, int nm,
                        V *a_buf, V *b_buf, int64_t stride_r, int64_t offset) {
     const kpm::Ell h = sys->ell();
-    const kpm::Sweep sw = sys->sweep(vshift);
+    kpm::Sweep sw;
+    KPM_TRY(sys->sweep(vshift, &sw));
     // Group partials live in a ring of kPartialRing moment slots that is
     // reduced into sys->dmom whenever it fills, bounding its size at any N_m.
     const int ring = std::min(std::max(nm, 2), kPartialRing);
@@ -279,8 +466,7 @@ kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir
             }
             sys->stats.site_updates += (int64_t)(c1 - m0) * sw.total;
         }
-        kpm::launch_reduce(sys->partial, sw.nwg, vshift, c1 - c0, sys->dmom, stride_r,
-                           offset + c0, s);
+        kpm::launch_reduce(sys->partial, sw, c1 - c0, sys->dmom, stride_r, offset + c0, s);
     }
     return KPM_OK;
 }
@@ -290,16 +476,20 @@ template <typename V>
 kpm_status run_evolve(kpm_system *sys, int vshift, const V *in, V *acc, const V *add,
                       double dt, int sign, int np, V *a_buf, V *b_buf) {
     const kpm::Ell h = sys->ell();
-    const kpm::Sweep sw = sys->sweep(vshift);
+    kpm::Sweep sw;
+    KPM_TRY(sys->sweep(vshift, &sw));
     std::vector<double2> c;
-    bessel_coeffs(np, sys->e_scale * dt / kHbar, sign, c);
+    const double2 *tab = nullptr;
+    KPM_TRY(sys->bessel(dt, sign, np, c, &tab));
     hipStream_t s = sys->stream;
-    kpm::launch_evolve_step<V>(h, sw, true, in, nullptr, a_buf, acc, add, c[0], c[1], s);
+    kpm::launch_evolve_step<V>(h, sw, true, in, nullptr, a_buf, acc, add,
+                               step_coef(c, tab, np, 0), step_coef(c, tab, np, 1), s);
     const V *p0 = in;
     V *p1 = a_buf;
     for (int m = 2; m < np; ++m) {
         V *out = (m == 2) ? b_buf : const_cast<V *>(p0);
-        kpm::launch_evolve_step<V>(h, sw, false, p1, p0, out, acc, nullptr, c[0], c[m], s);
+        kpm::launch_evolve_step<V>(h, sw, false, p1, p0, out, acc, nullptr,
+                                   step_coef(c, tab, np, 0), step_coef(c, tab, np, m), s);
         p0 = p1;
         p1 = out;
     }
@@ -312,19 +502,21 @@ template <typename V>
 kpm_status run_evolve_x(kpm_system *sys, int vshift, const V *in, V *accx, V *accu,
                         double dt, int np, V *pa, V *pb, V *qa, V *qb) {
     const kpm::Ell h = sys->ell();
-    const kpm::Sweep sw = sys->sweep(vshift);
+    kpm::Sweep sw;
+    KPM_TRY(sys->sweep(vshift, &sw));
     std::vector<double2> c;
-    bessel_coeffs(np, sys->e_scale * dt / kHbar, +1, c);
+    const double2 *tab = nullptr;
+    KPM_TRY(sys->bessel(dt, +1, np, c, &tab));
     hipStream_t s = sys->stream;
     kpm::launch_evolve_x_step<V>(h, sw, true, in, nullptr, pa, nullptr, nullptr, qa, accx,
-                                 accu, c[0], c[1], s);
+                                 accu, step_coef(c, tab, np, 0), step_coef(c, tab, np, 1), s);
     const V *p0 = in, *q0 = nullptr;
     V *p1 = pa, *q1 = qa;
     for (int m = 2; m < np; ++m) {
         V *pout = (m == 2) ? pb : const_cast<V *>(p0);
         V *qout = (m == 2) ? qb : const_cast<V *>(q0);
         kpm::launch_evolve_x_step<V>(h, sw, false, p1, p0, pout, q1, q0, qout, accx, accu,
-                                     c[0], c[m], s);
+                                     step_coef(c, tab, np, 0), step_coef(c, tab, np, m), s);
         p0 = p1;
         p1 = pout;
         q0 = q1;
@@ -356,21 +548,21 @@ kpm_status finish_moments(kpm_system *sys, size_t elems, double2 *host) {
 template <typename V>
 kpm_status moments_impl(kpm_system *sys, int vshift, const void *phil, const void *phir,
                         int nm, double *mu) {
-    KPM_TRY(sys->ensure_vecs(2, 1 << vshift));
-    const int64_t r = 1 << vshift;
-    KPM_TRY(sys->ensure_dmom((size_t)r * nm));
+    KPM_TRY(sys->ensure_vecs(2, vshift));
+    const size_t elems = (size_t)sys->nseg * ((size_t)1 << vshift) * nm;
+    KPM_TRY(sys->ensure_dmom(elems));
     V *a = (V *)sys->vecs[0], *b = (V *)sys->vecs[1];
     KPM_TRY(run_moments<V>(sys, vshift, (const V *)phil, (const V *)phir, nm, a, b, nm, 0));
-    return finish_moments(sys, (size_t)r * nm, (double2 *)mu);
+    return finish_moments(sys, elems, (double2 *)mu);
 }
 
 template <typename V>
 kpm_status evolve_impl(kpm_system *sys, int vshift, void *phi, double dt, int sign, int np) {
-    KPM_TRY(sys->ensure_vecs(3, 1 << vshift));
+    KPM_TRY(sys->ensure_vecs(3, vshift));
     V *a = (V *)sys->vecs[0], *b = (V *)sys->vecs[1], *acc = (V *)sys->vecs[2];
     KPM_TRY(run_evolve<V>(sys, vshift, (const V *)phi, acc, nullptr, dt, sign, np, a, b));
-    KPM_HIP(hipMemcpyAsync(phi, acc, (size_t)sys->n * (1 << vshift) * sys->elem_bytes(),
-                           hipMemcpyDeviceToDevice, sys->stream));
+    KPM_HIP(hipMemcpyAsync(phi, acc, sys->state_bytes(vshift), hipMemcpyDeviceToDevice,
+                           sys->stream));
     KPM_HIP(hipGetLastError());
     return KPM_OK;
 }
@@ -378,7 +570,7 @@ kpm_status evolve_impl(kpm_system *sys, int vshift, void *phi, double dt, int si
 template <typename V>
 kpm_status evolve_x_impl(kpm_system *sys, int vshift, const void *phi, void *outx, void *outu,
                          double dt, int np) {
-    KPM_TRY(sys->ensure_vecs(5, 1 << vshift));
+    KPM_TRY(sys->ensure_vecs(5, vshift));
     V *pa = (V *)sys->vecs[0], *pb = (V *)sys->vecs[1], *qa = (V *)sys->vecs[2],
       *qb = (V *)sys->vecs[3], *u = (V *)sys->vecs[4];
     KPM_TRY(run_evolve_x<V>(sys, vshift, (const V *)phi, (V *)outx, outu ? (V *)outu : u, dt,
@@ -391,17 +583,18 @@ kpm_status evolve_x_impl(kpm_system *sys, int vshift, const void *phi, void *out
 template <typename V>
 kpm_status vac_impl(kpm_system *sys, int vshift, const void *phi_v, int nsteps, double dt,
                     int np, int nm, double *out) {
-    KPM_TRY(sys->ensure_vecs(7, 1 << vshift));
-    const int64_t r = 1 << vshift;
+    KPM_TRY(sys->ensure_vecs(7, vshift));
     const int64_t per_r = (int64_t)(nsteps + 1) * nm;
-    KPM_TRY(sys->ensure_dmom((size_t)r * per_r));
+    const size_t elems = (size_t)sys->nseg * ((size_t)1 << vshift) * per_r;
+    KPM_TRY(sys->ensure_dmom(elems));
     V *a = (V *)sys->vecs[0], *b = (V *)sys->vecs[1];
     V *psi = (V *)sys->vecs[2], *psi2 = (V *)sys->vecs[3];
     V *rr = (V *)sys->vecs[4], *rr2 = (V *)sys->vecs[5], *ll = (V *)sys->vecs[6];
     const V *phi = (const V *)phi_v;
     const kpm::Ell h = sys->ell();
-    const kpm::Sweep sw = sys->sweep(vshift);
-    const double2 alpha = make_double2(0.0, -sys->e_scale / kHbar);   // V = -i (E_s/hbar) D
+    kpm::Sweep sw;
+    KPM_TRY(sys->sweep(vshift, &sw));
+    const kpm::Coef alpha = sys->alpha();
     // R_0 = V phi; L_0 = V psi_0 = R_0
     kpm::launch_apply_d<V>(h, sw, phi, rr, alpha, sys->stream);
     KPM_TRY(run_moments<V>(sys, vshift, rr, rr, nm, a, b, per_r, 0));
@@ -415,7 +608,7 @@ kpm_status vac_impl(kpm_system *sys, int vshift, const void *phi_v, int nsteps, 
         kpm::launch_apply_d<V>(h, sw, psi, ll, alpha, sys->stream);
         KPM_TRY(run_moments<V>(sys, vshift, ll, rr, nm, a, b, per_r, (int64_t)k * nm));
     }
-    std::vector<double2> host((size_t)r * per_r);
+    std::vector<double2> host(elems);
     KPM_TRY(finish_moments(sys, host.size(), host.data()));
     for (size_t q = 0; q < host.size(); ++q) out[q] = host[q].x;
     return KPM_OK;
@@ -425,16 +618,16 @@ kpm_status vac_impl(kpm_system *sys, int vshift, const void *phi_v, int nsteps, 
 template <typename V>
 kpm_status msd_impl(kpm_system *sys, int vshift, const void *phi_v, int nsteps, double dt,
                     int np, int nm, double *out) {
-    KPM_TRY(sys->ensure_vecs(9, 1 << vshift));
-    const int64_t r = 1 << vshift;
+    KPM_TRY(sys->ensure_vecs(9, vshift));
     const int64_t per_r = (int64_t)(nsteps + 1) * nm;
-    KPM_TRY(sys->ensure_dmom((size_t)r * per_r));
+    const size_t elems = (size_t)sys->nseg * ((size_t)1 << vshift) * per_r;
+    KPM_TRY(sys->ensure_dmom(elems));
     V *pa = (V *)sys->vecs[0], *pb = (V *)sys->vecs[1], *qa = (V *)sys->vecs[2],
       *qb = (V *)sys->vecs[3];
     V *y = (V *)sys->vecs[4], *y2 = (V *)sys->vecs[5], *xu = (V *)sys->vecs[6];
     V *psi = (V *)sys->vecs[7], *psi2 = (V *)sys->vecs[8];
     // Y_0 = [X, U(0)] phi = 0: its moments are exactly zero.
-    KPM_HIP(hipMemsetAsync(sys->dmom, 0, (size_t)r * per_r * sizeof(double2), sys->stream));
+    KPM_HIP(hipMemsetAsync(sys->dmom, 0, elems * sizeof(double2), sys->stream));
     const V *cur = (const V *)phi_v;
     for (int k = 1; k <= nsteps; ++k) {
         // [X, U(dt)] psi'_{k-1} and psi'_k = U(dt) psi'_{k-1}
@@ -449,23 +642,18 @@ kpm_status msd_impl(kpm_system *sys, int vshift, const void *phi_v, int nsteps, 
         }
         KPM_TRY(run_moments<V>(sys, vshift, y, y, nm, pa, pb, per_r, (int64_t)k * nm));
     }
-    // keep the buffer roles stable across calls is not needed: every call
-    // overwrites what it reads before reading it
-    std::vector<double2> host((size_t)r * per_r);
+    std::vector<double2> host(elems);
     KPM_TRY(finish_moments(sys, host.size(), host.data()));
     for (size_t q = 0; q < host.size(); ++q) out[q] = host[q].x;
     return KPM_OK;
 }
 
-}  // namespace
-
-namespace {
 template <typename V>
 kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_launch *best) {
-    KPM_TRY(sys->ensure_vecs(2, 1 << vs));
+    KPM_TRY(sys->ensure_vecs(2, vs));
     V *a = (V *)sys->vecs[0], *b = (V *)sys->vecs[1];
     hipStream_t s = sys->stream;
-    const size_t bytes = (size_t)sys->n * ((size_t)1 << vs) * sys->elem_bytes();
+    const size_t bytes = sys->state_bytes(vs);
     const kpm::Ell h = sys->ell();
     static const int groups[] = {4, 8, 16};
     static const int ilps[] = {1, 2, 4};
@@ -476,17 +664,18 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
     KPM_HIP(hipEventCreate(&e1));
     kpm_status st = KPM_OK;
     // Each candidate runs the real two-buffer recursion (the output of one
-    // step is the gathered input of the next) on copies of phi, twice; the
-    // faster round counts.
+    // step is the gathered input of the next) on copies of phi, three times;
+    // the fastest round counts.
     for (int g : groups) {
         for (int q = 0; q < 6 && st == KPM_OK; ++q) {
             kpm_launch l;
             l.groups_per_cu = g;
             l.ilp = ilps[q % 3];
             l.streaming = q / 3;
-            const kpm::Sweep sw = sys->sweep_with(vs, l);
+            kpm::Sweep sw;
+            if ((st = sys->sweep_with(vs, l, &sw)) != KPM_OK) break;
             if ((st = sys->ensure_partial(1, sw.nwg, 1 << vs)) != KPM_OK) break;
-            for (int round = 0; round < 2; ++round) {
+            for (int round = 0; round < 3; ++round) {
                 if (hipMemcpyAsync(a, phi, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
                     hipMemcpyAsync(b, phi, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) {
                     st = fail(KPM_ERR_DEVICE, "autotune copy");
@@ -521,6 +710,113 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
     if (best) *best = pick;
     return KPM_OK;
 }
+
+// Builds the device system from validated samples laid side by side.
+kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int device,
+                        void *hip_stream, kpm_system **out) {
+    const int nseg = (int)parts.size();
+    int64_t n = 0;
+    int w = 0;
+    bool any_hop = false, all_dx = true;
+    for (const Packed &p : parts) {
+        n += p.n;
+        w = std::max(w, p.w);
+        any_hop = any_hop || !p.hop.empty();
+        all_dx = all_dx && !p.dx.empty();
+    }
+    if (n >= ((int64_t)1 << 31)) return fail(KPM_ERR_INVALID, "total rows %lld exceed 2^31", (long long)n);
+
+    kpm_system *sys = new (std::nothrow) kpm_system();
+    if (!sys) return fail(KPM_ERR_OOM, "host allocation");
+    auto bail = [&](kpm_status st) {
+        delete sys;
+        return st;
+    };
+    sys->device = device;
+    sys->stream = (hipStream_t)hip_stream;
+    sys->prec = prec;
+    sys->n = n;
+    sys->w = w;
+    sys->nseg = nseg;
+    sys->has_dx = all_dx;
+    sys->off.assign(nseg + 1, 0);
+    sys->es.resize(nseg);
+    for (int s = 0; s < nseg; ++s) {
+        sys->off[s + 1] = sys->off[s] + parts[s].n;
+        sys->es[s] = parts[s].e_scale;
+    }
+    for (int v = 0; v < 7; ++v) sys->launch[v] = default_launch(v);
+    if (const char *env = std::getenv("KPM_GROUPS_PER_CU"))
+        for (auto &l : sys->launch) l.groups_per_cu = std::max(1, std::min(32, atoi(env)));
+    if (const char *env = std::getenv("KPM_ILP"))
+        for (auto &l : sys->launch) l.ilp = atoi(env) >= 4 ? 4 : (atoi(env) == 2 ? 2 : 1);
+    if (const char *env = std::getenv("KPM_STREAMING"))
+        for (auto &l : sys->launch) l.streaming = atoi(env) != 0;
+
+    // Concatenate, shift indices by the sample offset, fold 1/E_s of each
+    // sample into its rows.
+    std::vector<int32_t> nbr((size_t)w * n, -1);
+    std::vector<double> ons(n), hop(any_hop ? (size_t)w * n : 0), xw(all_dx ? (size_t)w * n : 0);
+    std::vector<double> tsc(nseg > 1 && !any_hop ? n : 0);
+    for (int s = 0; s < nseg; ++s) {
+        const Packed &p = parts[s];
+        const int64_t o = sys->off[s];
+        const double inv = 1.0 / p.e_scale;
+        for (int64_t r = 0; r < p.n; ++r) {
+            ons[o + r] = p.ons[r] * inv;
+            if (!tsc.empty()) tsc[o + r] = p.t * inv;
+            for (int k = 0; k < p.w; ++k) {
+                const size_t q = (size_t)k * p.n + r, qq = (size_t)k * n + o + r;
+                const int32_t m = p.nbr[q];
+                nbr[qq] = m >= 0 ? (int32_t)(m + o) : -1;
+                const double hv = p.hop.empty() ? p.t : p.hop[q];
+                if (any_hop) hop[qq] = m >= 0 ? hv * inv : 0.0;
+                if (all_dx) xw[qq] = m >= 0 ? p.dx[q] * hv * inv : 0.0;
+            }
+        }
+    }
+    sys->t_scaled = parts[0].t / parts[0].e_scale;
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return bail(fail(KPM_ERR_DEVICE, "no HIP device %d", device));
+    DeviceGuard guard(device);
+    if (hipDeviceGetAttribute(&sys->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        sys->cus = 256;
+    auto upload = [&](void **dst, const void *src, size_t bytes) -> kpm_status {
+        hipError_t e = hipMalloc(dst, bytes);
+        if (e != hipSuccess) return fail(KPM_ERR_OOM, "hipMalloc %zu bytes: %s", bytes, hipGetErrorString(e));
+        e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail(KPM_ERR_DEVICE, "upload: %s", hipGetErrorString(e));
+        return KPM_OK;
+    };
+    kpm_status st = upload((void **)&sys->d_nbr, nbr.data(), nbr.size() * sizeof(int32_t));
+    if (st == KPM_OK) st = upload((void **)&sys->d_ons, ons.data(), ons.size() * sizeof(double));
+    if (st == KPM_OK && any_hop) st = upload((void **)&sys->d_hop, hop.data(), hop.size() * sizeof(double));
+    if (st == KPM_OK && !tsc.empty()) st = upload((void **)&sys->d_tsc, tsc.data(), tsc.size() * sizeof(double));
+    if (st == KPM_OK && all_dx) st = upload((void **)&sys->d_xw, xw.data(), xw.size() * sizeof(double));
+    if (st == KPM_OK && nseg > 1) {
+        std::vector<double2> al(nseg);
+        for (int s = 0; s < nseg; ++s) al[s] = make_double2(0.0, -sys->es[s] / kHbar);
+        st = upload((void **)&sys->d_alpha, al.data(), al.size() * sizeof(double2));
+    }
+    if (st != KPM_OK) return bail(st);
+    *out = sys;
+    return KPM_OK;
+}
+
+kpm_status check_loop(kpm_system *sys, int n_vec, const void *phi, int n_steps, double dt_fs,
+                      int n_bessel, int n_moments, double *out, int *vs) {
+    KPM_TRY(check_common(sys, n_vec, vs));
+    if (!phi || !out) return fail(KPM_ERR_INVALID, "null buffer");
+    if (!sys->has_dx) return fail(KPM_ERR_INVALID, "system has no dx (velocity operator)");
+    if (n_steps < 0) return fail(KPM_ERR_INVALID, "n_steps must be >= 0");
+    if (n_bessel < 2) return fail(KPM_ERR_INVALID, "n_bessel must be >= 2");
+    if (n_moments < 1) return fail(KPM_ERR_INVALID, "n_moments must be >= 1");
+    if (!std::isfinite(dt_fs) || dt_fs < 0) return fail(KPM_ERR_INVALID, "dt_fs");
+    return KPM_OK;
+}
+
 }  // namespace
 
 // ======================================================================= ABI
@@ -528,7 +824,7 @@ extern "C" {
 
 const char *kpm_last_error(void) { return g_err.c_str(); }
 
-const char *kpm_version(void) { return "kpm-mi355x 0.1 (gfx950)"; }
+const char *kpm_version(void) { return "kpm-mi355x 0.2 (gfx950)"; }
 
 kpm_status kpm_build_graphene(int64_t nx, int64_t ny, kpm_geometry geometry,
                               const uint8_t *active, int32_t *nbr, double *dx) {
@@ -552,8 +848,8 @@ kpm_status kpm_build_graphene(int64_t nx, int64_t ny, kpm_geometry geometry,
             if (ri >= nx) { rok = pbc_x; ri -= nx; }
             if (vj < 0) { vok = pbc_y; vj += ny; }
             if (vj >= ny) { vok = pbc_y; vj -= ny; }
-            int64_t m[3] = {j * nx + li, j * nx + ri, vj * nx + i};
-            bool ok[3] = {lok, rok, vok};
+            const int64_t m[3] = {j * nx + li, j * nx + ri, vj * nx + i};
+            const bool ok[3] = {lok, rok, vok};
             // displacement X_s - X_m of each slot along the transport axis
             double d[3];
             if (geometry == KPM_AGNR) {
@@ -568,7 +864,7 @@ kpm_status kpm_build_graphene(int64_t nx, int64_t ny, kpm_geometry geometry,
             }
             const bool alive = !active || active[s];
             for (int k = 0; k < 3; ++k) {
-                bool use = alive && ok[k] && (!active || active[m[k]]);
+                const bool use = alive && ok[k] && (!active || active[m[k]]);
                 nbr[k * n + s] = use ? (int32_t)m[k] : -1;
                 if (dx) dx[k * n + s] = use ? d[k] : 0.0;
             }
@@ -579,113 +875,18 @@ kpm_status kpm_build_graphene(int64_t nx, int64_t ny, kpm_geometry geometry,
 
 kpm_status kpm_system_create(const kpm_system_desc *d, kpm_precision prec, int device,
                              void *hip_stream, kpm_system **out) {
-    if (!d || !out) return fail(KPM_ERR_INVALID, "null descriptor or output");
+    return kpm_batch_create(1, d, prec, device, hip_stream, out);
+}
+
+kpm_status kpm_batch_create(int n_sys, const kpm_system_desc *descs, kpm_precision prec,
+                            int device, void *hip_stream, kpm_system **out) {
+    if (!descs || !out) return fail(KPM_ERR_INVALID, "null descriptor or output");
     *out = nullptr;
-    const int64_t n = d->n_sites;
-    const int w = d->width;
-    if (n < 1 || n >= ((int64_t)1 << 31)) return fail(KPM_ERR_INVALID, "n_sites out of range");
-    if (w < 1 || w > KPM_MAX_WIDTH) return fail(KPM_ERR_INVALID, "width must be 1..%d", KPM_MAX_WIDTH);
-    if (!d->nbr) return fail(KPM_ERR_INVALID, "nbr is null");
+    if (n_sys < 1 || n_sys > 4096) return fail(KPM_ERR_INVALID, "n_sys must be 1..4096");
     if (prec != KPM_FP64 && prec != KPM_FP32_STATES) return fail(KPM_ERR_INVALID, "precision");
-    if (!(d->e_scale > 0) || !std::isfinite(d->e_scale)) return fail(KPM_ERR_INVALID, "e_scale");
-
-    // Pack: removed sites lose every bond and their on-site energy.
-    std::vector<int32_t> nbr((size_t)w * n);
-    std::vector<double> hop(d->hop ? (size_t)w * n : 0), ons(n, 0.0);
-    std::vector<double> dxs(d->dx ? (size_t)w * n : 0);
-    auto alive = [&](int64_t s) { return !d->active || d->active[s] != 0; };
-    for (int64_t s = 0; s < n; ++s) {
-        ons[s] = (alive(s) && d->onsite) ? d->onsite[s] : 0.0;
-        if (!std::isfinite(ons[s])) return fail(KPM_ERR_INVALID, "non-finite onsite at %lld", (long long)s);
-        for (int k = 0; k < w; ++k) {
-            const size_t q = (size_t)k * n + s;
-            int32_t m = d->nbr[q];
-            if (m < -1 || m >= n) return fail(KPM_ERR_INVALID, "neighbour index %d out of range at row %lld slot %d", m, (long long)s, k);
-            if (m >= 0 && (!alive(s) || !alive(m))) m = -1;
-            nbr[q] = m;
-            if (d->hop) hop[q] = m >= 0 ? d->hop[q] : 0.0;
-            if (d->dx) dxs[q] = m >= 0 ? d->dx[q] : 0.0;
-        }
-    }
-    // Symmetry: every bond listed from both ends with equal H and opposite dx.
-    const double tu = d->t_uniform;
-    double gersh = 0.0;
-    for (int64_t s = 0; s < n; ++s) {
-        double row = std::fabs(ons[s]);
-        for (int k = 0; k < w; ++k) {
-            const size_t q = (size_t)k * n + s;
-            const int32_t m = nbr[q];
-            if (m < 0) continue;
-            const double hv = d->hop ? hop[q] : tu;
-            row += std::fabs(hv);
-            bool found = false;
-            for (int k2 = 0; k2 < w && !found; ++k2) {
-                const size_t q2 = (size_t)k2 * n + m;
-                if (nbr[q2] != s) continue;
-                const double hb = d->hop ? hop[q2] : tu;
-                if (hb != hv) continue;
-                if (d->dx && dxs[q2] != -dxs[q]) continue;
-                found = true;
-            }
-            if (!found)
-                return fail(KPM_ERR_INVALID, "H not symmetric (or dx not antisymmetric) at row %lld slot %d", (long long)s, k);
-        }
-        gersh = std::max(gersh, row);
-    }
-    if (d->e_scale < gersh)
-        return fail(KPM_ERR_INVALID, "e_scale %.6g below the Gershgorin bound %.6g", d->e_scale, gersh);
-
-    kpm_system *sys = new (std::nothrow) kpm_system();
-    if (!sys) return fail(KPM_ERR_OOM, "host allocation");
-    sys->device = device;
-    sys->stream = (hipStream_t)hip_stream;
-    sys->prec = prec;
-    sys->n = n;
-    sys->w = w;
-    sys->e_scale = d->e_scale;
-    sys->has_dx = d->dx != nullptr;
-    sys->t_scaled = tu / d->e_scale;
-    for (int v = 0; v < 7; ++v) sys->launch[v] = default_launch(v);
-    if (const char *env = std::getenv("KPM_GROUPS_PER_CU"))
-        for (auto &l : sys->launch) l.groups_per_cu = std::max(1, atoi(env));
-    if (const char *env = std::getenv("KPM_ILP"))
-        for (auto &l : sys->launch) l.ilp = std::max(1, atoi(env));
-    if (const char *env = std::getenv("KPM_STREAMING"))
-        for (auto &l : sys->launch) l.streaming = atoi(env) != 0;
-
-    auto bail = [&](kpm_status st) { delete sys; return st; };
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
-        return bail(fail(KPM_ERR_DEVICE, "no HIP device %d", device));
-    DeviceGuard guard(device);
-    if (hipDeviceGetAttribute(&sys->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
-        sys->cus = 256;
-
-    std::vector<double> hs, xw;
-    if (d->hop) {
-        hs.resize(hop.size());
-        for (size_t q = 0; q < hop.size(); ++q) hs[q] = hop[q] / d->e_scale;
-    }
-    if (d->dx) {
-        xw.resize(dxs.size());
-        for (size_t q = 0; q < dxs.size(); ++q)
-            xw[q] = nbr[q] >= 0 ? dxs[q] * ((d->hop ? hop[q] : tu) / d->e_scale) : 0.0;
-    }
-    for (auto &o : ons) o /= d->e_scale;
-    auto upload = [&](void **dst, const void *src, size_t bytes) -> kpm_status {
-        hipError_t e = hipMalloc(dst, bytes);
-        if (e != hipSuccess) return fail(KPM_ERR_OOM, "hipMalloc %zu bytes: %s", bytes, hipGetErrorString(e));
-        e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
-        if (e != hipSuccess) return fail(KPM_ERR_DEVICE, "upload: %s", hipGetErrorString(e));
-        return KPM_OK;
-    };
-    kpm_status st = upload((void **)&sys->d_nbr, nbr.data(), nbr.size() * sizeof(int32_t));
-    if (st == KPM_OK) st = upload((void **)&sys->d_ons, ons.data(), ons.size() * sizeof(double));
-    if (st == KPM_OK && d->hop) st = upload((void **)&sys->d_hop, hs.data(), hs.size() * sizeof(double));
-    if (st == KPM_OK && d->dx) st = upload((void **)&sys->d_xw, xw.data(), xw.size() * sizeof(double));
-    if (st != KPM_OK) return bail(st);
-    *out = sys;
-    return KPM_OK;
+    std::vector<Packed> parts(n_sys);
+    for (int s = 0; s < n_sys; ++s) KPM_TRY(pack_desc(&descs[s], s, parts[s]));
+    return build_system(parts, prec, device, hip_stream, out);
 }
 
 kpm_status kpm_system_destroy(kpm_system *sys) {
@@ -705,6 +906,14 @@ kpm_status kpm_system_set_stream(kpm_system *sys, void *hip_stream) {
 }
 
 int64_t kpm_system_n_sites(const kpm_system *sys) { return sys ? sys->n : -1; }
+
+int32_t kpm_system_n_samples(const kpm_system *sys) { return sys ? sys->nseg : -1; }
+
+kpm_status kpm_system_offsets(const kpm_system *sys, int64_t *offsets) {
+    if (!sys || !offsets) return fail(KPM_ERR_INVALID, "null argument");
+    for (int s = 0; s <= sys->nseg; ++s) offsets[s] = sys->off[s];
+    return KPM_OK;
+}
 
 kpm_status kpm_moments(kpm_system *sys, int n_vec, const void *phil, const void *phir,
                        int n_moments, double *mu) {
@@ -746,18 +955,6 @@ kpm_status kpm_evolve_x(kpm_system *sys, int n_vec, const void *phi, void *out_x
                : evolve_x_impl<float2>(sys, vs, phi, out_x, out_u, dt_fs, n_bessel);
 }
 
-static kpm_status check_loop(kpm_system *sys, int n_vec, const void *phi, int n_steps,
-                             double dt_fs, int n_bessel, int n_moments, double *out, int *vs) {
-    KPM_TRY(check_common(sys, n_vec, vs));
-    if (!phi || !out) return fail(KPM_ERR_INVALID, "null buffer");
-    if (!sys->has_dx) return fail(KPM_ERR_INVALID, "system has no dx (velocity operator)");
-    if (n_steps < 0) return fail(KPM_ERR_INVALID, "n_steps must be >= 0");
-    if (n_bessel < 2) return fail(KPM_ERR_INVALID, "n_bessel must be >= 2");
-    if (n_moments < 1) return fail(KPM_ERR_INVALID, "n_moments must be >= 1");
-    if (!std::isfinite(dt_fs) || dt_fs < 0) return fail(KPM_ERR_INVALID, "dt_fs");
-    return KPM_OK;
-}
-
 kpm_status kpm_vac(kpm_system *sys, int n_vec, const void *phi, int n_steps, double dt_fs,
                    int n_bessel, int n_moments, double *out) {
     int vs;
@@ -788,9 +985,9 @@ kpm_status kpm_kpm_sum(int n_rows, int n_moments, const double *moments, int n_e
     const double a = 1.0 / (n_moments + 1);
     for (int m = 0; m < n_moments; ++m) {
         // Jackson damping, Eq. 35
-        double g = jackson ? (1 - m * a) * std::cos(kPi * m * a) +
-                                 a * std::sin(kPi * m * a) / std::tan(kPi * a)
-                           : 1.0;
+        const double g = jackson ? (1 - m * a) * std::cos(kPi * m * a) +
+                                       a * std::sin(kPi * m * a) / std::tan(kPi * a)
+                                 : 1.0;
         w[m] = g * (m == 0 ? 1.0 : 2.0);
     }
     for (int k = 0; k < n_energies; ++k) {
@@ -881,7 +1078,6 @@ kpm_status kpm_get_launch(kpm_system *sys, int n_vec, kpm_launch *out) {
     *out = sys->launch[vs];
     return KPM_OK;
 }
-
 
 kpm_status kpm_autotune(kpm_system *sys, int n_vec, const void *phi, int reps, kpm_launch *best) {
     int vs;

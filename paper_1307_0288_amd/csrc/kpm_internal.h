@@ -15,30 +15,53 @@ constexpr int kMaxWidth = 4;      // neighbour-list slots per row
 // Scaled sparse Hamiltonian on the device (neighbour-list layout of Alg. 8).
 struct Ell {
     const int32_t *nbr;   // [w][n] neighbour row, -1 = empty slot
-    const double *hop;    // [w][n] H_nm / E_s, or nullptr: every slot is t
+    const double *hop;    // [w][n] H_nm / E_s, or nullptr
+    const double *tsc;    // [n] hopping / E_s of the row's sample, or nullptr
     const double *xw;     // [w][n] (X_n - X_m) H_nm / E_s, or nullptr
     const double *ons;    // [n] H_nn / E_s
-    double t;             // uniform H_nm / E_s
+    double t;             // uniform H_nm / E_s when hop and tsc are nullptr
     int64_t n;            // rows
     int w;                // slots per row
 };
 
-// Persistent, XCD-aware sweep over `total` = rows * vectors elements.
-// Work-groups are dispatched round-robin over the XCDs, so group g runs on
-// XCD g % 8.  The element blocks are cut into 8 contiguous ranges, one per
-// XCD, and the groups of an XCD stride through its range together: rows
-// that share neighbours are then served by the same L2.
+// A segment is one independent sample of a batch: a contiguous element range
+// [e0, e1) and the contiguous work-groups [g0, g0 + nwg) that sweep it
+// (g0 and nwg multiples of 8).  A plain system is a single segment.
+struct Seg {
+    int64_t e0, e1;
+    int32_t g0, nwg;
+};
+
+// Persistent, XCD-aware sweep.  Work-groups are dispatched round-robin over
+// the XCDs, so group g runs on XCD g % 8.  Inside its segment, the element
+// blocks are cut into 8 contiguous ranges, one per XCD, and the segment's
+// groups on an XCD stride through that range together: rows that share
+// neighbours are then served by the same L2.
 struct Sweep {
-    int64_t total;        // elements (rows << vshift)
-    int64_t nblk;         // ceil(total / kBlock)
-    int64_t per_xcd;      // blocks per XCD range
+    int64_t total;        // elements of the whole system (rows << vshift)
     int nwg;              // work-groups in the grid (multiple of 8)
     int vshift;           // log2(vectors per row)
     int ilp;              // elements per thread per pass in the moment step (1, 2, 4)
     int nt;               // streaming (non-temporal) access to phi_0, phi_L and the output
+    int nseg;             // segments
+    const Seg *seg;       // [nseg] device table, or nullptr for one segment
+    const int32_t *wg_seg;// [nwg] device table: segment of each group (with seg)
+    Seg one;              // the segment when seg is nullptr
 };
 
-Sweep make_sweep(int64_t rows, int vshift, int nwg, int ilp, int nt);
+// Coefficient of a step: the value for segment s is tab[s * stride + idx]
+// when tab is set, else val.
+struct Coef {
+    const double2 *tab;
+    int stride;
+    int idx;
+    double2 val;
+};
+
+inline Coef coef_val(double2 v) { return Coef{nullptr, 0, 0, v}; }
+inline Coef coef_tab(const double2 *t, int stride, int idx, double2 v) {
+    return Coef{t, stride, idx, v};
+}
 
 // --- launchers (all asynchronous on `s`) ----------------------------------
 // Chebyshev moment step (Alg. 5 fused with Alg. 8 and the inner product):
@@ -55,8 +78,8 @@ void launch_moment_step(const Ell &h, const Sweep &sw, bool first, const V *p1,
 //   else : out = 2 H~ p1 - p0 (out may alias p0); acc += c out
 template <typename V>
 void launch_evolve_step(const Ell &h, const Sweep &sw, bool first, const V *p1,
-                        const V *p0, V *out, V *acc, const V *add, double2 c0,
-                        double2 c, hipStream_t s);
+                        const V *p0, V *out, V *acc, const V *add, Coef c0, Coef c,
+                        hipStream_t s);
 
 // Coupled T_m / [X, T_m] step (Alg. 7, Eq. 38-41), accumulating both sums:
 //   first: pout = H~ in, qout = D in; accx = c qout; accu = c0 in + c pout
@@ -65,17 +88,17 @@ void launch_evolve_step(const Ell &h, const Sweep &sw, bool first, const V *p1,
 template <typename V>
 void launch_evolve_x_step(const Ell &h, const Sweep &sw, bool first, const V *p1,
                           const V *p0, V *pout, const V *q1, const V *q0, V *qout,
-                          V *accx, V *accu, double2 c0, double2 c, hipStream_t s);
+                          V *accx, V *accu, Coef c0, Coef c, hipStream_t s);
 
-// y = alpha * D x, D = [X, H~].
+// y = alpha D x, D = [X, H~].
 template <typename V>
-void launch_apply_d(const Ell &h, const Sweep &sw, const V *x, V *y, double2 alpha,
+void launch_apply_d(const Ell &h, const Sweep &sw, const V *x, V *y, Coef alpha,
                     hipStream_t s);
 
-// dst[r * stride_r + offset + j] = sum_g partial[j][g][r] for j < slots, in a
-// fixed order (deterministic).
-void launch_reduce(const double2 *partial, int nwg, int vshift, int slots,
-                   double2 *dst, int64_t stride_r, int64_t offset, hipStream_t s);
+// dst[(seg * R + r) * stride_r + offset + j] = sum over the segment's groups g
+// of partial[j][g][r], j < slots, in a fixed order (deterministic).
+void launch_reduce(const double2 *partial, const Sweep &sw, int slots, double2 *dst,
+                   int64_t stride_r, int64_t offset, hipStream_t s);
 
 // out[t][k] = pref_k sum_m w_m T_m(e_k) mom[t][m]  (KPM sum, Eq. 29-31).
 void launch_kpm_sum(const double *mom, int rows, int nm, const double *w,

@@ -11,6 +11,10 @@
 // partial per work-group that a second small kernel sums in a fixed order.
 // The path is bound by HBM bandwidth (about 0.3 flop per byte), so there is
 // no matrix-core work here.
+//
+// A system may hold several independent samples (segments) side by side;
+// every work-group belongs to exactly one segment (see Seg in
+// kpm_internal.h), so per-sample inner products need no atomics.
 #include "kpm_internal.h"
 
 namespace kpm {
@@ -84,18 +88,28 @@ __device__ __forceinline__ double2 two_minus(double2 a, double2 b) {
     return make_double2(fma(2.0, a.x, -b.x), fma(2.0, a.y, -b.y));
 }
 
+__device__ __forceinline__ double2 coef(const Coef &c, int sg) {
+    return c.tab ? c.tab[sg * c.stride + c.idx] : c.val;
+}
+
+// Uniform hopping of row i (per-slot values are read separately).
+__device__ __forceinline__ double row_t(const Ell &h, int64_t i) {
+    return h.tsc ? h.tsc[i] : h.t;
+}
+
 // Sum of H~_im x_m over the filled slots of row i, plus the diagonal term.
 template <typename V>
-__device__ __forceinline__ double2 row_h(const Ell &h, const V *x, int64_t i,
-                                         int64_t v, int vshift, double2 xi) {
-    double o = h.ons[i];
+__device__ __forceinline__ double2 row_h(const Ell &h, const V *x, int64_t i, int64_t v,
+                                         int vshift, double2 xi) {
+    const double o = h.ons[i];
+    const double tr = row_t(h, i);
     double2 acc = make_double2(o * xi.x, o * xi.y);
 #pragma unroll
     for (int k = 0; k < kMaxWidth; ++k) {
         if (k < h.w) {
-            int32_t m = h.nbr[k * h.n + i];
-            double hk = h.hop ? h.hop[k * h.n + i] : h.t;
-            double2 xm = ld(x + ((int64_t)(m < 0 ? 0 : m) << vshift) + v);
+            const int32_t m = h.nbr[k * h.n + i];
+            double hk = h.hop ? h.hop[k * h.n + i] : tr;
+            const double2 xm = ld(x + ((int64_t)(m < 0 ? 0 : m) << vshift) + v);
             hk = m < 0 ? 0.0 : hk;
             acc = raxpy(acc, hk, xm);
         }
@@ -107,16 +121,17 @@ __device__ __forceinline__ double2 row_h(const Ell &h, const V *x, int64_t i,
 template <typename V>
 __device__ __forceinline__ void row_hd(const Ell &h, const V *x, int64_t i, int64_t v,
                                        int vshift, double2 xi, double2 &hx, double2 &dx) {
-    double o = h.ons[i];
+    const double o = h.ons[i];
+    const double tr = row_t(h, i);
     hx = make_double2(o * xi.x, o * xi.y);
     dx = make_double2(0.0, 0.0);
 #pragma unroll
     for (int k = 0; k < kMaxWidth; ++k) {
         if (k < h.w) {
-            int32_t m = h.nbr[k * h.n + i];
-            double hk = h.hop ? h.hop[k * h.n + i] : h.t;
+            const int32_t m = h.nbr[k * h.n + i];
+            double hk = h.hop ? h.hop[k * h.n + i] : tr;
             double xk = h.xw[k * h.n + i];
-            double2 xm = ld(x + ((int64_t)(m < 0 ? 0 : m) << vshift) + v);
+            const double2 xm = ld(x + ((int64_t)(m < 0 ? 0 : m) << vshift) + v);
             hk = m < 0 ? 0.0 : hk;
             xk = m < 0 ? 0.0 : xk;
             hx = raxpy(hx, hk, xm);
@@ -133,9 +148,9 @@ __device__ __forceinline__ double2 row_d(const Ell &h, const V *x, int64_t i, in
 #pragma unroll
     for (int k = 0; k < kMaxWidth; ++k) {
         if (k < h.w) {
-            int32_t m = h.nbr[k * h.n + i];
+            const int32_t m = h.nbr[k * h.n + i];
             double xk = h.xw[k * h.n + i];
-            double2 xm = ld(x + ((int64_t)(m < 0 ? 0 : m) << vshift) + v);
+            const double2 xm = ld(x + ((int64_t)(m < 0 ? 0 : m) << vshift) + v);
             xk = m < 0 ? 0.0 : xk;
             dx = raxpy(dx, xk, xm);
         }
@@ -165,16 +180,43 @@ __device__ __forceinline__ void block_sum(double2 s, int vshift, double2 *dst) {
     }
 }
 
-// Iterates the element blocks assigned to this work-group (see Sweep).
+// The element blocks this work-group visits: blocks b0 + loc, b0 + loc +
+// nloc, ... below b1 of its segment, elements e0 + b * kBlock + tid below e1.
+struct Walk {
+    int sg;
+    int loc, nloc;
+    int64_t b0, b1, e0, e1;
+};
+
+__device__ __forceinline__ Walk walk_of(const Sweep &sw) {
+    Walk w;
+    Seg s;
+    if (sw.seg) {
+        w.sg = sw.wg_seg[blockIdx.x];
+        s = sw.seg[w.sg];
+    } else {
+        w.sg = 0;
+        s = sw.one;
+    }
+    const int lb = (int)blockIdx.x - s.g0;      // g0 % 8 == 0: lb % 8 is the XCD
+    w.loc = lb / kXcds;
+    w.nloc = s.nwg / kXcds;
+    const int64_t nblk = (s.e1 - s.e0 + kBlock - 1) / kBlock;
+    const int64_t per = (nblk + kXcds - 1) / kXcds;
+    w.b0 = (int64_t)(lb % kXcds) * per;
+    w.b1 = min(w.b0 + per, nblk);
+    w.e0 = s.e0;
+    w.e1 = s.e1;
+    return w;
+}
+
 #define KPM_SWEEP_BEGIN(sw)                                                         \
-    const int xcd_ = blockIdx.x % kXcds;                                            \
-    const int loc_ = blockIdx.x / kXcds;                                            \
-    const int nloc_ = (sw).nwg / kXcds;                                             \
-    const int64_t b0_ = (int64_t)xcd_ * (sw).per_xcd;                               \
-    const int64_t b1_ = min(b0_ + (sw).per_xcd, (sw).nblk);                         \
-    for (int64_t b_ = b0_ + loc_; b_ < b1_; b_ += nloc_) {                          \
-        const int64_t e = b_ * kBlock + threadIdx.x;                                \
-        if (e < (sw).total) {                                                       \
+    const Walk wk_ = walk_of(sw);                                                   \
+    const int sg = wk_.sg;                                                          \
+    (void)sg;                                                                       \
+    for (int64_t b_ = wk_.b0 + wk_.loc; b_ < wk_.b1; b_ += wk_.nloc) {              \
+        const int64_t e = wk_.e0 + b_ * kBlock + threadIdx.x;                       \
+        if (e < wk_.e1) {                                                           \
             const int64_t i = e >> (sw).vshift;                                     \
             const int64_t v = e & ((1 << (sw).vshift) - 1);
 #define KPM_SWEEP_END \
@@ -182,65 +224,49 @@ __device__ __forceinline__ void block_sum(double2 s, int vshift, double2 *dst) {
     }
 
 // ---------------------------------------------------------------- kernels
-template <typename V, bool FIRST>
+// First step of the moments: out = H~ in, <L|in> and <L|out>.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_moment_first(Ell h, Sweep sw, const V *in, V *out,
+                                                         const V *__restrict__ phil,
+                                                         double2 *__restrict__ partial,
+                                                         int slot) {
+    double2 s0 = make_double2(0.0, 0.0), s1 = make_double2(0.0, 0.0);
+    KPM_SWEEP_BEGIN(sw)
+    const double2 xi = ld(in + e);
+    const double2 l = ld(phil + e);
+    const double2 o = rounded<V>(row_h(h, in, i, v, sw.vshift, xi));
+    st(out + e, o);
+    s0 = cdot_acc(s0, l, xi);
+    s1 = cdot_acc(s1, l, o);
+    KPM_SWEEP_END
+    const int64_t r = (int64_t)1 << sw.vshift;
+    block_sum(s0, sw.vshift, partial + ((int64_t)slot * sw.nwg + blockIdx.x) * r);
+    block_sum(s1, sw.vshift, partial + ((int64_t)(slot + 1) * sw.nwg + blockIdx.x) * r);
+}
+
+// Recursion step of the moments, out = 2 H~ p1 - p0 and <L|out>, with ILP
+// elements per thread per pass: all loads of the ILP elements are issued
+// before any arithmetic, so a wavefront keeps ILP times more bytes in flight
+// (the gathers depend on the index loads, which would otherwise serialise
+// two memory latencies per element).  Elements are visited in the same order
+// for every ILP, so every ILP gives bit-identical results.
+template <typename V, int ILP, bool NT>
 __global__ __launch_bounds__(kBlock) void k_moment_step(Ell h, Sweep sw, const V *p1,
                                                         const V *p0, V *out,
                                                         const V *__restrict__ phil,
                                                         double2 *__restrict__ partial,
                                                         int slot) {
-    double2 s0 = make_double2(0.0, 0.0), s1 = make_double2(0.0, 0.0);
-    KPM_SWEEP_BEGIN(sw)
-    double2 xi = ld(p1 + e);
-    double2 l = ld(phil + e);
-    double2 hx = row_h(h, p1, i, v, sw.vshift, xi);
-    double2 o;
-    if (FIRST) {
-        o = hx;
-        s1 = cdot_acc(s1, l, xi);
-    } else {
-        o = two_minus(hx, ld(p0 + e));
-    }
-    // the dot uses the stored (rounded) value, which the next step reads
-    o = rounded<V>(o);
-    st(out + e, o);
-    s0 = cdot_acc(s0, l, o);
-    KPM_SWEEP_END
-    const int64_t r = (int64_t)1 << sw.vshift;
-    if (FIRST) {
-        block_sum(s1, sw.vshift, partial + ((int64_t)slot * sw.nwg + blockIdx.x) * r);
-        block_sum(s0, sw.vshift, partial + ((int64_t)(slot + 1) * sw.nwg + blockIdx.x) * r);
-    } else {
-        block_sum(s0, sw.vshift, partial + ((int64_t)slot * sw.nwg + blockIdx.x) * r);
-    }
-}
-
-// Recursion step of the moments with ILP elements per thread per pass: all
-// loads of the ILP elements are issued before any arithmetic, so a wavefront
-// keeps ILP times more bytes in flight (the gathers depend on the index
-// loads, which would otherwise serialise two memory latencies per element).
-// Elements are visited in the same order as with one element per pass, so
-// every ILP gives bit-identical results.
-template <typename V, int ILP, bool NT>
-__global__ __launch_bounds__(kBlock) void k_moment_step_ilp(Ell h, Sweep sw, const V *p1,
-                                                            const V *p0, V *out,
-                                                            const V *__restrict__ phil,
-                                                            double2 *__restrict__ partial,
-                                                            int slot) {
     double2 s0 = make_double2(0.0, 0.0);
-    const int xcd = blockIdx.x % kXcds;
-    const int loc = blockIdx.x / kXcds;
-    const int nloc = sw.nwg / kXcds;
-    const int64_t b0 = (int64_t)xcd * sw.per_xcd;
-    const int64_t b1 = min(b0 + sw.per_xcd, sw.nblk);
+    const Walk wk = walk_of(sw);
     const int64_t vmask = ((int64_t)1 << sw.vshift) - 1;
-    for (int64_t b = b0 + loc; b < b1; b += (int64_t)nloc * ILP) {
+    for (int64_t b = wk.b0 + wk.loc; b < wk.b1; b += (int64_t)wk.nloc * ILP) {
         int64_t e[ILP];
         bool ok[ILP];
 #pragma unroll
         for (int u = 0; u < ILP; ++u) {
-            const int64_t bu = b + (int64_t)u * nloc;
-            e[u] = bu * kBlock + threadIdx.x;
-            ok[u] = bu < b1 && e[u] < sw.total;
+            const int64_t bu = b + (int64_t)u * wk.nloc;
+            e[u] = wk.e0 + bu * kBlock + threadIdx.x;
+            ok[u] = bu < wk.b1 && e[u] < wk.e1;
             e[u] = ok[u] ? e[u] : 0;          // a safe element; its result is dropped
         }
         int32_t m[ILP][kMaxWidth];
@@ -250,11 +276,12 @@ __global__ __launch_bounds__(kBlock) void k_moment_step_ilp(Ell h, Sweep sw, con
 #pragma unroll
         for (int u = 0; u < ILP; ++u) {
             const int64_t i = e[u] >> sw.vshift;
+            const double tr = row_t(h, i);
 #pragma unroll
             for (int k = 0; k < kMaxWidth; ++k) {
                 if (k < h.w) {
                     m[u][k] = h.nbr[k * h.n + i];
-                    hk[u][k] = h.hop ? h.hop[k * h.n + i] : h.t;
+                    hk[u][k] = h.hop ? h.hop[k * h.n + i] : tr;
                 }
             }
             on[u] = h.ons[i];
@@ -281,7 +308,10 @@ __global__ __launch_bounds__(kBlock) void k_moment_step_ilp(Ell h, Sweep sw, con
         for (int u = 0; u < ILP; ++u) {
             if (ok[u]) {
                 const double2 o = rounded<V>(two_minus(acc[u], q[u]));
-                if (NT) st_nt(out + e[u], o); else st(out + e[u], o);
+                if (NT)
+                    st_nt(out + e[u], o);
+                else
+                    st(out + e[u], o);
                 s0 = cdot_acc(s0, l[u], o);
             }
         }
@@ -293,19 +323,19 @@ __global__ __launch_bounds__(kBlock) void k_moment_step_ilp(Ell h, Sweep sw, con
 template <typename V, bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_evolve_step(Ell h, Sweep sw, const V *p1,
                                                         const V *p0, V *out, V *acc,
-                                                        const V *add, double2 c0,
-                                                        double2 c) {
+                                                        const V *add, Coef c0, Coef c) {
     KPM_SWEEP_BEGIN(sw)
-    double2 xi = ld(p1 + e);
-    double2 hx = row_h(h, p1, i, v, sw.vshift, xi);
+    const double2 cm = coef(c, sg);
+    const double2 xi = ld(p1 + e);
+    const double2 hx = row_h(h, p1, i, v, sw.vshift, xi);
     double2 o, a;
     if (FIRST) {
         o = rounded<V>(hx);
-        a = cmla(cmul(c0, xi), c, o);
+        a = cmla(cmul(coef(c0, sg), xi), cm, o);
         if (add) a = cadd(ld_nt(add + e), a);
     } else {
         o = rounded<V>(two_minus(hx, ld_nt(p0 + e)));
-        a = cmla(ld_nt(acc + e), c, o);
+        a = cmla(ld_nt(acc + e), cm, o);
     }
     st_nt(out + e, o);
     st_nt(acc + e, a);
@@ -317,9 +347,10 @@ __global__ __launch_bounds__(kBlock) void k_evolve_x_step(Ell h, Sweep sw, const
                                                           const V *p0, V *pout,
                                                           const V *q1, const V *q0,
                                                           V *qout, V *accx, V *accu,
-                                                          double2 c0, double2 c) {
+                                                          Coef c0, Coef c) {
     KPM_SWEEP_BEGIN(sw)
-    double2 xi = ld(p1 + e);
+    const double2 cm = coef(c, sg);
+    const double2 xi = ld(p1 + e);
     double2 hp, dp;
     row_hd(h, p1, i, v, sw.vshift, xi, hp, dp);
     if (FIRST) {
@@ -327,50 +358,52 @@ __global__ __launch_bounds__(kBlock) void k_evolve_x_step(Ell h, Sweep sw, const
         dp = rounded<V>(dp);
         st_nt(pout + e, hp);
         st_nt(qout + e, dp);
-        st_nt(accx + e, cmul(c, dp));
-        st_nt(accu + e, cmla(cmul(c0, xi), c, hp));
+        st_nt(accx + e, cmul(cm, dp));
+        st_nt(accu + e, cmla(cmul(coef(c0, sg), xi), cm, hp));
     } else {
-        double2 qi = ld(q1 + e);
-        double2 hq = row_h(h, q1, i, v, sw.vshift, qi);
-        double2 pp = ld_nt(p0 + e);
-        double2 qq = q0 ? ld_nt(q0 + e) : make_double2(0.0, 0.0);
-        double2 po = rounded<V>(two_minus(hp, pp));
-        double2 qo = rounded<V>(two_minus(cadd(dp, hq), qq));
+        const double2 qi = ld(q1 + e);
+        const double2 hq = row_h(h, q1, i, v, sw.vshift, qi);
+        const double2 pp = ld_nt(p0 + e);
+        const double2 qq = q0 ? ld_nt(q0 + e) : make_double2(0.0, 0.0);
+        const double2 po = rounded<V>(two_minus(hp, pp));
+        const double2 qo = rounded<V>(two_minus(cadd(dp, hq), qq));
         st_nt(pout + e, po);
         st_nt(qout + e, qo);
-        st_nt(accx + e, cmla(ld_nt(accx + e), c, qo));
-        st_nt(accu + e, cmla(ld_nt(accu + e), c, po));
+        st_nt(accx + e, cmla(ld_nt(accx + e), cm, qo));
+        st_nt(accu + e, cmla(ld_nt(accu + e), cm, po));
     }
     KPM_SWEEP_END
 }
 
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_apply_d(Ell h, Sweep sw, const V *x, V *y,
-                                                    double2 alpha) {
+                                                    Coef alpha) {
     KPM_SWEEP_BEGIN(sw)
-    st(y + e, cmul(alpha, row_d(h, x, i, v, sw.vshift)));
+    st(y + e, cmul(coef(alpha, sg), row_d(h, x, i, v, sw.vshift)));
     KPM_SWEEP_END
 }
 
-// One block per (slot, vector): sums the nwg partials in a fixed order.
+// One block per (slot, vector, segment): sums the segment's group partials
+// in a fixed order.
 __global__ __launch_bounds__(kBlock) void k_reduce(const double2 *__restrict__ partial,
-                                                   int nwg, int vshift,
-                                                   double2 *__restrict__ dst,
+                                                   Sweep sw, double2 *__restrict__ dst,
                                                    int64_t stride_r, int64_t offset) {
     const int slot = blockIdx.x;
     const int r = blockIdx.y;
-    const int64_t nr = (int64_t)1 << vshift;
-    const double2 *p = partial + (int64_t)slot * nwg * nr + r;
-    double2 s = make_double2(0.0, 0.0);
-    for (int g = threadIdx.x; g < nwg; g += kBlock) s = cadd(s, p[(int64_t)g * nr]);
+    const int sgi = blockIdx.z;
+    const Seg s = sw.seg ? sw.seg[sgi] : sw.one;
+    const int64_t nr = (int64_t)1 << sw.vshift;
+    const double2 *p = partial + ((int64_t)slot * sw.nwg + s.g0) * nr + r;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int g = threadIdx.x; g < s.nwg; g += kBlock) acc = cadd(acc, p[(int64_t)g * nr]);
     __shared__ double2 red[kBlock];
-    red[threadIdx.x] = s;
+    red[threadIdx.x] = acc;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + w]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) dst[(int64_t)r * stride_r + offset + slot] = red[0];
+    if (threadIdx.x == 0) dst[((int64_t)sgi * nr + r) * stride_r + offset + slot] = red[0];
 }
 
 // One thread per (row, energy): Chebyshev series by the three-term recurrence.
@@ -388,7 +421,7 @@ __global__ __launch_bounds__(kBlock) void k_kpm_sum(const double *__restrict__ m
     double s = w[0] * c[0];
     if (nm > 1) s = fma(w[1] * x, c[1], s);
     for (int m = 2; m < nm; ++m) {
-        double tm = fma(2.0 * x, tm1, -tm2);
+        const double tm = fma(2.0 * x, tm1, -tm2);
         s = fma(w[m] * tm, c[m], s);
         tm2 = tm1;
         tm1 = tm;
@@ -397,51 +430,37 @@ __global__ __launch_bounds__(kBlock) void k_kpm_sum(const double *__restrict__ m
 }
 
 // ---------------------------------------------------------------- launchers
-Sweep make_sweep(int64_t rows, int vshift, int nwg, int ilp, int nt) {
-    Sweep sw;
-    sw.ilp = ilp;
-    sw.nt = nt;
-    sw.total = rows << vshift;
-    sw.nblk = (sw.total + kBlock - 1) / kBlock;
-    sw.nwg = nwg;
-    sw.per_xcd = (sw.nblk + kXcds - 1) / kXcds;
-    sw.vshift = vshift;
-    return sw;
+template <typename V, int ILP, bool NT>
+static void launch_step_shape(const Ell &h, const Sweep &sw, const V *p1, const V *p0, V *out,
+                              const V *phil, double2 *partial, int slot, hipStream_t s) {
+    hipLaunchKernelGGL((k_moment_step<V, ILP, NT>), dim3(sw.nwg), dim3(kBlock), 0, s, h, sw,
+                       p1, p0, out, phil, partial, slot);
 }
 
 template <typename V>
 void launch_moment_step(const Ell &h, const Sweep &sw, bool first, const V *p1,
                         const V *p0, V *out, const V *phil, double2 *partial, int slot,
                         hipStream_t s) {
-    if (first)
-        hipLaunchKernelGGL((k_moment_step<V, true>), dim3(sw.nwg), dim3(kBlock), 0, s, h, sw,
-                           p1, p0, out, phil, partial, slot);
-    else if (sw.nt) {
-        if (sw.ilp >= 4)
-            hipLaunchKernelGGL((k_moment_step_ilp<V, 4, true>), dim3(sw.nwg), dim3(kBlock), 0, s,
-                               h, sw, p1, p0, out, phil, partial, slot);
-        else if (sw.ilp == 2)
-            hipLaunchKernelGGL((k_moment_step_ilp<V, 2, true>), dim3(sw.nwg), dim3(kBlock), 0, s,
-                               h, sw, p1, p0, out, phil, partial, slot);
-        else
-            hipLaunchKernelGGL((k_moment_step_ilp<V, 1, true>), dim3(sw.nwg), dim3(kBlock), 0, s,
-                               h, sw, p1, p0, out, phil, partial, slot);
+    if (first) {
+        hipLaunchKernelGGL((k_moment_first<V>), dim3(sw.nwg), dim3(kBlock), 0, s, h, sw, p1,
+                           out, phil, partial, slot);
+        return;
+    }
+    const int ilp = sw.ilp >= 4 ? 4 : (sw.ilp == 2 ? 2 : 1);
+    if (sw.nt) {
+        if (ilp == 4) launch_step_shape<V, 4, true>(h, sw, p1, p0, out, phil, partial, slot, s);
+        else if (ilp == 2) launch_step_shape<V, 2, true>(h, sw, p1, p0, out, phil, partial, slot, s);
+        else launch_step_shape<V, 1, true>(h, sw, p1, p0, out, phil, partial, slot, s);
     } else {
-        if (sw.ilp >= 4)
-            hipLaunchKernelGGL((k_moment_step_ilp<V, 4, false>), dim3(sw.nwg), dim3(kBlock), 0, s,
-                               h, sw, p1, p0, out, phil, partial, slot);
-        else if (sw.ilp == 2)
-            hipLaunchKernelGGL((k_moment_step_ilp<V, 2, false>), dim3(sw.nwg), dim3(kBlock), 0, s,
-                               h, sw, p1, p0, out, phil, partial, slot);
-        else
-            hipLaunchKernelGGL((k_moment_step_ilp<V, 1, false>), dim3(sw.nwg), dim3(kBlock), 0, s,
-                               h, sw, p1, p0, out, phil, partial, slot);
+        if (ilp == 4) launch_step_shape<V, 4, false>(h, sw, p1, p0, out, phil, partial, slot, s);
+        else if (ilp == 2) launch_step_shape<V, 2, false>(h, sw, p1, p0, out, phil, partial, slot, s);
+        else launch_step_shape<V, 1, false>(h, sw, p1, p0, out, phil, partial, slot, s);
     }
 }
 
 template <typename V>
 void launch_evolve_step(const Ell &h, const Sweep &sw, bool first, const V *p1, const V *p0,
-                        V *out, V *acc, const V *add, double2 c0, double2 c, hipStream_t s) {
+                        V *out, V *acc, const V *add, Coef c0, Coef c, hipStream_t s) {
     if (first)
         hipLaunchKernelGGL((k_evolve_step<V, true>), dim3(sw.nwg), dim3(kBlock), 0, s, h, sw,
                            p1, p0, out, acc, add, c0, c);
@@ -453,7 +472,7 @@ void launch_evolve_step(const Ell &h, const Sweep &sw, bool first, const V *p1, 
 template <typename V>
 void launch_evolve_x_step(const Ell &h, const Sweep &sw, bool first, const V *p1,
                           const V *p0, V *pout, const V *q1, const V *q0, V *qout,
-                          V *accx, V *accu, double2 c0, double2 c, hipStream_t s) {
+                          V *accx, V *accu, Coef c0, Coef c, hipStream_t s) {
     if (first)
         hipLaunchKernelGGL((k_evolve_x_step<V, true>), dim3(sw.nwg), dim3(kBlock), 0, s, h,
                            sw, p1, p0, pout, q1, q0, qout, accx, accu, c0, c);
@@ -463,21 +482,21 @@ void launch_evolve_x_step(const Ell &h, const Sweep &sw, bool first, const V *p1
 }
 
 template <typename V>
-void launch_apply_d(const Ell &h, const Sweep &sw, const V *x, V *y, double2 alpha,
+void launch_apply_d(const Ell &h, const Sweep &sw, const V *x, V *y, Coef alpha,
                     hipStream_t s) {
     hipLaunchKernelGGL((k_apply_d<V>), dim3(sw.nwg), dim3(kBlock), 0, s, h, sw, x, y, alpha);
 }
 
-void launch_reduce(const double2 *partial, int nwg, int vshift, int slots, double2 *dst,
+void launch_reduce(const double2 *partial, const Sweep &sw, int slots, double2 *dst,
                    int64_t stride_r, int64_t offset, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3(slots, 1 << vshift), dim3(kBlock), 0, s, partial, nwg,
-                       vshift, dst, stride_r, offset);
+    hipLaunchKernelGGL(k_reduce, dim3(slots, 1 << sw.vshift, sw.nseg), dim3(kBlock), 0, s,
+                       partial, sw, dst, stride_r, offset);
 }
 
 void launch_kpm_sum(const double *mom, int rows, int nm, const double *w, const double *eps,
                     const double *pref, int ne, double *out, hipStream_t s) {
-    int64_t total = (int64_t)rows * ne;
-    int blocks = (int)((total + kBlock - 1) / kBlock);
+    const int64_t total = (int64_t)rows * ne;
+    const int blocks = (int)((total + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_kpm_sum, dim3(blocks), dim3(kBlock), 0, s, mom, rows, nm, w, eps,
                        pref, ne, out);
 }
@@ -487,12 +506,12 @@ void launch_kpm_sum(const double *mom, int rows, int nm, const double *w, const 
                                         const V *, V *, const V *, double2 *, int,          \
                                         hipStream_t);                                       \
     template void launch_evolve_step<V>(const Ell &, const Sweep &, bool, const V *,        \
-                                        const V *, V *, V *, const V *, double2, double2,   \
+                                        const V *, V *, V *, const V *, Coef, Coef,         \
                                         hipStream_t);                                       \
     template void launch_evolve_x_step<V>(const Ell &, const Sweep &, bool, const V *,      \
                                           const V *, V *, const V *, const V *, V *, V *,   \
-                                          V *, double2, double2, hipStream_t);              \
-    template void launch_apply_d<V>(const Ell &, const Sweep &, const V *, V *, double2,    \
+                                          V *, Coef, Coef, hipStream_t);                    \
+    template void launch_apply_d<V>(const Ell &, const Sweep &, const V *, V *, Coef,       \
                                     hipStream_t);
 
 KPM_INSTANTIATE(double2)

@@ -25,7 +25,8 @@ BOND_NM = 0.142
 
 # Every symbol declared in include/kpm.h.
 ABI_SYMBOLS = ("kpm_build_graphene", "kpm_system_create", "kpm_system_destroy",
-               "kpm_system_set_stream", "kpm_system_n_sites", "kpm_moments", "kpm_evolve",
+               "kpm_system_set_stream", "kpm_system_n_sites", "kpm_batch_create",
+               "kpm_system_n_samples", "kpm_system_offsets", "kpm_moments", "kpm_evolve",
                "kpm_evolve_x", "kpm_vac", "kpm_msd", "kpm_kpm_sum", "kpm_sigma_gk",
                "kpm_sigma_e1", "kpm_sigma_e2", "kpm_set_launch", "kpm_get_launch",
                "kpm_autotune", "kpm_set_timing", "kpm_get_stats", "kpm_reset_stats",
@@ -70,6 +71,8 @@ def lib():
         sig = {
             "kpm_build_graphene": [i64, i64, C.c_int, C.POINTER(C.c_uint8), C.POINTER(C.c_int32), dp],
             "kpm_system_create": [C.POINTER(_Desc), C.c_int, C.c_int, vp, C.POINTER(vp)],
+            "kpm_batch_create": [C.c_int, C.POINTER(_Desc), C.c_int, C.c_int, vp, C.POINTER(vp)],
+            "kpm_system_offsets": [vp, C.POINTER(C.c_int64)],
             "kpm_system_destroy": [vp],
             "kpm_system_set_stream": [vp, vp],
             "kpm_moments": [vp, C.c_int, vp, vp, C.c_int, dp],
@@ -95,6 +98,8 @@ def lib():
             f.restype = C.c_int
         L.kpm_system_n_sites.argtypes = [vp]
         L.kpm_system_n_sites.restype = C.c_int64
+        L.kpm_system_n_samples.argtypes = [vp]
+        L.kpm_system_n_samples.restype = C.c_int32
         L.kpm_last_error.restype = C.c_char_p
         L.kpm_version.restype = C.c_char_p
         _lib = L
@@ -164,44 +169,75 @@ def kpm_sigma_e2(rho_msd, dt_fs):
 
 
 # ------------------------------------------------------------------ system
+def _make_desc(nbr, e_scale, t_uniform=-2.7, hop=None, onsite=None, dx=None, active=None,
+               keep=None):
+    """A kpm_system_desc over numpy arrays (kept alive in `keep`)."""
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+    if nbr.ndim != 2:
+        raise ValueError("nbr must be [width][n_sites]")
+    keep.append(nbr)
+    width, n = nbr.shape
+
+    def arr(a, dt, shape):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=dt)
+        if a.shape != shape:
+            raise ValueError(f"array shape {a.shape} != {shape}")
+        keep.append(a)
+        return a
+
+    hop = arr(hop, np.float64, nbr.shape)
+    onsite = arr(onsite, np.float64, (n,))
+    dx = arr(dx, np.float64, nbr.shape)
+    active = arr(active, np.uint8, (n,))
+    return _Desc(n, width, nbr.ctypes.data_as(C.POINTER(C.c_int32)), _dp(hop), t_uniform,
+                 _dp(onsite), _dp(dx),
+                 None if active is None else active.ctypes.data_as(C.POINTER(C.c_uint8)),
+                 e_scale)
+
+
 class System:
-    """A Hamiltonian resident on one GPU (wraps kpm_system_create)."""
+    """A Hamiltonian resident on one GPU (wraps kpm_system_create), or a ragged
+    batch of samples (System.batch, wraps kpm_batch_create)."""
 
     def __init__(self, nbr, e_scale: float, t_uniform: float = -2.7, hop=None, onsite=None,
                  dx=None, active=None, precision: str = "fp64", device: int | None = None):
+        keep = []
+        d = _make_desc(nbr, e_scale, t_uniform, hop, onsite, dx, active, keep)
+        self._create([d], precision, device)
+
+    @classmethod
+    def batch(cls, samples, precision: str = "fp64", device: int | None = None):
+        """samples: list of dicts with the keyword arguments of System()."""
+        keep = []
+        descs = [_make_desc(keep=keep, **smp) for smp in samples]
+        obj = cls.__new__(cls)
+        obj._create(descs, precision, device)
+        return obj
+
+    def _create(self, descs, precision, device):
         import torch
-        nbr = np.ascontiguousarray(nbr, dtype=np.int32)
-        if nbr.ndim != 2:
-            raise ValueError("nbr must be [width][n_sites]")
-        self.width, self.n_sites = nbr.shape
-        keep = [nbr]
-
-        def arr(a, dt, shape):
-            if a is None:
-                return None
-            a = np.ascontiguousarray(a, dtype=dt)
-            if a.shape != shape:
-                raise ValueError(f"array shape {a.shape} != {shape}")
-            keep.append(a)
-            return a
-
-        hop = arr(hop, np.float64, nbr.shape)
-        onsite = arr(onsite, np.float64, (self.n_sites,))
-        dx = arr(dx, np.float64, nbr.shape)
-        active = arr(active, np.uint8, (self.n_sites,))
-        d = _Desc(self.n_sites, self.width, nbr.ctypes.data_as(C.POINTER(C.c_int32)), _dp(hop),
-                  t_uniform, _dp(onsite), _dp(dx),
-                  None if active is None else active.ctypes.data_as(C.POINTER(C.c_uint8)),
-                  e_scale)
         self.precision = precision
-        self.e_scale = float(e_scale)
+        self.e_scale = float(descs[0].e_scale)
         self.device = torch.cuda.current_device() if device is None else int(device)
         self._h = C.c_void_p()
         prec = KPM_FP64 if precision == "fp64" else KPM_FP32_STATES
+        arr = (_Desc * len(descs))(*descs)
         with torch.cuda.device(self.device):
-            _check(lib().kpm_system_create(C.byref(d), prec, self.device, _stream(),
-                                           C.byref(self._h)))
+            _check(lib().kpm_batch_create(len(descs), arr, prec, self.device, _stream(),
+                                          C.byref(self._h)))
         self.cdtype = torch.complex128 if precision == "fp64" else torch.complex64
+        self.n_sites = int(lib().kpm_system_n_sites(self._h))
+        self.n_samples = int(lib().kpm_system_n_samples(self._h))
+        off = np.zeros(self.n_samples + 1, dtype=np.int64)
+        _check(lib().kpm_system_offsets(self._h, off.ctypes.data_as(C.POINTER(C.c_int64))))
+        self.offsets = off
+        self.width = max(int(d.width) for d in descs)
+
+    def _shape(self, out):
+        """Drop the leading sample axis of a host output for a single system."""
+        return out[0] if self.n_samples == 1 else out
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
@@ -255,15 +291,16 @@ class System:
 
 
 def kpm_moments(sys: System, phi_l, phi_r, n_moments: int) -> np.ndarray:
-    """C_m = <phi_L|T_m(H~)|phi_R>, complex128 [n_vec, n_moments] (Eq. 46)."""
+    """C_m = <phi_L|T_m(H~)|phi_R>, complex128 [n_vec, n_moments] (Eq. 46);
+    [n_samples, n_vec, n_moments] for a batch."""
     pl, nv = sys._state(phi_l, "phi_l")
     pr, nv2 = sys._state(phi_r, "phi_r")
     if nv != nv2:
         raise ValueError("phi_l and phi_r differ in n_vec")
-    out = np.empty((nv, n_moments, 2))
+    out = np.empty((sys.n_samples, nv, n_moments, 2))
     sys._sync_stream()
     _check(lib().kpm_moments(sys.handle, nv, pl, pr, n_moments, _dp(out)))
-    return out[..., 0] + 1j * out[..., 1]
+    return sys._shape(out[..., 0] + 1j * out[..., 1])
 
 
 def kpm_evolve(sys: System, phi, dt_fs: float, sign: int, n_bessel: int):
@@ -291,19 +328,21 @@ def kpm_evolve_x(sys: System, phi, out_x, out_u, dt_fs: float, n_bessel: int):
 
 def _loop(fn, sys, phi, n_steps, dt_fs, n_bessel, n_moments):
     p, nv = sys._state(phi, "phi")
-    out = np.empty((nv, n_steps + 1, n_moments))
+    out = np.empty((sys.n_samples, nv, n_steps + 1, n_moments))
     sys._sync_stream()
     _check(fn(sys.handle, nv, p, n_steps, dt_fs, n_bessel, n_moments, _dp(out)))
-    return out
+    return sys._shape(out)
 
 
 def kpm_vac(sys: System, phi, n_steps: int, dt_fs: float, n_bessel: int, n_moments: int):
-    """VAC moments [n_vec, n_steps+1, n_moments] in nm^2/fs^2 (Alg. 2)."""
+    """VAC moments [n_vec, n_steps+1, n_moments] in nm^2/fs^2 (Alg. 2); leading
+    sample axis for a batch."""
     return _loop(lib().kpm_vac, sys, phi, n_steps, dt_fs, n_bessel, n_moments)
 
 
 def kpm_msd(sys: System, phi, n_steps: int, dt_fs: float, n_bessel: int, n_moments: int):
-    """MSD moments [n_vec, n_steps+1, n_moments] in nm^2 (Alg. 3)."""
+    """MSD moments [n_vec, n_steps+1, n_moments] in nm^2 (Alg. 3); leading
+    sample axis for a batch."""
     return _loop(lib().kpm_msd, sys, phi, n_steps, dt_fs, n_bessel, n_moments)
 
 
@@ -358,4 +397,29 @@ def graphene_system(nx: int, ny: int, geometry: str = "sheet", t_ev: float = -2.
     ly = 3.0 * ny * BOND_NM / 2.0
     s.area_nm2 = lx * ly
     s.width_nm = lx if geometry == "agnr" else ly
+    return s
+
+
+def graphene_batch(samples, precision: str = "fp64", device: int | None = None) -> System:
+    """Ragged batch of graphene samples (Sec. 2).  samples: list of dicts with
+    nx, ny, geometry, and optionally t_ev, onsite, active, e_scale."""
+    descs = []
+    meta = []
+    for smp in samples:
+        nx, ny, geo = smp["nx"], smp["ny"], smp.get("geometry", "sheet")
+        t_ev = smp.get("t_ev", -2.7)
+        onsite, active = smp.get("onsite"), smp.get("active")
+        nbr, dx = kpm_build_graphene(nx, ny, geo, active)
+        es = smp.get("e_scale")
+        if es is None:
+            wmax = 0.0 if onsite is None else float(np.max(np.abs(onsite)))
+            es = 1.01 * (3 * abs(t_ev) + wmax)
+        descs.append(dict(nbr=nbr, e_scale=es, t_uniform=t_ev, onsite=onsite, dx=dx,
+                          active=active))
+        lx = np.sqrt(3.0) * nx * BOND_NM / 2.0
+        ly = 3.0 * ny * BOND_NM / 2.0
+        meta.append(dict(nx=nx, ny=ny, geometry=geo, e_scale=es, area_nm2=lx * ly,
+                         width_nm=lx if geo == "agnr" else ly))
+    s = System.batch(descs, precision, device)
+    s.samples = meta
     return s
