@@ -32,9 +32,9 @@ sys.path.insert(0, ROOT)
 import kpm_inputs as ki  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_SITE_UPDATE_FP64 = 84      # 4 state accesses x 16 B + 12 B index + 8 B on-site
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "moment_step_fp64_paper_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1307_0288_amd", "csrc", "kpm_kernels.hip")
+HOST_SRC = os.path.join(ROOT, "paper_1307_0288_amd", "csrc", "kpm_host.cpp")
 
 
 def log(msg):
@@ -46,6 +46,11 @@ def kernel_sha() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+def host_sha() -> str:
+    with open(HOST_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
 def measured_traffic(step_rows: int):
     """HBM bytes per moment-step launch from committed rocprofv3 counters,
     or None when they are absent or were taken on another kernel version."""
@@ -54,7 +59,8 @@ def measured_traffic(step_rows: int):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != kernel_sha() or t.get("step_rows") != step_rows:
+    if t.get("kernel_sha") != kernel_sha() or t.get("host_sha") != host_sha() \
+            or t.get("step_rows") != step_rows:
         return None
     return t.get("bytes_per_launch")
 
@@ -83,9 +89,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-moments", type=int, default=800,
                     help="moments in the oracle's CPU-baseline sample (0 skips it)")
-    ap.add_argument("--workload", default="paper", choices=["paper", "batched"],
+    ap.add_argument("--workload", default="paper", choices=["paper", "batched", "ragged"],
                     help="paper: plain FP64, one vector (default); batched: 64 vectors, "
-                         "FP32 states vs FP64")
+                         "FP32 states vs FP64; ragged: 32 samples of 1e4..1e6 sites in one "
+                         "launch per step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -100,6 +107,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batched":
         return batched(args)
+    if args.workload == "ragged":
+        return ragged(args)
 
     p = ki.sheet_config("paper")
     n = p["nx"] * p["ny"]
@@ -135,7 +144,8 @@ def main():
 
     value = st["site_updates"] / elapsed / 1e9
     launch_ms = st["step_ms"] / max(st["step_launches"], 1)
-    bytes_launch = BYTES_PER_SITE_UPDATE_FP64 * st["step_rows"]
+    bytes_launch = st["step_bytes"]
+    bpu = bytes_launch / st["step_rows"]
     achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
     traffic = measured_traffic(st["step_rows"])
 
@@ -166,7 +176,7 @@ def main():
                                f"{'true' if launch['streaming'] else 'false'}>", "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "bytes_per_site_update": BYTES_PER_SITE_UPDATE_FP64,
+                     "bytes_per_site_update": round(bpu, 3),
                      "avg_launch_us": round(launch_ms * 1e3, 3),
                      "launches": st["step_launches"], "launch_shape": launch},
         "cpu_baseline": cpu,
@@ -216,7 +226,8 @@ def batched(args):
         ups = (nm - 1) * n * r
         launch_ms = st["step_ms"] / max(st["step_launches"], 1)
         res[prec] = dict(seconds=min(times), gsu=ups / min(times) / 1e9,
-                         launch_us=launch_ms * 1e3, launch=res_launch)
+                         launch_us=launch_ms * 1e3, launch=res_launch,
+                         bpu=st["step_bytes"] / st["step_rows"])
         log(f"{prec} sigma runs (VAC + MSD, 2 steps)")
         vac = kp.kpm_vac(sysg, phi, 2, dt, nb, nm).mean(axis=0)
         msd = kp.kpm_msd(sysg, phi, 2, dt, nb, nm).mean(axis=0)
@@ -228,7 +239,7 @@ def batched(args):
         torch.cuda.empty_cache()
     err_gk = float(np.max(np.abs(sig["fp32"][0] - sig["fp64"][0])) / np.max(np.abs(sig["fp64"][0])))
     err_e1 = float(np.max(np.abs(sig["fp32"][1] - sig["fp64"][1])) / np.max(np.abs(sig["fp64"][1])))
-    bpu = {"fp64": 64 + 20 / r, "fp32": 32 + 20 / r}
+    bpu = {k: v["bpu"] for k, v in res.items()}
     out = {
         "metric": "Gsite-updates/s (batched Chebyshev moments, 64 vectors, FP32 states)",
         "value": round(res["fp32"]["gsu"], 3), "unit": "Gsite-updates/s", "n_gpus": 1,
@@ -250,6 +261,67 @@ def batched(args):
                             "frac": round(bpu[prec] * n * r / (res[prec]["launch_us"] * 1e-6) / 1e9
                                           / HBM_PEAK_GBS, 4)}
                      for prec in ("fp64", "fp32")},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def ragged(args):
+    """32 independent samples (AGNR, ZGNR, sheets of 1e4..1e6 sites, Anderson W in
+    {0.5, 1, 2} eV), 8 random vectors each, 1000 moments per sample, all samples
+    advanced by one launch per Chebyshev step; direct launches vs hipGraph replay,
+    FP64 and FP32 states."""
+    import torch
+    import paper_1307_0288_amd as kp
+    cfg = ki.sheet_config("ragged")
+    specs = ki.ragged_specs(cfg["count"], cfg["seed"], cfg["n_min"], cfg["n_max"],
+                            cfg["w_min"], cfg["w_max"])
+    r, nm = cfg["n_vec"], cfg["n_moments"]
+    samples, phis = [], []
+    for s, sp in enumerate(specs):
+        n = sp["nx"] * sp["ny"]
+        ons = ki.anderson_onsite(n, sp["w"], 1000 + s)
+        samples.append(dict(nx=sp["nx"], ny=sp["ny"], geometry=sp["geometry"], onsite=ons,
+                            e_scale=1.01 * (3 * 2.7 + sp["w"] / 2)))
+        phis.append(ki.random_phase(n, r, 3000 + 100 * s))
+    phi_h = np.concatenate(phis)
+    total = phi_h.shape[0]
+    log(f"ragged inputs: {len(specs)} samples, {total} sites, {r} vectors")
+    res = {}
+    for prec in ("fp64", "fp32"):
+        sysg = kp.graphene_batch(samples, prec)
+        phi = sysg.upload(phi_h)
+        launch = kp.kpm_autotune(sysg, phi, 20)
+        log(f"{prec} autotuned launch shape: {launch}")
+        for graphs in (False, True):
+            kp.kpm_set_graphs(sysg, graphs)
+            kp.kpm_moments(sysg, phi, phi, nm)                # warm-up (and capture)
+            torch.cuda.synchronize()
+            times = []
+            for k in range(max(args.steps, 1)):
+                t0 = time.perf_counter()
+                kp.kpm_moments(sysg, phi, phi, nm)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            ups = (nm - 1) * total * r
+            res[f"{prec}_{'graph' if graphs else 'direct'}"] = dict(
+                seconds=min(times), gsu=ups / min(times) / 1e9, launch=launch)
+            log(f"{prec} graphs={graphs}: {min(times) * 1e3:.1f} ms, "
+                f"{ups / min(times) / 1e9:.1f} Gsite-updates/s")
+        sysg.close()
+        del phi
+        torch.cuda.empty_cache()
+    best = res["fp64_graph"]
+    out = {
+        "metric": "Gsite-updates/s (ragged batch of 32 samples, Chebyshev moments, FP64)",
+        "value": round(best["gsu"], 3), "unit": "Gsite-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": round(best["seconds"] * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "32 samples: AGNR/ZGNR/sheets of 1e4..1e6 sites, widths 20-400 "
+                               "cells, W in {0.5,1,2} eV, 8 vectors each, 1000 moments",
+                   "n_sites": int(total), "n_vec": r, "samples": len(specs)},
+        "runs": {k: {"ms": round(v["seconds"] * 1e3, 3), "gsu": round(v["gsu"], 3),
+                     "launch_shape": v["launch"]} for k, v in res.items()},
     }
     print(json.dumps(out), flush=True)
 

@@ -87,6 +87,11 @@ typedef struct kpm_system kpm_system;
  *   e_scale    E_s in eV (see Conventions).
  * Validation: indices in range, H real symmetric (each bond listed from both
  * ends with equal hopping), dx antisymmetric, e_scale >= Gershgorin bound.
+ * Device form (chosen at creation, results agree to rounding): when the rows
+ * repeat at most 256 distinct neighbour-offset patterns (any lattice does),
+ * neighbours are stored as one pattern byte per row instead of the list, and
+ * when every on-site energy is exactly a float it is stored as a float.  The
+ * environment variable KPM_COMPACT=0 keeps the explicit forms.
  */
 typedef struct {
     int64_t n_sites;
@@ -249,15 +254,31 @@ kpm_status kpm_autotune(kpm_system *sys, int n_vec, const void *phi, int reps,
                         kpm_launch *best);
 
 /*
+ * hipGraph replay of the moment sets.  When enabled, the launch sequence of a
+ * moment set (first step, recursion steps, partial-sum reductions) is
+ * captured once per combination of buffers, sizes and launch shape and
+ * replayed on the system's stream; results are bit-identical to direct
+ * launches.  Graphs are dropped when scratch is reallocated or graphs are
+ * disabled.  Capture runs on an internal stream, so it also works when the
+ * system's stream is the null stream.
+ */
+kpm_status kpm_set_graphs(kpm_system *sys, int enable);
+
+/*
  * Timing of the hot recursion kernel.  When enabled, the library brackets
  * every uninterrupted run of Chebyshev moment steps with HIP events on the
- * system's stream and accumulates their elapsed time and launch count.
+ * system's stream and accumulates their elapsed time and launch count (with
+ * graphs, the events bracket each replayed moment set, whose first step and
+ * reductions then count towards the time).
  */
 typedef struct {
     double step_ms;           /* summed event time of moment-step runs      */
     int64_t step_launches;    /* moment-step kernel launches in those runs  */
     int64_t step_rows;        /* rows x vectors per launch (last run)       */
     int64_t site_updates;     /* all recursion site-updates issued          */
+    int64_t step_bytes;       /* algorithmic bytes per moment-step launch:
+                                 4 state accesses per row and vector plus
+                                 the row structure once per row (last run) */
 } kpm_stats;
 
 kpm_status kpm_set_timing(kpm_system *sys, int enable);

@@ -43,10 +43,14 @@ def uniform(seed: int, count: int, offset: int = 0) -> np.ndarray:
 
 
 def anderson_onsite(n_sites: int, w_ev: float, seed: int) -> np.ndarray:
-    """On-site energies uniform in [-W/2, W/2) eV, one per site index (float64)."""
+    """On-site energies uniform in [-W/2, W/2) eV, one per site index.
+
+    Returned as float64 holding values rounded to the nearest float32, so
+    that they are exactly representable in single precision as well.
+    """
     if w_ev == 0.0:
         return np.zeros(n_sites, dtype=np.float64)
-    return w_ev * (uniform(seed, n_sites) - 0.5)
+    return (w_ev * (uniform(seed, n_sites) - 0.5)).astype(np.float32).astype(np.float64)
 
 
 def vacancy_mask(n_sites: int, fraction: float, seed: int) -> np.ndarray:

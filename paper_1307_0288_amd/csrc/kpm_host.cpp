@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -195,13 +196,17 @@ struct kpm_system {
     int nseg = 1;
     std::vector<int64_t> off;
     std::vector<double> es;
+    std::vector<double> seg_t;   // uniform hopping / E_s of each sample
     // device Hamiltonian
-    int32_t *d_nbr = nullptr;
+    int32_t *d_nbr = nullptr;   // explicit neighbour list, or
+    uint8_t *d_pid = nullptr;   // compact form: pattern id per row
+    int32_t *d_pat = nullptr;   //   and offset patterns [npat][kMaxWidth]
+    int npat = 0;
     double *d_hop = nullptr;
-    double *d_tsc = nullptr;
     double *d_xw = nullptr;
-    double *d_ons = nullptr;
-    double t_scaled = 0;
+    double *d_ons = nullptr;    // H_nn / E_s, or
+    float *d_onsf = nullptr;    // H_nn (eV) when every value is a float
+    bool uniform_hop = true;
     double2 *d_alpha = nullptr;  // [nseg] velocity prefactor -i E_s / hbar (batches)
     // segment tables per (vshift, requested groups); batches only
     struct SegTab {
@@ -230,6 +235,43 @@ struct kpm_system {
     std::vector<hipEvent_t> events;
     size_t events_used = 0;
     kpm_stats stats{};
+    // captured moment sets (kpm_set_graphs): one executable graph per set of
+    // buffers, sizes and launch shape; dropped whenever scratch is reallocated
+    bool graphs = false;
+    hipStream_t cap = nullptr;
+    struct GraphKey {
+        const void *phil, *phir, *a, *b, *partial, *dmom;
+        int nm, vshift, groups, ilp, streaming;
+        int64_t stride_r, offset;
+        bool operator==(const GraphKey &o) const {
+            return phil == o.phil && phir == o.phir && a == o.a && b == o.b &&
+                   partial == o.partial && dmom == o.dmom && nm == o.nm && vshift == o.vshift &&
+                   groups == o.groups && ilp == o.ilp && streaming == o.streaming &&
+                   stride_r == o.stride_r && offset == o.offset;
+        }
+    };
+    struct GraphEntry {
+        GraphKey key;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graph_cache;
+
+    hipGraphExec_t find_graph(const GraphKey &k) const {
+        for (const GraphEntry &g : graph_cache)
+            if (g.key == k) return g.exec;
+        return nullptr;
+    }
+
+    void drop_graphs() {
+        for (GraphEntry &g : graph_cache) (void)hipGraphExecDestroy(g.exec);
+        graph_cache.clear();
+    }
+
+    kpm_status ensure_capture_stream() {
+        // default priority, non-blocking: the library never changes priorities
+        if (!cap) KPM_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        return KPM_OK;
+    }
 
     size_t elem_bytes() const { return prec == KPM_FP64 ? 16 : 8; }
     size_t state_bytes(int vshift) const { return (size_t)n * ((size_t)1 << vshift) * elem_bytes(); }
@@ -237,14 +279,24 @@ struct kpm_system {
     kpm::Ell ell() const {
         kpm::Ell h;
         h.nbr = d_nbr;
+        h.pid = d_pid;
+        h.pat = d_pat;
+        h.npat = npat;
         h.hop = d_hop;
-        h.tsc = d_tsc;
         h.xw = d_xw;
         h.ons = d_ons;
-        h.t = t_scaled;
+        h.onsf = d_onsf;
         h.n = n;
         h.w = w;
         return h;
+    }
+
+    // Algorithmic bytes of one moment-step launch: four state accesses per
+    // element (read phi_1, phi_0, phi_L, write phi_0) and the row structure
+    // once per row (neighbours, on-site term, per-slot hopping).
+    int64_t step_bytes(int vshift) const {
+        const int64_t per_row = (d_pid ? 1 : 4 * w) + (d_onsf ? 4 : 8) + (d_hop ? 8 * w : 0);
+        return n * (((int64_t)4 * elem_bytes()) << vshift) + n * per_row;
     }
 
     // The sweep of the moment step (and every other kernel) for n_vec =
@@ -264,7 +316,7 @@ struct kpm_system {
             sw.nseg = 1;
             sw.seg = nullptr;
             sw.wg_seg = nullptr;
-            sw.one = kpm::Seg{0, sw.total, 0, sw.nwg};
+            sw.one = kpm::Seg{0, sw.total, 0, sw.nwg, seg_t[0], 1.0 / es[0]};
             *out = sw;
             return KPM_OK;
         }
@@ -287,7 +339,7 @@ struct kpm_system {
             int64_t u = (int64_t)std::llround((double)units * rows / (double)n);
             u = std::max<int64_t>(1, std::min(u, (nblk + kpm::kXcds - 1) / kpm::kXcds));
             seg[s] = kpm::Seg{off[s] << vshift, off[s + 1] << vshift, (int32_t)g0,
-                              (int32_t)(u * kpm::kXcds)};
+                              (int32_t)(u * kpm::kXcds), seg_t[s], 1.0 / es[s]};
             g0 += u * kpm::kXcds;
         }
         if (g0 > (1 << 30)) return fail(KPM_ERR_INVALID, "batch needs too many work-groups");
@@ -340,6 +392,8 @@ struct kpm_system {
     kpm_status ensure_vecs(int count, int vshift) {
         const size_t bytes = state_bytes(vshift);
         if (bytes > vec_bytes) {
+            drop_graphs();
+            KPM_HIP(hipStreamSynchronize(stream));
             for (void *p : vecs) (void)hipFree(p);
             vecs.clear();
             vec_bytes = bytes;
@@ -356,6 +410,8 @@ struct kpm_system {
     kpm_status ensure_partial(int slots, int nwg, int n_vec) {
         const size_t need = (size_t)slots * nwg * n_vec;
         if (need > partial_elems) {
+            drop_graphs();
+            KPM_HIP(hipStreamSynchronize(stream));
             if (partial) (void)hipFree(partial);
             partial = nullptr;
             KPM_HIP(hipMalloc(&partial, need * sizeof(double2)));
@@ -366,6 +422,8 @@ struct kpm_system {
 
     kpm_status ensure_dmom(size_t elems) {
         if (elems > dmom_elems) {
+            drop_graphs();
+            KPM_HIP(hipStreamSynchronize(stream));
             if (dmom) (void)hipFree(dmom);
             dmom = nullptr;
             KPM_HIP(hipMalloc(&dmom, elems * sizeof(double2)));
@@ -400,6 +458,8 @@ struct kpm_system {
 
     ~kpm_system() {
         DeviceGuard g(device);
+        drop_graphs();
+        if (cap) (void)hipStreamDestroy(cap);
         for (void *p : vecs) (void)hipFree(p);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         for (SegTab &t : segtabs) {
@@ -410,8 +470,10 @@ struct kpm_system {
         if (partial) (void)hipFree(partial);
         if (dmom) (void)hipFree(dmom);
         if (d_nbr) (void)hipFree(d_nbr);
+        if (d_pid) (void)hipFree(d_pid);
+        if (d_pat) (void)hipFree(d_pat);
+        if (d_onsf) (void)hipFree(d_onsf);
         if (d_hop) (void)hipFree(d_hop);
-        if (d_tsc) (void)hipFree(d_tsc);
         if (d_xw) (void)hipFree(d_xw);
         if (d_ons) (void)hipFree(d_ons);
         if (d_alpha) (void)hipFree(d_alpha);
@@ -425,22 +487,16 @@ kpm::Coef step_coef(const std::vector<double2> &host, const double2 *tab, int np
 }
 
 // ---------------------------------------------------------------- drivers
-// Chebyshev moments of Alg. 5 for n_vec vector pairs (every sample), reduced
-// into sys->dmom[(s * R + r) * stride_r + offset + m] (complex).
+// Launches of one moment set (Alg. 5) on stream s: the first step, the
+// recursion steps and the ring reductions into sys->dmom.  `events` brackets
+// each uninterrupted run of recursion steps for kpm_set_timing.
 template <typename V>
-kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir, int nm,
-                       V *a_buf, V *b_buf, int64_t stride_r, int64_t offset) {
+kpm_status enqueue_moments(kpm_system *sys, const kpm::Sweep &sw, int ring, hipStream_t s,
+                           bool events, const V *phil, const V *phir, int nm, V *a_buf,
+                           V *b_buf, int64_t stride_r, int64_t offset) {
     const kpm::Ell h = sys->ell();
-    kpm::Sweep sw;
-    KPM_TRY(sys->sweep(vshift, &sw));
-    // Group partials live in a ring of kPartialRing moment slots that is
-    // reduced into sys->dmom whenever it fills, bounding its size at any N_m.
-    const int ring = std::min(std::max(nm, 2), kPartialRing);
-    KPM_TRY(sys->ensure_partial(ring, sw.nwg, 1 << vshift));
-    hipStream_t s = sys->stream;
     // C_0 and C_1 (phi_0 = phi_R, phi_1 = H~ phi_0)
     kpm::launch_moment_step<V>(h, sw, true, phir, nullptr, a_buf, phil, sys->partial, 0, s);
-    sys->stats.site_updates += sw.total;
     // phi_m = 2 H~ phi_{m-1} - phi_{m-2}, in place after the first step
     const V *p0 = phir;
     V *p1 = a_buf;
@@ -449,7 +505,7 @@ kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir
         const int m0 = std::max(c0, 2);
         if (m0 < c1) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (sys->timing) {
+            if (events) {
                 KPM_TRY(sys->event_pair(&e0, &e1));
                 KPM_HIP(hipEventRecord(e0, s));
             }
@@ -459,14 +515,65 @@ kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir
                 p0 = p1;
                 p1 = out;
             }
-            if (sys->timing) {
+            if (events) {
                 KPM_HIP(hipEventRecord(e1, s));
                 sys->stats.step_launches += c1 - m0;
-                sys->stats.step_rows = sw.total;
             }
-            sys->stats.site_updates += (int64_t)(c1 - m0) * sw.total;
         }
         kpm::launch_reduce(sys->partial, sw, c1 - c0, sys->dmom, stride_r, offset + c0, s);
+    }
+    return KPM_OK;
+}
+
+// Chebyshev moments of Alg. 5 for n_vec vector pairs (every sample), reduced
+// into sys->dmom[(s * R + r) * stride_r + offset + m] (complex).  With graphs
+// enabled the launch sequence is captured once per set of buffers and
+// replayed.
+template <typename V>
+kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir, int nm,
+                       V *a_buf, V *b_buf, int64_t stride_r, int64_t offset) {
+    kpm::Sweep sw;
+    KPM_TRY(sys->sweep(vshift, &sw));
+    // Group partials live in a ring of kPartialRing moment slots that is
+    // reduced into sys->dmom whenever it fills, bounding its size at any N_m.
+    const int ring = std::min(std::max(nm, 2), kPartialRing);
+    KPM_TRY(sys->ensure_partial(ring, sw.nwg, 1 << vshift));
+    sys->stats.step_rows = sw.total;
+    sys->stats.step_bytes = sys->step_bytes(vshift);
+    sys->stats.site_updates += (int64_t)(nm > 1 ? nm - 1 : 1) * sw.total;
+    if (!sys->graphs)
+        return enqueue_moments<V>(sys, sw, ring, sys->stream, sys->timing, phil, phir, nm,
+                                  a_buf, b_buf, stride_r, offset);
+    kpm_system::GraphKey key{phil, phir, a_buf, b_buf, sys->partial, sys->dmom, nm, vshift,
+                             sys->launch[vshift].groups_per_cu, sys->launch[vshift].ilp,
+                             sys->launch[vshift].streaming, stride_r, offset};
+    hipGraphExec_t exec = sys->find_graph(key);
+    if (!exec) {
+        KPM_TRY(sys->ensure_capture_stream());
+        KPM_HIP(hipStreamBeginCapture(sys->cap, hipStreamCaptureModeThreadLocal));
+        kpm_status st = enqueue_moments<V>(sys, sw, ring, sys->cap, false, phil, phir, nm, a_buf,
+                                           b_buf, stride_r, offset);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(sys->cap, &graph);
+        if (st != KPM_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (ec != hipSuccess) return fail(KPM_ERR_DEVICE, "graph capture: %s", hipGetErrorString(ec));
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return fail(KPM_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(ei));
+        sys->graph_cache.push_back({key, exec});
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (sys->timing) {
+        KPM_TRY(sys->event_pair(&e0, &e1));
+        KPM_HIP(hipEventRecord(e0, sys->stream));
+    }
+    KPM_HIP(hipGraphLaunch(exec, sys->stream));
+    if (sys->timing) {
+        KPM_HIP(hipEventRecord(e1, sys->stream));
+        sys->stats.step_launches += std::max(nm - 2, 0);
     }
     return KPM_OK;
 }
@@ -753,18 +860,21 @@ kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int devi
     if (const char *env = std::getenv("KPM_STREAMING"))
         for (auto &l : sys->launch) l.streaming = atoi(env) != 0;
 
-    // Concatenate, shift indices by the sample offset, fold 1/E_s of each
-    // sample into its rows.
+    // Concatenate and shift indices by the sample offset; per-slot weights
+    // carry 1/E_s of their sample.
     std::vector<int32_t> nbr((size_t)w * n, -1);
     std::vector<double> ons(n), hop(any_hop ? (size_t)w * n : 0), xw(all_dx ? (size_t)w * n : 0);
-    std::vector<double> tsc(nseg > 1 && !any_hop ? n : 0);
+    sys->seg_t.resize(nseg);
+    bool ons_float = std::getenv("KPM_COMPACT") == nullptr || atoi(std::getenv("KPM_COMPACT")) != 0;
+    const bool try_compact = ons_float;
     for (int s = 0; s < nseg; ++s) {
         const Packed &p = parts[s];
         const int64_t o = sys->off[s];
         const double inv = 1.0 / p.e_scale;
+        sys->seg_t[s] = p.t * inv;
         for (int64_t r = 0; r < p.n; ++r) {
-            ons[o + r] = p.ons[r] * inv;
-            if (!tsc.empty()) tsc[o + r] = p.t * inv;
+            ons[o + r] = p.ons[r];
+            ons_float = ons_float && (double)(float)p.ons[r] == p.ons[r];
             for (int k = 0; k < p.w; ++k) {
                 const size_t q = (size_t)k * p.n + r, qq = (size_t)k * n + o + r;
                 const int32_t m = p.nbr[q];
@@ -775,7 +885,44 @@ kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int devi
             }
         }
     }
-    sys->t_scaled = parts[0].t / parts[0].e_scale;
+    sys->uniform_hop = !any_hop;
+    // Compact neighbour form: one byte per row selects one of at most
+    // kMaxPatterns offset patterns (a lattice has only a few).
+    std::vector<uint8_t> pid;
+    std::vector<int32_t> pat;
+    if (try_compact) {
+        std::vector<std::array<int32_t, kpm::kMaxWidth>> pats;
+        pid.resize(n);
+        std::array<int32_t, kpm::kMaxWidth> cur{};
+        int last = -1;
+        for (int64_t r = 0; r < n && !pid.empty(); ++r) {
+            for (int k = 0; k < kpm::kMaxWidth; ++k) {
+                const int32_t m = k < w ? nbr[(size_t)k * n + r] : -1;
+                cur[k] = m < 0 ? kpm::kEmptySlot : (int32_t)(m - r);
+            }
+            int id = (last >= 0 && pats[last] == cur) ? last : -1;
+            for (int q = 0; id < 0 && q < (int)pats.size(); ++q)
+                if (pats[q] == cur) id = q;
+            if (id < 0) {
+                if ((int)pats.size() == kpm::kMaxPatterns) {
+                    pid.clear();
+                    break;
+                }
+                pats.push_back(cur);
+                id = (int)pats.size() - 1;
+            }
+            pid[r] = (uint8_t)id;
+            last = id;
+        }
+        if (!pid.empty()) {
+            for (const auto &a : pats) pat.insert(pat.end(), a.begin(), a.end());
+            sys->npat = (int)pats.size();
+        }
+    }
+    if (!ons_float) {
+        for (int s = 0; s < nseg; ++s)
+            for (int64_t r = sys->off[s]; r < sys->off[s + 1]; ++r) ons[r] /= parts[s].e_scale;
+    }
 
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
@@ -790,10 +937,20 @@ kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int devi
         if (e != hipSuccess) return fail(KPM_ERR_DEVICE, "upload: %s", hipGetErrorString(e));
         return KPM_OK;
     };
-    kpm_status st = upload((void **)&sys->d_nbr, nbr.data(), nbr.size() * sizeof(int32_t));
-    if (st == KPM_OK) st = upload((void **)&sys->d_ons, ons.data(), ons.size() * sizeof(double));
+    kpm_status st = KPM_OK;
+    if (!pid.empty()) {
+        st = upload((void **)&sys->d_pid, pid.data(), pid.size());
+        if (st == KPM_OK) st = upload((void **)&sys->d_pat, pat.data(), pat.size() * sizeof(int32_t));
+    } else {
+        st = upload((void **)&sys->d_nbr, nbr.data(), nbr.size() * sizeof(int32_t));
+    }
+    if (st == KPM_OK && ons_float) {
+        std::vector<float> of(ons.begin(), ons.end());
+        st = upload((void **)&sys->d_onsf, of.data(), of.size() * sizeof(float));
+    } else if (st == KPM_OK) {
+        st = upload((void **)&sys->d_ons, ons.data(), ons.size() * sizeof(double));
+    }
     if (st == KPM_OK && any_hop) st = upload((void **)&sys->d_hop, hop.data(), hop.size() * sizeof(double));
-    if (st == KPM_OK && !tsc.empty()) st = upload((void **)&sys->d_tsc, tsc.data(), tsc.size() * sizeof(double));
     if (st == KPM_OK && all_dx) st = upload((void **)&sys->d_xw, xw.data(), xw.size() * sizeof(double));
     if (st == KPM_OK && nseg > 1) {
         std::vector<double2> al(nseg);
@@ -1087,6 +1244,14 @@ kpm_status kpm_autotune(kpm_system *sys, int n_vec, const void *phi, int reps, k
     DeviceGuard g(sys->device);
     return sys->prec == KPM_FP64 ? autotune_impl<double2>(sys, vs, (const double2 *)phi, reps, best)
                                  : autotune_impl<float2>(sys, vs, (const float2 *)phi, reps, best);
+}
+
+kpm_status kpm_set_graphs(kpm_system *sys, int enable) {
+    if (!sys) return fail(KPM_ERR_INVALID, "null system");
+    DeviceGuard g(sys->device);
+    if (!enable) sys->drop_graphs();
+    sys->graphs = enable != 0;
+    return KPM_OK;
 }
 
 kpm_status kpm_set_timing(kpm_system *sys, int enable) {

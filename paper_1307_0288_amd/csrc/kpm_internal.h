@@ -11,25 +11,37 @@ constexpr int kBlock = 256;       // work-group size of the sweep kernels
 constexpr int kWave = 64;         // CDNA wavefront
 constexpr int kXcds = 8;          // MI355X: 8 accelerator complex dies
 constexpr int kMaxWidth = 4;      // neighbour-list slots per row
+constexpr int kMaxPatterns = 256; // distinct neighbour-offset patterns of the compact form
+constexpr int32_t kEmptySlot = INT32_MIN;   // pattern entry of an empty slot
 
 // Scaled sparse Hamiltonian on the device (neighbour-list layout of Alg. 8).
+// Neighbours come either from the explicit list `nbr` or, in the compact
+// form, from a one-byte pattern id per row: slot k of row i holds row
+// i + pat[pid[i]][k] (kEmptySlot = no bond).  Lattices repeat a handful of
+// offset patterns, so this replaces 4 bytes per slot with 1 byte per row.
+// On-site terms come from `ons` (H_nn / E_s) or, when every H_nn is exactly
+// a float, from `onsf` (H_nn in eV) times the sample's 1/E_s.
 struct Ell {
-    const int32_t *nbr;   // [w][n] neighbour row, -1 = empty slot
-    const double *hop;    // [w][n] H_nm / E_s, or nullptr
-    const double *tsc;    // [n] hopping / E_s of the row's sample, or nullptr
+    const int32_t *nbr;   // [w][n] neighbour row, -1 = empty slot (or nullptr)
+    const uint8_t *pid;   // [n] pattern id (compact form) or nullptr
+    const int32_t *pat;   // [npat][kMaxWidth] row offsets (compact form)
+    int npat;
+    const double *hop;    // [w][n] H_nm / E_s, or nullptr (uniform hopping)
     const double *xw;     // [w][n] (X_n - X_m) H_nm / E_s, or nullptr
-    const double *ons;    // [n] H_nn / E_s
-    double t;             // uniform H_nm / E_s when hop and tsc are nullptr
+    const double *ons;    // [n] H_nn / E_s, or nullptr
+    const float *onsf;    // [n] H_nn in eV, or nullptr
     int64_t n;            // rows
     int w;                // slots per row
 };
 
 // A segment is one independent sample of a batch: a contiguous element range
-// [e0, e1) and the contiguous work-groups [g0, g0 + nwg) that sweep it
-// (g0 and nwg multiples of 8).  A plain system is a single segment.
+// [e0, e1), the contiguous work-groups [g0, g0 + nwg) that sweep it (g0 and
+// nwg multiples of 8), its uniform hopping t / E_s and its 1 / E_s.  A plain
+// system is a single segment.
 struct Seg {
     int64_t e0, e1;
     int32_t g0, nwg;
+    double t, inv_es;
 };
 
 // Persistent, XCD-aware sweep.  Work-groups are dispatched round-robin over

@@ -92,23 +92,59 @@ __device__ __forceinline__ double2 coef(const Coef &c, int sg) {
     return c.tab ? c.tab[sg * c.stride + c.idx] : c.val;
 }
 
-// Uniform hopping of row i (per-slot values are read separately).
-__device__ __forceinline__ double row_t(const Ell &h, int64_t i) {
-    return h.tsc ? h.tsc[i] : h.t;
+// The element blocks this work-group visits: blocks b0 + loc, b0 + loc +
+// nloc, ... below b1 of its segment, elements e0 + b * kBlock + tid below e1;
+// t and inv_es are the segment's uniform hopping / E_s and 1 / E_s.
+struct Walk {
+    int sg;
+    int loc, nloc;
+    int64_t b0, b1, e0, e1;
+    double t, inv_es;
+};
+
+// Neighbour-offset patterns of the compact form, staged in LDS by every
+// work-group (at most kMaxPatterns x kMaxWidth words).
+#define KPM_PATTERNS(h)                                                          \
+    __shared__ int32_t lpat[kMaxPatterns * kMaxWidth];                           \
+    if ((h).pid) {                                                               \
+        for (int j_ = threadIdx.x; j_ < (h).npat * kMaxWidth; j_ += kBlock)      \
+            lpat[j_] = (h).pat[j_];                                              \
+        __syncthreads();                                                         \
+    }
+
+// Pattern id of row i (0 for the explicit form).
+__device__ __forceinline__ int row_pid(const Ell &h, int64_t i) {
+    return h.pid ? (int)h.pid[i] : 0;
+}
+
+// Row held by slot k of row i, or -1.
+__device__ __forceinline__ int32_t slot_row(const Ell &h, const int32_t *lpat, int pid,
+                                            int64_t i, int k) {
+    if (h.pid) {
+        const int32_t d = lpat[pid * kMaxWidth + k];
+        return d == kEmptySlot ? -1 : (int32_t)(i + d);
+    }
+    return h.nbr[k * h.n + i];
+}
+
+// H_ii / E_s of row i.
+__device__ __forceinline__ double row_ons(const Ell &h, const Walk &wk, int64_t i) {
+    return h.onsf ? (double)h.onsf[i] * wk.inv_es : h.ons[i];
 }
 
 // Sum of H~_im x_m over the filled slots of row i, plus the diagonal term.
 template <typename V>
-__device__ __forceinline__ double2 row_h(const Ell &h, const V *x, int64_t i, int64_t v,
-                                         int vshift, double2 xi) {
-    const double o = h.ons[i];
-    const double tr = row_t(h, i);
+__device__ __forceinline__ double2 row_h(const Ell &h, const Walk &wk, const int32_t *lpat,
+                                         const V *x, int64_t i, int64_t v, int vshift,
+                                         double2 xi) {
+    const double o = row_ons(h, wk, i);
+    const int pid = row_pid(h, i);
     double2 acc = make_double2(o * xi.x, o * xi.y);
 #pragma unroll
     for (int k = 0; k < kMaxWidth; ++k) {
         if (k < h.w) {
-            const int32_t m = h.nbr[k * h.n + i];
-            double hk = h.hop ? h.hop[k * h.n + i] : tr;
+            const int32_t m = slot_row(h, lpat, pid, i, k);
+            double hk = h.hop ? h.hop[k * h.n + i] : wk.t;
             const double2 xm = ld(x + ((int64_t)(m < 0 ? 0 : m) << vshift) + v);
             hk = m < 0 ? 0.0 : hk;
             acc = raxpy(acc, hk, xm);
@@ -119,17 +155,18 @@ __device__ __forceinline__ double2 row_h(const Ell &h, const V *x, int64_t i, in
 
 // H~ x and D x of row i together, sharing the gathered x_m.
 template <typename V>
-__device__ __forceinline__ void row_hd(const Ell &h, const V *x, int64_t i, int64_t v,
-                                       int vshift, double2 xi, double2 &hx, double2 &dx) {
-    const double o = h.ons[i];
-    const double tr = row_t(h, i);
+__device__ __forceinline__ void row_hd(const Ell &h, const Walk &wk, const int32_t *lpat,
+                                       const V *x, int64_t i, int64_t v, int vshift,
+                                       double2 xi, double2 &hx, double2 &dx) {
+    const double o = row_ons(h, wk, i);
+    const int pid = row_pid(h, i);
     hx = make_double2(o * xi.x, o * xi.y);
     dx = make_double2(0.0, 0.0);
 #pragma unroll
     for (int k = 0; k < kMaxWidth; ++k) {
         if (k < h.w) {
-            const int32_t m = h.nbr[k * h.n + i];
-            double hk = h.hop ? h.hop[k * h.n + i] : tr;
+            const int32_t m = slot_row(h, lpat, pid, i, k);
+            double hk = h.hop ? h.hop[k * h.n + i] : wk.t;
             double xk = h.xw[k * h.n + i];
             const double2 xm = ld(x + ((int64_t)(m < 0 ? 0 : m) << vshift) + v);
             hk = m < 0 ? 0.0 : hk;
@@ -142,13 +179,14 @@ __device__ __forceinline__ void row_hd(const Ell &h, const V *x, int64_t i, int6
 
 // D x of row i.
 template <typename V>
-__device__ __forceinline__ double2 row_d(const Ell &h, const V *x, int64_t i, int64_t v,
-                                         int vshift) {
+__device__ __forceinline__ double2 row_d(const Ell &h, const int32_t *lpat, const V *x,
+                                         int64_t i, int64_t v, int vshift) {
+    const int pid = row_pid(h, i);
     double2 dx = make_double2(0.0, 0.0);
 #pragma unroll
     for (int k = 0; k < kMaxWidth; ++k) {
         if (k < h.w) {
-            const int32_t m = h.nbr[k * h.n + i];
+            const int32_t m = slot_row(h, lpat, pid, i, k);
             double xk = h.xw[k * h.n + i];
             const double2 xm = ld(x + ((int64_t)(m < 0 ? 0 : m) << vshift) + v);
             xk = m < 0 ? 0.0 : xk;
@@ -180,14 +218,6 @@ __device__ __forceinline__ void block_sum(double2 s, int vshift, double2 *dst) {
     }
 }
 
-// The element blocks this work-group visits: blocks b0 + loc, b0 + loc +
-// nloc, ... below b1 of its segment, elements e0 + b * kBlock + tid below e1.
-struct Walk {
-    int sg;
-    int loc, nloc;
-    int64_t b0, b1, e0, e1;
-};
-
 __device__ __forceinline__ Walk walk_of(const Sweep &sw) {
     Walk w;
     Seg s;
@@ -207,10 +237,13 @@ __device__ __forceinline__ Walk walk_of(const Sweep &sw) {
     w.b1 = min(w.b0 + per, nblk);
     w.e0 = s.e0;
     w.e1 = s.e1;
+    w.t = s.t;
+    w.inv_es = s.inv_es;
     return w;
 }
 
-#define KPM_SWEEP_BEGIN(sw)                                                         \
+#define KPM_SWEEP_BEGIN(sw, h)                                                      \
+    KPM_PATTERNS(h)                                                                 \
     const Walk wk_ = walk_of(sw);                                                   \
     const int sg = wk_.sg;                                                          \
     (void)sg;                                                                       \
@@ -231,10 +264,10 @@ __global__ __launch_bounds__(kBlock) void k_moment_first(Ell h, Sweep sw, const 
                                                          double2 *__restrict__ partial,
                                                          int slot) {
     double2 s0 = make_double2(0.0, 0.0), s1 = make_double2(0.0, 0.0);
-    KPM_SWEEP_BEGIN(sw)
+    KPM_SWEEP_BEGIN(sw, h)
     const double2 xi = ld(in + e);
     const double2 l = ld(phil + e);
-    const double2 o = rounded<V>(row_h(h, in, i, v, sw.vshift, xi));
+    const double2 o = rounded<V>(row_h(h, wk_, lpat, in, i, v, sw.vshift, xi));
     st(out + e, o);
     s0 = cdot_acc(s0, l, xi);
     s1 = cdot_acc(s1, l, o);
@@ -257,6 +290,7 @@ __global__ __launch_bounds__(kBlock) void k_moment_step(Ell h, Sweep sw, const V
                                                         double2 *__restrict__ partial,
                                                         int slot) {
     double2 s0 = make_double2(0.0, 0.0);
+    KPM_PATTERNS(h)
     const Walk wk = walk_of(sw);
     const int64_t vmask = ((int64_t)1 << sw.vshift) - 1;
     for (int64_t b = wk.b0 + wk.loc; b < wk.b1; b += (int64_t)wk.nloc * ILP) {
@@ -276,15 +310,15 @@ __global__ __launch_bounds__(kBlock) void k_moment_step(Ell h, Sweep sw, const V
 #pragma unroll
         for (int u = 0; u < ILP; ++u) {
             const int64_t i = e[u] >> sw.vshift;
-            const double tr = row_t(h, i);
+            const int pid = row_pid(h, i);
 #pragma unroll
             for (int k = 0; k < kMaxWidth; ++k) {
                 if (k < h.w) {
-                    m[u][k] = h.nbr[k * h.n + i];
-                    hk[u][k] = h.hop ? h.hop[k * h.n + i] : tr;
+                    m[u][k] = slot_row(h, lpat, pid, i, k);
+                    hk[u][k] = h.hop ? h.hop[k * h.n + i] : wk.t;
                 }
             }
-            on[u] = h.ons[i];
+            on[u] = row_ons(h, wk, i);
             xi[u] = ld(p1 + e[u]);
             l[u] = NT ? ld_nt(phil + e[u]) : ld(phil + e[u]);
             q[u] = NT ? ld_nt(p0 + e[u]) : ld(p0 + e[u]);
@@ -324,10 +358,10 @@ template <typename V, bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_evolve_step(Ell h, Sweep sw, const V *p1,
                                                         const V *p0, V *out, V *acc,
                                                         const V *add, Coef c0, Coef c) {
-    KPM_SWEEP_BEGIN(sw)
+    KPM_SWEEP_BEGIN(sw, h)
     const double2 cm = coef(c, sg);
     const double2 xi = ld(p1 + e);
-    const double2 hx = row_h(h, p1, i, v, sw.vshift, xi);
+    const double2 hx = row_h(h, wk_, lpat, p1, i, v, sw.vshift, xi);
     double2 o, a;
     if (FIRST) {
         o = rounded<V>(hx);
@@ -348,11 +382,11 @@ __global__ __launch_bounds__(kBlock) void k_evolve_x_step(Ell h, Sweep sw, const
                                                           const V *q1, const V *q0,
                                                           V *qout, V *accx, V *accu,
                                                           Coef c0, Coef c) {
-    KPM_SWEEP_BEGIN(sw)
+    KPM_SWEEP_BEGIN(sw, h)
     const double2 cm = coef(c, sg);
     const double2 xi = ld(p1 + e);
     double2 hp, dp;
-    row_hd(h, p1, i, v, sw.vshift, xi, hp, dp);
+    row_hd(h, wk_, lpat, p1, i, v, sw.vshift, xi, hp, dp);
     if (FIRST) {
         hp = rounded<V>(hp);
         dp = rounded<V>(dp);
@@ -362,7 +396,7 @@ __global__ __launch_bounds__(kBlock) void k_evolve_x_step(Ell h, Sweep sw, const
         st_nt(accu + e, cmla(cmul(coef(c0, sg), xi), cm, hp));
     } else {
         const double2 qi = ld(q1 + e);
-        const double2 hq = row_h(h, q1, i, v, sw.vshift, qi);
+        const double2 hq = row_h(h, wk_, lpat, q1, i, v, sw.vshift, qi);
         const double2 pp = ld_nt(p0 + e);
         const double2 qq = q0 ? ld_nt(q0 + e) : make_double2(0.0, 0.0);
         const double2 po = rounded<V>(two_minus(hp, pp));
@@ -378,8 +412,8 @@ __global__ __launch_bounds__(kBlock) void k_evolve_x_step(Ell h, Sweep sw, const
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_apply_d(Ell h, Sweep sw, const V *x, V *y,
                                                     Coef alpha) {
-    KPM_SWEEP_BEGIN(sw)
-    st(y + e, cmul(coef(alpha, sg), row_d(h, x, i, v, sw.vshift)));
+    KPM_SWEEP_BEGIN(sw, h)
+    st(y + e, cmul(coef(alpha, sg), row_d(h, lpat, x, i, v, sw.vshift)));
     KPM_SWEEP_END
 }
 

@@ -29,7 +29,8 @@ ABI_SYMBOLS = ("kpm_build_graphene", "kpm_system_create", "kpm_system_destroy",
                "kpm_system_n_samples", "kpm_system_offsets", "kpm_moments", "kpm_evolve",
                "kpm_evolve_x", "kpm_vac", "kpm_msd", "kpm_kpm_sum", "kpm_sigma_gk",
                "kpm_sigma_e1", "kpm_sigma_e2", "kpm_set_launch", "kpm_get_launch",
-               "kpm_autotune", "kpm_set_timing", "kpm_get_stats", "kpm_reset_stats",
+               "kpm_autotune", "kpm_set_graphs", "kpm_set_timing", "kpm_get_stats",
+               "kpm_reset_stats",
                "kpm_last_error", "kpm_version")
 
 
@@ -53,7 +54,8 @@ class Launch(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("step_ms", C.c_double), ("step_launches", C.c_int64),
-                ("step_rows", C.c_int64), ("site_updates", C.c_int64)]
+                ("step_rows", C.c_int64), ("site_updates", C.c_int64),
+                ("step_bytes", C.c_int64)]
 
 
 _lib = None
@@ -88,6 +90,7 @@ def lib():
             "kpm_set_launch": [vp, C.c_int, C.POINTER(Launch)],
             "kpm_get_launch": [vp, C.c_int, C.POINTER(Launch)],
             "kpm_autotune": [vp, C.c_int, vp, C.c_int, C.POINTER(Launch)],
+            "kpm_set_graphs": [vp, C.c_int],
             "kpm_set_timing": [vp, C.c_int],
             "kpm_get_stats": [vp, C.POINTER(Stats)],
             "kpm_reset_stats": [vp],
@@ -367,6 +370,11 @@ def kpm_autotune(sys: System, phi, reps: int = 10) -> dict:
     return dict(groups_per_cu=out.groups_per_cu, ilp=out.ilp, streaming=out.streaming)
 
 
+def kpm_set_graphs(sys: System, enable: bool = True):
+    """Capture each moment set as a hipGraph once and replay it."""
+    _check(lib().kpm_set_graphs(sys.handle, int(bool(enable))))
+
+
 def kpm_set_timing(sys: System, enable: bool = True):
     _check(lib().kpm_set_timing(sys.handle, int(bool(enable))))
 
@@ -375,7 +383,7 @@ def kpm_get_stats(sys: System) -> dict:
     s = Stats()
     _check(lib().kpm_get_stats(sys.handle, C.byref(s)))
     return dict(step_ms=s.step_ms, step_launches=s.step_launches, step_rows=s.step_rows,
-                site_updates=s.site_updates)
+                site_updates=s.site_updates, step_bytes=s.step_bytes)
 
 
 def kpm_reset_stats(sys: System):

@@ -136,3 +136,35 @@ def test_batch_launch_shapes_and_autotune():
     mu = kp.kpm_moments(sysg, d, d, 30)
     assert rel_err(mu, ref, float(np.abs(ref[..., 0]).max())) < 1e-13
     assert best["groups_per_cu"] in (4, 8, 16)
+
+
+def test_graph_replays_match_eager():
+    """Moment sets replayed from captured hipGraphs equal direct launches bit
+    for bit, on every replay, with eager work and synchronisations between
+    the replays (single system and batch; moments and the VAC loop)."""
+    _need_gpu()
+    cases, sysg, phis = _batch(2)
+    d = sysg.upload(np.concatenate(phis))
+    ref = kp.kpm_moments(sysg, d, d, 300)
+    ref_v = kp.kpm_vac(sysg, d, 2, 0.3, 20, 64)
+    kp.kpm_set_graphs(sysg, True)
+    for rep in range(3):
+        got = kp.kpm_moments(sysg, d, d, 300)
+        assert np.array_equal(got, ref), rep
+        got_v = kp.kpm_vac(sysg, d, 2, 0.3, 20, 64)
+        assert np.array_equal(got_v, ref_v), rep
+        e = d.clone()
+        kp.kpm_evolve(sysg, e, 0.2, 1, 12)                 # eager work in between
+        torch.cuda.synchronize()
+    kp.kpm_set_graphs(sysg, False)
+    assert np.array_equal(kp.kpm_moments(sysg, d, d, 300), ref)
+
+    c = cases[3]
+    single = kp.graphene_system(c["nx"], c["ny"], c["geometry"], -2.7, c["onsite"],
+                                c["active"], c["e_scale"])
+    ds = single.upload(phis[3])
+    ref1 = kp.kpm_moments(single, ds, ds, 500)
+    kp.kpm_set_graphs(single, True)
+    for rep in range(3):
+        assert np.array_equal(kp.kpm_moments(single, ds, ds, 500), ref1), rep
+        torch.cuda.synchronize()
