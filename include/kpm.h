@@ -89,9 +89,10 @@ typedef struct kpm_system kpm_system;
  * ends with equal hopping), dx antisymmetric, e_scale >= Gershgorin bound.
  * Device form (chosen at creation, results agree to rounding): when the rows
  * repeat at most 256 distinct neighbour-offset patterns (any lattice does),
- * neighbours are stored as one pattern byte per row instead of the list, and
- * when every on-site energy is exactly a float it is stored as a float.  The
- * environment variable KPM_COMPACT=0 keeps the explicit forms.
+ * neighbours are also stored as one pattern byte per row (kpm_launch.compact
+ * selects the form a launch reads), and when every on-site energy is exactly
+ * a float it is stored as a float.  The environment variable KPM_COMPACT=0
+ * keeps only the explicit forms.
  */
 typedef struct {
     int64_t n_sites;
@@ -227,16 +228,19 @@ kpm_status kpm_sigma_e2(int n_times, int n_energies, const double *rho_msd,
 /*
  * Launch shape of the Chebyshev moment step for a given n_vec: work-groups
  * per compute unit of the persistent grid (1..32; the grid is rounded to a
- * multiple of the 8 XCDs), elements per thread per pass (ilp: 1, 2 or 4) and
+ * multiple of the 8 XCDs), elements per thread per pass (ilp: 1, 2 or 4),
  * streaming (non-temporal) access to the operands read or written once per
- * step (0 or 1).  At a fixed grid size the moments are bit-identical for
- * every ilp and streaming choice; the grid size changes only the order of
- * the inner-product partial sums.
+ * step (0 or 1), and whether neighbours are read in the compact pattern form
+ * (1) or from the explicit list (0; the explicit list is used regardless when
+ * the system has no compact form).  At a fixed grid size the moments are
+ * bit-identical for every ilp, streaming and compact choice; the grid size
+ * changes only the order of the inner-product partial sums.
  */
 typedef struct {
     int32_t groups_per_cu;
     int32_t ilp;
     int32_t streaming;
+    int32_t compact;
 } kpm_launch;
 
 kpm_status kpm_set_launch(kpm_system *sys, int n_vec, const kpm_launch *launch);
@@ -244,8 +248,8 @@ kpm_status kpm_get_launch(kpm_system *sys, int n_vec, kpm_launch *out);
 
 /*
  * Autotuner: times `reps` moment steps of every candidate shape
- * (groups_per_cu in {4, 8, 16} x ilp in {1, 2, 4} x streaming in {0, 1}) on
- * the device state
+ * (groups_per_cu in {4, 8, 16} x ilp in {1, 2, 4} x streaming in {0, 1} x
+ * compact in {0, 1} when the system has the compact form) on the device state
  * `phi` ([n_sites][n_vec], read only; only system scratch is written), keeps
  * the fastest for this n_vec and returns it in *best (may be NULL).
  * Synchronises the stream.

@@ -88,17 +88,21 @@ struct DeviceGuard {
 
 bool valid_launch(const kpm_launch &l) {
     return l.groups_per_cu >= 1 && l.groups_per_cu <= 32 &&
-           (l.ilp == 1 || l.ilp == 2 || l.ilp == 4) && (l.streaming == 0 || l.streaming == 1);
+           (l.ilp == 1 || l.ilp == 2 || l.ilp == 4) && (l.streaming == 0 || l.streaming == 1) &&
+           (l.compact == 0 || l.compact == 1);
 }
 
 // Launch shape used until kpm_autotune or kpm_set_launch picks another.
-kpm_launch default_launch(int vshift) {
+kpm_launch default_launch(int vshift, kpm_precision prec) {
     kpm_launch l;
     // measured on MI355X (paper-scale sheet): one vector favours 4 groups per
     // CU, many vectors 8; streaming helps every vector count
+    // the compact neighbour form pays off while the per-row structure is a
+    // noticeable share of the bytes (few vectors per row)
     l.groups_per_cu = vshift == 0 ? 4 : 8;
-    l.ilp = vshift >= 6 ? 4 : 1;
-    l.streaming = 1;
+    l.ilp = (vshift >= 6 && prec == KPM_FP32_STATES) ? 4 : 1;
+    l.streaming = vshift == 0 ? 0 : 1;
+    l.compact = vshift <= 3 ? 1 : 0;
     return l;
 }
 
@@ -241,13 +245,13 @@ struct kpm_system {
     hipStream_t cap = nullptr;
     struct GraphKey {
         const void *phil, *phir, *a, *b, *partial, *dmom;
-        int nm, vshift, groups, ilp, streaming;
+        int nm, vshift, groups, ilp, streaming, compact;
         int64_t stride_r, offset;
         bool operator==(const GraphKey &o) const {
             return phil == o.phil && phir == o.phir && a == o.a && b == o.b &&
                    partial == o.partial && dmom == o.dmom && nm == o.nm && vshift == o.vshift &&
                    groups == o.groups && ilp == o.ilp && streaming == o.streaming &&
-                   stride_r == o.stride_r && offset == o.offset;
+                   compact == o.compact && stride_r == o.stride_r && offset == o.offset;
         }
     };
     struct GraphEntry {
@@ -276,6 +280,13 @@ struct kpm_system {
     size_t elem_bytes() const { return prec == KPM_FP64 ? 16 : 8; }
     size_t state_bytes(int vshift) const { return (size_t)n * ((size_t)1 << vshift) * elem_bytes(); }
 
+    // The device Hamiltonian as a launch with shape l reads it.
+    kpm::Ell ell_for(const kpm_launch &l) const {
+        kpm::Ell h = ell();
+        if (!l.compact) h.pid = nullptr;
+        return h;
+    }
+
     kpm::Ell ell() const {
         kpm::Ell h;
         h.nbr = d_nbr;
@@ -295,7 +306,8 @@ struct kpm_system {
     // element (read phi_1, phi_0, phi_L, write phi_0) and the row structure
     // once per row (neighbours, on-site term, per-slot hopping).
     int64_t step_bytes(int vshift) const {
-        const int64_t per_row = (d_pid ? 1 : 4 * w) + (d_onsf ? 4 : 8) + (d_hop ? 8 * w : 0);
+        const bool compact = d_pid && launch[vshift].compact;
+        const int64_t per_row = (compact ? 1 : 4 * w) + (d_onsf ? 4 : 8) + (d_hop ? 8 * w : 0);
         return n * (((int64_t)4 * elem_bytes()) << vshift) + n * per_row;
     }
 
@@ -494,7 +506,7 @@ template <typename V>
 kpm_status enqueue_moments(kpm_system *sys, const kpm::Sweep &sw, int ring, hipStream_t s,
                            bool events, const V *phil, const V *phir, int nm, V *a_buf,
                            V *b_buf, int64_t stride_r, int64_t offset) {
-    const kpm::Ell h = sys->ell();
+    const kpm::Ell h = sys->ell_for(sys->launch[sw.vshift]);
     // C_0 and C_1 (phi_0 = phi_R, phi_1 = H~ phi_0)
     kpm::launch_moment_step<V>(h, sw, true, phir, nullptr, a_buf, phil, sys->partial, 0, s);
     // phi_m = 2 H~ phi_{m-1} - phi_{m-2}, in place after the first step
@@ -546,7 +558,8 @@ kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir
                                   a_buf, b_buf, stride_r, offset);
     kpm_system::GraphKey key{phil, phir, a_buf, b_buf, sys->partial, sys->dmom, nm, vshift,
                              sys->launch[vshift].groups_per_cu, sys->launch[vshift].ilp,
-                             sys->launch[vshift].streaming, stride_r, offset};
+                             sys->launch[vshift].streaming, sys->launch[vshift].compact,
+                             stride_r, offset};
     hipGraphExec_t exec = sys->find_graph(key);
     if (!exec) {
         KPM_TRY(sys->ensure_capture_stream());
@@ -582,7 +595,7 @@ kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir
 template <typename V>
 kpm_status run_evolve(kpm_system *sys, int vshift, const V *in, V *acc, const V *add,
                       double dt, int sign, int np, V *a_buf, V *b_buf) {
-    const kpm::Ell h = sys->ell();
+    const kpm::Ell h = sys->ell_for(sys->launch[vshift]);
     kpm::Sweep sw;
     KPM_TRY(sys->sweep(vshift, &sw));
     std::vector<double2> c;
@@ -608,7 +621,7 @@ kpm_status run_evolve(kpm_system *sys, int vshift, const V *in, V *acc, const V 
 template <typename V>
 kpm_status run_evolve_x(kpm_system *sys, int vshift, const V *in, V *accx, V *accu,
                         double dt, int np, V *pa, V *pb, V *qa, V *qb) {
-    const kpm::Ell h = sys->ell();
+    const kpm::Ell h = sys->ell_for(sys->launch[vshift]);
     kpm::Sweep sw;
     KPM_TRY(sys->sweep(vshift, &sw));
     std::vector<double2> c;
@@ -698,7 +711,7 @@ kpm_status vac_impl(kpm_system *sys, int vshift, const void *phi_v, int nsteps, 
     V *psi = (V *)sys->vecs[2], *psi2 = (V *)sys->vecs[3];
     V *rr = (V *)sys->vecs[4], *rr2 = (V *)sys->vecs[5], *ll = (V *)sys->vecs[6];
     const V *phi = (const V *)phi_v;
-    const kpm::Ell h = sys->ell();
+    const kpm::Ell h = sys->ell_for(sys->launch[vshift]);
     kpm::Sweep sw;
     KPM_TRY(sys->sweep(vshift, &sw));
     const kpm::Coef alpha = sys->alpha();
@@ -761,11 +774,9 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
     V *a = (V *)sys->vecs[0], *b = (V *)sys->vecs[1];
     hipStream_t s = sys->stream;
     const size_t bytes = sys->state_bytes(vs);
-    const kpm::Ell h = sys->ell();
     static const int groups[] = {4, 8, 16};
     static const int ilps[] = {1, 2, 4};
-    float best_ms = 1e30f;
-    kpm_launch pick = sys->launch[vs];
+    const int forms = sys->d_pid ? 2 : 1;
     hipEvent_t e0, e1;
     KPM_HIP(hipEventCreate(&e0));
     KPM_HIP(hipEventCreate(&e1));
@@ -773,38 +784,47 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
     // Each candidate runs the real two-buffer recursion (the output of one
     // step is the gathered input of the next) on copies of phi, three times;
     // the fastest round counts.
+    auto time_shape = [&](const kpm_launch &l, float *out_ms) -> kpm_status {
+        const kpm::Ell h = sys->ell_for(l);
+        kpm::Sweep sw;
+        KPM_TRY(sys->sweep_with(vs, l, &sw));
+        KPM_TRY(sys->ensure_partial(1, sw.nwg, 1 << vs));
+        float best = 1e30f;
+        for (int round = 0; round < 3; ++round) {
+            KPM_HIP(hipMemcpyAsync(a, phi, bytes, hipMemcpyDeviceToDevice, s));
+            KPM_HIP(hipMemcpyAsync(b, phi, bytes, hipMemcpyDeviceToDevice, s));
+            V *p0 = b, *p1 = a;
+            KPM_HIP(hipEventRecord(e0, s));
+            for (int k = 0; k < reps; ++k) {
+                kpm::launch_moment_step<V>(h, sw, false, p1, p0, p0, phi, sys->partial, 0, s);
+                std::swap(p0, p1);
+            }
+            KPM_HIP(hipEventRecord(e1, s));
+            KPM_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            KPM_HIP(hipEventElapsedTime(&ms, e0, e1));
+            best = std::min(best, ms);
+        }
+        *out_ms = best;
+        return KPM_OK;
+    };
+    // The current shape is the incumbent; a candidate replaces it only when
+    // it is more than 2 % faster, so near-ties keep a stable choice.
+    kpm_launch pick = sys->launch[vs];
+    float best_ms = 1e30f;
+    st = time_shape(pick, &best_ms);
     for (int g : groups) {
-        for (int q = 0; q < 6 && st == KPM_OK; ++q) {
+        for (int q = 0; q < 6 * forms && st == KPM_OK; ++q) {
             kpm_launch l;
             l.groups_per_cu = g;
             l.ilp = ilps[q % 3];
-            l.streaming = q / 3;
-            kpm::Sweep sw;
-            if ((st = sys->sweep_with(vs, l, &sw)) != KPM_OK) break;
-            if ((st = sys->ensure_partial(1, sw.nwg, 1 << vs)) != KPM_OK) break;
-            for (int round = 0; round < 3; ++round) {
-                if (hipMemcpyAsync(a, phi, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-                    hipMemcpyAsync(b, phi, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) {
-                    st = fail(KPM_ERR_DEVICE, "autotune copy");
-                    break;
-                }
-                V *p0 = b, *p1 = a;
-                (void)hipEventRecord(e0, s);
-                for (int k = 0; k < reps; ++k) {
-                    kpm::launch_moment_step<V>(h, sw, false, p1, p0, p0, phi, sys->partial, 0, s);
-                    std::swap(p0, p1);
-                }
-                (void)hipEventRecord(e1, s);
-                if (hipEventSynchronize(e1) != hipSuccess) {
-                    st = fail(KPM_ERR_DEVICE, "autotune: %s", hipGetErrorString(hipGetLastError()));
-                    break;
-                }
-                float ms = 0;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    pick = l;
-                }
+            l.streaming = (q / 3) % 2;
+            l.compact = forms == 2 ? q / 6 : 0;
+            float ms = 0;
+            if ((st = time_shape(l, &ms)) != KPM_OK) break;
+            if (ms < 0.98f * best_ms) {
+                best_ms = ms;
+                pick = l;
             }
         }
         if (st != KPM_OK) break;
@@ -852,13 +872,15 @@ kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int devi
         sys->off[s + 1] = sys->off[s] + parts[s].n;
         sys->es[s] = parts[s].e_scale;
     }
-    for (int v = 0; v < 7; ++v) sys->launch[v] = default_launch(v);
+    for (int v = 0; v < 7; ++v) sys->launch[v] = default_launch(v, prec);
     if (const char *env = std::getenv("KPM_GROUPS_PER_CU"))
         for (auto &l : sys->launch) l.groups_per_cu = std::max(1, std::min(32, atoi(env)));
     if (const char *env = std::getenv("KPM_ILP"))
         for (auto &l : sys->launch) l.ilp = atoi(env) >= 4 ? 4 : (atoi(env) == 2 ? 2 : 1);
     if (const char *env = std::getenv("KPM_STREAMING"))
         for (auto &l : sys->launch) l.streaming = atoi(env) != 0;
+    if (const char *env = std::getenv("KPM_COMPACT_LAUNCH"))
+        for (auto &l : sys->launch) l.compact = atoi(env) != 0;
 
     // Concatenate and shift indices by the sample offset; per-slot weights
     // carry 1/E_s of their sample.
@@ -866,7 +888,7 @@ kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int devi
     std::vector<double> ons(n), hop(any_hop ? (size_t)w * n : 0), xw(all_dx ? (size_t)w * n : 0);
     sys->seg_t.resize(nseg);
     bool ons_float = std::getenv("KPM_COMPACT") == nullptr || atoi(std::getenv("KPM_COMPACT")) != 0;
-    const bool try_compact = ons_float;
+    const bool try_compact = ons_float && w <= kpm::kMaxWidth;
     for (int s = 0; s < nseg; ++s) {
         const Packed &p = parts[s];
         const int64_t o = sys->off[s];
@@ -937,12 +959,10 @@ kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int devi
         if (e != hipSuccess) return fail(KPM_ERR_DEVICE, "upload: %s", hipGetErrorString(e));
         return KPM_OK;
     };
-    kpm_status st = KPM_OK;
-    if (!pid.empty()) {
+    kpm_status st = upload((void **)&sys->d_nbr, nbr.data(), nbr.size() * sizeof(int32_t));
+    if (st == KPM_OK && !pid.empty()) {
         st = upload((void **)&sys->d_pid, pid.data(), pid.size());
         if (st == KPM_OK) st = upload((void **)&sys->d_pat, pat.data(), pat.size() * sizeof(int32_t));
-    } else {
-        st = upload((void **)&sys->d_nbr, nbr.data(), nbr.size() * sizeof(int32_t));
     }
     if (st == KPM_OK && ons_float) {
         std::vector<float> of(ons.begin(), ons.end());

@@ -277,20 +277,41 @@ __global__ __launch_bounds__(kBlock) void k_moment_first(Ell h, Sweep sw, const 
     block_sum(s1, sw.vshift, partial + ((int64_t)(slot + 1) * sw.nwg + blockIdx.x) * r);
 }
 
+// Structure forms of the moment step.  kFormGeneric reads everything the
+// Ell may hold and checks it at run time (any width <= kMaxWidth, explicit or
+// compact neighbours, per-slot or uniform hopping, float or double on-site
+// terms).  The other forms fix, at compile time, width 3 and uniform hopping
+// (every graphene sample) and the neighbour and on-site storage, so the loop
+// body is straight-line code whose loads the compiler can issue together.
+enum { kFormGeneric = 0, kFormC3F = 1, kFormC3D = 2, kFormL3F = 3, kFormL3D = 4 };
+
+template <int FORM> struct FormTraits {
+    static constexpr bool generic = FORM == kFormGeneric;
+    static constexpr int width = generic ? kMaxWidth : 3;
+    static constexpr bool compact = FORM == kFormC3F || FORM == kFormC3D;
+    static constexpr bool ons_float = FORM == kFormC3F || FORM == kFormL3F;
+};
+
 // Recursion step of the moments, out = 2 H~ p1 - p0 and <L|out>, with ILP
 // elements per thread per pass: all loads of the ILP elements are issued
 // before any arithmetic, so a wavefront keeps ILP times more bytes in flight
 // (the gathers depend on the index loads, which would otherwise serialise
-// two memory latencies per element).  Elements are visited in the same order
-// for every ILP, so every ILP gives bit-identical results.
-template <typename V, int ILP, bool NT>
+// two memory latencies per element).  Elements are visited in the same order,
+// and every form performs the same floating-point operations, so all ILP,
+// streaming and form choices give bit-identical results.
+template <typename V, int ILP, bool NT, int FORM>
 __global__ __launch_bounds__(kBlock) void k_moment_step(Ell h, Sweep sw, const V *p1,
                                                         const V *p0, V *out,
                                                         const V *__restrict__ phil,
                                                         double2 *__restrict__ partial,
                                                         int slot) {
+    using F = FormTraits<FORM>;
     double2 s0 = make_double2(0.0, 0.0);
-    KPM_PATTERNS(h)
+    __shared__ int32_t lpat[kMaxPatterns * kMaxWidth];
+    if (F::compact || (F::generic && h.pid)) {
+        for (int j = threadIdx.x; j < h.npat * kMaxWidth; j += kBlock) lpat[j] = h.pat[j];
+        __syncthreads();
+    }
     const Walk wk = walk_of(sw);
     const int64_t vmask = ((int64_t)1 << sw.vshift) - 1;
     for (int64_t b = wk.b0 + wk.loc; b < wk.b1; b += (int64_t)wk.nloc * ILP) {
@@ -303,22 +324,40 @@ __global__ __launch_bounds__(kBlock) void k_moment_step(Ell h, Sweep sw, const V
             ok[u] = bu < wk.b1 && e[u] < wk.e1;
             e[u] = ok[u] ? e[u] : 0;          // a safe element; its result is dropped
         }
-        int32_t m[ILP][kMaxWidth];
-        double hk[ILP][kMaxWidth];
+        int32_t m[ILP][F::width];
+        double hk[ILP][F::width];
         double on[ILP];
         double2 xi[ILP], l[ILP], q[ILP];
 #pragma unroll
         for (int u = 0; u < ILP; ++u) {
             const int64_t i = e[u] >> sw.vshift;
-            const int pid = row_pid(h, i);
+            if constexpr (F::generic) {
+                const int pid = row_pid(h, i);
 #pragma unroll
-            for (int k = 0; k < kMaxWidth; ++k) {
-                if (k < h.w) {
-                    m[u][k] = slot_row(h, lpat, pid, i, k);
-                    hk[u][k] = h.hop ? h.hop[k * h.n + i] : wk.t;
+                for (int k = 0; k < F::width; ++k) {
+                    m[u][k] = k < h.w ? slot_row(h, lpat, pid, i, k) : -1;
+                    hk[u][k] = (k < h.w && h.hop) ? h.hop[k * h.n + i] : wk.t;
                 }
+                on[u] = row_ons(h, wk, i);
+            } else {
+                if constexpr (F::compact) {
+                    const int pid = h.pid[i];
+#pragma unroll
+                    for (int k = 0; k < F::width; ++k) {
+                        const int32_t d = lpat[pid * kMaxWidth + k];
+                        m[u][k] = d == kEmptySlot ? -1 : (int32_t)(i + d);
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < F::width; ++k) m[u][k] = h.nbr[k * h.n + i];
+                }
+#pragma unroll
+                for (int k = 0; k < F::width; ++k) hk[u][k] = wk.t;
+                if constexpr (F::ons_float)
+                    on[u] = (double)h.onsf[i] * wk.inv_es;
+                else
+                    on[u] = h.ons[i];
             }
-            on[u] = row_ons(h, wk, i);
             xi[u] = ld(p1 + e[u]);
             l[u] = NT ? ld_nt(phil + e[u]) : ld(phil + e[u]);
             q[u] = NT ? ld_nt(p0 + e[u]) : ld(p0 + e[u]);
@@ -329,13 +368,12 @@ __global__ __launch_bounds__(kBlock) void k_moment_step(Ell h, Sweep sw, const V
             const int64_t v = e[u] & vmask;
             acc[u] = make_double2(on[u] * xi[u].x, on[u] * xi[u].y);
 #pragma unroll
-            for (int k = 0; k < kMaxWidth; ++k) {
-                if (k < h.w) {
-                    const int32_t mm = m[u][k];
-                    const double2 xm = ld(p1 + ((int64_t)(mm < 0 ? 0 : mm) << sw.vshift) + v);
-                    const double hh = mm < 0 ? 0.0 : hk[u][k];
-                    acc[u] = raxpy(acc[u], hh, xm);
-                }
+            for (int k = 0; k < F::width; ++k) {
+                if (F::generic && k >= h.w) continue;
+                const int32_t mm = m[u][k];
+                const double2 xm = ld(p1 + ((int64_t)(mm < 0 ? 0 : mm) << sw.vshift) + v);
+                const double hh = mm < 0 ? 0.0 : hk[u][k];
+                acc[u] = raxpy(acc[u], hh, xm);
             }
         }
 #pragma unroll
@@ -467,8 +505,24 @@ __global__ __launch_bounds__(kBlock) void k_kpm_sum(const double *__restrict__ m
 template <typename V, int ILP, bool NT>
 static void launch_step_shape(const Ell &h, const Sweep &sw, const V *p1, const V *p0, V *out,
                               const V *phil, double2 *partial, int slot, hipStream_t s) {
-    hipLaunchKernelGGL((k_moment_step<V, ILP, NT>), dim3(sw.nwg), dim3(kBlock), 0, s, h, sw,
-                       p1, p0, out, phil, partial, slot);
+    const bool fixed = h.w == 3 && !h.hop;
+    int form = kFormGeneric;
+    if (fixed && h.pid) form = h.onsf ? kFormC3F : kFormC3D;
+    else if (fixed) form = h.onsf ? kFormL3F : kFormL3D;
+    switch (form) {
+#define KPM_FORM_CASE(F)                                                                       \
+        case F:                                                                                \
+            hipLaunchKernelGGL((k_moment_step<V, ILP, NT, F>), dim3(sw.nwg), dim3(kBlock), 0,  \
+                               s, h, sw, p1, p0, out, phil, partial, slot);                    \
+            break;
+        KPM_FORM_CASE(kFormC3F)
+        KPM_FORM_CASE(kFormC3D)
+        KPM_FORM_CASE(kFormL3F)
+        KPM_FORM_CASE(kFormL3D)
+        default:
+        KPM_FORM_CASE(kFormGeneric)
+#undef KPM_FORM_CASE
+    }
 }
 
 template <typename V>

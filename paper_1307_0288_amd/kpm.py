@@ -49,7 +49,8 @@ class _Desc(C.Structure):
 
 
 class Launch(C.Structure):
-    _fields_ = [("groups_per_cu", C.c_int32), ("ilp", C.c_int32), ("streaming", C.c_int32)]
+    _fields_ = [("groups_per_cu", C.c_int32), ("ilp", C.c_int32), ("streaming", C.c_int32),
+                ("compact", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -349,16 +350,19 @@ def kpm_msd(sys: System, phi, n_steps: int, dt_fs: float, n_bessel: int, n_momen
     return _loop(lib().kpm_msd, sys, phi, n_steps, dt_fs, n_bessel, n_moments)
 
 
-def kpm_set_launch(sys: System, n_vec: int, groups_per_cu: int, ilp: int, streaming: int = 0):
+def kpm_set_launch(sys: System, n_vec: int, groups_per_cu: int, ilp: int, streaming: int = 0,
+                   compact: int = 1):
     """Launch shape of the moment step for n_vec vectors (see kpm_launch in kpm.h)."""
     _check(lib().kpm_set_launch(sys.handle, n_vec,
-                                C.byref(Launch(groups_per_cu, ilp, int(bool(streaming))))))
+                                C.byref(Launch(groups_per_cu, ilp, int(bool(streaming)),
+                                               int(bool(compact))))))
 
 
 def kpm_get_launch(sys: System, n_vec: int) -> dict:
     out = Launch()
     _check(lib().kpm_get_launch(sys.handle, n_vec, C.byref(out)))
-    return dict(groups_per_cu=out.groups_per_cu, ilp=out.ilp, streaming=out.streaming)
+    return dict(groups_per_cu=out.groups_per_cu, ilp=out.ilp, streaming=out.streaming,
+                compact=out.compact)
 
 
 def kpm_autotune(sys: System, phi, reps: int = 10) -> dict:
@@ -367,7 +371,8 @@ def kpm_autotune(sys: System, phi, reps: int = 10) -> dict:
     out = Launch()
     sys._sync_stream()
     _check(lib().kpm_autotune(sys.handle, nv, p, reps, C.byref(out)))
-    return dict(groups_per_cu=out.groups_per_cu, ilp=out.ilp, streaming=out.streaming)
+    return dict(groups_per_cu=out.groups_per_cu, ilp=out.ilp, streaming=out.streaming,
+                compact=out.compact)
 
 
 def kpm_set_graphs(sys: System, enable: bool = True):

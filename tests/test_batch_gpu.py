@@ -128,10 +128,11 @@ def test_batch_launch_shapes_and_autotune():
     ref = None
     for ilp in (1, 2, 4):
         for nt in (0, 1):
-            kp.kpm_set_launch(sysg, 8, 8, ilp, nt)
-            mu = kp.kpm_moments(sysg, d, d, 30)
-            ref = mu if ref is None else ref
-            assert np.array_equal(mu, ref), (ilp, nt)
+            for cp in (0, 1):
+                kp.kpm_set_launch(sysg, 8, 8, ilp, nt, cp)
+                mu = kp.kpm_moments(sysg, d, d, 30)
+                ref = mu if ref is None else ref
+                assert np.array_equal(mu, ref), (ilp, nt, cp)
     best = kp.kpm_autotune(sysg, d, 3)
     mu = kp.kpm_moments(sysg, d, d, 30)
     assert rel_err(mu, ref, float(np.abs(ref[..., 0]).max())) < 1e-13

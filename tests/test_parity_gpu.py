@@ -297,13 +297,14 @@ def test_launch_shapes(n_vec, precision):
         ref = None
         for ilp in (1, 2, 4):
             for nt in (0, 1):
-                kp.kpm_set_launch(sysg, n_vec, g, ilp, nt)
-                mu = kp.kpm_moments(sysg, phi, phi, 40)
-                ref = mu if ref is None else ref
-                assert np.array_equal(mu, ref), (g, ilp, nt)
+                for cp in (0, 1):
+                    kp.kpm_set_launch(sysg, n_vec, g, ilp, nt, cp)
+                    mu = kp.kpm_moments(sysg, phi, phi, 40)
+                    ref = mu if ref is None else ref
+                    assert np.array_equal(mu, ref), (g, ilp, nt, cp)
         first = ref if first is None else first
         assert rel_err(ref, first, float(np.abs(first[:, 0]).max())) < 1e-13
     best = kp.kpm_autotune(sysg, phi, 3)
     assert best["groups_per_cu"] in (4, 8, 16) and best["ilp"] in (1, 2, 4)
-    assert best["streaming"] in (0, 1)
+    assert best["streaming"] in (0, 1) and best["compact"] in (0, 1)
     assert kp.kpm_get_launch(sysg, n_vec) == best
