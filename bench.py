@@ -34,7 +34,6 @@ import kpm_inputs as ki  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "moment_step_fp64_paper_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1307_0288_amd", "csrc", "kpm_kernels.hip")
-HOST_SRC = os.path.join(ROOT, "paper_1307_0288_amd", "csrc", "kpm_host.cpp")
 
 
 def log(msg):
@@ -42,16 +41,19 @@ def log(msg):
 
 
 def kernel_sha() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the source the moment step is compiled from: the kernel file up to
+    the first kernel after it, plus its launcher (edits elsewhere in the file do
+    not change the moment step)."""
+    with open(KERNEL_SRC) as f:
+        t = f.read()
+    head = t[:t.index("template <typename V, bool FIRST>\n__global__ __launch_bounds__(kBlock) "
+                      "void k_evolve_step(")]
+    a = t.index("template <typename V, int ILP, bool NT>\nstatic void launch_step_shape(")
+    b = t.index("template <typename V>\nvoid launch_evolve_step(")
+    return hashlib.sha256((head + t[a:b]).encode()).hexdigest()[:16]
 
 
-def host_sha() -> str:
-    with open(HOST_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
-
-
-def measured_traffic(step_rows: int):
+def measured_traffic(step_rows: int, launch: dict):
     """HBM bytes per moment-step launch from committed rocprofv3 counters,
     or None when they are absent or were taken on another kernel version."""
     try:
@@ -59,8 +61,8 @@ def measured_traffic(step_rows: int):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != kernel_sha() or t.get("host_sha") != host_sha() \
-            or t.get("step_rows") != step_rows:
+    if t.get("kernel_sha") != kernel_sha() or t.get("step_rows") != step_rows \
+            or t.get("launch_shape") != launch:
         return None
     return t.get("bytes_per_launch")
 
@@ -147,7 +149,7 @@ def main():
     bytes_launch = st["step_bytes"]
     bpu = bytes_launch / st["step_rows"]
     achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
-    traffic = measured_traffic(st["step_rows"])
+    traffic = measured_traffic(st["step_rows"], launch)
 
     cpu = None
     if args.cpu_moments > 0:

@@ -197,6 +197,30 @@ kpm_status kpm_msd(kpm_system *sys, int n_vec, const void *phi, int n_steps,
                    double dt_fs, int n_bessel, int n_moments, double *out);
 
 /*
+ * Fourier moments of the FTM (Alg. 4, Eq. 25-27):
+ * F_n = <phi_L| U(n dtau) |phi_R> for n = -n_moments .. n_moments, each step
+ * of dtau by the Chebyshev-Bessel expansion with n_bessel terms (forward for
+ * n > 0, backward for n < 0).  The aliasing-free step for a spectrum scaled to
+ * [-E_s, E_s] is dtau = pi hbar / E_s (Sec. 4.2; Bessel argument pi).
+ * phi_l, phi_r: device states.  f: host output [n_sys][n_vec][2 n_moments + 1][2]
+ * (re, im), index n + n_moments.  Synchronises the stream.
+ */
+kpm_status kpm_fourier_moments(kpm_system *sys, int n_vec, const void *phi_l,
+                               const void *phi_r, int n_moments, double dtau_fs,
+                               int n_bessel, double *f);
+
+/*
+ * FTM sum (Eq. 22-24) on the device:
+ * out[t][k] = dtau / (pi hbar Omega) sum_n w_n Re[exp(i E_k n dtau / hbar) F_n]
+ * with w_n the Hanning window (Eq. 28) when hanning != 0, else 1.
+ * f: host [n_rows][2 n_moments + 1][2]; energies: host [n_energies] eV;
+ * out: host [n_rows][n_energies].  Runs on `hip_stream` and synchronises it.
+ */
+kpm_status kpm_ftm_sum(int n_rows, int n_moments, const double *f, int n_energies,
+                       const double *energies, double dtau_fs, double area_nm2, int hanning,
+                       void *hip_stream, double *out);
+
+/*
  * KPM sum (Eq. 29-31) on the device:
  * out[t][k] = 2 / (pi Omega E_s sqrt(1 - e_k^2)) sum_m g_m (2 - delta_m0)
  *             T_m(e_k) moments[t][m],  e_k = energies[k] / E_s,

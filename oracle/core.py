@@ -40,6 +40,8 @@ def _lib():
         lib.orc_evolve.argtypes = ham + [C.c_double, C.c_double, C.c_int, C.c_int, dp, dp]
         lib.orc_evolve_x.restype = C.c_int
         lib.orc_evolve_x.argtypes = ham + [C.c_double, C.c_double, C.c_int, dp, dp, dp]
+        lib.orc_fourier.restype = C.c_int
+        lib.orc_fourier.argtypes = ham + [C.c_double, dp, dp, C.c_int, C.c_double, C.c_int, dp]
         for f in (lib.orc_vac, lib.orc_msd):
             f.restype = C.c_int
             f.argtypes = ham + [C.c_double, dp, C.c_int, C.c_double, C.c_int, C.c_int, dp]
@@ -203,3 +205,14 @@ def msd(lat: Lattice, e_scale: float, phi, n_steps: int, dt_fs: float, n_bessel:
     _check(_lib().orc_msd(*lat._ham(), e_scale, hbar, _p(a.view(np.float64)), n_steps, dt_fs,
                           n_bessel, n_moments, _p(out)), "msd")
     return out
+
+
+def fourier_moments(lat: Lattice, e_scale: float, phi_l, phi_r, n_moments: int, dtau_fs: float,
+                    n_bessel: int, hbar: float = HBAR_EV_FS) -> np.ndarray:
+    """F_n = <phi_L|U(n dtau)|phi_R>, n = -N_m .. N_m (Alg. 4). complex128 [2 N_m + 1]."""
+    l, r = _cvec(phi_l, lat.n), _cvec(phi_r, lat.n)
+    f = np.zeros(2 * n_moments + 1, dtype=np.complex128)
+    _check(_lib().orc_fourier(*lat._ham(), e_scale, hbar, _p(l.view(np.float64)),
+                              _p(r.view(np.float64)), n_moments, dtau_fs, n_bessel,
+                              _p(f.view(np.float64))), "fourier")
+    return f

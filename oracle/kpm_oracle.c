@@ -406,3 +406,34 @@ int orc_msd(int64_t n, const int64_t *row_ptr, const int64_t *col,
     free(y); free(ya); free(psi); free(xu); free(u); free(mu);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Fourier moments F_n = <phi_L| U(n dtau) |phi_R>, n = -nm .. nm (Alg. 4,   */
+/* Eq. 25-28): phi'_R is propagated forward by U(dtau) for n > 0 and        */
+/* backward by U(-dtau) = U(dtau)^dagger for n < 0, each step by the        */
+/* Chebyshev-Bessel expansion with np terms.  f[n + nm] receives F_n.       */
+/* ------------------------------------------------------------------------ */
+int orc_fourier(int64_t n, const int64_t *row_ptr, const int64_t *col,
+                const double *hop, const double *dx, const double *onsite,
+                double e_scale, double hbar, const double *phil, const double *phir,
+                int nm, double dtau, int np, double *f)
+{
+    if (nm < 0 || np < 2 || e_scale <= 0) return -1;
+    orc_ham h = {n, row_ptr, col, hop, dx, onsite, e_scale};
+    const cplx *l = (const cplx *)phil, *r = (const cplx *)phir;
+    cplx *out = (cplx *)f;
+    cplx *psi = cvec(n), *nxt = cvec(n);
+    int rc = (psi && nxt) ? 0 : -2;
+    if (!rc) out[nm] = dot(n, l, r);
+    for (int dir = +1; !rc && dir >= -1; dir -= 2) {
+        memcpy(psi, r, (size_t)n * sizeof(cplx));
+        for (int k = 1; !rc && k <= nm; ++k) {
+            rc = evolve(&h, hbar, dtau, dir, np, psi, nxt);
+            if (rc) break;
+            cplx *t = psi; psi = nxt; nxt = t;
+            out[nm + dir * k] = dot(n, l, psi);
+        }
+    }
+    free(psi); free(nxt);
+    return rc;
+}

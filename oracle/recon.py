@@ -29,6 +29,27 @@ def jackson(n_moments: int) -> np.ndarray:
     return (1 - n * a) * np.cos(np.pi * n * a) + a * np.sin(np.pi * n * a) / np.tan(np.pi * a)
 
 
+def hanning(n_moments: int) -> np.ndarray:
+    """Hanning window w_n = (1 + cos(pi n / (N_m + 1))) / 2, n = -N_m .. N_m (Eq. 28)."""
+    n = np.arange(-n_moments, n_moments + 1, dtype=np.float64)
+    return 0.5 * (1.0 + np.cos(np.pi * n / (n_moments + 1)))
+
+
+def ftm_sum(fmom, energies_ev, dtau_fs: float, area_nm2: float, window=None,
+            hbar: float = HBAR_EV_FS) -> np.ndarray:
+    """(dtau / (pi hbar Omega)) sum_n w_n Re[exp(i E n dtau / hbar) F_n] (Eq. 22-24).
+
+    fmom: [..., 2 N_m + 1] complex Fourier moments F_{-N_m} .. F_{N_m}.
+    """
+    fmom = np.asarray(fmom, dtype=np.complex128)
+    nm = (fmom.shape[-1] - 1) // 2
+    w = hanning(nm) if window is None else np.asarray(window)
+    n = np.arange(-nm, nm + 1, dtype=np.float64)
+    ph = np.exp(1j * np.outer(n, np.asarray(energies_ev, dtype=np.float64)) * dtau_fs / hbar)
+    s = np.real(np.tensordot(fmom * w, ph, axes=([-1], [0])))
+    return s * dtau_fs / (np.pi * hbar * area_nm2)
+
+
 def energies_grid(n_energies: int, e_scale: float, frac: float = 0.95) -> np.ndarray:
     """Uniform energies on [-frac E_s, frac E_s] (eV)."""
     return np.linspace(-frac * e_scale, frac * e_scale, n_energies)

@@ -768,6 +768,39 @@ kpm_status msd_impl(kpm_system *sys, int vshift, const void *phi_v, int nsteps, 
     return KPM_OK;
 }
 
+// Fourier moments of Alg. 4: F_n = <phi_L| U(n dtau) |phi_R>, n = -nm .. nm,
+// reduced into sys->dmom[(s * R + r) * (2 nm + 1) + nm + n].
+template <typename V>
+kpm_status fourier_impl(kpm_system *sys, int vshift, const void *phil_v, const void *phir_v,
+                        int nm, double dtau, int np, double *f) {
+    KPM_TRY(sys->ensure_vecs(4, vshift));
+    const int64_t per_r = 2 * (int64_t)nm + 1;
+    const size_t elems = (size_t)sys->nseg * ((size_t)1 << vshift) * per_r;
+    KPM_TRY(sys->ensure_dmom(elems));
+    kpm::Sweep sw;
+    KPM_TRY(sys->sweep(vshift, &sw));
+    KPM_TRY(sys->ensure_partial(1, sw.nwg, 1 << vshift));
+    V *a = (V *)sys->vecs[0], *b = (V *)sys->vecs[1], *psi = (V *)sys->vecs[2],
+      *psi2 = (V *)sys->vecs[3];
+    const V *phil = (const V *)phil_v, *phir = (const V *)phir_v;
+    hipStream_t s = sys->stream;
+    auto dot_into = [&](const V *x, int64_t idx) {
+        kpm::launch_dot<V>(sw, phil, x, sys->partial, 0, s);
+        kpm::launch_reduce(sys->partial, sw, 1, sys->dmom, per_r, idx, s);
+    };
+    dot_into(phir, nm);
+    for (int dir = +1; dir >= -1; dir -= 2) {
+        const V *cur = phir;
+        for (int k = 1; k <= nm; ++k) {
+            KPM_TRY(run_evolve<V>(sys, vshift, cur, psi2, nullptr, dtau, dir, np, a, b));
+            std::swap(psi, psi2);
+            cur = psi;
+            dot_into(cur, nm + dir * k);
+        }
+    }
+    return finish_moments(sys, elems, (double2 *)f);
+}
+
 template <typename V>
 kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_launch *best) {
     KPM_TRY(sys->ensure_vecs(2, vs));
@@ -1150,6 +1183,59 @@ kpm_status kpm_msd(kpm_system *sys, int n_vec, const void *phi, int n_steps, dou
     return sys->prec == KPM_FP64
                ? msd_impl<double2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, out)
                : msd_impl<float2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, out);
+}
+
+kpm_status kpm_fourier_moments(kpm_system *sys, int n_vec, const void *phi_l, const void *phi_r,
+                               int n_moments, double dtau_fs, int n_bessel, double *f) {
+    int vs;
+    KPM_TRY(check_common(sys, n_vec, &vs));
+    if (!phi_l || !phi_r || !f) return fail(KPM_ERR_INVALID, "null buffer");
+    if (n_moments < 0) return fail(KPM_ERR_INVALID, "n_moments must be >= 0");
+    if (n_bessel < 2) return fail(KPM_ERR_INVALID, "n_bessel must be >= 2");
+    if (!std::isfinite(dtau_fs) || dtau_fs < 0) return fail(KPM_ERR_INVALID, "dtau_fs");
+    DeviceGuard g(sys->device);
+    return sys->prec == KPM_FP64
+               ? fourier_impl<double2>(sys, vs, phi_l, phi_r, n_moments, dtau_fs, n_bessel, f)
+               : fourier_impl<float2>(sys, vs, phi_l, phi_r, n_moments, dtau_fs, n_bessel, f);
+}
+
+kpm_status kpm_ftm_sum(int n_rows, int n_moments, const double *f, int n_energies,
+                       const double *energies, double dtau_fs, double area_nm2, int hanning,
+                       void *hip_stream, double *out) {
+    if (n_rows < 1 || n_moments < 0 || n_energies < 1) return fail(KPM_ERR_INVALID, "sizes");
+    if (!f || !energies || !out) return fail(KPM_ERR_INVALID, "null buffer");
+    if (!(dtau_fs > 0) || !(area_nm2 > 0)) return fail(KPM_ERR_INVALID, "dtau / area");
+    const int nf = 2 * n_moments + 1;
+    std::vector<double> w(nf), theta(n_energies);
+    for (int j = 0; j < nf; ++j)     // Hanning window, Eq. 28
+        w[j] = hanning ? 0.5 * (1.0 + std::cos(kPi * (j - n_moments) / (n_moments + 1.0))) : 1.0;
+    for (int k = 0; k < n_energies; ++k) {
+        if (!std::isfinite(energies[k])) return fail(KPM_ERR_INVALID, "energy %d", k);
+        theta[k] = energies[k] * dtau_fs / kHbar;
+    }
+    const double pref = dtau_fs / (kPi * kHbar * area_nm2);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t nin = (size_t)n_rows * nf, nout = (size_t)n_rows * n_energies;
+    double *buf = nullptr;
+    const size_t total = 2 * nin + nf + (size_t)n_energies + nout;
+    KPM_HIP(hipMalloc(&buf, total * sizeof(double)));
+    double *dfv = buf, *dw = dfv + 2 * nin, *dth = dw + nf, *dout = dth + n_energies;
+    kpm_status st = KPM_OK;
+    auto chk = [&](hipError_t e) {
+        if (e != hipSuccess && st == KPM_OK) st = fail(KPM_ERR_DEVICE, "ftm_sum: %s", hipGetErrorString(e));
+    };
+    chk(hipMemcpyAsync(dfv, f, 2 * nin * sizeof(double), hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(dw, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(dth, theta.data(), theta.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    if (st == KPM_OK) {
+        kpm::launch_ftm_sum((const double2 *)dfv, n_rows, n_moments, dw, dth, n_energies, pref,
+                            dout, s);
+        chk(hipGetLastError());
+    }
+    chk(hipMemcpyAsync(out, dout, nout * sizeof(double), hipMemcpyDeviceToHost, s));
+    chk(hipStreamSynchronize(s));
+    (void)hipFree(buf);
+    return st;
 }
 
 kpm_status kpm_kpm_sum(int n_rows, int n_moments, const double *moments, int n_energies,

@@ -107,6 +107,16 @@ template <typename V>
 void launch_apply_d(const Ell &h, const Sweep &sw, const V *x, V *y, Coef alpha,
                     hipStream_t s);
 
+// partial[slot] = <a|b> per work-group and vector.
+template <typename V>
+void launch_dot(const Sweep &sw, const V *a, const V *b, double2 *partial, int slot,
+                hipStream_t s);
+
+// out[t][k] = pref sum_n w_n Re[exp(i theta_k n) f[t][n]], n = -nm .. nm
+// (Fourier sum, Eq. 22-24).
+void launch_ftm_sum(const double2 *f, int rows, int nm, const double *w, const double *theta,
+                    int ne, double pref, double *out, hipStream_t s);
+
 // dst[(seg * R + r) * stride_r + offset + j] = sum over the segment's groups g
 // of partial[j][g][r], j < slots, in a fixed order (deterministic).
 void launch_reduce(const double2 *partial, const Sweep &sw, int slots, double2 *dst,

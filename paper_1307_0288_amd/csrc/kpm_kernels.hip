@@ -455,6 +455,40 @@ __global__ __launch_bounds__(kBlock) void k_apply_d(Ell h, Sweep sw, const V *x,
     KPM_SWEEP_END
 }
 
+// partial[slot] = <a|b> per work-group (and vector).
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_dot(Sweep sw, const V *__restrict__ a,
+                                                const V *__restrict__ b,
+                                                double2 *__restrict__ partial, int slot) {
+    double2 s0 = make_double2(0.0, 0.0);
+    const Walk wk = walk_of(sw);
+    for (int64_t blk = wk.b0 + wk.loc; blk < wk.b1; blk += wk.nloc) {
+        const int64_t e = wk.e0 + blk * kBlock + threadIdx.x;
+        if (e < wk.e1) s0 = cdot_acc(s0, ld_nt(a + e), ld_nt(b + e));
+    }
+    const int64_t r = (int64_t)1 << sw.vshift;
+    block_sum(s0, sw.vshift, partial + ((int64_t)slot * sw.nwg + blockIdx.x) * r);
+}
+
+// One thread per (row, energy): Hanning-windowed Fourier sum (Eq. 22-24),
+// sum_n w_n Re[exp(i theta_k n) F_n] with theta_k = E_k dtau / hbar.
+__global__ __launch_bounds__(kBlock) void k_ftm_sum(const double2 *__restrict__ f, int rows,
+                                                    int nm, const double *__restrict__ w,
+                                                    const double *__restrict__ theta, int ne,
+                                                    double pref, double *__restrict__ out) {
+    const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (id >= (int64_t)rows * ne) return;
+    const int t = (int)(id / ne), k = (int)(id % ne);
+    const double2 *c = f + (int64_t)t * (2 * nm + 1);
+    double acc = 0.0;
+    for (int j = 0; j <= 2 * nm; ++j) {
+        double sn, cs;
+        sincos(theta[k] * (double)(j - nm), &sn, &cs);
+        acc = fma(w[j], fma(cs, c[j].x, -sn * c[j].y), acc);
+    }
+    out[id] = pref * acc;
+}
+
 // One block per (slot, vector, segment): sums the segment's group partials
 // in a fixed order.
 __global__ __launch_bounds__(kBlock) void k_reduce(const double2 *__restrict__ partial,
@@ -581,6 +615,20 @@ void launch_reduce(const double2 *partial, const Sweep &sw, int slots, double2 *
                        partial, sw, dst, stride_r, offset);
 }
 
+template <typename V>
+void launch_dot(const Sweep &sw, const V *a, const V *b, double2 *partial, int slot,
+                hipStream_t s) {
+    hipLaunchKernelGGL((k_dot<V>), dim3(sw.nwg), dim3(kBlock), 0, s, sw, a, b, partial, slot);
+}
+
+void launch_ftm_sum(const double2 *f, int rows, int nm, const double *w, const double *theta,
+                    int ne, double pref, double *out, hipStream_t s) {
+    const int64_t total = (int64_t)rows * ne;
+    const int blocks = (int)((total + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_ftm_sum, dim3(blocks), dim3(kBlock), 0, s, f, rows, nm, w, theta, ne,
+                       pref, out);
+}
+
 void launch_kpm_sum(const double *mom, int rows, int nm, const double *w, const double *eps,
                     const double *pref, int ne, double *out, hipStream_t s) {
     const int64_t total = (int64_t)rows * ne;
@@ -600,7 +648,9 @@ void launch_kpm_sum(const double *mom, int rows, int nm, const double *w, const 
                                           const V *, V *, const V *, const V *, V *, V *,   \
                                           V *, Coef, Coef, hipStream_t);                    \
     template void launch_apply_d<V>(const Ell &, const Sweep &, const V *, V *, Coef,       \
-                                    hipStream_t);
+                                    hipStream_t);                                           \
+    template void launch_dot<V>(const Sweep &, const V *, const V *, double2 *, int,        \
+                                hipStream_t);
 
 KPM_INSTANTIATE(double2)
 KPM_INSTANTIATE(float2)

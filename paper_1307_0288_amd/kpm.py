@@ -27,7 +27,8 @@ BOND_NM = 0.142
 ABI_SYMBOLS = ("kpm_build_graphene", "kpm_system_create", "kpm_system_destroy",
                "kpm_system_set_stream", "kpm_system_n_sites", "kpm_batch_create",
                "kpm_system_n_samples", "kpm_system_offsets", "kpm_moments", "kpm_evolve",
-               "kpm_evolve_x", "kpm_vac", "kpm_msd", "kpm_kpm_sum", "kpm_sigma_gk",
+               "kpm_evolve_x", "kpm_vac", "kpm_msd", "kpm_fourier_moments", "kpm_ftm_sum",
+               "kpm_kpm_sum", "kpm_sigma_gk",
                "kpm_sigma_e1", "kpm_sigma_e2", "kpm_set_launch", "kpm_get_launch",
                "kpm_autotune", "kpm_set_graphs", "kpm_set_timing", "kpm_get_stats",
                "kpm_reset_stats",
@@ -84,6 +85,9 @@ def lib():
             "kpm_vac": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, C.c_int, dp],
             "kpm_msd": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, C.c_int, dp],
             "kpm_kpm_sum": [C.c_int, C.c_int, dp, C.c_int, dp, C.c_double, C.c_double,
+                            C.c_int, vp, dp],
+            "kpm_fourier_moments": [vp, C.c_int, vp, vp, C.c_int, C.c_double, C.c_int, dp],
+            "kpm_ftm_sum": [C.c_int, C.c_int, dp, C.c_int, dp, C.c_double, C.c_double,
                             C.c_int, vp, dp],
             "kpm_sigma_gk": [C.c_int, C.c_int, dp, C.c_double, dp],
             "kpm_sigma_e1": [C.c_int, C.c_int, dp, C.c_double, dp],
@@ -146,6 +150,19 @@ def kpm_kpm_sum(moments, energies_ev, e_scale: float, area_nm2: float, jackson: 
     out = np.empty((mom.shape[0], en.shape[0]))
     _check(lib().kpm_kpm_sum(mom.shape[0], mom.shape[1], _dp(mom), en.shape[0], _dp(en),
                              e_scale, area_nm2, int(bool(jackson)), _stream(), _dp(out)))
+    return out[0] if squeeze else out
+
+
+def kpm_ftm_sum(fmom, energies_ev, dtau_fs: float, area_nm2: float, hanning: bool = True):
+    """Fourier (FTM) sum of Eq. 22-24 on the device: F [rows, 2 N_m + 1] -> [rows, K]."""
+    f = np.ascontiguousarray(fmom, dtype=np.complex128)
+    squeeze = f.ndim == 1
+    f = f.reshape(-1, f.shape[-1])
+    nm = (f.shape[1] - 1) // 2
+    en = np.ascontiguousarray(energies_ev, dtype=np.float64).reshape(-1)
+    out = np.empty((f.shape[0], en.shape[0]))
+    _check(lib().kpm_ftm_sum(f.shape[0], nm, _dp(f.view(np.float64)), en.shape[0], _dp(en),
+                             dtau_fs, area_nm2, int(bool(hanning)), _stream(), _dp(out)))
     return out[0] if squeeze else out
 
 
@@ -304,6 +321,21 @@ def kpm_moments(sys: System, phi_l, phi_r, n_moments: int) -> np.ndarray:
     out = np.empty((sys.n_samples, nv, n_moments, 2))
     sys._sync_stream()
     _check(lib().kpm_moments(sys.handle, nv, pl, pr, n_moments, _dp(out)))
+    return sys._shape(out[..., 0] + 1j * out[..., 1])
+
+
+def kpm_fourier_moments(sys: System, phi_l, phi_r, n_moments: int, dtau_fs: float,
+                        n_bessel: int) -> np.ndarray:
+    """F_n = <phi_L|U(n dtau)|phi_R>, n = -N_m .. N_m (Alg. 4): complex128
+    [n_vec, 2 N_m + 1]; leading sample axis for a batch."""
+    pl, nv = sys._state(phi_l, "phi_l")
+    pr, nv2 = sys._state(phi_r, "phi_r")
+    if nv != nv2:
+        raise ValueError("phi_l and phi_r differ in n_vec")
+    out = np.empty((sys.n_samples, nv, 2 * n_moments + 1, 2))
+    sys._sync_stream()
+    _check(lib().kpm_fourier_moments(sys.handle, nv, pl, pr, n_moments, dtau_fs, n_bessel,
+                                     _dp(out)))
     return sys._shape(out[..., 0] + 1j * out[..., 1])
 
 

@@ -27,6 +27,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--copy-mib", type=int, default=512)
     ap.add_argument("--copies", type=int, default=3)
+    ap.add_argument("--launch", default="",
+                    help="groups_per_cu,ilp,streaming,compact (default: the library's)")
     args = ap.parse_args()
 
     import torch
@@ -41,6 +43,10 @@ def main():
     sysg = kp.graphene_system(p["nx"], p["ny"], "sheet", p["t"], ons, act, p["e_scale"],
                               args.precision)
     phi = sysg.upload(ki.random_phase(n, args.n_vec, 3000, act))
+    if args.launch:
+        g, ilp, nt, cp = (int(x) for x in args.launch.split(","))
+        kp.kpm_set_launch(sysg, args.n_vec, g, ilp, nt, cp)
+    print(f"launch shape: {kp.kpm_get_launch(sysg, args.n_vec)}", flush=True)
     mu = kp.kpm_moments(sysg, phi, phi, args.moments)
     print(f"moments: n={n} n_vec={args.n_vec} {args.precision} C_0={mu[0, 0].real:.1f}",
           flush=True)

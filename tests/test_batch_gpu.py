@@ -169,3 +169,16 @@ def test_graph_replays_match_eager():
     for rep in range(3):
         assert np.array_equal(kp.kpm_moments(single, ds, ds, 500), ref1), rep
         torch.cuda.synchronize()
+
+
+def test_batch_fourier_moments_per_sample(batch2):
+    cases, sysg, phis, lats = batch2
+    d = sysg.upload(np.concatenate(phis))
+    nm, dtau = 6, 0.2
+    got = kp.kpm_fourier_moments(sysg, d, d, nm, dtau, 20)
+    for s, (c, lat) in enumerate(zip(cases, lats)):
+        for r in range(2):
+            ref = oracle.fourier_moments(lat, c["e_scale"], phis[s][:, r], phis[s][:, r], nm,
+                                         dtau, 20)
+            scale = max(np.vdot(phis[s][:, r], phis[s][:, r]).real, 1.0)
+            assert rel_err(got[s, r], ref, scale) < 1e-10, (s, r)

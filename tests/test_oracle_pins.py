@@ -394,3 +394,64 @@ def test_einstein_equals_green_kubo_exact_trace():
     gk = oracle.sigma_gk(rv, dt)
     scale = np.abs(gk).max()
     assert np.max(np.abs(e1[1:-1] - gk[1:-1])) < 2e-3 * scale
+
+
+# --------------------------------------------------------------------------- Fourier moments
+
+def test_fourier_moments_match_eigendecomposition():
+    """F_n = sum_a conj(<a|L>) <a|R> exp(-i e_a x n), x = E_s dtau / hbar (Eq. 25)."""
+    lat = _lat(12, 6, w=1.0, vac=0.05, seed=12)
+    es = _escale(lat)
+    phl = ki.random_phase(lat.n, 1, 3000, lat.active)[:, 0]
+    phr = ki.random_phase(lat.n, 1, 3100, lat.active)[:, 0]
+    nm, dtau = 12, np.pi * HBAR / es          # Bessel argument pi (Sec. 4.2)
+    got = oracle.fourier_moments(lat, es, phl, phr, nm, dtau, 40)
+    idx, ev, q = _active_eig(lat, es)
+    cl, cr = q.T @ phl[idx], q.T @ phr[idx]
+    n = np.arange(-nm, nm + 1)
+    ref = np.exp(-1j * np.outer(n, ev) * np.pi) @ (np.conj(cl) * cr)
+    assert np.max(np.abs(got - ref)) < 1e-11 * np.linalg.norm(phl) * np.linalg.norm(phr)
+    same = oracle.fourier_moments(lat, es, phl, phl, nm, dtau, 40)
+    assert np.allclose(same[::-1], np.conj(same), atol=1e-10)     # F_-n = conj(F_n)
+
+
+def test_hanning_window_and_ftm_normalisation():
+    """The Hanning-windowed Fourier DOS integrates to 2N/Omega over one period of
+    the energy axis (only n = 0 survives), and w_0 = 1 (Eq. 28)."""
+    lat = _lat(8, 4, w=1.0, seed=1)
+    es = _escale(lat)
+    nm = 30
+    dtau = np.pi * HBAR / es                   # period of E: 2 pi hbar / dtau = 2 E_s
+    ftot = np.zeros(2 * nm + 1, complex)
+    for k in range(lat.n):
+        e = np.zeros(lat.n, complex)
+        e[k] = 1.0
+        ftot += oracle.fourier_moments(lat, es, e, e, nm, dtau, 40)
+    w = oracle.hanning(nm)
+    assert w[nm] == 1.0 and np.allclose(w, w[::-1])
+    kq = 4 * nm + 7                            # uniform periodic grid: exact for |n| <= nm
+    en = -es + 2 * es * np.arange(kq) / kq
+    rho = oracle.ftm_sum(ftot, en, dtau, lat.area_nm2)
+    integral = np.sum(rho) * 2 * es / kq
+    assert abs(integral - 2 * lat.n / lat.area_nm2) < 1e-10 * lat.n / lat.area_nm2
+
+
+def test_ftm_and_kpm_dos_agree():
+    """Sec. 4.2: the FTM and KPM give consistent DOS curves; with the exact
+    trace the integrated densities of states agree across the band."""
+    lat = _lat(16, 8, w=1.0, seed=2)
+    es = _escale(lat)
+    nm_k, nm_f = 300, 150
+    dtau = np.pi * HBAR / es
+    mu = np.zeros(nm_k)
+    ftot = np.zeros(2 * nm_f + 1, complex)
+    ev = np.linalg.eigvalsh(oracle.dense_h(lat)) / es
+    mu = np.array([np.sum(np.cos(m * np.arccos(ev))) for m in range(nm_k)])
+    n = np.arange(-nm_f, nm_f + 1)
+    ftot = np.exp(-1j * np.outer(n, ev) * np.pi).sum(axis=1)   # exact-trace F_n
+    en = np.linspace(-0.95 * es, 0.95 * es, 4001)
+    rk = oracle.dos(mu, en, es, lat.area_nm2)
+    rf = oracle.ftm_sum(ftot, en, dtau, lat.area_nm2)
+    ck = np.cumsum(rk) * (en[1] - en[0]) * lat.area_nm2 / 2
+    cf = np.cumsum(rf) * (en[1] - en[0]) * lat.area_nm2 / 2
+    assert np.max(np.abs(ck - cf)) < 0.02 * lat.n

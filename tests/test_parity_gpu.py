@@ -308,3 +308,31 @@ def test_launch_shapes(n_vec, precision):
     assert best["groups_per_cu"] in (4, 8, 16) and best["ilp"] in (1, 2, 4)
     assert best["streaming"] in (0, 1) and best["compact"] in (0, 1)
     assert kp.kpm_get_launch(sysg, n_vec) == best
+
+
+# ------------------------------------------------------------------ Fourier moments (FTM)
+@pytest.mark.parametrize("geometry,nx,ny,vac,n_vec", [("sheet", 64, 32, 0.02, 1),
+                                                       ("zgnr", 30, 7, 0.0, 2)])
+def test_fourier_moments(geometry, nx, ny, vac, n_vec):
+    _need_gpu()
+    c = recipe(geometry, nx, ny, w=1.0, vac=vac, seed=13)
+    lat = oracle_lattice(c)
+    sysg = gpu_system(c)
+    pl = phases(c, n_vec, 3000)
+    pr = phases(c, n_vec, 3500)
+    nm, dtau = 24, np.pi * HBAR / c["e_scale"]
+    got = kp.kpm_fourier_moments(sysg, sysg.upload(pl), sysg.upload(pr), nm, dtau, 25)
+    for r in range(n_vec):
+        ref = oracle.fourier_moments(lat, c["e_scale"], pl[:, r], pr[:, r], nm, dtau, 25)
+        assert rel_err(got[r], ref, np.linalg.norm(pl[:, r]) * np.linalg.norm(pr[:, r])) < 1e-10
+
+
+def test_ftm_dos_device_sum(small):
+    c, lat, sysg = small
+    phi = phases(c, 1, 3000)
+    nm, dtau = 60, np.pi * HBAR / c["e_scale"]
+    f = oracle.fourier_moments(lat, c["e_scale"], phi[:, 0], phi[:, 0], nm, dtau, 25)
+    en = oracle.energies_grid(777, c["e_scale"])
+    ref = oracle.ftm_sum(f, en, dtau, lat.area_nm2)
+    got = kp.kpm_ftm_sum(f, en, dtau, lat.area_nm2)
+    assert rel_err(got, ref) < 1e-12
