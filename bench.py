@@ -18,7 +18,6 @@ the library on its stream, and the oracle's CPU rate on a bounded sample.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -30,41 +29,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 import kpm_inputs as ki  # noqa: E402
+from paper_1307_0288_amd.profile_run import measured_traffic  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "moment_step_fp64_paper_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1307_0288_amd", "csrc", "kpm_kernels.hip")
+TRAFFIC_FILE_DBL = os.path.join(ROOT, "profiles", "moment_step_doubled_fp64_paper_traffic.json")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_sha() -> str:
-    """Hash of the source the moment step is compiled from: the kernel file up to
-    the first kernel after it, plus its launcher (edits elsewhere in the file do
-    not change the moment step)."""
-    with open(KERNEL_SRC) as f:
-        t = f.read()
-    head = t[:t.index("template <typename V, bool FIRST>\n__global__ __launch_bounds__(kBlock) "
-                      "void k_evolve_step(")]
-    a = t.index("template <typename V, int ILP, bool NT>\nstatic void launch_step_shape(")
-    b = t.index("template <typename V>\nvoid launch_evolve_step(")
-    return hashlib.sha256((head + t[a:b]).encode()).hexdigest()[:16]
-
-
-def measured_traffic(step_rows: int, launch: dict):
-    """HBM bytes per moment-step launch from committed rocprofv3 counters,
-    or None when they are absent or were taken on another kernel version."""
-    try:
-        with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if t.get("kernel_sha") != kernel_sha() or t.get("step_rows") != step_rows \
-            or t.get("launch_shape") != launch:
-        return None
-    return t.get("bytes_per_launch")
+def step_kernel_name(v: str, launch: dict, dbl: bool) -> str:
+    """Instantiation of the moment step for a graphene system (width 3, uniform
+    hopping, float-exact on-site terms) under a launch shape."""
+    form = "kFormC3F" if launch["compact"] else "kFormL3F"
+    return (f"k_moment_step<{v},{launch['ilp']},{'true' if launch['streaming'] else 'false'},"
+            f"{form},{'true' if dbl else 'false'}>")
 
 
 def cpu_baseline(p, lat_args, n_moments: int):
@@ -91,10 +72,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-moments", type=int, default=800,
                     help="moments in the oracle's CPU-baseline sample (0 skips it)")
-    ap.add_argument("--workload", default="paper", choices=["paper", "batched", "ragged"],
+    ap.add_argument("--workload", default="paper",
+                    choices=["paper", "batched", "ragged", "doubled"],
                     help="paper: plain FP64, one vector (default); batched: 64 vectors, "
                          "FP32 states vs FP64; ragged: 32 samples of 1e4..1e6 sites in one "
-                         "launch per step")
+                         "launch per step; doubled: DOS and MSD moments in the doubling "
+                         "form vs the direct form, as moments/s")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -111,6 +94,8 @@ def main():
         return batched(args)
     if args.workload == "ragged":
         return ragged(args)
+    if args.workload == "doubled":
+        return doubled(args)
 
     p = ki.sheet_config("paper")
     n = p["nx"] * p["ny"]
@@ -149,7 +134,7 @@ def main():
     bytes_launch = st["step_bytes"]
     bpu = bytes_launch / st["step_rows"]
     achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
-    traffic = measured_traffic(st["step_rows"], launch)
+    traffic = measured_traffic(TRAFFIC_FILE, st["step_rows"], launch)
 
     cpu = None
     if args.cpu_moments > 0:
@@ -174,14 +159,91 @@ def main():
                                "x 40 Bessel terms, dt=hbar/|t|",
                    "n_sites": n, "n_vec": 1, "n_moments": nm, "n_steps": ns,
                    "n_bessel": nb, "site_updates_per_step": st["site_updates"] // args.steps},
-        "roofline": {"kernel": f"k_moment_step<double2,{launch['ilp']},"
-                               f"{'true' if launch['streaming'] else 'false'}>", "bound": "hbm",
+        "roofline": {"kernel": step_kernel_name("double2", launch, False), "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_site_update": round(bpu, 3),
                      "avg_launch_us": round(launch_ms * 1e3, 3),
                      "launches": st["step_launches"], "launch_shape": launch},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def doubled(args):
+    """Moment doubling for phi_L = phi_R on the paper-scale sheet (FP64, one
+    vector): 3000 DOS moments and the 20-step MSD, each in the direct form of
+    Alg. 5 and in the doubling form.  Reported as moments/s (moments of one
+    vector over the whole sheet per second), separately from the headline."""
+    import torch
+    import paper_1307_0288_amd as kp
+    p = ki.sheet_config("paper")
+    n = p["nx"] * p["ny"]
+    act = ki.vacancy_mask(n, p["vac"], 2000)
+    ons = ki.anderson_onsite(n, p["w"], 1000)
+    sysg = kp.graphene_system(p["nx"], p["ny"], "sheet", p["t"], ons, act, p["e_scale"], "fp64")
+    phi = sysg.upload(ki.random_phase(n, 1, 3000, act))
+    nm, ns, nb, dt = p["n_moments"], p["n_steps"], p["n_bessel"], p["dt_fs"]
+    launch = kp.kpm_autotune(sysg, phi, 50)
+    log(f"autotuned launch shape: {launch}")
+    calls = {
+        "dos_direct": lambda: kp.kpm_moments(sysg, phi, phi, nm),
+        "dos_doubled": lambda: kp.kpm_moments_doubled(sysg, phi, nm),
+        "msd_direct": lambda: kp.kpm_msd(sysg, phi, ns, dt, nb, nm),
+        "msd_doubled": lambda: kp.kpm_msd_doubled(sysg, phi, ns, dt, nb, nm),
+    }
+    res, outs = {}, {}
+    for name, fn in calls.items():
+        for _ in range(args.warmup):
+            fn()
+        kp.kpm_reset_stats(sysg)
+        kp.kpm_set_timing(sysg, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            outs[name] = fn()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / args.steps
+        st = kp.kpm_get_stats(sysg)
+        kp.kpm_set_timing(sysg, False)
+        launch_ms = st["step_ms"] / max(st["step_launches"], 1)
+        n_mom = nm * (ns if name.startswith("msd") else 1)
+        res[name] = {"ms": round(el * 1e3, 3), "moments_per_s": round(n_mom / el, 1),
+                     "step_launch_us": round(launch_ms * 1e3, 3),
+                     "step_bytes": st["step_bytes"],
+                     "step_gbs": round(st["step_bytes"] / (launch_ms * 1e-3) / 1e9, 1)}
+        log(f"{name}: {res[name]}")
+    n_act = float(np.count_nonzero(act))
+    err_dos = float(np.max(np.abs(outs["dos_doubled"] - outs["dos_direct"])) / n_act)
+    m_ref = outs["msd_direct"]
+    err_msd = float(np.max(np.abs(outs["msd_doubled"] - m_ref)) / np.max(np.abs(m_ref)))
+    dd = res["dos_doubled"]
+    out = {
+        "metric": "moments/s (DOS moments of one vector over the 4M-site sheet, doubling form)",
+        "value": dd["moments_per_s"],
+        "unit": "moments/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dd["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "graphene sheet 2828x1414 sites (3998792), 0.5% vacancies, "
+                               "W=0.1 eV, 1 random-phase vector, 3000 moments; MSD 20 steps x "
+                               "40 Bessel terms, dt=hbar/|t|",
+                   "n_sites": n, "n_moments": nm, "launch_shape": launch},
+        "roofline": {"kernel": step_kernel_name("double2", launch, True), "bound": "hbm",
+                     "achieved": dd["step_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(dd["step_gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(TRAFFIC_FILE_DBL, n, launch),
+                     "bytes_per_launch": dd["step_bytes"],
+                     "avg_launch_us": dd["step_launch_us"]},
+        "forms": res,
+        "max_rel_diff_vs_direct": {"dos": err_dos, "msd": err_msd},
+        "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 

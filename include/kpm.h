@@ -161,6 +161,20 @@ kpm_status kpm_moments(kpm_system *sys, int n_vec, const void *phi_l,
                        const void *phi_r, int n_moments, double *mu);
 
 /*
+ * The moments of kpm_moments for phi_l = phi_r = phi (the DOS of Eq. 29), from
+ * half the recursion steps: with phi_n = T_n(H~) phi, the product identities
+ * T_{2n} = 2 T_n^2 - T_0 and T_{2n+1} = 2 T_{n+1} T_n - T_1 of the Chebyshev
+ * polynomials (the KPM review the paper cites for Eq. 29-35) give
+ * C_{2n} = 2 <phi_n|phi_n> - C_0 and C_{2n+1} = 2 <phi_n|phi_{n+1}> - C_1.
+ * This is not the order of Alg. 5 (same values up to rounding, about
+ * ceil(n_moments / 2) recursion steps instead of n_moments - 1, and phi is
+ * read once per step instead of twice).  phi: device states; mu: host output
+ * [n_vec][n_moments][2] as for kpm_moments.  Synchronises the stream.
+ */
+kpm_status kpm_moments_doubled(kpm_system *sys, int n_vec, const void *phi, int n_moments,
+                               double *mu);
+
+/*
  * phi <- U(sign * dt) phi, U(t) = exp(-i H t / hbar), by the Chebyshev-Bessel
  * expansion with n_bessel terms (Eq. 36, Alg. 6); sign = +1 or -1 (U(-dt) =
  * U(dt)^dagger).  phi: device state, in place.  n_bessel >= 2.  Asynchronous.
@@ -195,6 +209,14 @@ kpm_status kpm_vac(kpm_system *sys, int n_vec, const void *phi, int n_steps,
  */
 kpm_status kpm_msd(kpm_system *sys, int n_vec, const void *phi, int n_steps,
                    double dt_fs, int n_bessel, int n_moments, double *out);
+
+/*
+ * kpm_msd with the moments of each [X, U(t_k)] phi taken in the doubling form
+ * of kpm_moments_doubled (the bra and ket of Eq. 44 are the same state).  Same
+ * arguments and output.
+ */
+kpm_status kpm_msd_doubled(kpm_system *sys, int n_vec, const void *phi, int n_steps,
+                           double dt_fs, int n_bessel, int n_moments, double *out);
 
 /*
  * Fourier moments of the FTM (Alg. 4, Eq. 25-27):
@@ -248,6 +270,53 @@ kpm_status kpm_sigma_e1(int n_times, int n_energies, const double *rho_msd,
                         double dt_fs, double *out);
 kpm_status kpm_sigma_e2(int n_times, int n_energies, const double *rho_msd,
                         double dt_fs, double *out);
+
+/*
+ * Transport quantities on the host (Sec. 5), all arrays [n_times][n_energies]
+ * at t_k = k dt unless stated; lengths and widths in nm, conductivities and
+ * conductances in e^2/h.  Invalid sizes or null pointers give
+ * KPM_ERR_INVALID; undefined entries are NaN as stated.
+ *
+ * kpm_length: L(E, t) = 2 sqrt(Delta X^2(E, t)) (Eq. 50) with the per-state
+ *   MSD Delta X^2 = rho_msd / rho (rho_msd: KPM sum of MSD moments, rho:
+ *   [n_energies] DOS).  NaN where rho = 0 or Delta X^2 < 0.
+ * kpm_conductance: G(E, L) = (W / L(E, t)) sigma(E, t) (Eq. 51, Eq. 59).
+ *   NaN where L <= 0 or is NaN (t = 0).
+ * kpm_ballistic_conductance: G(E) = (W/2) e^2 rho sqrt(v^2) (Eq. 52) with
+ *   v^2 = Delta X^2(E, t_k) / t_k^2 at each t_k > 0, i.e. pi hbar W rho
+ *   sqrt(v^2) in e^2/h.  Row 0 is NaN.
+ * kpm_sigma_sc_max: sigma_sc(E) = max over t_k > 0 of sigma(E, t_k) (Eq. 53).
+ *   n_times >= 2; out [n_energies].
+ * kpm_sigma_sc_average: sigma_sc(E) = (1/(t2 - t1)) int_{t1}^{t2} sigma dt
+ *   (Eq. 55) by the trapezoid rule, t1 = k1 dt, t2 = k2 dt,
+ *   0 <= k1 < k2 < n_times; out [n_energies].
+ * kpm_pade_fit: [m/n] Pade approximant of Eq. 58,
+ *   y(t) ~ sum_{j=0}^{m} a_j t^j / (1 + sum_{k=1}^{n} b_k t^k) (the k = 0
+ *   term of the printed denominator is taken as absent: it duplicates the 1),
+ *   by linear least squares on y (1 + sum b_k t^k) = sum a_j t^j over n_pts
+ *   points (Householder QR in t / max|t|).  a: [m+1], b: [n] host outputs.
+ *   n_pts >= m + n + 1, m + n < 32; KPM_ERR_NUMERIC if the system is rank
+ *   deficient.
+ * kpm_pade_eval: value (and, if deriv is not NULL, d/dt) of that approximant
+ *   at n_pts times; sigma_E1 of a fitted MSD is pi hbar rho times deriv.
+ * kpm_typical_conductance: G_typ(E) = exp(<ln G(E)>) over n_real
+ *   realisations (Eq. 60); g: [n_real][n_energies], all > 0; out [n_energies].
+ */
+kpm_status kpm_length(int n_times, int n_energies, const double *rho_msd, const double *rho,
+                      double *out);
+kpm_status kpm_conductance(int n_times, int n_energies, const double *sigma,
+                           const double *length_nm, double width_nm, double *out);
+kpm_status kpm_ballistic_conductance(int n_times, int n_energies, const double *rho_msd,
+                                     const double *rho, double dt_fs, double width_nm,
+                                     double *out);
+kpm_status kpm_sigma_sc_max(int n_times, int n_energies, const double *sigma, double *out);
+kpm_status kpm_sigma_sc_average(int n_times, int n_energies, const double *sigma, int k1,
+                                int k2, double *out);
+kpm_status kpm_pade_fit(int n_pts, const double *t, const double *y, int m, int n, double *a,
+                        double *b);
+kpm_status kpm_pade_eval(int m, int n, const double *a, const double *b, int n_pts,
+                         const double *t, double *value, double *deriv);
+kpm_status kpm_typical_conductance(int n_real, int n_energies, const double *g, double *out);
 
 /*
  * Launch shape of the Chebyshev moment step for a given n_vec: work-groups

@@ -3,7 +3,8 @@
     python -m paper_1307_0288_amd.build      (or build() from Python)
 
 Every call recompiles.  The library is the kernels (csrc/kpm_kernels.hip)
-plus the host driver and C ABI (csrc/kpm_host.cpp, include/kpm.h).
+plus the host driver and C ABI (csrc/kpm_host.cpp, csrc/kpm_transport.cpp,
+include/kpm.h).
 """
 from __future__ import annotations
 
@@ -18,7 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libkpm.so")
 OBJDIR = os.path.join(PKG, "_build")
-SOURCES = ["kpm_kernels.hip", "kpm_host.cpp"]
+SOURCES = ["kpm_kernels.hip", "kpm_host.cpp", "kpm_transport.cpp"]
 ARCH = "gfx950"
 
 

@@ -1,0 +1,9 @@
+// Error reporting shared by the host translation units of the C ABI: the
+// message is returned by kpm_last_error() on the calling thread.
+#pragma once
+
+#include "kpm.h"
+
+namespace kpm_detail {
+kpm_status set_error(kpm_status st, const char *msg);
+}

@@ -4,6 +4,7 @@
 // that sequence the gfx950 kernels.
 #include "kpm.h"
 #include "kpm_internal.h"
+#include "kpm_error.h"
 
 #include <hip/hip_runtime.h>
 
@@ -36,6 +37,15 @@ kpm_status fail(kpm_status st, const char *fmt, ...) {
     g_err = buf;
     return st;
 }
+
+}  // namespace
+
+kpm_status kpm_detail::set_error(kpm_status st, const char *msg) {
+    g_err = msg;
+    return st;
+}
+
+namespace {
 
 #define KPM_HIP(call)                                                                \
     do {                                                                             \
@@ -245,13 +255,14 @@ struct kpm_system {
     hipStream_t cap = nullptr;
     struct GraphKey {
         const void *phil, *phir, *a, *b, *partial, *dmom;
-        int nm, vshift, groups, ilp, streaming, compact;
+        int nm, vshift, groups, ilp, streaming, compact, dbl;
         int64_t stride_r, offset;
         bool operator==(const GraphKey &o) const {
             return phil == o.phil && phir == o.phir && a == o.a && b == o.b &&
                    partial == o.partial && dmom == o.dmom && nm == o.nm && vshift == o.vshift &&
                    groups == o.groups && ilp == o.ilp && streaming == o.streaming &&
-                   compact == o.compact && stride_r == o.stride_r && offset == o.offset;
+                   compact == o.compact && dbl == o.dbl && stride_r == o.stride_r &&
+                   offset == o.offset;
         }
     };
     struct GraphEntry {
@@ -303,12 +314,14 @@ struct kpm_system {
     }
 
     // Algorithmic bytes of one moment-step launch: four state accesses per
-    // element (read phi_1, phi_0, phi_L, write phi_0) and the row structure
-    // once per row (neighbours, on-site term, per-slot hopping).
-    int64_t step_bytes(int vshift) const {
+    // element (read phi_1, phi_0, phi_L, write phi_0; three in the doubling
+    // form, which reads no phi_L) and the row structure once per row
+    // (neighbours, on-site term, per-slot hopping).
+    int64_t step_bytes(int vshift, bool dbl = false) const {
         const bool compact = d_pid && launch[vshift].compact;
         const int64_t per_row = (compact ? 1 : 4 * w) + (d_onsf ? 4 : 8) + (d_hop ? 8 * w : 0);
-        return n * (((int64_t)4 * elem_bytes()) << vshift) + n * per_row;
+        const int64_t acc = dbl ? 3 : 4;
+        return n * ((acc * elem_bytes()) << vshift) + n * per_row;
     }
 
     // The sweep of the moment step (and every other kernel) for n_vec =
@@ -499,21 +512,30 @@ kpm::Coef step_coef(const std::vector<double2> &host, const double2 *tab, int np
 }
 
 // ---------------------------------------------------------------- drivers
+// Number of moment slots of a set: one per moment, or in the doubling form
+// (phi_L = phi_R) two per recursion step, rounded up to an even count.
+inline int moment_slots(int nm, bool dbl) { return dbl ? 2 * ((nm + 1) / 2) : nm; }
+
 // Launches of one moment set (Alg. 5) on stream s: the first step, the
 // recursion steps and the ring reductions into sys->dmom.  `events` brackets
-// each uninterrupted run of recursion steps for kpm_set_timing.
+// each uninterrupted run of recursion steps for kpm_set_timing.  In the
+// doubling form phil is phir, recursion step n fills slots 2n and 2n + 1, and
+// a final kernel turns the doubling sums into moments.
 template <typename V>
 kpm_status enqueue_moments(kpm_system *sys, const kpm::Sweep &sw, int ring, hipStream_t s,
-                           bool events, const V *phil, const V *phir, int nm, V *a_buf,
-                           V *b_buf, int64_t stride_r, int64_t offset) {
+                           bool events, bool dbl, const V *phil, const V *phir, int nm,
+                           V *a_buf, V *b_buf, int64_t stride_r, int64_t offset) {
     const kpm::Ell h = sys->ell_for(sys->launch[sw.vshift]);
     // C_0 and C_1 (phi_0 = phi_R, phi_1 = H~ phi_0)
     kpm::launch_moment_step<V>(h, sw, true, phir, nullptr, a_buf, phil, sys->partial, 0, s);
     // phi_m = 2 H~ phi_{m-1} - phi_{m-2}, in place after the first step
     const V *p0 = phir;
     V *p1 = a_buf;
-    for (int c0 = 0; c0 < nm; c0 += ring) {
-        const int c1 = std::min(nm, c0 + ring);
+    bool first = true;
+    const int slots = moment_slots(nm, dbl);
+    const int per_step = dbl ? 2 : 1;
+    for (int c0 = 0; c0 < slots; c0 += ring) {
+        const int c1 = std::min(slots, c0 + ring);
         const int m0 = std::max(c0, 2);
         if (m0 < c1) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -521,51 +543,60 @@ kpm_status enqueue_moments(kpm_system *sys, const kpm::Sweep &sw, int ring, hipS
                 KPM_TRY(sys->event_pair(&e0, &e1));
                 KPM_HIP(hipEventRecord(e0, s));
             }
-            for (int m = m0; m < c1; ++m) {
-                V *out = (m == 2) ? b_buf : const_cast<V *>(p0);
-                kpm::launch_moment_step<V>(h, sw, false, p1, p0, out, phil, sys->partial, m - c0, s);
+            for (int m = m0; m < c1; m += per_step) {
+                V *out = first ? b_buf : const_cast<V *>(p0);
+                if (dbl)
+                    kpm::launch_moment_step_doubled<V>(h, sw, p1, p0, out, sys->partial, m - c0, s);
+                else
+                    kpm::launch_moment_step<V>(h, sw, false, p1, p0, out, phil, sys->partial,
+                                               m - c0, s);
+                first = false;
                 p0 = p1;
                 p1 = out;
             }
             if (events) {
                 KPM_HIP(hipEventRecord(e1, s));
-                sys->stats.step_launches += c1 - m0;
+                sys->stats.step_launches += (c1 - m0) / per_step;
             }
         }
-        kpm::launch_reduce(sys->partial, sw, c1 - c0, sys->dmom, stride_r, offset + c0, s);
+        kpm::launch_reduce(sys->partial, sw, std::min(c1, nm) - c0, sys->dmom, stride_r,
+                           offset + c0, s);
     }
+    if (dbl) kpm::launch_undouble(sys->dmom, sw.nseg << sw.vshift, stride_r, offset, nm, s);
     return KPM_OK;
 }
 
 // Chebyshev moments of Alg. 5 for n_vec vector pairs (every sample), reduced
 // into sys->dmom[(s * R + r) * stride_r + offset + m] (complex).  With graphs
 // enabled the launch sequence is captured once per set of buffers and
-// replayed.
+// replayed.  dbl selects the doubling form (phil must equal phir).
 template <typename V>
 kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir, int nm,
-                       V *a_buf, V *b_buf, int64_t stride_r, int64_t offset) {
+                       V *a_buf, V *b_buf, int64_t stride_r, int64_t offset, bool dbl = false) {
     kpm::Sweep sw;
     KPM_TRY(sys->sweep(vshift, &sw));
     // Group partials live in a ring of kPartialRing moment slots that is
     // reduced into sys->dmom whenever it fills, bounding its size at any N_m.
-    const int ring = std::min(std::max(nm, 2), kPartialRing);
+    const int slots = moment_slots(nm, dbl);
+    const int ring = std::min(std::max(slots, 2), kPartialRing);
+    const int steps = dbl ? slots / 2 - 1 : std::max(nm - 2, 0);   // recursion launches
     KPM_TRY(sys->ensure_partial(ring, sw.nwg, 1 << vshift));
     sys->stats.step_rows = sw.total;
-    sys->stats.step_bytes = sys->step_bytes(vshift);
-    sys->stats.site_updates += (int64_t)(nm > 1 ? nm - 1 : 1) * sw.total;
+    sys->stats.step_bytes = sys->step_bytes(vshift, dbl);
+    sys->stats.site_updates += (int64_t)(steps + 1) * sw.total;
     if (!sys->graphs)
-        return enqueue_moments<V>(sys, sw, ring, sys->stream, sys->timing, phil, phir, nm,
+        return enqueue_moments<V>(sys, sw, ring, sys->stream, sys->timing, dbl, phil, phir, nm,
                                   a_buf, b_buf, stride_r, offset);
     kpm_system::GraphKey key{phil, phir, a_buf, b_buf, sys->partial, sys->dmom, nm, vshift,
                              sys->launch[vshift].groups_per_cu, sys->launch[vshift].ilp,
                              sys->launch[vshift].streaming, sys->launch[vshift].compact,
-                             stride_r, offset};
+                             dbl ? 1 : 0, stride_r, offset};
     hipGraphExec_t exec = sys->find_graph(key);
     if (!exec) {
         KPM_TRY(sys->ensure_capture_stream());
         KPM_HIP(hipStreamBeginCapture(sys->cap, hipStreamCaptureModeThreadLocal));
-        kpm_status st = enqueue_moments<V>(sys, sw, ring, sys->cap, false, phil, phir, nm, a_buf,
-                                           b_buf, stride_r, offset);
+        kpm_status st = enqueue_moments<V>(sys, sw, ring, sys->cap, false, dbl, phil, phir, nm,
+                                           a_buf, b_buf, stride_r, offset);
         hipGraph_t graph = nullptr;
         const hipError_t ec = hipStreamEndCapture(sys->cap, &graph);
         if (st != KPM_OK) {
@@ -586,7 +617,7 @@ kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir
     KPM_HIP(hipGraphLaunch(exec, sys->stream));
     if (sys->timing) {
         KPM_HIP(hipEventRecord(e1, sys->stream));
-        sys->stats.step_launches += std::max(nm - 2, 0);
+        sys->stats.step_launches += steps;
     }
     return KPM_OK;
 }
@@ -667,12 +698,12 @@ kpm_status finish_moments(kpm_system *sys, size_t elems, double2 *host) {
 
 template <typename V>
 kpm_status moments_impl(kpm_system *sys, int vshift, const void *phil, const void *phir,
-                        int nm, double *mu) {
+                        int nm, double *mu, bool dbl) {
     KPM_TRY(sys->ensure_vecs(2, vshift));
     const size_t elems = (size_t)sys->nseg * ((size_t)1 << vshift) * nm;
     KPM_TRY(sys->ensure_dmom(elems));
     V *a = (V *)sys->vecs[0], *b = (V *)sys->vecs[1];
-    KPM_TRY(run_moments<V>(sys, vshift, (const V *)phil, (const V *)phir, nm, a, b, nm, 0));
+    KPM_TRY(run_moments<V>(sys, vshift, (const V *)phil, (const V *)phir, nm, a, b, nm, 0, dbl));
     return finish_moments(sys, elems, (double2 *)mu);
 }
 
@@ -734,10 +765,10 @@ kpm_status vac_impl(kpm_system *sys, int vshift, const void *phi_v, int nsteps, 
     return KPM_OK;
 }
 
-// MSD loop of Alg. 3 (Eq. 44).
+// MSD loop of Alg. 3 (Eq. 44); dbl takes the moments of Y_k in the doubling form.
 template <typename V>
 kpm_status msd_impl(kpm_system *sys, int vshift, const void *phi_v, int nsteps, double dt,
-                    int np, int nm, double *out) {
+                    int np, int nm, double *out, bool dbl) {
     KPM_TRY(sys->ensure_vecs(9, vshift));
     const int64_t per_r = (int64_t)(nsteps + 1) * nm;
     const size_t elems = (size_t)sys->nseg * ((size_t)1 << vshift) * per_r;
@@ -760,7 +791,7 @@ kpm_status msd_impl(kpm_system *sys, int vshift, const void *phi_v, int nsteps, 
             KPM_TRY(run_evolve<V>(sys, vshift, y, y2, xu, dt, +1, np, pa, pb));
             std::swap(y, y2);                     // Y_k = U(dt) Y_{k-1} + [X, U(dt)] psi'
         }
-        KPM_TRY(run_moments<V>(sys, vshift, y, y, nm, pa, pb, per_r, (int64_t)k * nm));
+        KPM_TRY(run_moments<V>(sys, vshift, y, y, nm, pa, pb, per_r, (int64_t)k * nm, dbl));
     }
     std::vector<double2> host(elems);
     KPM_TRY(finish_moments(sys, host.size(), host.data()));
@@ -1132,8 +1163,19 @@ kpm_status kpm_moments(kpm_system *sys, int n_vec, const void *phil, const void 
     if (!phil || !phir || !mu) return fail(KPM_ERR_INVALID, "null buffer");
     if (n_moments < 1) return fail(KPM_ERR_INVALID, "n_moments must be >= 1");
     DeviceGuard g(sys->device);
-    return sys->prec == KPM_FP64 ? moments_impl<double2>(sys, vs, phil, phir, n_moments, mu)
-                                 : moments_impl<float2>(sys, vs, phil, phir, n_moments, mu);
+    return sys->prec == KPM_FP64 ? moments_impl<double2>(sys, vs, phil, phir, n_moments, mu, false)
+                                 : moments_impl<float2>(sys, vs, phil, phir, n_moments, mu, false);
+}
+
+kpm_status kpm_moments_doubled(kpm_system *sys, int n_vec, const void *phi, int n_moments,
+                               double *mu) {
+    int vs;
+    KPM_TRY(check_common(sys, n_vec, &vs));
+    if (!phi || !mu) return fail(KPM_ERR_INVALID, "null buffer");
+    if (n_moments < 1) return fail(KPM_ERR_INVALID, "n_moments must be >= 1");
+    DeviceGuard g(sys->device);
+    return sys->prec == KPM_FP64 ? moments_impl<double2>(sys, vs, phi, phi, n_moments, mu, true)
+                                 : moments_impl<float2>(sys, vs, phi, phi, n_moments, mu, true);
 }
 
 kpm_status kpm_evolve(kpm_system *sys, int n_vec, void *phi, double dt_fs, int sign,
@@ -1181,8 +1223,18 @@ kpm_status kpm_msd(kpm_system *sys, int n_vec, const void *phi, int n_steps, dou
     KPM_TRY(check_loop(sys, n_vec, phi, n_steps, dt_fs, n_bessel, n_moments, out, &vs));
     DeviceGuard g(sys->device);
     return sys->prec == KPM_FP64
-               ? msd_impl<double2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, out)
-               : msd_impl<float2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, out);
+               ? msd_impl<double2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, out, false)
+               : msd_impl<float2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, out, false);
+}
+
+kpm_status kpm_msd_doubled(kpm_system *sys, int n_vec, const void *phi, int n_steps,
+                           double dt_fs, int n_bessel, int n_moments, double *out) {
+    int vs;
+    KPM_TRY(check_loop(sys, n_vec, phi, n_steps, dt_fs, n_bessel, n_moments, out, &vs));
+    DeviceGuard g(sys->device);
+    return sys->prec == KPM_FP64
+               ? msd_impl<double2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, out, true)
+               : msd_impl<float2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, out, true);
 }
 
 kpm_status kpm_fourier_moments(kpm_system *sys, int n_vec, const void *phi_l, const void *phi_r,

@@ -85,6 +85,17 @@ void launch_moment_step(const Ell &h, const Sweep &sw, bool first, const V *p1,
                         const V *p0, V *out, const V *phil, double2 *partial,
                         int slot, hipStream_t s);
 
+// Doubling step for phi_L = phi_R: out = 2 H~ p1 - p0 (out may alias p0);
+// partial[slot] = <p1|p1>, partial[slot+1] = <p1|out>.
+template <typename V>
+void launch_moment_step_doubled(const Ell &h, const Sweep &sw, const V *p1, const V *p0,
+                                V *out, double2 *partial, int slot, hipStream_t s);
+
+// mom[t * stride + offset + j] = 2 mom[...j] - mom[...j % 2] for 2 <= j < nm,
+// t < rows: moments from the doubling sums.
+void launch_undouble(double2 *mom, int rows, int64_t stride, int64_t offset, int nm,
+                     hipStream_t s);
+
 // Chebyshev-Bessel propagator step (Alg. 6):
 //   first: out = H~ in; acc = add + c0 in + c out   (add may be nullptr)
 //   else : out = 2 H~ p1 - p0 (out may alias p0); acc += c out

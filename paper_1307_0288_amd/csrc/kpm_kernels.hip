@@ -299,14 +299,19 @@ template <int FORM> struct FormTraits {
 // two memory latencies per element).  Elements are visited in the same order,
 // and every form performs the same floating-point operations, so all ILP,
 // streaming and form choices give bit-identical results.
-template <typename V, int ILP, bool NT, int FORM>
+//
+// DBL is the doubling form for phi_L = phi_R (the product identities
+// T_{2n} = 2 T_n T_n - T_0 and T_{2n+1} = 2 T_{n+1} T_n - T_1): with
+// p1 = phi_n it accumulates <phi_n|phi_n> into slot and <phi_n|phi_{n+1}>
+// into slot + 1, from values the step holds anyway, so phi_L is not read.
+template <typename V, int ILP, bool NT, int FORM, bool DBL>
 __global__ __launch_bounds__(kBlock) void k_moment_step(Ell h, Sweep sw, const V *p1,
                                                         const V *p0, V *out,
                                                         const V *__restrict__ phil,
                                                         double2 *__restrict__ partial,
                                                         int slot) {
     using F = FormTraits<FORM>;
-    double2 s0 = make_double2(0.0, 0.0);
+    double2 s0 = make_double2(0.0, 0.0), s1 = make_double2(0.0, 0.0);
     __shared__ int32_t lpat[kMaxPatterns * kMaxWidth];
     if (F::compact || (F::generic && h.pid)) {
         for (int j = threadIdx.x; j < h.npat * kMaxWidth; j += kBlock) lpat[j] = h.pat[j];
@@ -359,7 +364,10 @@ __global__ __launch_bounds__(kBlock) void k_moment_step(Ell h, Sweep sw, const V
                     on[u] = h.ons[i];
             }
             xi[u] = ld(p1 + e[u]);
-            l[u] = NT ? ld_nt(phil + e[u]) : ld(phil + e[u]);
+            if constexpr (DBL)
+                l[u] = xi[u];
+            else
+                l[u] = NT ? ld_nt(phil + e[u]) : ld(phil + e[u]);
             q[u] = NT ? ld_nt(p0 + e[u]) : ld(p0 + e[u]);
         }
         double2 acc[ILP];
@@ -384,12 +392,34 @@ __global__ __launch_bounds__(kBlock) void k_moment_step(Ell h, Sweep sw, const V
                     st_nt(out + e[u], o);
                 else
                     st(out + e[u], o);
-                s0 = cdot_acc(s0, l[u], o);
+                if constexpr (DBL) {
+                    s0 = cdot_acc(s0, l[u], xi[u]);
+                    s1 = cdot_acc(s1, l[u], o);
+                } else {
+                    s0 = cdot_acc(s0, l[u], o);
+                }
             }
         }
     }
     const int64_t r = (int64_t)1 << sw.vshift;
     block_sum(s0, sw.vshift, partial + ((int64_t)slot * sw.nwg + blockIdx.x) * r);
+    if constexpr (DBL)
+        block_sum(s1, sw.vshift, partial + ((int64_t)(slot + 1) * sw.nwg + blockIdx.x) * r);
+}
+
+// Moments from the doubling sums, in place: row t of mom holds
+// a_j = <phi_n|phi_n> (j = 2n) and <phi_n|phi_{n+1}> (j = 2n + 1) for j >= 2 and
+// C_0, C_1 at j = 0, 1; C_j = 2 a_j - C_{j mod 2}.
+__global__ __launch_bounds__(kBlock) void k_undouble(double2 *__restrict__ mom, int rows,
+                                                     int64_t stride, int64_t offset, int nm) {
+    const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t per = nm - 2;
+    if (per <= 0 || id >= (int64_t)rows * per) return;
+    const int64_t t = id / per;
+    const int j = (int)(id % per) + 2;
+    double2 *c = mom + t * stride + offset;
+    const double2 a = c[j], b = c[j & 1];
+    c[j] = make_double2(fma(2.0, a.x, -b.x), fma(2.0, a.y, -b.y));
 }
 
 template <typename V, bool FIRST>
@@ -536,7 +566,7 @@ __global__ __launch_bounds__(kBlock) void k_kpm_sum(const double *__restrict__ m
 }
 
 // ---------------------------------------------------------------- launchers
-template <typename V, int ILP, bool NT>
+template <typename V, int ILP, bool NT, bool DBL>
 static void launch_step_shape(const Ell &h, const Sweep &sw, const V *p1, const V *p0, V *out,
                               const V *phil, double2 *partial, int slot, hipStream_t s) {
     const bool fixed = h.w == 3 && !h.hop;
@@ -546,8 +576,8 @@ static void launch_step_shape(const Ell &h, const Sweep &sw, const V *p1, const 
     switch (form) {
 #define KPM_FORM_CASE(F)                                                                       \
         case F:                                                                                \
-            hipLaunchKernelGGL((k_moment_step<V, ILP, NT, F>), dim3(sw.nwg), dim3(kBlock), 0,  \
-                               s, h, sw, p1, p0, out, phil, partial, slot);                    \
+            hipLaunchKernelGGL((k_moment_step<V, ILP, NT, F, DBL>), dim3(sw.nwg), dim3(kBlock), \
+                               0, s, h, sw, p1, p0, out, phil, partial, slot);                 \
             break;
         KPM_FORM_CASE(kFormC3F)
         KPM_FORM_CASE(kFormC3D)
@@ -556,6 +586,21 @@ static void launch_step_shape(const Ell &h, const Sweep &sw, const V *p1, const 
         default:
         KPM_FORM_CASE(kFormGeneric)
 #undef KPM_FORM_CASE
+    }
+}
+
+template <typename V, bool DBL>
+static void launch_step_ilp(const Ell &h, const Sweep &sw, const V *p1, const V *p0, V *out,
+                            const V *phil, double2 *partial, int slot, hipStream_t s) {
+    const int ilp = sw.ilp >= 4 ? 4 : (sw.ilp == 2 ? 2 : 1);
+    if (sw.nt) {
+        if (ilp == 4) launch_step_shape<V, 4, true, DBL>(h, sw, p1, p0, out, phil, partial, slot, s);
+        else if (ilp == 2) launch_step_shape<V, 2, true, DBL>(h, sw, p1, p0, out, phil, partial, slot, s);
+        else launch_step_shape<V, 1, true, DBL>(h, sw, p1, p0, out, phil, partial, slot, s);
+    } else {
+        if (ilp == 4) launch_step_shape<V, 4, false, DBL>(h, sw, p1, p0, out, phil, partial, slot, s);
+        else if (ilp == 2) launch_step_shape<V, 2, false, DBL>(h, sw, p1, p0, out, phil, partial, slot, s);
+        else launch_step_shape<V, 1, false, DBL>(h, sw, p1, p0, out, phil, partial, slot, s);
     }
 }
 
@@ -568,16 +613,22 @@ void launch_moment_step(const Ell &h, const Sweep &sw, bool first, const V *p1,
                            out, phil, partial, slot);
         return;
     }
-    const int ilp = sw.ilp >= 4 ? 4 : (sw.ilp == 2 ? 2 : 1);
-    if (sw.nt) {
-        if (ilp == 4) launch_step_shape<V, 4, true>(h, sw, p1, p0, out, phil, partial, slot, s);
-        else if (ilp == 2) launch_step_shape<V, 2, true>(h, sw, p1, p0, out, phil, partial, slot, s);
-        else launch_step_shape<V, 1, true>(h, sw, p1, p0, out, phil, partial, slot, s);
-    } else {
-        if (ilp == 4) launch_step_shape<V, 4, false>(h, sw, p1, p0, out, phil, partial, slot, s);
-        else if (ilp == 2) launch_step_shape<V, 2, false>(h, sw, p1, p0, out, phil, partial, slot, s);
-        else launch_step_shape<V, 1, false>(h, sw, p1, p0, out, phil, partial, slot, s);
-    }
+    launch_step_ilp<V, false>(h, sw, p1, p0, out, phil, partial, slot, s);
+}
+
+template <typename V>
+void launch_moment_step_doubled(const Ell &h, const Sweep &sw, const V *p1, const V *p0,
+                                V *out, double2 *partial, int slot, hipStream_t s) {
+    launch_step_ilp<V, true>(h, sw, p1, p0, out, nullptr, partial, slot, s);
+}
+
+void launch_undouble(double2 *mom, int rows, int64_t stride, int64_t offset, int nm,
+                     hipStream_t s) {
+    const int64_t total = (int64_t)rows * (nm - 2);
+    if (total <= 0) return;
+    const int blocks = (int)((total + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_undouble, dim3(blocks), dim3(kBlock), 0, s, mom, rows, stride, offset,
+                       nm);
 }
 
 template <typename V>
@@ -641,6 +692,9 @@ void launch_kpm_sum(const double *mom, int rows, int nm, const double *w, const 
     template void launch_moment_step<V>(const Ell &, const Sweep &, bool, const V *,        \
                                         const V *, V *, const V *, double2 *, int,          \
                                         hipStream_t);                                       \
+    template void launch_moment_step_doubled<V>(const Ell &, const Sweep &, const V *,      \
+                                                const V *, V *, double2 *, int,             \
+                                                hipStream_t);                               \
     template void launch_evolve_step<V>(const Ell &, const Sweep &, bool, const V *,        \
                                         const V *, V *, V *, const V *, Coef, Coef,         \
                                         hipStream_t);                                       \

@@ -26,10 +26,14 @@ BOND_NM = 0.142
 # Every symbol declared in include/kpm.h.
 ABI_SYMBOLS = ("kpm_build_graphene", "kpm_system_create", "kpm_system_destroy",
                "kpm_system_set_stream", "kpm_system_n_sites", "kpm_batch_create",
-               "kpm_system_n_samples", "kpm_system_offsets", "kpm_moments", "kpm_evolve",
-               "kpm_evolve_x", "kpm_vac", "kpm_msd", "kpm_fourier_moments", "kpm_ftm_sum",
+               "kpm_system_n_samples", "kpm_system_offsets", "kpm_moments",
+               "kpm_moments_doubled", "kpm_evolve", "kpm_evolve_x", "kpm_vac", "kpm_msd",
+               "kpm_msd_doubled", "kpm_fourier_moments", "kpm_ftm_sum",
                "kpm_kpm_sum", "kpm_sigma_gk",
-               "kpm_sigma_e1", "kpm_sigma_e2", "kpm_set_launch", "kpm_get_launch",
+               "kpm_sigma_e1", "kpm_sigma_e2", "kpm_length", "kpm_conductance",
+               "kpm_ballistic_conductance", "kpm_sigma_sc_max", "kpm_sigma_sc_average",
+               "kpm_pade_fit", "kpm_pade_eval", "kpm_typical_conductance",
+               "kpm_set_launch", "kpm_get_launch",
                "kpm_autotune", "kpm_set_graphs", "kpm_set_timing", "kpm_get_stats",
                "kpm_reset_stats",
                "kpm_last_error", "kpm_version")
@@ -80,10 +84,12 @@ def lib():
             "kpm_system_destroy": [vp],
             "kpm_system_set_stream": [vp, vp],
             "kpm_moments": [vp, C.c_int, vp, vp, C.c_int, dp],
+            "kpm_moments_doubled": [vp, C.c_int, vp, C.c_int, dp],
             "kpm_evolve": [vp, C.c_int, vp, C.c_double, C.c_int, C.c_int],
             "kpm_evolve_x": [vp, C.c_int, vp, vp, vp, C.c_double, C.c_int],
             "kpm_vac": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, C.c_int, dp],
             "kpm_msd": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, C.c_int, dp],
+            "kpm_msd_doubled": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, C.c_int, dp],
             "kpm_kpm_sum": [C.c_int, C.c_int, dp, C.c_int, dp, C.c_double, C.c_double,
                             C.c_int, vp, dp],
             "kpm_fourier_moments": [vp, C.c_int, vp, vp, C.c_int, C.c_double, C.c_int, dp],
@@ -92,6 +98,14 @@ def lib():
             "kpm_sigma_gk": [C.c_int, C.c_int, dp, C.c_double, dp],
             "kpm_sigma_e1": [C.c_int, C.c_int, dp, C.c_double, dp],
             "kpm_sigma_e2": [C.c_int, C.c_int, dp, C.c_double, dp],
+            "kpm_length": [C.c_int, C.c_int, dp, dp, dp],
+            "kpm_conductance": [C.c_int, C.c_int, dp, dp, C.c_double, dp],
+            "kpm_ballistic_conductance": [C.c_int, C.c_int, dp, dp, C.c_double, C.c_double, dp],
+            "kpm_sigma_sc_max": [C.c_int, C.c_int, dp, dp],
+            "kpm_sigma_sc_average": [C.c_int, C.c_int, dp, C.c_int, C.c_int, dp],
+            "kpm_pade_fit": [C.c_int, dp, dp, C.c_int, C.c_int, dp, dp],
+            "kpm_pade_eval": [C.c_int, C.c_int, dp, dp, C.c_int, dp, dp, dp],
+            "kpm_typical_conductance": [C.c_int, C.c_int, dp, dp],
             "kpm_set_launch": [vp, C.c_int, C.POINTER(Launch)],
             "kpm_get_launch": [vp, C.c_int, C.POINTER(Launch)],
             "kpm_autotune": [vp, C.c_int, vp, C.c_int, C.POINTER(Launch)],
@@ -187,6 +201,92 @@ def kpm_sigma_e1(rho_msd, dt_fs):
 def kpm_sigma_e2(rho_msd, dt_fs):
     """sigma_E2(E, t_k) / (e^2/h) from rho*MSD [T, K] (Eq. 11)."""
     return _sigma(lib().kpm_sigma_e2, rho_msd, dt_fs)
+
+
+def _rows(a):
+    """[T, K] float64 C-contiguous view of a [T, K] or [T] array."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a.reshape(a.shape[0], -1)
+
+
+def kpm_length(rho_msd, rho):
+    """L(E, t) = 2 sqrt(rho_msd / rho) in nm (Eq. 50); rho_msd [T, K], rho [K]."""
+    m = _rows(rho_msd)
+    r = np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)
+    if r.shape[0] != m.shape[1]:
+        raise ValueError("rho must have one entry per energy")
+    out = np.empty_like(m)
+    _check(lib().kpm_length(m.shape[0], m.shape[1], _dp(m), _dp(r), _dp(out)))
+    return out.reshape(np.shape(rho_msd))
+
+
+def kpm_conductance(sigma, length_nm, width_nm: float):
+    """G(E, L) = (W / L) sigma in e^2/h (Eq. 51, Eq. 59); [T, K] arrays."""
+    s, lg = _rows(sigma), _rows(length_nm)
+    if s.shape != lg.shape:
+        raise ValueError("sigma and length differ in shape")
+    out = np.empty_like(s)
+    _check(lib().kpm_conductance(s.shape[0], s.shape[1], _dp(s), _dp(lg), width_nm, _dp(out)))
+    return out.reshape(np.shape(sigma))
+
+
+def kpm_ballistic_conductance(rho_msd, rho, dt_fs: float, width_nm: float):
+    """G(E) = (W/2) e^2 rho sqrt(v^2) in e^2/h with v^2 = Delta X^2 / t^2 (Eq. 52)."""
+    m = _rows(rho_msd)
+    r = np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)
+    if r.shape[0] != m.shape[1]:
+        raise ValueError("rho must have one entry per energy")
+    out = np.empty_like(m)
+    _check(lib().kpm_ballistic_conductance(m.shape[0], m.shape[1], _dp(m), _dp(r), dt_fs,
+                                           width_nm, _dp(out)))
+    return out.reshape(np.shape(rho_msd))
+
+
+def kpm_sigma_sc_max(sigma):
+    """sigma_sc(E) = max over t > 0 of sigma(E, t) (Eq. 53): [T, K] -> [K]."""
+    s = _rows(sigma)
+    out = np.empty(s.shape[1])
+    _check(lib().kpm_sigma_sc_max(s.shape[0], s.shape[1], _dp(s), _dp(out)))
+    return out
+
+
+def kpm_sigma_sc_average(sigma, k1: int, k2: int):
+    """sigma_sc(E) = time-block average of sigma over [k1 dt, k2 dt] (Eq. 55)."""
+    s = _rows(sigma)
+    out = np.empty(s.shape[1])
+    _check(lib().kpm_sigma_sc_average(s.shape[0], s.shape[1], _dp(s), k1, k2, _dp(out)))
+    return out
+
+
+def kpm_pade_fit(t, y, m: int, n: int):
+    """[m/n] Pade coefficients (a [m+1], b [n]) of Eq. 58 by linear least squares."""
+    t = np.ascontiguousarray(t, dtype=np.float64).reshape(-1)
+    y = np.ascontiguousarray(y, dtype=np.float64).reshape(-1)
+    if t.shape != y.shape:
+        raise ValueError("t and y differ in length")
+    a, b = np.empty(m + 1), np.empty(max(n, 1))
+    _check(lib().kpm_pade_fit(t.shape[0], _dp(t), _dp(y), m, n, _dp(a), _dp(b)))
+    return a, b[:n]
+
+
+def kpm_pade_eval(a, b, t):
+    """Value and d/dt of the Pade approximant (a, b) at the times t."""
+    a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+    b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
+    t = np.ascontiguousarray(t, dtype=np.float64).reshape(-1)
+    bb = b if b.shape[0] else np.zeros(1)
+    v, d = np.empty_like(t), np.empty_like(t)
+    _check(lib().kpm_pade_eval(a.shape[0] - 1, b.shape[0], _dp(a), _dp(bb), t.shape[0], _dp(t),
+                               _dp(v), _dp(d)))
+    return v, d
+
+
+def kpm_typical_conductance(g):
+    """G_typ(E) = exp(<ln G(E)>) over realisations (Eq. 60): [R, K] -> [K]."""
+    gg = _rows(g)
+    out = np.empty(gg.shape[1])
+    _check(lib().kpm_typical_conductance(gg.shape[0], gg.shape[1], _dp(gg), _dp(out)))
+    return out
 
 
 # ------------------------------------------------------------------ system
@@ -324,6 +424,16 @@ def kpm_moments(sys: System, phi_l, phi_r, n_moments: int) -> np.ndarray:
     return sys._shape(out[..., 0] + 1j * out[..., 1])
 
 
+def kpm_moments_doubled(sys: System, phi, n_moments: int) -> np.ndarray:
+    """kpm_moments(sys, phi, phi, n_moments) from about half the recursion
+    steps (product identities of T_n); same shape and values up to rounding."""
+    p, nv = sys._state(phi, "phi")
+    out = np.empty((sys.n_samples, nv, n_moments, 2))
+    sys._sync_stream()
+    _check(lib().kpm_moments_doubled(sys.handle, nv, p, n_moments, _dp(out)))
+    return sys._shape(out[..., 0] + 1j * out[..., 1])
+
+
 def kpm_fourier_moments(sys: System, phi_l, phi_r, n_moments: int, dtau_fs: float,
                         n_bessel: int) -> np.ndarray:
     """F_n = <phi_L|U(n dtau)|phi_R>, n = -N_m .. N_m (Alg. 4): complex128
@@ -380,6 +490,12 @@ def kpm_msd(sys: System, phi, n_steps: int, dt_fs: float, n_bessel: int, n_momen
     """MSD moments [n_vec, n_steps+1, n_moments] in nm^2 (Alg. 3); leading
     sample axis for a batch."""
     return _loop(lib().kpm_msd, sys, phi, n_steps, dt_fs, n_bessel, n_moments)
+
+
+def kpm_msd_doubled(sys: System, phi, n_steps: int, dt_fs: float, n_bessel: int,
+                    n_moments: int):
+    """kpm_msd with the moments of each state in the doubling form."""
+    return _loop(lib().kpm_msd_doubled, sys, phi, n_steps, dt_fs, n_bessel, n_moments)
 
 
 def kpm_set_launch(sys: System, n_vec: int, groups_per_cu: int, ilp: int, streaming: int = 0,

@@ -1,17 +1,34 @@
-"""Short, fixed workload for hardware-counter collection with rocprofv3.
+"""Short, fixed workload for hardware-counter collection with rocprofv3, and
+the summary of its counter readings.
 
-    rocprofv3 --pmc FETCH_SIZE -d OUT -o fetch --output-format csv -- \
+Collect (one counter per run):
+
+    rocprofv3 --pmc FETCH_SIZE -d OUT/fetch -o c --output-format csv -- \
+        python3 -m paper_1307_0288_amd.profile_run --moments 40 --copy-mib 512 \
+        --meta OUT/meta.json
+    rocprofv3 --pmc WRITE_SIZE -d OUT/write -o c --output-format csv -- \
         python3 -m paper_1307_0288_amd.profile_run --moments 40 --copy-mib 512
 
-Runs one Chebyshev-moment call on the paper-scale sheet (2828 x 1414 sites,
-0.5 % vacancies, W = 0.1 eV; n_moments - 2 launches of the fused moment step)
-in the precision and vector count asked for, followed by plain device-to-device
-copies of a known size, whose counter readings calibrate FETCH_SIZE and
-WRITE_SIZE to bytes.
+Summarise:
+
+    python3 -m paper_1307_0288_amd.profile_run --summarize OUT/fetch OUT/write \
+        --meta OUT/meta.json --out profiles/<name>.json
+    python3 -m paper_1307_0288_amd.profile_run --trace-table OUT/bench_kernel_stats.csv
+
+The run does one Chebyshev-moment call on the paper-scale sheet (2828 x 1414
+sites, 0.5 % vacancies, W = 0.1 eV; n_moments - 2 launches of the fused moment
+step, or about n_moments / 2 in the doubling form) in the precision and vector
+count asked for, followed by plain device-to-device copies of a known size.
+FETCH_SIZE and WRITE_SIZE count in KiB per dispatch; the copies, which read
+and write exactly copy-mib MiB each, give the factor that turns each counter
+into bytes.
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import hashlib
+import json
 import os
 import sys
 
@@ -19,17 +36,134 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+KERNEL_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "kpm_kernels.hip")
+
+
+def kernel_sha() -> str:
+    """Hash of the source the moment step is compiled from: the kernel file up to
+    the first kernel after it, plus its launchers (edits elsewhere in the file do
+    not change the moment step)."""
+    with open(KERNEL_SRC) as f:
+        t = f.read()
+    head = t[:t.index("template <typename V, bool FIRST>\n__global__ __launch_bounds__(kBlock) "
+                      "void k_evolve_step(")]
+    a = t.index("template <typename V, int ILP, bool NT, bool DBL>\nstatic void launch_step_shape(")
+    b = t.index("template <typename V>\nvoid launch_evolve_step(")
+    return hashlib.sha256((head + t[a:b]).encode()).hexdigest()[:16]
+
+
+def measured_traffic(path: str, step_rows: int, launch: dict):
+    """HBM bytes per moment-step launch from a committed counter summary, or
+    None when it is absent or was taken on another kernel version, size or
+    launch shape."""
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_sha() or t.get("step_rows") != step_rows \
+            or t.get("launch_shape") != launch:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def _read_counter(d: str):
+    rows = []
+    for root, _, files in os.walk(d):
+        for fn in files:
+            if fn.endswith("counter_collection.csv"):
+                with open(os.path.join(root, fn)) as f:
+                    rows.extend(csv.DictReader(f))
+    if not rows:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    return rows
+
+
+def _mean(vals):
+    vals = list(vals)
+    if not vals:
+        raise SystemExit("no matching dispatches")
+    return sum(vals) / len(vals)
+
+
+def summarize(fetch_dir: str, write_dir: str, meta_path: str, out_path: str):
+    with open(meta_path) as f:
+        meta = json.load(f)
+    step_prefix = "void kpm::k_moment_step<"
+    res = {}
+    for key, d in (("fetch", fetch_dir), ("write", write_dir)):
+        rows = _read_counter(d)
+        copies = [r for r in rows if r["Kernel_Name"] == "__amd_rocclr_copyBuffer"]
+        big = max(int(r["Grid_Size"]) for r in copies)
+        copy_kib = _mean(float(r["Counter_Value"]) for r in copies if int(r["Grid_Size"]) == big)
+        step = _mean(float(r["Counter_Value"]) for r in rows
+                     if r["Kernel_Name"].startswith(step_prefix))
+        res[key] = (step, meta["copy_mib"] * 1024.0 / copy_kib)
+    fetch_kib, fs = res["fetch"]
+    write_kib, ws = res["write"]
+    out = {
+        "kernel": meta["kernel"],
+        "kernel_sha": meta["kernel_sha"],
+        "step_rows": meta["step_rows"],
+        "launch_shape": meta["launch_shape"],
+        "fetch_kib_per_launch": round(fetch_kib, 3),
+        "write_kib_per_launch": round(write_kib, 3),
+        "fetch_scale": round(fs, 4),
+        "write_scale": round(ws, 4),
+        "bytes_per_launch": int(round((fetch_kib * fs + write_kib * ws) * 1024)),
+        "algorithmic_bytes_per_launch": meta["step_bytes"],
+        "command": meta["command"],
+    }
+    out["traffic_over_algorithmic"] = round(out["bytes_per_launch"] / meta["step_bytes"], 4)
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+def _short_kernel_name(name: str) -> str:
+    name = name.replace("HIP_vector_type<double, 2u>", "double2")
+    name = name.replace("HIP_vector_type<float, 2u>", "float2")
+    name = name.removeprefix("void ")
+    return name.split("(")[0] if "(" in name else name
+
+
+def trace_table(stats_csv: str, top: int) -> str:
+    """Markdown table of the `top` kernels of a rocprofv3 --stats kernel summary."""
+    with open(stats_csv) as f:
+        rows = list(csv.DictReader(f))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["| kernel | calls | avg (us) | min (us) | max (us) | share of GPU time |",
+           "|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        out.append(f"| `{_short_kernel_name(r['Name'])}` | {r['Calls']} | "
+                   f"{float(r['AverageNs']) / 1e3:.3f} | {float(r['MinNs']) / 1e3:.3f} | "
+                   f"{float(r['MaxNs']) / 1e3:.3f} | {float(r['Percentage']):.2f} % |")
+    return "\n".join(out)
+
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--moments", type=int, default=40)
     ap.add_argument("--n-vec", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--doubled", action="store_true", help="doubling form (kpm_moments_doubled)")
     ap.add_argument("--copy-mib", type=int, default=512)
     ap.add_argument("--copies", type=int, default=3)
     ap.add_argument("--launch", default="",
                     help="groups_per_cu,ilp,streaming,compact (default: the library's)")
+    ap.add_argument("--meta", default="", help="write the run's launch shape, sizes and "
+                                               "algorithmic bytes here")
+    ap.add_argument("--summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--out", default="")
+    ap.add_argument("--trace-table", metavar="KERNEL_STATS_CSV",
+                    help="print a markdown table of a --stats kernel summary")
+    ap.add_argument("--top", type=int, default=12)
     args = ap.parse_args()
+    if args.trace_table:
+        print(trace_table(args.trace_table, args.top))
+        return
+    if args.summarize:
+        return summarize(args.summarize[0], args.summarize[1], args.meta, args.out)
 
     import torch
     import kpm_inputs as ki
@@ -46,16 +180,47 @@ def main():
     if args.launch:
         g, ilp, nt, cp = (int(x) for x in args.launch.split(","))
         kp.kpm_set_launch(sysg, args.n_vec, g, ilp, nt, cp)
-    print(f"launch shape: {kp.kpm_get_launch(sysg, args.n_vec)}", flush=True)
-    mu = kp.kpm_moments(sysg, phi, phi, args.moments)
-    print(f"moments: n={n} n_vec={args.n_vec} {args.precision} C_0={mu[0, 0].real:.1f}",
-          flush=True)
+    launch = kp.kpm_get_launch(sysg, args.n_vec)
+    print(f"launch shape: {launch}", flush=True)
+    kp.kpm_reset_stats(sysg)
+    if args.doubled:
+        mu = kp.kpm_moments_doubled(sysg, phi, args.moments)
+    else:
+        mu = kp.kpm_moments(sysg, phi, phi, args.moments)
+    st = kp.kpm_get_stats(sysg)
+    print(f"moments: n={n} n_vec={args.n_vec} {args.precision} doubled={args.doubled} "
+          f"C_0={mu[0, 0].real:.1f}", flush=True)
     src = torch.ones(args.copy_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(args.copies):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(f"copies: {args.copies} x {args.copy_mib} MiB", flush=True)
+    if args.meta:
+        v = "double2" if args.precision == "fp64" else "float2"
+        form = "kFormC3F" if launch["compact"] else "kFormL3F"
+        cmd = ["python3 -m paper_1307_0288_amd.profile_run", f"--moments {args.moments}",
+               f"--n-vec {args.n_vec}", f"--precision {args.precision}",
+               f"--copy-mib {args.copy_mib}"]
+        if args.doubled:
+            cmd.append("--doubled")
+        if args.launch:
+            cmd.append(f"--launch {args.launch}")
+        meta = {
+            "kernel": f"k_moment_step<{v},{launch['ilp']},"
+                      f"{'true' if launch['streaming'] else 'false'},{form},"
+                      f"{'true' if args.doubled else 'false'}> ({args.precision}, "
+                      f"{args.n_vec} vector(s))",
+            "kernel_sha": kernel_sha(),
+            "step_rows": st["step_rows"],
+            "step_bytes": st["step_bytes"],
+            "launch_shape": launch,
+            "copy_mib": args.copy_mib,
+            "command": "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -d OUT -o c "
+                       "--output-format csv -- " + " ".join(cmd),
+        }
+        with open(args.meta, "w") as f:
+            json.dump(meta, f, indent=1)
 
 
 if __name__ == "__main__":

@@ -253,6 +253,22 @@ def test_paper_scale_moments_prefix_and_properties(paper):
     assert rel_err(got[:64], ref, n_act) < 1e-10
 
 
+def test_paper_scale_doubled_moments(paper):
+    """Doubling form on the full sheet: the first 64 moments against the
+    oracle, all 3000 against the direct form (rounding only)."""
+    p, c, lat, sysg = paper
+    phi = phases(c, 1, 3000)
+    d = sysg.upload(phi)
+    n_act = int(np.count_nonzero(c["active"]))
+    _log("paper-scale gpu doubled moments 3000")
+    got = kp.kpm_moments_doubled(sysg, d, p["n_moments"])[0]
+    direct = kp.kpm_moments(sysg, d, d, p["n_moments"])[0]
+    assert rel_err(got, direct, n_act) < 1e-10
+    _log("paper-scale oracle moments 64")
+    ref = oracle.moments(lat, c["e_scale"], phi[:, 0], phi[:, 0], 64)
+    assert rel_err(got[:64], ref, n_act) < 1e-10
+
+
 def test_paper_scale_vac_msd_one_step(paper):
     p, c, lat, sysg = paper
     phi = phases(c, 1, 3000)
