@@ -73,11 +73,12 @@ def main():
     ap.add_argument("--cpu-moments", type=int, default=800,
                     help="moments in the oracle's CPU-baseline sample (0 skips it)")
     ap.add_argument("--workload", default="paper",
-                    choices=["paper", "batched", "ragged", "doubled"],
+                    choices=["paper", "batched", "ragged", "doubled", "ballistic"],
                     help="paper: plain FP64, one vector (default); batched: 64 vectors, "
                          "FP32 states vs FP64; ragged: 32 samples of 1e4..1e6 sites in one "
                          "launch per step; doubled: DOS and MSD moments in the doubling "
-                         "form vs the direct form, as moments/s")
+                         "form vs the direct form, as moments/s; ballistic: G(E) of a "
+                         "pristine 65536x16 ZGNR from the exact trace over one cell")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -96,6 +97,8 @@ def main():
         return ragged(args)
     if args.workload == "doubled":
         return doubled(args)
+    if args.workload == "ballistic":
+        return ballistic(args)
 
     p = ki.sheet_config("paper")
     n = p["nx"] * p["ny"]
@@ -243,6 +246,89 @@ def doubled(args):
                      "avg_launch_us": dd["step_launch_us"]},
         "forms": res,
         "max_rel_diff_vs_direct": {"dos": err_dos, "msd": err_msd},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def ballistic(args):
+    """Ballistic conductance of the paper's pristine ZGNR (Sec. 5.1): 65536 x 16
+    sites (1,048,576), periodic along x.  The trace over all sites is exact
+    from the 32 unit vectors of one translation cell (2 sites along x times 16
+    chains) times the 32768 cells, so one batch of 32 vectors per Chebyshev
+    step gives rho(E) and Delta X^2(E, t) without stochastic error.  One step:
+    DOS and MSD moments (doubling form, 1000 moments, 20 time steps of 2 fs,
+    45 Bessel terms), then G(E) = (W/L) sigma_E1 (Eq. 51) on 64 energies.
+    Reports Gsite-updates/s and the deviation of G from 2 e^2/h on the first
+    plateau (0.2 eV <= |E| <= 1.6 eV)."""
+    import torch
+    import paper_1307_0288_amd as kp
+    nx, ny, nm, ns, dt, nb = 65536, 16, 1000, 20, 2.0, 45
+    es = 1.01 * 3 * 2.7
+    n = nx * ny
+    n_vec = 2 * ny
+    sites = np.array([j * nx + i for j in range(ny) for i in (0, 1)], dtype=np.int64)
+    phi_h = np.zeros((n, n_vec), dtype=np.complex128)
+    phi_h[sites, np.arange(n_vec)] = 1.0
+    cells = nx // 2
+    sysg = kp.graphene_system(nx, ny, "zgnr", -2.7, None, None, es, "fp64")
+    phi = sysg.upload(phi_h)
+    del phi_h
+    launch = kp.kpm_autotune(sysg, phi, 20)
+    log(f"autotuned launch shape (32 vectors): {launch}")
+    lx = np.sqrt(3.0) * nx * 0.142 / 2.0
+    width = 3.0 * ny * 0.142 / 2.0
+    area = lx * width
+    en = np.linspace(-3.0, 3.0, 64)
+
+    def step():
+        mu = kp.kpm_moments_doubled(sysg, phi, nm).real.sum(axis=0) * cells
+        ms = kp.kpm_msd_doubled(sysg, phi, ns, dt, nb, nm).sum(axis=0) * cells
+        rho = kp.kpm_kpm_sum(mu, en, es, area)
+        rm = kp.kpm_kpm_sum(ms, en, es, area)
+        return kp.kpm_conductance(kp.kpm_sigma_e1(rm, dt), kp.kpm_length(rm, rho), width)
+
+    for _ in range(args.warmup):
+        step()
+    kp.kpm_reset_stats(sysg)
+    kp.kpm_set_timing(sysg, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        g = step()
+        log(f"step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = kp.kpm_get_stats(sysg)
+    kp.kpm_set_timing(sysg, False)
+    launch_ms = st["step_ms"] / max(st["step_launches"], 1)
+    achieved = st["step_bytes"] / (launch_ms * 1e-3) / 1e9
+    plateau = (np.abs(en) >= 0.2) & (np.abs(en) <= 1.6)
+    k_mid = ns // 2
+    dev = float(np.max(np.abs(g[k_mid:-1, plateau] - 2.0)))
+    out = {
+        "metric": "Gsite-updates/s (ballistic G(E) pipeline, exact cell trace, 32 vectors)",
+        "value": round(st["site_updates"] / elapsed / 1e9, 4),
+        "unit": "Gsite-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "pristine ZGNR 65536x16 sites (1048576), periodic along x, exact "
+                               "trace from 32 cell unit vectors, 1000 moments (doubling form), "
+                               "MSD 20 steps x 2 fs x 45 Bessel terms, G(E) on 64 energies",
+                   "n_sites": n, "n_vec": n_vec, "launch_shape": launch},
+        "roofline": {"kernel": step_kernel_name("double2", launch, True), "bound": "hbm",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "avg_launch_us": round(launch_ms * 1e3, 3)},
+        "first_plateau_max_abs_dev_from_2": dev,
+        "g_at_t_mid": {f"{e:.3f}": round(float(v), 5) for e, v in zip(en, g[k_mid])},
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)

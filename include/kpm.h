@@ -293,10 +293,12 @@ kpm_status kpm_sigma_e2(int n_times, int n_energies, const double *rho_msd,
  * kpm_pade_fit: [m/n] Pade approximant of Eq. 58,
  *   y(t) ~ sum_{j=0}^{m} a_j t^j / (1 + sum_{k=1}^{n} b_k t^k) (the k = 0
  *   term of the printed denominator is taken as absent: it duplicates the 1),
- *   by linear least squares on y (1 + sum b_k t^k) = sum a_j t^j over n_pts
- *   points (Householder QR in t / max|t|).  a: [m+1], b: [n] host outputs.
- *   n_pts >= m + n + 1, m + n < 32; KPM_ERR_NUMERIC if the system is rank
- *   deficient.
+ *   fitted over n_pts points by least squares on the linearised residual
+ *   y q - p, re-weighted by 1 / |q| of the previous solution `sweeps` times
+ *   (Sanathanan-Koerner iteration, which approaches the least-squares fit of
+ *   y - p/q); each solve is a Householder QR in t / max|t|.  a: [m+1], b: [n]
+ *   host outputs.  n_pts >= m + n + 1, m + n < 32, 0 <= sweeps <= 64;
+ *   KPM_ERR_NUMERIC if a system is rank deficient.
  * kpm_pade_eval: value (and, if deriv is not NULL, d/dt) of that approximant
  *   at n_pts times; sigma_E1 of a fitted MSD is pi hbar rho times deriv.
  * kpm_typical_conductance: G_typ(E) = exp(<ln G(E)>) over n_real
@@ -312,8 +314,8 @@ kpm_status kpm_ballistic_conductance(int n_times, int n_energies, const double *
 kpm_status kpm_sigma_sc_max(int n_times, int n_energies, const double *sigma, double *out);
 kpm_status kpm_sigma_sc_average(int n_times, int n_energies, const double *sigma, int k1,
                                 int k2, double *out);
-kpm_status kpm_pade_fit(int n_pts, const double *t, const double *y, int m, int n, double *a,
-                        double *b);
+kpm_status kpm_pade_fit(int n_pts, const double *t, const double *y, int m, int n, int sweeps,
+                        double *a, double *b);
 kpm_status kpm_pade_eval(int m, int n, const double *a, const double *b, int n_pts,
                          const double *t, double *value, double *deriv);
 kpm_status kpm_typical_conductance(int n_real, int n_energies, const double *g, double *out);

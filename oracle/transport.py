@@ -75,12 +75,15 @@ def sigma_sc_average(sigma, k1: int, k2: int):
     return (0.5 * (s[0] + s[-1]) + s[1:-1].sum(axis=0)) / (k2 - k1)
 
 
-def pade_fit(t, y, m: int, n: int):
+def pade_fit(t, y, m: int, n: int, sweeps: int = 8):
     """Coefficients of the [m/n] Pade approximant of Eq. 58,
     y(t) ~ sum_{j=0}^{m} a_j t^j / (1 + sum_{k=1}^{n} b_k t^k),
-    by linear least squares on y (1 + sum b_k t^k) = sum a_j t^j over the given
-    points.  The fit runs in tau = t / t_max (an exact change of variable) and
-    the coefficients are returned for t: a_j / t_max^j, b_k / t_max^k."""
+    fitted in the least-squares sense.  The paper does not say how; here the
+    linearised residual y q - p (q, p: denominator and numerator) is minimised
+    and then re-weighted by 1 / q of the previous solution, `sweeps` times
+    (the Sanathanan-Koerner iteration), which approaches the least-squares fit
+    of y - p/q itself.  Each solve runs in tau = t / t_max (an exact change of
+    variable); the coefficients are returned for t: a_j / t_max^j, b_k / t_max^k."""
     t = np.asarray(t, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     if t.shape != y.shape or t.ndim != 1 or t.shape[0] < m + n + 1:
@@ -89,7 +92,13 @@ def pade_fit(t, y, m: int, n: int):
     tau = t / ts
     cols = [tau ** j for j in range(m + 1)] + [-y * tau ** k for k in range(1, n + 1)]
     a_mat = np.stack(cols, axis=1)
-    sol = np.linalg.lstsq(a_mat, y, rcond=None)[0]
+    w = np.ones_like(t)
+    for _ in range(sweeps + 1):
+        sol = np.linalg.lstsq(a_mat * w[:, None], y * w, rcond=None)[0]
+        q = 1.0 + sum(sol[m + k] * tau ** k for k in range(1, n + 1))
+        if np.any(q == 0):
+            raise ValueError("pole at a data point")
+        w = 1.0 / np.abs(q)
     a = sol[:m + 1] / ts ** np.arange(m + 1)
     b = sol[m + 1:] / ts ** np.arange(1, n + 1)
     return a, b

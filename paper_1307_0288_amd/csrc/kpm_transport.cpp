@@ -118,28 +118,44 @@ kpm_status kpm_sigma_sc_average(int nt, int ne, const double *sigma, int k1, int
     return KPM_OK;
 }
 
-kpm_status kpm_pade_fit(int n_pts, const double *t, const double *y, int m, int n, double *a,
-                        double *b) {
-    if (m < 0 || n < 0 || m + n + 1 > 32 || n_pts < m + n + 1 || !t || !y || !a || (n > 0 && !b))
-        return bad("pade_fit arguments (n_pts >= m + n + 1, m + n < 32)");
+kpm_status kpm_pade_fit(int n_pts, const double *t, const double *y, int m, int n, int sweeps,
+                        double *a, double *b) {
+    if (m < 0 || n < 0 || m + n + 1 > 32 || n_pts < m + n + 1 || sweeps < 0 || sweeps > 64 ||
+        !t || !y || !a || (n > 0 && !b))
+        return bad("pade_fit arguments (n_pts >= m + n + 1, m + n < 32, 0 <= sweeps <= 64)");
     double ts = 0.0;
     for (int i = 0; i < n_pts; ++i) {
         if (!std::isfinite(t[i]) || !std::isfinite(y[i])) return bad("pade_fit: non-finite data");
         ts = std::fmax(ts, std::fabs(t[i]));
     }
     if (!(ts > 0)) return bad("pade_fit: all times are zero");
-    // y (1 + sum_k b_k tau^k) = sum_j a_j tau^j in tau = t / ts, linear in (a, b)
+    // Linearised residual w (y q - p) in tau = t / ts, linear in (a, b); the
+    // weight w = 1 / |q| of the previous solve (1 at first) is refreshed
+    // `sweeps` times (Sanathanan-Koerner iteration).
     const int cols = m + n + 1;
-    std::vector<double> mat((size_t)n_pts * cols), rhs(y, y + n_pts), x;
-    for (int i = 0; i < n_pts; ++i) {
-        const double tau = t[i] / ts;
-        double p = 1.0;
-        for (int j = 0; j <= m; ++j, p *= tau) mat[(size_t)j * n_pts + i] = p;
-        p = tau;
-        for (int k = 1; k <= n; ++k, p *= tau) mat[(size_t)(m + k) * n_pts + i] = -y[i] * p;
+    std::vector<double> tau(n_pts), w(n_pts, 1.0), mat, rhs, x;
+    for (int i = 0; i < n_pts; ++i) tau[i] = t[i] / ts;
+    for (int it = 0; it <= sweeps; ++it) {
+        mat.assign((size_t)n_pts * cols, 0.0);
+        rhs.resize(n_pts);
+        for (int i = 0; i < n_pts; ++i) {
+            double p = w[i];
+            for (int j = 0; j <= m; ++j, p *= tau[i]) mat[(size_t)j * n_pts + i] = p;
+            p = w[i] * tau[i];
+            for (int k = 1; k <= n; ++k, p *= tau[i]) mat[(size_t)(m + k) * n_pts + i] = -y[i] * p;
+            rhs[i] = w[i] * y[i];
+        }
+        if (!least_squares(n_pts, cols, mat, rhs, x))
+            return kpm_detail::set_error(KPM_ERR_NUMERIC, "pade_fit: rank-deficient system");
+        for (int i = 0; i < n_pts; ++i) {
+            double q = 0.0;
+            for (int k = n; k >= 1; --k) q = q * tau[i] + x[m + k];
+            q = 1.0 + tau[i] * q;
+            if (!(std::fabs(q) > 0.0))
+                return kpm_detail::set_error(KPM_ERR_NUMERIC, "pade_fit: pole at a data point");
+            w[i] = 1.0 / std::fabs(q);
+        }
     }
-    if (!least_squares(n_pts, cols, mat, rhs, x))
-        return kpm_detail::set_error(KPM_ERR_NUMERIC, "pade_fit: rank-deficient system");
     double f = 1.0;
     for (int j = 0; j <= m; ++j, f *= ts) a[j] = x[j] / f;
     f = ts;

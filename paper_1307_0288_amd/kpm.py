@@ -103,7 +103,7 @@ def lib():
             "kpm_ballistic_conductance": [C.c_int, C.c_int, dp, dp, C.c_double, C.c_double, dp],
             "kpm_sigma_sc_max": [C.c_int, C.c_int, dp, dp],
             "kpm_sigma_sc_average": [C.c_int, C.c_int, dp, C.c_int, C.c_int, dp],
-            "kpm_pade_fit": [C.c_int, dp, dp, C.c_int, C.c_int, dp, dp],
+            "kpm_pade_fit": [C.c_int, dp, dp, C.c_int, C.c_int, C.c_int, dp, dp],
             "kpm_pade_eval": [C.c_int, C.c_int, dp, dp, C.c_int, dp, dp, dp],
             "kpm_typical_conductance": [C.c_int, C.c_int, dp, dp],
             "kpm_set_launch": [vp, C.c_int, C.POINTER(Launch)],
@@ -258,14 +258,15 @@ def kpm_sigma_sc_average(sigma, k1: int, k2: int):
     return out
 
 
-def kpm_pade_fit(t, y, m: int, n: int):
-    """[m/n] Pade coefficients (a [m+1], b [n]) of Eq. 58 by linear least squares."""
+def kpm_pade_fit(t, y, m: int, n: int, sweeps: int = 8):
+    """[m/n] Pade coefficients (a [m+1], b [n]) of Eq. 58 by re-weighted
+    linearised least squares (`sweeps` re-weightings)."""
     t = np.ascontiguousarray(t, dtype=np.float64).reshape(-1)
     y = np.ascontiguousarray(y, dtype=np.float64).reshape(-1)
     if t.shape != y.shape:
         raise ValueError("t and y differ in length")
     a, b = np.empty(m + 1), np.empty(max(n, 1))
-    _check(lib().kpm_pade_fit(t.shape[0], _dp(t), _dp(y), m, n, _dp(a), _dp(b)))
+    _check(lib().kpm_pade_fit(t.shape[0], _dp(t), _dp(y), m, n, sweeps, _dp(a), _dp(b)))
     return a, b[:n]
 
 

@@ -33,3 +33,24 @@ def rel_err(got, ref, scale=None):
     got, ref = np.asarray(got), np.asarray(ref)
     s = np.max(np.abs(ref)) if scale is None else scale
     return float(np.max(np.abs(got - ref)) / s) if s > 0 else float(np.max(np.abs(got - ref)))
+
+
+def cell_trace_states(geometry, nx, ny):
+    """Unit vectors on one translation cell of a pristine ribbon, and the number
+    of cells: for an operator that commutes with the lattice translations the
+    trace over all sites is that number times the sum of the cell's diagonal
+    elements, so these states give the exact trace.  ZGNR (periodic along x)
+    repeats every 2 sites along x, AGNR (periodic along y) every 2 chains."""
+    n = nx * ny
+    if geometry == "zgnr":
+        sites = [j * nx + i for j in range(ny) for i in (0, 1)]
+        cells = nx // 2
+    elif geometry == "agnr":
+        sites = [j * nx + i for j in (0, 1) for i in range(nx)]
+        cells = ny // 2
+    else:
+        raise ValueError(geometry)
+    phi = np.zeros((n, len(sites)), dtype=np.complex128)
+    for c, s in enumerate(sites):
+        phi[s, c] = 1.0
+    return phi, cells

@@ -96,6 +96,68 @@ def test_running_conductivities_match_oracle():
     assert np.allclose(kp.kpm_sigma_e2(rows, dt), oracle.sigma_e2(rows, dt), rtol=1e-13, atol=1e-14)
 
 
+def _same(a, b, rtol=1e-13, atol=1e-14):
+    a, b = np.asarray(a), np.asarray(b)
+    assert a.shape == b.shape
+    assert np.array_equal(np.isnan(a), np.isnan(b))
+    m = ~np.isnan(a)
+    assert np.allclose(a[m], b[m], rtol=rtol, atol=atol)
+
+
+def test_transport_quantities_match_oracle():
+    """Host transport functions of the library (Eq. 50-55, 60) against the
+    oracle on random data, NaN pattern included (rho = 0 and a negative MSD
+    give NaN lengths)."""
+    from oracle import transport as tr
+    rng = np.random.default_rng(1)
+    nt, ne, dt, w = 13, 7, 0.3, 2.5
+    rho = rng.uniform(0.01, 0.1, ne)
+    rho[3] = 0.0
+    rm = rng.uniform(0.0, 5.0, (nt, ne)) * rho
+    rm[0] = 0.0
+    rm[5, 1] = -0.2
+    sig = rng.standard_normal((nt, ne))
+    lg_lib, lg_orc = kp.kpm_length(rm, rho), tr.length(rm, rho)
+    _same(lg_lib, lg_orc)
+    _same(kp.kpm_conductance(sig, lg_orc, w), tr.conductance(sig, lg_orc, w))
+    _same(kp.kpm_ballistic_conductance(rm, rho, dt, w), tr.ballistic_conductance(rm, rho, dt, w))
+    _same(kp.kpm_sigma_sc_max(sig), tr.sigma_sc_max(sig))
+    _same(kp.kpm_sigma_sc_average(sig, 2, 9), tr.sigma_sc_average(sig, 2, 9))
+    g = rng.uniform(0.01, 3.0, (6, ne))
+    _same(kp.kpm_typical_conductance(g), tr.typical_conductance(g))
+
+
+@pytest.mark.parametrize("m,n,sweeps", [(2, 2, 8), (2, 2, 0), (3, 1, 4), (1, 0, 0)])
+def test_pade_matches_oracle(m, n, sweeps):
+    from oracle import transport as tr
+    rng = np.random.default_rng(2)
+    t = np.linspace(50.0, 3000.0, 120)
+    y = 300.0 * t ** 2 / (2e5 + t ** 2) * (1 + 1e-3 * rng.standard_normal(t.shape))
+    a_l, b_l = kp.kpm_pade_fit(t, y, m, n, sweeps)
+    a_o, b_o = tr.pade_fit(t, y, m, n, sweeps)
+    v_l, d_l = kp.kpm_pade_eval(a_l, b_l, t)
+    v_o, d_o = tr.pade_eval(a_o, b_o, t)
+    # two independent least-squares solvers: agreement to the conditioning of the fit
+    assert np.allclose(v_l, v_o, rtol=1e-8, atol=1e-10 * np.abs(v_o).max())
+    assert np.allclose(d_l, d_o, rtol=1e-6, atol=1e-8 * np.abs(d_o).max())
+    # evaluation alone, same coefficients
+    v2, d2 = kp.kpm_pade_eval(a_o, b_o, t)
+    assert np.allclose(v2, v_o, rtol=1e-13) and np.allclose(d2, d_o, rtol=1e-12, atol=1e-15)
+
+
+def test_transport_rejects_bad_arguments():
+    with pytest.raises(kp.KpmError):
+        kp.kpm_sigma_sc_average(np.zeros((5, 2)), 3, 3)
+    with pytest.raises(kp.KpmError):
+        kp.kpm_sigma_sc_max(np.zeros((1, 2)))
+    with pytest.raises(kp.KpmError):
+        kp.kpm_pade_fit(np.arange(3.0), np.arange(3.0), 2, 2)      # too few points
+    with pytest.raises(kp.KpmError):
+        kp.kpm_typical_conductance(np.array([[1.0, -1.0]]))
+    with pytest.raises(kp.KpmError):
+        kp.kpm_conductance(np.ones((2, 2)), np.ones((2, 2)), 0.0)
+
+
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(kb, "LIB_PATH", str(tmp_path / "missing.so"))
     monkeypatch.setattr(kb, "_lib", None)
