@@ -135,3 +135,31 @@ def sheet_config(name: str) -> dict:
         return dict(count=32, seed=4000, n_min=1e4, n_max=1e6, w_min=20, w_max=400,
                     n_vec=8, n_moments=1000, t=-2.7)
     raise KeyError(name)
+
+
+def learned_sample_specs(count: int, seed: int) -> list:
+    """Disordered sheets for the learned reconstruction: per sample a vacancy
+    fraction uniform in [0, 0.02) and an Anderson width W uniform in [0, 2) eV
+    (W rounded to a float32 value), and the seeds of its disorder, vacancies and
+    random vectors (1000 + k, 2000 + k, 3000 + 100 k with k = seed + index)."""
+    u = uniform(seed, 2 * count)
+    out = []
+    for s in range(count):
+        k = seed + s
+        out.append(dict(vac=float(0.02 * u[2 * s]),
+                        w=float(np.float32(2.0 * u[2 * s + 1])),
+                        onsite_seed=1000 + k, vac_seed=2000 + k, vec_seed=3000 + 100 * k))
+    return out
+
+
+def mlp_init(sizes, seed: int) -> list:
+    """Initial weights of a fully connected network with layer widths `sizes`
+    (Glorot-uniform W_l in [-a, a), a = sqrt(6 / (fan_in + fan_out)), zero
+    biases), as float32 values held in float64: [(W_l [out, in], b_l [out])]."""
+    params = []
+    for l in range(len(sizes) - 1):
+        fi, fo = sizes[l], sizes[l + 1]
+        a = np.sqrt(6.0 / (fi + fo))
+        w = (a * (2.0 * uniform(seed + l, fi * fo) - 1.0)).astype(np.float32).astype(np.float64)
+        params.append((w.reshape(fo, fi), np.zeros(fo)))
+    return params
