@@ -321,21 +321,86 @@ kpm_status kpm_pade_eval(int m, int n, const double *a, const double *b, int n_p
 kpm_status kpm_typical_conductance(int n_real, int n_energies, const double *g, double *out);
 
 /*
+ * Learned moment-to-spectrum reconstruction (not part of the paper's method;
+ * plain Jackson-damped KPM of the full moment set stays the reference and the
+ * fallback).  A fully connected network of n_layers weight layers with widths
+ * widths[0 .. n_layers]: hidden a_{l+1} = tanh(a_l W_l^T + b_l), linear output,
+ * trained on the mean squared error with Adam (Kingma and Ba), FP32 throughout.
+ * Parameters are packed [W_0 (widths[1] x widths[0], row-major), b_0, W_1,
+ * b_1, ...].  x, y: device [batch][widths[0]] and [batch][widths[n_layers]]
+ * float arrays, batch <= max_batch.  All work on hip_stream; calls that return
+ * host values synchronise it.  Parameters start at zero; kpm_mlp_set_params
+ * also resets the Adam state.
+ */
+typedef struct kpm_mlp kpm_mlp;
+typedef struct {
+    float lr, beta1, beta2, eps;
+} kpm_adam;
+kpm_status kpm_mlp_create(int n_layers, const int32_t *widths, int max_batch, int device,
+                          void *hip_stream, kpm_mlp **out);
+kpm_status kpm_mlp_destroy(kpm_mlp *net);
+int64_t kpm_mlp_n_params(const kpm_mlp *net);
+kpm_status kpm_mlp_set_params(kpm_mlp *net, const float *params);   /* host [n_params] */
+kpm_status kpm_mlp_get_params(kpm_mlp *net, float *params);         /* host [n_params] */
+/* y <- network(x). */
+kpm_status kpm_mlp_forward(kpm_mlp *net, int batch, const float *x, float *y);
+/* loss = mean (network(x) - y)^2 (host); grads (host [n_params], may be NULL). */
+kpm_status kpm_mlp_gradients(kpm_mlp *net, int batch, const float *x, const float *y,
+                             double *loss, float *grads);
+/* One Adam step on the batch; loss (host) is that of the parameters before it. */
+kpm_status kpm_mlp_train_step(kpm_mlp *net, int batch, const float *x, const float *y,
+                              const kpm_adam *opt, double *loss);
+
+/*
+ * Features and targets of the learned reconstruction, from moments of
+ * n_samples samples with n_vec random vectors each (real parts, host
+ * [n_samples][n_vec][n_moments]; averaged over the vectors first): with mu the
+ * DOS moments (Eq. 46) and c the MSD moments at one time t* (Eq. 44),
+ *   x = [mu_n / mu_0, n < n_in] + [c_n / c_0, n < n_in] + [ln(c_0 / mu_0)]
+ *       (host float [n_samples][2 n_in + 1]),
+ *   y = [10 eV rho(E_k) Omega / (2 mu_0)] + [0.25 sigma_E2(E_k, t*) / (e^2/h)]
+ *       (host float [n_samples][2 n_energies]),
+ * rho and rho Delta X^2 being the Jackson-damped KPM sums (Eq. 29-31) of all
+ * n_moments moments on the device (hip_stream) and sigma_E2 = pi hbar rho
+ * Delta X^2 / t* (Eq. 11).
+ */
+kpm_status kpm_learned_features(int n_samples, int n_vec, int n_moments, const double *mu_dos,
+                                const double *mu_msd, int n_in, float *x);
+kpm_status kpm_learned_targets(int n_samples, int n_vec, int n_moments, const double *mu_dos,
+                               const double *mu_msd, int n_energies, const double *energies,
+                               double e_scale, double area_nm2, double t_star_fs,
+                               void *hip_stream, float *y);
+
+/*
+ * [X, U(n_steps dt)] phi by the recursion of Eq. 44 (the state whose moments
+ * kpm_msd takes at t = n_steps dt), written to the device buffer out (same
+ * layout as phi, must not alias it).  n_steps >= 1.  Asynchronous.
+ */
+kpm_status kpm_xu_state(kpm_system *sys, int n_vec, const void *phi, int n_steps, double dt_fs,
+                        int n_bessel, void *out);
+
+/*
  * Launch shape of the Chebyshev moment step for a given n_vec: work-groups
  * per compute unit of the persistent grid (1..32; the grid is rounded to a
  * multiple of the 8 XCDs), elements per thread per pass (ilp: 1, 2 or 4),
  * streaming (non-temporal) access to the operands read or written once per
  * step (0 or 1), and whether neighbours are read in the compact pattern form
  * (1) or from the explicit list (0; the explicit list is used regardless when
- * the system has no compact form).  At a fixed grid size the moments are
- * bit-identical for every ilp, streaming and compact choice; the grid size
- * changes only the order of the inner-product partial sums.
+ * the system has no compact form).  tiled = 1 visits the rows of a lattice
+ * sample strip by strip (tiles of consecutive columns of successive chains,
+ * the chain length found from the most common neighbour offset beyond 1) so
+ * that a row's vertical neighbour is reused from cache even when a row
+ * carries many vectors; samples without such a chain structure keep row
+ * order.  At a fixed grid size and traversal the moments are bit-identical for
+ * every ilp, streaming and compact choice; the grid size and the traversal
+ * change only the order of the inner-product partial sums.
  */
 typedef struct {
     int32_t groups_per_cu;
     int32_t ilp;
     int32_t streaming;
     int32_t compact;
+    int32_t tiled;
 } kpm_launch;
 
 kpm_status kpm_set_launch(kpm_system *sys, int n_vec, const kpm_launch *launch);

@@ -4,7 +4,8 @@
 
 Every call recompiles.  The library is the kernels (csrc/kpm_kernels.hip)
 plus the host driver and C ABI (csrc/kpm_host.cpp, csrc/kpm_transport.cpp,
-include/kpm.h).
+csrc/kpm_learned.cpp, include/kpm.h) and the network of the learned
+reconstruction (csrc/kpm_mlp.hip).
 """
 from __future__ import annotations
 
@@ -19,7 +20,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libkpm.so")
 OBJDIR = os.path.join(PKG, "_build")
-SOURCES = ["kpm_kernels.hip", "kpm_host.cpp", "kpm_transport.cpp"]
+SOURCES = ["kpm_kernels.hip", "kpm_host.cpp", "kpm_transport.cpp", "kpm_learned.cpp",
+           "kpm_mlp.hip"]
 ARCH = "gfx950"
 
 

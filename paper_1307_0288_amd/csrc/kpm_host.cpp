@@ -99,7 +99,43 @@ struct DeviceGuard {
 bool valid_launch(const kpm_launch &l) {
     return l.groups_per_cu >= 1 && l.groups_per_cu <= 32 &&
            (l.ilp == 1 || l.ilp == 2 || l.ilp == 4) && (l.streaming == 0 || l.streaming == 1) &&
-           (l.compact == 0 || l.compact == 1);
+           (l.compact == 0 || l.compact == 1) && (l.tiled == 0 || l.tiled == 1);
+}
+
+// Tile width (rows) of the tiled traversal for 2^vshift vectors per row: a
+// power of two with tw << vshift a multiple of the block, at least 64 rows.
+int tile_rows(int vshift) { return std::max(64, kpm::kBlock >> vshift); }
+
+// Chain length of a lattice sample: the most common neighbour offset beyond 1
+// when it divides the rows and spans at least two tiles; 0 otherwise.
+int32_t chain_length(const std::vector<int32_t> &nbr, int w, int64_t n) {
+    std::vector<std::pair<int64_t, int64_t>> counts;    // (offset, count), few distinct
+    for (int64_t r = 0; r < n; ++r)
+        for (int k = 0; k < w; ++k) {
+            const int32_t m = nbr[(size_t)k * n + r];
+            if (m < 0) continue;
+            const int64_t d = m > r ? m - r : r - m;
+            if (d <= 1) continue;
+            bool found = false;
+            for (auto &c : counts)
+                if (c.first == d) {
+                    ++c.second;
+                    found = true;
+                    break;
+                }
+            if (!found) {
+                if (counts.size() >= 64) return 0;       // not a lattice
+                counts.emplace_back(d, 1);
+            }
+        }
+    int64_t best = 0, cnt = 0;
+    for (const auto &c : counts)
+        if (c.second > cnt) {
+            best = c.first;
+            cnt = c.second;
+        }
+    if (best < 2 * 64 || best >= ((int64_t)1 << 30) || n % best != 0 || n / best < 2) return 0;
+    return (int32_t)best;
 }
 
 // Launch shape used until kpm_autotune or kpm_set_launch picks another.
@@ -113,6 +149,9 @@ kpm_launch default_launch(int vshift, kpm_precision prec) {
     l.ilp = (vshift >= 6 && prec == KPM_FP32_STATES) ? 4 : 1;
     l.streaming = vshift == 0 ? 0 : 1;
     l.compact = vshift <= 3 ? 1 : 0;
+    // with 8+ vectors per row a row's vertical neighbour lies megabytes ahead in
+    // row order, beyond an XCD's L2
+    l.tiled = vshift >= 3 ? 1 : 0;
     return l;
 }
 
@@ -211,6 +250,7 @@ struct kpm_system {
     std::vector<int64_t> off;
     std::vector<double> es;
     std::vector<double> seg_t;   // uniform hopping / E_s of each sample
+    std::vector<int32_t> chain;  // chain length of each sample (tiled traversal), 0 = none
     // device Hamiltonian
     int32_t *d_nbr = nullptr;   // explicit neighbour list, or
     uint8_t *d_pid = nullptr;   // compact form: pattern id per row
@@ -224,7 +264,7 @@ struct kpm_system {
     double2 *d_alpha = nullptr;  // [nseg] velocity prefactor -i E_s / hbar (batches)
     // segment tables per (vshift, requested groups); batches only
     struct SegTab {
-        int vshift, groups;
+        int vshift, groups, tiled;
         int nwg;
         kpm::Seg *seg;
         int32_t *wg;
@@ -255,13 +295,14 @@ struct kpm_system {
     hipStream_t cap = nullptr;
     struct GraphKey {
         const void *phil, *phir, *a, *b, *partial, *dmom;
-        int nm, vshift, groups, ilp, streaming, compact, dbl;
+        int nm, vshift, groups, ilp, streaming, compact, tiled, dbl;
         int64_t stride_r, offset;
         bool operator==(const GraphKey &o) const {
             return phil == o.phil && phir == o.phir && a == o.a && b == o.b &&
                    partial == o.partial && dmom == o.dmom && nm == o.nm && vshift == o.vshift &&
                    groups == o.groups && ilp == o.ilp && streaming == o.streaming &&
-                   compact == o.compact && dbl == o.dbl && stride_r == o.stride_r &&
+                   compact == o.compact && tiled == o.tiled && dbl == o.dbl &&
+                   stride_r == o.stride_r &&
                    offset == o.offset;
         }
     };
@@ -334,6 +375,10 @@ struct kpm_system {
         sw.ilp = l.ilp;
         sw.nt = l.streaming;
         const int64_t want = std::max<int64_t>(kpm::kXcds, ((int64_t)cus * l.groups_per_cu) / kpm::kXcds * kpm::kXcds);
+        const int tw = tile_rows(vshift);
+        auto tiling = [&](int s, int32_t *tnx) {
+            *tnx = (l.tiled && chain[s] >= 2 * tw) ? chain[s] : 0;
+        };
         if (nseg == 1) {
             const int64_t nblk = (sw.total + kpm::kBlock - 1) / kpm::kBlock;
             const int64_t cap = ((nblk + kpm::kXcds - 1) / kpm::kXcds) * kpm::kXcds;
@@ -341,12 +386,14 @@ struct kpm_system {
             sw.nseg = 1;
             sw.seg = nullptr;
             sw.wg_seg = nullptr;
-            sw.one = kpm::Seg{0, sw.total, 0, sw.nwg, seg_t[0], 1.0 / es[0]};
+            int32_t tnx;
+            tiling(0, &tnx);
+            sw.one = kpm::Seg{0, sw.total, 0, sw.nwg, seg_t[0], 1.0 / es[0], tnx, tw};
             *out = sw;
             return KPM_OK;
         }
         for (const SegTab &t : segtabs) {
-            if (t.vshift == vshift && t.groups == l.groups_per_cu) {
+            if (t.vshift == vshift && t.groups == l.groups_per_cu && t.tiled == l.tiled) {
                 sw.nwg = t.nwg;
                 sw.nseg = nseg;
                 sw.seg = t.seg;
@@ -363,15 +410,17 @@ struct kpm_system {
             const int64_t nblk = ((rows << vshift) + kpm::kBlock - 1) / kpm::kBlock;
             int64_t u = (int64_t)std::llround((double)units * rows / (double)n);
             u = std::max<int64_t>(1, std::min(u, (nblk + kpm::kXcds - 1) / kpm::kXcds));
+            int32_t tnx;
+            tiling(s, &tnx);
             seg[s] = kpm::Seg{off[s] << vshift, off[s + 1] << vshift, (int32_t)g0,
-                              (int32_t)(u * kpm::kXcds), seg_t[s], 1.0 / es[s]};
+                              (int32_t)(u * kpm::kXcds), seg_t[s], 1.0 / es[s], tnx, tw};
             g0 += u * kpm::kXcds;
         }
         if (g0 > (1 << 30)) return fail(KPM_ERR_INVALID, "batch needs too many work-groups");
         std::vector<int32_t> wg(g0);
         for (int s = 0; s < nseg; ++s)
             for (int g = 0; g < seg[s].nwg; ++g) wg[seg[s].g0 + g] = s;
-        SegTab t{vshift, l.groups_per_cu, (int)g0, nullptr, nullptr};
+        SegTab t{vshift, l.groups_per_cu, l.tiled, (int)g0, nullptr, nullptr};
         KPM_HIP(hipMalloc(&t.seg, seg.size() * sizeof(kpm::Seg)));
         KPM_HIP(hipMalloc(&t.wg, wg.size() * sizeof(int32_t)));
         KPM_HIP(hipMemcpy(t.seg, seg.data(), seg.size() * sizeof(kpm::Seg), hipMemcpyHostToDevice));
@@ -590,7 +639,7 @@ kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir
     kpm_system::GraphKey key{phil, phir, a_buf, b_buf, sys->partial, sys->dmom, nm, vshift,
                              sys->launch[vshift].groups_per_cu, sys->launch[vshift].ilp,
                              sys->launch[vshift].streaming, sys->launch[vshift].compact,
-                             dbl ? 1 : 0, stride_r, offset};
+                             sys->launch[vshift].tiled, dbl ? 1 : 0, stride_r, offset};
     hipGraphExec_t exec = sys->find_graph(key);
     if (!exec) {
         KPM_TRY(sys->ensure_capture_stream());
@@ -799,6 +848,32 @@ kpm_status msd_impl(kpm_system *sys, int vshift, const void *phi_v, int nsteps, 
     return KPM_OK;
 }
 
+// Y_n = [X, U(n dt)] phi by the recursion of Eq. 44, copied to out.
+template <typename V>
+kpm_status xu_state_impl(kpm_system *sys, int vshift, const void *phi_v, int nsteps, double dt,
+                         int np, void *out) {
+    KPM_TRY(sys->ensure_vecs(9, vshift));
+    V *pa = (V *)sys->vecs[0], *pb = (V *)sys->vecs[1], *qa = (V *)sys->vecs[2],
+      *qb = (V *)sys->vecs[3];
+    V *y = (V *)sys->vecs[4], *y2 = (V *)sys->vecs[5], *xu = (V *)sys->vecs[6];
+    V *psi = (V *)sys->vecs[7], *psi2 = (V *)sys->vecs[8];
+    const V *cur = (const V *)phi_v;
+    for (int k = 1; k <= nsteps; ++k) {
+        KPM_TRY(run_evolve_x<V>(sys, vshift, cur, xu, psi2, dt, np, pa, pb, qa, qb));
+        std::swap(psi, psi2);
+        cur = psi;
+        if (k == 1) {
+            std::swap(y, xu);
+        } else {
+            KPM_TRY(run_evolve<V>(sys, vshift, y, y2, xu, dt, +1, np, pa, pb));
+            std::swap(y, y2);
+        }
+    }
+    KPM_HIP(hipMemcpyAsync(out, y, sys->state_bytes(vshift), hipMemcpyDeviceToDevice, sys->stream));
+    KPM_HIP(hipGetLastError());
+    return KPM_OK;
+}
+
 // Fourier moments of Alg. 4: F_n = <phi_L| U(n dtau) |phi_R>, n = -nm .. nm,
 // reduced into sys->dmom[(s * R + r) * (2 nm + 1) + nm + n].
 template <typename V>
@@ -841,6 +916,9 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
     static const int groups[] = {4, 8, 16};
     static const int ilps[] = {1, 2, 4};
     const int forms = sys->d_pid ? 2 : 1;
+    bool can_tile = false;
+    for (int32_t c : sys->chain) can_tile = can_tile || c >= 2 * tile_rows(vs);
+    const int tilings = can_tile ? 2 : 1;
     hipEvent_t e0, e1;
     KPM_HIP(hipEventCreate(&e0));
     KPM_HIP(hipEventCreate(&e1));
@@ -878,12 +956,13 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
     float best_ms = 1e30f;
     st = time_shape(pick, &best_ms);
     for (int g : groups) {
-        for (int q = 0; q < 6 * forms && st == KPM_OK; ++q) {
+        for (int q = 0; q < 6 * forms * tilings && st == KPM_OK; ++q) {
             kpm_launch l;
             l.groups_per_cu = g;
             l.ilp = ilps[q % 3];
             l.streaming = (q / 3) % 2;
-            l.compact = forms == 2 ? q / 6 : 0;
+            l.compact = forms == 2 ? (q / 6) % 2 : 0;
+            l.tiled = tilings == 2 ? q / (6 * forms) : 0;
             float ms = 0;
             if ((st = time_shape(l, &ms)) != KPM_OK) break;
             if (ms < 0.98f * best_ms) {
@@ -945,6 +1024,10 @@ kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int devi
         for (auto &l : sys->launch) l.streaming = atoi(env) != 0;
     if (const char *env = std::getenv("KPM_COMPACT_LAUNCH"))
         for (auto &l : sys->launch) l.compact = atoi(env) != 0;
+    if (const char *env = std::getenv("KPM_TILED"))
+        for (auto &l : sys->launch) l.tiled = atoi(env) != 0;
+    sys->chain.resize(nseg);
+    for (int s = 0; s < nseg; ++s) sys->chain[s] = chain_length(parts[s].nbr, parts[s].w, parts[s].n);
 
     // Concatenate and shift indices by the sample offset; per-slot weights
     // carry 1/E_s of their sample.
@@ -1235,6 +1318,21 @@ kpm_status kpm_msd_doubled(kpm_system *sys, int n_vec, const void *phi, int n_st
     return sys->prec == KPM_FP64
                ? msd_impl<double2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, out, true)
                : msd_impl<float2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, out, true);
+}
+
+kpm_status kpm_xu_state(kpm_system *sys, int n_vec, const void *phi, int n_steps, double dt_fs,
+                        int n_bessel, void *out) {
+    int vs;
+    KPM_TRY(check_common(sys, n_vec, &vs));
+    if (!phi || !out || phi == out) return fail(KPM_ERR_INVALID, "null or aliased buffer");
+    if (!sys->has_dx) return fail(KPM_ERR_INVALID, "system has no dx (velocity operator)");
+    if (n_steps < 1) return fail(KPM_ERR_INVALID, "n_steps must be >= 1");
+    if (n_bessel < 2) return fail(KPM_ERR_INVALID, "n_bessel must be >= 2");
+    if (!std::isfinite(dt_fs) || dt_fs < 0) return fail(KPM_ERR_INVALID, "dt_fs");
+    DeviceGuard g(sys->device);
+    return sys->prec == KPM_FP64
+               ? xu_state_impl<double2>(sys, vs, phi, n_steps, dt_fs, n_bessel, out)
+               : xu_state_impl<float2>(sys, vs, phi, n_steps, dt_fs, n_bessel, out);
 }
 
 kpm_status kpm_fourier_moments(kpm_system *sys, int n_vec, const void *phi_l, const void *phi_r,

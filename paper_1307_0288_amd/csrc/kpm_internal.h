@@ -38,10 +38,19 @@ struct Ell {
 // [e0, e1), the contiguous work-groups [g0, g0 + nwg) that sweep it (g0 and
 // nwg multiples of 8), its uniform hopping t / E_s and its 1 / E_s.  A plain
 // system is a single segment.
+//
+// Tiled traversal (tnx > 0): the segment's rows form chains of tnx rows (a
+// lattice whose vertical bonds join row i to row i +- tnx).  Blocks are then
+// visited strip by strip: strip s holds columns [s tw, (s + 1) tw) of every
+// chain, chain after chain, so the vertical neighbour of a row is gathered
+// shortly after (or before) it is read in the neighbouring chain's tile, from
+// L2, however many vectors a row carries.  tw is a power of two with tw << R
+// a multiple of the block; the last strip is padded (masked elements).
 struct Seg {
     int64_t e0, e1;
     int32_t g0, nwg;
     double t, inv_es;
+    int32_t tnx, tw;       // chain length and tile width in rows; tnx = 0: row order
 };
 
 // Persistent, XCD-aware sweep.  Work-groups are dispatched round-robin over

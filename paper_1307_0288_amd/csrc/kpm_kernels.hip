@@ -100,7 +100,27 @@ struct Walk {
     int loc, nloc;
     int64_t b0, b1, e0, e1;
     double t, inv_es;
+    // tiled traversal (tnx > 0): blocks per tile = 1 << lbps, nch chains
+    int32_t tnx, tw, lbps, nch;
 };
+
+// Element of thread `tid` in logical block b of the walk's segment, and
+// whether it exists.  Row order: consecutive blocks.  Tiled: block b is part
+// k of tile t = b >> lbps, the tile of chain j = t % nch in strip s = t / nch.
+__device__ __forceinline__ bool block_elem(const Walk &w, int64_t b, int tid, int vshift,
+                                           int64_t &e) {
+    if (w.tnx == 0) {
+        e = w.e0 + b * kBlock + tid;
+        return e < w.e1;
+    }
+    const uint32_t t = (uint32_t)(b >> w.lbps);
+    const uint32_t s = t / (uint32_t)w.nch;
+    const uint32_t j = t - s * (uint32_t)w.nch;
+    const int64_t loc = ((b & ((1 << w.lbps) - 1)) * kBlock) + tid;
+    const int64_t width = min((int64_t)w.tw, (int64_t)w.tnx - (int64_t)s * w.tw);
+    e = w.e0 + (((int64_t)j * w.tnx + (int64_t)s * w.tw) << vshift) + loc;
+    return loc < (width << vshift);
+}
 
 // Neighbour-offset patterns of the compact form, staged in LDS by every
 // work-group (at most kMaxPatterns x kMaxWidth words).
@@ -231,7 +251,19 @@ __device__ __forceinline__ Walk walk_of(const Sweep &sw) {
     const int lb = (int)blockIdx.x - s.g0;      // g0 % 8 == 0: lb % 8 is the XCD
     w.loc = lb / kXcds;
     w.nloc = s.nwg / kXcds;
-    const int64_t nblk = (s.e1 - s.e0 + kBlock - 1) / kBlock;
+    w.tnx = s.tnx;
+    w.tw = s.tw;
+    int64_t nblk;
+    if (s.tnx > 0) {
+        const int64_t rows = (s.e1 - s.e0) >> sw.vshift;
+        w.nch = (int32_t)(rows / s.tnx);
+        w.lbps = 31 - __builtin_clz((uint32_t)((s.tw << sw.vshift) / kBlock));
+        nblk = ((int64_t)(s.tnx + s.tw - 1) / s.tw) * w.nch << w.lbps;
+    } else {
+        w.nch = 0;
+        w.lbps = 0;
+        nblk = (s.e1 - s.e0 + kBlock - 1) / kBlock;
+    }
     const int64_t per = (nblk + kXcds - 1) / kXcds;
     w.b0 = (int64_t)(lb % kXcds) * per;
     w.b1 = min(w.b0 + per, nblk);
@@ -248,8 +280,8 @@ __device__ __forceinline__ Walk walk_of(const Sweep &sw) {
     const int sg = wk_.sg;                                                          \
     (void)sg;                                                                       \
     for (int64_t b_ = wk_.b0 + wk_.loc; b_ < wk_.b1; b_ += wk_.nloc) {              \
-        const int64_t e = wk_.e0 + b_ * kBlock + threadIdx.x;                       \
-        if (e < wk_.e1) {                                                           \
+        int64_t e;                                                                  \
+        if (block_elem(wk_, b_, threadIdx.x, (sw).vshift, e)) {                     \
             const int64_t i = e >> (sw).vshift;                                     \
             const int64_t v = e & ((1 << (sw).vshift) - 1);
 #define KPM_SWEEP_END \
@@ -325,8 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_moment_step(Ell h, Sweep sw, const V
 #pragma unroll
         for (int u = 0; u < ILP; ++u) {
             const int64_t bu = b + (int64_t)u * wk.nloc;
-            e[u] = wk.e0 + bu * kBlock + threadIdx.x;
-            ok[u] = bu < wk.b1 && e[u] < wk.e1;
+            ok[u] = bu < wk.b1 && block_elem(wk, bu, threadIdx.x, sw.vshift, e[u]);
             e[u] = ok[u] ? e[u] : 0;          // a safe element; its result is dropped
         }
         int32_t m[ILP][F::width];
@@ -493,8 +524,9 @@ __global__ __launch_bounds__(kBlock) void k_dot(Sweep sw, const V *__restrict__ 
     double2 s0 = make_double2(0.0, 0.0);
     const Walk wk = walk_of(sw);
     for (int64_t blk = wk.b0 + wk.loc; blk < wk.b1; blk += wk.nloc) {
-        const int64_t e = wk.e0 + blk * kBlock + threadIdx.x;
-        if (e < wk.e1) s0 = cdot_acc(s0, ld_nt(a + e), ld_nt(b + e));
+        int64_t e;
+        if (block_elem(wk, blk, threadIdx.x, sw.vshift, e))
+            s0 = cdot_acc(s0, ld_nt(a + e), ld_nt(b + e));
     }
     const int64_t r = (int64_t)1 << sw.vshift;
     block_sum(s0, sw.vshift, partial + ((int64_t)slot * sw.nwg + blockIdx.x) * r);

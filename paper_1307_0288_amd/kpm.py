@@ -33,6 +33,10 @@ ABI_SYMBOLS = ("kpm_build_graphene", "kpm_system_create", "kpm_system_destroy",
                "kpm_sigma_e1", "kpm_sigma_e2", "kpm_length", "kpm_conductance",
                "kpm_ballistic_conductance", "kpm_sigma_sc_max", "kpm_sigma_sc_average",
                "kpm_pade_fit", "kpm_pade_eval", "kpm_typical_conductance",
+               "kpm_mlp_create", "kpm_mlp_destroy", "kpm_mlp_n_params", "kpm_mlp_set_params",
+               "kpm_mlp_get_params", "kpm_mlp_forward", "kpm_mlp_gradients",
+               "kpm_mlp_train_step", "kpm_learned_features", "kpm_learned_targets",
+               "kpm_xu_state",
                "kpm_set_launch", "kpm_get_launch",
                "kpm_autotune", "kpm_set_graphs", "kpm_set_timing", "kpm_get_stats",
                "kpm_reset_stats",
@@ -55,7 +59,15 @@ class _Desc(C.Structure):
 
 class Launch(C.Structure):
     _fields_ = [("groups_per_cu", C.c_int32), ("ilp", C.c_int32), ("streaming", C.c_int32),
-                ("compact", C.c_int32)]
+                ("compact", C.c_int32), ("tiled", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return dict(groups_per_cu=self.groups_per_cu, ilp=self.ilp, streaming=self.streaming,
+                    compact=self.compact, tiled=self.tiled)
+
+
+class Adam(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
 
 
 class Stats(C.Structure):
@@ -76,6 +88,7 @@ def lib():
                               "`python -m paper_1307_0288_amd.build` (hipcc, gfx950)")
         L = C.CDLL(LIB_PATH)
         vp, dp, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int64
+        fp = C.POINTER(C.c_float)
         sig = {
             "kpm_build_graphene": [i64, i64, C.c_int, C.POINTER(C.c_uint8), C.POINTER(C.c_int32), dp],
             "kpm_system_create": [C.POINTER(_Desc), C.c_int, C.c_int, vp, C.POINTER(vp)],
@@ -106,6 +119,18 @@ def lib():
             "kpm_pade_fit": [C.c_int, dp, dp, C.c_int, C.c_int, C.c_int, dp, dp],
             "kpm_pade_eval": [C.c_int, C.c_int, dp, dp, C.c_int, dp, dp, dp],
             "kpm_typical_conductance": [C.c_int, C.c_int, dp, dp],
+            "kpm_mlp_create": [C.c_int, C.POINTER(C.c_int32), C.c_int, C.c_int, vp,
+                               C.POINTER(vp)],
+            "kpm_mlp_destroy": [vp],
+            "kpm_mlp_set_params": [vp, fp],
+            "kpm_mlp_get_params": [vp, fp],
+            "kpm_mlp_forward": [vp, C.c_int, vp, vp],
+            "kpm_mlp_gradients": [vp, C.c_int, vp, vp, dp, fp],
+            "kpm_mlp_train_step": [vp, C.c_int, vp, vp, C.POINTER(Adam), dp],
+            "kpm_learned_features": [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, fp],
+            "kpm_learned_targets": [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, dp, C.c_double,
+                                    C.c_double, C.c_double, vp, fp],
+            "kpm_xu_state": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, vp],
             "kpm_set_launch": [vp, C.c_int, C.POINTER(Launch)],
             "kpm_get_launch": [vp, C.c_int, C.POINTER(Launch)],
             "kpm_autotune": [vp, C.c_int, vp, C.c_int, C.POINTER(Launch)],
@@ -120,6 +145,8 @@ def lib():
             f.restype = C.c_int
         L.kpm_system_n_sites.argtypes = [vp]
         L.kpm_system_n_sites.restype = C.c_int64
+        L.kpm_mlp_n_params.argtypes = [vp]
+        L.kpm_mlp_n_params.restype = C.c_int64
         L.kpm_system_n_samples.argtypes = [vp]
         L.kpm_system_n_samples.restype = C.c_int32
         L.kpm_last_error.restype = C.c_char_p
@@ -500,18 +527,17 @@ def kpm_msd_doubled(sys: System, phi, n_steps: int, dt_fs: float, n_bessel: int,
 
 
 def kpm_set_launch(sys: System, n_vec: int, groups_per_cu: int, ilp: int, streaming: int = 0,
-                   compact: int = 1):
+                   compact: int = 1, tiled: int = 0):
     """Launch shape of the moment step for n_vec vectors (see kpm_launch in kpm.h)."""
     _check(lib().kpm_set_launch(sys.handle, n_vec,
                                 C.byref(Launch(groups_per_cu, ilp, int(bool(streaming)),
-                                               int(bool(compact))))))
+                                               int(bool(compact)), int(bool(tiled))))))
 
 
 def kpm_get_launch(sys: System, n_vec: int) -> dict:
     out = Launch()
     _check(lib().kpm_get_launch(sys.handle, n_vec, C.byref(out)))
-    return dict(groups_per_cu=out.groups_per_cu, ilp=out.ilp, streaming=out.streaming,
-                compact=out.compact)
+    return out.as_dict()
 
 
 def kpm_autotune(sys: System, phi, reps: int = 10) -> dict:
@@ -520,8 +546,7 @@ def kpm_autotune(sys: System, phi, reps: int = 10) -> dict:
     out = Launch()
     sys._sync_stream()
     _check(lib().kpm_autotune(sys.handle, nv, p, reps, C.byref(out)))
-    return dict(groups_per_cu=out.groups_per_cu, ilp=out.ilp, streaming=out.streaming,
-                compact=out.compact)
+    return out.as_dict()
 
 
 def kpm_set_graphs(sys: System, enable: bool = True):
@@ -585,3 +610,124 @@ def graphene_batch(samples, precision: str = "fp64", device: int | None = None) 
     s = System.batch(descs, precision, device)
     s.samples = meta
     return s
+
+
+# ------------------------------------------------------------------ learned reconstruction
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def _f32_gpu(t, name, width):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 \
+            or t.dim() != 2 or t.shape[1] != width or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 GPU tensor [batch, {width}]")
+    return C.c_void_p(t.data_ptr())
+
+
+class MLP:
+    """Network of the learned reconstruction (kpm_mlp_create): widths d_0 .. d_L,
+    tanh hidden layers, linear output, FP32, on the current torch stream."""
+
+    def __init__(self, widths, max_batch: int, device: int | None = None):
+        import torch
+        self.widths = [int(w) for w in widths]
+        self.device = torch.cuda.current_device() if device is None else device
+        arr = (C.c_int32 * len(self.widths))(*self.widths)
+        h = C.c_void_p()
+        _check(lib().kpm_mlp_create(len(self.widths) - 1, arr, max_batch, self.device,
+                                    _stream(), C.byref(h)))
+        self._h = h
+        self.max_batch = max_batch
+
+    @property
+    def n_params(self) -> int:
+        return int(lib().kpm_mlp_n_params(self._h))
+
+    def set_params(self, flat):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        if a.size != self.n_params:
+            raise ValueError("parameter count mismatch")
+        _check(lib().kpm_mlp_set_params(self._h, _fp(a)))
+
+    def get_params(self) -> np.ndarray:
+        a = np.empty(self.n_params, dtype=np.float32)
+        _check(lib().kpm_mlp_get_params(self._h, _fp(a)))
+        return a
+
+    def forward(self, x):
+        import torch
+        b = x.shape[0]
+        y = torch.empty((b, self.widths[-1]), dtype=torch.float32, device=x.device)
+        _check(lib().kpm_mlp_forward(self._h, b, _f32_gpu(x, "x", self.widths[0]),
+                                     _f32_gpu(y, "y", self.widths[-1])))
+        return y
+
+    def gradients(self, x, y):
+        loss = C.c_double()
+        g = np.empty(self.n_params, dtype=np.float32)
+        _check(lib().kpm_mlp_gradients(self._h, x.shape[0], _f32_gpu(x, "x", self.widths[0]),
+                                       _f32_gpu(y, "y", self.widths[-1]), C.byref(loss), _fp(g)))
+        return loss.value, g
+
+    def train_step(self, x, y, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                   eps: float = 1e-8) -> float:
+        loss = C.c_double()
+        opt = Adam(lr, beta1, beta2, eps)
+        _check(lib().kpm_mlp_train_step(self._h, x.shape[0], _f32_gpu(x, "x", self.widths[0]),
+                                        _f32_gpu(y, "y", self.widths[-1]), C.byref(opt),
+                                        C.byref(loss)))
+        return loss.value
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().kpm_mlp_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _moments_real(mu):
+    """Real parts of moments [S, R, N] (or [R, N] for one sample) as float64."""
+    a = np.real(np.asarray(mu))
+    if a.ndim == 2:
+        a = a[None]
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def kpm_learned_features(mu_dos, mu_msd, n_in: int) -> np.ndarray:
+    """Features [S, 2 n_in + 1] (float32) of the learned reconstruction."""
+    d, c = _moments_real(mu_dos), _moments_real(mu_msd)
+    if d.shape != c.shape:
+        raise ValueError("DOS and MSD moments differ in shape")
+    x = np.empty((d.shape[0], 2 * n_in + 1), dtype=np.float32)
+    _check(lib().kpm_learned_features(d.shape[0], d.shape[1], d.shape[2], _dp(d), _dp(c), n_in,
+                                      _fp(x)))
+    return x
+
+
+def kpm_learned_targets(mu_dos, mu_msd, energies_ev, e_scale: float, area_nm2: float,
+                        t_star_fs: float) -> np.ndarray:
+    """Targets [S, 2 K] (float32): scaled DOS and sigma_E2(t*) from all the moments."""
+    d, c = _moments_real(mu_dos), _moments_real(mu_msd)
+    if d.shape != c.shape:
+        raise ValueError("DOS and MSD moments differ in shape")
+    en = np.ascontiguousarray(energies_ev, dtype=np.float64).reshape(-1)
+    y = np.empty((d.shape[0], 2 * en.size), dtype=np.float32)
+    _check(lib().kpm_learned_targets(d.shape[0], d.shape[1], d.shape[2], _dp(d), _dp(c), en.size,
+                                     _dp(en), e_scale, area_nm2, t_star_fs, _stream(), _fp(y)))
+    return y
+
+
+def kpm_xu_state(sys: System, phi, n_steps: int, dt_fs: float, n_bessel: int):
+    """[X, U(n_steps dt)] phi (Eq. 44) as a new device state."""
+    p, nv = sys._state(phi, "phi")
+    out = sys.new_state(nv)
+    sys._sync_stream()
+    _check(lib().kpm_xu_state(sys.handle, nv, p, n_steps, dt_fs, n_bessel,
+                              C.c_void_p(out.data_ptr())))
+    return out

@@ -150,7 +150,7 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=512)
     ap.add_argument("--copies", type=int, default=3)
     ap.add_argument("--launch", default="",
-                    help="groups_per_cu,ilp,streaming,compact (default: the library's)")
+                    help="groups_per_cu,ilp,streaming,compact[,tiled] (default: the library's)")
     ap.add_argument("--meta", default="", help="write the run's launch shape, sizes and "
                                                "algorithmic bytes here")
     ap.add_argument("--summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
@@ -178,8 +178,7 @@ def main():
                               args.precision)
     phi = sysg.upload(ki.random_phase(n, args.n_vec, 3000, act))
     if args.launch:
-        g, ilp, nt, cp = (int(x) for x in args.launch.split(","))
-        kp.kpm_set_launch(sysg, args.n_vec, g, ilp, nt, cp)
+        kp.kpm_set_launch(sysg, args.n_vec, *(int(x) for x in args.launch.split(",")))
     launch = kp.kpm_get_launch(sysg, args.n_vec)
     print(f"launch shape: {launch}", flush=True)
     kp.kpm_reset_stats(sysg)

@@ -163,3 +163,18 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(kb, "_lib", None)
     with pytest.raises(ImportError):
         kb.lib()
+
+
+def test_learned_features_match_oracle():
+    from oracle import learned as ln
+    rng = np.random.default_rng(4)
+    mu = rng.uniform(-1, 1, (3, 2, 40))
+    mu[:, :, 0] = rng.uniform(50, 60, (3, 2))
+    c = rng.uniform(-1, 1, (3, 2, 40))
+    c[:, :, 0] = rng.uniform(500, 600, (3, 2))
+    x = kp.kpm_learned_features(mu, c, 16)
+    ref = ln.features(mu, c, 16)
+    assert x.dtype == np.float32 and x.shape == (3, 33)
+    assert np.allclose(x, ref, rtol=2e-7, atol=1e-7)
+    with pytest.raises(kp.KpmError):
+        kp.kpm_learned_features(mu, c, 41)

@@ -125,14 +125,18 @@ def test_batch_launch_shapes_and_autotune():
     _need_gpu()
     cases, sysg, phis = _batch(8)
     d = sysg.upload(np.concatenate(phis))
-    ref = None
-    for ilp in (1, 2, 4):
-        for nt in (0, 1):
-            for cp in (0, 1):
-                kp.kpm_set_launch(sysg, 8, 8, ilp, nt, cp)
-                mu = kp.kpm_moments(sysg, d, d, 30)
-                ref = mu if ref is None else ref
-                assert np.array_equal(mu, ref), (ilp, nt, cp)
+    first = None
+    for tiled in (0, 1):          # the 200-row zigzag chains of one sample are tiled
+        ref = None
+        for ilp in (1, 2, 4):
+            for nt in (0, 1):
+                for cp in (0, 1):
+                    kp.kpm_set_launch(sysg, 8, 8, ilp, nt, cp, tiled)
+                    mu = kp.kpm_moments(sysg, d, d, 30)
+                    ref = mu if ref is None else ref
+                    assert np.array_equal(mu, ref), (tiled, ilp, nt, cp)
+        first = ref if first is None else first
+        assert rel_err(ref, first, float(np.abs(first[..., 0]).max())) < 1e-13
     best = kp.kpm_autotune(sysg, d, 3)
     mu = kp.kpm_moments(sysg, d, d, 30)
     assert rel_err(mu, ref, float(np.abs(ref[..., 0]).max())) < 1e-13

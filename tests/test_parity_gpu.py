@@ -322,8 +322,51 @@ def test_launch_shapes(n_vec, precision):
         assert rel_err(ref, first, float(np.abs(first[:, 0]).max())) < 1e-13
     best = kp.kpm_autotune(sysg, phi, 3)
     assert best["groups_per_cu"] in (4, 8, 16) and best["ilp"] in (1, 2, 4)
-    assert best["streaming"] in (0, 1) and best["compact"] in (0, 1)
+    assert best["streaming"] in (0, 1) and best["compact"] in (0, 1) and best["tiled"] in (0, 1)
     assert kp.kpm_get_launch(sysg, n_vec) == best
+
+
+@pytest.mark.parametrize("nx,ny,n_vec,precision", [(300, 30, 8, "fp64"), (300, 30, 64, "fp32"),
+                                                    (600, 16, 1, "fp64"), (300, 30, 64, "fp64")])
+def test_tiled_traversal(nx, ny, n_vec, precision):
+    """Strip-by-strip traversal (chains of nx rows, tiles of 64 rows for 8+
+    vectors and 256 rows for one; nx is not a multiple of the tile, so the last
+    strip is padded): moments, evolution and the VAC agree with row order up to
+    the order of the partial sums, and with the oracle; every ILP, streaming
+    and neighbour form is bit-identical under the tiled traversal."""
+    _need_gpu()
+    _log(f"tiled traversal {nx}x{ny} n_vec={n_vec} {precision}")
+    c = recipe("sheet", nx, ny, w=1.0, vac=0.01, seed=21)
+    sysg = gpu_system(c, precision)
+    phi = phases(c, n_vec, 3000)
+    d = sysg.upload(phi)
+    kp.kpm_set_launch(sysg, n_vec, 8, 1, 1, 1, 0)
+    row = kp.kpm_moments(sysg, d, d, 60)
+    e_row = d.clone()
+    kp.kpm_evolve(sysg, e_row, 0.5, 1, 20)
+    ref = None
+    for ilp in (1, 2, 4):
+        for nt in (0, 1):
+            for cp in (0, 1):
+                kp.kpm_set_launch(sysg, n_vec, 8, ilp, nt, cp, 1)
+                mu = kp.kpm_moments(sysg, d, d, 60)
+                ref = mu if ref is None else ref
+                assert np.array_equal(mu, ref), (ilp, nt, cp)
+    norm = float(np.abs(row[:, 0]).max())
+    tol = 1e-13 if precision == "fp64" else 1e-6
+    assert rel_err(ref, row, norm) < tol
+    e_t = d.clone()
+    kp.kpm_evolve(sysg, e_t, 0.5, 1, 20)
+    assert rel_err(e_t.cpu().numpy(), e_row.cpu().numpy()) < (1e-13 if precision == "fp64" else 1e-6)
+    if precision == "fp64":
+        lat = oracle_lattice(c)
+        for r in (0, n_vec - 1):
+            mo = oracle.moments(lat, c["e_scale"], phi[:, r], phi[:, r], 60)
+            assert rel_err(ref[r], mo, np.vdot(phi[:, r], phi[:, r]).real) < 1e-10
+        if n_vec <= 8:
+            gv = kp.kpm_vac(sysg, d, 2, 0.4, 16, 32)
+            rv = oracle.vac(lat, c["e_scale"], phi[:, 0], 2, 0.4, 16, 32)
+            assert rel_err(gv[0], rv) < 1e-10
 
 
 # ------------------------------------------------------------------ Fourier moments (FTM)
