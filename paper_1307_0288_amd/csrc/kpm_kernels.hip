@@ -324,6 +324,89 @@ template <int FORM> struct FormTraits {
     static constexpr bool ons_float = FORM == kFormC3F || FORM == kFormL3F;
 };
 
+// Structure form of a system (see launch_step_shape).
+inline int form_of(const Ell &h) {
+    const bool fixed = h.w == 3 && !h.hop;
+    if (fixed && h.pid) return h.onsf ? kFormC3F : kFormC3D;
+    if (fixed) return h.onsf ? kFormL3F : kFormL3D;
+    return kFormGeneric;
+}
+
+// Neighbours of row i in a fixed (width 3, uniform hopping) form.
+template <int FORM>
+__device__ __forceinline__ void row_nbrs(const Ell &h, const int32_t *lpat, int64_t i,
+                                         int32_t m[3]) {
+    if constexpr (FormTraits<FORM>::compact) {
+        const int pid = h.pid[i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int32_t d = lpat[pid * kMaxWidth + k];
+            m[k] = d == kEmptySlot ? -1 : (int32_t)(i + d);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) m[k] = h.nbr[k * h.n + i];
+    }
+}
+
+template <int FORM>
+__device__ __forceinline__ double row_ons_f(const Ell &h, const Walk &wk, int64_t i) {
+    if constexpr (FormTraits<FORM>::ons_float)
+        return (double)h.onsf[i] * wk.inv_es;
+    else
+        return h.ons[i];
+}
+
+// row_h with the structure form fixed at compile time (same operations, in
+// the same order, as row_h).
+template <int FORM, typename V>
+__device__ __forceinline__ double2 row_h_f(const Ell &h, const Walk &wk, const int32_t *lpat,
+                                           const V *x, int64_t i, int64_t v, int vshift,
+                                           double2 xi) {
+    if constexpr (FormTraits<FORM>::generic) {
+        return row_h(h, wk, lpat, x, i, v, vshift, xi);
+    } else {
+        int32_t m[3];
+        row_nbrs<FORM>(h, lpat, i, m);
+        const double o = row_ons_f<FORM>(h, wk, i);
+        double2 xm[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xm[k] = ld(x + ((int64_t)(m[k] < 0 ? 0 : m[k]) << vshift) + v);
+        double2 acc = make_double2(o * xi.x, o * xi.y);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc = raxpy(acc, m[k] < 0 ? 0.0 : wk.t, xm[k]);
+        return acc;
+    }
+}
+
+// row_hd with the structure form fixed at compile time.
+template <int FORM, typename V>
+__device__ __forceinline__ void row_hd_f(const Ell &h, const Walk &wk, const int32_t *lpat,
+                                         const V *x, int64_t i, int64_t v, int vshift,
+                                         double2 xi, double2 &hx, double2 &dx) {
+    if constexpr (FormTraits<FORM>::generic) {
+        row_hd(h, wk, lpat, x, i, v, vshift, xi, hx, dx);
+    } else {
+        int32_t m[3];
+        row_nbrs<FORM>(h, lpat, i, m);
+        const double o = row_ons_f<FORM>(h, wk, i);
+        double2 xm[3];
+        double xk[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            xm[k] = ld(x + ((int64_t)(m[k] < 0 ? 0 : m[k]) << vshift) + v);
+            xk[k] = h.xw[k * h.n + i];
+        }
+        hx = make_double2(o * xi.x, o * xi.y);
+        dx = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            hx = raxpy(hx, m[k] < 0 ? 0.0 : wk.t, xm[k]);
+            dx = raxpy(dx, m[k] < 0 ? 0.0 : xk[k], xm[k]);
+        }
+    }
+}
+
 // Recursion step of the moments, out = 2 H~ p1 - p0 and <L|out>, with ILP
 // elements per thread per pass: all loads of the ILP elements are issued
 // before any arithmetic, so a wavefront keeps ILP times more bytes in flight
@@ -453,14 +536,14 @@ __global__ __launch_bounds__(kBlock) void k_undouble(double2 *__restrict__ mom, 
     c[j] = make_double2(fma(2.0, a.x, -b.x), fma(2.0, a.y, -b.y));
 }
 
-template <typename V, bool FIRST>
+template <typename V, bool FIRST, int FORM>
 __global__ __launch_bounds__(kBlock) void k_evolve_step(Ell h, Sweep sw, const V *p1,
                                                         const V *p0, V *out, V *acc,
                                                         const V *add, Coef c0, Coef c) {
     KPM_SWEEP_BEGIN(sw, h)
     const double2 cm = coef(c, sg);
     const double2 xi = ld(p1 + e);
-    const double2 hx = row_h(h, wk_, lpat, p1, i, v, sw.vshift, xi);
+    const double2 hx = row_h_f<FORM>(h, wk_, lpat, p1, i, v, sw.vshift, xi);
     double2 o, a;
     if (FIRST) {
         o = rounded<V>(hx);
@@ -475,7 +558,7 @@ __global__ __launch_bounds__(kBlock) void k_evolve_step(Ell h, Sweep sw, const V
     KPM_SWEEP_END
 }
 
-template <typename V, bool FIRST>
+template <typename V, bool FIRST, int FORM>
 __global__ __launch_bounds__(kBlock) void k_evolve_x_step(Ell h, Sweep sw, const V *p1,
                                                           const V *p0, V *pout,
                                                           const V *q1, const V *q0,
@@ -485,7 +568,7 @@ __global__ __launch_bounds__(kBlock) void k_evolve_x_step(Ell h, Sweep sw, const
     const double2 cm = coef(c, sg);
     const double2 xi = ld(p1 + e);
     double2 hp, dp;
-    row_hd(h, wk_, lpat, p1, i, v, sw.vshift, xi, hp, dp);
+    row_hd_f<FORM>(h, wk_, lpat, p1, i, v, sw.vshift, xi, hp, dp);
     if (FIRST) {
         hp = rounded<V>(hp);
         dp = rounded<V>(dp);
@@ -495,7 +578,7 @@ __global__ __launch_bounds__(kBlock) void k_evolve_x_step(Ell h, Sweep sw, const
         st_nt(accu + e, cmla(cmul(coef(c0, sg), xi), cm, hp));
     } else {
         const double2 qi = ld(q1 + e);
-        const double2 hq = row_h(h, wk_, lpat, q1, i, v, sw.vshift, qi);
+        const double2 hq = row_h_f<FORM>(h, wk_, lpat, q1, i, v, sw.vshift, qi);
         const double2 pp = ld_nt(p0 + e);
         const double2 qq = q0 ? ld_nt(q0 + e) : make_double2(0.0, 0.0);
         const double2 po = rounded<V>(two_minus(hp, pp));
@@ -601,11 +684,7 @@ __global__ __launch_bounds__(kBlock) void k_kpm_sum(const double *__restrict__ m
 template <typename V, int ILP, bool NT, bool DBL>
 static void launch_step_shape(const Ell &h, const Sweep &sw, const V *p1, const V *p0, V *out,
                               const V *phil, double2 *partial, int slot, hipStream_t s) {
-    const bool fixed = h.w == 3 && !h.hop;
-    int form = kFormGeneric;
-    if (fixed && h.pid) form = h.onsf ? kFormC3F : kFormC3D;
-    else if (fixed) form = h.onsf ? kFormL3F : kFormL3D;
-    switch (form) {
+    switch (form_of(h)) {
 #define KPM_FORM_CASE(F)                                                                       \
         case F:                                                                                \
             hipLaunchKernelGGL((k_moment_step<V, ILP, NT, F, DBL>), dim3(sw.nwg), dim3(kBlock), \
@@ -663,27 +742,42 @@ void launch_undouble(double2 *mom, int rows, int64_t stride, int64_t offset, int
                        nm);
 }
 
+#define KPM_BY_FORM(form, CALL)                                                    \
+    switch (form) {                                                                \
+        case kFormC3F: { constexpr int F = kFormC3F; CALL; } break;                \
+        case kFormC3D: { constexpr int F = kFormC3D; CALL; } break;                \
+        case kFormL3F: { constexpr int F = kFormL3F; CALL; } break;                \
+        case kFormL3D: { constexpr int F = kFormL3D; CALL; } break;                \
+        default: { constexpr int F = kFormGeneric; CALL; } break;                  \
+    }
+
 template <typename V>
 void launch_evolve_step(const Ell &h, const Sweep &sw, bool first, const V *p1, const V *p0,
                         V *out, V *acc, const V *add, Coef c0, Coef c, hipStream_t s) {
-    if (first)
-        hipLaunchKernelGGL((k_evolve_step<V, true>), dim3(sw.nwg), dim3(kBlock), 0, s, h, sw,
-                           p1, p0, out, acc, add, c0, c);
-    else
-        hipLaunchKernelGGL((k_evolve_step<V, false>), dim3(sw.nwg), dim3(kBlock), 0, s, h, sw,
-                           p1, p0, out, acc, add, c0, c);
+    if (first) {
+        KPM_BY_FORM(form_of(h),
+                    hipLaunchKernelGGL((k_evolve_step<V, true, F>), dim3(sw.nwg), dim3(kBlock), 0,
+                                       s, h, sw, p1, p0, out, acc, add, c0, c))
+    } else {
+        KPM_BY_FORM(form_of(h),
+                    hipLaunchKernelGGL((k_evolve_step<V, false, F>), dim3(sw.nwg), dim3(kBlock),
+                                       0, s, h, sw, p1, p0, out, acc, add, c0, c))
+    }
 }
 
 template <typename V>
 void launch_evolve_x_step(const Ell &h, const Sweep &sw, bool first, const V *p1,
                           const V *p0, V *pout, const V *q1, const V *q0, V *qout,
                           V *accx, V *accu, Coef c0, Coef c, hipStream_t s) {
-    if (first)
-        hipLaunchKernelGGL((k_evolve_x_step<V, true>), dim3(sw.nwg), dim3(kBlock), 0, s, h,
-                           sw, p1, p0, pout, q1, q0, qout, accx, accu, c0, c);
-    else
-        hipLaunchKernelGGL((k_evolve_x_step<V, false>), dim3(sw.nwg), dim3(kBlock), 0, s, h,
-                           sw, p1, p0, pout, q1, q0, qout, accx, accu, c0, c);
+    if (first) {
+        KPM_BY_FORM(form_of(h),
+                    hipLaunchKernelGGL((k_evolve_x_step<V, true, F>), dim3(sw.nwg), dim3(kBlock),
+                                       0, s, h, sw, p1, p0, pout, q1, q0, qout, accx, accu, c0, c))
+    } else {
+        KPM_BY_FORM(form_of(h),
+                    hipLaunchKernelGGL((k_evolve_x_step<V, false, F>), dim3(sw.nwg), dim3(kBlock),
+                                       0, s, h, sw, p1, p0, pout, q1, q0, qout, accx, accu, c0, c))
+    }
 }
 
 template <typename V>
