@@ -399,7 +399,7 @@ def learned(args):
     n_train = int(0.9 * len(specs))
     sizes = [x.shape[1], 1024, 1024, y.shape[1]]
     batch = 100
-    net = kp.MLP(sizes, max_batch=batch)
+    net = kp.MLP(sizes, max_batch=max(batch, len(specs) - n_train))
     net.set_params(np.concatenate([np.concatenate([w.ravel(), b.ravel()])
                                    for w, b in ki.mlp_init(sizes, 77)]).astype(np.float32))
     xt = torch.from_numpy(x[:n_train]).cuda()
@@ -433,6 +433,13 @@ def learned(args):
     e_dos = np.max(np.abs(pred[:, :k] - yh[:, :k]), axis=1) / np.max(np.abs(yh[:, :k]), axis=1)
     e_sig = np.max(np.abs(pred[:, k:] - yh[:, k:]), axis=1) / np.max(np.abs(yh[:, k:]), axis=1)
     accept = (e_dos <= 1e-3) & (e_sig <= 1e-3)
+    # stochastic spread of plain KPM itself on the same samples: the targets of
+    # the two disjoint vector pairs differ by about twice the error of the
+    # four-vector target
+    ya = kp.kpm_learned_targets(mu[n_train:, :2], cm[n_train:, :2], en, es, area, t_star)
+    yb = kp.kpm_learned_targets(mu[n_train:, 2:], cm[n_train:, 2:], en, es, area, t_star)
+    s_dos = 0.5 * np.max(np.abs(ya[:, :k] - yb[:, :k]), axis=1) / np.max(np.abs(yh[:, :k]), axis=1)
+    s_sig = 0.5 * np.max(np.abs(ya[:, k:] - yb[:, k:]), axis=1) / np.max(np.abs(yh[:, k:]), axis=1)
     # cost per sample: the learned path needs the first 256 moments of each set,
     # plain KPM all 4000; both need the [X, U(t*)] state
     flops_step = 6.0 * batch * sum(sizes[l] * sizes[l + 1] for l in range(len(sizes) - 1))
@@ -456,6 +463,10 @@ def learned(args):
         "learned_error": {"dos_median": float(np.median(e_dos)), "dos_p90": float(np.quantile(e_dos, 0.9)),
                           "sigma_median": float(np.median(e_sig)),
                           "sigma_p90": float(np.quantile(e_sig, 0.9))},
+        "kpm_stochastic_error": {"dos_median": float(np.median(s_dos)),
+                                 "sigma_median": float(np.median(s_sig)),
+                                 "estimate": "half the difference of the targets of vectors "
+                                             "{0,1} and {2,3}, same norm"},
         "accepted_at_1e-3": int(accept.sum()), "fallback_to_kpm": int((~accept).sum()),
         "train_seconds": round(t_train, 2), "train_steps": steps,
         "train_tflops": round(flops_step * steps / t_train / 1e12, 3),
