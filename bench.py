@@ -447,9 +447,11 @@ def learned(args):
     su_state = 2 * (nb - 1) * nc + (nb - 1) * (nc - 1)            # coupled steps count twice
     frac_learned = (2 * (n_in // 2) + su_state) / (2 * (nm // 2) + su_state)
     out = {
-        "metric": "samples/s (learned sigma(E)/DOS reconstruction from 256 moments) and its "
-                  "error against 4000-moment KPM",
-        "value": round(1.0 / (gen_per_sample * frac_learned), 3),
+        "metric": "samples/s (learned sigma(E)/DOS reconstruction from 256 moments with plain "
+                  "4000-moment KPM as fallback above 1e-3 error) and the learned error",
+        # the path as deployed: learned inputs for every sample, plus plain KPM for
+        # every held-out sample the judge sends back
+        "value": round(1.0 / (gen_per_sample * (frac_learned + float(np.mean(~accept)))), 3),
         "unit": "samples/s",
         "n_gpus": 1, "steps": epochs, "warmup": 0,
         "ms_per_step": round(t_train / steps * 1e3, 3),
@@ -460,6 +462,7 @@ def learned(args):
                                "moments; MLP 513-1024-1024-2048 on 256 moments, 1024 energies",
                    "train": n_train, "held_out": len(specs) - n_train},
         "plain_kpm_samples_per_s": round(1.0 / gen_per_sample, 3),
+        "learned_only_samples_per_s": round(1.0 / (gen_per_sample * frac_learned), 3),
         "learned_error": {"dos_median": float(np.median(e_dos)), "dos_p90": float(np.quantile(e_dos, 0.9)),
                           "sigma_median": float(np.median(e_sig)),
                           "sigma_p90": float(np.quantile(e_sig, 0.9))},

@@ -123,6 +123,7 @@ def summarize(fetch_dir: str, write_dir: str, meta_path: str, out_path: str):
 def _short_kernel_name(name: str) -> str:
     name = name.replace("HIP_vector_type<double, 2u>", "double2")
     name = name.replace("HIP_vector_type<float, 2u>", "float2")
+    name = name.replace("(anonymous namespace)::", "")
     name = name.removeprefix("void ")
     return name.split("(")[0] if "(" in name else name
 

@@ -67,7 +67,9 @@ def _desc(nbr, e_scale, onsite=None):
     return d, keep
 
 
-@pytest.mark.parametrize("case", ["asymmetric", "out_of_range", "gershgorin", "width"])
+@pytest.mark.parametrize("case", ["asymmetric", "out_of_range", "gershgorin", "width",
+                                  "too_many_sites", "no_sites", "nan_scale", "null_nbr",
+                                  "nan_onsite"])
 def test_create_validates_before_touching_a_device(case):
     nbr, _ = kp.kpm_build_graphene(8, 4)
     nbr = nbr.copy()
@@ -78,9 +80,21 @@ def test_create_validates_before_touching_a_device(case):
         nbr[0, 3] = 10_000
     elif case == "gershgorin":
         es = 8.0                                      # 3 * 2.7 = 8.1 > 8.0
-    d, keep = _desc(nbr, es)
+    elif case == "nan_scale":
+        es = float("nan")
+    ons = None
+    if case == "nan_onsite":
+        ons = np.zeros(32)
+        ons[7] = np.nan
+    d, keep = _desc(nbr, es, ons)
     if case == "width":
         d.width = 9
+    elif case == "too_many_sites":
+        d.n_sites = 2 ** 31                           # rejected before the arrays are read
+    elif case == "no_sites":
+        d.n_sites = 0
+    elif case == "null_nbr":
+        d.nbr = None
     h = C.c_void_p()
     st = kp.lib().kpm_system_create(C.byref(d), 0, 0, None, C.byref(h))
     assert st == 1, kp.lib().kpm_last_error()
