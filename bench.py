@@ -410,12 +410,16 @@ def learned(args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     steps = 0
+    loss = float("nan")
     for ep in range(epochs):
         rng.shuffle(order)
         lr = 1e-3 * (0.5 * (1 + np.cos(np.pi * ep / epochs)))
+        last = (n_train - batch) // batch * batch
         for q in range(0, n_train - batch + 1, batch):
             idx = torch.from_numpy(order[q:q + batch]).cuda()
-            loss = net.train_step(xt[idx].contiguous(), yt[idx].contiguous(), float(lr))
+            out_loss = net.train_step(xt[idx].contiguous(), yt[idx].contiguous(), float(lr),
+                                      want_loss=(q == last))
+            loss = out_loss if out_loss is not None else loss
             steps += 1
         if ep % 50 == 0 or ep == epochs - 1:
             log(f"epoch {ep}: loss {loss:.3e}")

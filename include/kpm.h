@@ -347,7 +347,8 @@ kpm_status kpm_mlp_forward(kpm_mlp *net, int batch, const float *x, float *y);
 /* loss = mean (network(x) - y)^2 (host); grads (host [n_params], may be NULL). */
 kpm_status kpm_mlp_gradients(kpm_mlp *net, int batch, const float *x, const float *y,
                              double *loss, float *grads);
-/* One Adam step on the batch; loss (host) is that of the parameters before it. */
+/* One Adam step on the batch; loss (host, may be NULL) is that of the parameters
+ * before it.  With loss NULL the call does not synchronise the stream. */
 kpm_status kpm_mlp_train_step(kpm_mlp *net, int batch, const float *x, const float *y,
                               const kpm_adam *opt, double *loss);
 

@@ -22,56 +22,85 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
 constexpr int kTile = 64;     // block tile of C (rows and columns)
-constexpr int kChunk = 16;    // K staged in LDS per pass
+constexpr int kChunk = 32;    // K staged in LDS per pass
+constexpr int kMaxSplit = 8;  // K ranges of a split product
+constexpr int kLoads = kTile * kChunk / kThreads;   // values of A (and of B) per thread per pass
 
 enum { kEpiNone = 0, kEpiBias = 1, kEpiBiasTanh = 2, kEpiTanhGrad = 3 };
 
-// C[M][N] = op(A) op(B) with A(m, k) = TA ? A[k lda + m] : A[m lda + k] and
-// B(k, n) = TB ? B[n ldb + k] : B[k ldb + n], then the epilogue:
+template <int EPI>
+__device__ __forceinline__ float epilogue(float v, int row, int col, int ldc,
+                                          const float *__restrict__ bias,
+                                          const float *__restrict__ aux) {
+    if (EPI == kEpiBias) v += bias[col];
+    if (EPI == kEpiBiasTanh) v = tanhf(v + bias[col]);
+    if (EPI == kEpiTanhGrad) {
+        const float t = aux[(size_t)row * ldc + col];
+        v *= 1.f - t * t;
+    }
+    return v;
+}
+
+// C[M][N] = op(A) op(B) over k in [z Kc, (z + 1) Kc) for z = blockIdx.z, with
+// A(m, k) = TA ? A[k lda + m] : A[m lda + k] and B(k, n) = TB ? B[n ldb + k] :
+// B[k ldb + n].  One K range (gridDim.z = 1): the epilogue is applied and C
+// written; several: the raw partial goes to ws[z][M][N] for k_split_sum.
 //   kEpiBias:     + bias[n]
 //   kEpiBiasTanh: tanh(. + bias[n])
 //   kEpiTanhGrad: . * (1 - aux[m ldc + n]^2)
 // Block: 4 waves, each a 32 x 32 quarter of the 64 x 64 tile as 2 x 2 MFMA
 // 16 x 16 tiles.  For v_mfma_f32_16x16x4_f32 lane l supplies A(l % 16, l / 16)
 // and B(l / 16, l % 16) of its 16 x 4 and 4 x 16 operands and holds
-// C(4 (l / 16) + r, l % 16) in accumulator element r.
+// C(4 (l / 16) + r, l % 16) in accumulator element r.  The next K chunk is
+// loaded into registers while the current one is multiplied out of LDS.
 template <bool TA, bool TB, int EPI>
-__global__ __launch_bounds__(kThreads) void k_gemm(int M, int N, int K,
+__global__ __launch_bounds__(kThreads) void k_gemm(int M, int N, int K, int Kc,
                                                    const float *__restrict__ A, int lda,
                                                    const float *__restrict__ B, int ldb,
                                                    float *__restrict__ C, int ldc,
                                                    const float *__restrict__ bias,
-                                                   const float *__restrict__ aux) {
+                                                   const float *__restrict__ aux,
+                                                   float *__restrict__ ws) {
     __shared__ float sa[kChunk][kTile + 4];
     __shared__ float sb[kChunk][kTile + 4];
     const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
+    const int kb = blockIdx.z * Kc, ke = min(K, kb + Kc);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    float ra[kLoads], rb[kLoads];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < kLoads; ++q) {
+            const int idx = tid + q * kThreads;
+            const int mm = TA ? idx % kTile : idx / kChunk;
+            const int ka = TA ? idx / kTile : idx % kChunk;
+            const int gm = m0 + mm, gka = k0 + ka;
+            ra[q] = (gm < M && gka < ke) ? (TA ? A[(size_t)gka * lda + gm] : A[(size_t)gm * lda + gka])
+                                         : 0.f;
+            const int nn = TB ? idx / kChunk : idx % kTile;
+            const int kbb = TB ? idx % kChunk : idx / kTile;
+            const int gn = n0 + nn, gkb = k0 + kbb;
+            rb[q] = (gn < N && gkb < ke) ? (TB ? B[(size_t)gn * ldb + gkb] : B[(size_t)gkb * ldb + gn])
+                                         : 0.f;
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int q = 0; q < kLoads; ++q) {
+            const int idx = tid + q * kThreads;
+            sa[TA ? idx / kTile : idx % kChunk][TA ? idx % kTile : idx / kChunk] = ra[q];
+            sb[TB ? idx % kChunk : idx / kTile][TB ? idx / kChunk : idx % kTile] = rb[q];
+        }
+    };
     f4 acc[2][2];
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += kChunk) {
-#pragma unroll
-        for (int q = 0; q < kTile * kChunk / kThreads; ++q) {
-            const int idx = tid + q * kThreads;
-            const int mm = TA ? idx % kTile : idx / kChunk;
-            const int kk = TA ? idx / kTile : idx % kChunk;
-            const int gm = m0 + mm, gk = k0 + kk;
-            float v = 0.f;
-            if (gm < M && gk < K) v = TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
-            sa[kk][mm] = v;
-        }
-#pragma unroll
-        for (int q = 0; q < kTile * kChunk / kThreads; ++q) {
-            const int idx = tid + q * kThreads;
-            const int nn = TB ? idx / kChunk : idx % kTile;
-            const int kk = TB ? idx % kChunk : idx / kTile;
-            const int gn = n0 + nn, gk = k0 + kk;
-            float v = 0.f;
-            if (gn < N && gk < K) v = TB ? B[(size_t)gn * ldb + gk] : B[(size_t)gk * ldb + gn];
-            sb[kk][nn] = v;
-        }
+    if (kb < ke) fetch(kb);
+    for (int k0 = kb; k0 < ke; k0 += kChunk) {
+        __syncthreads();                 // the previous chunk is no longer read
+        stash();
         __syncthreads();
+        if (k0 + kChunk < ke) fetch(k0 + kChunk);
 #pragma unroll
         for (int ks = 0; ks < kChunk; ks += 4) {
             const int kk = ks + (lane >> 4);
@@ -86,8 +115,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm(int M, int N, int K,
                 for (int j = 0; j < 2; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
         }
-        __syncthreads();
     }
+    const bool split = gridDim.z > 1;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -97,15 +126,26 @@ __global__ __launch_bounds__(kThreads) void k_gemm(int M, int N, int K,
                 const int row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
                 const int col = n0 + wn + j * 16 + (lane & 15);
                 if (row >= M || col >= N) continue;
-                float v = acc[i][j][r];
-                if (EPI == kEpiBias) v += bias[col];
-                if (EPI == kEpiBiasTanh) v = tanhf(v + bias[col]);
-                if (EPI == kEpiTanhGrad) {
-                    const float t = aux[(size_t)row * ldc + col];
-                    v *= 1.f - t * t;
-                }
-                C[(size_t)row * ldc + col] = v;
+                if (split)
+                    ws[((size_t)blockIdx.z * M + row) * N + col] = acc[i][j][r];
+                else
+                    C[(size_t)row * ldc + col] = epilogue<EPI>(acc[i][j][r], row, col, ldc, bias, aux);
             }
+}
+
+// C = epilogue(sum over z < S of ws[z]), summed in z order.
+template <int EPI>
+__global__ __launch_bounds__(kThreads) void k_split_sum(int M, int N, int S,
+                                                        const float *__restrict__ ws,
+                                                        float *__restrict__ C, int ldc,
+                                                        const float *__restrict__ bias,
+                                                        const float *__restrict__ aux) {
+    const int64_t id = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (id >= (int64_t)M * N) return;
+    const int row = (int)(id / N), col = (int)(id % N);
+    float v = 0.f;
+    for (int z = 0; z < S; ++z) v += ws[(size_t)z * M * N + id];
+    C[(size_t)row * ldc + col] = epilogue<EPI>(v, row, col, ldc, bias, aux);
 }
 
 // out[n] = sum_m G[m N + n], one thread per column, in row order (double sum).
@@ -157,12 +197,25 @@ __global__ __launch_bounds__(kThreads) void k_adam(int64_t n, float *__restrict_
     }
 }
 
+// Products with few output tiles split K over up to kMaxSplit ranges (at
+// least 64 deep each) so that about 256 blocks run; the partials go through
+// `ws` (ws_elems floats) and are summed in a fixed order.
 template <bool TA, bool TB, int EPI>
-void gemm(hipStream_t s, int M, int N, int K, const float *A, int lda, const float *B, int ldb,
-          float *C, int ldc, const float *bias = nullptr, const float *aux = nullptr) {
-    const dim3 grid((N + kTile - 1) / kTile, (M + kTile - 1) / kTile);
-    hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(kThreads), 0, s, M, N, K, A, lda, B,
-                       ldb, C, ldc, bias, aux);
+void gemm(hipStream_t s, float *ws, size_t ws_elems, int M, int N, int K, const float *A,
+          int lda, const float *B, int ldb, float *C, int ldc, const float *bias = nullptr,
+          const float *aux = nullptr) {
+    const int mt = (M + kTile - 1) / kTile, nt = (N + kTile - 1) / kTile;
+    int split = std::max(1, std::min({kMaxSplit, 256 / (mt * nt), (K + 63) / 64}));
+    while (split > 1 && (size_t)split * M * N > ws_elems) --split;
+    const int kc = ((K + split - 1) / split + kChunk - 1) / kChunk * kChunk;
+    split = (K + kc - 1) / kc;
+    hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), dim3(nt, mt, std::max(split, 1)), dim3(kThreads), 0,
+                       s, M, N, K, kc, A, lda, B, ldb, C, ldc, bias, aux, ws);
+    if (split > 1) {
+        const int64_t total = (int64_t)M * N;
+        hipLaunchKernelGGL((k_split_sum<EPI>), dim3((unsigned)((total + kThreads - 1) / kThreads)),
+                           dim3(kThreads), 0, s, M, N, split, ws, C, ldc, bias, aux);
+    }
 }
 
 constexpr int kLossBlocks = 64;
@@ -182,6 +235,8 @@ struct kpm_mlp {
     float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
     std::vector<float *> act;       // act[l], l = 1 .. L: [max_batch][d_l]
     float *gbuf[2] = {nullptr, nullptr};
+    float *ws = nullptr;            // partial products of split-K products
+    size_t ws_elems = 0;
     double *lpart = nullptr;
     int64_t t = 0;                  // Adam steps taken
 
@@ -189,7 +244,7 @@ struct kpm_mlp {
         int prev = -1;
         (void)hipGetDevice(&prev);
         (void)hipSetDevice(device);
-        for (float *p : {params, grads, m, v, gbuf[0], gbuf[1]})
+        for (float *p : {params, grads, m, v, gbuf[0], gbuf[1], ws})
             if (p) (void)hipFree(p);
         for (float *p : act)
             if (p) (void)hipFree(p);
@@ -231,9 +286,10 @@ kpm_status forward(kpm_mlp *net, int batch, const float *x, float *out) {
         const bool last = l == net->layers - 1;
         float *c = (last && out) ? out : net->act[l + 1];
         if (last)
-            gemm<false, true, kEpiBias>(s, batch, dn, di, a, di, w, di, c, dn, b);
+            gemm<false, true, kEpiBias>(s, net->ws, net->ws_elems, batch, dn, di, a, di, w, di, c, dn, b);
         else
-            gemm<false, true, kEpiBiasTanh>(s, batch, dn, di, a, di, w, di, c, dn, b);
+            gemm<false, true, kEpiBiasTanh>(s, net->ws, net->ws_elems, batch, dn, di, a, di, w, di, c, dn,
+                                            b);
         a = c;
     }
     MLP_HIP(hipGetLastError());
@@ -257,17 +313,20 @@ kpm_status backward(kpm_mlp *net, int batch, const float *x, const float *y, dou
         const float *a = l == 0 ? x : net->act[l];
         const float *w = net->params + net->w_off[l];
         // dW_l = G^T a_l, db_l = column sums of G
-        gemm<true, false, kEpiNone>(s, dn, di, batch, g, dn, a, di, net->grads + net->w_off[l], di);
+        gemm<true, false, kEpiNone>(s, net->ws, net->ws_elems, dn, di, batch, g, dn, a, di,
+                                    net->grads + net->w_off[l], di);
         hipLaunchKernelGGL(k_colsum, dim3((dn + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
                            batch, dn, g, net->grads + net->b_off[l]);
         if (l > 0) {
             // G_{l-1} = (G W_l) * (1 - a_l^2)
             float *gn = g == net->gbuf[0] ? net->gbuf[1] : net->gbuf[0];
-            gemm<false, false, kEpiTanhGrad>(s, batch, di, dn, g, dn, w, di, gn, di, nullptr, a);
+            gemm<false, false, kEpiTanhGrad>(s, net->ws, net->ws_elems, batch, di, dn, g, dn, w, di, gn,
+                                             di, nullptr, a);
             g = gn;
         }
     }
     MLP_HIP(hipGetLastError());
+    if (!loss) return KPM_OK;            // no host value asked for: stay asynchronous
     double part[kLossBlocks];
     MLP_HIP(hipMemcpyAsync(part, net->lpart, sizeof part, hipMemcpyDeviceToHost, s));
     MLP_HIP(hipStreamSynchronize(s));
@@ -316,6 +375,7 @@ kpm_status kpm_mlp_create(int n_layers, const int32_t *widths, int max_batch, in
     }
     for (int l = 0; l <= n_layers; ++l) dmax = std::max(dmax, widths[l]);
     net->np = o;
+    net->ws_elems = (size_t)kMaxSplit * max_batch * dmax;
     Dev g(device);
     auto alloc = [&](float **p, size_t n) -> bool {
         return hipMalloc(p, n * sizeof(float)) == hipSuccess;
@@ -323,6 +383,7 @@ kpm_status kpm_mlp_create(int n_layers, const int32_t *widths, int max_batch, in
     bool ok = alloc(&net->params, o) && alloc(&net->grads, o) && alloc(&net->m, o) &&
               alloc(&net->v, o) && alloc(&net->gbuf[0], (size_t)max_batch * dmax) &&
               alloc(&net->gbuf[1], (size_t)max_batch * dmax) &&
+              alloc(&net->ws, (size_t)kMaxSplit * max_batch * dmax) &&
               hipMalloc(&net->lpart, kLossBlocks * sizeof(double)) == hipSuccess;
     net->act.assign(n_layers + 1, nullptr);
     for (int l = 1; ok && l <= n_layers; ++l) ok = alloc(&net->act[l], (size_t)max_batch * widths[l]);
@@ -399,7 +460,7 @@ kpm_status kpm_mlp_train_step(kpm_mlp *net, int batch, const float *x, const flo
         kpm_status st = check_batch(net, batch, x, y);
         if (st != KPM_OK) return st;
     }
-    if (!opt || !loss) return err(KPM_ERR_INVALID, "null argument");
+    if (!opt) return err(KPM_ERR_INVALID, "null argument");
     if (!(opt->lr > 0) || !(opt->beta1 >= 0 && opt->beta1 < 1) ||
         !(opt->beta2 >= 0 && opt->beta2 < 1) || !(opt->eps > 0))
         return err(KPM_ERR_INVALID, "Adam parameters out of range");

@@ -671,13 +671,15 @@ class MLP:
         return loss.value, g
 
     def train_step(self, x, y, lr: float, beta1: float = 0.9, beta2: float = 0.999,
-                   eps: float = 1e-8) -> float:
+                   eps: float = 1e-8, want_loss: bool = True):
+        """One Adam step; returns the loss before it (a host sync), or None
+        without synchronising when want_loss is False."""
         loss = C.c_double()
         opt = Adam(lr, beta1, beta2, eps)
         _check(lib().kpm_mlp_train_step(self._h, x.shape[0], _f32_gpu(x, "x", self.widths[0]),
                                         _f32_gpu(y, "y", self.widths[-1]), C.byref(opt),
-                                        C.byref(loss)))
-        return loss.value
+                                        C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

@@ -21,8 +21,10 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 kp = pytest.importorskip("paper_1307_0288_amd")
 
-# widths not multiples of the 64 x 64 tiles or the 16-deep K chunks
+# widths not multiples of the 64 x 64 tiles or the 32-deep K chunks
 SIZES = [37, 70, 45, 130]
+# deep enough for products split over several K ranges (partials summed in order)
+SIZES_SPLIT = [300, 200, 150, 96]
 
 
 def _need_gpu():
@@ -46,29 +48,34 @@ def _net_and_data(sizes=SIZES, batch=33, seed=5):
     return params, x, y, net
 
 
-def test_forward_matches_oracle():
+@pytest.mark.parametrize("sizes", [SIZES, SIZES_SPLIT])
+def test_forward_matches_oracle(sizes):
     _need_gpu()
-    params, x, y, net = _net_and_data()
+    params, x, y, net = _net_and_data(sizes)
     got = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
     ref = ln.forward(params, x.astype(np.float64))[-1]
     assert rel_err(got, ref) < 2e-5
     assert np.array_equal(net.get_params(), ln.flatten(params).astype(np.float32))
 
 
-@pytest.mark.parametrize("batch", [1, 33, 64])
-def test_gradients_match_oracle(batch):
+@pytest.mark.parametrize("batch,sizes", [(1, SIZES), (33, SIZES), (64, SIZES), (33, SIZES_SPLIT),
+                                         (64, SIZES_SPLIT)])
+def test_gradients_match_oracle(batch, sizes):
     _need_gpu()
-    params, x, y, net = _net_and_data(batch=batch)
+    params, x, y, net = _net_and_data(sizes, batch=batch)
     loss, g = net.gradients(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda())
     rl, rg = ln.loss_and_grads(params, x.astype(np.float64), y.astype(np.float64))
     assert loss == pytest.approx(rl, rel=1e-5)
-    got = ln.unflatten(g.astype(np.float64), SIZES)
+    got = ln.unflatten(g.astype(np.float64), sizes)
     for l, ((gw, gb), (rw, rb)) in enumerate(zip(got, rg)):
         assert rel_err(gw, rw) < 1e-4, l
         assert rel_err(gb, rb) < 1e-4, l
 
 
-def test_adam_steps_match_oracle():
+@pytest.mark.parametrize("want_loss", [True, False])
+def test_adam_steps_match_oracle(want_loss):
+    """Five Adam steps, with the loss read back after each (a host sync) or
+    not at all (the steps queue on the stream)."""
     _need_gpu()
     params, x, y, net = _net_and_data()
     xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
@@ -76,9 +83,12 @@ def test_adam_steps_match_oracle():
     state = ln.adam_init(params)
     ref = params
     for _ in range(5):
-        loss = net.train_step(xd, yd, lr, 0.9, 0.999, eps)
+        loss = net.train_step(xd, yd, lr, 0.9, 0.999, eps, want_loss=want_loss)
         rl, rg = ln.loss_and_grads(ref, x.astype(np.float64), y.astype(np.float64))
-        assert loss == pytest.approx(rl, rel=1e-4)
+        if want_loss:
+            assert loss == pytest.approx(rl, rel=1e-4)
+        else:
+            assert loss is None
         ref, state = ln.adam_step(ref, rg, state, lr, eps=eps)
     got = net.get_params().astype(np.float64)
     moved = np.max(np.abs(ln.flatten(ref) - ln.flatten(params)))
