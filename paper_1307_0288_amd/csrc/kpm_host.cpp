@@ -379,6 +379,19 @@ struct kpm_system {
         auto tiling = [&](int s, int32_t *tnx) {
             *tnx = (l.tiled && chain[s] >= 2 * tw) ? chain[s] : 0;
         };
+        // multiply-shift constants for t / nch (nch = rows / tnx chains)
+        auto divider = [&](int s, int32_t tnx, kpm::Seg &g) {
+            g.div_m = 0;
+            g.div_l = 0;
+            if (!tnx) return;
+            const uint64_t d = (uint64_t)((off[s + 1] - off[s]) / tnx);
+            int l = 0;
+            while (((uint64_t)1 << l) < d) ++l;
+            g.div_l = l;
+            // ceil(2^(32 + l) / d) < 2^33
+            const unsigned __int128 num = (unsigned __int128)1 << (32 + l);
+            g.div_m = (uint64_t)((num + d - 1) / d);
+        };
         if (nseg == 1) {
             const int64_t nblk = (sw.total + kpm::kBlock - 1) / kpm::kBlock;
             const int64_t cap = ((nblk + kpm::kXcds - 1) / kpm::kXcds) * kpm::kXcds;
@@ -388,7 +401,8 @@ struct kpm_system {
             sw.wg_seg = nullptr;
             int32_t tnx;
             tiling(0, &tnx);
-            sw.one = kpm::Seg{0, sw.total, 0, sw.nwg, seg_t[0], 1.0 / es[0], tnx, tw};
+            sw.one = kpm::Seg{0, sw.total, 0, sw.nwg, seg_t[0], 1.0 / es[0], tnx, tw, 0, 0};
+            divider(0, tnx, sw.one);
             *out = sw;
             return KPM_OK;
         }
@@ -413,7 +427,8 @@ struct kpm_system {
             int32_t tnx;
             tiling(s, &tnx);
             seg[s] = kpm::Seg{off[s] << vshift, off[s + 1] << vshift, (int32_t)g0,
-                              (int32_t)(u * kpm::kXcds), seg_t[s], 1.0 / es[s], tnx, tw};
+                              (int32_t)(u * kpm::kXcds), seg_t[s], 1.0 / es[s], tnx, tw, 0, 0};
+            divider(s, tnx, seg[s]);
             g0 += u * kpm::kXcds;
         }
         if (g0 > (1 << 30)) return fail(KPM_ERR_INVALID, "batch needs too many work-groups");

@@ -51,6 +51,11 @@ struct Seg {
     int32_t g0, nwg;
     double t, inv_es;
     int32_t tnx, tw;       // chain length and tile width in rows; tnx = 0: row order
+    // t / nch as (t * div_m) >> (32 + div_l), div_l = ceil(log2 nch), div_m =
+    // ceil(2^(32 + div_l) / nch) < 2^33 (Granlund and Montgomery, PLDI 1994): exact
+    // for t < 2^32, and t * div_m fits 64 bits for the tile indices t < 2^31 used
+    uint64_t div_m;
+    int32_t div_l;
 };
 
 // Persistent, XCD-aware sweep.  Work-groups are dispatched round-robin over

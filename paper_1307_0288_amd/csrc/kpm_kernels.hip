@@ -100,8 +100,11 @@ struct Walk {
     int loc, nloc;
     int64_t b0, b1, e0, e1;
     double t, inv_es;
-    // tiled traversal (tnx > 0): blocks per tile = 1 << lbps, nch chains
+    // tiled traversal (tnx > 0): blocks per tile = 1 << lbps, nch chains,
+    // division by nch as a multiply and shift
     int32_t tnx, tw, lbps, nch;
+    uint64_t div_m;
+    int32_t div_l;
 };
 
 // Element of thread `tid` in logical block b of the walk's segment, and
@@ -114,7 +117,7 @@ __device__ __forceinline__ bool block_elem(const Walk &w, int64_t b, int tid, in
         return e < w.e1;
     }
     const uint32_t t = (uint32_t)(b >> w.lbps);
-    const uint32_t s = t / (uint32_t)w.nch;
+    const uint32_t s = (uint32_t)(((uint64_t)t * w.div_m) >> (32 + w.div_l));
     const uint32_t j = t - s * (uint32_t)w.nch;
     const int64_t loc = ((b & ((1 << w.lbps) - 1)) * kBlock) + tid;
     const int64_t width = min((int64_t)w.tw, (int64_t)w.tnx - (int64_t)s * w.tw);
@@ -253,6 +256,8 @@ __device__ __forceinline__ Walk walk_of(const Sweep &sw) {
     w.nloc = s.nwg / kXcds;
     w.tnx = s.tnx;
     w.tw = s.tw;
+    w.div_m = s.div_m;
+    w.div_l = s.div_l;
     int64_t nblk;
     if (s.tnx > 0) {
         const int64_t rows = (s.e1 - s.e0) >> sw.vshift;
