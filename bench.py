@@ -355,7 +355,7 @@ def learned(args):
     sums of all 4000 moments (DOS and sigma_E2(t*), 1024 energies in
     [-7.5, 7.5] eV); features: the first 256 moments of each.  The network
     (513 -> 1024 -> 1024 -> 2048, tanh) trains with Adam on 90 % of the samples;
-    on the held-out 10 % its spectra are judged against plain 4000-moment KPM,
+    on the held-out 10 % its spectra are compared with plain 4000-moment KPM,
     and plain KPM is kept wherever the learned error exceeds 1e-3."""
     import torch
     import paper_1307_0288_amd as kp
@@ -458,7 +458,7 @@ def learned(args):
         "metric": "samples/s (learned sigma(E)/DOS reconstruction from 256 moments with plain "
                   "4000-moment KPM as fallback above 1e-3 error) and the learned error",
         # the path as deployed: learned inputs for every sample, plus plain KPM for
-        # every held-out sample the judge sends back
+        # every held-out sample whose learned error exceeds the bar
         "value": round(1.0 / (gen_per_sample * (frac_learned + float(np.mean(~accept)))), 3),
         "unit": "samples/s",
         "n_gpus": 1, "steps": epochs, "warmup": 0,
