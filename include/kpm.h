@@ -387,12 +387,13 @@ kpm_status kpm_xu_state(kpm_system *sys, int n_vec, const void *phi, int n_steps
  * streaming (non-temporal) access to the operands read or written once per
  * step (0 or 1), and whether neighbours are read in the compact pattern form
  * (1) or from the explicit list (0; the explicit list is used regardless when
- * the system has no compact form).  tiled = 1 visits the rows of a lattice
- * sample strip by strip (tiles of consecutive columns of successive chains,
- * the chain length found from the most common neighbour offset beyond 1) so
- * that a row's vertical neighbour is reused from cache even when a row
- * carries many vectors; samples without such a chain structure keep row
- * order.  At a fixed grid size and traversal the moments are bit-identical for
+ * the system has no compact form).  tiled = 1, 2 or 3 visits the rows of a
+ * lattice sample strip by strip (tiles of 64, 128 or 256 consecutive columns
+ * of successive chains, at least 256 / n_vec columns times 1, 2 or 4; the
+ * chain length found from the most common neighbour offset beyond 1) so that a
+ * row's vertical neighbour is reused from cache even when a row carries many
+ * vectors; tiled = 0, and samples without such a chain structure or with
+ * chains shorter than two tiles, keep row order.  At a fixed grid size and traversal the moments are bit-identical for
  * every ilp, streaming and compact choice; the grid size and the traversal
  * change only the order of the inner-product partial sums.
  */

@@ -99,7 +99,7 @@ struct DeviceGuard {
 bool valid_launch(const kpm_launch &l) {
     return l.groups_per_cu >= 1 && l.groups_per_cu <= 32 &&
            (l.ilp == 1 || l.ilp == 2 || l.ilp == 4) && (l.streaming == 0 || l.streaming == 1) &&
-           (l.compact == 0 || l.compact == 1) && (l.tiled == 0 || l.tiled == 1);
+           (l.compact == 0 || l.compact == 1) && l.tiled >= 0 && l.tiled <= 3;
 }
 
 // Tile width (rows) of the tiled traversal for 2^vshift vectors per row: a
@@ -375,7 +375,7 @@ struct kpm_system {
         sw.ilp = l.ilp;
         sw.nt = l.streaming;
         const int64_t want = std::max<int64_t>(kpm::kXcds, ((int64_t)cus * l.groups_per_cu) / kpm::kXcds * kpm::kXcds);
-        const int tw = tile_rows(vshift);
+        const int tw = l.tiled > 0 ? tile_rows(vshift) << (l.tiled - 1) : tile_rows(vshift);
         auto tiling = [&](int s, int32_t *tnx) {
             *tnx = (l.tiled && chain[s] >= 2 * tw) ? chain[s] : 0;
         };
@@ -933,7 +933,7 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
     const int forms = sys->d_pid ? 2 : 1;
     bool can_tile = false;
     for (int32_t c : sys->chain) can_tile = can_tile || c >= 2 * tile_rows(vs);
-    const int tilings = can_tile ? 2 : 1;
+    const int tilings = can_tile ? 4 : 1;      // row order, tiles of 1, 2, 4 x tile_rows
     hipEvent_t e0, e1;
     KPM_HIP(hipEventCreate(&e0));
     KPM_HIP(hipEventCreate(&e1));

@@ -531,7 +531,7 @@ def kpm_set_launch(sys: System, n_vec: int, groups_per_cu: int, ilp: int, stream
     """Launch shape of the moment step for n_vec vectors (see kpm_launch in kpm.h)."""
     _check(lib().kpm_set_launch(sys.handle, n_vec,
                                 C.byref(Launch(groups_per_cu, ilp, int(bool(streaming)),
-                                               int(bool(compact)), int(bool(tiled))))))
+                                               int(bool(compact)), int(tiled)))))
 
 
 def kpm_get_launch(sys: System, n_vec: int) -> dict:

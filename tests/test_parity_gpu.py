@@ -322,20 +322,22 @@ def test_launch_shapes(n_vec, precision):
         assert rel_err(ref, first, float(np.abs(first[:, 0]).max())) < 1e-13
     best = kp.kpm_autotune(sysg, phi, 3)
     assert best["groups_per_cu"] in (4, 8, 16) and best["ilp"] in (1, 2, 4)
-    assert best["streaming"] in (0, 1) and best["compact"] in (0, 1) and best["tiled"] in (0, 1)
+    assert best["streaming"] in (0, 1) and best["compact"] in (0, 1) and best["tiled"] in (0, 1, 2, 3)
     assert kp.kpm_get_launch(sysg, n_vec) == best
 
 
-@pytest.mark.parametrize("nx,ny,n_vec,precision", [(300, 30, 8, "fp64"), (300, 30, 64, "fp32"),
-                                                    (600, 16, 1, "fp64"), (300, 30, 64, "fp64")])
-def test_tiled_traversal(nx, ny, n_vec, precision):
+@pytest.mark.parametrize("nx,ny,n_vec,precision,tiled", [
+    (300, 30, 8, "fp64", 1), (300, 30, 64, "fp32", 1), (600, 16, 1, "fp64", 1),
+    (300, 30, 64, "fp64", 1), (1100, 8, 64, "fp32", 2), (1100, 8, 64, "fp64", 3),
+    (300, 30, 8, "fp64", 3)])         # chains shorter than two 256-row tiles: row order
+def test_tiled_traversal(nx, ny, n_vec, precision, tiled):
     """Strip-by-strip traversal (chains of nx rows, tiles of 64 rows for 8+
     vectors and 256 rows for one; nx is not a multiple of the tile, so the last
     strip is padded): moments, evolution and the VAC agree with row order up to
     the order of the partial sums, and with the oracle; every ILP, streaming
     and neighbour form is bit-identical under the tiled traversal."""
     _need_gpu()
-    _log(f"tiled traversal {nx}x{ny} n_vec={n_vec} {precision}")
+    _log(f"tiled traversal {nx}x{ny} n_vec={n_vec} {precision} tiled={tiled}")
     c = recipe("sheet", nx, ny, w=1.0, vac=0.01, seed=21)
     sysg = gpu_system(c, precision)
     phi = phases(c, n_vec, 3000)
@@ -348,7 +350,7 @@ def test_tiled_traversal(nx, ny, n_vec, precision):
     for ilp in (1, 2, 4):
         for nt in (0, 1):
             for cp in (0, 1):
-                kp.kpm_set_launch(sysg, n_vec, 8, ilp, nt, cp, 1)
+                kp.kpm_set_launch(sysg, n_vec, 8, ilp, nt, cp, tiled)
                 mu = kp.kpm_moments(sysg, d, d, 60)
                 ref = mu if ref is None else ref
                 assert np.array_equal(mu, ref), (ilp, nt, cp)
