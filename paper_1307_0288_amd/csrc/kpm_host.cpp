@@ -933,7 +933,8 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
     const int forms = sys->d_pid ? 2 : 1;
     bool can_tile = false;
     for (int32_t c : sys->chain) can_tile = can_tile || c >= 2 * tile_rows(vs);
-    const int tilings = can_tile ? 4 : 1;      // row order, tiles of 1, 2, 4 x tile_rows
+    // row order and the base tile (wider tiles measured slower on every shape tried)
+    const int tilings = can_tile ? 2 : 1;
     hipEvent_t e0, e1;
     KPM_HIP(hipEventCreate(&e0));
     KPM_HIP(hipEventCreate(&e1));

@@ -152,6 +152,9 @@ def main():
     ap.add_argument("--copies", type=int, default=3)
     ap.add_argument("--launch", default="",
                     help="groups_per_cu,ilp,streaming,compact[,tiled] (default: the library's)")
+    ap.add_argument("--autotune", type=int, default=0,
+                    help="run kpm_autotune with this many repetitions first (the benchmark's "
+                         "choice of shape)")
     ap.add_argument("--meta", default="", help="write the run's launch shape, sizes and "
                                                "algorithmic bytes here")
     ap.add_argument("--summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
@@ -180,6 +183,8 @@ def main():
     phi = sysg.upload(ki.random_phase(n, args.n_vec, 3000, act))
     if args.launch:
         kp.kpm_set_launch(sysg, args.n_vec, *(int(x) for x in args.launch.split(",")))
+    if args.autotune:
+        kp.kpm_autotune(sysg, phi, args.autotune)
     launch = kp.kpm_get_launch(sysg, args.n_vec)
     print(f"launch shape: {launch}", flush=True)
     kp.kpm_reset_stats(sysg)
@@ -206,6 +211,8 @@ def main():
             cmd.append("--doubled")
         if args.launch:
             cmd.append(f"--launch {args.launch}")
+        if args.autotune:
+            cmd.append(f"--autotune {args.autotune}")
         meta = {
             "kernel": f"k_moment_step<{v},{launch['ilp']},"
                       f"{'true' if launch['streaming'] else 'false'},{form},"
