@@ -541,7 +541,22 @@ __global__ __launch_bounds__(kBlock) void k_undouble(double2 *__restrict__ mom, 
     c[j] = make_double2(fma(2.0, a.x, -b.x), fma(2.0, a.y, -b.y));
 }
 
-template <typename V, bool FIRST, int FORM>
+// Loads and stores of the propagator kernels: non-temporal when NT (many
+// vectors: the streams do not fit in cache), cached otherwise (the written
+// state is gathered again by the next step).
+template <bool NT, typename V>
+__device__ __forceinline__ double2 ldx(const V *p) {
+    return NT ? ld_nt(p) : ld(p);
+}
+template <bool NT, typename V>
+__device__ __forceinline__ void stx(V *p, double2 v) {
+    if (NT)
+        st_nt(p, v);
+    else
+        st(p, v);
+}
+
+template <typename V, bool FIRST, int FORM, bool NT>
 __global__ __launch_bounds__(kBlock) void k_evolve_step(Ell h, Sweep sw, const V *p1,
                                                         const V *p0, V *out, V *acc,
                                                         const V *add, Coef c0, Coef c) {
@@ -553,17 +568,17 @@ __global__ __launch_bounds__(kBlock) void k_evolve_step(Ell h, Sweep sw, const V
     if (FIRST) {
         o = rounded<V>(hx);
         a = cmla(cmul(coef(c0, sg), xi), cm, o);
-        if (add) a = cadd(ld_nt(add + e), a);
+        if (add) a = cadd(ldx<NT>(add + e), a);
     } else {
-        o = rounded<V>(two_minus(hx, ld_nt(p0 + e)));
-        a = cmla(ld_nt(acc + e), cm, o);
+        o = rounded<V>(two_minus(hx, ldx<NT>(p0 + e)));
+        a = cmla(ldx<NT>(acc + e), cm, o);
     }
-    st_nt(out + e, o);
-    st_nt(acc + e, a);
+    stx<NT>(out + e, o);
+    stx<NT>(acc + e, a);
     KPM_SWEEP_END
 }
 
-template <typename V, bool FIRST, int FORM>
+template <typename V, bool FIRST, int FORM, bool NT>
 __global__ __launch_bounds__(kBlock) void k_evolve_x_step(Ell h, Sweep sw, const V *p1,
                                                           const V *p0, V *pout,
                                                           const V *q1, const V *q0,
@@ -577,21 +592,21 @@ __global__ __launch_bounds__(kBlock) void k_evolve_x_step(Ell h, Sweep sw, const
     if (FIRST) {
         hp = rounded<V>(hp);
         dp = rounded<V>(dp);
-        st_nt(pout + e, hp);
-        st_nt(qout + e, dp);
-        st_nt(accx + e, cmul(cm, dp));
-        st_nt(accu + e, cmla(cmul(coef(c0, sg), xi), cm, hp));
+        stx<NT>(pout + e, hp);
+        stx<NT>(qout + e, dp);
+        stx<NT>(accx + e, cmul(cm, dp));
+        stx<NT>(accu + e, cmla(cmul(coef(c0, sg), xi), cm, hp));
     } else {
         const double2 qi = ld(q1 + e);
         const double2 hq = row_h_f<FORM>(h, wk_, lpat, q1, i, v, sw.vshift, qi);
-        const double2 pp = ld_nt(p0 + e);
-        const double2 qq = q0 ? ld_nt(q0 + e) : make_double2(0.0, 0.0);
+        const double2 pp = ldx<NT>(p0 + e);
+        const double2 qq = q0 ? ldx<NT>(q0 + e) : make_double2(0.0, 0.0);
         const double2 po = rounded<V>(two_minus(hp, pp));
         const double2 qo = rounded<V>(two_minus(cadd(dp, hq), qq));
-        st_nt(pout + e, po);
-        st_nt(qout + e, qo);
-        st_nt(accx + e, cmla(ld_nt(accx + e), cm, qo));
-        st_nt(accu + e, cmla(ld_nt(accu + e), cm, po));
+        stx<NT>(pout + e, po);
+        stx<NT>(qout + e, qo);
+        stx<NT>(accx + e, cmla(ldx<NT>(accx + e), cm, qo));
+        stx<NT>(accu + e, cmla(ldx<NT>(accu + e), cm, po));
     }
     KPM_SWEEP_END
 }
@@ -759,30 +774,31 @@ void launch_undouble(double2 *mom, int rows, int64_t stride, int64_t offset, int
 template <typename V>
 void launch_evolve_step(const Ell &h, const Sweep &sw, bool first, const V *p1, const V *p0,
                         V *out, V *acc, const V *add, Coef c0, Coef c, hipStream_t s) {
-    if (first) {
-        KPM_BY_FORM(form_of(h),
-                    hipLaunchKernelGGL((k_evolve_step<V, true, F>), dim3(sw.nwg), dim3(kBlock), 0,
-                                       s, h, sw, p1, p0, out, acc, add, c0, c))
-    } else {
-        KPM_BY_FORM(form_of(h),
-                    hipLaunchKernelGGL((k_evolve_step<V, false, F>), dim3(sw.nwg), dim3(kBlock),
-                                       0, s, h, sw, p1, p0, out, acc, add, c0, c))
-    }
+#define KPM_EVOLVE(FIRST_, NT_)                                                               \
+    KPM_BY_FORM(form_of(h),                                                                   \
+                hipLaunchKernelGGL((k_evolve_step<V, FIRST_, F, NT_>), dim3(sw.nwg),          \
+                                   dim3(kBlock), 0, s, h, sw, p1, p0, out, acc, add, c0, c))
+    if (first && sw.nt) { KPM_EVOLVE(true, true) }
+    else if (first) { KPM_EVOLVE(true, false) }
+    else if (sw.nt) { KPM_EVOLVE(false, true) }
+    else { KPM_EVOLVE(false, false) }
+#undef KPM_EVOLVE
 }
 
 template <typename V>
 void launch_evolve_x_step(const Ell &h, const Sweep &sw, bool first, const V *p1,
                           const V *p0, V *pout, const V *q1, const V *q0, V *qout,
                           V *accx, V *accu, Coef c0, Coef c, hipStream_t s) {
-    if (first) {
-        KPM_BY_FORM(form_of(h),
-                    hipLaunchKernelGGL((k_evolve_x_step<V, true, F>), dim3(sw.nwg), dim3(kBlock),
-                                       0, s, h, sw, p1, p0, pout, q1, q0, qout, accx, accu, c0, c))
-    } else {
-        KPM_BY_FORM(form_of(h),
-                    hipLaunchKernelGGL((k_evolve_x_step<V, false, F>), dim3(sw.nwg), dim3(kBlock),
-                                       0, s, h, sw, p1, p0, pout, q1, q0, qout, accx, accu, c0, c))
-    }
+#define KPM_EVOLVE_X(FIRST_, NT_)                                                             \
+    KPM_BY_FORM(form_of(h),                                                                   \
+                hipLaunchKernelGGL((k_evolve_x_step<V, FIRST_, F, NT_>), dim3(sw.nwg),        \
+                                   dim3(kBlock), 0, s, h, sw, p1, p0, pout, q1, q0, qout,     \
+                                   accx, accu, c0, c))
+    if (first && sw.nt) { KPM_EVOLVE_X(true, true) }
+    else if (first) { KPM_EVOLVE_X(true, false) }
+    else if (sw.nt) { KPM_EVOLVE_X(false, true) }
+    else { KPM_EVOLVE_X(false, false) }
+#undef KPM_EVOLVE_X
 }
 
 template <typename V>

@@ -45,8 +45,7 @@ def kernel_sha() -> str:
     not change the moment step)."""
     with open(KERNEL_SRC) as f:
         t = f.read()
-    head = t[:t.index("template <typename V, bool FIRST, int FORM>\n__global__ __launch_bounds__(kBlock) "
-                      "void k_evolve_step(")]
+    head = t[:t.index("// Loads and stores of the propagator kernels")]
     a = t.index("template <typename V, int ILP, bool NT, bool DBL>\nstatic void launch_step_shape(")
     b = t.index("template <typename V>\nvoid launch_evolve_step(")
     return hashlib.sha256((head + t[a:b]).encode()).hexdigest()[:16]
