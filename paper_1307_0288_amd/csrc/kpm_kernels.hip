@@ -541,9 +541,9 @@ __global__ __launch_bounds__(kBlock) void k_undouble(double2 *__restrict__ mom, 
     c[j] = make_double2(fma(2.0, a.x, -b.x), fma(2.0, a.y, -b.y));
 }
 
-// Loads and stores of the propagator kernels: non-temporal when NT (many
-// vectors: the streams do not fit in cache), cached otherwise (the written
-// state is gathered again by the next step).
+// Loads and stores of the propagator kernels: non-temporal when NT, cached
+// otherwise (with few vectors the written state, gathered again by the next
+// step, then stays in cache).
 template <bool NT, typename V>
 __device__ __forceinline__ double2 ldx(const V *p) {
     return NT ? ld_nt(p) : ld(p);
@@ -794,10 +794,10 @@ void launch_evolve_x_step(const Ell &h, const Sweep &sw, bool first, const V *p1
                 hipLaunchKernelGGL((k_evolve_x_step<V, FIRST_, F, NT_>), dim3(sw.nwg),        \
                                    dim3(kBlock), 0, s, h, sw, p1, p0, pout, q1, q0, qout,     \
                                    accx, accu, c0, c))
-    if (first && sw.nt) { KPM_EVOLVE_X(true, true) }
-    else if (first) { KPM_EVOLVE_X(true, false) }
-    else if (sw.nt) { KPM_EVOLVE_X(false, true) }
-    else { KPM_EVOLVE_X(false, false) }
+    // always non-temporal: with ten state streams per step, caching them evicts
+    // the gathered state (measured slower with one vector as well)
+    if (first) { KPM_EVOLVE_X(true, true) }
+    else { KPM_EVOLVE_X(false, true) }
 #undef KPM_EVOLVE_X
 }
 
