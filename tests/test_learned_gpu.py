@@ -43,7 +43,7 @@ def _net_and_data(sizes=SIZES, batch=33, seed=5):
               for w, b in params]
     x = rng.standard_normal((batch, sizes[0])).astype(np.float32)
     y = rng.standard_normal((batch, sizes[-1])).astype(np.float32)
-    net = kp.MLP(sizes, max_batch=64)
+    net = kp.MLP(sizes, max_batch=max(64, batch))
     net.set_params(ln.flatten(params).astype(np.float32))
     return params, x, y, net
 
@@ -68,6 +68,24 @@ def test_gradients_match_oracle(batch, sizes):
     assert loss == pytest.approx(rl, rel=1e-5)
     got = ln.unflatten(g.astype(np.float64), sizes)
     for l, ((gw, gb), (rw, rb)) in enumerate(zip(got, rg)):
+        assert rel_err(gw, rw) < 1e-4, l
+        assert rel_err(gb, rb) < 1e-4, l
+
+
+def test_full_size_network_matches_oracle():
+    """The network of the learned workload (513 -> 1024 -> 1024 -> 2048, batch
+    100, split-K products) against the oracle: outputs, loss and gradients."""
+    _need_gpu()
+    sizes = [513, 1024, 1024, 2048]
+    params, x, y, net = _net_and_data(sizes, batch=100)
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    got = net.forward(xd).cpu().numpy()
+    acts = ln.forward(params, x.astype(np.float64))
+    assert rel_err(got, acts[-1]) < 2e-5
+    loss, g = net.gradients(xd, yd)
+    rl, rg = ln.loss_and_grads(params, x.astype(np.float64), y.astype(np.float64))
+    assert loss == pytest.approx(rl, rel=1e-5)
+    for l, ((gw, gb), (rw, rb)) in enumerate(zip(ln.unflatten(g.astype(np.float64), sizes), rg)):
         assert rel_err(gw, rw) < 1e-4, l
         assert rel_err(gb, rb) < 1e-4, l
 

@@ -232,7 +232,10 @@ def paper():
     p = ki.sheet_config("paper")
     c = recipe("sheet", p["nx"], p["ny"], w=p["w"], vac=p["vac"], e_scale=p["e_scale"])
     _log("paper-scale lattice (3998792 sites)")
-    return p, c, oracle_lattice(c), gpu_system(c)
+    sysg = gpu_system(c)
+    # the launch shape bench.py times: autotuned on the same vector
+    _log(f"autotuned shape {kp.kpm_autotune(sysg, sysg.upload(phases(c, 1, 3000)), 50)}")
+    return p, c, oracle_lattice(c), sysg
 
 
 def test_paper_scale_moments_prefix_and_properties(paper):
