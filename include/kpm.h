@@ -219,6 +219,28 @@ kpm_status kpm_msd_doubled(kpm_system *sys, int n_vec, const void *phi, int n_st
                            double dt_fs, int n_bessel, int n_moments, double *out);
 
 /*
+ * Resumable forms of kpm_vac and kpm_msd for long correlation times: the loop
+ * state lives in two caller-owned device buffers (same layout as phi) that are
+ * updated in place, so a run can be split into pieces, checkpointed (copy the
+ * two buffers and the moments out) and resumed, with results bit-identical to
+ * one uninterrupted call on the same system.
+ *  kpm_vac_continue: state psi = U^dagger(t_k) phi, r = U^dagger(t_k) V phi.
+ *  kpm_msd_continue: state psi = U(t_k) phi, y = [X, U(t_k)] phi (Eq. 44);
+ *                    doubled = 1 takes the moments in the doubling form.
+ * start = 1 begins at t = 0: psi holds phi on entry, r (y) is set here, and
+ * the moments at t = 0 come first.  start = 0 continues from t_k.  The call
+ * advances n_steps steps of dt; out: host [n_sys][n_vec][n_steps + start]
+ * [n_moments].  kpm_vac(phi, n) equals kpm_vac_continue(start = 1, n) on a
+ * copy of phi, and also start = 1 for n1 steps followed by start = 0 for
+ * n - n1 steps (likewise for the MSD).  Synchronises the stream.
+ */
+kpm_status kpm_vac_continue(kpm_system *sys, int n_vec, void *psi, void *r, int start,
+                            int n_steps, double dt_fs, int n_bessel, int n_moments, double *out);
+kpm_status kpm_msd_continue(kpm_system *sys, int n_vec, void *psi, void *y, int start,
+                            int n_steps, double dt_fs, int n_bessel, int n_moments, int doubled,
+                            double *out);
+
+/*
  * Fourier moments of the FTM (Alg. 4, Eq. 25-27):
  * F_n = <phi_L| U(n dtau) |phi_R> for n = -n_moments .. n_moments, each step
  * of dtau by the Chebyshev-Bessel expansion with n_bessel terms (forward for

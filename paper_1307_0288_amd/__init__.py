@@ -17,7 +17,8 @@ from .kpm import (ABI_SYMBOLS, HBAR_EV_FS, BOND_NM, KpmError, System, graphene_b
                   kpm_sigma_e2, kpm_sigma_gk, kpm_vac, kpm_length, kpm_conductance,
                   kpm_ballistic_conductance, kpm_sigma_sc_max, kpm_sigma_sc_average,
                   kpm_pade_fit, kpm_pade_eval, kpm_typical_conductance, kpm_msd_doubled,
-                  MLP, kpm_learned_features, kpm_learned_targets, kpm_xu_state, lib)
+                  MLP, kpm_learned_features, kpm_learned_targets, kpm_xu_state,
+                  kpm_vac_continue, kpm_msd_continue, lib)
 
 __all__ = ["ABI_SYMBOLS", "HBAR_EV_FS", "BOND_NM", "KpmError", "System", "graphene_batch",
            "graphene_system",
@@ -29,4 +30,4 @@ __all__ = ["ABI_SYMBOLS", "HBAR_EV_FS", "BOND_NM", "KpmError", "System", "graphe
            "kpm_conductance", "kpm_ballistic_conductance", "kpm_sigma_sc_max",
            "kpm_sigma_sc_average", "kpm_pade_fit", "kpm_pade_eval", "kpm_typical_conductance",
            "kpm_msd_doubled", "MLP", "kpm_learned_features", "kpm_learned_targets",
-           "kpm_xu_state", "lib"]
+           "kpm_xu_state", "kpm_vac_continue", "kpm_msd_continue", "lib"]

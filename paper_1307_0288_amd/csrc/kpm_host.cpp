@@ -794,73 +794,112 @@ kpm_status evolve_x_impl(kpm_system *sys, int vshift, const void *phi, void *out
     return KPM_OK;
 }
 
-// VAC loop of Alg. 2 (Eq. 42-43).
+// VAC loop of Alg. 2 (Eq. 42-43) from the state psi = U^dag(t_k) phi,
+// rr = U^dag(t_k) V phi: n steps of U(-dt) on both, then the moments
+// <V psi| T_m |rr>.  start: psi holds phi, rr is set to V phi here, and the
+// moments at t_k come first.  psi_io and rr_io are updated in place (the
+// final state is copied back when it ends in a scratch buffer).  out: host
+// [n_sys][n_vec][n_steps + start][nm] real parts.
 template <typename V>
-kpm_status vac_impl(kpm_system *sys, int vshift, const void *phi_v, int nsteps, double dt,
-                    int np, int nm, double *out) {
+kpm_status vac_run(kpm_system *sys, int vshift, V *psi_io, V *rr_io, bool start, int nsteps,
+                   double dt, int np, int nm, double *out) {
     KPM_TRY(sys->ensure_vecs(7, vshift));
-    const int64_t per_r = (int64_t)(nsteps + 1) * nm;
+    const int rows = nsteps + (start ? 1 : 0);
+    const int64_t per_r = (int64_t)rows * nm;
     const size_t elems = (size_t)sys->nseg * ((size_t)1 << vshift) * per_r;
     KPM_TRY(sys->ensure_dmom(elems));
     V *a = (V *)sys->vecs[0], *b = (V *)sys->vecs[1];
-    V *psi = (V *)sys->vecs[2], *psi2 = (V *)sys->vecs[3];
-    V *rr = (V *)sys->vecs[4], *rr2 = (V *)sys->vecs[5], *ll = (V *)sys->vecs[6];
-    const V *phi = (const V *)phi_v;
+    V *psi2 = (V *)sys->vecs[3], *rr2 = (V *)sys->vecs[5], *ll = (V *)sys->vecs[6];
     const kpm::Ell h = sys->ell_for(sys->launch[vshift]);
     kpm::Sweep sw;
     KPM_TRY(sys->sweep(vshift, &sw));
     const kpm::Coef alpha = sys->alpha();
-    // R_0 = V phi; L_0 = V psi_0 = R_0
-    kpm::launch_apply_d<V>(h, sw, phi, rr, alpha, sys->stream);
-    KPM_TRY(run_moments<V>(sys, vshift, rr, rr, nm, a, b, per_r, 0));
-    const V *cur = phi;
-    for (int k = 1; k <= nsteps; ++k) {
-        KPM_TRY(run_evolve<V>(sys, vshift, cur, psi2, nullptr, dt, -1, np, a, b));
+    V *psi = psi_io, *rr = rr_io;
+    int row = 0;
+    if (start) {
+        // R_0 = V phi; L_0 = V psi_0 = R_0
+        kpm::launch_apply_d<V>(h, sw, psi, rr, alpha, sys->stream);
+        KPM_TRY(run_moments<V>(sys, vshift, rr, rr, nm, a, b, per_r, 0));
+        row = 1;
+    }
+    for (int k = 1; k <= nsteps; ++k, ++row) {
+        KPM_TRY(run_evolve<V>(sys, vshift, psi, psi2, nullptr, dt, -1, np, a, b));
         std::swap(psi, psi2);
-        cur = psi;
         KPM_TRY(run_evolve<V>(sys, vshift, rr, rr2, nullptr, dt, -1, np, a, b));
         std::swap(rr, rr2);
         kpm::launch_apply_d<V>(h, sw, psi, ll, alpha, sys->stream);
-        KPM_TRY(run_moments<V>(sys, vshift, ll, rr, nm, a, b, per_r, (int64_t)k * nm));
+        KPM_TRY(run_moments<V>(sys, vshift, ll, rr, nm, a, b, per_r, (int64_t)row * nm));
     }
+    const size_t bytes = sys->state_bytes(vshift);
+    if (psi != psi_io) KPM_HIP(hipMemcpyAsync(psi_io, psi, bytes, hipMemcpyDeviceToDevice, sys->stream));
+    if (rr != rr_io) KPM_HIP(hipMemcpyAsync(rr_io, rr, bytes, hipMemcpyDeviceToDevice, sys->stream));
     std::vector<double2> host(elems);
     KPM_TRY(finish_moments(sys, host.size(), host.data()));
     for (size_t q = 0; q < host.size(); ++q) out[q] = host[q].x;
     return KPM_OK;
 }
 
-// MSD loop of Alg. 3 (Eq. 44); dbl takes the moments of Y_k in the doubling form.
 template <typename V>
-kpm_status msd_impl(kpm_system *sys, int vshift, const void *phi_v, int nsteps, double dt,
-                    int np, int nm, double *out, bool dbl) {
+kpm_status vac_impl(kpm_system *sys, int vshift, const void *phi, int nsteps, double dt, int np,
+                    int nm, double *out) {
     KPM_TRY(sys->ensure_vecs(9, vshift));
-    const int64_t per_r = (int64_t)(nsteps + 1) * nm;
+    V *psi = (V *)sys->vecs[7], *rr = (V *)sys->vecs[8];
+    KPM_HIP(hipMemcpyAsync(psi, phi, sys->state_bytes(vshift), hipMemcpyDeviceToDevice,
+                           sys->stream));
+    return vac_run<V>(sys, vshift, psi, rr, true, nsteps, dt, np, nm, out);
+}
+
+// MSD loop of Alg. 3 (Eq. 44) from the state psi' = U(t_k) phi, y = Y_k =
+// [X, U(t_k)] phi: n steps of Y <- U(dt) Y + [X, U(dt)] psi', psi' <- U(dt)
+// psi', then the moments of Y (in the doubling form when dbl).  start: psi'
+// holds phi and Y_0 = 0 (y's contents are ignored); the zero moments at t_k
+// come first.  In/out buffers and out as for vac_run.
+template <typename V>
+kpm_status msd_run(kpm_system *sys, int vshift, V *psi_io, V *y_io, bool start, int nsteps,
+                   double dt, int np, int nm, bool dbl, double *out) {
+    KPM_TRY(sys->ensure_vecs(7, vshift));
+    const int rows = nsteps + (start ? 1 : 0);
+    const int64_t per_r = (int64_t)rows * nm;
     const size_t elems = (size_t)sys->nseg * ((size_t)1 << vshift) * per_r;
     KPM_TRY(sys->ensure_dmom(elems));
     V *pa = (V *)sys->vecs[0], *pb = (V *)sys->vecs[1], *qa = (V *)sys->vecs[2],
       *qb = (V *)sys->vecs[3];
-    V *y = (V *)sys->vecs[4], *y2 = (V *)sys->vecs[5], *xu = (V *)sys->vecs[6];
-    V *psi = (V *)sys->vecs[7], *psi2 = (V *)sys->vecs[8];
+    V *y2 = (V *)sys->vecs[4], *xu = (V *)sys->vecs[5], *psi2 = (V *)sys->vecs[6];
     // Y_0 = [X, U(0)] phi = 0: its moments are exactly zero.
-    KPM_HIP(hipMemsetAsync(sys->dmom, 0, elems * sizeof(double2), sys->stream));
-    const V *cur = (const V *)phi_v;
-    for (int k = 1; k <= nsteps; ++k) {
+    if (start) KPM_HIP(hipMemsetAsync(sys->dmom, 0, elems * sizeof(double2), sys->stream));
+    V *psi = psi_io, *y = y_io;
+    bool y_zero = start;
+    int row = start ? 1 : 0;
+    for (int k = 1; k <= nsteps; ++k, ++row) {
         // [X, U(dt)] psi'_{k-1} and psi'_k = U(dt) psi'_{k-1}
-        KPM_TRY(run_evolve_x<V>(sys, vshift, cur, xu, psi2, dt, np, pa, pb, qa, qb));
+        KPM_TRY(run_evolve_x<V>(sys, vshift, psi, xu, psi2, dt, np, pa, pb, qa, qb));
         std::swap(psi, psi2);
-        cur = psi;
-        if (k == 1) {
+        if (y_zero) {
             std::swap(y, xu);                     // Y_1 = U(dt) 0 + [X, U(dt)] phi
+            y_zero = false;
         } else {
             KPM_TRY(run_evolve<V>(sys, vshift, y, y2, xu, dt, +1, np, pa, pb));
             std::swap(y, y2);                     // Y_k = U(dt) Y_{k-1} + [X, U(dt)] psi'
         }
-        KPM_TRY(run_moments<V>(sys, vshift, y, y, nm, pa, pb, per_r, (int64_t)k * nm, dbl));
+        KPM_TRY(run_moments<V>(sys, vshift, y, y, nm, pa, pb, per_r, (int64_t)row * nm, dbl));
     }
+    const size_t bytes = sys->state_bytes(vshift);
+    if (psi != psi_io) KPM_HIP(hipMemcpyAsync(psi_io, psi, bytes, hipMemcpyDeviceToDevice, sys->stream));
+    if (y != y_io) KPM_HIP(hipMemcpyAsync(y_io, y, bytes, hipMemcpyDeviceToDevice, sys->stream));
     std::vector<double2> host(elems);
     KPM_TRY(finish_moments(sys, host.size(), host.data()));
     for (size_t q = 0; q < host.size(); ++q) out[q] = host[q].x;
     return KPM_OK;
+}
+
+template <typename V>
+kpm_status msd_impl(kpm_system *sys, int vshift, const void *phi, int nsteps, double dt, int np,
+                    int nm, double *out, bool dbl) {
+    KPM_TRY(sys->ensure_vecs(9, vshift));
+    V *psi = (V *)sys->vecs[7], *y = (V *)sys->vecs[8];
+    KPM_HIP(hipMemcpyAsync(psi, phi, sys->state_bytes(vshift), hipMemcpyDeviceToDevice,
+                           sys->stream));
+    return msd_run<V>(sys, vshift, psi, y, true, nsteps, dt, np, nm, dbl, out);
 }
 
 // Y_n = [X, U(n dt)] phi by the recursion of Eq. 44, copied to out.
@@ -1334,6 +1373,42 @@ kpm_status kpm_msd_doubled(kpm_system *sys, int n_vec, const void *phi, int n_st
     return sys->prec == KPM_FP64
                ? msd_impl<double2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, out, true)
                : msd_impl<float2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, out, true);
+}
+
+static kpm_status check_continue(kpm_system *sys, int n_vec, void *a, void *b, int start,
+                                 int n_steps, double dt_fs, int n_bessel, int n_moments,
+                                 double *out, int *vs) {
+    KPM_TRY(check_loop(sys, n_vec, a, n_steps, dt_fs, n_bessel, n_moments, out, vs));
+    if (!b || a == b) return fail(KPM_ERR_INVALID, "null or aliased state buffers");
+    if (start != 0 && start != 1) return fail(KPM_ERR_INVALID, "start must be 0 or 1");
+    if (!start && n_steps < 1) return fail(KPM_ERR_INVALID, "n_steps must be >= 1 when continuing");
+    return KPM_OK;
+}
+
+kpm_status kpm_vac_continue(kpm_system *sys, int n_vec, void *psi, void *r, int start,
+                            int n_steps, double dt_fs, int n_bessel, int n_moments, double *out) {
+    int vs;
+    KPM_TRY(check_continue(sys, n_vec, psi, r, start, n_steps, dt_fs, n_bessel, n_moments, out, &vs));
+    DeviceGuard g(sys->device);
+    return sys->prec == KPM_FP64
+               ? vac_run<double2>(sys, vs, (double2 *)psi, (double2 *)r, start != 0, n_steps, dt_fs,
+                                  n_bessel, n_moments, out)
+               : vac_run<float2>(sys, vs, (float2 *)psi, (float2 *)r, start != 0, n_steps, dt_fs,
+                                 n_bessel, n_moments, out);
+}
+
+kpm_status kpm_msd_continue(kpm_system *sys, int n_vec, void *psi, void *y, int start,
+                            int n_steps, double dt_fs, int n_bessel, int n_moments, int doubled,
+                            double *out) {
+    int vs;
+    KPM_TRY(check_continue(sys, n_vec, psi, y, start, n_steps, dt_fs, n_bessel, n_moments, out, &vs));
+    if (doubled != 0 && doubled != 1) return fail(KPM_ERR_INVALID, "doubled must be 0 or 1");
+    DeviceGuard g(sys->device);
+    return sys->prec == KPM_FP64
+               ? msd_run<double2>(sys, vs, (double2 *)psi, (double2 *)y, start != 0, n_steps, dt_fs,
+                                  n_bessel, n_moments, doubled != 0, out)
+               : msd_run<float2>(sys, vs, (float2 *)psi, (float2 *)y, start != 0, n_steps, dt_fs,
+                                 n_bessel, n_moments, doubled != 0, out);
 }
 
 kpm_status kpm_xu_state(kpm_system *sys, int n_vec, const void *phi, int n_steps, double dt_fs,

@@ -36,7 +36,7 @@ ABI_SYMBOLS = ("kpm_build_graphene", "kpm_system_create", "kpm_system_destroy",
                "kpm_mlp_create", "kpm_mlp_destroy", "kpm_mlp_n_params", "kpm_mlp_set_params",
                "kpm_mlp_get_params", "kpm_mlp_forward", "kpm_mlp_gradients",
                "kpm_mlp_train_step", "kpm_learned_features", "kpm_learned_targets",
-               "kpm_xu_state",
+               "kpm_xu_state", "kpm_vac_continue", "kpm_msd_continue",
                "kpm_set_launch", "kpm_get_launch",
                "kpm_autotune", "kpm_set_graphs", "kpm_set_timing", "kpm_get_stats",
                "kpm_reset_stats",
@@ -131,6 +131,10 @@ def lib():
             "kpm_learned_targets": [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, dp, C.c_double,
                                     C.c_double, C.c_double, vp, fp],
             "kpm_xu_state": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, vp],
+            "kpm_vac_continue": [vp, C.c_int, vp, vp, C.c_int, C.c_int, C.c_double, C.c_int,
+                                 C.c_int, dp],
+            "kpm_msd_continue": [vp, C.c_int, vp, vp, C.c_int, C.c_int, C.c_double, C.c_int,
+                                 C.c_int, C.c_int, dp],
             "kpm_set_launch": [vp, C.c_int, C.POINTER(Launch)],
             "kpm_get_launch": [vp, C.c_int, C.POINTER(Launch)],
             "kpm_autotune": [vp, C.c_int, vp, C.c_int, C.POINTER(Launch)],
@@ -524,6 +528,32 @@ def kpm_msd_doubled(sys: System, phi, n_steps: int, dt_fs: float, n_bessel: int,
                     n_moments: int):
     """kpm_msd with the moments of each state in the doubling form."""
     return _loop(lib().kpm_msd_doubled, sys, phi, n_steps, dt_fs, n_bessel, n_moments)
+
+
+def _continue(fn, sys, a, b, start, n_steps, dt_fs, n_bessel, n_moments, *extra):
+    pa, nv = sys._state(a, "psi")
+    pb, nv2 = sys._state(b, "second state")
+    if nv != nv2:
+        raise ValueError("state buffers differ in n_vec")
+    out = np.empty((sys.n_samples, nv, n_steps + int(bool(start)), n_moments))
+    sys._sync_stream()
+    _check(fn(sys.handle, nv, pa, pb, int(bool(start)), n_steps, dt_fs, n_bessel, n_moments,
+              *extra, _dp(out)))
+    return sys._shape(out)
+
+
+def kpm_vac_continue(sys: System, psi, r, start: bool, n_steps: int, dt_fs: float,
+                     n_bessel: int, n_moments: int):
+    """VAC loop from the state (psi, r), both updated in place (see kpm.h)."""
+    return _continue(lib().kpm_vac_continue, sys, psi, r, start, n_steps, dt_fs, n_bessel,
+                     n_moments)
+
+
+def kpm_msd_continue(sys: System, psi, y, start: bool, n_steps: int, dt_fs: float,
+                     n_bessel: int, n_moments: int, doubled: bool = False):
+    """MSD loop from the state (psi, y), both updated in place (see kpm.h)."""
+    return _continue(lib().kpm_msd_continue, sys, psi, y, start, n_steps, dt_fs, n_bessel,
+                     n_moments, int(bool(doubled)))
 
 
 def kpm_set_launch(sys: System, n_vec: int, groups_per_cu: int, ilp: int, streaming: int = 0,
