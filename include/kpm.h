@@ -93,6 +93,11 @@ typedef struct kpm_system kpm_system;
  * selects the form a launch reads), and when every on-site energy is exactly
  * a float it is stored as a float.  The environment variable KPM_COMPACT=0
  * keeps only the explicit forms.
+ * Scratch: each system allocates its working memory (recursion states, group
+ * partials, moment staging) on first use and keeps it until destroy.  With
+ * KPM_SCRATCH_LIMIT_MB=M set at creation, a call whose working memory would
+ * exceed M MiB returns KPM_ERR_OOM before allocating anything; the system
+ * stays usable for smaller calls.
  */
 typedef struct {
     int64_t n_sites;
@@ -119,6 +124,18 @@ typedef struct {
  */
 kpm_status kpm_build_graphene(int64_t nx, int64_t ny, kpm_geometry geometry,
                               const uint8_t *active, int32_t *nbr, double *dx);
+
+/*
+ * Host-only check of one descriptor against every rule kpm_system_create
+ * applies (listed under kpm_system_desc), without touching a device.  When
+ * the structure is valid, *gershgorin (may be NULL) receives the Gershgorin
+ * bound max_n (|H_nn| + sum_m |H_nm|) in eV: the smallest e_scale for which
+ * the scaled spectrum lies in [-1, 1] as the Chebyshev expansion (Eq. 46)
+ * requires.  It is written also when e_scale itself is rejected, so a
+ * caller may validate with e_scale = 0 to learn the bound.
+ * Returns KPM_OK, or KPM_ERR_INVALID with the first violated rule.
+ */
+kpm_status kpm_validate(const kpm_system_desc *desc, double *gershgorin);
 
 /*
  * Create a system on `device` whose work runs on `hip_stream` (a

@@ -26,27 +26,33 @@ def _lib():
         if not os.path.exists(path):
             from . import build as _b
             _b.build()
-        lib = C.CDLL(path)
-        i64, dp, ip = C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_int64)
-        up = C.POINTER(C.c_ubyte)
-        lib.orc_graphene.restype = i64
-        lib.orc_graphene.argtypes = [i64, i64, C.c_int, C.c_double, up, ip, ip, dp, dp]
-        ham = [i64, ip, ip, dp, dp, dp, C.c_double]
-        lib.orc_moments.restype = C.c_int
-        lib.orc_moments.argtypes = ham + [dp, dp, C.c_int, dp]
-        lib.orc_bessel_j.restype = C.c_int
-        lib.orc_bessel_j.argtypes = [C.c_int, C.c_double, dp]
-        lib.orc_evolve.restype = C.c_int
-        lib.orc_evolve.argtypes = ham + [C.c_double, C.c_double, C.c_int, C.c_int, dp, dp]
-        lib.orc_evolve_x.restype = C.c_int
-        lib.orc_evolve_x.argtypes = ham + [C.c_double, C.c_double, C.c_int, dp, dp, dp]
-        lib.orc_fourier.restype = C.c_int
-        lib.orc_fourier.argtypes = ham + [C.c_double, dp, dp, C.c_int, C.c_double, C.c_int, dp]
-        for f in (lib.orc_vac, lib.orc_msd):
-            f.restype = C.c_int
-            f.argtypes = ham + [C.c_double, dp, C.c_int, C.c_double, C.c_int, C.c_int, dp]
-        _LIB = lib
+        _LIB = load(path)
     return _LIB
+
+
+def load(path):
+    """The C oracle built at `path` (liborc.so, or an instrumented build of the
+    same source), with its argument types set."""
+    lib = C.CDLL(path)
+    i64, dp, ip = C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_int64)
+    up = C.POINTER(C.c_ubyte)
+    lib.orc_graphene.restype = i64
+    lib.orc_graphene.argtypes = [i64, i64, C.c_int, C.c_double, up, ip, ip, dp, dp]
+    ham = [i64, ip, ip, dp, dp, dp, C.c_double]
+    lib.orc_moments.restype = C.c_int
+    lib.orc_moments.argtypes = ham + [dp, dp, C.c_int, dp]
+    lib.orc_bessel_j.restype = C.c_int
+    lib.orc_bessel_j.argtypes = [C.c_int, C.c_double, dp]
+    lib.orc_evolve.restype = C.c_int
+    lib.orc_evolve.argtypes = ham + [C.c_double, C.c_double, C.c_int, C.c_int, dp, dp]
+    lib.orc_evolve_x.restype = C.c_int
+    lib.orc_evolve_x.argtypes = ham + [C.c_double, C.c_double, C.c_int, dp, dp, dp]
+    lib.orc_fourier.restype = C.c_int
+    lib.orc_fourier.argtypes = ham + [C.c_double, dp, dp, C.c_int, C.c_double, C.c_int, dp]
+    for f in (lib.orc_vac, lib.orc_msd):
+        f.restype = C.c_int
+        f.argtypes = ham + [C.c_double, dp, C.c_int, C.c_double, C.c_int, C.c_int, dp]
+    return lib
 
 
 def _p(a, t=C.c_double):

@@ -6,4 +6,6 @@
 
 namespace kpm_detail {
 kpm_status set_error(kpm_status st, const char *msg);
+// set_error with a printf-style message
+kpm_status fail(kpm_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 }

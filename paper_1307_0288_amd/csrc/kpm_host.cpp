@@ -1,10 +1,11 @@
-// Host side of the C ABI declared in include/kpm.h: descriptor validation and
-// packing, device residency of the scaled Hamiltonian (one sample, or many
+// Host side of the C ABI declared in include/kpm.h: packing of validated
+// descriptors, device residency of the scaled Hamiltonian (one sample, or many
 // side by side), recursion scratch, and the drivers of Alg. 2, 3, 5, 6 and 7
 // that sequence the gfx950 kernels.
 #include "kpm.h"
 #include "kpm_internal.h"
 #include "kpm_error.h"
+#include "kpm_lattice.h"
 
 #include <hip/hip_runtime.h>
 
@@ -22,30 +23,12 @@
 namespace {
 
 constexpr double kHbar = 0.6582119569;   // eV fs
-constexpr double kBond = 0.142;          // nm, carbon-carbon distance (Sec. 2)
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kPartialRing = 256;        // moment slots of group partials kept at once
 
-thread_local std::string g_err;
-
-kpm_status fail(kpm_status st, const char *fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_err = buf;
-    return st;
-}
-
-}  // namespace
-
-kpm_status kpm_detail::set_error(kpm_status st, const char *msg) {
-    g_err = msg;
-    return st;
-}
-
-namespace {
+using kpm_detail::fail;
+using kpm_detail::Packed;
+using kpm_detail::pack_desc;
 
 #define KPM_HIP(call)                                                                \
     do {                                                                             \
@@ -153,85 +136,6 @@ kpm_launch default_launch(int vshift, kpm_precision prec) {
     // row order, beyond an XCD's L2
     l.tiled = vshift >= 3 ? 1 : 0;
     return l;
-}
-
-// One validated sample in neighbour-list form, energies in eV.  Removed
-// sites lose every bond and their on-site energy.
-struct Packed {
-    int64_t n = 0;
-    int w = 0;
-    std::vector<int32_t> nbr;   // [w][n], -1 = empty
-    std::vector<double> hop;    // [w][n] or empty (uniform t)
-    std::vector<double> ons;    // [n]
-    std::vector<double> dx;     // [w][n] or empty
-    double t = 0;
-    double e_scale = 1;
-};
-
-kpm_status pack_desc(const kpm_system_desc *d, int index, Packed &p) {
-    const int64_t n = d->n_sites;
-    const int w = d->width;
-    if (n < 1 || n >= ((int64_t)1 << 31)) return fail(KPM_ERR_INVALID, "sample %d: n_sites out of range", index);
-    if (w < 1 || w > KPM_MAX_WIDTH) return fail(KPM_ERR_INVALID, "sample %d: width must be 1..%d", index, KPM_MAX_WIDTH);
-    if (!d->nbr) return fail(KPM_ERR_INVALID, "sample %d: nbr is null", index);
-    if (!(d->e_scale > 0) || !std::isfinite(d->e_scale)) return fail(KPM_ERR_INVALID, "sample %d: e_scale", index);
-    if (!std::isfinite(d->t_uniform)) return fail(KPM_ERR_INVALID, "sample %d: t_uniform", index);
-    p.n = n;
-    p.w = w;
-    p.t = d->t_uniform;
-    p.e_scale = d->e_scale;
-    p.nbr.assign((size_t)w * n, -1);
-    p.ons.assign(n, 0.0);
-    if (d->hop) p.hop.assign((size_t)w * n, 0.0);
-    if (d->dx) p.dx.assign((size_t)w * n, 0.0);
-    auto alive = [&](int64_t s) { return !d->active || d->active[s] != 0; };
-    for (int64_t s = 0; s < n; ++s) {
-        p.ons[s] = (alive(s) && d->onsite) ? d->onsite[s] : 0.0;
-        if (!std::isfinite(p.ons[s])) return fail(KPM_ERR_INVALID, "sample %d: non-finite onsite at %lld", index, (long long)s);
-        for (int k = 0; k < w; ++k) {
-            const size_t q = (size_t)k * n + s;
-            int32_t m = d->nbr[q];
-            if (m < -1 || m >= n)
-                return fail(KPM_ERR_INVALID, "sample %d: neighbour index %d out of range at row %lld slot %d", index, m, (long long)s, k);
-            if (m >= 0 && (!alive(s) || !alive(m))) m = -1;
-            p.nbr[q] = m;
-            if (d->hop) {
-                p.hop[q] = m >= 0 ? d->hop[q] : 0.0;
-                if (!std::isfinite(p.hop[q])) return fail(KPM_ERR_INVALID, "sample %d: non-finite hop", index);
-            }
-            if (d->dx) {
-                p.dx[q] = m >= 0 ? d->dx[q] : 0.0;
-                if (!std::isfinite(p.dx[q])) return fail(KPM_ERR_INVALID, "sample %d: non-finite dx", index);
-            }
-        }
-    }
-    // Symmetry: every bond listed from both ends with equal H and opposite dx.
-    double gersh = 0.0;
-    for (int64_t s = 0; s < n; ++s) {
-        double row = std::fabs(p.ons[s]);
-        for (int k = 0; k < w; ++k) {
-            const size_t q = (size_t)k * n + s;
-            const int32_t m = p.nbr[q];
-            if (m < 0) continue;
-            const double hv = d->hop ? p.hop[q] : p.t;
-            row += std::fabs(hv);
-            bool found = false;
-            for (int k2 = 0; k2 < w && !found; ++k2) {
-                const size_t q2 = (size_t)k2 * n + m;
-                if (p.nbr[q2] != s) continue;
-                const double hb = d->hop ? p.hop[q2] : p.t;
-                if (hb != hv) continue;
-                if (d->dx && p.dx[q2] != -p.dx[q]) continue;
-                found = true;
-            }
-            if (!found)
-                return fail(KPM_ERR_INVALID, "sample %d: H not symmetric (or dx not antisymmetric) at row %lld slot %d", index, (long long)s, k);
-        }
-        gersh = std::max(gersh, row);
-    }
-    if (d->e_scale < gersh)
-        return fail(KPM_ERR_INVALID, "sample %d: e_scale %.6g below the Gershgorin bound %.6g", index, d->e_scale, gersh);
-    return KPM_OK;
 }
 
 }  // namespace
@@ -477,9 +381,22 @@ struct kpm_system {
         return nseg == 1 ? kpm::coef_val(v) : kpm::coef_tab(d_alpha, 1, 0, v);
     }
 
+    // Scratch limit (KPM_SCRATCH_LIMIT_MB at creation; 0 = none): the recursion
+    // buffers, partials and moments together may not exceed it.
+    size_t scratch_limit = 0;
+    kpm_status check_scratch(size_t nvec, size_t vbytes, size_t pelems, size_t delems) const {
+        const size_t total = nvec * vbytes + (pelems + delems) * sizeof(double2);
+        if (scratch_limit && total > scratch_limit)
+            return fail(KPM_ERR_OOM, "scratch of %zu bytes exceeds the limit of %zu bytes", total,
+                        scratch_limit);
+        return KPM_OK;
+    }
+
     // Makes sure `count` state vectors of n_vec vectors each exist.
     kpm_status ensure_vecs(int count, int vshift) {
         const size_t bytes = state_bytes(vshift);
+        KPM_TRY(check_scratch(std::max<size_t>(count, vecs.size()), std::max(bytes, vec_bytes),
+                              partial_elems, dmom_elems));
         if (bytes > vec_bytes) {
             drop_graphs();
             KPM_HIP(hipStreamSynchronize(stream));
@@ -499,6 +416,7 @@ struct kpm_system {
     kpm_status ensure_partial(int slots, int nwg, int n_vec) {
         const size_t need = (size_t)slots * nwg * n_vec;
         if (need > partial_elems) {
+            KPM_TRY(check_scratch(vecs.size(), vec_bytes, need, dmom_elems));
             drop_graphs();
             KPM_HIP(hipStreamSynchronize(stream));
             if (partial) (void)hipFree(partial);
@@ -511,6 +429,7 @@ struct kpm_system {
 
     kpm_status ensure_dmom(size_t elems) {
         if (elems > dmom_elems) {
+            KPM_TRY(check_scratch(vecs.size(), vec_bytes, partial_elems, elems));
             drop_graphs();
             KPM_HIP(hipStreamSynchronize(stream));
             if (dmom) (void)hipFree(dmom);
@@ -1080,7 +999,9 @@ kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int devi
     if (const char *env = std::getenv("KPM_COMPACT_LAUNCH"))
         for (auto &l : sys->launch) l.compact = atoi(env) != 0;
     if (const char *env = std::getenv("KPM_TILED"))
-        for (auto &l : sys->launch) l.tiled = atoi(env) != 0;
+        for (auto &l : sys->launch) l.tiled = std::max(0, std::min(3, atoi(env)));
+    if (const char *env = std::getenv("KPM_SCRATCH_LIMIT_MB"))
+        sys->scratch_limit = (size_t)(std::max(0.0, atof(env)) * 1048576.0);
     sys->chain.resize(nseg);
     for (int s = 0; s < nseg; ++s) sys->chain[s] = chain_length(parts[s].nbr, parts[s].w, parts[s].n);
 
@@ -1200,57 +1121,6 @@ kpm_status check_loop(kpm_system *sys, int n_vec, const void *phi, int n_steps, 
 
 // ======================================================================= ABI
 extern "C" {
-
-const char *kpm_last_error(void) { return g_err.c_str(); }
-
-const char *kpm_version(void) { return "kpm-mi355x 0.2 (gfx950)"; }
-
-kpm_status kpm_build_graphene(int64_t nx, int64_t ny, kpm_geometry geometry,
-                              const uint8_t *active, int32_t *nbr, double *dx) {
-    const bool pbc_x = geometry == KPM_SHEET || geometry == KPM_ZGNR;
-    const bool pbc_y = geometry == KPM_SHEET || geometry == KPM_AGNR;
-    if (geometry < KPM_SHEET || geometry > KPM_AGNR) return fail(KPM_ERR_INVALID, "geometry");
-    if (nx < 2 || ny < 1 || nx * ny >= (int64_t)1 << 31)
-        return fail(KPM_ERR_INVALID, "lattice size %lld x %lld", (long long)nx, (long long)ny);
-    if (pbc_x && (nx % 2 || nx < 4)) return fail(KPM_ERR_INVALID, "periodic x needs even nx >= 4");
-    if (pbc_y && (ny % 2 || ny < 2)) return fail(KPM_ERR_INVALID, "periodic y needs even ny >= 2");
-    if (!nbr) return fail(KPM_ERR_INVALID, "nbr is null");
-    const int64_t n = nx * ny;
-    const double half_zig = std::sqrt(3.0) * kBond / 2.0;
-    for (int64_t j = 0; j < ny; ++j) {
-        for (int64_t i = 0; i < nx; ++i) {
-            const int64_t s = j * nx + i;
-            const bool up = ((i + j) & 1) != 0;             // odd sites bond upwards
-            int64_t li = i - 1, ri = i + 1, vj = up ? j + 1 : j - 1;
-            bool lok = true, rok = true, vok = true;
-            if (li < 0) { lok = pbc_x; li += nx; }
-            if (ri >= nx) { rok = pbc_x; ri -= nx; }
-            if (vj < 0) { vok = pbc_y; vj += ny; }
-            if (vj >= ny) { vok = pbc_y; vj -= ny; }
-            const int64_t m[3] = {j * nx + li, j * nx + ri, vj * nx + i};
-            const bool ok[3] = {lok, rok, vok};
-            // displacement X_s - X_m of each slot along the transport axis
-            double d[3];
-            if (geometry == KPM_AGNR) {
-                const double dy = up ? kBond / 2 : -kBond / 2;   // chain neighbours
-                d[0] = dy;
-                d[1] = dy;
-                d[2] = up ? -kBond : kBond;
-            } else {
-                d[0] = half_zig;
-                d[1] = -half_zig;
-                d[2] = 0.0;
-            }
-            const bool alive = !active || active[s];
-            for (int k = 0; k < 3; ++k) {
-                const bool use = alive && ok[k] && (!active || active[m[k]]);
-                nbr[k * n + s] = use ? (int32_t)m[k] : -1;
-                if (dx) dx[k * n + s] = use ? d[k] : 0.0;
-            }
-        }
-    }
-    return KPM_OK;
-}
 
 kpm_status kpm_system_create(const kpm_system_desc *d, kpm_precision prec, int device,
                              void *hip_stream, kpm_system **out) {
@@ -1522,49 +1392,6 @@ kpm_status kpm_kpm_sum(int n_rows, int n_moments, const double *moments, int n_e
     chk(hipStreamSynchronize(s));
     (void)hipFree(buf);
     return st;
-}
-
-kpm_status kpm_sigma_gk(int nt, int ne, const double *in, double dt, double *out) {
-    if (nt < 1 || ne < 1 || !in || !out || in == out || !(dt > 0))
-        return fail(KPM_ERR_INVALID, "sigma_gk arguments");
-    const double f = 2.0 * kPi * kHbar;
-    for (int k = 0; k < ne; ++k) {
-        double acc = 0.0;
-        out[k] = 0.0;
-        for (int t = 1; t < nt; ++t) {
-            acc += 0.5 * (in[(size_t)t * ne + k] + in[(size_t)(t - 1) * ne + k]) * dt;
-            out[(size_t)t * ne + k] = f * acc;
-        }
-    }
-    return KPM_OK;
-}
-
-kpm_status kpm_sigma_e1(int nt, int ne, const double *in, double dt, double *out) {
-    if (nt < 1 || ne < 1 || !in || !out || in == out || !(dt > 0))
-        return fail(KPM_ERR_INVALID, "sigma_e1 arguments");
-    const double f = kPi * kHbar;
-    for (int k = 0; k < ne; ++k) {
-        for (int t = 0; t < nt; ++t) {
-            double d;
-            if (nt == 1) d = 0.0;
-            else if (t == 0) d = (in[(size_t)ne + k] - in[k]) / dt;
-            else if (t == nt - 1) d = (in[(size_t)t * ne + k] - in[(size_t)(t - 1) * ne + k]) / dt;
-            else d = (in[(size_t)(t + 1) * ne + k] - in[(size_t)(t - 1) * ne + k]) / (2.0 * dt);
-            out[(size_t)t * ne + k] = f * d;
-        }
-    }
-    return KPM_OK;
-}
-
-kpm_status kpm_sigma_e2(int nt, int ne, const double *in, double dt, double *out) {
-    if (nt < 1 || ne < 1 || !in || !out || in == out || !(dt > 0))
-        return fail(KPM_ERR_INVALID, "sigma_e2 arguments");
-    const double f = kPi * kHbar;
-    for (int k = 0; k < ne; ++k) out[k] = 0.0;
-    for (int t = 1; t < nt; ++t)
-        for (int k = 0; k < ne; ++k)
-            out[(size_t)t * ne + k] = f * in[(size_t)t * ne + k] / (t * dt);
-    return KPM_OK;
 }
 
 kpm_status kpm_set_launch(kpm_system *sys, int n_vec, const kpm_launch *l) {

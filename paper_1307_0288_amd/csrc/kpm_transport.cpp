@@ -1,5 +1,5 @@
-// Transport quantities derived from the running conductivities (host side of
-// the C ABI): length and conductance (Sec. 5.1, Eq. 50-52), semi-classical
+// Running conductivities (Eq. 6, 9, 11) and the transport quantities derived
+// from them (host side of the C ABI): length and conductance (Sec. 5.1, Eq. 50-52), semi-classical
 // conductivity by maximum or time-block average (Sec. 5.2, Eq. 53 and 55),
 // the Pade fit of a saturating MSD (Sec. 5.3, Eq. 58) and the typical
 // conductance (Eq. 60).  Arrays are [n_times][n_energies], time t_k = k dt.
@@ -61,6 +61,53 @@ bool least_squares(int rows, int cols, std::vector<double> &a, std::vector<doubl
 }  // namespace
 
 extern "C" {
+
+// Running conductivities in e^2/h from the per-time inputs: Green-Kubo
+// (Eq. 6, trapezoid integral of the VAC), Einstein E1 (Eq. 9, derivative of
+// the MSD, central differences inside, one-sided at the ends) and E2 (Eq. 11,
+// MSD over time).
+kpm_status kpm_sigma_gk(int nt, int ne, const double *in, double dt, double *out) {
+    if (nt < 1 || ne < 1 || !in || !out || in == out || !(dt > 0))
+        return bad("sigma_gk arguments");
+    const double f = 2.0 * kPi * kHbar;
+    for (int k = 0; k < ne; ++k) {
+        double acc = 0.0;
+        out[k] = 0.0;
+        for (int t = 1; t < nt; ++t) {
+            acc += 0.5 * (in[(size_t)t * ne + k] + in[(size_t)(t - 1) * ne + k]) * dt;
+            out[(size_t)t * ne + k] = f * acc;
+        }
+    }
+    return KPM_OK;
+}
+
+kpm_status kpm_sigma_e1(int nt, int ne, const double *in, double dt, double *out) {
+    if (nt < 1 || ne < 1 || !in || !out || in == out || !(dt > 0))
+        return bad("sigma_e1 arguments");
+    const double f = kPi * kHbar;
+    for (int k = 0; k < ne; ++k) {
+        for (int t = 0; t < nt; ++t) {
+            double d;
+            if (nt == 1) d = 0.0;
+            else if (t == 0) d = (in[(size_t)ne + k] - in[k]) / dt;
+            else if (t == nt - 1) d = (in[(size_t)t * ne + k] - in[(size_t)(t - 1) * ne + k]) / dt;
+            else d = (in[(size_t)(t + 1) * ne + k] - in[(size_t)(t - 1) * ne + k]) / (2.0 * dt);
+            out[(size_t)t * ne + k] = f * d;
+        }
+    }
+    return KPM_OK;
+}
+
+kpm_status kpm_sigma_e2(int nt, int ne, const double *in, double dt, double *out) {
+    if (nt < 1 || ne < 1 || !in || !out || in == out || !(dt > 0))
+        return bad("sigma_e2 arguments");
+    const double f = kPi * kHbar;
+    for (int k = 0; k < ne; ++k) out[k] = 0.0;
+    for (int t = 1; t < nt; ++t)
+        for (int k = 0; k < ne; ++k)
+            out[(size_t)t * ne + k] = f * in[(size_t)t * ne + k] / (t * dt);
+    return KPM_OK;
+}
 
 kpm_status kpm_length(int nt, int ne, const double *rho_msd, const double *rho, double *out) {
     if (nt < 1 || ne < 1 || !rho_msd || !rho || !out) return bad("length arguments");

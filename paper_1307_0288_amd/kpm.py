@@ -24,7 +24,7 @@ HBAR_EV_FS = 0.6582119569
 BOND_NM = 0.142
 
 # Every symbol declared in include/kpm.h.
-ABI_SYMBOLS = ("kpm_build_graphene", "kpm_system_create", "kpm_system_destroy",
+ABI_SYMBOLS = ("kpm_build_graphene", "kpm_validate", "kpm_system_create", "kpm_system_destroy",
                "kpm_system_set_stream", "kpm_system_n_sites", "kpm_batch_create",
                "kpm_system_n_samples", "kpm_system_offsets", "kpm_moments",
                "kpm_moments_doubled", "kpm_evolve", "kpm_evolve_x", "kpm_vac", "kpm_msd",
@@ -79,6 +79,67 @@ class Stats(C.Structure):
 _lib = None
 
 
+def _signatures():
+    """Argument types of every compute entry point (all return kpm_status)."""
+    vp, dp, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int64
+    fp = C.POINTER(C.c_float)
+    return {
+        "kpm_build_graphene": [i64, i64, C.c_int, C.POINTER(C.c_uint8), C.POINTER(C.c_int32), dp],
+        "kpm_validate": [C.POINTER(_Desc), dp],
+        "kpm_system_create": [C.POINTER(_Desc), C.c_int, C.c_int, vp, C.POINTER(vp)],
+        "kpm_batch_create": [C.c_int, C.POINTER(_Desc), C.c_int, C.c_int, vp, C.POINTER(vp)],
+        "kpm_system_offsets": [vp, C.POINTER(C.c_int64)],
+        "kpm_system_destroy": [vp],
+        "kpm_system_set_stream": [vp, vp],
+        "kpm_moments": [vp, C.c_int, vp, vp, C.c_int, dp],
+        "kpm_moments_doubled": [vp, C.c_int, vp, C.c_int, dp],
+        "kpm_evolve": [vp, C.c_int, vp, C.c_double, C.c_int, C.c_int],
+        "kpm_evolve_x": [vp, C.c_int, vp, vp, vp, C.c_double, C.c_int],
+        "kpm_vac": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, C.c_int, dp],
+        "kpm_msd": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, C.c_int, dp],
+        "kpm_msd_doubled": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, C.c_int, dp],
+        "kpm_kpm_sum": [C.c_int, C.c_int, dp, C.c_int, dp, C.c_double, C.c_double,
+                        C.c_int, vp, dp],
+        "kpm_fourier_moments": [vp, C.c_int, vp, vp, C.c_int, C.c_double, C.c_int, dp],
+        "kpm_ftm_sum": [C.c_int, C.c_int, dp, C.c_int, dp, C.c_double, C.c_double,
+                        C.c_int, vp, dp],
+        "kpm_sigma_gk": [C.c_int, C.c_int, dp, C.c_double, dp],
+        "kpm_sigma_e1": [C.c_int, C.c_int, dp, C.c_double, dp],
+        "kpm_sigma_e2": [C.c_int, C.c_int, dp, C.c_double, dp],
+        "kpm_length": [C.c_int, C.c_int, dp, dp, dp],
+        "kpm_conductance": [C.c_int, C.c_int, dp, dp, C.c_double, dp],
+        "kpm_ballistic_conductance": [C.c_int, C.c_int, dp, dp, C.c_double, C.c_double, dp],
+        "kpm_sigma_sc_max": [C.c_int, C.c_int, dp, dp],
+        "kpm_sigma_sc_average": [C.c_int, C.c_int, dp, C.c_int, C.c_int, dp],
+        "kpm_pade_fit": [C.c_int, dp, dp, C.c_int, C.c_int, C.c_int, dp, dp],
+        "kpm_pade_eval": [C.c_int, C.c_int, dp, dp, C.c_int, dp, dp, dp],
+        "kpm_typical_conductance": [C.c_int, C.c_int, dp, dp],
+        "kpm_mlp_create": [C.c_int, C.POINTER(C.c_int32), C.c_int, C.c_int, vp,
+                           C.POINTER(vp)],
+        "kpm_mlp_destroy": [vp],
+        "kpm_mlp_set_params": [vp, fp],
+        "kpm_mlp_get_params": [vp, fp],
+        "kpm_mlp_forward": [vp, C.c_int, vp, vp],
+        "kpm_mlp_gradients": [vp, C.c_int, vp, vp, dp, fp],
+        "kpm_mlp_train_step": [vp, C.c_int, vp, vp, C.POINTER(Adam), dp],
+        "kpm_learned_features": [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, fp],
+        "kpm_learned_targets": [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, dp, C.c_double,
+                                C.c_double, C.c_double, vp, fp],
+        "kpm_xu_state": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, vp],
+        "kpm_vac_continue": [vp, C.c_int, vp, vp, C.c_int, C.c_int, C.c_double, C.c_int,
+                             C.c_int, dp],
+        "kpm_msd_continue": [vp, C.c_int, vp, vp, C.c_int, C.c_int, C.c_double, C.c_int,
+                             C.c_int, C.c_int, dp],
+        "kpm_set_launch": [vp, C.c_int, C.POINTER(Launch)],
+        "kpm_get_launch": [vp, C.c_int, C.POINTER(Launch)],
+        "kpm_autotune": [vp, C.c_int, vp, C.c_int, C.POINTER(Launch)],
+        "kpm_set_graphs": [vp, C.c_int],
+        "kpm_set_timing": [vp, C.c_int],
+        "kpm_get_stats": [vp, C.POINTER(Stats)],
+        "kpm_reset_stats": [vp],
+    }
+
+
 def lib():
     """The loaded libkpm.so; raises if it has not been built."""
     global _lib
@@ -87,62 +148,8 @@ def lib():
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_1307_0288_amd.build` (hipcc, gfx950)")
         L = C.CDLL(LIB_PATH)
-        vp, dp, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int64
-        fp = C.POINTER(C.c_float)
-        sig = {
-            "kpm_build_graphene": [i64, i64, C.c_int, C.POINTER(C.c_uint8), C.POINTER(C.c_int32), dp],
-            "kpm_system_create": [C.POINTER(_Desc), C.c_int, C.c_int, vp, C.POINTER(vp)],
-            "kpm_batch_create": [C.c_int, C.POINTER(_Desc), C.c_int, C.c_int, vp, C.POINTER(vp)],
-            "kpm_system_offsets": [vp, C.POINTER(C.c_int64)],
-            "kpm_system_destroy": [vp],
-            "kpm_system_set_stream": [vp, vp],
-            "kpm_moments": [vp, C.c_int, vp, vp, C.c_int, dp],
-            "kpm_moments_doubled": [vp, C.c_int, vp, C.c_int, dp],
-            "kpm_evolve": [vp, C.c_int, vp, C.c_double, C.c_int, C.c_int],
-            "kpm_evolve_x": [vp, C.c_int, vp, vp, vp, C.c_double, C.c_int],
-            "kpm_vac": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, C.c_int, dp],
-            "kpm_msd": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, C.c_int, dp],
-            "kpm_msd_doubled": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, C.c_int, dp],
-            "kpm_kpm_sum": [C.c_int, C.c_int, dp, C.c_int, dp, C.c_double, C.c_double,
-                            C.c_int, vp, dp],
-            "kpm_fourier_moments": [vp, C.c_int, vp, vp, C.c_int, C.c_double, C.c_int, dp],
-            "kpm_ftm_sum": [C.c_int, C.c_int, dp, C.c_int, dp, C.c_double, C.c_double,
-                            C.c_int, vp, dp],
-            "kpm_sigma_gk": [C.c_int, C.c_int, dp, C.c_double, dp],
-            "kpm_sigma_e1": [C.c_int, C.c_int, dp, C.c_double, dp],
-            "kpm_sigma_e2": [C.c_int, C.c_int, dp, C.c_double, dp],
-            "kpm_length": [C.c_int, C.c_int, dp, dp, dp],
-            "kpm_conductance": [C.c_int, C.c_int, dp, dp, C.c_double, dp],
-            "kpm_ballistic_conductance": [C.c_int, C.c_int, dp, dp, C.c_double, C.c_double, dp],
-            "kpm_sigma_sc_max": [C.c_int, C.c_int, dp, dp],
-            "kpm_sigma_sc_average": [C.c_int, C.c_int, dp, C.c_int, C.c_int, dp],
-            "kpm_pade_fit": [C.c_int, dp, dp, C.c_int, C.c_int, C.c_int, dp, dp],
-            "kpm_pade_eval": [C.c_int, C.c_int, dp, dp, C.c_int, dp, dp, dp],
-            "kpm_typical_conductance": [C.c_int, C.c_int, dp, dp],
-            "kpm_mlp_create": [C.c_int, C.POINTER(C.c_int32), C.c_int, C.c_int, vp,
-                               C.POINTER(vp)],
-            "kpm_mlp_destroy": [vp],
-            "kpm_mlp_set_params": [vp, fp],
-            "kpm_mlp_get_params": [vp, fp],
-            "kpm_mlp_forward": [vp, C.c_int, vp, vp],
-            "kpm_mlp_gradients": [vp, C.c_int, vp, vp, dp, fp],
-            "kpm_mlp_train_step": [vp, C.c_int, vp, vp, C.POINTER(Adam), dp],
-            "kpm_learned_features": [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, fp],
-            "kpm_learned_targets": [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, dp, C.c_double,
-                                    C.c_double, C.c_double, vp, fp],
-            "kpm_xu_state": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, vp],
-            "kpm_vac_continue": [vp, C.c_int, vp, vp, C.c_int, C.c_int, C.c_double, C.c_int,
-                                 C.c_int, dp],
-            "kpm_msd_continue": [vp, C.c_int, vp, vp, C.c_int, C.c_int, C.c_double, C.c_int,
-                                 C.c_int, C.c_int, dp],
-            "kpm_set_launch": [vp, C.c_int, C.POINTER(Launch)],
-            "kpm_get_launch": [vp, C.c_int, C.POINTER(Launch)],
-            "kpm_autotune": [vp, C.c_int, vp, C.c_int, C.POINTER(Launch)],
-            "kpm_set_graphs": [vp, C.c_int],
-            "kpm_set_timing": [vp, C.c_int],
-            "kpm_get_stats": [vp, C.POINTER(Stats)],
-            "kpm_reset_stats": [vp],
-        }
+        vp = C.c_void_p
+        sig = _signatures()
         for name, args in sig.items():
             f = getattr(L, name)
             f.argtypes = args
@@ -348,6 +355,19 @@ def _make_desc(nbr, e_scale, t_uniform=-2.7, hop=None, onsite=None, dx=None, act
                  _dp(onsite), _dp(dx),
                  None if active is None else active.ctypes.data_as(C.POINTER(C.c_uint8)),
                  e_scale)
+
+
+def kpm_validate(nbr, e_scale: float = 0.0, t_uniform: float = -2.7, hop=None, onsite=None,
+                 dx=None, active=None):
+    """Host check of a descriptor (the rules of kpm_system_create); returns the
+    Gershgorin bound in eV.  With e_scale = 0 only the structure is checked."""
+    keep = []
+    d = _make_desc(nbr, e_scale, t_uniform, hop, onsite, dx, active, keep)
+    bound = C.c_double(float("nan"))
+    st = lib().kpm_validate(C.byref(d), C.byref(bound))
+    if st != KPM_OK and not (e_scale == 0.0 and np.isfinite(bound.value)):
+        _check(st)
+    return bound.value
 
 
 class System:

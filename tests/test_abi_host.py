@@ -98,7 +98,28 @@ def test_create_validates_before_touching_a_device(case):
     h = C.c_void_p()
     st = kp.lib().kpm_system_create(C.byref(d), 0, 0, None, C.byref(h))
     assert st == 1, kp.lib().kpm_last_error()
-    assert kp.lib().kpm_last_error()
+    msg = kp.lib().kpm_last_error()
+    assert msg
+    # the host-only check applies the same rules and reports the same message
+    bound = C.c_double(-1.0)
+    assert kp.lib().kpm_validate(C.byref(d), C.byref(bound)) == 1
+    assert kp.lib().kpm_last_error() == msg
+
+
+@pytest.mark.parametrize("geometry", ["sheet", "zgnr", "agnr"])
+def test_validate_reports_gershgorin_bound(geometry):
+    """Full coordination in a periodic sheet: 3|t| + max|H_nn|; ribbon edges and
+    vacancies lower some rows but a bulk row still has three bonds."""
+    n = 12 * 10
+    ons = ki.anderson_onsite(n, 1.2, 3)
+    act = ki.vacancy_mask(n, 0.03, 4)
+    nbr, dx = kp.kpm_build_graphene(12, 10, geometry, act)
+    bound = kp.kpm_validate(nbr, dx=dx, onsite=ons, active=act)
+    rows = [abs(ons[s]) * act[s] + 2.7 * np.sum(nbr[:, s] >= 0) for s in range(n)]
+    assert bound == pytest.approx(max(rows), rel=1e-15)
+    assert kp.kpm_validate(nbr, e_scale=bound, dx=dx, onsite=ons, active=act) == bound
+    with pytest.raises(kp.KpmError):
+        kp.kpm_validate(nbr, e_scale=0.999 * bound, dx=dx, onsite=ons, active=act)
 
 
 def test_running_conductivities_match_oracle():
