@@ -29,23 +29,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 import kpm_inputs as ki  # noqa: E402
-from paper_1307_0288_amd.profile_run import measured_traffic  # noqa: E402
+from paper_1307_0288_amd.profile_run import (measured_traffic, moment_kernel_name,  # noqa: E402
+                                              multi_step)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "moment_step_fp64_paper_traffic.json")
 TRAFFIC_FILE_DBL = os.path.join(ROOT, "profiles", "moment_step_doubled_fp64_paper_traffic.json")
+TRAFFIC_FILE2 = os.path.join(ROOT, "profiles", "moment_multistep_fp64_paper_traffic.json")
+TRAFFIC_FILE2_DBL = os.path.join(ROOT, "profiles", "moment_multistep_doubled_fp64_paper_traffic.json")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def step_kernel_name(v: str, launch: dict, dbl: bool) -> str:
-    """Instantiation of the moment step for a graphene system (width 3, uniform
-    hopping, float-exact on-site terms) under a launch shape."""
-    form = "kFormC3F" if launch["compact"] else "kFormL3F"
-    return (f"k_moment_step<{v},{launch['ilp']},{'true' if launch['streaming'] else 'false'},"
-            f"{form},{'true' if dbl else 'false'}>")
+def achieved_gbs(st) -> float:
+    """Algorithmic GB/s of the timed moment-step launches: their bytes over
+    their summed event time."""
+    return st["step_bytes_total"] / max(st["step_ms"], 1e-9) / 1e6
 
 
 def cpu_baseline(p, lat_args, n_moments: int):
@@ -144,9 +145,10 @@ def main():
     value = st["site_updates"] / elapsed / 1e9
     launch_ms = st["step_ms"] / max(st["step_launches"], 1)
     bytes_launch = st["step_bytes"]
-    bpu = bytes_launch / st["step_rows"]
-    achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
-    traffic = measured_traffic(TRAFFIC_FILE, st["step_rows"], launch)
+    two = multi_step(launch)
+    bpu = bytes_launch / st["step_rows"] / (launch["steps"] if two else 1)
+    achieved = achieved_gbs(st)
+    traffic = measured_traffic(TRAFFIC_FILE2 if two else TRAFFIC_FILE, st["step_rows"], launch)
 
     cpu = None
     if args.cpu_moments > 0:
@@ -171,7 +173,7 @@ def main():
                                "x 40 Bessel terms, dt=hbar/|t|",
                    "n_sites": n, "n_vec": 1, "n_moments": nm, "n_steps": ns,
                    "n_bessel": nb, "site_updates_per_step": st["site_updates"] // args.steps},
-        "roofline": {"kernel": step_kernel_name("double2", launch, False), "bound": "hbm",
+        "roofline": {"kernel": moment_kernel_name("double2", launch, False), "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_site_update": round(bpu, 3),
@@ -223,7 +225,7 @@ def doubled(args):
         res[name] = {"ms": round(el * 1e3, 3), "moments_per_s": round(n_mom / el, 1),
                      "step_launch_us": round(launch_ms * 1e3, 3),
                      "step_bytes": st["step_bytes"],
-                     "step_gbs": round(st["step_bytes"] / (launch_ms * 1e-3) / 1e9, 1)}
+                     "step_gbs": round(achieved_gbs(st), 1)}
         log(f"{name}: {res[name]}")
     n_act = float(np.count_nonzero(act))
     err_dos = float(np.max(np.abs(outs["dos_doubled"] - outs["dos_direct"])) / n_act)
@@ -247,10 +249,11 @@ def doubled(args):
                                "W=0.1 eV, 1 random-phase vector, 3000 moments; MSD 20 steps x "
                                "40 Bessel terms, dt=hbar/|t|",
                    "n_sites": n, "n_moments": nm, "launch_shape": launch},
-        "roofline": {"kernel": step_kernel_name("double2", launch, True), "bound": "hbm",
+        "roofline": {"kernel": moment_kernel_name("double2", launch, True), "bound": "hbm",
                      "achieved": dd["step_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(dd["step_gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(TRAFFIC_FILE_DBL, n, launch),
+                     "traffic": measured_traffic(TRAFFIC_FILE2_DBL if multi_step(launch)
+                                                 else TRAFFIC_FILE_DBL, n, launch),
                      "bytes_per_launch": dd["step_bytes"],
                      "avg_launch_us": dd["step_launch_us"]},
         "forms": res,
@@ -312,7 +315,7 @@ def ballistic(args):
     st = kp.kpm_get_stats(sysg)
     kp.kpm_set_timing(sysg, False)
     launch_ms = st["step_ms"] / max(st["step_launches"], 1)
-    achieved = st["step_bytes"] / (launch_ms * 1e-3) / 1e9
+    achieved = achieved_gbs(st)
     plateau = (np.abs(en) >= 0.2) & (np.abs(en) <= 0.55)
     k_mid = ns // 2
     dev = float(np.max(np.abs(g[k_mid:-1, plateau] - 2.0)))
@@ -333,7 +336,7 @@ def ballistic(args):
                                "trace from 32 cell unit vectors, 1000 moments (doubling form), "
                                "MSD 20 steps x 2 fs x 45 Bessel terms, G(E) on 64 energies",
                    "n_sites": n, "n_vec": n_vec, "launch_shape": launch},
-        "roofline": {"kernel": step_kernel_name("double2", launch, True), "bound": "hbm",
+        "roofline": {"kernel": moment_kernel_name("double2", launch, True, n_vec), "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "avg_launch_us": round(launch_ms * 1e3, 3)},

@@ -432,9 +432,23 @@ kpm_status kpm_xu_state(kpm_system *sys, int n_vec, const void *phi, int n_steps
  * chain length found from the most common neighbour offset beyond 1) so that a
  * row's vertical neighbour is reused from cache even when a row carries many
  * vectors; tiled = 0, and samples without such a chain structure or with
- * chains shorter than two tiles, keep row order.  At a fixed grid size and traversal the moments are bit-identical for
- * every ilp, streaming and compact choice; the grid size and the traversal
- * change only the order of the inner-product partial sums.
+ * chains shorter than two tiles, keep row order.  steps = 2, 3 or 4
+ * advances the recursion that many steps per pass: from phi_n and phi_{n-1}
+ * a pass writes only the last two states, so each row's states cross HBM once
+ * per pass instead of once per step.  It applies to one vector per row on a
+ * single-sample lattice in the compact width-3 form whose every bond joins
+ * rows at most one column and one chain apart (chains of at least 68 rows, at
+ * least 4 chains); other calls take single steps.  Two steps run in tiles of
+ * 16 chains x 64 columns staged in LDS (tiled = 0) or, where the slots follow
+ * the order of kpm_build_graphene (and there are at least 16 chains), in
+ * register tiles of one wavefront each, 8 chains (tiled = 1) or 4 (tiled >=
+ * 2) by 64 - 2 steps columns; 3 and 4 steps need the register tiles (else 2
+ * steps apply).  Under steps > 1 any single steps keep row order.  Default
+ * for one vector: groups_per_cu 4, steps 4, tiled 2; for more vectors single
+ * steps.  At a fixed grid size, traversal and step count the moments
+ * are bit-identical for every ilp, streaming and compact choice; the
+ * recursion states are bit-identical for every shape, and the shape changes
+ * only the order of the inner-product partial sums.
  */
 typedef struct {
     int32_t groups_per_cu;
@@ -442,6 +456,7 @@ typedef struct {
     int32_t streaming;
     int32_t compact;
     int32_t tiled;
+    int32_t steps;
 } kpm_launch;
 
 kpm_status kpm_set_launch(kpm_system *sys, int n_vec, const kpm_launch *launch);
@@ -450,7 +465,11 @@ kpm_status kpm_get_launch(kpm_system *sys, int n_vec, kpm_launch *out);
 /*
  * Autotuner: times `reps` moment steps of every candidate shape
  * (groups_per_cu in {4, 8, 16} x ilp in {1, 2, 4} x streaming in {0, 1} x
- * compact in {0, 1} when the system has the compact form) on the device state
+ * compact in {0, 1} when the system has the compact form x tiled in {0, 1}
+ * for lattices with long chains; plus, where the multi-step sweeps apply,
+ * steps = 2 in LDS tiles with groups_per_cu in {2, 3, 4, 6} x streaming in
+ * {0, 1}, and steps in {2, 3, 4} in register tiles (tiled in {1, 2}) with
+ * groups_per_cu in {1, 2, 3, 4, 6, 8}) on the device state
  * `phi` ([n_sites][n_vec], read only; only system scratch is written), keeps
  * the fastest for this n_vec and returns it in *best (may be NULL).
  * Synchronises the stream.
@@ -483,7 +502,11 @@ typedef struct {
     int64_t site_updates;     /* all recursion site-updates issued          */
     int64_t step_bytes;       /* algorithmic bytes per moment-step launch:
                                  4 state accesses per row and vector plus
-                                 the row structure once per row (last run) */
+                                 the row structure once per row (last run;
+                                 5 accesses per row for a multi-step launch,
+                                 4 in the doubling form)                     */
+    int64_t step_bytes_total; /* algorithmic bytes of all launches in the
+                                 timed moment-step runs                     */
 } kpm_stats;
 
 kpm_status kpm_set_timing(kpm_system *sys, int enable);

@@ -82,7 +82,8 @@ struct DeviceGuard {
 bool valid_launch(const kpm_launch &l) {
     return l.groups_per_cu >= 1 && l.groups_per_cu <= 32 &&
            (l.ilp == 1 || l.ilp == 2 || l.ilp == 4) && (l.streaming == 0 || l.streaming == 1) &&
-           (l.compact == 0 || l.compact == 1) && l.tiled >= 0 && l.tiled <= 3;
+           (l.compact == 0 || l.compact == 1) && l.tiled >= 0 && l.tiled <= 3 &&
+           l.steps >= 1 && l.steps <= 4;
 }
 
 // Tile width (rows) of the tiled traversal for 2^vshift vectors per row: a
@@ -90,7 +91,8 @@ bool valid_launch(const kpm_launch &l) {
 int tile_rows(int vshift) { return std::max(64, kpm::kBlock >> vshift); }
 
 // Chain length of a lattice sample: the most common neighbour offset beyond 1
-// when it divides the rows and spans at least two tiles; 0 otherwise.
+// when it divides the rows into at least two chains of at least 68 rows; 0
+// otherwise.
 int32_t chain_length(const std::vector<int32_t> &nbr, int w, int64_t n) {
     std::vector<std::pair<int64_t, int64_t>> counts;    // (offset, count), few distinct
     for (int64_t r = 0; r < n; ++r)
@@ -117,8 +119,63 @@ int32_t chain_length(const std::vector<int32_t> &nbr, int w, int64_t n) {
             best = c.first;
             cnt = c.second;
         }
-    if (best < 2 * 64 || best >= ((int64_t)1 << 30) || n % best != 0 || n / best < 2) return 0;
+    if (best < kpm::kTileCols + 4 || best >= ((int64_t)1 << 30) || n % best != 0 || n / best < 2)
+        return 0;
     return (int32_t)best;
+}
+
+// (chain, column) step codes of the two-step sweep (see kpm::Lat2) for a
+// one-sample system with nx-row chains: for every row, the chain and column
+// distance to each neighbour, -1, 0 or 1 under periodic wrap, must be the same
+// for every row of its pattern.  False when some row breaks this.
+bool lattice_codes(const std::vector<int32_t> &nbr, int w, int64_t n, int64_t nx,
+                   const std::vector<uint8_t> &pid, int npat, std::vector<uint32_t> &code) {
+    if (nx < kpm::kTileCols + 4 || n % nx != 0 || n / nx < 4 || w > 4) return false;
+    const int64_t ny = n / nx;
+    code.assign(npat, 0u);
+    std::vector<uint8_t> seen(npat, 0);
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t j = r / nx, i = r % nx;
+        uint32_t c = 0xFFFFFFFFu;
+        for (int k = 0; k < w; ++k) {
+            const int32_t m = nbr[(size_t)k * n + r];
+            if (m < 0) continue;
+            int64_t di = m % nx - i, dj = m / nx - j;
+            if (di == nx - 1) di = -1;
+            if (di == 1 - nx) di = 1;
+            if (dj == ny - 1) dj = -1;
+            if (dj == 1 - ny) dj = 1;
+            if (di < -1 || di > 1 || dj < -1 || dj > 1) return false;
+            const uint32_t b = (uint32_t)((dj + 1) * 3 + (di + 1));
+            c = (c & ~(0xFFu << (8 * k))) | (b << (8 * k));
+        }
+        const int p = pid[r];
+        if (!seen[p]) {
+            seen[p] = 1;
+            code[p] = c;
+        } else if (code[p] != c) {
+            return false;
+        }
+    }
+    return true;
+}
+
+// Slot flags of the register-tiled two-step sweep from the lattice codes:
+// slot 0 the previous column, slot 1 the next, slot 2 the previous or next
+// chain, each possibly empty, and no fourth slot.  False otherwise.
+bool graphene_flags(const std::vector<uint32_t> &code, std::vector<uint32_t> &flags) {
+    flags.assign(code.size(), 0u);
+    for (size_t p = 0; p < code.size(); ++p) {
+        const uint32_t b0 = code[p] & 0xFFu, b1 = (code[p] >> 8) & 0xFFu,
+                       b2 = (code[p] >> 16) & 0xFFu, b3 = code[p] >> 24;
+        // byte = (dj + 1) * 3 + (di + 1): 3 = (0, -1), 5 = (0, +1), 7 = (+1, 0), 1 = (-1, 0)
+        if ((b0 != 0xFFu && b0 != 3u) || (b1 != 0xFFu && b1 != 5u) ||
+            (b2 != 0xFFu && b2 != 7u && b2 != 1u) || b3 != 0xFFu)
+            return false;
+        flags[p] = (b0 != 0xFFu ? 1u : 0u) | (b1 != 0xFFu ? 2u : 0u) | (b2 != 0xFFu ? 4u : 0u) |
+                   (b2 == 7u ? 8u : 0u);
+    }
+    return true;
 }
 
 // Launch shape used until kpm_autotune or kpm_set_launch picks another.
@@ -135,6 +192,14 @@ kpm_launch default_launch(int vshift, kpm_precision prec) {
     // with 8+ vectors per row a row's vertical neighbour lies megabytes ahead in
     // row order, beyond an XCD's L2
     l.tiled = vshift >= 3 ? 1 : 0;
+    l.steps = 1;
+    // one vector: four recursion steps per pass in register tiles of 4 chains
+    // where the sample allows (measured fastest on paper-scale sheets);
+    // elsewhere single steps in row order
+    if (vshift == 0) {
+        l.tiled = 2;
+        l.steps = 4;
+    }
     return l;
 }
 
@@ -155,6 +220,13 @@ struct kpm_system {
     std::vector<double> es;
     std::vector<double> seg_t;   // uniform hopping / E_s of each sample
     std::vector<int32_t> chain;  // chain length of each sample (tiled traversal), 0 = none
+    // two-step sweep (kpm_launch.steps = 2): lattice codes of a one-sample
+    // chain lattice, or none; its two extra recursion states
+    int32_t l2nx = 0, l2ny = 0;
+    uint32_t *d_code = nullptr;
+    uint32_t *d_flags = nullptr;   // graphene slot flags (register tiles), or none
+    void *xbuf[2] = {nullptr, nullptr};
+    size_t xbuf_bytes = 0;
     // device Hamiltonian
     int32_t *d_nbr = nullptr;   // explicit neighbour list, or
     uint8_t *d_pid = nullptr;   // compact form: pattern id per row
@@ -199,13 +271,14 @@ struct kpm_system {
     hipStream_t cap = nullptr;
     struct GraphKey {
         const void *phil, *phir, *a, *b, *partial, *dmom;
-        int nm, vshift, groups, ilp, streaming, compact, tiled, dbl;
+        int nm, vshift, groups, ilp, streaming, compact, tiled, steps, dbl;
         int64_t stride_r, offset;
         bool operator==(const GraphKey &o) const {
             return phil == o.phil && phir == o.phir && a == o.a && b == o.b &&
                    partial == o.partial && dmom == o.dmom && nm == o.nm && vshift == o.vshift &&
                    groups == o.groups && ilp == o.ilp && streaming == o.streaming &&
-                   compact == o.compact && tiled == o.tiled && dbl == o.dbl &&
+                   compact == o.compact && tiled == o.tiled && steps == o.steps &&
+                   dbl == o.dbl &&
                    stride_r == o.stride_r &&
                    offset == o.offset;
         }
@@ -243,6 +316,25 @@ struct kpm_system {
         return h;
     }
 
+    // Recursion steps per pass of moment sets with 2^vshift vectors under
+    // launch shape l: l.steps where a multi-step sweep applies (one vector,
+    // chain lattice, compact form; 3 and 4 steps need the graphene slot order,
+    // else 2), 1 otherwise.
+    int multi_steps(int vshift, const kpm_launch &l) const {
+        if (!d_code || vshift != 0 || l.steps < 2 || !l.compact) return 1;
+        return d_flags ? l.steps : 2;
+    }
+
+    // Multi-step tiles: two steps in LDS tiles of 16 chains x kTileCols
+    // columns (tiled = 0, or no graphene slot order); register tiles of 8
+    // chains (tiled = 1, or tiled = 0 with 3 or 4 steps) or 4 (tiled >= 2).
+    kpm::Lat2 lat2(const kpm_launch &l, int k) const {
+        const bool reg = d_flags && (l.tiled >= 1 || k > 2);
+        const int tj = reg ? (l.tiled >= 2 ? 4 : 8) : 16;
+        return kpm::Lat2{l2nx, l2ny, k, reg ? 1 : 0, tj, (l2nx + kpm::kTileCols - 1) / kpm::kTileCols,
+                         (l2ny + tj - 1) / tj, d_code, d_flags};
+    }
+
     kpm::Ell ell() const {
         kpm::Ell h;
         h.nbr = d_nbr;
@@ -269,6 +361,14 @@ struct kpm_system {
         return n * ((acc * elem_bytes()) << vshift) + n * per_row;
     }
 
+    // Algorithmic bytes of one multi-step launch (one vector, compact form):
+    // read phi_n, phi_{n-1} (and phi_L), write the last two states, and the
+    // row structure once.
+    int64_t step2_bytes(bool dbl) const {
+        const int64_t acc = dbl ? 4 : 5;
+        return n * (acc * (int64_t)elem_bytes() + 1 + (d_onsf ? 4 : 8));
+    }
+
     // The sweep of the moment step (and every other kernel) for n_vec =
     // 2^vshift under launch shape l.  Batches give each sample a contiguous
     // run of work-groups (a multiple of 8) in proportion to its rows.
@@ -279,9 +379,12 @@ struct kpm_system {
         sw.ilp = l.ilp;
         sw.nt = l.streaming;
         const int64_t want = std::max<int64_t>(kpm::kXcds, ((int64_t)cus * l.groups_per_cu) / kpm::kXcds * kpm::kXcds);
-        const int tw = l.tiled > 0 ? tile_rows(vshift) << (l.tiled - 1) : tile_rows(vshift);
+        // the single-step traversal; under a multi-step shape, tiled selects
+        // the multi-step tiles and single steps keep row order
+        const int tiled = l.steps == 1 ? l.tiled : 0;
+        const int tw = tiled > 0 ? tile_rows(vshift) << (tiled - 1) : tile_rows(vshift);
         auto tiling = [&](int s, int32_t *tnx) {
-            *tnx = (l.tiled && chain[s] >= 2 * tw) ? chain[s] : 0;
+            *tnx = (tiled && chain[s] >= 2 * tw) ? chain[s] : 0;
         };
         // multiply-shift constants for t / nch (nch = rows / tnx chains)
         auto divider = [&](int s, int32_t tnx, kpm::Seg &g) {
@@ -311,7 +414,7 @@ struct kpm_system {
             return KPM_OK;
         }
         for (const SegTab &t : segtabs) {
-            if (t.vshift == vshift && t.groups == l.groups_per_cu && t.tiled == l.tiled) {
+            if (t.vshift == vshift && t.groups == l.groups_per_cu && t.tiled == tiled) {
                 sw.nwg = t.nwg;
                 sw.nseg = nseg;
                 sw.seg = t.seg;
@@ -339,7 +442,7 @@ struct kpm_system {
         std::vector<int32_t> wg(g0);
         for (int s = 0; s < nseg; ++s)
             for (int g = 0; g < seg[s].nwg; ++g) wg[seg[s].g0 + g] = s;
-        SegTab t{vshift, l.groups_per_cu, l.tiled, (int)g0, nullptr, nullptr};
+        SegTab t{vshift, l.groups_per_cu, tiled, (int)g0, nullptr, nullptr};
         KPM_HIP(hipMalloc(&t.seg, seg.size() * sizeof(kpm::Seg)));
         KPM_HIP(hipMalloc(&t.wg, wg.size() * sizeof(int32_t)));
         KPM_HIP(hipMemcpy(t.seg, seg.data(), seg.size() * sizeof(kpm::Seg), hipMemcpyHostToDevice));
@@ -384,8 +487,9 @@ struct kpm_system {
     // Scratch limit (KPM_SCRATCH_LIMIT_MB at creation; 0 = none): the recursion
     // buffers, partials and moments together may not exceed it.
     size_t scratch_limit = 0;
-    kpm_status check_scratch(size_t nvec, size_t vbytes, size_t pelems, size_t delems) const {
-        const size_t total = nvec * vbytes + (pelems + delems) * sizeof(double2);
+    kpm_status check_scratch(size_t nvec, size_t vbytes, size_t pelems, size_t delems,
+                             size_t xbytes) const {
+        const size_t total = nvec * vbytes + 2 * xbytes + (pelems + delems) * sizeof(double2);
         if (scratch_limit && total > scratch_limit)
             return fail(KPM_ERR_OOM, "scratch of %zu bytes exceeds the limit of %zu bytes", total,
                         scratch_limit);
@@ -396,7 +500,7 @@ struct kpm_system {
     kpm_status ensure_vecs(int count, int vshift) {
         const size_t bytes = state_bytes(vshift);
         KPM_TRY(check_scratch(std::max<size_t>(count, vecs.size()), std::max(bytes, vec_bytes),
-                              partial_elems, dmom_elems));
+                              partial_elems, dmom_elems, xbuf_bytes));
         if (bytes > vec_bytes) {
             drop_graphs();
             KPM_HIP(hipStreamSynchronize(stream));
@@ -413,10 +517,27 @@ struct kpm_system {
         return KPM_OK;
     }
 
+    // The two extra recursion states of the two-step sweep.
+    kpm_status ensure_xbuf(int vshift) {
+        const size_t bytes = state_bytes(vshift);
+        if (bytes <= xbuf_bytes) return KPM_OK;
+        KPM_TRY(check_scratch(vecs.size(), vec_bytes, partial_elems, dmom_elems, bytes));
+        drop_graphs();
+        KPM_HIP(hipStreamSynchronize(stream));
+        for (void *&p : xbuf) {
+            if (p) (void)hipFree(p);
+            p = nullptr;
+        }
+        xbuf_bytes = 0;
+        for (void *&p : xbuf) KPM_HIP(hipMalloc(&p, bytes));
+        xbuf_bytes = bytes;
+        return KPM_OK;
+    }
+
     kpm_status ensure_partial(int slots, int nwg, int n_vec) {
         const size_t need = (size_t)slots * nwg * n_vec;
         if (need > partial_elems) {
-            KPM_TRY(check_scratch(vecs.size(), vec_bytes, need, dmom_elems));
+            KPM_TRY(check_scratch(vecs.size(), vec_bytes, need, dmom_elems, xbuf_bytes));
             drop_graphs();
             KPM_HIP(hipStreamSynchronize(stream));
             if (partial) (void)hipFree(partial);
@@ -429,7 +550,7 @@ struct kpm_system {
 
     kpm_status ensure_dmom(size_t elems) {
         if (elems > dmom_elems) {
-            KPM_TRY(check_scratch(vecs.size(), vec_bytes, partial_elems, elems));
+            KPM_TRY(check_scratch(vecs.size(), vec_bytes, partial_elems, elems, xbuf_bytes));
             drop_graphs();
             KPM_HIP(hipStreamSynchronize(stream));
             if (dmom) (void)hipFree(dmom);
@@ -469,6 +590,10 @@ struct kpm_system {
         drop_graphs();
         if (cap) (void)hipStreamDestroy(cap);
         for (void *p : vecs) (void)hipFree(p);
+        for (void *p : xbuf)
+            if (p) (void)hipFree(p);
+        if (d_code) (void)hipFree(d_code);
+        if (d_flags) (void)hipFree(d_flags);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         for (SegTab &t : segtabs) {
             (void)hipFree(t.seg);
@@ -499,52 +624,103 @@ kpm::Coef step_coef(const std::vector<double2> &host, const double2 *tab, int np
 // (phi_L = phi_R) two per recursion step, rounded up to an even count.
 inline int moment_slots(int nm, bool dbl) { return dbl ? 2 * ((nm + 1) / 2) : nm; }
 
+// Launch plan of one moment set: partial slots [c0, c1) form one ring
+// segment (the first holds ring + 2 slots, C_0 and C_1 included, the others
+// ring), and inside a segment the recursion takes k-step launches while all k
+// steps fit and single steps otherwise.  visit(kind, m, c0) is called for
+// every recursion launch (kind 1 or k, first moment slot m) and
+// segment(c0, c1, m0) once a segment's launches are done.
+template <typename F, typename G>
+void moment_plan(int slots, int ring, bool dbl, int k, F visit, G segment) {
+    const int per_step = dbl ? 2 : 1;
+    for (int c0 = 0; c0 < slots;) {
+        const int c1 = std::min(slots, c0 == 0 ? ring + 2 : c0 + ring);
+        const int m0 = std::max(c0, 2);
+        for (int m = m0; m < c1;) {
+            const int kind = (k > 1 && m + k * per_step <= c1) ? k : 1;
+            visit(kind, m, c0);
+            m += kind * per_step;
+        }
+        segment(c0, c1, m0);
+        c0 = c1;
+    }
+}
+
 // Launches of one moment set (Alg. 5) on stream s: the first step, the
 // recursion steps and the ring reductions into sys->dmom.  `events` brackets
 // each uninterrupted run of recursion steps for kpm_set_timing.  In the
 // doubling form phil is phir, recursion step n fills slots 2n and 2n + 1, and
-// a final kernel turns the doubling sums into moments.
+// a final kernel turns the doubling sums into moments.  States rotate through
+// a_buf, b_buf (and the system's two extra states for two-step launches);
+// phir is only read.
 template <typename V>
 kpm_status enqueue_moments(kpm_system *sys, const kpm::Sweep &sw, int ring, hipStream_t s,
                            bool events, bool dbl, const V *phil, const V *phir, int nm,
                            V *a_buf, V *b_buf, int64_t stride_r, int64_t offset) {
-    const kpm::Ell h = sys->ell_for(sys->launch[sw.vshift]);
+    const kpm_launch &l = sys->launch[sw.vshift];
+    const kpm::Ell h = sys->ell_for(l);
+    const int k = sys->multi_steps(sw.vshift, l);
+    const kpm::Lat2 lat = sys->lat2(l, k);
+    V *pool[4] = {a_buf, b_buf, (V *)sys->xbuf[0], (V *)sys->xbuf[1]};
+    const int npool = k > 1 ? 4 : 2;
+    // a pool state that is none of x, y, z
+    auto free_state = [&](const V *x, const V *y, const V *z) -> V * {
+        for (int q = 0; q < npool; ++q)
+            if (pool[q] != x && pool[q] != y && pool[q] != z) return pool[q];
+        return nullptr;
+    };
     // C_0 and C_1 (phi_0 = phi_R, phi_1 = H~ phi_0)
     kpm::launch_moment_step<V>(h, sw, true, phir, nullptr, a_buf, phil, sys->partial, 0, s);
-    // phi_m = 2 H~ phi_{m-1} - phi_{m-2}, in place after the first step
+    // phi_m = 2 H~ phi_{m-1} - phi_{m-2}; a single step writes over phi_{m-2}
+    // (when it is scratch), a two-step launch into two other states
     const V *p0 = phir;
     V *p1 = a_buf;
-    bool first = true;
     const int slots = moment_slots(nm, dbl);
-    const int per_step = dbl ? 2 : 1;
-    for (int c0 = 0; c0 < slots; c0 += ring) {
-        const int c1 = std::min(slots, c0 + ring);
-        const int m0 = std::max(c0, 2);
-        if (m0 < c1) {
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (events) {
-                KPM_TRY(sys->event_pair(&e0, &e1));
-                KPM_HIP(hipEventRecord(e0, s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool open = false;
+    kpm_status st = KPM_OK;
+    moment_plan(
+        slots, ring, dbl, k,
+        [&](int kind, int m, int c0) {
+            if (st != KPM_OK) return;
+            if (events && !open) {
+                if ((st = sys->event_pair(&e0, &e1)) != KPM_OK) return;
+                if (hipEventRecord(e0, s) != hipSuccess) {
+                    st = fail(KPM_ERR_DEVICE, "event record");
+                    return;
+                }
+                open = true;
             }
-            for (int m = m0; m < c1; m += per_step) {
-                V *out = first ? b_buf : const_cast<V *>(p0);
-                if (dbl)
-                    kpm::launch_moment_step_doubled<V>(h, sw, p1, p0, out, sys->partial, m - c0, s);
-                else
-                    kpm::launch_moment_step<V>(h, sw, false, p1, p0, out, phil, sys->partial,
-                                               m - c0, s);
-                first = false;
-                p0 = p1;
-                p1 = out;
+            if (kind > 1) {
+                V *o1 = free_state(p0, p1, nullptr);
+                V *o2 = free_state(p0, p1, o1);
+                kpm::launch_moment_multi<V>(h, sw, lat, p1, p0, o1, o2, phil, sys->partial,
+                                            m - c0, dbl, s);
+                p0 = o1;
+                p1 = o2;
+                return;
             }
-            if (events) {
-                KPM_HIP(hipEventRecord(e1, s));
-                sys->stats.step_launches += (c1 - m0) / per_step;
+            bool scratch = false;
+            for (int q = 0; q < npool; ++q) scratch = scratch || pool[q] == p0;
+            V *out = scratch ? const_cast<V *>(p0) : free_state(p0, p1, nullptr);
+            if (dbl)
+                kpm::launch_moment_step_doubled<V>(h, sw, p1, p0, out, sys->partial, m - c0, s);
+            else
+                kpm::launch_moment_step<V>(h, sw, false, p1, p0, out, phil, sys->partial,
+                                           m - c0, s);
+            p0 = p1;
+            p1 = out;
+        },
+        [&](int c0, int c1, int) {
+            if (st != KPM_OK) return;
+            if (open) {
+                if (hipEventRecord(e1, s) != hipSuccess) st = fail(KPM_ERR_DEVICE, "event record");
+                open = false;
             }
-        }
-        kpm::launch_reduce(sys->partial, sw, std::min(c1, nm) - c0, sys->dmom, stride_r,
-                           offset + c0, s);
-    }
+            kpm::launch_reduce(sys->partial, sw, std::min(c1, nm) - c0, sys->dmom, stride_r,
+                               offset + c0, s);
+        });
+    KPM_TRY(st);
     if (dbl) kpm::launch_undouble(sys->dmom, sw.nseg << sw.vshift, stride_r, offset, nm, s);
     return KPM_OK;
 }
@@ -558,22 +734,34 @@ kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir
                        V *a_buf, V *b_buf, int64_t stride_r, int64_t offset, bool dbl = false) {
     kpm::Sweep sw;
     KPM_TRY(sys->sweep(vshift, &sw));
-    // Group partials live in a ring of kPartialRing moment slots that is
-    // reduced into sys->dmom whenever it fills, bounding its size at any N_m.
+    const kpm_launch &l = sys->launch[vshift];
+    const int k = sys->multi_steps(vshift, l);
+    if (k > 1) KPM_TRY(sys->ensure_xbuf(vshift));
+    // Group partials live in a ring of moment slots that is reduced into
+    // sys->dmom whenever it fills, bounding its size at any N_m; the ring is
+    // a multiple of the slots of one k-step launch.
     const int slots = moment_slots(nm, dbl);
-    const int ring = std::min(std::max(slots, 2), kPartialRing);
-    const int steps = dbl ? slots / 2 - 1 : std::max(nm - 2, 0);   // recursion launches
-    KPM_TRY(sys->ensure_partial(ring, sw.nwg, 1 << vshift));
+    const int per_launch = k * (dbl ? 2 : 1);
+    const int ring = std::min(std::max(slots, 2), kPartialRing - kPartialRing % per_launch);
+    KPM_TRY(sys->ensure_partial(ring + 2, sw.nwg, 1 << vshift));
+    int64_t n1 = 0, n2 = 0;
+    moment_plan(slots, ring, dbl, k, [&](int kind, int, int) { (kind > 1 ? n2 : n1) += 1; },
+                [](int, int, int) {});
+    const int64_t b1 = sys->step_bytes(vshift, dbl), b2 = sys->step2_bytes(dbl);
+    const int steps = dbl ? slots / 2 - 1 : std::max(nm - 2, 0);   // recursion steps
     sys->stats.step_rows = sw.total;
-    sys->stats.step_bytes = sys->step_bytes(vshift, dbl);
+    sys->stats.step_bytes = n2 > 0 ? b2 : b1;
     sys->stats.site_updates += (int64_t)(steps + 1) * sw.total;
+    if (sys->timing) {
+        sys->stats.step_launches += n1 + n2;
+        sys->stats.step_bytes_total += n1 * b1 + n2 * b2;
+    }
     if (!sys->graphs)
         return enqueue_moments<V>(sys, sw, ring, sys->stream, sys->timing, dbl, phil, phir, nm,
                                   a_buf, b_buf, stride_r, offset);
     kpm_system::GraphKey key{phil, phir, a_buf, b_buf, sys->partial, sys->dmom, nm, vshift,
-                             sys->launch[vshift].groups_per_cu, sys->launch[vshift].ilp,
-                             sys->launch[vshift].streaming, sys->launch[vshift].compact,
-                             sys->launch[vshift].tiled, dbl ? 1 : 0, stride_r, offset};
+                             l.groups_per_cu, l.ilp, l.streaming, l.compact, l.tiled, l.steps,
+                             dbl ? 1 : 0, stride_r, offset};
     hipGraphExec_t exec = sys->find_graph(key);
     if (!exec) {
         KPM_TRY(sys->ensure_capture_stream());
@@ -598,10 +786,7 @@ kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir
         KPM_HIP(hipEventRecord(e0, sys->stream));
     }
     KPM_HIP(hipGraphLaunch(exec, sys->stream));
-    if (sys->timing) {
-        KPM_HIP(hipEventRecord(e1, sys->stream));
-        sys->stats.step_launches += steps;
-    }
+    if (sys->timing) KPM_HIP(hipEventRecord(e1, sys->stream));
     return KPM_OK;
 }
 
@@ -904,14 +1089,25 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
         const kpm::Ell h = sys->ell_for(l);
         kpm::Sweep sw;
         KPM_TRY(sys->sweep_with(vs, l, &sw));
-        KPM_TRY(sys->ensure_partial(1, sw.nwg, 1 << vs));
+        const int ks = sys->multi_steps(vs, l);
+        if (ks > 1) KPM_TRY(sys->ensure_xbuf(vs));
+        KPM_TRY(sys->ensure_partial(ks, sw.nwg, 1 << vs));
+        const kpm::Lat2 lat = sys->lat2(l, ks);
         float best = 1e30f;
         for (int round = 0; round < 3; ++round) {
             KPM_HIP(hipMemcpyAsync(a, phi, bytes, hipMemcpyDeviceToDevice, s));
             KPM_HIP(hipMemcpyAsync(b, phi, bytes, hipMemcpyDeviceToDevice, s));
-            V *p0 = b, *p1 = a;
+            V *p0 = b, *p1 = a, *o1 = (V *)sys->xbuf[0], *o2 = (V *)sys->xbuf[1];
             KPM_HIP(hipEventRecord(e0, s));
             for (int k = 0; k < reps; ++k) {
+                if (ks > 1 && k + ks <= reps) {
+                    kpm::launch_moment_multi<V>(h, sw, lat, p1, p0, o1, o2, phi, sys->partial, 0,
+                                                false, s);
+                    std::swap(p0, o1);
+                    std::swap(p1, o2);
+                    k += ks - 1;
+                    continue;
+                }
                 kpm::launch_moment_step<V>(h, sw, false, p1, p0, p0, phi, sys->partial, 0, s);
                 std::swap(p0, p1);
             }
@@ -937,6 +1133,7 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
             l.streaming = (q / 3) % 2;
             l.compact = forms == 2 ? (q / 6) % 2 : 0;
             l.tiled = tilings == 2 ? q / (6 * forms) : 0;
+            l.steps = 1;
             float ms = 0;
             if ((st = time_shape(l, &ms)) != KPM_OK) break;
             if (ms < 0.98f * best_ms) {
@@ -945,6 +1142,28 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
             }
         }
         if (st != KPM_OK) break;
+    }
+    // several recursion steps per pass (chain lattices, one vector): two
+    // steps in LDS tiles, and 2, 3 or 4 steps in register tiles of 8 or 4
+    // chains where the slots follow the graphene order
+    std::vector<kpm_launch> multi;
+    if (sys->d_code && vs == 0) {
+        for (int g : {2, 3, 4, 6})
+            for (int nt : {0, 1}) multi.push_back(kpm_launch{g, 1, nt, 1, 0, 2});
+        if (sys->d_flags)
+            for (int ksteps : {2, 3, 4})
+                for (int tiled : {1, 2})
+                    for (int g : {1, 2, 3, 4, 6, 8})
+                        multi.push_back(kpm_launch{g, 1, 0, 1, tiled, ksteps});
+    }
+    for (const kpm_launch &l : multi) {
+        if (st != KPM_OK) break;
+        float ms = 0;
+        if ((st = time_shape(l, &ms)) != KPM_OK) break;
+        if (ms < 0.98f * best_ms) {
+            best_ms = ms;
+            pick = l;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1000,6 +1219,8 @@ kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int devi
         for (auto &l : sys->launch) l.compact = atoi(env) != 0;
     if (const char *env = std::getenv("KPM_TILED"))
         for (auto &l : sys->launch) l.tiled = std::max(0, std::min(3, atoi(env)));
+    if (const char *env = std::getenv("KPM_STEPS"))
+        for (auto &l : sys->launch) l.steps = std::max(1, std::min(4, atoi(env)));
     if (const char *env = std::getenv("KPM_SCRATCH_LIMIT_MB"))
         sys->scratch_limit = (size_t)(std::max(0.0, atof(env)) * 1048576.0);
     sys->chain.resize(nseg);
@@ -1064,6 +1285,11 @@ kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int devi
             sys->npat = (int)pats.size();
         }
     }
+    // Chain-lattice codes of the two-step sweep (one sample, compact width-3
+    // form with uniform hopping).
+    std::vector<uint32_t> code;
+    const bool lat2 = nseg == 1 && !pid.empty() && w == 3 && !any_hop && sys->chain[0] > 0 &&
+                      lattice_codes(nbr, w, n, sys->chain[0], pid, sys->npat, code);
     if (!ons_float) {
         for (int s = 0; s < nseg; ++s)
             for (int64_t r = sys->off[s]; r < sys->off[s + 1]; ++r) ons[r] /= parts[s].e_scale;
@@ -1086,6 +1312,14 @@ kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int devi
     if (st == KPM_OK && !pid.empty()) {
         st = upload((void **)&sys->d_pid, pid.data(), pid.size());
         if (st == KPM_OK) st = upload((void **)&sys->d_pat, pat.data(), pat.size() * sizeof(int32_t));
+    }
+    if (st == KPM_OK && lat2) {
+        st = upload((void **)&sys->d_code, code.data(), code.size() * sizeof(uint32_t));
+        sys->l2nx = sys->chain[0];
+        sys->l2ny = (int32_t)(n / sys->chain[0]);
+        std::vector<uint32_t> flags;
+        if (st == KPM_OK && sys->l2ny >= 16 && graphene_flags(code, flags))
+            st = upload((void **)&sys->d_flags, flags.data(), flags.size() * sizeof(uint32_t));
     }
     if (st == KPM_OK && ons_float) {
         std::vector<float> of(ons.begin(), ons.end());

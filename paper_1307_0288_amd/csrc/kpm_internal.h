@@ -75,6 +75,25 @@ struct Sweep {
     Seg one;              // the segment when seg is nullptr
 };
 
+// Chain-lattice geometry of a one-sample system for the multi-step moment
+// sweeps: row j * nx + i is column i of chain j, and slot k of every row with
+// pattern p holds the row dj chains and di columns away (each -1, 0 or 1,
+// periodic wrap), code[p] byte k = (dj + 1) * 3 + (di + 1), or 0xFF for an
+// empty slot.  k recursion steps per pass (2, 3 or 4).  reg = 0: the LDS form
+// (k = 2; tiles of tj = 16 chains x kTileCols columns, nti x ntj of them).
+// reg = 1: the register-tiled form (tiles of tj = 4 or 8 chains x (64 - 2k)
+// columns per wavefront) for samples whose slots follow the graphene
+// builder's order: flags[p] bit k = slot k filled, bit 3 = slot 2 joins the
+// next chain.
+constexpr int kTileCols = 64;
+struct Lat2 {
+    int32_t nx, ny;
+    int32_t k, reg, tj;
+    int32_t nti, ntj;
+    const uint32_t *code;    // [npat]
+    const uint32_t *flags;   // [npat], or nullptr
+};
+
 // Coefficient of a step: the value for segment s is tab[s * stride + idx]
 // when tab is set, else val.
 struct Coef {
@@ -104,6 +123,18 @@ void launch_moment_step(const Ell &h, const Sweep &sw, bool first, const V *p1,
 template <typename V>
 void launch_moment_step_doubled(const Ell &h, const Sweep &sw, const V *p1, const V *p0,
                                 V *out, double2 *partial, int slot, hipStream_t s);
+
+// lat.k recursion steps per pass on a chain lattice (one vector per row,
+// width-3 compact form, one sample): from p1 = phi_n and p0 = phi_{n-1},
+// out1 = phi_{n+k-1} and out2 = phi_{n+k}; out1 and out2 must not alias p1,
+// p0 or each other.  Non-doubling: partial[slot + s - 1] = <L|phi_{n+s}>,
+// s = 1 .. k; doubling (phil unused): partial[slot + 2 (s - 1)] =
+// <phi_{n+s-1}|phi_{n+s-1}> and partial[slot + 2 (s - 1) + 1] =
+// <phi_{n+s-1}|phi_{n+s}>.
+template <typename V>
+void launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V *p1,
+                         const V *p0, V *out1, V *out2, const V *phil, double2 *partial,
+                         int slot, bool dbl, hipStream_t s);
 
 // mom[t * stride + offset + j] = 2 mom[...j] - mom[...j % 2] for 2 <= j < nm,
 // t < rows: moments from the doubling sums.

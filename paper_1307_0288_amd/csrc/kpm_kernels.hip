@@ -700,6 +700,353 @@ __global__ __launch_bounds__(kBlock) void k_kpm_sum(const double *__restrict__ m
     out[id] = pref[k] * s;
 }
 
+// ---------------------------------------------------------------- multi-step sweeps
+// Two recursion steps of the moments per pass over a chain lattice (one
+// vector per row, width-3 compact form): from phi_n (p1) and phi_{n-1} (p0)
+// it writes phi_{n+1} (out1) and phi_{n+2} (out2), so each row's operands
+// cross HBM once per two steps instead of once per step.
+//
+// A work-group takes a tile of TJ chains x kTileCols columns.  It
+// stages phi_n on the tile widened by two columns and two chains in LDS
+// (s0w), computes phi_{n+1} on the tile widened by one (s1w; the ring around
+// the tile is recomputed by the neighbouring tiles too), writes the tile's
+// phi_{n+1}, and then phi_{n+2} of the tile from s1w.  Neighbours are found
+// in LDS from each pattern's (chain, column) steps in lat.code, which the host
+// has checked against every row.  Periodic wrap is by index, so any tile of
+// any sample size reads in bounds.  Every element goes through the same
+// floating-point operations as k_moment_step (phi_{n+1} stored in s1w is the
+// value a store into V holds), so the states are the single-step states;
+// only the grouping of the inner-product partial sums differs.
+//
+// Inputs are never written: out1 and out2 must differ from p1, p0 and each
+// other (a neighbouring tile may still read p0 and p1 at this tile's rows).
+// Non-DBL: partial[slot] = <L|phi_{n+1}>, partial[slot+1] = <L|phi_{n+2}>.
+// DBL (phi_L = phi_R): slots slot .. slot+3 get <phi_n|phi_n>,
+// <phi_n|phi_{n+1}>, <phi_{n+1}|phi_{n+1}>, <phi_{n+1}|phi_{n+2}>.
+__device__ __forceinline__ int wrap_index(int x, int n) {
+    return x < 0 ? x + n : (x >= n ? x - n : x);
+}
+
+// Row offset in a window of row width WW for slot code c (0xFF = empty: 0).
+template <int WW>
+__device__ __forceinline__ int code_offset(uint32_t c) {
+    const int dj = (int)((c * 11u) >> 5) - 1;    // c / 3 - 1 for c < 9
+    const int di = (int)c - 3 * (dj + 1) - 1;
+    return c == 0xFFu ? 0 : dj * WW + di;
+}
+
+template <typename V, bool NT, bool ONSF, bool DBL, int TJ>
+__global__ __launch_bounds__(kBlock) void k_moment_step2(Ell h, Sweep sw, Lat2 lat,
+                                                         const V *p1, const V *p0,
+                                                         V *__restrict__ out1,
+                                                         V *__restrict__ out2,
+                                                         const V *__restrict__ phil,
+                                                         double2 *__restrict__ partial,
+                                                         int slot) {
+    constexpr int TI = kTileCols;
+    constexpr int W0 = TI + 4, W1 = TI + 2;           // row widths of the two windows
+    constexpr int N0 = (TJ + 4) * W0, N1 = (TJ + 2) * W1;
+    constexpr int L0 = (N0 + kBlock - 1) / kBlock;     // window loads per thread
+    constexpr int NI = TJ * TI / kBlock;               // tile elements per thread
+    static_assert(TJ * TI % kBlock == 0 && 2 * W1 + 2 * TJ <= kBlock, "tile shape");
+    __shared__ double2 s0w[N0];
+    __shared__ double2 s1w[N1];
+    __shared__ uint32_t lcode[kMaxPatterns];
+    for (int j = threadIdx.x; j < h.npat; j += kBlock) lcode[j] = lat.code[j];
+    __syncthreads();
+    const int tid = threadIdx.x;
+    const int nx = lat.nx, ny = lat.ny;
+    const double t = sw.one.t, inv_es = sw.one.inv_es;
+    const int lb = blockIdx.x;
+    const int loc = lb / kXcds, nloc = sw.nwg / kXcds;
+    const int ntile = lat.nti * lat.ntj;
+    const int per = (ntile + kXcds - 1) / kXcds;
+    const int b0 = (lb % kXcds) * per, b1 = min(b0 + per, ntile);
+    double2 a0 = make_double2(0.0, 0.0), a1 = a0, a2 = a0, a3 = a0;
+    for (int b = b0 + loc; b < b1; b += nloc) {
+        const int strip = b / lat.ntj;
+        const int i0 = strip * TI, j0 = (b - strip * lat.ntj) * TJ;
+        const int W = min(TI, nx - i0), H = min(TJ, ny - j0);
+        const int n0 = (H + 4) * W0;
+        // global loads of the whole tile first
+        double2 win[L0];
+#pragma unroll
+        for (int u = 0; u < L0; ++u) {
+            const int idx = tid + u * kBlock;
+            const int wj = idx / W0, wi = idx - (idx / W0) * W0;
+            const int gj = wrap_index(j0 - 2 + wj, ny), gi = wrap_index(i0 - 2 + wi, nx);
+            win[u] = idx < n0 ? ld(p1 + (int64_t)gj * nx + gi) : make_double2(0.0, 0.0);
+        }
+        int rI[NI], pI[NI];
+        bool okI[NI];
+        double oI[NI];
+        double2 qI[NI], lI[NI];
+#pragma unroll
+        for (int u = 0; u < NI; ++u) {
+            const int idx = tid + u * kBlock;
+            const int wi = idx % TI, wj = idx / TI;
+            okI[u] = wi < W && wj < H;
+            rI[u] = okI[u] ? (j0 + wj) * nx + i0 + wi : 0;     // row 0: a safe row
+            pI[u] = h.pid[rI[u]];
+            oI[u] = ONSF ? (double)h.onsf[rI[u]] * inv_es : h.ons[rI[u]];
+            qI[u] = ldx<NT>(p0 + rI[u]);
+            lI[u] = DBL ? make_double2(0.0, 0.0) : ldx<NT>(phil + rI[u]);
+        }
+        // the ring of window 1 around the tile: one element per thread
+        const int nh = 2 * (W + 2) + 2 * H;
+        int hj, hi;
+        if (tid < W + 2) {
+            hj = 0;
+            hi = tid;
+        } else if (tid < 2 * (W + 2)) {
+            hj = H + 1;
+            hi = tid - (W + 2);
+        } else {
+            const int k = tid - 2 * (W + 2);
+            hj = 1 + (k >> 1);
+            hi = (k & 1) ? W + 1 : 0;
+        }
+        const bool okH = tid < nh;
+        const int rH = okH ? wrap_index(j0 - 1 + hj, ny) * nx + wrap_index(i0 - 1 + hi, nx) : 0;
+        const int pH = h.pid[rH];
+        const double oH = ONSF ? (double)h.onsf[rH] * inv_es : h.ons[rH];
+        const double2 qH = ldx<NT>(p0 + rH);
+
+        __syncthreads();                 // the previous tile is done with s0w and s1w
+#pragma unroll
+        for (int u = 0; u < L0; ++u) {
+            const int idx = tid + u * kBlock;
+            if (idx < n0) s0w[idx] = win[u];
+        }
+        __syncthreads();
+        // Pattern codes are looked up only now: an LDS lookup that depends on a
+        // global load would wait for every load issued before it.
+        uint32_t cI[NI];
+#pragma unroll
+        for (int u = 0; u < NI; ++u) cI[u] = lcode[pI[u]];
+        const uint32_t cH = lcode[pH];
+        // phase 1: phi_{n+1} on the tile (kept for phase 2) and on the ring
+#pragma unroll
+        for (int u = 0; u < NI; ++u) {
+            const int idx = tid + u * kBlock;
+            const int wi = idx % TI, wj = idx / TI;
+            const int pos = (wj + 2) * W0 + wi + 2;
+            const double2 x = s0w[pos];
+            double2 acc = make_double2(oI[u] * x.x, oI[u] * x.y);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const uint32_t c = (cI[u] >> (8 * k)) & 0xFFu;
+                acc = raxpy(acc, c == 0xFFu ? 0.0 : t, s0w[pos + code_offset<W0>(c)]);
+            }
+            const double2 y = rounded<V>(two_minus(acc, qI[u]));
+            if (okI[u]) {
+                s1w[(wj + 1) * W1 + wi + 1] = y;
+                stx<NT>(out1 + rI[u], y);
+                if (DBL) {
+                    a0 = cdot_acc(a0, x, x);
+                    a1 = cdot_acc(a1, x, y);
+                } else {
+                    a0 = cdot_acc(a0, lI[u], y);
+                }
+            }
+        }
+        if (okH) {
+            const int pos = (hj + 1) * W0 + hi + 1;
+            const double2 x = s0w[pos];
+            double2 acc = make_double2(oH * x.x, oH * x.y);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const uint32_t c = (cH >> (8 * k)) & 0xFFu;
+                acc = raxpy(acc, c == 0xFFu ? 0.0 : t, s0w[pos + code_offset<W0>(c)]);
+            }
+            s1w[hj * W1 + hi] = rounded<V>(two_minus(acc, qH));
+        }
+        __syncthreads();
+        // phase 2: phi_{n+2} on the tile
+#pragma unroll
+        for (int u = 0; u < NI; ++u) {
+            if (!okI[u]) continue;
+            const int idx = tid + u * kBlock;
+            const int wi = idx % TI, wj = idx / TI;
+            const int pos = (wj + 1) * W1 + wi + 1;
+            const double2 x = s1w[pos];
+            double2 acc = make_double2(oI[u] * x.x, oI[u] * x.y);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const uint32_t c = (cI[u] >> (8 * k)) & 0xFFu;
+                acc = raxpy(acc, c == 0xFFu ? 0.0 : t, s1w[pos + code_offset<W1>(c)]);
+            }
+            const double2 z = rounded<V>(two_minus(acc, s0w[(wj + 2) * W0 + wi + 2]));
+            stx<NT>(out2 + rI[u], z);
+            if (DBL) {
+                a2 = cdot_acc(a2, x, x);
+                a3 = cdot_acc(a3, x, z);
+            } else {
+                a1 = cdot_acc(a1, lI[u], z);
+            }
+        }
+    }
+    const int nw = sw.nwg;
+    block_sum(a0, 0, partial + (int64_t)slot * nw + blockIdx.x);
+    block_sum(a1, 0, partial + (int64_t)(slot + 1) * nw + blockIdx.x);
+    if (DBL) {
+        block_sum(a2, 0, partial + (int64_t)(slot + 2) * nw + blockIdx.x);
+        block_sum(a3, 0, partial + (int64_t)(slot + 3) * nw + blockIdx.x);
+    }
+}
+
+// Register-tiled sweep of K = 2, 3 or 4 recursion steps per pass, for
+// lattices whose slots are ordered like the graphene builder's (slot 0 the
+// previous column, slot 1 the next column, slot 2 the previous or next chain,
+// each possibly empty; lat.flags[p] bit k = slot k filled, bit 3 = slot 2 is
+// the next chain).  A wavefront takes a tile of TJ chains x (kWave - 2K)
+// columns on its own: lane l holds column c0 - K + l of every row, so a row's
+// vertical neighbours sit in the lane's own registers and its horizontal ones
+// in lanes l -+ 1 (cross-lane moves).  phi_n is loaded on TJ + 2K chains and
+// step s computes phi_{n+s} on TJ + 2 (K - s) of them, valid in lanes
+// s .. kWave - 1 - s, so after K steps the tile (lanes K .. kWave - 1 - K)
+// holds phi_{n+K}.  Only phi_{n+K-1} (out1) and phi_{n+K} (out2) are written,
+// the two states the next pass starts from: per row, phi_n, phi_{n-1}, phi_L
+// and the structure are read and two states written once per K steps.  No
+// LDS tile and no barrier: every load of a tile is issued before its
+// arithmetic.  Each state value goes through the operations of
+// k_moment_step, in its slot order.
+// Partials: non-DBL slot + s - 1 = <L|phi_{n+s}>, s = 1 .. K; DBL slots
+// slot + 2 (s - 1) and + 1 = <phi_{n+s-1}|phi_{n+s-1}>, <phi_{n+s-1}|phi_{n+s}>.
+__device__ __forceinline__ double2 lane_prev(double2 v) {     // value of lane l - 1
+    return make_double2(__shfl_up(v.x, 1, kWave), __shfl_up(v.y, 1, kWave));
+}
+__device__ __forceinline__ double2 lane_next(double2 v) {     // value of lane l + 1
+    return make_double2(__shfl_down(v.x, 1, kWave), __shfl_down(v.y, 1, kWave));
+}
+
+// 2 H~ x - q at a row with flags f: own value x, horizontal neighbours from
+// the adjacent lanes, vertical from xup (next chain) or xdn (previous chain).
+__device__ __forceinline__ double2 reg_row_step(double o, double t, uint32_t f, double2 x,
+                                                double2 xup, double2 xdn, double2 q) {
+    const double2 xl = lane_prev(x), xr = lane_next(x);
+    const double2 xv = (f & 8u) ? xup : xdn;
+    double2 acc = make_double2(o * x.x, o * x.y);
+    acc = raxpy(acc, (f & 1u) ? t : 0.0, xl);
+    acc = raxpy(acc, (f & 2u) ? t : 0.0, xr);
+    acc = raxpy(acc, (f & 4u) ? t : 0.0, xv);
+    return two_minus(acc, q);
+}
+
+// Element at a byte offset from a wave-uniform row base.
+template <typename T>
+__device__ __forceinline__ T *row_at(T *base, uint32_t byte_off) {
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ const T *row_at(const T *base, uint32_t byte_off) {
+    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
+template <typename V, bool ONSF, bool DBL, int TJ, int K>
+__global__ __launch_bounds__(kBlock) void k_moment_stepk(Ell h, Sweep sw, Lat2 lat,
+                                                         const V *p1, const V *p0,
+                                                         V *__restrict__ out1,
+                                                         V *__restrict__ out2,
+                                                         const V *__restrict__ phil,
+                                                         double2 *__restrict__ partial,
+                                                         int slot) {
+    constexpr int TC = kWave - 2 * K;                  // columns per tile
+    constexpr int R0 = TJ + 2 * K;                     // window: chains j0 - K .. j0 + TJ + K - 1
+    constexpr int NA = DBL ? 2 * K : K;                // partial sums
+    __shared__ uint32_t lflag[kMaxPatterns];
+    for (int j = threadIdx.x; j < h.npat; j += kBlock) lflag[j] = lat.flags[j];
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1);
+    const int nx = lat.nx, ny = lat.ny;
+    const double t = sw.one.t, inv_es = sw.one.inv_es;
+    const int nst = (nx + TC - 1) / TC, nrb = (ny + TJ - 1) / TJ;
+    const int ntile = nst * nrb;
+    const int lb = blockIdx.x;
+    const int per = (ntile + kXcds - 1) / kXcds;
+    const int b0 = (lb % kXcds) * per, b1 = min(b0 + per, ntile);
+    constexpr int kWaves = kBlock / kWave;
+    // the wavefront's index as a scalar: tile coordinates and row bases are
+    // then scalar, and each load takes the lane's column as its offset
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int wloc = (lb / kXcds) * kWaves + wv;
+    const int wn = (sw.nwg / kXcds) * kWaves;
+    double2 acc[NA];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) acc[k] = make_double2(0.0, 0.0);
+    for (int b = b0 + wloc; b < b1; b += wn) {
+        const int strip = b / nrb;
+        const int j0 = (b - strip * nrb) * TJ, c0 = strip * TC;
+        const int gi = wrap_index(c0 - K + lane, nx);
+        const bool colok = lane >= K && lane < K + TC && c0 - K + lane < nx;
+        const int H = min(TJ, ny - j0);
+        const uint32_t ov = (uint32_t)gi * sizeof(V);
+        auto base = [&](int w) { return (int64_t)wrap_index(j0 - K + w, ny) * nx; };
+        // every load of the tile first, pattern ids leading (their flag
+        // lookups then wait for nothing else)
+        int pf[R0];
+#pragma unroll
+        for (int w = 1; w < R0 - 1; ++w) pf[w] = *row_at(h.pid + base(w), (uint32_t)gi);
+        double2 B[R0];                                  // phi_n
+#pragma unroll
+        for (int w = 0; w < R0; ++w) B[w] = ld(row_at(p1 + base(w), ov));
+        double2 A[R0];                                  // phi_{n-1}
+        float of[R0];
+        double od[R0];
+#pragma unroll
+        for (int w = 1; w < R0 - 1; ++w) {
+            A[w] = ld(row_at(p0 + base(w), ov));
+            if (ONSF)
+                of[w] = *row_at(h.onsf + base(w), (uint32_t)gi * 4u);
+            else
+                od[w] = *row_at(h.ons + base(w), (uint32_t)gi * 8u);
+        }
+        double2 L[TJ];
+#pragma unroll
+        for (int r = 0; r < TJ; ++r)
+            L[r] = DBL ? make_double2(0.0, 0.0) : ld(row_at(phil + base(K + r), ov));
+        uint32_t fl[R0];
+#pragma unroll
+        for (int w = 1; w < R0 - 1; ++w) fl[w] = lflag[pf[w]];
+#pragma unroll
+        for (int s = 1; s <= K; ++s) {
+            double2 C[R0];
+#pragma unroll
+            for (int w = s; w < R0 - s; ++w) {
+                const double o = ONSF ? (double)of[w] * inv_es : od[w];
+                C[w] = rounded<V>(reg_row_step(o, t, fl[w], B[w], B[w + 1], B[w - 1], A[w]));
+            }
+#pragma unroll
+            for (int r = 0; r < TJ; ++r) {
+                if (r < H && colok) {
+                    if (DBL) {
+                        acc[2 * (s - 1)] = cdot_acc(acc[2 * (s - 1)], B[K + r], B[K + r]);
+                        acc[2 * (s - 1) + 1] = cdot_acc(acc[2 * (s - 1) + 1], B[K + r], C[K + r]);
+                    } else {
+                        acc[s - 1] = cdot_acc(acc[s - 1], L[r], C[K + r]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int w = s; w < R0 - s; ++w) {
+                A[w] = B[w];
+                B[w] = C[w];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < TJ; ++r) {
+            if (r < H && colok) {
+                const int64_t rb = (int64_t)(j0 + r) * nx;
+                st(row_at(out1 + rb, ov), A[K + r]);
+                st(row_at(out2 + rb, ov), B[K + r]);
+            }
+        }
+    }
+    const int nw = sw.nwg;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) block_sum(acc[k], 0, partial + (int64_t)(slot + k) * nw + blockIdx.x);
+}
+
 // ---------------------------------------------------------------- launchers
 template <typename V, int ILP, bool NT, bool DBL>
 static void launch_step_shape(const Ell &h, const Sweep &sw, const V *p1, const V *p0, V *out,
@@ -835,6 +1182,44 @@ void launch_kpm_sum(const double *mom, int rows, int nm, const double *w, const 
                        pref, ne, out);
 }
 
+template <typename V>
+void launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V *p1,
+                         const V *p0, V *out1, V *out2, const V *phil, double2 *partial,
+                         int slot, bool dbl, hipStream_t s) {
+    const bool onsf = h.onsf != nullptr;
+#define KPM_LDS2(NT_, ONSF_, DBL_)                                                            \
+    hipLaunchKernelGGL((k_moment_step2<V, NT_, ONSF_, DBL_, 16>), dim3(sw.nwg), dim3(kBlock),  \
+                       0, s, h, sw, lat, p1, p0, out1, out2, phil, partial, slot)
+#define KPM_REGK(ONSF_, DBL_, TJ_, K_)                                                        \
+    hipLaunchKernelGGL((k_moment_stepk<V, ONSF_, DBL_, TJ_, K_>), dim3(sw.nwg), dim3(kBlock),  \
+                       0, s, h, sw, lat, p1, p0, out1, out2, phil, partial, slot)
+#define KPM_REG_K(ONSF_, DBL_, TJ_)                                                           \
+    do {                                                                                      \
+        if (lat.k == 4) KPM_REGK(ONSF_, DBL_, TJ_, 4);                                        \
+        else if (lat.k == 3) KPM_REGK(ONSF_, DBL_, TJ_, 3);                                   \
+        else KPM_REGK(ONSF_, DBL_, TJ_, 2);                                                   \
+    } while (0)
+#define KPM_REG(ONSF_, DBL_)                                                                  \
+    do {                                                                                      \
+        if (lat.tj == 4) KPM_REG_K(ONSF_, DBL_, 4);                                           \
+        else KPM_REG_K(ONSF_, DBL_, 8);                                                       \
+    } while (0)
+    if (lat.reg) {
+        if (onsf) { if (dbl) KPM_REG(true, true); else KPM_REG(true, false); }
+        else { if (dbl) KPM_REG(false, true); else KPM_REG(false, false); }
+    } else if (sw.nt) {
+        if (onsf) { if (dbl) KPM_LDS2(true, true, true); else KPM_LDS2(true, true, false); }
+        else { if (dbl) KPM_LDS2(true, false, true); else KPM_LDS2(true, false, false); }
+    } else {
+        if (onsf) { if (dbl) KPM_LDS2(false, true, true); else KPM_LDS2(false, true, false); }
+        else { if (dbl) KPM_LDS2(false, false, true); else KPM_LDS2(false, false, false); }
+    }
+#undef KPM_LDS2
+#undef KPM_REGK
+#undef KPM_REG_K
+#undef KPM_REG
+}
+
 #define KPM_INSTANTIATE(V)                                                                  \
     template void launch_moment_step<V>(const Ell &, const Sweep &, bool, const V *,        \
                                         const V *, V *, const V *, double2 *, int,          \
@@ -851,7 +1236,10 @@ void launch_kpm_sum(const double *mom, int rows, int nm, const double *w, const 
     template void launch_apply_d<V>(const Ell &, const Sweep &, const V *, V *, Coef,       \
                                     hipStream_t);                                           \
     template void launch_dot<V>(const Sweep &, const V *, const V *, double2 *, int,        \
-                                hipStream_t);
+                                hipStream_t);                                               \
+    template void launch_moment_multi<V>(const Ell &, const Sweep &, const Lat2 &, const V *, \
+                                         const V *, V *, V *, const V *, double2 *, int,    \
+                                         bool, hipStream_t);
 
 KPM_INSTANTIATE(double2)
 KPM_INSTANTIATE(float2)

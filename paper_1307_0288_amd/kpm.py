@@ -59,11 +59,11 @@ class _Desc(C.Structure):
 
 class Launch(C.Structure):
     _fields_ = [("groups_per_cu", C.c_int32), ("ilp", C.c_int32), ("streaming", C.c_int32),
-                ("compact", C.c_int32), ("tiled", C.c_int32)]
+                ("compact", C.c_int32), ("tiled", C.c_int32), ("steps", C.c_int32)]
 
     def as_dict(self) -> dict:
         return dict(groups_per_cu=self.groups_per_cu, ilp=self.ilp, streaming=self.streaming,
-                    compact=self.compact, tiled=self.tiled)
+                    compact=self.compact, tiled=self.tiled, steps=self.steps)
 
 
 class Adam(C.Structure):
@@ -73,7 +73,7 @@ class Adam(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("step_ms", C.c_double), ("step_launches", C.c_int64),
                 ("step_rows", C.c_int64), ("site_updates", C.c_int64),
-                ("step_bytes", C.c_int64)]
+                ("step_bytes", C.c_int64), ("step_bytes_total", C.c_int64)]
 
 
 _lib = None
@@ -577,11 +577,11 @@ def kpm_msd_continue(sys: System, psi, y, start: bool, n_steps: int, dt_fs: floa
 
 
 def kpm_set_launch(sys: System, n_vec: int, groups_per_cu: int, ilp: int, streaming: int = 0,
-                   compact: int = 1, tiled: int = 0):
+                   compact: int = 1, tiled: int = 0, steps: int = 1):
     """Launch shape of the moment step for n_vec vectors (see kpm_launch in kpm.h)."""
     _check(lib().kpm_set_launch(sys.handle, n_vec,
                                 C.byref(Launch(groups_per_cu, ilp, int(bool(streaming)),
-                                               int(bool(compact)), int(tiled)))))
+                                               int(bool(compact)), int(tiled), int(steps)))))
 
 
 def kpm_get_launch(sys: System, n_vec: int) -> dict:
@@ -612,7 +612,8 @@ def kpm_get_stats(sys: System) -> dict:
     s = Stats()
     _check(lib().kpm_get_stats(sys.handle, C.byref(s)))
     return dict(step_ms=s.step_ms, step_launches=s.step_launches, step_rows=s.step_rows,
-                site_updates=s.site_updates, step_bytes=s.step_bytes)
+                site_updates=s.site_updates, step_bytes=s.step_bytes,
+                step_bytes_total=s.step_bytes_total)
 
 
 def kpm_reset_stats(sys: System):

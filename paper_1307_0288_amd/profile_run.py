@@ -39,13 +39,40 @@ if ROOT not in sys.path:
 KERNEL_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "kpm_kernels.hip")
 
 
-def kernel_sha() -> str:
-    """Hash of the source the moment step is compiled from: the kernel file up to
-    the first kernel after it, plus its launchers (edits elsewhere in the file do
-    not change the moment step)."""
+def multi_step(launch: dict, n_vec: int = 1) -> bool:
+    """Whether moment sets take the multi-step sweeps under this launch shape
+    (one vector, compact form; the sample must be a chain lattice)."""
+    return launch.get("steps", 1) >= 2 and n_vec == 1 and bool(launch["compact"])
+
+
+def moment_kernel_name(v: str, launch: dict, dbl: bool, n_vec: int = 1) -> str:
+    """Instantiation of the moment step for a graphene system from the builder
+    (width 3, uniform hopping, float-exact on-site terms, at least 16 chains)
+    under a launch shape."""
+    nt, db = ("true" if launch["streaming"] else "false"), ("true" if dbl else "false")
+    if multi_step(launch, n_vec):
+        k, tiled = launch["steps"], launch["tiled"]
+        if k == 2 and tiled == 0:
+            return f"k_moment_step2<{v},{nt},true,{db},16>"
+        return f"k_moment_stepk<{v},true,{db},{4 if tiled >= 2 else 8},{k}>"
+    form = "kFormC3F" if launch["compact"] else "kFormL3F"
+    return f"k_moment_step<{v},{launch['ilp']},{nt},{form},{db}>"
+
+
+def kernel_sha(launch: dict | None = None) -> str:
+    """Hash of the source the moment step under `launch` is compiled from (the
+    single-step kernel by default): the kernel file up to the first kernel
+    after the moment step, plus the multi-step kernels for a multi-step shape,
+    plus the launchers (edits elsewhere in the file change neither)."""
     with open(KERNEL_SRC) as f:
         t = f.read()
     head = t[:t.index("// Loads and stores of the propagator kernels")]
+    if launch is not None and multi_step(launch):
+        a = t.index("// ---------------------------------------------------------------- multi-step sweeps")
+        b = t.index("// ---------------------------------------------------------------- launchers")
+        c = t.index("template <typename V>\nvoid launch_moment_multi(")
+        d = t.index("#define KPM_INSTANTIATE(V)")
+        return hashlib.sha256((head + t[a:b] + t[c:d]).encode()).hexdigest()[:16]
     a = t.index("template <typename V, int ILP, bool NT, bool DBL>\nstatic void launch_step_shape(")
     b = t.index("template <typename V>\nvoid launch_evolve_step(")
     return hashlib.sha256((head + t[a:b]).encode()).hexdigest()[:16]
@@ -60,8 +87,9 @@ def measured_traffic(path: str, step_rows: int, launch: dict):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != kernel_sha() or t.get("step_rows") != step_rows \
-            or t.get("launch_shape") != launch:
+    stored = dict({"steps": 1}, **t.get("launch_shape", {}))
+    if t.get("kernel_sha") != kernel_sha(launch) or t.get("step_rows") != step_rows \
+            or stored != dict({"steps": 1}, **launch):
         return None
     return t.get("bytes_per_launch")
 
@@ -202,7 +230,6 @@ def main():
     print(f"copies: {args.copies} x {args.copy_mib} MiB", flush=True)
     if args.meta:
         v = "double2" if args.precision == "fp64" else "float2"
-        form = "kFormC3F" if launch["compact"] else "kFormL3F"
         cmd = ["python3 -m paper_1307_0288_amd.profile_run", f"--moments {args.moments}",
                f"--n-vec {args.n_vec}", f"--precision {args.precision}",
                f"--copy-mib {args.copy_mib}"]
@@ -213,11 +240,9 @@ def main():
         if args.autotune:
             cmd.append(f"--autotune {args.autotune}")
         meta = {
-            "kernel": f"k_moment_step<{v},{launch['ilp']},"
-                      f"{'true' if launch['streaming'] else 'false'},{form},"
-                      f"{'true' if args.doubled else 'false'}> ({args.precision}, "
-                      f"{args.n_vec} vector(s))",
-            "kernel_sha": kernel_sha(),
+            "kernel": f"{moment_kernel_name(v, launch, args.doubled, args.n_vec)} "
+                      f"({args.precision}, {args.n_vec} vector(s))",
+            "kernel_sha": kernel_sha(launch),
             "step_rows": st["step_rows"],
             "step_bytes": st["step_bytes"],
             "launch_shape": launch,

@@ -1,0 +1,192 @@
+"""Several recursion steps per pass (kpm_launch.steps = 2, 3, 4) on chain lattices.
+
+The sizes leave ragged tiles in both directions (130 columns = 64 + 64 + 2,
+26 or 38 chains = 16 + 10 or 16 + 16 + 6), odd moment counts leave a final
+single step, and every geometry's boundary (periodic sheet, open-y ZGNR,
+open-x AGNR) goes through the periodic-wrap indexing of the tiles.  The
+recursion states are the single-step states exactly, so the moments agree
+with the single-step path to summation-order rounding and with the oracle
+to the parity bound."""
+import numpy as np
+import pytest
+
+import oracle
+from cases import gpu_system, oracle_lattice, phases, recipe, rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+kp = pytest.importorskip("paper_1307_0288_amd")
+
+SHAPES = [("sheet", 130, 26), ("zgnr", 130, 38), ("agnr", 132, 26), ("sheet", 200, 40)]
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _log(msg):
+    print(f"[two-step] {msg}", flush=True)
+
+
+def _pair(c, precision="fp64", tiled=0, steps=2):
+    """Systems on the same sample: single steps, and `steps` steps per pass in
+    LDS tiles of 16 chains (tiled = 0, two steps) or register tiles of 8
+    (tiled = 1) or 4 (tiled = 2) chains."""
+    one, two = gpu_system(c, precision), gpu_system(c, precision)
+    kp.kpm_set_launch(one, 1, 4, 1, 0, 1, 0, 1)
+    kp.kpm_set_launch(two, 1, 3, 1, 0, 1, tiled, steps)
+    return one, two
+
+
+MULTI = [(2, 0), (2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (4, 2)]
+
+
+@pytest.mark.parametrize("geometry,nx,ny", SHAPES)
+@pytest.mark.parametrize("nm", [101, 64])
+@pytest.mark.parametrize("steps,tiled", MULTI)
+def test_moments_match_oracle_and_single_step(geometry, nx, ny, nm, steps, tiled):
+    _need_gpu()
+    c = recipe(geometry, nx, ny, w=1.5, vac=0.02, seed=nx + ny)
+    _log(f"moments {geometry} {nx}x{ny} nm={nm} steps={steps} tiled={tiled}")
+    one, two = _pair(c, tiled=tiled, steps=steps)
+    phi = phases(c, 1, 4400)
+    d = one.upload(phi)
+    kp.kpm_set_timing(two, True)
+    kp.kpm_reset_stats(two)
+    m2 = kp.kpm_moments(two, d, d, nm)[0]
+    st = kp.kpm_get_stats(two)
+    m1 = kp.kpm_moments(one, d, d, nm)[0]
+    ref = oracle.moments(oracle_lattice(c), c["e_scale"], phi[:, 0], phi[:, 0], nm)
+    scale = np.vdot(phi, phi).real
+    assert rel_err(m2, ref, scale) < 1e-10
+    assert rel_err(m2, m1, scale) < 1e-13
+    n = nx * ny
+    # 5 state accesses of 16 B, pattern byte and float on-site term per row
+    assert st["step_bytes"] == n * (5 * 16 + 1 + 4)
+    n2 = (nm - 2) // steps
+    assert st["step_launches"] == n2 + (nm - 2) % steps
+    assert st["step_bytes_total"] == n2 * st["step_bytes"] + (nm - 2) % steps * n * (4 * 16 + 1 + 4)
+
+
+@pytest.mark.parametrize("geometry,nx,ny", SHAPES[:3])
+@pytest.mark.parametrize("steps,tiled", MULTI)
+def test_distinct_left_vector_and_doubling(geometry, nx, ny, steps, tiled):
+    _need_gpu()
+    c = recipe(geometry, nx, ny, w=0.8, vac=0.01, seed=7 * nx + ny)
+    _log(f"phi_L != phi_R and doubling {geometry} {nx}x{ny} steps={steps} tiled={tiled}")
+    one, two = _pair(c, tiled=tiled, steps=steps)
+    pl, pr = phases(c, 1, 4500), phases(c, 1, 4501)
+    lat = oracle_lattice(c)
+    got = kp.kpm_moments(two, two.upload(pl), two.upload(pr), 77)[0]
+    ref = oracle.moments(lat, c["e_scale"], pl[:, 0], pr[:, 0], 77)
+    assert rel_err(got, ref, np.sqrt(np.vdot(pl, pl).real * np.vdot(pr, pr).real)) < 1e-10
+    for nm in (100, 99, 103, 97):        # 2 steps x 2 slots per launch; 2-slot tails
+        dbl = kp.kpm_moments_doubled(two, two.upload(pr), nm)[0]
+        ref = oracle.moments(lat, c["e_scale"], pr[:, 0], pr[:, 0], nm)
+        assert rel_err(dbl, ref, np.vdot(pr, pr).real) < 1e-10, nm
+
+
+@pytest.mark.parametrize("steps,tiled", [(2, 0), (3, 1)])
+def test_double_onsite_form(steps, tiled):
+    """On-site energies that are not floats: the width-3 compact form with
+    double on-site terms."""
+    _need_gpu()
+    c = recipe("sheet", 130, 26, w=1.0, vac=0.02, seed=3)
+    c["onsite"] = c["onsite"] + 1e-9 * np.sin(np.arange(c["onsite"].size))
+    _log("double on-site sheet 130x26")
+    one, two = _pair(c, tiled=tiled, steps=steps)
+    phi = phases(c, 1, 4650)
+    d = one.upload(phi)
+    kp.kpm_reset_stats(two)
+    kp.kpm_set_timing(two, True)
+    m2 = kp.kpm_moments(two, d, d, 70)[0]
+    assert kp.kpm_get_stats(two)["step_bytes"] == 130 * 26 * (5 * 16 + 1 + 8)
+    m1 = kp.kpm_moments(one, d, d, 70)[0]
+    ref = oracle.moments(oracle_lattice(c), c["e_scale"], phi[:, 0], phi[:, 0], 70)
+    scale = np.vdot(phi, phi).real
+    assert rel_err(m2, ref, scale) < 1e-10 and rel_err(m2, m1, scale) < 1e-13
+
+
+@pytest.mark.parametrize("steps,tiled", [(2, 0), (4, 2)])
+def test_fp32_states_equal_single_step(steps, tiled):
+    _need_gpu()
+    c = recipe("sheet", 130, 26, w=1.0, vac=0.02, seed=5)
+    _log(f"fp32 states sheet 130x26 steps={steps}")
+    one, two = _pair(c, "fp32", tiled, steps)
+    phi = phases(c, 1, 4600)
+    d = one.upload(phi)
+    m1 = kp.kpm_moments(one, d, d, 90)[0]
+    m2 = kp.kpm_moments(two, d, d, 90)[0]
+    scale = np.vdot(phi, phi).real
+    assert rel_err(m2, m1, scale) < 1e-12
+    ref = oracle.moments(oracle_lattice(c), c["e_scale"], phi[:, 0], phi[:, 0], 90)
+    assert rel_err(m2, ref, scale) < 1e-4
+
+
+@pytest.mark.parametrize("kind", ["vac", "msd"])
+@pytest.mark.parametrize("steps,tiled", [(2, 0), (3, 2)])
+def test_time_loops_with_two_step_moments(kind, steps, tiled):
+    _need_gpu()
+    c = recipe("sheet", 130, 26, w=1.0, vac=0.02, seed=9)
+    _log(f"{kind} sheet 130x26 steps={steps}")
+    one, two = _pair(c, tiled=tiled, steps=steps)
+    phi = phases(c, 1, 4700)
+    fn = kp.kpm_vac if kind == "vac" else kp.kpm_msd
+    got = fn(two, two.upload(phi), 3, 0.5, 20, 61)
+    lat = oracle_lattice(c)
+    ofn = oracle.vac if kind == "vac" else oracle.msd
+    ref = ofn(lat, c["e_scale"], phi[:, 0], 3, 0.5, 20, 61)
+    assert got.shape == (1, 4, 61)
+    assert rel_err(got[0], ref) < 1e-10
+
+
+@pytest.mark.parametrize("steps,tiled", [(2, 0), (4, 1)])
+def test_graph_replays_match_eager(steps, tiled):
+    _need_gpu()
+    c = recipe("zgnr", 130, 38, w=1.0, vac=0.02, seed=11)
+    _log(f"graphs zgnr 130x38 steps={steps}")
+    _, two = _pair(c, tiled=tiled, steps=steps)
+    phi = phases(c, 1, 4800)
+    d = two.upload(phi)
+    eager = kp.kpm_moments(two, d, d, 151)[0]
+    kp.kpm_set_graphs(two, True)
+    for _ in range(3):
+        rep = kp.kpm_moments(two, d, d, 151)[0]
+        torch.cuda.synchronize()
+        assert np.array_equal(rep, eager)
+    kp.kpm_set_graphs(two, False)
+
+
+def test_not_applicable_falls_back_to_single_steps():
+    """Chains shorter than 68 rows and several vectors per row take single
+    steps under steps = 2, with the same results."""
+    _need_gpu()
+    c = recipe("sheet", 48, 20, w=1.0, vac=0.02, seed=13)
+    one, two = _pair(c)
+    kp.kpm_set_launch(two, 1, 4, 1, 0, 1, 0, 2)
+    phi = phases(c, 1, 4900)
+    d = one.upload(phi)
+    assert np.array_equal(kp.kpm_moments(one, d, d, 40), kp.kpm_moments(two, d, d, 40))
+    c = recipe("sheet", 130, 26, w=1.0, vac=0.02, seed=13)
+    one, two = _pair(c)
+    kp.kpm_set_launch(one, 2, 4, 1, 0, 1, 0, 1)
+    kp.kpm_set_launch(two, 2, 4, 1, 0, 1, 0, 2)
+    phi = phases(c, 2, 4901)
+    d = one.upload(phi)
+    assert np.array_equal(kp.kpm_moments(one, d, d, 40), kp.kpm_moments(two, d, d, 40))
+
+
+def test_autotune_considers_two_steps():
+    _need_gpu()
+    c = recipe("sheet", 512, 256, w=0.5, vac=0.005, seed=17)
+    _log("autotune sheet 512x256")
+    sysg = gpu_system(c)
+    phi = phases(c, 1, 5000)
+    d = sysg.upload(phi)
+    best = kp.kpm_autotune(sysg, d, 20)
+    assert best["steps"] in (1, 2, 3, 4)
+    got = kp.kpm_moments(sysg, d, d, 50)[0]
+    ref = oracle.moments(oracle_lattice(c), c["e_scale"], phi[:, 0], phi[:, 0], 50)
+    assert rel_err(got, ref, np.vdot(phi, phi).real) < 1e-10
