@@ -116,7 +116,8 @@ def _mean(vals):
 def summarize(fetch_dir: str, write_dir: str, meta_path: str, out_path: str):
     with open(meta_path) as f:
         meta = json.load(f)
-    step_prefix = "void kpm::k_moment_step<"
+    # dispatches of the kernel named in the meta (any instantiation of it)
+    step_prefix = "void kpm::" + meta["kernel"].split("<")[0] + "<"
     res = {}
     for key, d in (("fetch", fetch_dir), ("write", write_dir)):
         rows = _read_counter(d)
