@@ -441,9 +441,10 @@ kpm_status kpm_xu_state(kpm_system *sys, int n_vec, const void *phi, int n_steps
  * least 4 chains); other calls take single steps.  Two steps run in tiles of
  * 16 chains x 64 columns staged in LDS (tiled = 0) or, where the slots follow
  * the order of kpm_build_graphene (and there are at least 16 chains), in
- * register tiles of one wavefront each, 8 chains (tiled = 1) or 4 (tiled >=
- * 2) by 64 - 2 steps columns; 3 and 4 steps need the register tiles (else 2
- * steps apply).  Under steps > 1 any single steps keep row order.  Default
+ * register tiles of one wavefront each, 8 chains (tiled = 1) or 4 (tiled =
+ * 2) by 64 - 2 steps columns, or in strips of 64 - 2 steps columns that one
+ * wavefront walks chain by chain, 16, 32 or 64 chains long (tiled = 3, 4, 5);
+ * 3 and 4 steps need the register forms (else 2 steps apply).  Under steps > 1 any single steps keep row order.  Default
  * for one vector: groups_per_cu 4, steps 4, tiled 2; for more vectors single
  * steps.  At a fixed grid size, traversal and step count the moments
  * are bit-identical for every ilp, streaming and compact choice; the
@@ -468,8 +469,9 @@ kpm_status kpm_get_launch(kpm_system *sys, int n_vec, kpm_launch *out);
  * compact in {0, 1} when the system has the compact form x tiled in {0, 1}
  * for lattices with long chains; plus, where the multi-step sweeps apply,
  * steps = 2 in LDS tiles with groups_per_cu in {2, 3, 4, 6} x streaming in
- * {0, 1}, and steps in {2, 3, 4} in register tiles (tiled in {1, 2}) with
- * groups_per_cu in {1, 2, 3, 4, 6, 8}) on the device state
+ * {0, 1}, steps in {2, 3, 4} in register tiles (tiled in {1, 2}) with
+ * groups_per_cu in {1, 2, 3, 4, 6, 8}, and steps in {3, 4} in marching strips
+ * (tiled in {3, 4}) with groups_per_cu in {2, 3, 4}) on the device state
  * `phi` ([n_sites][n_vec], read only; only system scratch is written), keeps
  * the fastest for this n_vec and returns it in *best (may be NULL).
  * Synchronises the stream.

@@ -82,8 +82,8 @@ struct DeviceGuard {
 bool valid_launch(const kpm_launch &l) {
     return l.groups_per_cu >= 1 && l.groups_per_cu <= 32 &&
            (l.ilp == 1 || l.ilp == 2 || l.ilp == 4) && (l.streaming == 0 || l.streaming == 1) &&
-           (l.compact == 0 || l.compact == 1) && l.tiled >= 0 && l.tiled <= 3 &&
-           l.steps >= 1 && l.steps <= 4;
+           (l.compact == 0 || l.compact == 1) && l.tiled >= 0 &&
+           l.tiled <= (l.steps > 1 ? 5 : 3) && l.steps >= 1 && l.steps <= 4;
 }
 
 // Tile width (rows) of the tiled traversal for 2^vshift vectors per row: a
@@ -327,11 +327,12 @@ struct kpm_system {
 
     // Multi-step tiles: two steps in LDS tiles of 16 chains x kTileCols
     // columns (tiled = 0, or no graphene slot order); register tiles of 8
-    // chains (tiled = 1, or tiled = 0 with 3 or 4 steps) or 4 (tiled >= 2).
+    // chains (tiled = 1, or tiled = 0 with 3 or 4 steps) or 4 (tiled = 2);
+    // marching strips of 16, 32 or 64 chains (tiled = 3, 4, 5).
     kpm::Lat2 lat2(const kpm_launch &l, int k) const {
-        const bool reg = d_flags && (l.tiled >= 1 || k > 2);
-        const int tj = reg ? (l.tiled >= 2 ? 4 : 8) : 16;
-        return kpm::Lat2{l2nx, l2ny, k, reg ? 1 : 0, tj, (l2nx + kpm::kTileCols - 1) / kpm::kTileCols,
+        const int reg = !d_flags ? 0 : (l.tiled >= 3 ? 2 : ((l.tiled >= 1 || k > 2) ? 1 : 0));
+        const int tj = reg == 2 ? 16 << (l.tiled - 3) : (reg == 1 ? (l.tiled == 2 ? 4 : 8) : 16);
+        return kpm::Lat2{l2nx, l2ny, k, reg, tj, (l2nx + kpm::kTileCols - 1) / kpm::kTileCols,
                          (l2ny + tj - 1) / tj, d_code, d_flags};
     }
 
@@ -1150,11 +1151,15 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
     if (sys->d_code && vs == 0) {
         for (int g : {2, 3, 4, 6})
             for (int nt : {0, 1}) multi.push_back(kpm_launch{g, 1, nt, 1, 0, 2});
-        if (sys->d_flags)
+        if (sys->d_flags) {
             for (int ksteps : {2, 3, 4})
                 for (int tiled : {1, 2})
                     for (int g : {1, 2, 3, 4, 6, 8})
                         multi.push_back(kpm_launch{g, 1, 0, 1, tiled, ksteps});
+            for (int ksteps : {3, 4})
+                for (int tiled : {3, 4})
+                    for (int g : {2, 3, 4}) multi.push_back(kpm_launch{g, 1, 0, 1, tiled, ksteps});
+        }
     }
     for (const kpm_launch &l : multi) {
         if (st != KPM_OK) break;

@@ -82,9 +82,9 @@ struct Sweep {
 // empty slot.  k recursion steps per pass (2, 3 or 4).  reg = 0: the LDS form
 // (k = 2; tiles of tj = 16 chains x kTileCols columns, nti x ntj of them).
 // reg = 1: the register-tiled form (tiles of tj = 4 or 8 chains x (64 - 2k)
-// columns per wavefront) for samples whose slots follow the graphene
-// builder's order: flags[p] bit k = slot k filled, bit 3 = slot 2 joins the
-// next chain.
+// columns per wavefront) and reg = 2 its marching form (strips of tj chains
+// walked row by row), for samples whose slots follow the graphene builder's
+// order: flags[p] bit k = slot k filled, bit 3 = slot 2 joins the next chain.
 constexpr int kTileCols = 64;
 struct Lat2 {
     int32_t nx, ny;

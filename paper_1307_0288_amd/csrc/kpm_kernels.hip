@@ -933,14 +933,38 @@ __device__ __forceinline__ double2 reg_row_step(double o, double t, uint32_t f, 
     return two_minus(acc, q);
 }
 
-// Element at a byte offset from a wave-uniform row base.
-template <typename T>
-__device__ __forceinline__ T *row_at(T *base, uint32_t byte_off) {
-    return reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off);
+// Row accesses of the register tiles: one buffer resource per row (a
+// wave-uniform base and the row's byte size, so out-of-row offsets read 0 and
+// drop stores) and the lane's byte offset in the row, shared by all rows.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kBufWord3 = 0x00020000;     // raw 32-bit access, gfx9 buffer resource
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, kBufWord3);
 }
-template <typename T>
-__device__ __forceinline__ const T *row_at(const T *base, uint32_t byte_off) {
-    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+__device__ __forceinline__ double2 buf_ld(const double2 *row, uint32_t bytes, uint32_t off) {
+    const d2v v = __builtin_bit_cast(
+        d2v, __builtin_amdgcn_raw_buffer_load_b128(row_rsrc(row, bytes), (int)off, 0, 0));
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ double2 buf_ld(const float2 *row, uint32_t bytes, uint32_t off) {
+    const f2v v = __builtin_bit_cast(
+        f2v, __builtin_amdgcn_raw_buffer_load_b64(row_rsrc(row, bytes), (int)off, 0, 0));
+    return make_double2((double)v.x, (double)v.y);
+}
+__device__ __forceinline__ void buf_st(double2 *row, uint32_t bytes, uint32_t off, double2 x) {
+    d2v v;
+    v.x = x.x;
+    v.y = x.y;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), row_rsrc(row, bytes),
+                                           (int)off, 0, 0);
+}
+__device__ __forceinline__ void buf_st(float2 *row, uint32_t bytes, uint32_t off, double2 x) {
+    f2v v;
+    v.x = (float)x.x;
+    v.y = (float)x.y;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), row_rsrc(row, bytes),
+                                          (int)off, 0, 0);
 }
 
 template <typename V, bool ONSF, bool DBL, int TJ, int K>
@@ -980,31 +1004,37 @@ __global__ __launch_bounds__(kBlock) void k_moment_stepk(Ell h, Sweep sw, Lat2 l
         const int gi = wrap_index(c0 - K + lane, nx);
         const bool colok = lane >= K && lane < K + TC && c0 - K + lane < nx;
         const int H = min(TJ, ny - j0);
-        const uint32_t ov = (uint32_t)gi * sizeof(V);
+        const uint32_t ov = (uint32_t)gi * sizeof(V), rb = (uint32_t)nx * sizeof(V);
         auto base = [&](int w) { return (int64_t)wrap_index(j0 - K + w, ny) * nx; };
         // every load of the tile first, pattern ids leading (their flag
         // lookups then wait for nothing else)
         int pf[R0];
 #pragma unroll
-        for (int w = 1; w < R0 - 1; ++w) pf[w] = *row_at(h.pid + base(w), (uint32_t)gi);
+        for (int w = 1; w < R0 - 1; ++w)
+            pf[w] = __builtin_amdgcn_raw_buffer_load_b8(row_rsrc(h.pid + base(w), (uint32_t)nx),
+                                                        gi, 0, 0);
         double2 B[R0];                                  // phi_n
 #pragma unroll
-        for (int w = 0; w < R0; ++w) B[w] = ld(row_at(p1 + base(w), ov));
+        for (int w = 0; w < R0; ++w) B[w] = buf_ld(p1 + base(w), rb, ov);
         double2 A[R0];                                  // phi_{n-1}
         float of[R0];
         double od[R0];
 #pragma unroll
         for (int w = 1; w < R0 - 1; ++w) {
-            A[w] = ld(row_at(p0 + base(w), ov));
+            A[w] = buf_ld(p0 + base(w), rb, ov);
             if (ONSF)
-                of[w] = *row_at(h.onsf + base(w), (uint32_t)gi * 4u);
+                of[w] = __builtin_bit_cast(
+                    float, __builtin_amdgcn_raw_buffer_load_b32(
+                               row_rsrc(h.onsf + base(w), (uint32_t)nx * 4u), gi * 4, 0, 0));
             else
-                od[w] = *row_at(h.ons + base(w), (uint32_t)gi * 8u);
+                od[w] = __builtin_bit_cast(
+                    double, __builtin_amdgcn_raw_buffer_load_b64(
+                                row_rsrc(h.ons + base(w), (uint32_t)nx * 8u), gi * 8, 0, 0));
         }
         double2 L[TJ];
 #pragma unroll
         for (int r = 0; r < TJ; ++r)
-            L[r] = DBL ? make_double2(0.0, 0.0) : ld(row_at(phil + base(K + r), ov));
+            L[r] = DBL ? make_double2(0.0, 0.0) : buf_ld(phil + base(K + r), rb, ov);
         uint32_t fl[R0];
 #pragma unroll
         for (int w = 1; w < R0 - 1; ++w) fl[w] = lflag[pf[w]];
@@ -1036,9 +1066,142 @@ __global__ __launch_bounds__(kBlock) void k_moment_stepk(Ell h, Sweep sw, Lat2 l
 #pragma unroll
         for (int r = 0; r < TJ; ++r) {
             if (r < H && colok) {
-                const int64_t rb = (int64_t)(j0 + r) * nx;
-                st(row_at(out1 + rb, ov), A[K + r]);
-                st(row_at(out2 + rb, ov), B[K + r]);
+                const int64_t row = (int64_t)(j0 + r) * nx;
+                buf_st(out1 + row, rb, ov, A[K + r]);
+                buf_st(out2 + row, rb, ov, B[K + r]);
+            }
+        }
+    }
+    const int nw = sw.nwg;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) block_sum(acc[k], 0, partial + (int64_t)(slot + k) * nw + blockIdx.x);
+}
+
+// Marching form of the register-tiled K-step sweep: a wavefront takes a strip
+// of (kWave - 2K) columns (lanes as in k_moment_stepk) and J chains, and walks
+// down the chains.  Iteration t brings in chain row t of phi_n (window rows
+// j0 - K .. j0 + J + K - 1) and computes level s = 1 .. K (phi_{n+s}) on row
+// t - s, from level s - 1 on rows t - s - 1 .. t - s + 1 and level s - 2 on
+// row t - s.  Each level keeps its last three rows in registers, so rows are
+// computed once per level except the K - 1 boundary rows at each end of the
+// strip, instead of once per tile as in k_moment_stepk.  phi_n and phi_{n-1}
+// are loaded kDs rows ahead and the per-row terms (pattern id, on-site term,
+// phi_L) kRingP - 1 - K rows ahead, in rings of kRingP rows; the loop is
+// unrolled by kRingP so every ring index is a compile-time constant.
+constexpr int kRingP = 6;
+constexpr int kDs = 3;
+
+template <typename V, bool ONSF, bool DBL, int K>
+__global__ __launch_bounds__(kBlock) void k_moment_march(Ell h, Sweep sw, Lat2 lat,
+                                                         const V *p1, const V *p0,
+                                                         V *__restrict__ out1,
+                                                         V *__restrict__ out2,
+                                                         const V *__restrict__ phil,
+                                                         double2 *__restrict__ partial,
+                                                         int slot) {
+    constexpr int TC = kWave - 2 * K;                  // columns per strip
+    constexpr int P = kRingP, DS = kDs, DR = kRingP - 1 - K;
+    constexpr int NA = DBL ? 2 * K : K;
+    static_assert(DR >= 1 && DS < P, "ring too short for K");
+    __shared__ uint32_t lflag[kMaxPatterns];
+    for (int j = threadIdx.x; j < h.npat; j += kBlock) lflag[j] = lat.flags[j];
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1);
+    const int nx = lat.nx, ny = lat.ny, J = lat.tj;
+    const double t = sw.one.t, inv_es = sw.one.inv_es;
+    const int nst = (nx + TC - 1) / TC, nsg = (ny + J - 1) / J;
+    const int ntile = nst * nsg;
+    const int lb = blockIdx.x;
+    const int per = (ntile + kXcds - 1) / kXcds;
+    const int b0 = (lb % kXcds) * per, b1 = min(b0 + per, ntile);
+    constexpr int kWaves = kBlock / kWave;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int wloc = (lb / kXcds) * kWaves + wv;
+    const int wn = (sw.nwg / kXcds) * kWaves;
+    double2 acc[NA];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) acc[k] = make_double2(0.0, 0.0);
+    for (int b = b0 + wloc; b < b1; b += wn) {
+        const int strip = b / nsg;
+        const int j0 = (b - strip * nsg) * J, c0 = strip * TC;
+        const int gi = wrap_index(c0 - K + lane, nx);
+        const bool colok = lane >= K && lane < K + TC && c0 - K + lane < nx;
+        const int Jt = min(J, ny - j0), T = Jt + 2 * K;
+        const uint32_t ov = (uint32_t)gi * sizeof(V), rb = (uint32_t)nx * sizeof(V);
+        auto base = [&](int rho) { return (int64_t)wrap_index(j0 - K + rho, ny) * nx; };
+        double2 X0[P], Xm[P], LL[P];                   // phi_n, phi_{n-1}, phi_L rings
+        int PI[P];                                     // pattern ids
+        float OF[P];
+        double OD[P];
+        double2 LV[K][3];                              // levels 1 .. K, last three rows
+        auto load_state = [&](int rho, int q) {
+            X0[q] = buf_ld(p1 + base(rho), rb, ov);
+            Xm[q] = buf_ld(p0 + base(rho), rb, ov);
+        };
+        auto load_row = [&](int rho, int q) {
+            const int64_t rbase = base(rho);
+            PI[q] = __builtin_amdgcn_raw_buffer_load_b8(row_rsrc(h.pid + rbase, (uint32_t)nx), gi,
+                                                        0, 0);
+            if (ONSF)
+                OF[q] = __builtin_bit_cast(
+                    float, __builtin_amdgcn_raw_buffer_load_b32(
+                               row_rsrc(h.onsf + rbase, (uint32_t)nx * 4u), gi * 4, 0, 0));
+            else
+                OD[q] = __builtin_bit_cast(
+                    double, __builtin_amdgcn_raw_buffer_load_b64(
+                                row_rsrc(h.ons + rbase, (uint32_t)nx * 8u), gi * 8, 0, 0));
+            if (!DBL && rho >= K && rho < K + Jt) LL[q] = buf_ld(phil + rbase, rb, ov);
+        };
+#pragma unroll
+        for (int r = 0; r < DS; ++r)
+            if (r < T) load_state(r, r);
+#pragma unroll
+        for (int r = 0; r < DR; ++r)
+            if (r < T) load_row(r, r);
+        for (int t0 = 0; t0 < T; t0 += P) {
+#pragma unroll
+            for (int u = 0; u < P; ++u) {
+                const int tt = t0 + u;
+                if (tt >= T) break;
+                if (tt + DS < T) load_state(tt + DS, (u + DS) % P);
+                if (tt + DR < T) load_row(tt + DR, (u + DR) % P);
+#pragma unroll
+                for (int s = 1; s <= K; ++s) {
+                    const int rho = tt - s;
+                    if (rho < s) continue;
+                    // ring slots of rows rho - 1, rho, rho + 1 (rho = t0 + u - s)
+                    const int qp = ((u - s) % P + P) % P;               // per-row ring, row rho
+                    const int q3 = ((u - s) % 3 + 3) % 3;               // level rings, row rho
+                    const int q3m = (q3 + 2) % 3, q3p = (q3 + 1) % 3;   // rows rho - 1, rho + 1
+                    const int qm = (qp + P - 1) % P, qq = (qp + 1) % P;
+                    double2 xm1, x0, xp1, old;
+                    if (s == 1) {
+                        xm1 = X0[qm];
+                        x0 = X0[qp];
+                        xp1 = X0[qq];
+                        old = Xm[qp];
+                    } else {
+                        xm1 = LV[s - 2][q3m];
+                        x0 = LV[s - 2][q3];
+                        xp1 = LV[s - 2][q3p];
+                        old = s == 2 ? X0[qp] : LV[s - 3 < 0 ? 0 : s - 3][q3];
+                    }
+                    const double o = ONSF ? (double)OF[qp] * inv_es : OD[qp];
+                    const uint32_t f = lflag[PI[qp]];
+                    const double2 c = rounded<V>(reg_row_step(o, t, f, x0, xp1, xm1, old));
+                    LV[s - 1][q3] = c;
+                    if (rho >= K && rho < K + Jt && colok) {
+                        if (DBL) {
+                            acc[2 * (s - 1)] = cdot_acc(acc[2 * (s - 1)], x0, x0);
+                            acc[2 * (s - 1) + 1] = cdot_acc(acc[2 * (s - 1) + 1], x0, c);
+                        } else {
+                            acc[s - 1] = cdot_acc(acc[s - 1], LL[qp], c);
+                        }
+                        const int64_t row = (int64_t)(j0 + rho - K) * nx;
+                        if (s == K - 1) buf_st(out1 + row, rb, ov, c);
+                        if (s == K) buf_st(out2 + row, rb, ov, c);
+                    }
+                }
             }
         }
     }
@@ -1199,10 +1362,20 @@ void launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
         else if (lat.k == 3) KPM_REGK(ONSF_, DBL_, TJ_, 3);                                   \
         else KPM_REGK(ONSF_, DBL_, TJ_, 2);                                                   \
     } while (0)
+#define KPM_MARCHK(ONSF_, DBL_, K_)                                                          \
+    hipLaunchKernelGGL((k_moment_march<V, ONSF_, DBL_, K_>), dim3(sw.nwg), dim3(kBlock), 0, s, \
+                       h, sw, lat, p1, p0, out1, out2, phil, partial, slot)
 #define KPM_REG(ONSF_, DBL_)                                                                  \
     do {                                                                                      \
-        if (lat.tj == 4) KPM_REG_K(ONSF_, DBL_, 4);                                           \
-        else KPM_REG_K(ONSF_, DBL_, 8);                                                       \
+        if (lat.reg == 2) {                                                                   \
+            if (lat.k == 4) KPM_MARCHK(ONSF_, DBL_, 4);                                       \
+            else if (lat.k == 3) KPM_MARCHK(ONSF_, DBL_, 3);                                  \
+            else KPM_MARCHK(ONSF_, DBL_, 2);                                                  \
+        } else if (lat.tj == 4) {                                                             \
+            KPM_REG_K(ONSF_, DBL_, 4);                                                        \
+        } else {                                                                              \
+            KPM_REG_K(ONSF_, DBL_, 8);                                                        \
+        }                                                                                     \
     } while (0)
     if (lat.reg) {
         if (onsf) { if (dbl) KPM_REG(true, true); else KPM_REG(true, false); }
@@ -1218,6 +1391,7 @@ void launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
 #undef KPM_REGK
 #undef KPM_REG_K
 #undef KPM_REG
+#undef KPM_MARCHK
 }
 
 #define KPM_INSTANTIATE(V)                                                                  \

@@ -54,7 +54,9 @@ def moment_kernel_name(v: str, launch: dict, dbl: bool, n_vec: int = 1) -> str:
         k, tiled = launch["steps"], launch["tiled"]
         if k == 2 and tiled == 0:
             return f"k_moment_step2<{v},{nt},true,{db},16>"
-        return f"k_moment_stepk<{v},true,{db},{4 if tiled >= 2 else 8},{k}>"
+        if tiled >= 3:
+            return f"k_moment_march<{v},true,{db},{k}>"
+        return f"k_moment_stepk<{v},true,{db},{4 if tiled == 2 else 8},{k}>"
     form = "kFormC3F" if launch["compact"] else "kFormL3F"
     return f"k_moment_step<{v},{launch['ilp']},{nt},{form},{db}>"
 

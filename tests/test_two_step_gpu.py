@@ -32,15 +32,17 @@ def _log(msg):
 
 def _pair(c, precision="fp64", tiled=0, steps=2):
     """Systems on the same sample: single steps, and `steps` steps per pass in
-    LDS tiles of 16 chains (tiled = 0, two steps) or register tiles of 8
-    (tiled = 1) or 4 (tiled = 2) chains."""
+    LDS tiles of 16 chains (tiled = 0, two steps), register tiles of 8
+    (tiled = 1) or 4 (tiled = 2) chains, or marching strips of 16, 32 or 64
+    chains (tiled = 3, 4, 5)."""
     one, two = gpu_system(c, precision), gpu_system(c, precision)
     kp.kpm_set_launch(one, 1, 4, 1, 0, 1, 0, 1)
     kp.kpm_set_launch(two, 1, 3, 1, 0, 1, tiled, steps)
     return one, two
 
 
-MULTI = [(2, 0), (2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (4, 2)]
+MULTI = [(2, 0), (2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (4, 2), (2, 3), (3, 4), (4, 3), (4, 4),
+         (4, 5)]
 
 
 @pytest.mark.parametrize("geometry,nx,ny", SHAPES)
@@ -88,7 +90,7 @@ def test_distinct_left_vector_and_doubling(geometry, nx, ny, steps, tiled):
         assert rel_err(dbl, ref, np.vdot(pr, pr).real) < 1e-10, nm
 
 
-@pytest.mark.parametrize("steps,tiled", [(2, 0), (3, 1)])
+@pytest.mark.parametrize("steps,tiled", [(2, 0), (3, 1), (3, 3)])
 def test_double_onsite_form(steps, tiled):
     """On-site energies that are not floats: the width-3 compact form with
     double on-site terms."""
@@ -109,7 +111,7 @@ def test_double_onsite_form(steps, tiled):
     assert rel_err(m2, ref, scale) < 1e-10 and rel_err(m2, m1, scale) < 1e-13
 
 
-@pytest.mark.parametrize("steps,tiled", [(2, 0), (4, 2)])
+@pytest.mark.parametrize("steps,tiled", [(2, 0), (4, 2), (4, 4)])
 def test_fp32_states_equal_single_step(steps, tiled):
     _need_gpu()
     c = recipe("sheet", 130, 26, w=1.0, vac=0.02, seed=5)
@@ -126,7 +128,7 @@ def test_fp32_states_equal_single_step(steps, tiled):
 
 
 @pytest.mark.parametrize("kind", ["vac", "msd"])
-@pytest.mark.parametrize("steps,tiled", [(2, 0), (3, 2)])
+@pytest.mark.parametrize("steps,tiled", [(2, 0), (3, 2), (4, 3)])
 def test_time_loops_with_two_step_moments(kind, steps, tiled):
     _need_gpu()
     c = recipe("sheet", 130, 26, w=1.0, vac=0.02, seed=9)
@@ -142,7 +144,7 @@ def test_time_loops_with_two_step_moments(kind, steps, tiled):
     assert rel_err(got[0], ref) < 1e-10
 
 
-@pytest.mark.parametrize("steps,tiled", [(2, 0), (4, 1)])
+@pytest.mark.parametrize("steps,tiled", [(2, 0), (4, 1), (4, 4)])
 def test_graph_replays_match_eager(steps, tiled):
     _need_gpu()
     c = recipe("zgnr", 130, 38, w=1.0, vac=0.02, seed=11)
