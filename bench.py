@@ -199,7 +199,8 @@ def doubled(args):
     phi = sysg.upload(ki.random_phase(n, 1, 3000, act))
     nm, ns, nb, dt = p["n_moments"], p["n_steps"], p["n_bessel"], p["dt_fs"]
     launch = kp.kpm_autotune(sysg, phi, 50)
-    log(f"autotuned launch shape: {launch}")
+    launch_dbl = kp.kpm_get_launch_doubled(sysg, 1)
+    log(f"autotuned launch shapes: direct {launch}, doubling {launch_dbl}")
     calls = {
         "dos_direct": lambda: kp.kpm_moments(sysg, phi, phi, nm),
         "dos_doubled": lambda: kp.kpm_moments_doubled(sysg, phi, nm),
@@ -248,12 +249,13 @@ def doubled(args):
         "config": {"workload": "graphene sheet 2828x1414 sites (3998792), 0.5% vacancies, "
                                "W=0.1 eV, 1 random-phase vector, 3000 moments; MSD 20 steps x "
                                "40 Bessel terms, dt=hbar/|t|",
-                   "n_sites": n, "n_moments": nm, "launch_shape": launch},
-        "roofline": {"kernel": moment_kernel_name("double2", launch, True), "bound": "hbm",
+                   "n_sites": n, "n_moments": nm, "launch_shape": launch,
+                   "launch_shape_doubling": launch_dbl},
+        "roofline": {"kernel": moment_kernel_name("double2", launch_dbl, True), "bound": "hbm",
                      "achieved": dd["step_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(dd["step_gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(TRAFFIC_FILE2_DBL if multi_step(launch)
-                                                 else TRAFFIC_FILE_DBL, n, launch),
+                     "traffic": measured_traffic(TRAFFIC_FILE2_DBL if multi_step(launch_dbl)
+                                                 else TRAFFIC_FILE_DBL, n, launch_dbl),
                      "bytes_per_launch": dd["step_bytes"],
                      "avg_launch_us": dd["step_launch_us"]},
         "forms": res,

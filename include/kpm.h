@@ -460,8 +460,14 @@ typedef struct {
     int32_t steps;
 } kpm_launch;
 
+/* kpm_set_launch sets the shape of both forms (direct and doubling);
+ * kpm_get_launch returns the direct form's. */
 kpm_status kpm_set_launch(kpm_system *sys, int n_vec, const kpm_launch *launch);
 kpm_status kpm_get_launch(kpm_system *sys, int n_vec, kpm_launch *out);
+/* The shape of moment sets in the doubling form (kpm_moments_doubled,
+ * kpm_msd_doubled), which kpm_autotune chooses separately. */
+kpm_status kpm_set_launch_doubled(kpm_system *sys, int n_vec, const kpm_launch *launch);
+kpm_status kpm_get_launch_doubled(kpm_system *sys, int n_vec, kpm_launch *out);
 
 /*
  * Autotuner: times `reps` moment steps of every candidate shape
@@ -472,8 +478,9 @@ kpm_status kpm_get_launch(kpm_system *sys, int n_vec, kpm_launch *out);
  * {0, 1}, steps in {2, 3, 4} in register tiles (tiled in {1, 2}) with
  * groups_per_cu in {1, 2, 3, 4, 6, 8}, and steps in {3, 4} in marching strips
  * (tiled in {3, 4}) with groups_per_cu in {2, 3, 4}) on the device state
- * `phi` ([n_sites][n_vec], read only; only system scratch is written), keeps
- * the fastest for this n_vec and returns it in *best (may be NULL).
+ * `phi` ([n_sites][n_vec], read only; only system scratch is written), for
+ * the direct and, separately, the doubling form, keeps the fastest of each
+ * for this n_vec and returns the direct form's in *best (may be NULL).
  * Synchronises the stream.
  */
 kpm_status kpm_autotune(kpm_system *sys, int n_vec, const void *phi, int reps,

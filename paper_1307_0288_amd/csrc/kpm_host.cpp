@@ -214,6 +214,11 @@ struct kpm_system {
     bool has_dx = false;
     int cus = 256;
     kpm_launch launch[7];       // launch shape of the moment step per log2(n_vec)
+    kpm_launch launch_dbl[7];   // the same for moment sets in the doubling form
+
+    const kpm_launch &shape(int vshift, bool dbl) const {
+        return dbl ? launch_dbl[vshift] : launch[vshift];
+    }
     // samples: rows [off[s], off[s+1]) hold sample s, whose scale is es[s]
     int nseg = 1;
     std::vector<int64_t> off;
@@ -356,7 +361,7 @@ struct kpm_system {
     // form, which reads no phi_L) and the row structure once per row
     // (neighbours, on-site term, per-slot hopping).
     int64_t step_bytes(int vshift, bool dbl = false) const {
-        const bool compact = d_pid && launch[vshift].compact;
+        const bool compact = d_pid && shape(vshift, dbl).compact;
         const int64_t per_row = (compact ? 1 : 4 * w) + (d_onsf ? 4 : 8) + (d_hop ? 8 * w : 0);
         const int64_t acc = dbl ? 3 : 4;
         return n * ((acc * elem_bytes()) << vshift) + n * per_row;
@@ -658,7 +663,7 @@ template <typename V>
 kpm_status enqueue_moments(kpm_system *sys, const kpm::Sweep &sw, int ring, hipStream_t s,
                            bool events, bool dbl, const V *phil, const V *phir, int nm,
                            V *a_buf, V *b_buf, int64_t stride_r, int64_t offset) {
-    const kpm_launch &l = sys->launch[sw.vshift];
+    const kpm_launch &l = sys->shape(sw.vshift, dbl);
     const kpm::Ell h = sys->ell_for(l);
     const int k = sys->multi_steps(sw.vshift, l);
     const kpm::Lat2 lat = sys->lat2(l, k);
@@ -733,9 +738,9 @@ kpm_status enqueue_moments(kpm_system *sys, const kpm::Sweep &sw, int ring, hipS
 template <typename V>
 kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir, int nm,
                        V *a_buf, V *b_buf, int64_t stride_r, int64_t offset, bool dbl = false) {
+    const kpm_launch &l = sys->shape(vshift, dbl);
     kpm::Sweep sw;
-    KPM_TRY(sys->sweep(vshift, &sw));
-    const kpm_launch &l = sys->launch[vshift];
+    KPM_TRY(sys->sweep_with(vshift, l, &sw));
     const int k = sys->multi_steps(vshift, l);
     if (k > 1) KPM_TRY(sys->ensure_xbuf(vshift));
     // Group partials live in a ring of moment slots that is reduced into
@@ -1086,13 +1091,13 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
     // Each candidate runs the real two-buffer recursion (the output of one
     // step is the gathered input of the next) on copies of phi, three times;
     // the fastest round counts.
-    auto time_shape = [&](const kpm_launch &l, float *out_ms) -> kpm_status {
+    auto time_shape = [&](const kpm_launch &l, bool dbl, float *out_ms) -> kpm_status {
         const kpm::Ell h = sys->ell_for(l);
         kpm::Sweep sw;
         KPM_TRY(sys->sweep_with(vs, l, &sw));
         const int ks = sys->multi_steps(vs, l);
         if (ks > 1) KPM_TRY(sys->ensure_xbuf(vs));
-        KPM_TRY(sys->ensure_partial(ks, sw.nwg, 1 << vs));
+        KPM_TRY(sys->ensure_partial(2 * ks, sw.nwg, 1 << vs));
         const kpm::Lat2 lat = sys->lat2(l, ks);
         float best = 1e30f;
         for (int round = 0; round < 3; ++round) {
@@ -1103,13 +1108,16 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
             for (int k = 0; k < reps; ++k) {
                 if (ks > 1 && k + ks <= reps) {
                     kpm::launch_moment_multi<V>(h, sw, lat, p1, p0, o1, o2, phi, sys->partial, 0,
-                                                false, s);
+                                                dbl, s);
                     std::swap(p0, o1);
                     std::swap(p1, o2);
                     k += ks - 1;
                     continue;
                 }
-                kpm::launch_moment_step<V>(h, sw, false, p1, p0, p0, phi, sys->partial, 0, s);
+                if (dbl)
+                    kpm::launch_moment_step_doubled<V>(h, sw, p1, p0, p0, sys->partial, 0, s);
+                else
+                    kpm::launch_moment_step<V>(h, sw, false, p1, p0, p0, phi, sys->partial, 0, s);
                 std::swap(p0, p1);
             }
             KPM_HIP(hipEventRecord(e1, s));
@@ -1121,13 +1129,14 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
         *out_ms = best;
         return KPM_OK;
     };
-    // The current shape is the incumbent; a candidate replaces it only when
-    // it is more than 2 % faster, so near-ties keep a stable choice.
-    kpm_launch pick = sys->launch[vs];
-    float best_ms = 1e30f;
-    st = time_shape(pick, &best_ms);
-    for (int g : groups) {
-        for (int q = 0; q < 6 * forms * tilings && st == KPM_OK; ++q) {
+    // Candidates: single steps (grid x ILP x streaming x neighbour form x
+    // traversal), then several recursion steps per pass on chain lattices
+    // with one vector: two steps in LDS tiles, and 2, 3 or 4 steps in register
+    // tiles of 8 or 4 chains or marching strips where the slots follow the
+    // graphene order.
+    std::vector<kpm_launch> cand;
+    for (int g : groups)
+        for (int q = 0; q < 6 * forms * tilings; ++q) {
             kpm_launch l;
             l.groups_per_cu = g;
             l.ilp = ilps[q % 3];
@@ -1135,39 +1144,38 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
             l.compact = forms == 2 ? (q / 6) % 2 : 0;
             l.tiled = tilings == 2 ? q / (6 * forms) : 0;
             l.steps = 1;
-            float ms = 0;
-            if ((st = time_shape(l, &ms)) != KPM_OK) break;
-            if (ms < 0.98f * best_ms) {
-                best_ms = ms;
-                pick = l;
-            }
+            cand.push_back(l);
         }
-        if (st != KPM_OK) break;
-    }
-    // several recursion steps per pass (chain lattices, one vector): two
-    // steps in LDS tiles, and 2, 3 or 4 steps in register tiles of 8 or 4
-    // chains where the slots follow the graphene order
-    std::vector<kpm_launch> multi;
     if (sys->d_code && vs == 0) {
         for (int g : {2, 3, 4, 6})
-            for (int nt : {0, 1}) multi.push_back(kpm_launch{g, 1, nt, 1, 0, 2});
+            for (int nt : {0, 1}) cand.push_back(kpm_launch{g, 1, nt, 1, 0, 2});
         if (sys->d_flags) {
             for (int ksteps : {2, 3, 4})
                 for (int tiled : {1, 2})
                     for (int g : {1, 2, 3, 4, 6, 8})
-                        multi.push_back(kpm_launch{g, 1, 0, 1, tiled, ksteps});
+                        cand.push_back(kpm_launch{g, 1, 0, 1, tiled, ksteps});
             for (int ksteps : {3, 4})
                 for (int tiled : {3, 4})
-                    for (int g : {2, 3, 4}) multi.push_back(kpm_launch{g, 1, 0, 1, tiled, ksteps});
+                    for (int g : {2, 3, 4}) cand.push_back(kpm_launch{g, 1, 0, 1, tiled, ksteps});
         }
     }
-    for (const kpm_launch &l : multi) {
-        if (st != KPM_OK) break;
-        float ms = 0;
-        if ((st = time_shape(l, &ms)) != KPM_OK) break;
-        if (ms < 0.98f * best_ms) {
-            best_ms = ms;
-            pick = l;
+    // Each form (direct, doubling) keeps its current shape as the incumbent; a
+    // candidate replaces it only when more than 2 % faster, so near-ties keep
+    // a stable choice.
+    kpm_launch pick = sys->launch[vs], pick_dbl = sys->launch_dbl[vs];
+    for (int form = 0; form < 2 && st == KPM_OK; ++form) {
+        const bool dbl = form == 1;
+        kpm_launch &p = dbl ? pick_dbl : pick;
+        float best_ms = 1e30f;
+        st = time_shape(p, dbl, &best_ms);
+        for (const kpm_launch &l : cand) {
+            if (st != KPM_OK) break;
+            float ms = 0;
+            if ((st = time_shape(l, dbl, &ms)) != KPM_OK) break;
+            if (ms < 0.98f * best_ms) {
+                best_ms = ms;
+                p = l;
+            }
         }
     }
     (void)hipEventDestroy(e0);
@@ -1175,6 +1183,7 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
     if (st != KPM_OK) return st;
     KPM_HIP(hipGetLastError());
     sys->launch[vs] = pick;
+    sys->launch_dbl[vs] = pick_dbl;
     if (best) *best = pick;
     return KPM_OK;
 }
@@ -1226,6 +1235,7 @@ kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int devi
         for (auto &l : sys->launch) l.tiled = std::max(0, std::min(3, atoi(env)));
     if (const char *env = std::getenv("KPM_STEPS"))
         for (auto &l : sys->launch) l.steps = std::max(1, std::min(4, atoi(env)));
+    for (int v = 0; v < 7; ++v) sys->launch_dbl[v] = sys->launch[v];
     if (const char *env = std::getenv("KPM_SCRATCH_LIMIT_MB"))
         sys->scratch_limit = (size_t)(std::max(0.0, atof(env)) * 1048576.0);
     sys->chain.resize(nseg);
@@ -1638,6 +1648,7 @@ kpm_status kpm_set_launch(kpm_system *sys, int n_vec, const kpm_launch *l) {
     KPM_TRY(check_common(sys, n_vec, &vs));
     if (!l || !valid_launch(*l)) return fail(KPM_ERR_INVALID, "launch shape out of range");
     sys->launch[vs] = *l;
+    sys->launch_dbl[vs] = *l;
     return KPM_OK;
 }
 
@@ -1646,6 +1657,22 @@ kpm_status kpm_get_launch(kpm_system *sys, int n_vec, kpm_launch *out) {
     KPM_TRY(check_common(sys, n_vec, &vs));
     if (!out) return fail(KPM_ERR_INVALID, "null output");
     *out = sys->launch[vs];
+    return KPM_OK;
+}
+
+kpm_status kpm_set_launch_doubled(kpm_system *sys, int n_vec, const kpm_launch *l) {
+    int vs;
+    KPM_TRY(check_common(sys, n_vec, &vs));
+    if (!l || !valid_launch(*l)) return fail(KPM_ERR_INVALID, "launch shape out of range");
+    sys->launch_dbl[vs] = *l;
+    return KPM_OK;
+}
+
+kpm_status kpm_get_launch_doubled(kpm_system *sys, int n_vec, kpm_launch *out) {
+    int vs;
+    KPM_TRY(check_common(sys, n_vec, &vs));
+    if (!out) return fail(KPM_ERR_INVALID, "null output");
+    *out = sys->launch_dbl[vs];
     return KPM_OK;
 }
 

@@ -1085,10 +1085,12 @@ __global__ __launch_bounds__(kBlock) void k_moment_stepk(Ell h, Sweep sw, Lat2 l
 // row t - s.  Each level keeps its last three rows in registers, so rows are
 // computed once per level except the K - 1 boundary rows at each end of the
 // strip, instead of once per tile as in k_moment_stepk.  phi_n and phi_{n-1}
-// are loaded kDs rows ahead and the per-row terms (pattern id, on-site term,
-// phi_L) kRingP - 1 - K rows ahead, in rings of kRingP rows; the loop is
-// unrolled by kRingP so every ring index is a compile-time constant.
-constexpr int kRingP = 6;
+// are loaded kDs rows ahead into rings of kStateRing rows, the per-row terms
+// (pattern id, on-site term, phi_L) kRowRing - 1 - K rows ahead into rings of
+// kRowRing rows; the loop is unrolled by kRowRing (a multiple of kStateRing
+// and of 3) so every ring index is a compile-time constant.
+constexpr int kStateRing = 6;
+constexpr int kRowRing = 12;
 constexpr int kDs = 3;
 
 template <typename V, bool ONSF, bool DBL, int K>
@@ -1100,9 +1102,9 @@ __global__ __launch_bounds__(kBlock) void k_moment_march(Ell h, Sweep sw, Lat2 l
                                                          double2 *__restrict__ partial,
                                                          int slot) {
     constexpr int TC = kWave - 2 * K;                  // columns per strip
-    constexpr int P = kRingP, DS = kDs, DR = kRingP - 1 - K;
+    constexpr int P = kRowRing, PS = kStateRing, DS = kDs, DR = kRowRing - 1 - K;
     constexpr int NA = DBL ? 2 * K : K;
-    static_assert(DR >= 1 && DS < P, "ring too short for K");
+    static_assert(DR >= 1 && DS + 3 <= PS && P % PS == 0 && PS % 3 == 0, "ring sizes");
     __shared__ uint32_t lflag[kMaxPatterns];
     for (int j = threadIdx.x; j < h.npat; j += kBlock) lflag[j] = lat.flags[j];
     __syncthreads();
@@ -1129,7 +1131,7 @@ __global__ __launch_bounds__(kBlock) void k_moment_march(Ell h, Sweep sw, Lat2 l
         const int Jt = min(J, ny - j0), T = Jt + 2 * K;
         const uint32_t ov = (uint32_t)gi * sizeof(V), rb = (uint32_t)nx * sizeof(V);
         auto base = [&](int rho) { return (int64_t)wrap_index(j0 - K + rho, ny) * nx; };
-        double2 X0[P], Xm[P], LL[P];                   // phi_n, phi_{n-1}, phi_L rings
+        double2 X0[PS], Xm[PS], LL[P];                 // phi_n, phi_{n-1}, phi_L rings
         int PI[P];                                     // pattern ids
         float OF[P];
         double OD[P];
@@ -1154,7 +1156,7 @@ __global__ __launch_bounds__(kBlock) void k_moment_march(Ell h, Sweep sw, Lat2 l
         };
 #pragma unroll
         for (int r = 0; r < DS; ++r)
-            if (r < T) load_state(r, r);
+            if (r < T) load_state(r, r % PS);
 #pragma unroll
         for (int r = 0; r < DR; ++r)
             if (r < T) load_row(r, r);
@@ -1163,7 +1165,7 @@ __global__ __launch_bounds__(kBlock) void k_moment_march(Ell h, Sweep sw, Lat2 l
             for (int u = 0; u < P; ++u) {
                 const int tt = t0 + u;
                 if (tt >= T) break;
-                if (tt + DS < T) load_state(tt + DS, (u + DS) % P);
+                if (tt + DS < T) load_state(tt + DS, (u + DS) % PS);
                 if (tt + DR < T) load_row(tt + DR, (u + DR) % P);
 #pragma unroll
                 for (int s = 1; s <= K; ++s) {
@@ -1171,20 +1173,21 @@ __global__ __launch_bounds__(kBlock) void k_moment_march(Ell h, Sweep sw, Lat2 l
                     if (rho < s) continue;
                     // ring slots of rows rho - 1, rho, rho + 1 (rho = t0 + u - s)
                     const int qp = ((u - s) % P + P) % P;               // per-row ring, row rho
+                    const int qs = ((u - s) % PS + PS) % PS;            // state rings, row rho
                     const int q3 = ((u - s) % 3 + 3) % 3;               // level rings, row rho
                     const int q3m = (q3 + 2) % 3, q3p = (q3 + 1) % 3;   // rows rho - 1, rho + 1
-                    const int qm = (qp + P - 1) % P, qq = (qp + 1) % P;
+                    const int qm = (qs + PS - 1) % PS, qq = (qs + 1) % PS;
                     double2 xm1, x0, xp1, old;
                     if (s == 1) {
                         xm1 = X0[qm];
-                        x0 = X0[qp];
+                        x0 = X0[qs];
                         xp1 = X0[qq];
-                        old = Xm[qp];
+                        old = Xm[qs];
                     } else {
                         xm1 = LV[s - 2][q3m];
                         x0 = LV[s - 2][q3];
                         xp1 = LV[s - 2][q3p];
-                        old = s == 2 ? X0[qp] : LV[s - 3 < 0 ? 0 : s - 3][q3];
+                        old = s == 2 ? X0[qs] : LV[s - 3 < 0 ? 0 : s - 3][q3];
                     }
                     const double o = ONSF ? (double)OF[qp] * inv_es : OD[qp];
                     const uint32_t f = lflag[PI[qp]];

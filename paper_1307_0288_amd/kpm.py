@@ -37,7 +37,8 @@ ABI_SYMBOLS = ("kpm_build_graphene", "kpm_validate", "kpm_system_create", "kpm_s
                "kpm_mlp_get_params", "kpm_mlp_forward", "kpm_mlp_gradients",
                "kpm_mlp_train_step", "kpm_learned_features", "kpm_learned_targets",
                "kpm_xu_state", "kpm_vac_continue", "kpm_msd_continue",
-               "kpm_set_launch", "kpm_get_launch",
+               "kpm_set_launch", "kpm_get_launch", "kpm_set_launch_doubled",
+               "kpm_get_launch_doubled",
                "kpm_autotune", "kpm_set_graphs", "kpm_set_timing", "kpm_get_stats",
                "kpm_reset_stats",
                "kpm_last_error", "kpm_version")
@@ -132,6 +133,8 @@ def _signatures():
                              C.c_int, C.c_int, dp],
         "kpm_set_launch": [vp, C.c_int, C.POINTER(Launch)],
         "kpm_get_launch": [vp, C.c_int, C.POINTER(Launch)],
+        "kpm_set_launch_doubled": [vp, C.c_int, C.POINTER(Launch)],
+        "kpm_get_launch_doubled": [vp, C.c_int, C.POINTER(Launch)],
         "kpm_autotune": [vp, C.c_int, vp, C.c_int, C.POINTER(Launch)],
         "kpm_set_graphs": [vp, C.c_int],
         "kpm_set_timing": [vp, C.c_int],
@@ -587,6 +590,21 @@ def kpm_set_launch(sys: System, n_vec: int, groups_per_cu: int, ilp: int, stream
 def kpm_get_launch(sys: System, n_vec: int) -> dict:
     out = Launch()
     _check(lib().kpm_get_launch(sys.handle, n_vec, C.byref(out)))
+    return out.as_dict()
+
+
+def kpm_set_launch_doubled(sys: System, n_vec: int, groups_per_cu: int, ilp: int,
+                           streaming: int = 0, compact: int = 1, tiled: int = 0, steps: int = 1):
+    """Launch shape of doubling-form moment sets (kpm_set_launch sets both forms)."""
+    _check(lib().kpm_set_launch_doubled(sys.handle, n_vec,
+                                        C.byref(Launch(groups_per_cu, ilp, int(bool(streaming)),
+                                                       int(bool(compact)), int(tiled),
+                                                       int(steps)))))
+
+
+def kpm_get_launch_doubled(sys: System, n_vec: int) -> dict:
+    out = Launch()
+    _check(lib().kpm_get_launch_doubled(sys.handle, n_vec, C.byref(out)))
     return out.as_dict()
 
 

@@ -70,11 +70,18 @@ def kernel_sha(launch: dict | None = None) -> str:
         t = f.read()
     head = t[:t.index("// Loads and stores of the propagator kernels")]
     if launch is not None and multi_step(launch):
-        a = t.index("// ---------------------------------------------------------------- multi-step sweeps")
-        b = t.index("// ---------------------------------------------------------------- launchers")
+        # LDS tiles | register tiles (and the helpers the marching form uses) |
+        # marching strips: each form hashes its own section(s)
+        lds = t.index("// ---------------------------------------------------------------- multi-step sweeps")
+        reg = t.index("// Register-tiled sweep of K = 2, 3 or 4")
+        march = t.index("// Marching form of the register-tiled K-step sweep")
+        end = t.index("// ---------------------------------------------------------------- launchers")
         c = t.index("template <typename V>\nvoid launch_moment_multi(")
         d = t.index("#define KPM_INSTANTIATE(V)")
-        return hashlib.sha256((head + t[a:b] + t[c:d]).encode()).hexdigest()[:16]
+        k, tiled = launch["steps"], launch["tiled"]
+        body = (t[lds:reg] if (k == 2 and tiled == 0) else
+                t[reg:end] if tiled >= 3 else t[reg:march])
+        return hashlib.sha256((head + body + t[c:d]).encode()).hexdigest()[:16]
     a = t.index("template <typename V, int ILP, bool NT, bool DBL>\nstatic void launch_step_shape(")
     b = t.index("template <typename V>\nvoid launch_evolve_step(")
     return hashlib.sha256((head + t[a:b]).encode()).hexdigest()[:16]

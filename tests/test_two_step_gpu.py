@@ -192,3 +192,25 @@ def test_autotune_considers_two_steps():
     got = kp.kpm_moments(sysg, d, d, 50)[0]
     ref = oracle.moments(oracle_lattice(c), c["e_scale"], phi[:, 0], phi[:, 0], 50)
     assert rel_err(got, ref, np.vdot(phi, phi).real) < 1e-10
+
+
+def test_doubling_form_has_its_own_shape():
+    """kpm_set_launch sets both forms, kpm_set_launch_doubled only the doubling
+    one; the autotuner picks each form's shape; moments stay correct."""
+    _need_gpu()
+    c = recipe("sheet", 200, 40, w=1.0, vac=0.02, seed=19)
+    sysg = gpu_system(c)
+    kp.kpm_set_launch(sysg, 1, 2, 1, 0, 1, 2, 4)
+    kp.kpm_set_launch_doubled(sysg, 1, 3, 1, 0, 1, 3, 3)
+    assert kp.kpm_get_launch(sysg, 1)["tiled"] == 2
+    assert kp.kpm_get_launch_doubled(sysg, 1) == dict(groups_per_cu=3, ilp=1, streaming=0,
+                                                      compact=1, tiled=3, steps=3)
+    phi = phases(c, 1, 5100)
+    d = sysg.upload(phi)
+    ref = oracle.moments(oracle_lattice(c), c["e_scale"], phi[:, 0], phi[:, 0], 81)
+    scale = np.vdot(phi, phi).real
+    assert rel_err(kp.kpm_moments_doubled(sysg, d, 81)[0], ref, scale) < 1e-10
+    assert rel_err(kp.kpm_moments(sysg, d, d, 81)[0], ref, scale) < 1e-10
+    kp.kpm_autotune(sysg, d, 8)
+    assert kp.kpm_get_launch_doubled(sysg, 1)["steps"] in (1, 2, 3, 4)
+    assert rel_err(kp.kpm_moments_doubled(sysg, d, 81)[0], ref, scale) < 1e-10
