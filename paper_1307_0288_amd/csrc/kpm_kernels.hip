@@ -999,8 +999,11 @@ __global__ __launch_bounds__(kBlock) void k_moment_stepk(Ell h, Sweep sw, Lat2 l
 #pragma unroll
     for (int k = 0; k < NA; ++k) acc[k] = make_double2(0.0, 0.0);
     for (int b = b0 + wloc; b < b1; b += wn) {
-        const int strip = b / nrb;
-        const int j0 = (b - strip * nrb) * TJ, c0 = strip * TC;
+        // tiles across the strips first: the column halos a tile shares with
+        // its horizontal neighbours, like the chain halos it shares with its
+        // vertical ones, are then read by wavefronts in flight together
+        const int strip = b % nst;
+        const int j0 = (b / nst) * TJ, c0 = strip * TC;
         const int gi = wrap_index(c0 - K + lane, nx);
         const bool colok = lane >= K && lane < K + TC && c0 - K + lane < nx;
         const int H = min(TJ, ny - j0);
@@ -1124,8 +1127,8 @@ __global__ __launch_bounds__(kBlock) void k_moment_march(Ell h, Sweep sw, Lat2 l
 #pragma unroll
     for (int k = 0; k < NA; ++k) acc[k] = make_double2(0.0, 0.0);
     for (int b = b0 + wloc; b < b1; b += wn) {
-        const int strip = b / nsg;
-        const int j0 = (b - strip * nsg) * J, c0 = strip * TC;
+        const int strip = b % nst;                     // across the strips first
+        const int j0 = (b / nst) * J, c0 = strip * TC;
         const int gi = wrap_index(c0 - K + lane, nx);
         const bool colok = lane >= K && lane < K + TC && c0 - K + lane < nx;
         const int Jt = min(J, ny - j0), T = Jt + 2 * K;

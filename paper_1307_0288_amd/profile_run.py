@@ -88,19 +88,21 @@ def kernel_sha(launch: dict | None = None) -> str:
 
 
 def measured_traffic(path: str, step_rows: int, launch: dict):
-    """HBM bytes per moment-step launch from a committed counter summary, or
-    None when it is absent or was taken on another kernel version, size or
-    launch shape."""
+    """HBM bytes per moment-step launch from a committed counter summary (one
+    record, or {"records": [...]} for several launch shapes), or None when
+    no record matches this kernel version, size and launch shape."""
     try:
         with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    stored = dict({"steps": 1}, **t.get("launch_shape", {}))
-    if t.get("kernel_sha") != kernel_sha(launch) or t.get("step_rows") != step_rows \
-            or stored != dict({"steps": 1}, **launch):
-        return None
-    return t.get("bytes_per_launch")
+    sha = kernel_sha(launch)
+    for r in t.get("records", [t]):
+        stored = dict({"steps": 1}, **r.get("launch_shape", {}))
+        if r.get("kernel_sha") == sha and r.get("step_rows") == step_rows \
+                and stored == dict({"steps": 1}, **launch):
+            return r.get("bytes_per_launch")
+    return None
 
 
 def _read_counter(d: str):
