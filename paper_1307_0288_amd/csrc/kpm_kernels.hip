@@ -902,7 +902,7 @@ __global__ __launch_bounds__(kBlock) void k_moment_step2(Ell h, Sweep sw, Lat2 l
 // the next chain).  A wavefront takes a tile of TJ chains x (kWave - 2K)
 // columns on its own: lane l holds column c0 - K + l of every row, so a row's
 // vertical neighbours sit in the lane's own registers and its horizontal ones
-// in lanes l -+ 1 (cross-lane moves).  phi_n is loaded on TJ + 2K chains and
+// in lanes l -+ 1 (DPP wavefront shifts).  phi_n is loaded on TJ + 2K chains and
 // step s computes phi_{n+s} on TJ + 2 (K - s) of them, valid in lanes
 // s .. kWave - 1 - s, so after K steps the tile (lanes K .. kWave - 1 - K)
 // holds phi_{n+K}.  Only phi_{n+K-1} (out1) and phi_{n+K} (out2) are written,
@@ -913,11 +913,22 @@ __global__ __launch_bounds__(kBlock) void k_moment_step2(Ell h, Sweep sw, Lat2 l
 // k_moment_step, in its slot order.
 // Partials: non-DBL slot + s - 1 = <L|phi_{n+s}>, s = 1 .. K; DBL slots
 // slot + 2 (s - 1) and + 1 = <phi_{n+s-1}|phi_{n+s-1}>, <phi_{n+s-1}|phi_{n+s}>.
+// Cross-lane moves by one lane as DPP wavefront shifts (one VALU move per
+// 32-bit half, no LDS): wave_shr:1 gives lane l the value of lane l - 1,
+// wave_shl:1 that of lane l + 1; the end lane keeps its own value.
+constexpr int kDppWaveShl1 = 0x130;
+constexpr int kDppWaveShr1 = 0x138;
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false),
+                            __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false));
+}
 __device__ __forceinline__ double2 lane_prev(double2 v) {     // value of lane l - 1
-    return make_double2(__shfl_up(v.x, 1, kWave), __shfl_up(v.y, 1, kWave));
+    return make_double2(dpp_move<kDppWaveShr1>(v.x), dpp_move<kDppWaveShr1>(v.y));
 }
 __device__ __forceinline__ double2 lane_next(double2 v) {     // value of lane l + 1
-    return make_double2(__shfl_down(v.x, 1, kWave), __shfl_down(v.y, 1, kWave));
+    return make_double2(dpp_move<kDppWaveShl1>(v.x), dpp_move<kDppWaveShl1>(v.y));
 }
 
 // 2 H~ x - q at a row with flags f: own value x, horizontal neighbours from
