@@ -83,7 +83,8 @@ bool valid_launch(const kpm_launch &l) {
     return l.groups_per_cu >= 1 && l.groups_per_cu <= 32 &&
            (l.ilp == 1 || l.ilp == 2 || l.ilp == 4) && (l.streaming == 0 || l.streaming == 1) &&
            (l.compact == 0 || l.compact == 1) && l.tiled >= 0 &&
-           l.tiled <= (l.steps > 1 ? 5 : 3) && l.steps >= 1 && l.steps <= 4;
+           l.tiled <= (l.steps > 1 ? 5 : 3) && l.steps >= 1 &&
+           l.steps <= (l.tiled >= 3 ? 6 : 4);
 }
 
 // Tile width (rows) of the tiled traversal for 2^vshift vectors per row: a
@@ -193,12 +194,13 @@ kpm_launch default_launch(int vshift, kpm_precision prec) {
     // row order, beyond an XCD's L2
     l.tiled = vshift >= 3 ? 1 : 0;
     l.steps = 1;
-    // one vector: four recursion steps per pass in register tiles of 4 chains
-    // where the sample allows (measured fastest on paper-scale sheets);
-    // elsewhere single steps in row order
+    // one vector: five recursion steps per pass in marching strips of 16
+    // chains where the sample allows (measured fastest on paper-scale sheets,
+    // with 2 groups per CU); elsewhere single steps in row order
     if (vshift == 0) {
-        l.tiled = 2;
-        l.steps = 4;
+        l.groups_per_cu = 2;
+        l.tiled = 3;
+        l.steps = 5;
     }
     return l;
 }
@@ -1099,14 +1101,17 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
         if (ks > 1) KPM_TRY(sys->ensure_xbuf(vs));
         KPM_TRY(sys->ensure_partial(2 * ks, sw.nwg, 1 << vs));
         const kpm::Lat2 lat = sys->lat2(l, ks);
+        // whole passes only (a long moment set has no tail to speak of), at
+        // least one
+        const int steps = ks > 1 ? std::max(1, reps / ks) * ks : reps;
         float best = 1e30f;
         for (int round = 0; round < 3; ++round) {
             KPM_HIP(hipMemcpyAsync(a, phi, bytes, hipMemcpyDeviceToDevice, s));
             KPM_HIP(hipMemcpyAsync(b, phi, bytes, hipMemcpyDeviceToDevice, s));
             V *p0 = b, *p1 = a, *o1 = (V *)sys->xbuf[0], *o2 = (V *)sys->xbuf[1];
             KPM_HIP(hipEventRecord(e0, s));
-            for (int k = 0; k < reps; ++k) {
-                if (ks > 1 && k + ks <= reps) {
+            for (int k = 0; k < steps; ++k) {
+                if (ks > 1 && k + ks <= steps) {
                     kpm::launch_moment_multi<V>(h, sw, lat, p1, p0, o1, o2, phi, sys->partial, 0,
                                                 dbl, s);
                     std::swap(p0, o1);
@@ -1126,7 +1131,7 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
             KPM_HIP(hipEventElapsedTime(&ms, e0, e1));
             best = std::min(best, ms);
         }
-        *out_ms = best;
+        *out_ms = best * (float)reps / (float)steps;     // per reps recursion steps
         return KPM_OK;
     };
     // Candidates: single steps (grid x ILP x streaming x neighbour form x
@@ -1154,7 +1159,7 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
                 for (int tiled : {1, 2})
                     for (int g : {1, 2, 3, 4, 6, 8})
                         cand.push_back(kpm_launch{g, 1, 0, 1, tiled, ksteps});
-            for (int ksteps : {3, 4})
+            for (int ksteps : {3, 4, 5, 6})
                 for (int tiled : {3, 4})
                     for (int g : {2, 3, 4}) cand.push_back(kpm_launch{g, 1, 0, 1, tiled, ksteps});
         }

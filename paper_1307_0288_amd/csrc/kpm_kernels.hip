@@ -1091,7 +1091,8 @@ __global__ __launch_bounds__(kBlock) void k_moment_stepk(Ell h, Sweep sw, Lat2 l
     for (int k = 0; k < NA; ++k) block_sum(acc[k], 0, partial + (int64_t)(slot + k) * nw + blockIdx.x);
 }
 
-// Marching form of the register-tiled K-step sweep: a wavefront takes a strip
+// Marching form of the register-tiled K-step sweep (K = 2 .. 6; each level
+// costs only its three-row ring of registers): a wavefront takes a strip
 // of (kWave - 2K) columns (lanes as in k_moment_stepk) and J chains, and walks
 // down the chains.  Iteration t brings in chain row t of phi_n (window rows
 // j0 - K .. j0 + J + K - 1) and computes level s = 1 .. K (phi_{n+s}) on row
@@ -1385,7 +1386,9 @@ void launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
 #define KPM_REG(ONSF_, DBL_)                                                                  \
     do {                                                                                      \
         if (lat.reg == 2) {                                                                   \
-            if (lat.k == 4) KPM_MARCHK(ONSF_, DBL_, 4);                                       \
+            if (lat.k == 6) KPM_MARCHK(ONSF_, DBL_, 6);                                       \
+            else if (lat.k == 5) KPM_MARCHK(ONSF_, DBL_, 5);                                  \
+            else if (lat.k == 4) KPM_MARCHK(ONSF_, DBL_, 4);                                  \
             else if (lat.k == 3) KPM_MARCHK(ONSF_, DBL_, 3);                                  \
             else KPM_MARCHK(ONSF_, DBL_, 2);                                                  \
         } else if (lat.tj == 4) {                                                             \
