@@ -443,10 +443,12 @@ kpm_status kpm_xu_state(kpm_system *sys, int n_vec, const void *phi, int n_steps
  * the order of kpm_build_graphene (and there are at least 16 chains), in
  * register tiles of one wavefront each, 8 chains (tiled = 1) or 4 (tiled =
  * 2) by 64 - 2 steps columns, or in strips of 64 - 2 steps columns that one
- * wavefront walks chain by chain, 16, 32 or 64 chains long (tiled = 3, 4, 5).
+ * wavefront walks chain by chain, 16 or 32 chains long (tiled = 3, 4) or as
+ * long as one strip per wavefront of the grid allows (8 .. 64 chains,
+ * tiled = 5).
  * 3 and 4 steps need the register forms (else 2 steps apply), 5 and 6 steps
  * the strips.  Under steps > 1 any single steps keep row order.  Default for
- * one vector: groups_per_cu 2, steps 5, tiled 3; for more vectors single
+ * one vector: groups_per_cu 2, steps 5, tiled 5; for more vectors single
  * steps.  At a fixed grid size, traversal and step count the moments are
  * bit-identical for every ilp, streaming and compact choice; the recursion
  * states are bit-identical for every shape, and the shape changes only the
@@ -478,7 +480,7 @@ kpm_status kpm_get_launch_doubled(kpm_system *sys, int n_vec, kpm_launch *out);
  * steps = 2 in LDS tiles with groups_per_cu in {2, 3, 4, 6} x streaming in
  * {0, 1}, steps in {2, 3, 4} in register tiles (tiled in {1, 2}) with
  * groups_per_cu in {1, 2, 3, 4, 6, 8}, and steps in {3, 4, 5, 6} in marching
- * strips (tiled in {3, 4}) with groups_per_cu in {2, 3, 4}) on the device state
+ * strips (tiled in {3, 4, 5}) with groups_per_cu in {2, 3, 4}) on the device state
  * `phi` ([n_sites][n_vec], read only; only system scratch is written), for
  * the direct and, separately, the doubling form, keeps the fastest of each
  * for this n_vec and returns the direct form's in *best (may be NULL).

@@ -194,12 +194,13 @@ kpm_launch default_launch(int vshift, kpm_precision prec) {
     // row order, beyond an XCD's L2
     l.tiled = vshift >= 3 ? 1 : 0;
     l.steps = 1;
-    // one vector: five recursion steps per pass in marching strips of 16
-    // chains where the sample allows (measured fastest on paper-scale sheets,
-    // with 2 groups per CU); elsewhere single steps in row order
+    // one vector: five recursion steps per pass in marching strips, one per
+    // wavefront of the grid, where the sample allows (measured fastest on
+    // paper-scale sheets, with 2 groups per CU); elsewhere single steps in
+    // row order
     if (vshift == 0) {
         l.groups_per_cu = 2;
-        l.tiled = 3;
+        l.tiled = 5;
         l.steps = 5;
     }
     return l;
@@ -335,10 +336,18 @@ struct kpm_system {
     // Multi-step tiles: two steps in LDS tiles of 16 chains x kTileCols
     // columns (tiled = 0, or no graphene slot order); register tiles of 8
     // chains (tiled = 1, or tiled = 0 with 3 or 4 steps) or 4 (tiled = 2);
-    // marching strips of 16, 32 or 64 chains (tiled = 3, 4, 5).
-    kpm::Lat2 lat2(const kpm_launch &l, int k) const {
+    // marching strips of 16 or 32 chains (tiled = 3, 4), or as long as one
+    // strip per wavefront of the grid allows (tiled = 5).
+    kpm::Lat2 lat2(const kpm_launch &l, int k, int nwg) const {
         const int reg = !d_flags ? 0 : (l.tiled >= 3 ? 2 : ((l.tiled >= 1 || k > 2) ? 1 : 0));
-        const int tj = reg == 2 ? 16 << (l.tiled - 3) : (reg == 1 ? (l.tiled == 2 ? 4 : 8) : 16);
+        int tj = reg == 2 ? 16 << (l.tiled - 3) : (reg == 1 ? (l.tiled == 2 ? 4 : 8) : 16);
+        if (reg == 2 && l.tiled == 5) {
+            // strips just filling the grid's wavefronts once: as long as that
+            // allows (fewer reloaded boundary chains), 8 .. 64 chains
+            const int nst = (l2nx + kpm::kWave - 2 * k - 1) / (kpm::kWave - 2 * k);
+            const int per_col = std::max(1, nwg * (kpm::kBlock / kpm::kWave) / nst);
+            tj = std::max(8, std::min(64, (l2ny + per_col - 1) / per_col));
+        }
         return kpm::Lat2{l2nx, l2ny, k, reg, tj, (l2nx + kpm::kTileCols - 1) / kpm::kTileCols,
                          (l2ny + tj - 1) / tj, d_code, d_flags};
     }
@@ -668,7 +677,7 @@ kpm_status enqueue_moments(kpm_system *sys, const kpm::Sweep &sw, int ring, hipS
     const kpm_launch &l = sys->shape(sw.vshift, dbl);
     const kpm::Ell h = sys->ell_for(l);
     const int k = sys->multi_steps(sw.vshift, l);
-    const kpm::Lat2 lat = sys->lat2(l, k);
+    const kpm::Lat2 lat = sys->lat2(l, k, sw.nwg);
     V *pool[4] = {a_buf, b_buf, (V *)sys->xbuf[0], (V *)sys->xbuf[1]};
     const int npool = k > 1 ? 4 : 2;
     // a pool state that is none of x, y, z
@@ -1100,7 +1109,7 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
         const int ks = sys->multi_steps(vs, l);
         if (ks > 1) KPM_TRY(sys->ensure_xbuf(vs));
         KPM_TRY(sys->ensure_partial(2 * ks, sw.nwg, 1 << vs));
-        const kpm::Lat2 lat = sys->lat2(l, ks);
+        const kpm::Lat2 lat = sys->lat2(l, ks, sw.nwg);
         // whole passes only (a long moment set has no tail to speak of), at
         // least one
         const int steps = ks > 1 ? std::max(1, reps / ks) * ks : reps;
@@ -1160,7 +1169,7 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
                     for (int g : {1, 2, 3, 4, 6, 8})
                         cand.push_back(kpm_launch{g, 1, 0, 1, tiled, ksteps});
             for (int ksteps : {3, 4, 5, 6})
-                for (int tiled : {3, 4})
+                for (int tiled : {3, 4, 5})
                     for (int g : {2, 3, 4}) cand.push_back(kpm_launch{g, 1, 0, 1, tiled, ksteps});
         }
     }

@@ -42,7 +42,7 @@ def _pair(c, precision="fp64", tiled=0, steps=2):
 
 
 MULTI = [(2, 0), (2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (4, 2), (2, 3), (3, 4), (4, 3), (4, 4),
-         (4, 5), (5, 3), (6, 4)]
+         (4, 5), (5, 3), (6, 4), (5, 5), (6, 5)]
 
 
 @pytest.mark.parametrize("geometry,nx,ny", SHAPES)
