@@ -432,27 +432,29 @@ kpm_status kpm_xu_state(kpm_system *sys, int n_vec, const void *phi, int n_steps
  * chain length found from the most common neighbour offset beyond 1) so that a
  * row's vertical neighbour is reused from cache even when a row carries many
  * vectors; tiled = 0, and samples without such a chain structure or with
- * chains shorter than two tiles, keep row order.  steps = 2 .. 6 advances
+ * chains shorter than two tiles, keep row order.  steps = 2 .. 8 advances
  * the recursion that many steps per pass: from phi_n and phi_{n-1} a pass
  * writes only the last two states, so each row's states cross HBM once per
  * pass instead of once per step.  It applies to one vector per row on a
  * single-sample lattice in the compact width-3 form whose every bond joins
  * rows at most one column and one chain apart (chains of at least 68 rows, at
- * least 4 chains); other calls take single steps.  Two steps run in tiles of
+ * least 24 chains); other calls take single steps.  Two steps run in tiles of
  * 16 chains x 64 columns staged in LDS (tiled = 0) or, where the slots follow
- * the order of kpm_build_graphene (and there are at least 16 chains), in
- * register tiles of one wavefront each, 8 chains (tiled = 1) or 4 (tiled =
- * 2) by 64 - 2 steps columns, or in strips of 64 - 2 steps columns that one
- * wavefront walks chain by chain, 16 or 32 chains long (tiled = 3, 4) or as
- * long as one strip per wavefront of the grid allows (8 .. 64 chains,
- * tiled = 5).
- * 3 and 4 steps need the register forms (else 2 steps apply), 5 and 6 steps
+ * the order of kpm_build_graphene, in register tiles of one wavefront each, 8
+ * chains (tiled = 1) or 4 (tiled = 2) by 64 - 2 steps columns, or in strips
+ * of 64 - 2 steps columns that one wavefront walks chain by chain, 16 or 32
+ * chains long (tiled = 3, 4) or of the length (8 .. 64 chains) that lets the
+ * grid's wavefronts finish all strips in the fewest passes of 12 rows
+ * (tiled = 5).
+ * 3 and 4 steps need the register forms (else 2 steps apply), 5 .. 8 steps
  * the strips.  Under steps > 1 any single steps keep row order.  Default for
  * one vector: groups_per_cu 2, steps 5, tiled 5; for more vectors single
  * steps.  At a fixed grid size, traversal and step count the moments are
  * bit-identical for every ilp, streaming and compact choice; the recursion
- * states are bit-identical for every shape, and the shape changes only the
- * order of the inner-product partial sums.
+ * states are bit-identical for every shape (up to the sign of zero), and the
+ * shape changes only the order of the inner-product partial sums (in the
+ * doubling form the strips accumulate only the real parts, the moments of
+ * phi_L = phi_R being real).
  */
 typedef struct {
     int32_t groups_per_cu;
@@ -479,8 +481,9 @@ kpm_status kpm_get_launch_doubled(kpm_system *sys, int n_vec, kpm_launch *out);
  * for lattices with long chains; plus, where the multi-step sweeps apply,
  * steps = 2 in LDS tiles with groups_per_cu in {2, 3, 4, 6} x streaming in
  * {0, 1}, steps in {2, 3, 4} in register tiles (tiled in {1, 2}) with
- * groups_per_cu in {1, 2, 3, 4, 6, 8}, and steps in {3, 4, 5, 6} in marching
- * strips (tiled in {3, 4, 5}) with groups_per_cu in {2, 3, 4}) on the device state
+ * groups_per_cu in {1, 2, 3, 4, 6, 8}, and steps in {3, .., 8} in marching
+ * strips (tiled 5 with groups_per_cu in {2, 3, 4}; up to 6 steps also tiled
+ * in {3, 4} with groups_per_cu 2)) on the device state
  * `phi` ([n_sites][n_vec], read only; only system scratch is written), for
  * the direct and, separately, the doubling form, keeps the fastest of each
  * for this n_vec and returns the direct form's in *best (may be NULL).

@@ -84,7 +84,7 @@ bool valid_launch(const kpm_launch &l) {
            (l.ilp == 1 || l.ilp == 2 || l.ilp == 4) && (l.streaming == 0 || l.streaming == 1) &&
            (l.compact == 0 || l.compact == 1) && l.tiled >= 0 &&
            l.tiled <= (l.steps > 1 ? 5 : 3) && l.steps >= 1 &&
-           l.steps <= (l.tiled >= 3 ? 6 : 4);
+           l.steps <= (l.tiled >= 3 ? 8 : 4);
 }
 
 // Tile width (rows) of the tiled traversal for 2^vshift vectors per row: a
@@ -329,7 +329,8 @@ struct kpm_system {
     // chain lattice, compact form; 3 and 4 steps need the graphene slot order,
     // else 2), 1 otherwise.
     int multi_steps(int vshift, const kpm_launch &l) const {
-        if (!d_code || vshift != 0 || l.steps < 2 || !l.compact) return 1;
+        if (!d_code || vshift != 0 || l.steps < 2 || !l.compact || l2ny < kpm::kMinChains)
+            return 1;
         return d_flags ? l.steps : 2;
     }
 
@@ -342,11 +343,22 @@ struct kpm_system {
         const int reg = !d_flags ? 0 : (l.tiled >= 3 ? 2 : ((l.tiled >= 1 || k > 2) ? 1 : 0));
         int tj = reg == 2 ? 16 << (l.tiled - 3) : (reg == 1 ? (l.tiled == 2 ? 4 : 8) : 16);
         if (reg == 2 && l.tiled == 5) {
-            // strips just filling the grid's wavefronts once: as long as that
-            // allows (fewer reloaded boundary chains), 8 .. 64 chains
-            const int nst = (l2nx + kpm::kWave - 2 * k - 1) / (kpm::kWave - 2 * k);
-            const int per_col = std::max(1, nwg * (kpm::kBlock / kpm::kWave) / nst);
-            tj = std::max(8, std::min(64, (l2ny + per_col - 1) / per_col));
+            // strips sized for the grid: the fewest loop passes of the wavefront
+            // with the most strips (passes of kMarchRows rows, tj + 2k rows per
+            // strip), then the longest strips (fewer reloaded boundary chains);
+            // 8 .. 64 chains
+            const int64_t nst = (l2nx + kpm::kWave - 2 * k - 1) / (kpm::kWave - 2 * k);
+            const int64_t waves = (int64_t)nwg * (kpm::kBlock / kpm::kWave);
+            int64_t best = -1;
+            for (int j = 8; j <= 64; ++j) {
+                const int64_t strips = nst * ((l2ny + j - 1) / j);
+                const int64_t passes = (j + 2 * k + kpm::kMarchRows - 1) / kpm::kMarchRows;
+                const int64_t cost = (strips + waves - 1) / waves * passes;
+                if (best < 0 || cost <= best) {
+                    best = cost;
+                    tj = j;
+                }
+            }
         }
         return kpm::Lat2{l2nx, l2ny, k, reg, tj, (l2nx + kpm::kTileCols - 1) / kpm::kTileCols,
                          (l2ny + tj - 1) / tj, d_code, d_flags};
@@ -1145,9 +1157,9 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
     };
     // Candidates: single steps (grid x ILP x streaming x neighbour form x
     // traversal), then several recursion steps per pass on chain lattices
-    // with one vector: two steps in LDS tiles, and 2, 3 or 4 steps in register
-    // tiles of 8 or 4 chains or marching strips where the slots follow the
-    // graphene order.
+    // with one vector: two steps in LDS tiles, 2, 3 or 4 steps in register
+    // tiles of 8 or 4 chains and 3 .. 8 steps in marching strips where the
+    // slots follow the graphene order.
     std::vector<kpm_launch> cand;
     for (int g : groups)
         for (int q = 0; q < 6 * forms * tilings; ++q) {
@@ -1168,9 +1180,11 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
                 for (int tiled : {1, 2})
                     for (int g : {1, 2, 3, 4, 6, 8})
                         cand.push_back(kpm_launch{g, 1, 0, 1, tiled, ksteps});
-            for (int ksteps : {3, 4, 5, 6})
-                for (int tiled : {3, 4, 5})
-                    for (int g : {2, 3, 4}) cand.push_back(kpm_launch{g, 1, 0, 1, tiled, ksteps});
+            for (int ksteps : {3, 4, 5, 6, 7, 8}) {
+                for (int g : {2, 3, 4}) cand.push_back(kpm_launch{g, 1, 0, 1, 5, ksteps});
+                if (ksteps <= 6)
+                    for (int tiled : {3, 4}) cand.push_back(kpm_launch{2, 1, 0, 1, tiled, ksteps});
+            }
         }
     }
     // Each form (direct, doubling) keeps its current shape as the incumbent; a
@@ -1248,7 +1262,10 @@ kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int devi
     if (const char *env = std::getenv("KPM_TILED"))
         for (auto &l : sys->launch) l.tiled = std::max(0, std::min(3, atoi(env)));
     if (const char *env = std::getenv("KPM_STEPS"))
-        for (auto &l : sys->launch) l.steps = std::max(1, std::min(4, atoi(env)));
+        for (auto &l : sys->launch) {
+            l.steps = std::max(1, std::min(8, atoi(env)));
+            if (l.steps > 4) l.tiled = 5;                // more than 4 steps need the strips
+        }
     for (int v = 0; v < 7; ++v) sys->launch_dbl[v] = sys->launch[v];
     if (const char *env = std::getenv("KPM_SCRATCH_LIMIT_MB"))
         sys->scratch_limit = (size_t)(std::max(0.0, atof(env)) * 1048576.0);

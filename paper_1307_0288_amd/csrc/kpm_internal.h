@@ -79,13 +79,18 @@ struct Sweep {
 // sweeps: row j * nx + i is column i of chain j, and slot k of every row with
 // pattern p holds the row dj chains and di columns away (each -1, 0 or 1,
 // periodic wrap), code[p] byte k = (dj + 1) * 3 + (di + 1), or 0xFF for an
-// empty slot.  k recursion steps per pass (2, 3 or 4).  reg = 0: the LDS form
+// empty slot.  k recursion steps per pass (2 .. 6).  reg = 0: the LDS form
 // (k = 2; tiles of tj = 16 chains x kTileCols columns, nti x ntj of them).
 // reg = 1: the register-tiled form (tiles of tj = 4 or 8 chains x (64 - 2k)
 // columns per wavefront) and reg = 2 its marching form (strips of tj chains
-// walked row by row), for samples whose slots follow the graphene builder's
-// order: flags[p] bit k = slot k filled, bit 3 = slot 2 joins the next chain.
+// walked row by row, kMarchRows rows per loop pass, so a strip of tj chains
+// costs tj + 2k rounded up to a multiple of kMarchRows), for samples whose
+// slots follow the graphene builder's order: flags[p] bit k = slot k filled,
+// bit 3 = slot 2 joins the next chain.  All multi-step forms need at least
+// kMinChains chains (their windows wrap around the sample at most once).
 constexpr int kTileCols = 64;
+constexpr int kMarchRows = 12;
+constexpr int kMinChains = 24;
 struct Lat2 {
     int32_t nx, ny;
     int32_t k, reg, tj;

@@ -915,14 +915,16 @@ __global__ __launch_bounds__(kBlock) void k_moment_step2(Ell h, Sweep sw, Lat2 l
 // slot + 2 (s - 1) and + 1 = <phi_{n+s-1}|phi_{n+s-1}>, <phi_{n+s-1}|phi_{n+s}>.
 // Cross-lane moves by one lane as DPP wavefront shifts (one VALU move per
 // 32-bit half, no LDS): wave_shr:1 gives lane l the value of lane l - 1,
-// wave_shl:1 that of lane l + 1; the end lane keeps its own value.
+// wave_shl:1 that of lane l + 1; the end lane, which has no source, reads 0
+// (bound_ctrl), so the move needs no copy of its old value.  End lanes are
+// halo lanes of every tile: their values are never used.
 constexpr int kDppWaveShl1 = 0x130;
 constexpr int kDppWaveShr1 = 0x138;
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v) {
     const int lo = __double2loint(v), hi = __double2hiint(v);
-    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false),
-                            __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false));
+    return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, true),
+                            __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, true));
 }
 __device__ __forceinline__ double2 lane_prev(double2 v) {     // value of lane l - 1
     return make_double2(dpp_move<kDppWaveShr1>(v.x), dpp_move<kDppWaveShr1>(v.y));
@@ -1091,7 +1093,7 @@ __global__ __launch_bounds__(kBlock) void k_moment_stepk(Ell h, Sweep sw, Lat2 l
     for (int k = 0; k < NA; ++k) block_sum(acc[k], 0, partial + (int64_t)(slot + k) * nw + blockIdx.x);
 }
 
-// Marching form of the register-tiled K-step sweep (K = 2 .. 6; each level
+// Marching form of the register-tiled K-step sweep (K = 2 .. 8; each level
 // costs only its three-row ring of registers): a wavefront takes a strip
 // of (kWave - 2K) columns (lanes as in k_moment_stepk) and J chains, and walks
 // down the chains.  Iteration t brings in chain row t of phi_n (window rows
@@ -1099,17 +1101,29 @@ __global__ __launch_bounds__(kBlock) void k_moment_stepk(Ell h, Sweep sw, Lat2 l
 // t - s, from level s - 1 on rows t - s - 1 .. t - s + 1 and level s - 2 on
 // row t - s.  Each level keeps its last three rows in registers, so rows are
 // computed once per level except the K - 1 boundary rows at each end of the
-// strip, instead of once per tile as in k_moment_stepk.  phi_n and phi_{n-1}
-// are loaded kDs rows ahead into rings of kStateRing rows, the per-row terms
-// (pattern id, on-site term, phi_L) kRowRing - 1 - K rows ahead into rings of
-// kRowRing rows; the loop is unrolled by kRowRing (a multiple of kStateRing
-// and of 3) so every ring index is a compile-time constant.
+// strip, instead of once per tile as in k_moment_stepk.  phi_n, phi_{n-1} and
+// phi_L are loaded kDs rows ahead, the pattern id and on-site term
+// kRowRing - 1 - K rows ahead; a row's slot weights (from a per-pattern table
+// in LDS: t or 0 for the previous column, the next column, the next chain and
+// the previous chain) and scaled on-site term are formed one iteration before
+// their first use.  The loop is unrolled by kRowRing (a multiple of
+// kStateRing and of 3) so every ring index is a compile-time constant.
+// The loop body has no branch: a strip runs whole passes of kRowRing rows,
+// rows past the window load as zeros (buffer resources of size 0), levels are
+// computed on every row (a value of a row outside a level's range is finite
+// and feeds only other such rows), and rows or lanes that own no output read
+// phi_L as 0 and store through an empty resource or an offset past the row.
+// Every load is then issued on every path and stays where it is written, so
+// the wait before each use leaves the later rows' loads in flight.  A zero
+// weight adds an exact zero, so each state value is the one k_moment_step
+// computes.
 constexpr int kStateRing = 6;
-constexpr int kRowRing = 12;
+constexpr int kRowRing = kMarchRows;
 constexpr int kDs = 3;
+constexpr uint32_t kOffNone = 0x80000000u;   // past the end of every row
 
 template <typename V, bool ONSF, bool DBL, int K>
-__global__ __launch_bounds__(kBlock) void k_moment_march(Ell h, Sweep sw, Lat2 lat,
+__global__ __launch_bounds__(kBlock, 2) void k_moment_march(Ell h, Sweep sw, Lat2 lat,
                                                          const V *p1, const V *p0,
                                                          V *__restrict__ out1,
                                                          V *__restrict__ out2,
@@ -1120,12 +1134,22 @@ __global__ __launch_bounds__(kBlock) void k_moment_march(Ell h, Sweep sw, Lat2 l
     constexpr int P = kRowRing, PS = kStateRing, DS = kDs, DR = kRowRing - 1 - K;
     constexpr int NA = DBL ? 2 * K : K;
     static_assert(DR >= 1 && DS + 3 <= PS && P % PS == 0 && PS % 3 == 0, "ring sizes");
-    __shared__ uint32_t lflag[kMaxPatterns];
-    for (int j = threadIdx.x; j < h.npat; j += kBlock) lflag[j] = lat.flags[j];
+    // up to 5 steps the row terms are formed once per row, ahead of their first
+    // use; with more levels their registers are needed for the level rings
+    static_assert(K >= 2 && K <= 8, "steps per pass");
+    constexpr bool kAhead = K <= 5;
+    const double t = sw.one.t, inv_es = sw.one.inv_es;
+    // per pattern: (previous column, next column), (next chain, previous chain)
+    __shared__ double2 lwt[2 * kMaxPatterns];
+    for (int j = threadIdx.x; j < h.npat; j += kBlock) {
+        const uint32_t f = lat.flags[j];
+        const double tv = (f & 4u) ? t : 0.0;
+        lwt[2 * j] = make_double2((f & 1u) ? t : 0.0, (f & 2u) ? t : 0.0);
+        lwt[2 * j + 1] = make_double2((f & 8u) ? tv : 0.0, (f & 8u) ? 0.0 : tv);
+    }
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
     const int nx = lat.nx, ny = lat.ny, J = lat.tj;
-    const double t = sw.one.t, inv_es = sw.one.inv_es;
     const int nst = (nx + TC - 1) / TC, nsg = (ny + J - 1) / J;
     const int ntile = nst * nsg;
     const int lb = blockIdx.x;
@@ -1145,47 +1169,80 @@ __global__ __launch_bounds__(kBlock) void k_moment_march(Ell h, Sweep sw, Lat2 l
         const bool colok = lane >= K && lane < K + TC && c0 - K + lane < nx;
         const int Jt = min(J, ny - j0), T = Jt + 2 * K;
         const uint32_t ov = (uint32_t)gi * sizeof(V), rb = (uint32_t)nx * sizeof(V);
+        const uint32_t ovo = colok ? ov : kOffNone;   // offset of the strip's own columns
+        const double mcol = colok ? 1.0 : 0.0;
         auto base = [&](int rho) { return (int64_t)wrap_index(j0 - K + rho, ny) * nx; };
+        auto owned = [&](int rho) { return rho >= K && rho < K + Jt; };
         double2 X0[PS], Xm[PS], LL[P];                 // phi_n, phi_{n-1}, phi_L rings
         int PI[P];                                     // pattern ids
         float OF[P];
         double OD[P];
         double2 LV[K][3];                              // levels 1 .. K, last three rows
-        auto load_state = [&](int rho, int q) {
-            X0[q] = buf_ld(p1 + base(rho), rb, ov);
-            Xm[q] = buf_ld(p0 + base(rho), rb, ov);
+        // rows ahead of the first loads and the levels' first rows start as 0
+#pragma unroll
+        for (int q = 0; q < PS; ++q) X0[q] = Xm[q] = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            LL[q] = make_double2(0.0, 0.0);
+            PI[q] = 0;
+            OF[q] = 0.0f;
+            OD[q] = 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < K; ++s) LV[s][0] = LV[s][1] = LV[s][2] = make_double2(0.0, 0.0);
+        // per row: slot weights and on-site term, taken from the pattern table
+        // and the loaded on-site value one iteration before their first use
+        double2 WH[P], WV[P];
+        double OO[P];
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            WH[q] = WV[q] = make_double2(0.0, 0.0);
+            OO[q] = 0.0;
+        }
+        auto row_terms = [&](int q) {
+            if (!kAhead) return;
+            WH[q] = lwt[2 * PI[q]];
+            WV[q] = lwt[2 * PI[q] + 1];
+            OO[q] = ONSF ? (double)OF[q] * inv_es : OD[q];
         };
+        auto load_state = [&](int rho, int q, int ql) {
+            const int64_t rbase = base(rho);
+            const uint32_t nb = rho < T ? rb : 0u;
+            X0[q] = buf_ld(p1 + rbase, nb, ov);
+            Xm[q] = buf_ld(p0 + rbase, nb, ov);
+            if (!DBL) LL[ql] = buf_ld(phil + rbase, owned(rho) ? rb : 0u, ovo);
+        };
+
         auto load_row = [&](int rho, int q) {
             const int64_t rbase = base(rho);
-            PI[q] = __builtin_amdgcn_raw_buffer_load_b8(row_rsrc(h.pid + rbase, (uint32_t)nx), gi,
-                                                        0, 0);
+            const bool in = rho < T;
+            PI[q] = __builtin_amdgcn_raw_buffer_load_b8(
+                row_rsrc(h.pid + rbase, in ? (uint32_t)nx : 0u), gi, 0, 0);
             if (ONSF)
                 OF[q] = __builtin_bit_cast(
                     float, __builtin_amdgcn_raw_buffer_load_b32(
-                               row_rsrc(h.onsf + rbase, (uint32_t)nx * 4u), gi * 4, 0, 0));
+                               row_rsrc(h.onsf + rbase, in ? (uint32_t)nx * 4u : 0u), gi * 4, 0,
+                               0));
             else
                 OD[q] = __builtin_bit_cast(
                     double, __builtin_amdgcn_raw_buffer_load_b64(
-                                row_rsrc(h.ons + rbase, (uint32_t)nx * 8u), gi * 8, 0, 0));
-            if (!DBL && rho >= K && rho < K + Jt) LL[q] = buf_ld(phil + rbase, rb, ov);
+                                row_rsrc(h.ons + rbase, in ? (uint32_t)nx * 8u : 0u), gi * 8, 0,
+                                0));
         };
 #pragma unroll
-        for (int r = 0; r < DS; ++r)
-            if (r < T) load_state(r, r % PS);
+        for (int r = 0; r < DS; ++r) load_state(r, r % PS, r);
 #pragma unroll
-        for (int r = 0; r < DR; ++r)
-            if (r < T) load_row(r, r);
+        for (int r = 0; r < DR; ++r) load_row(r, r);
         for (int t0 = 0; t0 < T; t0 += P) {
 #pragma unroll
             for (int u = 0; u < P; ++u) {
                 const int tt = t0 + u;
-                if (tt >= T) break;
-                if (tt + DS < T) load_state(tt + DS, (u + DS) % PS);
-                if (tt + DR < T) load_row(tt + DR, (u + DR) % P);
+                load_state(tt + DS, (u + DS) % PS, (u + DS) % P);
+                load_row(tt + DR, (u + DR) % P);
+                row_terms(u);
 #pragma unroll
                 for (int s = 1; s <= K; ++s) {
                     const int rho = tt - s;
-                    if (rho < s) continue;
                     // ring slots of rows rho - 1, rho, rho + 1 (rho = t0 + u - s)
                     const int qp = ((u - s) % P + P) % P;               // per-row ring, row rho
                     const int qs = ((u - s) % PS + PS) % PS;            // state rings, row rho
@@ -1204,22 +1261,41 @@ __global__ __launch_bounds__(kBlock) void k_moment_march(Ell h, Sweep sw, Lat2 l
                         xp1 = LV[s - 2][q3p];
                         old = s == 2 ? X0[qs] : LV[s - 3 < 0 ? 0 : s - 3][q3];
                     }
-                    const double o = ONSF ? (double)OF[qp] * inv_es : OD[qp];
-                    const uint32_t f = lflag[PI[qp]];
-                    const double2 c = rounded<V>(reg_row_step(o, t, f, x0, xp1, xm1, old));
+                    // 2 H~ x - q in the slot order of k_moment_step (of the two
+                    // vertical terms one has weight 0; the previous chain's comes
+                    // first, as the next chain's value is the one computed last)
+                    if (!kAhead) {                 // the row's terms, read at each level
+                        WH[qp] = lwt[2 * PI[qp]];
+                        WV[qp] = lwt[2 * PI[qp] + 1];
+                        OO[qp] = ONSF ? (double)OF[qp] * inv_es : OD[qp];
+                    }
+                    double2 a = make_double2(OO[qp] * x0.x, OO[qp] * x0.y);
+                    a = raxpy(a, WH[qp].x, lane_prev(x0));
+                    a = raxpy(a, WH[qp].y, lane_next(x0));
+                    a = raxpy(a, WV[qp].y, xm1);
+                    a = raxpy(a, WV[qp].x, xp1);
+                    const double2 c = rounded<V>(two_minus(a, old));
                     LV[s - 1][q3] = c;
-                    if (rho >= K && rho < K + Jt && colok) {
-                        if (DBL) {
-                            acc[2 * (s - 1)] = cdot_acc(acc[2 * (s - 1)], x0, x0);
-                            acc[2 * (s - 1) + 1] = cdot_acc(acc[2 * (s - 1) + 1], x0, c);
-                        } else {
-                            acc[s - 1] = cdot_acc(acc[s - 1], LL[qp], c);
-                        }
-                        const int64_t row = (int64_t)(j0 + rho - K) * nx;
-                        if (s == K - 1) buf_st(out1 + row, rb, ov, c);
-                        if (s == K) buf_st(out2 + row, rb, ov, c);
+                    if (DBL) {
+                        const double m = owned(rho) ? mcol : 0.0;
+                        const double2 xw = make_double2(x0.x * m, x0.y * m);
+                        // <phi_m|phi_n> = <phi_0|T_m(H~) T_n(H~)|phi_0> is real (H~
+                        // Hermitian): only the real parts are accumulated
+                        acc[2 * (s - 1)].x = fma(xw.x, x0.x, fma(xw.y, x0.y, acc[2 * (s - 1)].x));
+                        acc[2 * (s - 1) + 1].x =
+                            fma(xw.x, c.x, fma(xw.y, c.y, acc[2 * (s - 1) + 1].x));
+                    } else {
+                        acc[s - 1] = cdot_acc(acc[s - 1], LL[qp], c);
+                    }
+                    if (s >= K - 1) {
+                        const bool own = owned(rho);
+                        const int64_t row = (int64_t)(own ? j0 + rho - K : 0) * nx;
+                        buf_st((s == K ? out2 : out1) + row, own ? rb : 0u, ovo, c);
                     }
                 }
+                // each iteration is scheduled on its own: the live values stay
+                // those of the rings
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
@@ -1386,7 +1462,9 @@ void launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
 #define KPM_REG(ONSF_, DBL_)                                                                  \
     do {                                                                                      \
         if (lat.reg == 2) {                                                                   \
-            if (lat.k == 6) KPM_MARCHK(ONSF_, DBL_, 6);                                       \
+            if (lat.k == 8) KPM_MARCHK(ONSF_, DBL_, 8);                                       \
+            else if (lat.k == 7) KPM_MARCHK(ONSF_, DBL_, 7);                                  \
+            else if (lat.k == 6) KPM_MARCHK(ONSF_, DBL_, 6);                                  \
             else if (lat.k == 5) KPM_MARCHK(ONSF_, DBL_, 5);                                  \
             else if (lat.k == 4) KPM_MARCHK(ONSF_, DBL_, 4);                                  \
             else if (lat.k == 3) KPM_MARCHK(ONSF_, DBL_, 3);                                  \

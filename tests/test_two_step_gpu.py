@@ -1,4 +1,4 @@
-"""Several recursion steps per pass (kpm_launch.steps = 2, 3, 4) on chain lattices.
+"""Several recursion steps per pass (kpm_launch.steps = 2 .. 8) on chain lattices.
 
 The sizes leave ragged tiles in both directions (130 columns = 64 + 64 + 2,
 26 or 38 chains = 16 + 10 or 16 + 16 + 6), odd moment counts leave a final
@@ -42,7 +42,7 @@ def _pair(c, precision="fp64", tiled=0, steps=2):
 
 
 MULTI = [(2, 0), (2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (4, 2), (2, 3), (3, 4), (4, 3), (4, 4),
-         (4, 5), (5, 3), (6, 4), (5, 5), (6, 5)]
+         (4, 5), (5, 3), (6, 4), (5, 5), (6, 5), (7, 5), (8, 5), (7, 3), (8, 4)]
 
 
 @pytest.mark.parametrize("geometry,nx,ny", SHAPES)
@@ -162,8 +162,8 @@ def test_graph_replays_match_eager(steps, tiled):
 
 
 def test_not_applicable_falls_back_to_single_steps():
-    """Chains shorter than 68 rows and several vectors per row take single
-    steps under steps = 2, with the same results."""
+    """Chains shorter than 68 rows, fewer than 24 chains and several vectors
+    per row take single steps under steps > 1, with the same results."""
     _need_gpu()
     c = recipe("sheet", 48, 20, w=1.0, vac=0.02, seed=13)
     one, two = _pair(c)
@@ -171,6 +171,16 @@ def test_not_applicable_falls_back_to_single_steps():
     phi = phases(c, 1, 4900)
     d = one.upload(phi)
     assert np.array_equal(kp.kpm_moments(one, d, d, 40), kp.kpm_moments(two, d, d, 40))
+    for ny in (4, 10, 22):
+        c = recipe("sheet", 130, ny, w=1.0, vac=0.02, seed=14)
+        _log(f"fallback sheet 130x{ny}")
+        one, two = _pair(c, tiled=5, steps=5)
+        kp.kpm_reset_stats(two)
+        kp.kpm_set_timing(two, True)
+        phi = phases(c, 1, 4902)
+        d = one.upload(phi)
+        assert np.array_equal(kp.kpm_moments(one, d, d, 40), kp.kpm_moments(two, d, d, 40))
+        assert kp.kpm_get_stats(two)["step_launches"] == 38
     c = recipe("sheet", 130, 26, w=1.0, vac=0.02, seed=13)
     one, two = _pair(c)
     kp.kpm_set_launch(one, 2, 4, 1, 0, 1, 0, 1)
@@ -188,7 +198,7 @@ def test_autotune_considers_two_steps():
     phi = phases(c, 1, 5000)
     d = sysg.upload(phi)
     best = kp.kpm_autotune(sysg, d, 20)
-    assert best["steps"] in (1, 2, 3, 4)
+    assert best["steps"] in range(1, 7)
     got = kp.kpm_moments(sysg, d, d, 50)[0]
     ref = oracle.moments(oracle_lattice(c), c["e_scale"], phi[:, 0], phi[:, 0], 50)
     assert rel_err(got, ref, np.vdot(phi, phi).real) < 1e-10
@@ -212,5 +222,5 @@ def test_doubling_form_has_its_own_shape():
     assert rel_err(kp.kpm_moments_doubled(sysg, d, 81)[0], ref, scale) < 1e-10
     assert rel_err(kp.kpm_moments(sysg, d, d, 81)[0], ref, scale) < 1e-10
     kp.kpm_autotune(sysg, d, 8)
-    assert kp.kpm_get_launch_doubled(sysg, 1)["steps"] in (1, 2, 3, 4)
+    assert kp.kpm_get_launch_doubled(sysg, 1)["steps"] in range(1, 7)
     assert rel_err(kp.kpm_moments_doubled(sysg, d, 81)[0], ref, scale) < 1e-10
