@@ -448,7 +448,7 @@ kpm_status kpm_xu_state(kpm_system *sys, int n_vec, const void *phi, int n_steps
  * (tiled = 5).
  * 3 and 4 steps need the register forms (else 2 steps apply), 5 .. 8 steps
  * the strips.  Under steps > 1 any single steps keep row order.  Default for
- * one vector: groups_per_cu 2, steps 5, tiled 5; for more vectors single
+ * one vector: groups_per_cu 2, steps 8, tiled 5; for more vectors single
  * steps.  At a fixed grid size, traversal and step count the moments are
  * bit-identical for every ilp, streaming and compact choice; the recursion
  * states are bit-identical for every shape (up to the sign of zero), and the

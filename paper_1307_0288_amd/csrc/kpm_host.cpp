@@ -194,14 +194,14 @@ kpm_launch default_launch(int vshift, kpm_precision prec) {
     // row order, beyond an XCD's L2
     l.tiled = vshift >= 3 ? 1 : 0;
     l.steps = 1;
-    // one vector: five recursion steps per pass in marching strips, one per
-    // wavefront of the grid, where the sample allows (measured fastest on
-    // paper-scale sheets, with 2 groups per CU); elsewhere single steps in
+    // one vector: eight recursion steps per pass in marching strips sized for
+    // the grid, where the sample allows (measured fastest on paper-scale
+    // sheets, in both forms, with 2 groups per CU); elsewhere single steps in
     // row order
     if (vshift == 0) {
         l.groups_per_cu = 2;
         l.tiled = 5;
-        l.steps = 5;
+        l.steps = 8;
     }
     return l;
 }
