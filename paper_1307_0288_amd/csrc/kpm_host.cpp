@@ -834,7 +834,32 @@ kpm_status run_evolve(kpm_system *sys, int vshift, const V *in, V *acc, const V 
                                step_coef(c, tab, np, 0), step_coef(c, tab, np, 1), s);
     const V *p0 = in;
     V *p1 = a_buf;
-    for (int m = 2; m < np; ++m) {
+    int m = 2;
+    // Several steps per pass in the moment sets' marching strips (one sample,
+    // one vector per row): the new states go to two of the four scratch
+    // states that the pass does not read (never to `in`), and a last pass
+    // takes the remaining steps when there are at least two
+    const kpm_launch &l = sys->launch[vshift];
+    const int k = sys->multi_steps(vshift, l);
+    if (k > 1 && l.tiled >= 3 && sys->d_flags && !tab && np - m >= 2) {
+        KPM_TRY(sys->ensure_xbuf(vshift));
+        V *pool[4] = {a_buf, b_buf, (V *)sys->xbuf[0], (V *)sys->xbuf[1]};
+        while (np - m >= 2) {
+            const int kk = std::min({k, np - m, kpm::kMaxMarchSteps});
+            V *o[2];
+            int no = 0;
+            for (V *q : pool)
+                if (q != p1 && q != p0 && no < 2) o[no++] = q;
+            kpm::CoefK ck{};
+            for (int j = 0; j < kk; ++j) ck.c[j] = c[m + j];
+            kpm::launch_evolve_multi<V>(h, sw, sys->lat2(l, kk, sw.nwg), p1, p0, o[0], o[1], acc,
+                                        ck, s);
+            p0 = o[0];
+            p1 = o[1];
+            m += kk;
+        }
+    }
+    for (; m < np; ++m) {
         V *out = (m == 2) ? b_buf : const_cast<V *>(p0);
         kpm::launch_evolve_step<V>(h, sw, false, p1, p0, out, acc, nullptr,
                                    step_coef(c, tab, np, 0), step_coef(c, tab, np, m), s);

@@ -141,6 +141,21 @@ void launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
                          const V *p0, V *out1, V *out2, const V *phil, double2 *partial,
                          int slot, bool dbl, hipStream_t s);
 
+// Coefficients of the K steps of one multi-step propagator pass.
+constexpr int kMaxMarchSteps = 8;
+struct CoefK {
+    double2 c[kMaxMarchSteps];
+};
+
+// K = lat.k steps of the Chebyshev-Bessel propagator (Alg. 6) in marching
+// strips (lat.reg == 2): from p1 = phi_n and p0 = phi_{n-1}, out1 = phi_{n+K-1},
+// out2 = phi_{n+K} (neither aliasing p1, p0 or each other) and acc += c_m
+// phi_m for m = n+1 .. n+K, c_m = ck.c[m - n - 1], in step order.
+template <typename V>
+void launch_evolve_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V *p1,
+                         const V *p0, V *out1, V *out2, V *acc, const CoefK &ck,
+                         hipStream_t s);
+
 // mom[t * stride + offset + j] = 2 mom[...j] - mom[...j % 2] for 2 <= j < nm,
 // t < rows: moments from the doubling sums.
 void launch_undouble(double2 *mom, int rows, int64_t stride, int64_t offset, int nm,

@@ -1102,8 +1102,8 @@ __global__ __launch_bounds__(kBlock) void k_moment_stepk(Ell h, Sweep sw, Lat2 l
 // row t - s.  Each level keeps its last three rows in registers, so rows are
 // computed once per level except the K - 1 boundary rows at each end of the
 // strip, instead of once per tile as in k_moment_stepk.  phi_n, phi_{n-1} and
-// phi_L are loaded kDs rows ahead, the pattern id and on-site term
-// kRowRing - 1 - K rows ahead; a row's slot weights (from a per-pattern table
+// phi_L are loaded kDs rows ahead (phi_L fewer at K = 8), the pattern id and
+// on-site term kRowRing - 1 - K rows ahead; a row's slot weights (from a per-pattern table
 // in LDS: t or 0 for the previous column, the next column, the next chain and
 // the previous chain) and scaled on-site term are formed one iteration before
 // their first use.  The loop is unrolled by kRowRing (a multiple of
@@ -1122,18 +1122,27 @@ constexpr int kRowRing = kMarchRows;
 constexpr int kDs = 3;
 constexpr uint32_t kOffNone = 0x80000000u;   // past the end of every row
 
-template <typename V, bool ONSF, bool DBL, int K>
-__global__ __launch_bounds__(kBlock, 2) void k_moment_march(Ell h, Sweep sw, Lat2 lat,
-                                                         const V *p1, const V *p0,
-                                                         V *__restrict__ out1,
-                                                         V *__restrict__ out2,
-                                                         const V *__restrict__ phil,
-                                                         double2 *__restrict__ partial,
-                                                         int slot) {
+// MODE: kMarchDirect (moments <phi_L|phi_{n+s}>), kMarchDoubled (the two
+// doubling sums per level, phi_L unused) or kMarchBessel (the propagator's
+// accumulator: lacc holds acc, updated acc += c_{n+s} phi_{n+s} at each level
+// in step order and stored after level K; no inner products).
+constexpr int kMarchDirect = 0, kMarchDoubled = 1, kMarchBessel = 2;
+
+template <typename V, bool ONSF, int MODE, int K>
+__device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const Lat2 &lat,
+                                            const V *p1, const V *p0, V *__restrict__ out1,
+                                            V *__restrict__ out2, V *__restrict__ lacc,
+                                            double2 *__restrict__ partial, int slot,
+                                            const CoefK &ck) {
+    constexpr bool DBL = MODE == kMarchDoubled, BES = MODE == kMarchBessel;
     constexpr int TC = kWave - 2 * K;                  // columns per strip
     constexpr int P = kRowRing, PS = kStateRing, DS = kDs, DR = kRowRing - 1 - K;
-    constexpr int NA = DBL ? 2 * K : K;
-    static_assert(DR >= 1 && DS + 3 <= PS && P % PS == 0 && PS % 3 == 0, "ring sizes");
+    // phi_L rows are loaded DL ahead and used through K iterations after their
+    // own (fewer rows ahead at K = 8 keep that kernel within its registers)
+    constexpr int DL = K >= 8 ? (sizeof(V) == sizeof(double2) ? 2 : 1) : (DS < DR ? DS : DR);
+    constexpr int NA = BES ? 1 : (DBL ? 2 * K : K);
+    static_assert(DR >= 1 && DS + 3 <= PS && P % PS == 0 && PS % 3 == 0 && DL + K < P,
+                  "ring sizes");
     // up to 5 steps the row terms are formed once per row, ahead of their first
     // use; with more levels their registers are needed for the level rings
     static_assert(K >= 2 && K <= 8, "steps per pass");
@@ -1205,12 +1214,14 @@ __global__ __launch_bounds__(kBlock, 2) void k_moment_march(Ell h, Sweep sw, Lat
             WV[q] = lwt[2 * PI[q] + 1];
             OO[q] = ONSF ? (double)OF[q] * inv_es : OD[q];
         };
-        auto load_state = [&](int rho, int q, int ql) {
+        auto load_state = [&](int rho, int q) {
             const int64_t rbase = base(rho);
             const uint32_t nb = rho < T ? rb : 0u;
             X0[q] = buf_ld(p1 + rbase, nb, ov);
             Xm[q] = buf_ld(p0 + rbase, nb, ov);
-            if (!DBL) LL[ql] = buf_ld(phil + rbase, owned(rho) ? rb : 0u, ovo);
+        };
+        auto load_left = [&](int rho, int q) {
+            if (!DBL) LL[q] = buf_ld(lacc + base(rho), owned(rho) ? rb : 0u, ovo);
         };
 
         auto load_row = [&](int rho, int q) {
@@ -1230,14 +1241,17 @@ __global__ __launch_bounds__(kBlock, 2) void k_moment_march(Ell h, Sweep sw, Lat
                                 0));
         };
 #pragma unroll
-        for (int r = 0; r < DS; ++r) load_state(r, r % PS, r);
+        for (int r = 0; r < DS; ++r) load_state(r, r % PS);
+#pragma unroll
+        for (int r = 0; r < DL; ++r) load_left(r, r);
 #pragma unroll
         for (int r = 0; r < DR; ++r) load_row(r, r);
         for (int t0 = 0; t0 < T; t0 += P) {
 #pragma unroll
             for (int u = 0; u < P; ++u) {
                 const int tt = t0 + u;
-                load_state(tt + DS, (u + DS) % PS, (u + DS) % P);
+                load_state(tt + DS, (u + DS) % PS);
+                load_left(tt + DL, (u + DL) % P);
                 load_row(tt + DR, (u + DR) % P);
                 row_terms(u);
 #pragma unroll
@@ -1276,7 +1290,14 @@ __global__ __launch_bounds__(kBlock, 2) void k_moment_march(Ell h, Sweep sw, Lat
                     a = raxpy(a, WV[qp].x, xp1);
                     const double2 c = rounded<V>(two_minus(a, old));
                     LV[s - 1][q3] = c;
-                    if (DBL) {
+                    if (BES) {
+                        LL[qp] = rounded<V>(cmla(LL[qp], ck.c[s - 1], c));
+                        if (s == K) {
+                            const bool own = owned(rho);
+                            const int64_t row = (int64_t)(own ? j0 + rho - K : 0) * nx;
+                            buf_st(lacc + row, own ? rb : 0u, ovo, LL[qp]);
+                        }
+                    } else if (DBL) {
                         const double m = owned(rho) ? mcol : 0.0;
                         const double2 xw = make_double2(x0.x * m, x0.y * m);
                         // <phi_m|phi_n> = <phi_0|T_m(H~) T_n(H~)|phi_0> is real (H~
@@ -1299,10 +1320,35 @@ __global__ __launch_bounds__(kBlock, 2) void k_moment_march(Ell h, Sweep sw, Lat
             }
         }
     }
+    if (BES) return;
     const int nw = sw.nwg;
 #pragma unroll
     for (int k = 0; k < NA; ++k) block_sum(acc[k], 0, partial + (int64_t)(slot + k) * nw + blockIdx.x);
 }
+
+template <typename V, bool ONSF, bool DBL, int K>
+__global__ __launch_bounds__(kBlock, 2) void k_moment_march(Ell h, Sweep sw, Lat2 lat,
+                                                         const V *p1, const V *p0,
+                                                         V *__restrict__ out1,
+                                                         V *__restrict__ out2,
+                                                         const V *__restrict__ phil,
+                                                         double2 *__restrict__ partial,
+                                                         int slot) {
+    march_sweep<V, ONSF, DBL ? kMarchDoubled : kMarchDirect, K>(
+        h, sw, lat, p1, p0, out1, out2, const_cast<V *>(phil), partial, slot, CoefK{});
+}
+
+// K steps of the Chebyshev-Bessel propagator (Alg. 6) per pass: the states as
+// in k_moment_march, and acc += c_m phi_m for the K new states, c_m = ck.c[m - n - 1].
+template <typename V, bool ONSF, int K>
+__global__ __launch_bounds__(kBlock, 2) void k_evolve_march(Ell h, Sweep sw, Lat2 lat,
+                                                         const V *p1, const V *p0,
+                                                         V *__restrict__ out1,
+                                                         V *__restrict__ out2,
+                                                         V *__restrict__ acc, CoefK ck) {
+    march_sweep<V, ONSF, kMarchBessel, K>(h, sw, lat, p1, p0, out1, out2, acc, nullptr, 0, ck);
+}
+
 
 // ---------------------------------------------------------------- launchers
 template <typename V, int ILP, bool NT, bool DBL>
@@ -1492,6 +1538,29 @@ void launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
 #undef KPM_MARCHK
 }
 
+template <typename V>
+void launch_evolve_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V *p1,
+                         const V *p0, V *out1, V *out2, V *acc, const CoefK &ck,
+                         hipStream_t s) {
+#define KPM_EVK(ONSF_, K_)                                                                    \
+    hipLaunchKernelGGL((k_evolve_march<V, ONSF_, K_>), dim3(sw.nwg), dim3(kBlock), 0, s, h,   \
+                       sw, lat, p1, p0, out1, out2, acc, ck)
+#define KPM_EV(ONSF_)                                                                         \
+    switch (lat.k) {                                                                          \
+        case 8: KPM_EVK(ONSF_, 8); break;                                                     \
+        case 7: KPM_EVK(ONSF_, 7); break;                                                     \
+        case 6: KPM_EVK(ONSF_, 6); break;                                                     \
+        case 5: KPM_EVK(ONSF_, 5); break;                                                     \
+        case 4: KPM_EVK(ONSF_, 4); break;                                                     \
+        case 3: KPM_EVK(ONSF_, 3); break;                                                     \
+        default: KPM_EVK(ONSF_, 2); break;                                                    \
+    }
+    if (h.onsf) { KPM_EV(true) }
+    else { KPM_EV(false) }
+#undef KPM_EV
+#undef KPM_EVK
+}
+
 #define KPM_INSTANTIATE(V)                                                                  \
     template void launch_moment_step<V>(const Ell &, const Sweep &, bool, const V *,        \
                                         const V *, V *, const V *, double2 *, int,          \
@@ -1511,7 +1580,10 @@ void launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
                                 hipStream_t);                                               \
     template void launch_moment_multi<V>(const Ell &, const Sweep &, const Lat2 &, const V *, \
                                          const V *, V *, V *, const V *, double2 *, int,    \
-                                         bool, hipStream_t);
+                                         bool, hipStream_t);                                \
+    template void launch_evolve_multi<V>(const Ell &, const Sweep &, const Lat2 &, const V *, \
+                                         const V *, V *, V *, V *, const CoefK &,           \
+                                         hipStream_t);
 
 KPM_INSTANTIATE(double2)
 KPM_INSTANTIATE(float2)

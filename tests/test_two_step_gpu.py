@@ -144,6 +144,47 @@ def test_time_loops_with_two_step_moments(kind, steps, tiled):
     assert rel_err(got[0], ref) < 1e-10
 
 
+EVOLVE = [(2, 5), (3, 5), (5, 5), (6, 5), (8, 5), (7, 3), (8, 4)]
+
+
+@pytest.mark.parametrize("geometry,nx,ny", SHAPES[:3])
+@pytest.mark.parametrize("steps,tiled", EVOLVE)
+def test_propagator_in_strips_equals_single_steps(geometry, nx, ny, steps, tiled):
+    """U(+-dt) with the recursion in marching strips (Alg. 6 several steps per
+    pass): the same states and accumulator as single steps, and the oracle's
+    result; Bessel term counts leave full passes, a short last pass, a
+    single last step, or no multi-step pass at all."""
+    _need_gpu()
+    c = recipe(geometry, nx, ny, w=1.2, vac=0.02, seed=3 * nx + ny)
+    _log(f"propagator {geometry} {nx}x{ny} steps={steps} tiled={tiled}")
+    one, two = _pair(c, tiled=tiled, steps=steps)
+    lat = oracle_lattice(c)
+    for sign, nb, dt in ((1, 40, 1.0), (-1, 13, 0.3), (1, 11, 0.2), (1, 3, 0.2), (-1, 2, 0.05)):
+        phi = phases(c, 1, 4950 + nb)
+        ref = oracle.evolve(lat, c["e_scale"], phi[:, 0], dt, sign, nb)
+        d1, d2 = one.upload(phi), two.upload(phi)
+        kp.kpm_evolve(one, d1, dt, sign, nb)
+        kp.kpm_evolve(two, d2, dt, sign, nb)
+        g1, g2 = d1.cpu().numpy()[:, 0], d2.cpu().numpy()[:, 0]
+        assert np.array_equal(g2, g1), (sign, nb)
+        assert rel_err(g2, ref) < 1e-12, (sign, nb)
+
+
+@pytest.mark.parametrize("steps,tiled", [(5, 5), (8, 5)])
+def test_propagator_in_strips_fp32(steps, tiled):
+    _need_gpu()
+    c = recipe("zgnr", 130, 38, w=1.0, vac=0.02, seed=23)
+    _log(f"propagator fp32 zgnr 130x38 steps={steps}")
+    one, two = _pair(c, "fp32", tiled, steps)
+    phi = phases(c, 1, 4990)
+    d1, d2 = one.upload(phi), two.upload(phi)
+    kp.kpm_evolve(one, d1, 0.8, 1, 30)
+    kp.kpm_evolve(two, d2, 0.8, 1, 30)
+    assert np.array_equal(d2.cpu().numpy(), d1.cpu().numpy())
+    ref = oracle.evolve(oracle_lattice(c), c["e_scale"], phi[:, 0], 0.8, 1, 30)
+    assert rel_err(d2.cpu().numpy()[:, 0], ref) < 1e-5
+
+
 @pytest.mark.parametrize("steps,tiled", [(2, 0), (4, 1), (4, 4)])
 def test_graph_replays_match_eager(steps, tiled):
     _need_gpu()
