@@ -128,7 +128,7 @@ def test_fp32_states_equal_single_step(steps, tiled):
 
 
 @pytest.mark.parametrize("kind", ["vac", "msd"])
-@pytest.mark.parametrize("steps,tiled", [(2, 0), (3, 2), (4, 3)])
+@pytest.mark.parametrize("steps,tiled", [(2, 0), (3, 2), (4, 3), (8, 5)])
 def test_time_loops_with_two_step_moments(kind, steps, tiled):
     _need_gpu()
     c = recipe("sheet", 130, 26, w=1.0, vac=0.02, seed=9)
