@@ -233,7 +233,8 @@ struct kpm_system {
     int32_t l2nx = 0, l2ny = 0;
     uint32_t *d_code = nullptr;
     uint32_t *d_flags = nullptr;   // graphene slot flags (register tiles), or none
-    void *xbuf[2] = {nullptr, nullptr};
+    void *xbuf[4] = {nullptr, nullptr, nullptr, nullptr};
+    int xbuf_count = 0;
     size_t xbuf_bytes = 0;
     // device Hamiltonian
     int32_t *d_nbr = nullptr;   // explicit neighbour list, or
@@ -242,6 +243,7 @@ struct kpm_system {
     int npat = 0;
     double *d_hop = nullptr;
     double *d_xw = nullptr;
+    double *d_pxw = nullptr;    // [npat][4] commutator weights per slot (chain lattices)
     double *d_ons = nullptr;    // H_nn / E_s, or
     float *d_onsf = nullptr;    // H_nn (eV) when every value is a float
     bool uniform_hop = true;
@@ -516,9 +518,10 @@ struct kpm_system {
     // Scratch limit (KPM_SCRATCH_LIMIT_MB at creation; 0 = none): the recursion
     // buffers, partials and moments together may not exceed it.
     size_t scratch_limit = 0;
+    // xbytes: all extra multi-step states together
     kpm_status check_scratch(size_t nvec, size_t vbytes, size_t pelems, size_t delems,
                              size_t xbytes) const {
-        const size_t total = nvec * vbytes + 2 * xbytes + (pelems + delems) * sizeof(double2);
+        const size_t total = nvec * vbytes + xbytes + (pelems + delems) * sizeof(double2);
         if (scratch_limit && total > scratch_limit)
             return fail(KPM_ERR_OOM, "scratch of %zu bytes exceeds the limit of %zu bytes", total,
                         scratch_limit);
@@ -529,7 +532,7 @@ struct kpm_system {
     kpm_status ensure_vecs(int count, int vshift) {
         const size_t bytes = state_bytes(vshift);
         KPM_TRY(check_scratch(std::max<size_t>(count, vecs.size()), std::max(bytes, vec_bytes),
-                              partial_elems, dmom_elems, xbuf_bytes));
+                              partial_elems, dmom_elems, xbuf_bytes * xbuf_count));
         if (bytes > vec_bytes) {
             drop_graphs();
             KPM_HIP(hipStreamSynchronize(stream));
@@ -546,11 +549,15 @@ struct kpm_system {
         return KPM_OK;
     }
 
-    // The two extra recursion states of the two-step sweep.
-    kpm_status ensure_xbuf(int vshift) {
+    // The extra recursion states of the multi-step sweeps: two (one
+    // recursion) or four (the coupled propagator).
+    kpm_status ensure_xbuf(int vshift, int count = 2) {
         const size_t bytes = state_bytes(vshift);
-        if (bytes <= xbuf_bytes) return KPM_OK;
-        KPM_TRY(check_scratch(vecs.size(), vec_bytes, partial_elems, dmom_elems, bytes));
+        if (bytes <= xbuf_bytes && count <= xbuf_count) return KPM_OK;
+        count = std::max(count, xbuf_count);
+        KPM_TRY(check_scratch(vecs.size(), vec_bytes, partial_elems, dmom_elems,
+                              std::max(bytes, xbuf_bytes) * (size_t)count));
+        const size_t nb = std::max(bytes, xbuf_bytes);
         drop_graphs();
         KPM_HIP(hipStreamSynchronize(stream));
         for (void *&p : xbuf) {
@@ -558,15 +565,18 @@ struct kpm_system {
             p = nullptr;
         }
         xbuf_bytes = 0;
-        for (void *&p : xbuf) KPM_HIP(hipMalloc(&p, bytes));
-        xbuf_bytes = bytes;
+        xbuf_count = 0;
+        for (int i = 0; i < count; ++i) KPM_HIP(hipMalloc(&xbuf[i], nb));
+        xbuf_bytes = nb;
+        xbuf_count = count;
         return KPM_OK;
     }
 
     kpm_status ensure_partial(int slots, int nwg, int n_vec) {
         const size_t need = (size_t)slots * nwg * n_vec;
         if (need > partial_elems) {
-            KPM_TRY(check_scratch(vecs.size(), vec_bytes, need, dmom_elems, xbuf_bytes));
+            KPM_TRY(check_scratch(vecs.size(), vec_bytes, need, dmom_elems,
+                                  xbuf_bytes * xbuf_count));
             drop_graphs();
             KPM_HIP(hipStreamSynchronize(stream));
             if (partial) (void)hipFree(partial);
@@ -579,7 +589,8 @@ struct kpm_system {
 
     kpm_status ensure_dmom(size_t elems) {
         if (elems > dmom_elems) {
-            KPM_TRY(check_scratch(vecs.size(), vec_bytes, partial_elems, elems, xbuf_bytes));
+            KPM_TRY(check_scratch(vecs.size(), vec_bytes, partial_elems, elems,
+                                  xbuf_bytes * xbuf_count));
             drop_graphs();
             KPM_HIP(hipStreamSynchronize(stream));
             if (dmom) (void)hipFree(dmom);
@@ -637,6 +648,7 @@ struct kpm_system {
         if (d_onsf) (void)hipFree(d_onsf);
         if (d_hop) (void)hipFree(d_hop);
         if (d_xw) (void)hipFree(d_xw);
+        if (d_pxw) (void)hipFree(d_pxw);
         if (d_ons) (void)hipFree(d_ons);
         if (d_alpha) (void)hipFree(d_alpha);
     }
@@ -885,7 +897,39 @@ kpm_status run_evolve_x(kpm_system *sys, int vshift, const V *in, V *accx, V *ac
                                  accu, step_coef(c, tab, np, 0), step_coef(c, tab, np, 1), s);
     const V *p0 = in, *q0 = nullptr;
     V *p1 = pa, *q1 = qa;
-    for (int m = 2; m < np; ++m) {
+    int m = 2;
+    // Up to three coupled steps per pass in marching strips where the moment
+    // sets use strips and the commutator weights follow the neighbour patterns;
+    // each recursion's new states go to two of its four scratch states that the
+    // pass does not read
+    const kpm_launch &l = sys->launch[vshift];
+    const int k = std::min(sys->multi_steps(vshift, l), 3);
+    if (k > 1 && l.tiled >= 3 && sys->d_flags && sys->d_pxw && !tab && np - m >= 2) {
+        KPM_TRY(sys->ensure_xbuf(vshift, 4));
+        V *pool_p[4] = {pa, pb, (V *)sys->xbuf[0], (V *)sys->xbuf[1]};
+        V *pool_q[4] = {qa, qb, (V *)sys->xbuf[2], (V *)sys->xbuf[3]};
+        auto pick = [](V *const *pool, const V *a, const V *b, V **o) {
+            int no = 0;
+            for (int i = 0; i < 4; ++i)
+                if (pool[i] != a && pool[i] != b && no < 2) o[no++] = pool[i];
+        };
+        while (np - m >= 2) {
+            const int kk = std::min(k, np - m);
+            V *po[2], *qo[2];
+            pick(pool_p, p1, p0, po);
+            pick(pool_q, q1, q0, qo);
+            kpm::CoefK ck{};
+            for (int j = 0; j < kk; ++j) ck.c[j] = c[m + j];
+            kpm::launch_evolve_x_multi<V>(h, sw, sys->lat2(l, kk, sw.nwg), sys->d_pxw, p1, p0,
+                                          po[0], po[1], q1, q0, qo[0], qo[1], accx, accu, ck, s);
+            p0 = po[0];
+            p1 = po[1];
+            q0 = qo[0];
+            q1 = qo[1];
+            m += kk;
+        }
+    }
+    for (; m < np; ++m) {
         V *pout = (m == 2) ? pb : const_cast<V *>(p0);
         V *qout = (m == 2) ? qb : const_cast<V *>(q0);
         kpm::launch_evolve_x_step<V>(h, sw, false, p1, p0, pout, q1, q0, qout, accx, accu,
@@ -1389,8 +1433,27 @@ kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int devi
         sys->l2nx = sys->chain[0];
         sys->l2ny = (int32_t)(n / sys->chain[0]);
         std::vector<uint32_t> flags;
-        if (st == KPM_OK && sys->l2ny >= 16 && graphene_flags(code, flags))
+        if (st == KPM_OK && sys->l2ny >= 16 && graphene_flags(code, flags)) {
             st = upload((void **)&sys->d_flags, flags.data(), flags.size() * sizeof(uint32_t));
+            // per-pattern commutator weights of the coupled strips, where every
+            // row of a pattern carries the same ones (as on a builder lattice)
+            if (st == KPM_OK && all_dx) {
+                std::vector<double> pxw((size_t)sys->npat * 4, 0.0);
+                std::vector<uint8_t> seen(sys->npat, 0);
+                bool same = true;
+                for (int64_t r = 0; r < n && same; ++r) {
+                    const int q = pid[r];
+                    for (int k = 0; k < 3; ++k) {
+                        const double v = xw[(size_t)k * n + r];
+                        if (!seen[q]) pxw[(size_t)q * 4 + k] = v;
+                        else same = same && pxw[(size_t)q * 4 + k] == v;
+                    }
+                    seen[q] = 1;
+                }
+                if (same)
+                    st = upload((void **)&sys->d_pxw, pxw.data(), pxw.size() * sizeof(double));
+            }
+        }
     }
     if (st == KPM_OK && ons_float) {
         std::vector<float> of(ons.begin(), ons.end());

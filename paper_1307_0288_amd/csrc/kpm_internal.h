@@ -156,6 +156,17 @@ void launch_evolve_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
                          const V *p0, V *out1, V *out2, V *acc, const CoefK &ck,
                          hipStream_t s);
 
+// K = lat.k = 2 or 3 coupled steps of Alg. 7 (Eq. 37-41) in marching strips:
+// from p1, p0 (T_n psi, T_{n-1} psi) and q1, q0 ([X, T_n] psi, [X, T_{n-1}] psi;
+// q0 may be nullptr for 0) the last two states of each recursion, and accu +=
+// c_m p_m, accx += c_m q_m for m = n+1 .. n+K (c_m = ck.c[m - n - 1]).  pxw:
+// [npat][4] commutator weight of each slot per pattern.  Outputs alias no input.
+template <typename V>
+void launch_evolve_x_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const double *pxw,
+                           const V *p1, const V *p0, V *pout1, V *pout2, const V *q1,
+                           const V *q0, V *qout1, V *qout2, V *accx, V *accu, const CoefK &ck,
+                           hipStream_t s);
+
 // mom[t * stride + offset + j] = 2 mom[...j] - mom[...j % 2] for 2 <= j < nm,
 // t < rows: moments from the doubling sums.
 void launch_undouble(double2 *mom, int rows, int64_t stride, int64_t offset, int nm,

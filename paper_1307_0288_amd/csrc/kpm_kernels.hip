@@ -1588,4 +1588,215 @@ void launch_evolve_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
 KPM_INSTANTIATE(double2)
 KPM_INSTANTIATE(float2)
 
+// ---------------------------------------------------------------- coupled propagator strips
+// K coupled steps of Alg. 7 per pass (Eq. 37-41): the recursion of T_m(H~) psi
+// (p) and of [X, T_m(H~)] psi (q), q_{m+1} = 2 ([X, H~] p_m + H~ q_m) - q_{m-1},
+// walked in marching strips as k_moment_march walks one recursion: each level
+// keeps three rows of p and of q in registers.  acc_u += c_m p_m and acc_x +=
+// c_m q_m are loaded once per pass for the rows a strip owns, updated at each
+// level in step order and stored after the last one.  q0 may be null (q_0 =
+// 0).  The commutator weights come from a per-pattern table (xw[pattern][slot],
+// the same for every row of a pattern).  Every value goes through the
+// operations of k_evolve_x_step in its order.
+template <typename V, bool ONSF, int K>
+__global__ __launch_bounds__(kBlock, 2) void k_evolve_x_march(
+    Ell h, Sweep sw, Lat2 lat, const double *pxw, const V *p1, const V *p0,
+    V *__restrict__ pout1, V *__restrict__ pout2, const V *q1, const V *q0,
+    V *__restrict__ qout1, V *__restrict__ qout2, V *__restrict__ accx, V *__restrict__ accu,
+    CoefK ck) {
+    constexpr int TC = kWave - 2 * K;
+    constexpr int P = kRowRing, PS = kStateRing, DS = kDs, DR = kRowRing - 1 - K;
+    constexpr int DL = DS < DR ? DS : DR;
+    static_assert(K >= 2 && K <= 3, "coupled steps per pass");
+    static_assert(DR >= 1 && DS + 3 <= PS && P % PS == 0 && PS % 3 == 0 && DL + K < P,
+                  "ring sizes");
+    const double t = sw.one.t, inv_es = sw.one.inv_es;
+    // per pattern: hopping (previous column, next column), (next chain, previous
+    // chain), then commutator weights in the same order
+    __shared__ double2 lwt[4 * kMaxPatterns];
+    for (int j = threadIdx.x; j < h.npat; j += kBlock) {
+        const uint32_t f = lat.flags[j];
+        const double tv = (f & 4u) ? t : 0.0, xv = pxw[4 * j + 2];
+        lwt[4 * j] = make_double2((f & 1u) ? t : 0.0, (f & 2u) ? t : 0.0);
+        lwt[4 * j + 1] = make_double2((f & 8u) ? tv : 0.0, (f & 8u) ? 0.0 : tv);
+        lwt[4 * j + 2] = make_double2(pxw[4 * j], pxw[4 * j + 1]);
+        lwt[4 * j + 3] = make_double2((f & 8u) ? xv : 0.0, (f & 8u) ? 0.0 : xv);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1);
+    const int nx = lat.nx, ny = lat.ny, J = lat.tj;
+    const int nst = (nx + TC - 1) / TC, nsg = (ny + J - 1) / J;
+    const int ntile = nst * nsg;
+    const int lb = blockIdx.x;
+    const int per = (ntile + kXcds - 1) / kXcds;
+    const int b0 = (lb % kXcds) * per, b1 = min(b0 + per, ntile);
+    constexpr int kWaves = kBlock / kWave;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int wloc = (lb / kXcds) * kWaves + wv;
+    const int wn = (sw.nwg / kXcds) * kWaves;
+    for (int b = b0 + wloc; b < b1; b += wn) {
+        const int strip = b % nst;
+        const int j0 = (b / nst) * J, c0 = strip * TC;
+        const int gi = wrap_index(c0 - K + lane, nx);
+        const bool colok = lane >= K && lane < K + TC && c0 - K + lane < nx;
+        const int Jt = min(J, ny - j0), T = Jt + 2 * K;
+        const uint32_t ov = (uint32_t)gi * sizeof(V), rb = (uint32_t)nx * sizeof(V);
+        const uint32_t ovo = colok ? ov : kOffNone;
+        auto base = [&](int rho) { return (int64_t)wrap_index(j0 - K + rho, ny) * nx; };
+        auto owned = [&](int rho) { return rho >= K && rho < K + Jt; };
+        double2 X0[PS], Xm[PS], Y0[PS], Ym[PS];        // p_n, p_{n-1}, q_n, q_{n-1}
+        double2 AU[P], AX[P];                          // accumulators of the owned rows
+        int PI[P];
+        float OF[P];
+        double OD[P];
+        double2 LP[K][3], LQ[K][3];                    // levels 1 .. K of p and q
+#pragma unroll
+        for (int q = 0; q < PS; ++q) X0[q] = Xm[q] = Y0[q] = Ym[q] = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            AU[q] = AX[q] = make_double2(0.0, 0.0);
+            PI[q] = 0;
+            OF[q] = 0.0f;
+            OD[q] = 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < K; ++s)
+            LP[s][0] = LP[s][1] = LP[s][2] = LQ[s][0] = LQ[s][1] = LQ[s][2] =
+                make_double2(0.0, 0.0);
+        auto load_state = [&](int rho, int q) {
+            const int64_t rbase = base(rho);
+            const uint32_t nb = rho < T ? rb : 0u;
+            X0[q] = buf_ld(p1 + rbase, nb, ov);
+            Xm[q] = buf_ld(p0 + rbase, nb, ov);
+            Y0[q] = buf_ld(q1 + rbase, nb, ov);
+            Ym[q] = buf_ld(q0 ? q0 + rbase : q1, q0 ? nb : 0u, ov);
+        };
+        auto load_acc = [&](int rho, int q) {
+            const int64_t rbase = base(rho);
+            const uint32_t nb = owned(rho) ? rb : 0u;
+            AU[q] = buf_ld(accu + rbase, nb, ovo);
+            AX[q] = buf_ld(accx + rbase, nb, ovo);
+        };
+        auto load_row = [&](int rho, int q) {
+            const int64_t rbase = base(rho);
+            const bool in = rho < T;
+            PI[q] = __builtin_amdgcn_raw_buffer_load_b8(
+                row_rsrc(h.pid + rbase, in ? (uint32_t)nx : 0u), gi, 0, 0);
+            if (ONSF)
+                OF[q] = __builtin_bit_cast(
+                    float, __builtin_amdgcn_raw_buffer_load_b32(
+                               row_rsrc(h.onsf + rbase, in ? (uint32_t)nx * 4u : 0u), gi * 4, 0,
+                               0));
+            else
+                OD[q] = __builtin_bit_cast(
+                    double, __builtin_amdgcn_raw_buffer_load_b64(
+                                row_rsrc(h.ons + rbase, in ? (uint32_t)nx * 8u : 0u), gi * 8, 0,
+                                0));
+        };
+#pragma unroll
+        for (int r = 0; r < DS; ++r) load_state(r, r % PS);
+#pragma unroll
+        for (int r = 0; r < DL; ++r) load_acc(r, r);
+#pragma unroll
+        for (int r = 0; r < DR; ++r) load_row(r, r);
+        for (int t0 = 0; t0 < T; t0 += P) {
+#pragma unroll
+            for (int u = 0; u < P; ++u) {
+                const int tt = t0 + u;
+                load_state(tt + DS, (u + DS) % PS);
+                load_acc(tt + DL, (u + DL) % P);
+                load_row(tt + DR, (u + DR) % P);
+#pragma unroll
+                for (int s = 1; s <= K; ++s) {
+                    const int rho = tt - s;
+                    const int qp = ((u - s) % P + P) % P;
+                    const int qs = ((u - s) % PS + PS) % PS;
+                    const int q3 = ((u - s) % 3 + 3) % 3;
+                    const int q3m = (q3 + 2) % 3, q3p = (q3 + 1) % 3;
+                    const int qm = (qs + PS - 1) % PS, qq = (qs + 1) % PS;
+                    double2 xm1, x0, xp1, xo, ym1, y0, yp1, yo;
+                    if (s == 1) {
+                        xm1 = X0[qm]; x0 = X0[qs]; xp1 = X0[qq]; xo = Xm[qs];
+                        ym1 = Y0[qm]; y0 = Y0[qs]; yp1 = Y0[qq]; yo = Ym[qs];
+                    } else {
+                        xm1 = LP[s - 2][q3m]; x0 = LP[s - 2][q3]; xp1 = LP[s - 2][q3p];
+                        ym1 = LQ[s - 2][q3m]; y0 = LQ[s - 2][q3]; yp1 = LQ[s - 2][q3p];
+                        xo = s == 2 ? X0[qs] : LP[s - 3 < 0 ? 0 : s - 3][q3];
+                        yo = s == 2 ? Y0[qs] : LQ[s - 3 < 0 ? 0 : s - 3][q3];
+                    }
+                    const double o = ONSF ? (double)OF[qp] * inv_es : OD[qp];
+                    const double2 wh = lwt[4 * PI[qp]], wv2 = lwt[4 * PI[qp] + 1];
+                    const double2 xh = lwt[4 * PI[qp] + 2], xv2 = lwt[4 * PI[qp] + 3];
+                    // H~ p and [X, H~] p, then H~ q, each in slot order (one of
+                    // the two vertical terms has weight 0)
+                    const double2 xl = lane_prev(x0), xr = lane_next(x0);
+                    double2 hp = make_double2(o * x0.x, o * x0.y);
+                    double2 dp = make_double2(0.0, 0.0);
+                    hp = raxpy(hp, wh.x, xl);
+                    dp = raxpy(dp, xh.x, xl);
+                    hp = raxpy(hp, wh.y, xr);
+                    dp = raxpy(dp, xh.y, xr);
+                    hp = raxpy(hp, wv2.y, xm1);
+                    dp = raxpy(dp, xv2.y, xm1);
+                    hp = raxpy(hp, wv2.x, xp1);
+                    dp = raxpy(dp, xv2.x, xp1);
+                    double2 hq = make_double2(o * y0.x, o * y0.y);
+                    hq = raxpy(hq, wh.x, lane_prev(y0));
+                    hq = raxpy(hq, wh.y, lane_next(y0));
+                    hq = raxpy(hq, wv2.y, ym1);
+                    hq = raxpy(hq, wv2.x, yp1);
+                    const double2 po = rounded<V>(two_minus(hp, xo));
+                    const double2 qo = rounded<V>(two_minus(cadd(dp, hq), yo));
+                    LP[s - 1][q3] = po;
+                    LQ[s - 1][q3] = qo;
+                    AU[qp] = rounded<V>(cmla(AU[qp], ck.c[s - 1], po));
+                    AX[qp] = rounded<V>(cmla(AX[qp], ck.c[s - 1], qo));
+                    if (s >= K - 1) {
+                        const bool own = owned(rho);
+                        const int64_t row = (int64_t)(own ? j0 + rho - K : 0) * nx;
+                        const uint32_t nb = own ? rb : 0u;
+                        buf_st((s == K ? pout2 : pout1) + row, nb, ovo, po);
+                        buf_st((s == K ? qout2 : qout1) + row, nb, ovo, qo);
+                        if (s == K) {
+                            buf_st(accu + row, nb, ovo, AU[qp]);
+                            buf_st(accx + row, nb, ovo, AX[qp]);
+                        }
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+}
+
+template <typename V>
+void launch_evolve_x_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const double *pxw,
+                           const V *p1, const V *p0, V *pout1, V *pout2, const V *q1,
+                           const V *q0, V *qout1, V *qout2, V *accx, V *accu, const CoefK &ck,
+                           hipStream_t s) {
+#define KPM_EXK(ONSF_, K_)                                                                    \
+    hipLaunchKernelGGL((k_evolve_x_march<V, ONSF_, K_>), dim3(sw.nwg), dim3(kBlock), 0, s, h, \
+                       sw, lat, pxw, p1, p0, pout1, pout2, q1, q0, qout1, qout2, accx, accu, ck)
+#define KPM_EX(ONSF_)                                                                         \
+    switch (lat.k) {                                                                          \
+        case 3: KPM_EXK(ONSF_, 3); break;                                                     \
+        default: KPM_EXK(ONSF_, 2); break;                                                    \
+    }
+    if (h.onsf) { KPM_EX(true) }
+    else { KPM_EX(false) }
+#undef KPM_EX
+#undef KPM_EXK
+}
+
+template void launch_evolve_x_multi<double2>(const Ell &, const Sweep &, const Lat2 &,
+                                             const double *, const double2 *, const double2 *,
+                                             double2 *, double2 *, const double2 *,
+                                             const double2 *, double2 *, double2 *, double2 *,
+                                             double2 *, const CoefK &, hipStream_t);
+template void launch_evolve_x_multi<float2>(const Ell &, const Sweep &, const Lat2 &,
+                                            const double *, const float2 *, const float2 *,
+                                            float2 *, float2 *, const float2 *, const float2 *,
+                                            float2 *, float2 *, float2 *, float2 *,
+                                            const CoefK &, hipStream_t);
+
 }  // namespace kpm

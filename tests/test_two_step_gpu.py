@@ -170,6 +170,31 @@ def test_propagator_in_strips_equals_single_steps(geometry, nx, ny, steps, tiled
         assert rel_err(g2, ref) < 1e-12, (sign, nb)
 
 
+@pytest.mark.parametrize("geometry,nx,ny", SHAPES[:3])
+@pytest.mark.parametrize("steps,tiled", [(2, 5), (3, 5), (8, 5), (5, 3), (4, 4)])
+def test_commutator_propagator_in_strips_equals_single_steps(geometry, nx, ny, steps, tiled):
+    """[X, U(dt)] psi and U(dt) psi (Alg. 7) with up to three coupled steps per
+    pass in marching strips: the same results as single steps, and the
+    oracle's; term counts leave full passes, a short last pass, a single last
+    step, or no multi-step pass."""
+    _need_gpu()
+    c = recipe(geometry, nx, ny, w=1.1, vac=0.02, seed=5 * nx + ny)
+    _log(f"commutator propagator {geometry} {nx}x{ny} steps={steps} tiled={tiled}")
+    one, two = _pair(c, tiled=tiled, steps=steps)
+    lat = oracle_lattice(c)
+    for nb, dt in ((40, 1.0), (12, 0.3), (9, 0.2), (4, 0.2), (3, 0.1), (2, 0.05)):
+        phi = phases(c, 1, 5050 + nb)
+        rx, ru = oracle.evolve_x(lat, c["e_scale"], phi[:, 0], dt, nb)
+        outs = []
+        for sysg in (one, two):
+            d = sysg.upload(phi)
+            ox, ou = sysg.new_state(1), sysg.new_state(1)
+            kp.kpm_evolve_x(sysg, d, ox, ou, dt, nb)
+            outs.append((ox.cpu().numpy()[:, 0], ou.cpu().numpy()[:, 0]))
+        assert np.array_equal(outs[1][0], outs[0][0]) and np.array_equal(outs[1][1], outs[0][1]), nb
+        assert rel_err(outs[1][0], rx) < 1e-12 and rel_err(outs[1][1], ru) < 1e-12, nb
+
+
 @pytest.mark.parametrize("steps,tiled", [(5, 5), (8, 5)])
 def test_propagator_in_strips_fp32(steps, tiled):
     _need_gpu()
@@ -183,6 +208,12 @@ def test_propagator_in_strips_fp32(steps, tiled):
     assert np.array_equal(d2.cpu().numpy(), d1.cpu().numpy())
     ref = oracle.evolve(oracle_lattice(c), c["e_scale"], phi[:, 0], 0.8, 1, 30)
     assert rel_err(d2.cpu().numpy()[:, 0], ref) < 1e-5
+    outs = []
+    for sysg, d in ((one, d1), (two, d2)):
+        ox, ou = sysg.new_state(1), sysg.new_state(1)
+        kp.kpm_evolve_x(sysg, d, ox, ou, 0.8, 30)
+        outs.append((ox.cpu().numpy(), ou.cpu().numpy()))
+    assert np.array_equal(outs[1][0], outs[0][0]) and np.array_equal(outs[1][1], outs[0][1])
 
 
 @pytest.mark.parametrize("steps,tiled", [(2, 0), (4, 1), (4, 4)])
