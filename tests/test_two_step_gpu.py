@@ -216,7 +216,7 @@ def test_propagator_in_strips_fp32(steps, tiled):
     assert np.array_equal(outs[1][0], outs[0][0]) and np.array_equal(outs[1][1], outs[0][1])
 
 
-@pytest.mark.parametrize("steps,tiled", [(2, 0), (4, 1), (4, 4)])
+@pytest.mark.parametrize("steps,tiled", [(2, 0), (4, 1), (4, 4), (8, 5)])
 def test_graph_replays_match_eager(steps, tiled):
     _need_gpu()
     c = recipe("zgnr", 130, 38, w=1.0, vac=0.02, seed=11)
