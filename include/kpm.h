@@ -195,6 +195,9 @@ kpm_status kpm_moments_doubled(kpm_system *sys, int n_vec, const void *phi, int 
  * phi <- U(sign * dt) phi, U(t) = exp(-i H t / hbar), by the Chebyshev-Bessel
  * expansion with n_bessel terms (Eq. 36, Alg. 6); sign = +1 or -1 (U(-dt) =
  * U(dt)^dagger).  phi: device state, in place.  n_bessel >= 2.  Asynchronous.
+ * Where the moment sets of this system and n_vec run several steps per pass in
+ * marching strips (kpm_launch steps > 1, tiled >= 3), so does the recursion
+ * here after its first step, with the same result as single steps.
  */
 kpm_status kpm_evolve(kpm_system *sys, int n_vec, void *phi, double dt_fs,
                       int sign, int n_bessel);
@@ -203,6 +206,10 @@ kpm_status kpm_evolve(kpm_system *sys, int n_vec, void *phi, double dt_fs,
  * out_x <- [X, U(dt)] phi (Eq. 37 with the recursion Eq. 38-41, Alg. 7) and,
  * if out_u is not NULL, out_u <- U(dt) phi from the same recursion.  Device
  * states; out_x and out_u must not alias phi or each other.  Asynchronous.
+ * As for kpm_evolve, the coupled recursion takes up to three steps per pass in
+ * marching strips where the moment sets use strips and the commutator weights
+ * are the same for every row of a neighbour pattern; same result as single
+ * steps.
  */
 kpm_status kpm_evolve_x(kpm_system *sys, int n_vec, const void *phi, void *out_x,
                         void *out_u, double dt_fs, int n_bessel);
