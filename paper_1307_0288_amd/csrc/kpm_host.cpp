@@ -668,9 +668,10 @@ inline int moment_slots(int nm, bool dbl) { return dbl ? 2 * ((nm + 1) / 2) : nm
 // Launch plan of one moment set: partial slots [c0, c1) form one ring
 // segment (the first holds ring + 2 slots, C_0 and C_1 included, the others
 // ring), and inside a segment the recursion takes k-step launches while all k
-// steps fit and single steps otherwise.  visit(kind, m, c0) is called for
-// every recursion launch (kind 1 or k, first moment slot m) and
-// segment(c0, c1, m0) once a segment's launches are done.
+// steps fit, then one launch of the 2 .. k - 1 steps that still fit, and single
+// steps otherwise.  visit(kind, m, c0) is called for every recursion launch
+// (kind = steps of the launch, first moment slot m) and segment(c0, c1, m0)
+// once a segment's launches are done.
 template <typename F, typename G>
 void moment_plan(int slots, int ring, bool dbl, int k, F visit, G segment) {
     const int per_step = dbl ? 2 : 1;
@@ -678,7 +679,8 @@ void moment_plan(int slots, int ring, bool dbl, int k, F visit, G segment) {
         const int c1 = std::min(slots, c0 == 0 ? ring + 2 : c0 + ring);
         const int m0 = std::max(c0, 2);
         for (int m = m0; m < c1;) {
-            const int kind = (k > 1 && m + k * per_step <= c1) ? k : 1;
+            const int fit = (c1 - m) / per_step;          // whole steps left in the segment
+            const int kind = k > 1 ? std::max(1, std::min(k, fit)) : 1;
             visit(kind, m, c0);
             m += kind * per_step;
         }
@@ -735,8 +737,8 @@ kpm_status enqueue_moments(kpm_system *sys, const kpm::Sweep &sw, int ring, hipS
             if (kind > 1) {
                 V *o1 = free_state(p0, p1, nullptr);
                 V *o2 = free_state(p0, p1, o1);
-                kpm::launch_moment_multi<V>(h, sw, lat, p1, p0, o1, o2, phil, sys->partial,
-                                            m - c0, dbl, s);
+                kpm::launch_moment_multi<V>(h, sw, kind == k ? lat : sys->lat2(l, kind, sw.nwg),
+                                            p1, p0, o1, o2, phil, sys->partial, m - c0, dbl, s);
                 p0 = o1;
                 p1 = o2;
                 return;
