@@ -148,7 +148,10 @@ def main():
     two = multi_step(launch)
     bpu = bytes_launch / st["step_rows"] / (launch["steps"] if two else 1)
     achieved = achieved_gbs(st)
-    traffic = measured_traffic(TRAFFIC_FILE2 if two else TRAFFIC_FILE, st["step_rows"], launch)
+    # the VAC and MSD moment sets (all but the DOS set) keep only real parts
+    kname = moment_kernel_name("double2", launch, False, real=True)
+    traffic = measured_traffic(TRAFFIC_FILE2 if two else TRAFFIC_FILE, st["step_rows"], launch,
+                               kname if two else "")
 
     cpu = None
     if args.cpu_moments > 0:
@@ -173,7 +176,7 @@ def main():
                                "x 40 Bessel terms, dt=hbar/|t|",
                    "n_sites": n, "n_vec": 1, "n_moments": nm, "n_steps": ns,
                    "n_bessel": nb, "site_updates_per_step": st["site_updates"] // args.steps},
-        "roofline": {"kernel": moment_kernel_name("double2", launch, False), "bound": "hbm",
+        "roofline": {"kernel": kname, "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_site_update": round(bpu, 3),

@@ -281,14 +281,14 @@ struct kpm_system {
     hipStream_t cap = nullptr;
     struct GraphKey {
         const void *phil, *phir, *a, *b, *partial, *dmom;
-        int nm, vshift, groups, ilp, streaming, compact, tiled, steps, dbl;
+        int nm, vshift, groups, ilp, streaming, compact, tiled, steps, dbl, re;
         int64_t stride_r, offset;
         bool operator==(const GraphKey &o) const {
             return phil == o.phil && phir == o.phir && a == o.a && b == o.b &&
                    partial == o.partial && dmom == o.dmom && nm == o.nm && vshift == o.vshift &&
                    groups == o.groups && ilp == o.ilp && streaming == o.streaming &&
                    compact == o.compact && tiled == o.tiled && steps == o.steps &&
-                   dbl == o.dbl &&
+                   dbl == o.dbl && re == o.re &&
                    stride_r == o.stride_r &&
                    offset == o.offset;
         }
@@ -698,7 +698,7 @@ void moment_plan(int slots, int ring, bool dbl, int k, F visit, G segment) {
 // phir is only read.
 template <typename V>
 kpm_status enqueue_moments(kpm_system *sys, const kpm::Sweep &sw, int ring, hipStream_t s,
-                           bool events, bool dbl, const V *phil, const V *phir, int nm,
+                           bool events, bool dbl, bool re, const V *phil, const V *phir, int nm,
                            V *a_buf, V *b_buf, int64_t stride_r, int64_t offset) {
     const kpm_launch &l = sys->shape(sw.vshift, dbl);
     const kpm::Ell h = sys->ell_for(l);
@@ -738,7 +738,8 @@ kpm_status enqueue_moments(kpm_system *sys, const kpm::Sweep &sw, int ring, hipS
                 V *o1 = free_state(p0, p1, nullptr);
                 V *o2 = free_state(p0, p1, o1);
                 kpm::launch_moment_multi<V>(h, sw, kind == k ? lat : sys->lat2(l, kind, sw.nwg),
-                                            p1, p0, o1, o2, phil, sys->partial, m - c0, dbl, s);
+                                            p1, p0, o1, o2, phil, sys->partial, m - c0, dbl, re,
+                                            s);
                 p0 = o1;
                 p1 = o2;
                 return;
@@ -771,10 +772,13 @@ kpm_status enqueue_moments(kpm_system *sys, const kpm::Sweep &sw, int ring, hipS
 // Chebyshev moments of Alg. 5 for n_vec vector pairs (every sample), reduced
 // into sys->dmom[(s * R + r) * stride_r + offset + m] (complex).  With graphs
 // enabled the launch sequence is captured once per set of buffers and
-// replayed.  dbl selects the doubling form (phil must equal phir).
+// replayed.  dbl selects the doubling form (phil must equal phir).  re: the
+// caller uses only the real parts of the moments (their imaginary parts may
+// then be left at 0).
 template <typename V>
 kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir, int nm,
-                       V *a_buf, V *b_buf, int64_t stride_r, int64_t offset, bool dbl = false) {
+                       V *a_buf, V *b_buf, int64_t stride_r, int64_t offset, bool dbl = false,
+                       bool re = false) {
     const kpm_launch &l = sys->shape(vshift, dbl);
     kpm::Sweep sw;
     KPM_TRY(sys->sweep_with(vshift, l, &sw));
@@ -800,17 +804,17 @@ kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir
         sys->stats.step_bytes_total += n1 * b1 + n2 * b2;
     }
     if (!sys->graphs)
-        return enqueue_moments<V>(sys, sw, ring, sys->stream, sys->timing, dbl, phil, phir, nm,
-                                  a_buf, b_buf, stride_r, offset);
+        return enqueue_moments<V>(sys, sw, ring, sys->stream, sys->timing, dbl, re, phil, phir,
+                                  nm, a_buf, b_buf, stride_r, offset);
     kpm_system::GraphKey key{phil, phir, a_buf, b_buf, sys->partial, sys->dmom, nm, vshift,
                              l.groups_per_cu, l.ilp, l.streaming, l.compact, l.tiled, l.steps,
-                             dbl ? 1 : 0, stride_r, offset};
+                             dbl ? 1 : 0, re ? 1 : 0, stride_r, offset};
     hipGraphExec_t exec = sys->find_graph(key);
     if (!exec) {
         KPM_TRY(sys->ensure_capture_stream());
         KPM_HIP(hipStreamBeginCapture(sys->cap, hipStreamCaptureModeThreadLocal));
-        kpm_status st = enqueue_moments<V>(sys, sw, ring, sys->cap, false, dbl, phil, phir, nm,
-                                           a_buf, b_buf, stride_r, offset);
+        kpm_status st = enqueue_moments<V>(sys, sw, ring, sys->cap, false, dbl, re, phil, phir,
+                                           nm, a_buf, b_buf, stride_r, offset);
         hipGraph_t graph = nullptr;
         const hipError_t ec = hipStreamEndCapture(sys->cap, &graph);
         if (st != KPM_OK) {
@@ -1023,7 +1027,7 @@ kpm_status vac_run(kpm_system *sys, int vshift, V *psi_io, V *rr_io, bool start,
     if (start) {
         // R_0 = V phi; L_0 = V psi_0 = R_0
         kpm::launch_apply_d<V>(h, sw, psi, rr, alpha, sys->stream);
-        KPM_TRY(run_moments<V>(sys, vshift, rr, rr, nm, a, b, per_r, 0));
+        KPM_TRY(run_moments<V>(sys, vshift, rr, rr, nm, a, b, per_r, 0, false, true));
         row = 1;
     }
     for (int k = 1; k <= nsteps; ++k, ++row) {
@@ -1032,7 +1036,8 @@ kpm_status vac_run(kpm_system *sys, int vshift, V *psi_io, V *rr_io, bool start,
         KPM_TRY(run_evolve<V>(sys, vshift, rr, rr2, nullptr, dt, -1, np, a, b));
         std::swap(rr, rr2);
         kpm::launch_apply_d<V>(h, sw, psi, ll, alpha, sys->stream);
-        KPM_TRY(run_moments<V>(sys, vshift, ll, rr, nm, a, b, per_r, (int64_t)row * nm));
+        KPM_TRY(run_moments<V>(sys, vshift, ll, rr, nm, a, b, per_r, (int64_t)row * nm, false,
+                               true));
     }
     const size_t bytes = sys->state_bytes(vshift);
     if (psi != psi_io) KPM_HIP(hipMemcpyAsync(psi_io, psi, bytes, hipMemcpyDeviceToDevice, sys->stream));
@@ -1085,7 +1090,8 @@ kpm_status msd_run(kpm_system *sys, int vshift, V *psi_io, V *y_io, bool start, 
             KPM_TRY(run_evolve<V>(sys, vshift, y, y2, xu, dt, +1, np, pa, pb));
             std::swap(y, y2);                     // Y_k = U(dt) Y_{k-1} + [X, U(dt)] psi'
         }
-        KPM_TRY(run_moments<V>(sys, vshift, y, y, nm, pa, pb, per_r, (int64_t)row * nm, dbl));
+        KPM_TRY(run_moments<V>(sys, vshift, y, y, nm, pa, pb, per_r, (int64_t)row * nm, dbl,
+                               true));
     }
     const size_t bytes = sys->state_bytes(vshift);
     if (psi != psi_io) KPM_HIP(hipMemcpyAsync(psi_io, psi, bytes, hipMemcpyDeviceToDevice, sys->stream));
@@ -1205,7 +1211,7 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
             for (int k = 0; k < steps; ++k) {
                 if (ks > 1 && k + ks <= steps) {
                     kpm::launch_moment_multi<V>(h, sw, lat, p1, p0, o1, o2, phi, sys->partial, 0,
-                                                dbl, s);
+                                                dbl, false, s);
                     std::swap(p0, o1);
                     std::swap(p1, o2);
                     k += ks - 1;

@@ -135,11 +135,12 @@ void launch_moment_step_doubled(const Ell &h, const Sweep &sw, const V *p1, cons
 // p0 or each other.  Non-doubling: partial[slot + s - 1] = <L|phi_{n+s}>,
 // s = 1 .. k; doubling (phil unused): partial[slot + 2 (s - 1)] =
 // <phi_{n+s-1}|phi_{n+s-1}> and partial[slot + 2 (s - 1) + 1] =
-// <phi_{n+s-1}|phi_{n+s}>.
+// <phi_{n+s-1}|phi_{n+s}>.  re: only the real parts are needed (the marching
+// strips then skip the imaginary parts, which read 0; other forms ignore it).
 template <typename V>
 void launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V *p1,
                          const V *p0, V *out1, V *out2, const V *phil, double2 *partial,
-                         int slot, bool dbl, hipStream_t s);
+                         int slot, bool dbl, bool re, hipStream_t s);
 
 // Coefficients of the K steps of one multi-step propagator pass.
 constexpr int kMaxMarchSteps = 8;

@@ -1122,11 +1122,13 @@ constexpr int kRowRing = kMarchRows;
 constexpr int kDs = 3;
 constexpr uint32_t kOffNone = 0x80000000u;   // past the end of every row
 
-// MODE: kMarchDirect (moments <phi_L|phi_{n+s}>), kMarchDoubled (the two
-// doubling sums per level, phi_L unused) or kMarchBessel (the propagator's
-// accumulator: lacc holds acc, updated acc += c_{n+s} phi_{n+s} at each level
-// in step order and stored after level K; no inner products).
-constexpr int kMarchDirect = 0, kMarchDoubled = 1, kMarchBessel = 2;
+// MODE: kMarchDirect (moments <phi_L|phi_{n+s}>), kMarchDirectRe (their real
+// parts only, for callers that use no more: the same real parts, bit for
+// bit), kMarchDoubled (the two doubling sums per level, phi_L unused) or
+// kMarchBessel (the propagator's accumulator: lacc holds acc, updated acc +=
+// c_{n+s} phi_{n+s} at each level in step order and stored after level K; no
+// inner products).
+constexpr int kMarchDirect = 0, kMarchDoubled = 1, kMarchBessel = 2, kMarchDirectRe = 3;
 
 template <typename V, bool ONSF, int MODE, int K>
 __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const Lat2 &lat,
@@ -1134,7 +1136,8 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
                                             V *__restrict__ out2, V *__restrict__ lacc,
                                             double2 *__restrict__ partial, int slot,
                                             const CoefK &ck) {
-    constexpr bool DBL = MODE == kMarchDoubled, BES = MODE == kMarchBessel;
+    constexpr bool DBL = MODE == kMarchDoubled, BES = MODE == kMarchBessel,
+                   RE = MODE == kMarchDirectRe;
     constexpr int TC = kWave - 2 * K;                  // columns per strip
     constexpr int P = kRowRing, PS = kStateRing, DS = kDs, DR = kRowRing - 1 - K;
     // phi_L rows are loaded DL ahead and used through K iterations after their
@@ -1305,6 +1308,8 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
                         acc[2 * (s - 1)].x = fma(xw.x, x0.x, fma(xw.y, x0.y, acc[2 * (s - 1)].x));
                         acc[2 * (s - 1) + 1].x =
                             fma(xw.x, c.x, fma(xw.y, c.y, acc[2 * (s - 1) + 1].x));
+                    } else if (RE) {
+                        acc[s - 1].x = fma(LL[qp].x, c.x, fma(LL[qp].y, c.y, acc[s - 1].x));
                     } else {
                         acc[s - 1] = cdot_acc(acc[s - 1], LL[qp], c);
                     }
@@ -1336,6 +1341,19 @@ __global__ __launch_bounds__(kBlock, 2) void k_moment_march(Ell h, Sweep sw, Lat
                                                          int slot) {
     march_sweep<V, ONSF, DBL ? kMarchDoubled : kMarchDirect, K>(
         h, sw, lat, p1, p0, out1, out2, const_cast<V *>(phil), partial, slot, CoefK{});
+}
+
+// k_moment_march's direct form accumulating only Re <phi_L|phi_{n+s}>.
+template <typename V, bool ONSF, int K>
+__global__ __launch_bounds__(kBlock, 2) void k_moment_march_re(Ell h, Sweep sw, Lat2 lat,
+                                                            const V *p1, const V *p0,
+                                                            V *__restrict__ out1,
+                                                            V *__restrict__ out2,
+                                                            const V *__restrict__ phil,
+                                                            double2 *__restrict__ partial,
+                                                            int slot) {
+    march_sweep<V, ONSF, kMarchDirectRe, K>(h, sw, lat, p1, p0, out1, out2, const_cast<V *>(phil),
+                                            partial, slot, CoefK{});
 }
 
 // K steps of the Chebyshev-Bessel propagator (Alg. 6) per pass: the states as
@@ -1488,7 +1506,7 @@ void launch_kpm_sum(const double *mom, int rows, int nm, const double *w, const 
 template <typename V>
 void launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V *p1,
                          const V *p0, V *out1, V *out2, const V *phil, double2 *partial,
-                         int slot, bool dbl, hipStream_t s) {
+                         int slot, bool dbl, bool re, hipStream_t s) {
     const bool onsf = h.onsf != nullptr;
 #define KPM_LDS2(NT_, ONSF_, DBL_)                                                            \
     hipLaunchKernelGGL((k_moment_step2<V, NT_, ONSF_, DBL_, 16>), dim3(sw.nwg), dim3(kBlock),  \
@@ -1503,8 +1521,15 @@ void launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
         else KPM_REGK(ONSF_, DBL_, TJ_, 2);                                                   \
     } while (0)
 #define KPM_MARCHK(ONSF_, DBL_, K_)                                                          \
-    hipLaunchKernelGGL((k_moment_march<V, ONSF_, DBL_, K_>), dim3(sw.nwg), dim3(kBlock), 0, s, \
-                       h, sw, lat, p1, p0, out1, out2, phil, partial, slot)
+    do {                                                                                      \
+        if (!(DBL_) && re)                                                                    \
+            hipLaunchKernelGGL((k_moment_march_re<V, ONSF_, K_>), dim3(sw.nwg), dim3(kBlock),  \
+                               0, s, h, sw, lat, p1, p0, out1, out2, phil, partial, slot);    \
+        else                                                                                  \
+            hipLaunchKernelGGL((k_moment_march<V, ONSF_, DBL_, K_>), dim3(sw.nwg),            \
+                               dim3(kBlock), 0, s, h, sw, lat, p1, p0, out1, out2, phil,      \
+                               partial, slot);                                                \
+    } while (0)
 #define KPM_REG(ONSF_, DBL_)                                                                  \
     do {                                                                                      \
         if (lat.reg == 2) {                                                                   \
@@ -1580,7 +1605,7 @@ void launch_evolve_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
                                 hipStream_t);                                               \
     template void launch_moment_multi<V>(const Ell &, const Sweep &, const Lat2 &, const V *, \
                                          const V *, V *, V *, const V *, double2 *, int,    \
-                                         bool, hipStream_t);                                \
+                                         bool, bool, hipStream_t);                          \
     template void launch_evolve_multi<V>(const Ell &, const Sweep &, const Lat2 &, const V *, \
                                          const V *, V *, V *, V *, const CoefK &,           \
                                          hipStream_t);

@@ -45,15 +45,19 @@ def multi_step(launch: dict, n_vec: int = 1) -> bool:
     return launch.get("steps", 1) >= 2 and n_vec == 1 and bool(launch["compact"])
 
 
-def moment_kernel_name(v: str, launch: dict, dbl: bool, n_vec: int = 1) -> str:
+def moment_kernel_name(v: str, launch: dict, dbl: bool, n_vec: int = 1,
+                       real: bool = False) -> str:
     """Instantiation of the moment step for a graphene system from the builder
-    (width 3, uniform hopping, float-exact on-site terms, at least 16 chains)
-    under a launch shape."""
+    (width 3, uniform hopping, float-exact on-site terms, at least 24 chains)
+    under a launch shape; real: the moment sets whose callers keep only the
+    real parts (VAC and MSD), which the marching strips accumulate alone."""
     nt, db = ("true" if launch["streaming"] else "false"), ("true" if dbl else "false")
     if multi_step(launch, n_vec):
         k, tiled = launch["steps"], launch["tiled"]
         if k == 2 and tiled == 0:
             return f"k_moment_step2<{v},{nt},true,{db},16>"
+        if tiled >= 3 and real and not dbl:
+            return f"k_moment_march_re<{v},true,{k}>"
         if tiled >= 3:
             return f"k_moment_march<{v},true,{db},{k}>"
         return f"k_moment_stepk<{v},true,{db},{4 if tiled == 2 else 8},{k}>"
@@ -87,10 +91,11 @@ def kernel_sha(launch: dict | None = None) -> str:
     return hashlib.sha256((head + t[a:b]).encode()).hexdigest()[:16]
 
 
-def measured_traffic(path: str, step_rows: int, launch: dict):
+def measured_traffic(path: str, step_rows: int, launch: dict, kernel: str = ""):
     """HBM bytes per moment-step launch from a committed counter summary (one
     record, or {"records": [...]} for several launch shapes), or None when
-    no record matches this kernel version, size and launch shape."""
+    no record matches this kernel version, size and launch shape (and, when
+    given, kernel name)."""
     try:
         with open(path) as f:
             t = json.load(f)
@@ -100,7 +105,8 @@ def measured_traffic(path: str, step_rows: int, launch: dict):
     for r in t.get("records", [t]):
         stored = dict({"steps": 1}, **r.get("launch_shape", {}))
         if r.get("kernel_sha") == sha and r.get("step_rows") == step_rows \
-                and stored == dict({"steps": 1}, **launch):
+                and stored == dict({"steps": 1}, **launch) \
+                and (not kernel or r.get("kernel", "").split(" ")[0] == kernel):
             return r.get("bytes_per_launch")
     return None
 
@@ -115,6 +121,14 @@ def _read_counter(d: str):
     if not rows:
         raise SystemExit(f"no counter_collection.csv under {d}")
     return rows
+
+
+def _dispatch_sums(rows):
+    """Counter value per dispatch (summed over the rows of its instances)."""
+    out = {}
+    for r in rows:
+        out[r["Dispatch_Id"]] = out.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    return out
 
 
 def _mean(vals):
@@ -132,9 +146,11 @@ def summarize(fetch_dir: str, write_dir: str, meta_path: str, out_path: str):
     res = {}
     for key, d in (("fetch", fetch_dir), ("write", write_dir)):
         rows = _read_counter(d)
-        copies = [r for r in rows if r["Kernel_Name"] == "__amd_rocclr_copyBuffer"]
-        big = max(int(r["Grid_Size"]) for r in copies)
-        copy_kib = _mean(float(r["Counter_Value"]) for r in copies if int(r["Grid_Size"]) == big)
+        # the calibration copies: the largest device copies of the run (a
+        # workload's own state copies, of one state each, are far smaller)
+        copies = _dispatch_sums(r for r in rows if r["Kernel_Name"] == "__amd_rocclr_copyBuffer")
+        big = max(copies.values())
+        copy_kib = _mean(v for v in copies.values() if v >= 0.5 * big)
         step = _mean(float(r["Counter_Value"]) for r in rows
                      if r["Kernel_Name"].startswith(step_prefix))
         res[key] = (step, meta["copy_mib"] * 1024.0 / copy_kib)
@@ -187,6 +203,9 @@ def main():
     ap.add_argument("--n-vec", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--doubled", action="store_true", help="doubling form (kpm_moments_doubled)")
+    ap.add_argument("--real", action="store_true",
+                    help="a real-part moment set as the VAC takes them (kpm_vac, no time steps: "
+                         "the moments of V phi)")
     ap.add_argument("--copy-mib", type=int, default=512)
     ap.add_argument("--copies", type=int, default=3)
     ap.add_argument("--launch", default="",
@@ -229,6 +248,8 @@ def main():
     kp.kpm_reset_stats(sysg)
     if args.doubled:
         mu = kp.kpm_moments_doubled(sysg, phi, args.moments)
+    elif args.real:
+        mu = kp.kpm_vac(sysg, phi, 0, p["dt_fs"], p["n_bessel"], args.moments)[:, 0, :]
     else:
         mu = kp.kpm_moments(sysg, phi, phi, args.moments)
     st = kp.kpm_get_stats(sysg)
@@ -247,12 +268,14 @@ def main():
                f"--copy-mib {args.copy_mib}"]
         if args.doubled:
             cmd.append("--doubled")
+        if args.real:
+            cmd.append("--real")
         if args.launch:
             cmd.append(f"--launch {args.launch}")
         if args.autotune:
             cmd.append(f"--autotune {args.autotune}")
         meta = {
-            "kernel": f"{moment_kernel_name(v, launch, args.doubled, args.n_vec)} "
+            "kernel": f"{moment_kernel_name(v, launch, args.doubled, args.n_vec, args.real)} "
                       f"({args.precision}, {args.n_vec} vector(s))",
             "kernel_sha": kernel_sha(launch),
             "step_rows": st["step_rows"],

@@ -218,6 +218,22 @@ def test_propagator_in_strips_fp32(steps, tiled):
     assert np.array_equal(outs[1][0], outs[0][0]) and np.array_equal(outs[1][1], outs[0][1])
 
 
+@pytest.mark.parametrize("steps,tiled", [(8, 5), (5, 3), (4, 1)])
+def test_real_part_moment_sets_equal_complex_ones(steps, tiled):
+    """The VAC takes its moments as real parts only (the strips then skip the
+    imaginary parts): at t = 0 (R_0 = L_0 = V phi) they equal, bit for bit, the
+    real parts of kpm_moments on V phi under the same launch shape."""
+    _need_gpu()
+    c = recipe("sheet", 200, 40, w=1.0, vac=0.02, seed=29)
+    _log(f"real-part moments sheet 200x40 steps={steps} tiled={tiled}")
+    _, two = _pair(c, tiled=tiled, steps=steps)
+    phi = phases(c, 1, 5200)
+    psi, r = two.upload(phi), two.new_state(1)
+    got = kp.kpm_vac_continue(two, psi, r, True, 0, 0.5, 20, 91)
+    ref = kp.kpm_moments(two, r, r, 91)
+    assert np.array_equal(np.asarray(got).reshape(-1), ref.real.reshape(-1))
+
+
 @pytest.mark.parametrize("steps,tiled", [(2, 0), (4, 1), (4, 4), (8, 5)])
 def test_graph_replays_match_eager(steps, tiled):
     _need_gpu()
