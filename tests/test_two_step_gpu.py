@@ -129,7 +129,7 @@ def test_fp32_states_equal_single_step(steps, tiled):
     assert rel_err(m2, ref, scale) < 1e-4
 
 
-@pytest.mark.parametrize("kind", ["vac", "msd"])
+@pytest.mark.parametrize("kind", ["vac", "msd", "msd_doubled"])
 @pytest.mark.parametrize("steps,tiled", [(2, 0), (3, 2), (4, 3), (8, 5)])
 def test_time_loops_with_two_step_moments(kind, steps, tiled):
     _need_gpu()
@@ -137,13 +137,32 @@ def test_time_loops_with_two_step_moments(kind, steps, tiled):
     _log(f"{kind} sheet 130x26 steps={steps}")
     one, two = _pair(c, tiled=tiled, steps=steps)
     phi = phases(c, 1, 4700)
-    fn = kp.kpm_vac if kind == "vac" else kp.kpm_msd
+    fn = {"vac": kp.kpm_vac, "msd": kp.kpm_msd, "msd_doubled": kp.kpm_msd_doubled}[kind]
     got = fn(two, two.upload(phi), 3, 0.5, 20, 61)
     lat = oracle_lattice(c)
     ofn = oracle.vac if kind == "vac" else oracle.msd
     ref = ofn(lat, c["e_scale"], phi[:, 0], 3, 0.5, 20, 61)
     assert got.shape == (1, 4, 61)
     assert rel_err(got[0], ref) < 1e-10
+
+
+@pytest.mark.parametrize("kind", ["vac", "msd"])
+def test_resumed_loops_in_strips_equal_one_call(kind):
+    """A VAC / MSD run split into two resumable calls gives, bit for bit, the
+    moments of one uninterrupted call, with moments and both propagators in
+    eight-step strips."""
+    _need_gpu()
+    c = recipe("zgnr", 130, 38, w=1.0, vac=0.02, seed=31)
+    _log(f"resumed {kind} zgnr 130x38 steps=8")
+    _, two = _pair(c, tiled=5, steps=8)
+    phi = phases(c, 1, 5300)
+    fn = kp.kpm_vac if kind == "vac" else kp.kpm_msd
+    cont = kp.kpm_vac_continue if kind == "vac" else kp.kpm_msd_continue
+    whole = np.asarray(fn(two, two.upload(phi), 4, 0.5, 20, 45)).reshape(5, 45)
+    psi, r = two.upload(phi), two.new_state(1)
+    first = np.asarray(cont(two, psi, r, True, 2, 0.5, 20, 45)).reshape(3, 45)
+    rest = np.asarray(cont(two, psi, r, False, 2, 0.5, 20, 45)).reshape(2, 45)
+    assert np.array_equal(np.concatenate([first, rest]), whole)
 
 
 EVOLVE = [(2, 5), (3, 5), (5, 5), (6, 5), (8, 5), (7, 3), (8, 4)]
