@@ -331,7 +331,10 @@ struct kpm_system {
     // chain lattice, compact form; 3 and 4 steps need the graphene slot order,
     // else 2), 1 otherwise.
     int multi_steps(int vshift, const kpm_launch &l) const {
-        if (!d_code || vshift != 0 || l.steps < 2 || !l.compact || l2ny < kpm::kMinChains)
+        // the tiles address a row through a buffer resource of 32-bit byte size,
+        // with offsets from 2^31 up as the "no access" offset
+        if (!d_code || vshift != 0 || l.steps < 2 || !l.compact || l2ny < kpm::kMinChains ||
+            (int64_t)l2nx * (int64_t)sizeof(double2) >= ((int64_t)1 << 31))
             return 1;
         return d_flags ? l.steps : 2;
     }
