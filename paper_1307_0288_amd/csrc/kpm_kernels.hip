@@ -1103,11 +1103,14 @@ __global__ __launch_bounds__(kBlock) void k_moment_stepk(Ell h, Sweep sw, Lat2 l
 // computed once per level except the K - 1 boundary rows at each end of the
 // strip, instead of once per tile as in k_moment_stepk.  phi_n, phi_{n-1} and
 // phi_L are loaded kDs rows ahead (phi_L fewer at K = 8), the pattern id and
-// on-site term kRowRing - 1 - K rows ahead; a row's slot weights (from a per-pattern table
-// in LDS: t or 0 for the previous column, the next column, the next chain and
-// the previous chain) and scaled on-site term are formed one iteration before
-// their first use.  The loop is unrolled by kRowRing (a multiple of
-// kStateRing and of 3) so every ring index is a compile-time constant.
+// on-site term kRowRing - 1 - K rows ahead; a row's slot weights (from a
+// per-pattern table in LDS: t or 0 for the previous column, the next column,
+// the next chain and the previous chain) and scaled on-site term are formed
+// one iteration before their first use up to K = 5, and at each level above
+// (their registers then go to the level rings).  The loop is unrolled by
+// kRowRing (a multiple of kStateRing and of 3) so every ring index is a
+// compile-time constant.  The same walk serves the moments (direct, real
+// parts only, doubling) and the propagator (MODE below).
 // The loop body has no branch: a strip runs whole passes of kRowRing rows,
 // rows past the window load as zeros (buffer resources of size 0), levels are
 // computed on every row (a value of a row outside a level's range is finite
