@@ -29,10 +29,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 import kpm_inputs as ki  # noqa: E402
-from paper_1307_0288_amd.profile_run import (measured_traffic, moment_kernel_name,  # noqa: E402
-                                              multi_step)
+from profile_run import (float_onsite, measured_traffic, moment_kernel_name,  # noqa: E402
+                         multi_step)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 vector
+# instruction per SIMD every 4 cycles (16 lanes per cycle; the FP64 FMA at this
+# rate is the published 78.6 TFLOP/s)
+VALU_PEAK_GINST = 256 * 4 * 2.4 / 4
+SQ_FILE = os.path.join(ROOT, "profiles", "moment_multistep_fp64_paper_sq.json")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "moment_step_fp64_paper_traffic.json")
 TRAFFIC_FILE_DBL = os.path.join(ROOT, "profiles", "moment_step_doubled_fp64_paper_traffic.json")
 TRAFFIC_FILE2 = os.path.join(ROOT, "profiles", "moment_multistep_fp64_paper_traffic.json")
@@ -49,21 +54,91 @@ def achieved_gbs(st) -> float:
     return st["step_bytes_total"] / max(st["step_ms"], 1e-9) / 1e6
 
 
+def host_cores() -> int:
+    """Host threads this process may use: the CPU affinity set, capped by
+    OMP_NUM_THREADS when that is set (the share of the host given to one GPU)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, min(n, int(env))) if env.isdigit() else max(1, n)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(p, lat_args, n_moments: int):
-    """The oracle's moment recursion on a bounded sample of the same sheet."""
+    """The oracle's moment recursion on a bounded sample of the same sheet, on
+    one core and on all the host cores this process may use (the oracle's row
+    loops split over threads; its inner products stay serial)."""
     import oracle
     c_ons, c_act = lat_args
     lat = oracle.graphene(p["nx"], p["ny"], "sheet", p["t"], c_ons, c_act)
     phi = ki.random_phase(lat.n, 1, 3000, c_act)[:, 0]
-    t0 = time.perf_counter()
-    oracle.moments(lat, p["e_scale"], phi, phi, n_moments)
-    dt = time.perf_counter() - t0
     ups = (n_moments - 1) * lat.n
-    return {"value": round(ups / dt / 1e9, 5), "unit": "Gsite-updates/s", "cores": 1,
+    rates = {}
+    cores = host_cores()
+    for th in (1, cores):
+        oracle.set_threads(th)
+        t0 = time.perf_counter()
+        oracle.moments(lat, p["e_scale"], phi, phi, n_moments)
+        rates[th] = (ups / (time.perf_counter() - t0) / 1e9, time.perf_counter() - t0)
+    sample = (f"{n_moments} Chebyshev moments (phi_2 = 2H~phi_1 - phi_0 plus the inner product) "
+              f"on the full {lat.n}-site sheet, one vector, complex128 C oracle")
+    return {"value": round(rates[cores][0], 5), "unit": "Gsite-updates/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{n_moments} Chebyshev moments (phi_2 = 2H~phi_1 - phi_0 plus the "
-                      f"inner product) on the full {lat.n}-site sheet, one vector, "
-                      f"serial complex128 C, {dt:.1f} s"}
+            "sample": f"{sample}, row loops on {cores} threads, {rates[cores][1]:.1f} s",
+            "all_cores": {"value": round(rates[cores][0], 5), "cores": cores},
+            "one_core": {"value": round(rates[1][0], 5), "cores": 1,
+                         "seconds": round(rates[1][1], 1)},
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
+
+
+def copy_ceiling_gbs(gib: float = 1.0, reps: int = 10) -> float:
+    """Device-to-device copy rate of two buffers beyond every cache (read +
+    write bytes per second, best of 3 rounds): the streaming rate this box
+    reaches in practice, below the 8 TB/s of the data sheet."""
+    import torch
+    n = int(gib * (1 << 30)) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = 0.0
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = max(best, 2 * 8 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(best, 1)
+
+
+def valu_record(path: str, step_rows: int, launch: dict, kernel: str):
+    """Vector instructions per launch of the dominant kernel from a committed
+    SQ-counter record (same kernel source, size, shape and name), or None."""
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    from profile_run import kernel_sha
+    sha = kernel_sha(launch)
+    for r in t.get("records", [t]):
+        if r.get("kernel_sha") == sha and r.get("step_rows") == step_rows \
+                and dict({"steps": 1}, **r.get("launch_shape", {})) == dict({"steps": 1}, **launch) \
+                and r.get("kernel", "").split(" ")[0] == kernel:
+            return r
+    return None
 
 
 def main():
@@ -71,7 +146,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-moments", type=int, default=800,
+    ap.add_argument("--cpu-moments", type=int, default=400,
                     help="moments in the oracle's CPU-baseline sample (0 skips it)")
     ap.add_argument("--workload", default="paper",
                     choices=["paper", "batched", "ragged", "doubled", "ballistic", "learned",
@@ -85,6 +160,10 @@ def main():
                          "DOS by KPM vs the Fourier-transform method at equal resolution")
     ap.add_argument("--samples", type=int, default=2000,
                     help="learned workload: generated samples (the last 10 %% are held out)")
+    ap.add_argument("--onsite", default="f64", choices=["f64", "f32"],
+                    help="paper workload: the generator's disorder draw (f64, default), or the "
+                         "same draw rounded to float32 (f32: the library then stores the on-site "
+                         "terms in 4 bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -115,6 +194,9 @@ def main():
     log(f"inputs: {p['nx']}x{p['ny']} sheet, {n} sites")
     act = ki.vacancy_mask(n, p["vac"], 2000)
     ons = ki.anderson_onsite(n, p["w"], 1000)
+    if args.onsite == "f32":
+        ons = ons.astype(np.float32).astype(np.float64)
+    onsf = float_onsite(ons)
     phi_h = ki.random_phase(n, 1, 3000, act)
     sysg = kp.graphene_system(p["nx"], p["ny"], "sheet", p["t"], ons, act, p["e_scale"], "fp64")
     phi = sysg.upload(phi_h)
@@ -149,13 +231,24 @@ def main():
     bpu = bytes_launch / st["step_rows"] / (launch["steps"] if two else 1)
     achieved = achieved_gbs(st)
     # the VAC and MSD moment sets (all but the DOS set) keep only real parts
-    kname = moment_kernel_name("double2", launch, False, real=True)
-    traffic = measured_traffic(TRAFFIC_FILE2 if two else TRAFFIC_FILE, st["step_rows"], launch,
-                               kname if two else "")
+    kname = moment_kernel_name("double2", launch, False, real=True, onsf=onsf)
+    tfile = TRAFFIC_FILE2 if two else TRAFFIC_FILE
+    traffic = measured_traffic(tfile, st["step_rows"], launch, kname if two else "")
+    sq = valu_record(SQ_FILE, st["step_rows"], launch, kname)
+    launch_s = launch_ms * 1e-3
+    hbm = (traffic if traffic is not None else bytes_launch) / launch_s / 1e9
+    roofs = {"hbm": round(hbm / HBM_PEAK_GBS, 4)}
+    valu = None
+    if sq is not None:
+        valu = sq["valu_insts_per_launch"] / launch_s / 1e9
+        roofs["alu"] = round(valu / VALU_PEAK_GINST, 4)
+    bound = max(roofs, key=roofs.get)
+    log("copy ceiling")
+    ceiling = copy_ceiling_gbs()
 
     cpu = None
     if args.cpu_moments > 0:
-        log(f"cpu baseline: oracle, {args.cpu_moments} moments")
+        log(f"cpu baseline: oracle, {args.cpu_moments} moments, 1 core and all cores")
         cpu = cpu_baseline(p, (ons, act), args.cpu_moments)
 
     out = {
@@ -172,15 +265,39 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "graphene sheet 2828x1414 sites (3998792), 0.5% vacancies, "
-                               "W=0.1 eV, 1 random-phase vector, 3000 moments, VAC+MSD 20 steps "
+                               "W=0.1 eV" + (" (on-site draw rounded to float32)"
+                                             if args.onsite == "f32" else "") +
+                               ", 1 random-phase vector, 3000 moments, VAC+MSD 20 steps "
                                "x 40 Bessel terms, dt=hbar/|t|",
                    "n_sites": n, "n_vec": 1, "n_moments": nm, "n_steps": ns,
-                   "n_bessel": nb, "site_updates_per_step": st["site_updates"] // args.steps},
-        "roofline": {"kernel": kname, "bound": "hbm",
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                   "n_bessel": nb, "onsite_bytes": 4 if onsf else 8,
+                   "site_updates_per_step": st["site_updates"] // args.steps},
+        "roofline": {"kernel": kname, "bound": bound,
+                     **({"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4)} if bound == "hbm" else
+                        {"achieved": round(valu, 1), "peak": VALU_PEAK_GINST,
+                         "unit": "G VALU wave-instructions/s",
+                         "frac": round(valu / VALU_PEAK_GINST, 4),
+                         "hbm_algorithmic_gbs": round(achieved, 1)}),
+                     "traffic": traffic,
+                     "traffic_source": (f"lookup: {os.path.relpath(tfile, ROOT)} (rocprofv3 "
+                                        "FETCH_SIZE + WRITE_SIZE, calibrated, same kernel "
+                                        "source, size and shape; not measured in this run)")
+                                       if traffic is not None else None,
+                     "bound_by": {"roof": bound, "frac_of_peak": roofs,
+                                  "hbm_gbs": round(hbm, 1),
+                                  "hbm_basis": "measured traffic" if traffic is not None
+                                               else "algorithmic bytes",
+                                  "valu_ginst_per_s": None if valu is None else round(valu, 1),
+                                  "valu_peak_ginst_per_s": VALU_PEAK_GINST,
+                                  "valu_source": (f"lookup: {os.path.relpath(SQ_FILE, ROOT)} "
+                                                  "(rocprofv3 SQ_INSTS_VALU)") if sq else None},
+                     "copy_ceiling_gbs": ceiling,
+                     "frac_of_copy_ceiling": round(hbm / ceiling, 4),
                      "bytes_per_site_update": round(bpu, 3),
                      "avg_launch_us": round(launch_ms * 1e3, 3),
+                     "timing": "HIP events around each run of launches on the library's stream "
+                               "(mean over the timed steps; direct launches, no graph replay)",
                      "launches": st["step_launches"], "launch_shape": launch},
         "cpu_baseline": cpu,
     }

@@ -472,6 +472,15 @@ typedef struct {
     int32_t steps;
 } kpm_launch;
 
+/* The shape a new system starts with for n_vec vectors per row (both forms):
+ * the default above with the environment overrides KPM_GROUPS_PER_CU,
+ * KPM_ILP, KPM_STREAMING, KPM_COMPACT_LAUNCH, KPM_TILED and KPM_STEPS applied,
+ * each clamped to its range and combined into a valid shape (more than 4
+ * steps select the strips, a traversal below 3 caps the steps at 4, single
+ * steps take a traversal of at most 3).  Host only; kpm_system_create reads
+ * the same environment.  KPM_ERR_INVALID for a bad n_vec or precision. */
+kpm_status kpm_default_launch(int n_vec, kpm_precision precision, kpm_launch *out);
+
 /* kpm_set_launch sets the shape of both forms (direct and doubling);
  * kpm_get_launch returns the direct form's. */
 kpm_status kpm_set_launch(kpm_system *sys, int n_vec, const kpm_launch *launch);

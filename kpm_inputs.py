@@ -43,14 +43,10 @@ def uniform(seed: int, count: int, offset: int = 0) -> np.ndarray:
 
 
 def anderson_onsite(n_sites: int, w_ev: float, seed: int) -> np.ndarray:
-    """On-site energies uniform in [-W/2, W/2) eV, one per site index.
-
-    Returned as float64 holding values rounded to the nearest float32, so
-    that they are exactly representable in single precision as well.
-    """
+    """On-site energies uniform in [-W/2, W/2) eV, one per site index (float64)."""
     if w_ev == 0.0:
         return np.zeros(n_sites, dtype=np.float64)
-    return (w_ev * (uniform(seed, n_sites) - 0.5)).astype(np.float32).astype(np.float64)
+    return w_ev * (uniform(seed, n_sites) - 0.5)
 
 
 def vacancy_mask(n_sites: int, fraction: float, seed: int) -> np.ndarray:
@@ -139,15 +135,15 @@ def sheet_config(name: str) -> dict:
 
 def learned_sample_specs(count: int, seed: int) -> list:
     """Disordered sheets for the learned reconstruction: per sample a vacancy
-    fraction uniform in [0, 0.02) and an Anderson width W uniform in [0, 2) eV
-    (W rounded to a float32 value), and the seeds of its disorder, vacancies and
-    random vectors (1000 + k, 2000 + k, 3000 + 100 k with k = seed + index)."""
+    fraction uniform in [0, 0.02) and an Anderson width W uniform in [0, 2) eV,
+    and the seeds of its disorder, vacancies and random vectors (1000 + k,
+    2000 + k, 3000 + 100 k with k = seed + index)."""
     u = uniform(seed, 2 * count)
     out = []
     for s in range(count):
         k = seed + s
         out.append(dict(vac=float(0.02 * u[2 * s]),
-                        w=float(np.float32(2.0 * u[2 * s + 1])),
+                        w=float(2.0 * u[2 * s + 1]),
                         onsite_seed=1000 + k, vac_seed=2000 + k, vec_seed=3000 + 100 * k))
     return out
 

@@ -10,11 +10,11 @@ import this package.  The GPU library never does, and this package never
 imports the GPU library.
 """
 from .core import (HBAR_EV_FS, BOND_NM, Lattice, graphene, moments, bessel_j,
-                   evolve, evolve_x, vac, msd, dense_h, dense_d, fourier_moments)
+                   evolve, evolve_x, vac, msd, dense_h, dense_d, fourier_moments, set_threads)
 from .recon import (jackson, kpm_sum, dos, sigma_gk, sigma_e1, sigma_e2,
                     energies_grid, hanning, ftm_sum)
 
 __all__ = ["HBAR_EV_FS", "BOND_NM", "Lattice", "graphene", "moments", "bessel_j",
-           "evolve", "evolve_x", "vac", "msd", "dense_h", "dense_d", "fourier_moments",
+           "evolve", "evolve_x", "vac", "msd", "dense_h", "dense_d", "fourier_moments", "set_threads",
            "jackson", "kpm_sum", "dos", "sigma_gk", "sigma_e1", "sigma_e2", "energies_grid",
            "hanning", "ftm_sum"]

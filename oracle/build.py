@@ -1,4 +1,4 @@
-"""Compile the C oracle (test infrastructure) into oracle/liborc.so with gcc."""
+"""Compile the C oracle (test infrastructure) into oracle/liborc.so with gcc (OpenMP)."""
 from __future__ import annotations
 
 import os
@@ -12,7 +12,9 @@ LIB = os.path.join(HERE, "liborc.so")
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-Wextra",
+    # OpenMP splits the row loops over threads; results do not depend on the
+    # thread count (the inner products stay serial)
+    cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
            "-o", tmp, SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -36,6 +36,8 @@ def load(path):
     lib = C.CDLL(path)
     i64, dp, ip = C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_int64)
     up = C.POINTER(C.c_ubyte)
+    lib.orc_set_threads.restype = C.c_int
+    lib.orc_set_threads.argtypes = [C.c_int]
     lib.orc_graphene.restype = i64
     lib.orc_graphene.argtypes = [i64, i64, C.c_int, C.c_double, up, ip, ip, dp, dp]
     ham = [i64, ip, ip, dp, dp, dp, C.c_double]
@@ -53,6 +55,12 @@ def load(path):
         f.restype = C.c_int
         f.argtypes = ham + [C.c_double, dp, C.c_int, C.c_double, C.c_int, C.c_int, dp]
     return lib
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads of the oracle's parallel row loops (n >= 1 sets them); returns
+    the count in use.  Results are the same for every count."""
+    return _lib().orc_set_threads(int(n))
 
 
 def _p(a, t=C.c_double):

@@ -206,6 +206,40 @@ kpm_launch default_launch(int vshift, kpm_precision prec) {
     return l;
 }
 
+// The default shape for 2^vshift vectors with the KPM_* environment overrides
+// applied (KPM_GROUPS_PER_CU, KPM_ILP, KPM_STREAMING, KPM_COMPACT_LAUNCH,
+// KPM_TILED, KPM_STEPS; each value clamped to its range).  A shape must stay
+// one the kernels exist for: more than 4 steps per pass run only in the
+// marching strips (KPM_STEPS above 4 selects them), a traversal below the
+// strips caps the steps at 4, and single steps take a traversal of at most 3
+// (row order when the default was a strip shape).  KPM_ERR_INVALID when the
+// result is still not a valid shape.
+kpm_status env_launch(int vshift, kpm_precision prec, kpm_launch *out) {
+    kpm_launch l = default_launch(vshift, prec);
+    if (const char *env = std::getenv("KPM_GROUPS_PER_CU"))
+        l.groups_per_cu = std::max(1, std::min(32, atoi(env)));
+    if (const char *env = std::getenv("KPM_ILP"))
+        l.ilp = atoi(env) >= 4 ? 4 : (atoi(env) == 2 ? 2 : 1);
+    if (const char *env = std::getenv("KPM_STREAMING")) l.streaming = atoi(env) != 0;
+    if (const char *env = std::getenv("KPM_COMPACT_LAUNCH")) l.compact = atoi(env) != 0;
+    const char *env_tiled = std::getenv("KPM_TILED");
+    const char *env_steps = std::getenv("KPM_STEPS");
+    if (env_tiled) l.tiled = std::max(0, std::min(5, atoi(env_tiled)));
+    if (env_steps) {
+        l.steps = std::max(1, std::min(8, atoi(env_steps)));
+        if (l.steps > 4 && l.tiled < 3) l.tiled = 5;
+    }
+    if (l.steps > 4 && l.tiled < 3) l.steps = 4;
+    if (l.steps == 1 && l.tiled > 3) l.tiled = env_tiled ? 3 : 0;
+    if (!valid_launch(l))
+        return fail(KPM_ERR_INVALID,
+                    "KPM_* launch overrides give an invalid shape (groups %d ilp %d streaming "
+                    "%d compact %d tiled %d steps %d)",
+                    l.groups_per_cu, l.ilp, l.streaming, l.compact, l.tiled, l.steps);
+    *out = l;
+    return KPM_OK;
+}
+
 }  // namespace
 
 struct kpm_system {
@@ -740,9 +774,12 @@ kpm_status enqueue_moments(kpm_system *sys, const kpm::Sweep &sw, int ring, hipS
             if (kind > 1) {
                 V *o1 = free_state(p0, p1, nullptr);
                 V *o2 = free_state(p0, p1, o1);
-                kpm::launch_moment_multi<V>(h, sw, kind == k ? lat : sys->lat2(l, kind, sw.nwg),
-                                            p1, p0, o1, o2, phil, sys->partial, m - c0, dbl, re,
-                                            s);
+                if (!kpm::launch_moment_multi<V>(
+                        h, sw, kind == k ? lat : sys->lat2(l, kind, sw.nwg), p1, p0, o1, o2,
+                        phil, sys->partial, m - c0, dbl, re, s)) {
+                    st = fail(KPM_ERR_UNSUPPORTED, "no multi-step kernel for %d steps", kind);
+                    return;
+                }
                 p0 = o1;
                 p1 = o2;
                 return;
@@ -873,8 +910,9 @@ kpm_status run_evolve(kpm_system *sys, int vshift, const V *in, V *acc, const V 
                 if (q != p1 && q != p0 && no < 2) o[no++] = q;
             kpm::CoefK ck{};
             for (int j = 0; j < kk; ++j) ck.c[j] = c[m + j];
-            kpm::launch_evolve_multi<V>(h, sw, sys->lat2(l, kk, sw.nwg), p1, p0, o[0], o[1], acc,
-                                        ck, s);
+            if (!kpm::launch_evolve_multi<V>(h, sw, sys->lat2(l, kk, sw.nwg), p1, p0, o[0], o[1],
+                                             acc, ck, s))
+                return fail(KPM_ERR_UNSUPPORTED, "no propagator kernel for %d steps", kk);
             p0 = o[0];
             p1 = o[1];
             m += kk;
@@ -929,8 +967,10 @@ kpm_status run_evolve_x(kpm_system *sys, int vshift, const V *in, V *accx, V *ac
             pick(pool_q, q1, q0, qo);
             kpm::CoefK ck{};
             for (int j = 0; j < kk; ++j) ck.c[j] = c[m + j];
-            kpm::launch_evolve_x_multi<V>(h, sw, sys->lat2(l, kk, sw.nwg), sys->d_pxw, p1, p0,
-                                          po[0], po[1], q1, q0, qo[0], qo[1], accx, accu, ck, s);
+            if (!kpm::launch_evolve_x_multi<V>(h, sw, sys->lat2(l, kk, sw.nwg), sys->d_pxw, p1,
+                                               p0, po[0], po[1], q1, q0, qo[0], qo[1], accx,
+                                               accu, ck, s))
+                return fail(KPM_ERR_UNSUPPORTED, "no coupled propagator kernel for %d steps", kk);
             p0 = po[0];
             p1 = po[1];
             q0 = qo[0];
@@ -1213,8 +1253,9 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
             KPM_HIP(hipEventRecord(e0, s));
             for (int k = 0; k < steps; ++k) {
                 if (ks > 1 && k + ks <= steps) {
-                    kpm::launch_moment_multi<V>(h, sw, lat, p1, p0, o1, o2, phi, sys->partial, 0,
-                                                dbl, false, s);
+                    if (!kpm::launch_moment_multi<V>(h, sw, lat, p1, p0, o1, o2, phi,
+                                                     sys->partial, 0, dbl, false, s))
+                        return fail(KPM_ERR_UNSUPPORTED, "no multi-step kernel for %d steps", ks);
                     std::swap(p0, o1);
                     std::swap(p1, o2);
                     k += ks - 1;
@@ -1330,23 +1371,11 @@ kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int devi
         sys->off[s + 1] = sys->off[s] + parts[s].n;
         sys->es[s] = parts[s].e_scale;
     }
-    for (int v = 0; v < 7; ++v) sys->launch[v] = default_launch(v, prec);
-    if (const char *env = std::getenv("KPM_GROUPS_PER_CU"))
-        for (auto &l : sys->launch) l.groups_per_cu = std::max(1, std::min(32, atoi(env)));
-    if (const char *env = std::getenv("KPM_ILP"))
-        for (auto &l : sys->launch) l.ilp = atoi(env) >= 4 ? 4 : (atoi(env) == 2 ? 2 : 1);
-    if (const char *env = std::getenv("KPM_STREAMING"))
-        for (auto &l : sys->launch) l.streaming = atoi(env) != 0;
-    if (const char *env = std::getenv("KPM_COMPACT_LAUNCH"))
-        for (auto &l : sys->launch) l.compact = atoi(env) != 0;
-    if (const char *env = std::getenv("KPM_TILED"))
-        for (auto &l : sys->launch) l.tiled = std::max(0, std::min(3, atoi(env)));
-    if (const char *env = std::getenv("KPM_STEPS"))
-        for (auto &l : sys->launch) {
-            l.steps = std::max(1, std::min(8, atoi(env)));
-            if (l.steps > 4) l.tiled = 5;                // more than 4 steps need the strips
-        }
-    for (int v = 0; v < 7; ++v) sys->launch_dbl[v] = sys->launch[v];
+    for (int v = 0; v < 7; ++v) {
+        const kpm_status st = env_launch(v, prec, &sys->launch[v]);
+        if (st != KPM_OK) return bail(st);
+        sys->launch_dbl[v] = sys->launch[v];
+    }
     if (const char *env = std::getenv("KPM_SCRATCH_LIMIT_MB"))
         sys->scratch_limit = (size_t)(std::max(0.0, atof(env)) * 1048576.0);
     sys->chain.resize(nseg);
@@ -1771,6 +1800,15 @@ kpm_status kpm_kpm_sum(int n_rows, int n_moments, const double *moments, int n_e
     chk(hipStreamSynchronize(s));
     (void)hipFree(buf);
     return st;
+}
+
+kpm_status kpm_default_launch(int n_vec, kpm_precision precision, kpm_launch *out) {
+    const int vs = vshift_of(n_vec);
+    if (vs < 0) return fail(KPM_ERR_INVALID, "n_vec must be 1, 2, 4, ..., 64 (got %d)", n_vec);
+    if (precision != KPM_FP64 && precision != KPM_FP32_STATES)
+        return fail(KPM_ERR_INVALID, "precision");
+    if (!out) return fail(KPM_ERR_INVALID, "null output");
+    return env_launch(vs, precision, out);
 }
 
 kpm_status kpm_set_launch(kpm_system *sys, int n_vec, const kpm_launch *l) {

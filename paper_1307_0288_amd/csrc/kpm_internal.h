@@ -137,8 +137,12 @@ void launch_moment_step_doubled(const Ell &h, const Sweep &sw, const V *p1, cons
 // <phi_{n+s-1}|phi_{n+s-1}> and partial[slot + 2 (s - 1) + 1] =
 // <phi_{n+s-1}|phi_{n+s}>.  re: only the real parts are needed (the marching
 // strips then skip the imaginary parts, which read 0; other forms ignore it).
+// The multi-step launchers return false, launching nothing, for a step count
+// or form that has no kernel (lat.k outside 2 .. 8 for strips, 2 .. 4 for
+// register tiles, 2 for LDS tiles; the propagators need strips, and the
+// coupled one 2 or 3 steps).
 template <typename V>
-void launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V *p1,
+bool launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V *p1,
                          const V *p0, V *out1, V *out2, const V *phil, double2 *partial,
                          int slot, bool dbl, bool re, hipStream_t s);
 
@@ -153,7 +157,7 @@ struct CoefK {
 // out2 = phi_{n+K} (neither aliasing p1, p0 or each other) and acc += c_m
 // phi_m for m = n+1 .. n+K, c_m = ck.c[m - n - 1], in step order.
 template <typename V>
-void launch_evolve_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V *p1,
+bool launch_evolve_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V *p1,
                          const V *p0, V *out1, V *out2, V *acc, const CoefK &ck,
                          hipStream_t s);
 
@@ -163,7 +167,7 @@ void launch_evolve_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
 // c_m p_m, accx += c_m q_m for m = n+1 .. n+K (c_m = ck.c[m - n - 1]).  pxw:
 // [npat][4] commutator weight of each slot per pattern.  Outputs alias no input.
 template <typename V>
-void launch_evolve_x_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const double *pxw,
+bool launch_evolve_x_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const double *pxw,
                            const V *p1, const V *p0, V *pout1, V *pout2, const V *q1,
                            const V *q0, V *qout1, V *qout2, V *accx, V *accu, const CoefK &ck,
                            hipStream_t s);

@@ -1507,10 +1507,14 @@ void launch_kpm_sum(const double *mom, int rows, int nm, const double *w, const 
 }
 
 template <typename V>
-void launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V *p1,
+bool launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V *p1,
                          const V *p0, V *out1, V *out2, const V *phil, double2 *partial,
                          int slot, bool dbl, bool re, hipStream_t s) {
     const bool onsf = h.onsf != nullptr;
+    // the step counts each form is built for: LDS tiles 2, register tiles
+    // 2 .. 4, marching strips 2 .. 8
+    if (lat.k < 2 || lat.k > (lat.reg == 2 ? kMaxMarchSteps : (lat.reg == 1 ? 4 : 2)))
+        return false;
 #define KPM_LDS2(NT_, ONSF_, DBL_)                                                            \
     hipLaunchKernelGGL((k_moment_step2<V, NT_, ONSF_, DBL_, 16>), dim3(sw.nwg), dim3(kBlock),  \
                        0, s, h, sw, lat, p1, p0, out1, out2, phil, partial, slot)
@@ -1564,12 +1568,14 @@ void launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
 #undef KPM_REG_K
 #undef KPM_REG
 #undef KPM_MARCHK
+    return true;
 }
 
 template <typename V>
-void launch_evolve_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V *p1,
+bool launch_evolve_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V *p1,
                          const V *p0, V *out1, V *out2, V *acc, const CoefK &ck,
                          hipStream_t s) {
+    if (lat.reg != 2 || lat.k < 2 || lat.k > kMaxMarchSteps) return false;
 #define KPM_EVK(ONSF_, K_)                                                                    \
     hipLaunchKernelGGL((k_evolve_march<V, ONSF_, K_>), dim3(sw.nwg), dim3(kBlock), 0, s, h,   \
                        sw, lat, p1, p0, out1, out2, acc, ck)
@@ -1587,6 +1593,7 @@ void launch_evolve_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
     else { KPM_EV(false) }
 #undef KPM_EV
 #undef KPM_EVK
+    return true;
 }
 
 #define KPM_INSTANTIATE(V)                                                                  \
@@ -1606,10 +1613,10 @@ void launch_evolve_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
                                     hipStream_t);                                           \
     template void launch_dot<V>(const Sweep &, const V *, const V *, double2 *, int,        \
                                 hipStream_t);                                               \
-    template void launch_moment_multi<V>(const Ell &, const Sweep &, const Lat2 &, const V *, \
+    template bool launch_moment_multi<V>(const Ell &, const Sweep &, const Lat2 &, const V *, \
                                          const V *, V *, V *, const V *, double2 *, int,    \
                                          bool, bool, hipStream_t);                          \
-    template void launch_evolve_multi<V>(const Ell &, const Sweep &, const Lat2 &, const V *, \
+    template bool launch_evolve_multi<V>(const Ell &, const Sweep &, const Lat2 &, const V *, \
                                          const V *, V *, V *, V *, const CoefK &,           \
                                          hipStream_t);
 
@@ -1798,10 +1805,11 @@ __global__ __launch_bounds__(kBlock, 2) void k_evolve_x_march(
 }
 
 template <typename V>
-void launch_evolve_x_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const double *pxw,
+bool launch_evolve_x_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const double *pxw,
                            const V *p1, const V *p0, V *pout1, V *pout2, const V *q1,
                            const V *q0, V *qout1, V *qout2, V *accx, V *accu, const CoefK &ck,
                            hipStream_t s) {
+    if (lat.reg != 2 || lat.k < 2 || lat.k > 3) return false;
 #define KPM_EXK(ONSF_, K_)                                                                    \
     hipLaunchKernelGGL((k_evolve_x_march<V, ONSF_, K_>), dim3(sw.nwg), dim3(kBlock), 0, s, h, \
                        sw, lat, pxw, p1, p0, pout1, pout2, q1, q0, qout1, qout2, accx, accu, ck)
@@ -1814,14 +1822,15 @@ void launch_evolve_x_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const
     else { KPM_EX(false) }
 #undef KPM_EX
 #undef KPM_EXK
+    return true;
 }
 
-template void launch_evolve_x_multi<double2>(const Ell &, const Sweep &, const Lat2 &,
+template bool launch_evolve_x_multi<double2>(const Ell &, const Sweep &, const Lat2 &,
                                              const double *, const double2 *, const double2 *,
                                              double2 *, double2 *, const double2 *,
                                              const double2 *, double2 *, double2 *, double2 *,
                                              double2 *, const CoefK &, hipStream_t);
-template void launch_evolve_x_multi<float2>(const Ell &, const Sweep &, const Lat2 &,
+template bool launch_evolve_x_multi<float2>(const Ell &, const Sweep &, const Lat2 &,
                                             const double *, const float2 *, const float2 *,
                                             float2 *, float2 *, const float2 *, const float2 *,
                                             float2 *, float2 *, float2 *, float2 *,

@@ -37,7 +37,7 @@ ABI_SYMBOLS = ("kpm_build_graphene", "kpm_validate", "kpm_system_create", "kpm_s
                "kpm_mlp_get_params", "kpm_mlp_forward", "kpm_mlp_gradients",
                "kpm_mlp_train_step", "kpm_learned_features", "kpm_learned_targets",
                "kpm_xu_state", "kpm_vac_continue", "kpm_msd_continue",
-               "kpm_set_launch", "kpm_get_launch", "kpm_set_launch_doubled",
+               "kpm_default_launch", "kpm_set_launch", "kpm_get_launch", "kpm_set_launch_doubled",
                "kpm_get_launch_doubled",
                "kpm_autotune", "kpm_set_graphs", "kpm_set_timing", "kpm_get_stats",
                "kpm_reset_stats",
@@ -131,6 +131,7 @@ def _signatures():
                              C.c_int, dp],
         "kpm_msd_continue": [vp, C.c_int, vp, vp, C.c_int, C.c_int, C.c_double, C.c_int,
                              C.c_int, C.c_int, dp],
+        "kpm_default_launch": [C.c_int, C.c_int, C.POINTER(Launch)],
         "kpm_set_launch": [vp, C.c_int, C.POINTER(Launch)],
         "kpm_get_launch": [vp, C.c_int, C.POINTER(Launch)],
         "kpm_set_launch_doubled": [vp, C.c_int, C.POINTER(Launch)],
@@ -585,6 +586,15 @@ def kpm_set_launch(sys: System, n_vec: int, groups_per_cu: int, ilp: int, stream
     _check(lib().kpm_set_launch(sys.handle, n_vec,
                                 C.byref(Launch(groups_per_cu, ilp, int(bool(streaming)),
                                                int(bool(compact)), int(tiled), int(steps)))))
+
+
+def kpm_default_launch(n_vec: int, precision: str = "fp64") -> dict:
+    """Launch shape a new system starts with (environment overrides applied);
+    host only."""
+    out = Launch()
+    prec = KPM_FP64 if precision == "fp64" else KPM_FP32_STATES
+    _check(lib().kpm_default_launch(n_vec, prec, C.byref(out)))
+    return out.as_dict()
 
 
 def kpm_get_launch(sys: System, n_vec: int) -> dict:

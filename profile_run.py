@@ -4,16 +4,16 @@ the summary of its counter readings.
 Collect (one counter per run):
 
     rocprofv3 --pmc FETCH_SIZE -d OUT/fetch -o c --output-format csv -- \
-        python3 -m paper_1307_0288_amd.profile_run --moments 40 --copy-mib 512 \
+        python3 profile_run.py --moments 40 --copy-mib 512 \
         --meta OUT/meta.json
     rocprofv3 --pmc WRITE_SIZE -d OUT/write -o c --output-format csv -- \
-        python3 -m paper_1307_0288_amd.profile_run --moments 40 --copy-mib 512
+        python3 profile_run.py --moments 40 --copy-mib 512
 
 Summarise:
 
-    python3 -m paper_1307_0288_amd.profile_run --summarize OUT/fetch OUT/write \
+    python3 profile_run.py --summarize OUT/fetch OUT/write \
         --meta OUT/meta.json --out profiles/<name>.json
-    python3 -m paper_1307_0288_amd.profile_run --trace-table OUT/bench_kernel_stats.csv
+    python3 profile_run.py --trace-table OUT/bench_kernel_stats.csv
 
 The run does one Chebyshev-moment call on the paper-scale sheet (2828 x 1414
 sites, 0.5 % vacancies, W = 0.1 eV; n_moments - 2 launches of the fused moment
@@ -32,11 +32,11 @@ import json
 import os
 import sys
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-KERNEL_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "kpm_kernels.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_1307_0288_amd", "csrc", "kpm_kernels.hip")
 
 
 def multi_step(launch: dict, n_vec: int = 1) -> bool:
@@ -45,23 +45,36 @@ def multi_step(launch: dict, n_vec: int = 1) -> bool:
     return launch.get("steps", 1) >= 2 and n_vec == 1 and bool(launch["compact"])
 
 
+def float_onsite(onsite) -> bool:
+    """Whether the library stores these on-site energies as floats (it does
+    when every value is exactly a float)."""
+    import numpy as np
+    if onsite is None:
+        return True
+    a = np.asarray(onsite, dtype=np.float64)
+    return bool(np.array_equal(a.astype(np.float32).astype(np.float64), a))
+
+
 def moment_kernel_name(v: str, launch: dict, dbl: bool, n_vec: int = 1,
-                       real: bool = False) -> str:
+                       real: bool = False, onsf: bool = True) -> str:
     """Instantiation of the moment step for a graphene system from the builder
-    (width 3, uniform hopping, float-exact on-site terms, at least 24 chains)
-    under a launch shape; real: the moment sets whose callers keep only the
-    real parts (VAC and MSD), which the marching strips accumulate alone."""
+    (width 3, uniform hopping, at least 24 chains) under a launch shape; onsf:
+    on-site terms stored as floats (float_onsite) or doubles; real: the moment
+    sets whose callers keep only the real parts (VAC and MSD), which the
+    marching strips accumulate alone."""
     nt, db = ("true" if launch["streaming"] else "false"), ("true" if dbl else "false")
+    of = "true" if onsf else "false"
     if multi_step(launch, n_vec):
         k, tiled = launch["steps"], launch["tiled"]
         if k == 2 and tiled == 0:
-            return f"k_moment_step2<{v},{nt},true,{db},16>"
+            return f"k_moment_step2<{v},{nt},{of},{db},16>"
         if tiled >= 3 and real and not dbl:
-            return f"k_moment_march_re<{v},true,{k}>"
+            return f"k_moment_march_re<{v},{of},{k}>"
         if tiled >= 3:
-            return f"k_moment_march<{v},true,{db},{k}>"
-        return f"k_moment_stepk<{v},true,{db},{4 if tiled == 2 else 8},{k}>"
-    form = "kFormC3F" if launch["compact"] else "kFormL3F"
+            return f"k_moment_march<{v},{of},{db},{k}>"
+        return f"k_moment_stepk<{v},{of},{db},{4 if tiled == 2 else 8},{k}>"
+    form = ("kFormC3F" if onsf else "kFormC3D") if launch["compact"] else \
+        ("kFormL3F" if onsf else "kFormL3D")
     return f"k_moment_step<{v},{launch['ilp']},{nt},{form},{db}>"
 
 
@@ -80,7 +93,7 @@ def kernel_sha(launch: dict | None = None) -> str:
         reg = t.index("// Register-tiled sweep of K = 2, 3 or 4")
         march = t.index("// Marching form of the register-tiled K-step sweep")
         end = t.index("// ---------------------------------------------------------------- launchers")
-        c = t.index("template <typename V>\nvoid launch_moment_multi(")
+        c = t.index("template <typename V>\nbool launch_moment_multi(")
         d = t.index("#define KPM_INSTANTIATE(V)")
         k, tiled = launch["steps"], launch["tiled"]
         body = (t[lds:reg] if (k == 2 and tiled == 0) else
@@ -263,7 +276,7 @@ def main():
     print(f"copies: {args.copies} x {args.copy_mib} MiB", flush=True)
     if args.meta:
         v = "double2" if args.precision == "fp64" else "float2"
-        cmd = ["python3 -m paper_1307_0288_amd.profile_run", f"--moments {args.moments}",
+        cmd = ["python3 profile_run.py", f"--moments {args.moments}",
                f"--n-vec {args.n_vec}", f"--precision {args.precision}",
                f"--copy-mib {args.copy_mib}"]
         if args.doubled:

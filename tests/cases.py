@@ -5,13 +5,32 @@ import kpm_inputs as ki
 import oracle
 
 
-def recipe(geometry, nx, ny, w=0.0, vac=0.0, seed=0, e_scale=None):
-    """Seeded on-site disorder, vacancies and E_s for an nx x ny sample."""
+def recipe(geometry, nx, ny, w=0.0, vac=0.0, seed=0, e_scale=None, onsite="f64"):
+    """Seeded on-site disorder, vacancies and E_s for an nx x ny sample.
+
+    onsite="f32" is the float-exact disorder variant of a test case: the same
+    draw rounded to the nearest float32 (the library then stores the on-site
+    terms in 4 bytes); both sides of a comparison receive the rounded values."""
     n = nx * ny
     act = ki.vacancy_mask(n, vac, 2000 + seed) if vac else None
     ons = ki.anderson_onsite(n, w, 1000 + seed)
+    if onsite == "f32":
+        ons = float_exact(ons)
+    elif onsite != "f64":
+        raise ValueError(onsite)
     es = 1.01 * (3 * 2.7 + w / 2) if e_scale is None else e_scale
     return dict(geometry=geometry, nx=nx, ny=ny, onsite=ons, active=act, e_scale=es)
+
+
+def float_exact(values):
+    """Values rounded to the nearest float32, held in float64."""
+    return np.asarray(values, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def onsite_bytes(c):
+    """Bytes per row the library stores for the on-site term of case c."""
+    ons = np.asarray(c["onsite"])
+    return 4 if np.array_equal(float_exact(ons), ons) else 8
 
 
 def oracle_lattice(c):

@@ -213,3 +213,52 @@ def test_learned_features_match_oracle():
     assert np.allclose(x, ref, rtol=2e-7, atol=1e-7)
     with pytest.raises(kp.KpmError):
         kp.kpm_learned_features(mu, c, 41)
+
+
+ENV_KEYS = ("KPM_GROUPS_PER_CU", "KPM_ILP", "KPM_STREAMING", "KPM_COMPACT_LAUNCH", "KPM_TILED",
+            "KPM_STEPS")
+
+
+def _valid_shape(l):
+    """The shapes kernels exist for (kpm_set_launch accepts exactly these)."""
+    return (1 <= l["groups_per_cu"] <= 32 and l["ilp"] in (1, 2, 4) and l["streaming"] in (0, 1)
+            and l["compact"] in (0, 1) and 0 <= l["tiled"] <= (5 if l["steps"] > 1 else 3)
+            and 1 <= l["steps"] <= (8 if l["tiled"] >= 3 else 4))
+
+
+@pytest.mark.parametrize("tiled", [None, "0", "1", "2", "3", "4", "5", "9", "-1"])
+@pytest.mark.parametrize("steps", [None, "1", "2", "3", "4", "5", "8", "12"])
+def test_environment_overrides_give_valid_shapes(monkeypatch, tiled, steps):
+    """Every combination of KPM_TILED and KPM_STEPS (with the other overrides
+    set too) yields a shape the multi-step kernels exist for: a traversal
+    below the strips never keeps more than 4 steps."""
+    for k in ENV_KEYS:
+        monkeypatch.delenv(k, raising=False)
+    if tiled is not None:
+        monkeypatch.setenv("KPM_TILED", tiled)
+    if steps is not None:
+        monkeypatch.setenv("KPM_STEPS", steps)
+    monkeypatch.setenv("KPM_GROUPS_PER_CU", "3")
+    for n_vec in (1, 2, 8, 64):
+        for prec in ("fp64", "fp32"):
+            l = kp.kpm_default_launch(n_vec, prec)
+            assert _valid_shape(l), (n_vec, prec, l)
+            assert l["groups_per_cu"] == 3
+            if steps is not None:
+                want = max(1, min(8, int(steps)))
+                if tiled is not None and int(tiled) < 3 and 4 < want:
+                    assert l["steps"] == want and l["tiled"] == 5    # steps select the strips
+                elif want <= 4 or l["tiled"] >= 3:
+                    assert l["steps"] == want
+            if tiled is not None and steps is None and int(tiled) < 3:
+                assert l["tiled"] == max(0, int(tiled)) and l["steps"] <= 4
+
+
+def test_default_shapes_without_overrides(monkeypatch):
+    for k in ENV_KEYS:
+        monkeypatch.delenv(k, raising=False)
+    one = kp.kpm_default_launch(1)
+    assert one == dict(groups_per_cu=2, ilp=1, streaming=0, compact=1, tiled=5, steps=8)
+    assert kp.kpm_default_launch(64, "fp32")["steps"] == 1
+    with pytest.raises(kp.KpmError):
+        kp.kpm_default_launch(3)

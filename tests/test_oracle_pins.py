@@ -455,3 +455,32 @@ def test_ftm_and_kpm_dos_agree():
     ck = np.cumsum(rk) * (en[1] - en[0]) * lat.area_nm2 / 2
     cf = np.cumsum(rf) * (en[1] - en[0]) * lat.area_nm2 / 2
     assert np.max(np.abs(ck - cf)) < 0.02 * lat.n
+
+
+def test_threaded_oracle_equals_serial_bit_for_bit():
+    """The oracle's row loops may run on several threads; every value is then
+    computed by the same operations in the same order and the inner products
+    stay serial, so moments, propagators and both time loops are bit-identical
+    for 1 and 4 threads."""
+    nx, ny = 64, 32
+    n = nx * ny
+    act = ki.vacancy_mask(n, 0.02, 2000)
+    lat = oracle.graphene(nx, ny, "sheet", -2.7, ki.anderson_onsite(n, 1.0, 1000), act)
+    es = 1.01 * (3 * 2.7 + 0.5)
+    phi = ki.random_phase(n, 1, 3000, act)[:, 0]
+    psi = ki.random_phase(n, 1, 3001, act)[:, 0]
+    prev = oracle.set_threads()
+    out = {}
+    try:
+        for th in (1, 4):
+            oracle.set_threads(th)
+            out[th] = (oracle.moments(lat, es, psi, phi, 90),
+                       oracle.evolve(lat, es, phi, 0.3, -1, 17),
+                       *oracle.evolve_x(lat, es, phi, 0.3, 17),
+                       oracle.vac(lat, es, phi, 2, 0.3, 17, 40),
+                       oracle.msd(lat, es, phi, 2, 0.3, 17, 40),
+                       oracle.fourier_moments(lat, es, psi, phi, 3, 0.2, 12))
+    finally:
+        oracle.set_threads(prev)
+    for a, b in zip(out[1], out[4]):
+        assert np.array_equal(a, b)

@@ -1,0 +1,144 @@
+"""Parity on the paper-scale sheet, end to end, in the launch configuration
+bench.py times (autotuned on the same vector).
+
+The sample: 2828 x 1414 periodic sheet (3,998,792 sites), 0.5 % vacancies,
+W = 0.1 eV, the random-phase vector of seed 3000; 3000 moments, 20 time steps
+of dt = hbar/|t| with 40 Bessel terms.  Reference values: the oracle's, stored
+by tests/golden/make_paper_sheet_golden.py (DOS moments, and the VAC and MSD
+moments at all 21 time points).  Bars: moments max|dC| / (|phi_L| |phi_R|) <=
+1e-10 (DOS), max|dC| / max|C| <= 1e-10 (VAC, MSD), sigma_GK / sigma_E1 /
+sigma_E2 and the DOS on 2048 energies max|d| / max|ref| <= 1e-8.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import kpm_inputs as ki
+import oracle
+from cases import rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+kp = pytest.importorskip("paper_1307_0288_amd")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden", "paper_sheet_oracle.npz")
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def load_golden():
+    """The stored oracle values, checked against today's inputs."""
+    import sys
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    import make_paper_sheet_golden as mk
+    z = np.load(GOLDEN, allow_pickle=False)
+    meta = json.loads(bytes(z["meta"]).decode())
+    p, ons, act, phi = mk.inputs()
+    assert meta["input_sha256"] == mk.input_digest(ons, act, phi), \
+        "stored oracle values belong to other inputs: rerun make_paper_sheet_golden.py"
+    return p, ons, act, phi, dict(dos=z["dos_re"] + 1j * z["dos_im"], vac=z["vac"], msd=z["msd"])
+
+
+@pytest.fixture(scope="module")
+def paper():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    p, ons, act, phi, gold = load_golden()
+    _log("paper-scale sheet (3998792 sites): system, autotune")
+    sysg = kp.graphene_system(p["nx"], p["ny"], "sheet", p["t"], ons, act, p["e_scale"], "fp64")
+    d = sysg.upload(phi[:, None])
+    launch = kp.kpm_autotune(sysg, d, 50)
+    _log(f"autotuned shape {launch}")
+    return p, act, phi, gold, sysg, d
+
+
+def test_dos_moments_all_3000(paper):
+    p, act, phi, gold, sysg, d = paper
+    _log("paper-scale DOS moments (3000)")
+    got = kp.kpm_moments(sysg, d, d, p["n_moments"])[0]
+    n_act = float(np.count_nonzero(act))
+    assert abs(got[0] - n_act) < 1e-6
+    assert rel_err(got, gold["dos"], n_act) < 1e-10
+
+
+def test_dos_moments_doubled_all_3000(paper):
+    p, act, phi, gold, sysg, d = paper
+    _log("paper-scale DOS moments, doubling form (3000)")
+    got = kp.kpm_moments_doubled(sysg, d, p["n_moments"])[0]
+    assert rel_err(got, gold["dos"], float(np.count_nonzero(act))) < 1e-10
+
+
+@pytest.fixture(scope="module")
+def loops(paper):
+    p, act, phi, gold, sysg, d = paper
+    args = (p["n_steps"], p["dt_fs"], p["n_bessel"], p["n_moments"])
+    _log("paper-scale VAC and MSD (20 steps x 3000 moments)")
+    return kp.kpm_vac(sysg, d, *args)[0], kp.kpm_msd(sysg, d, *args)[0]
+
+
+def test_vac_all_time_points(paper, loops):
+    gold = paper[3]
+    gv, _ = loops
+    assert gv.shape == gold["vac"].shape == (21, 3000)
+    assert rel_err(gv, gold["vac"]) < 1e-10
+    for k in (0, 10, 20):
+        assert rel_err(gv[k], gold["vac"][k]) < 1e-10, k
+
+
+def test_msd_all_time_points(paper, loops):
+    gold = paper[3]
+    _, gm = loops
+    assert np.all(gm[0] == 0)
+    assert rel_err(gm, gold["msd"]) < 1e-10
+    for k in (1, 10, 20):
+        assert rel_err(gm[k], gold["msd"][k]) < 1e-10, k
+
+
+def test_msd_doubled_all_time_points(paper):
+    p, act, phi, gold, sysg, d = paper
+    _log("paper-scale MSD, doubling form")
+    gm = kp.kpm_msd_doubled(sysg, d, p["n_steps"], p["dt_fs"], p["n_bessel"], p["n_moments"])[0]
+    assert rel_err(gm, gold["msd"]) < 1e-10
+
+
+def test_sigma_on_2048_energies(paper, loops):
+    """DOS, sigma_GK (Eq. 6), sigma_E1 (Eq. 9) and sigma_E2 (Eq. 11) from the
+    GPU moments through the library's sums, against the oracle's
+    reconstruction of the stored moments."""
+    p, act, phi, gold, sysg, d = paper
+    gv, gm = loops
+    es, dt = p["e_scale"], p["dt_fs"]
+    area = sysg.area_nm2
+    # the oracle side's area: L_x L_y of its lattice (Sec. 2)
+    o_area = (np.sqrt(3.0) * p["nx"] * oracle.BOND_NM / 2.0) * (3.0 * p["ny"] * oracle.BOND_NM / 2.0)
+    en = oracle.energies_grid(2048, es)
+    g_dos = kp.kpm_kpm_sum(kp.kpm_moments(sysg, d, d, p["n_moments"])[0].real, en, es, area)
+    r_dos = oracle.dos(gold["dos"].real, en, es, o_area)
+    assert rel_err(g_dos, r_dos) < 1e-8
+    r_v = oracle.kpm_sum(gold["vac"], en, es, o_area)
+    r_m = oracle.kpm_sum(gold["msd"], en, es, o_area)
+    g_v, g_m = kp.kpm_kpm_sum(gv, en, es, area), kp.kpm_kpm_sum(gm, en, es, area)
+    pairs = ((kp.kpm_sigma_gk(g_v, dt), oracle.sigma_gk(r_v, dt)),
+             (kp.kpm_sigma_e1(g_m, dt), oracle.sigma_e1(r_m, dt)),
+             (kp.kpm_sigma_e2(g_m, dt), oracle.sigma_e2(r_m, dt)))
+    for name, (g, r) in zip(("gk", "e1", "e2"), pairs):
+        assert g.shape == r.shape == (21, 2048)
+        assert rel_err(g, r) < 1e-8, name
+
+
+def test_evolve_norm_and_inverse(paper):
+    p, act, phi, gold, sysg, d = paper
+    e = sysg.upload(ki.random_phase(phi.shape[0], 1, 3005, act))
+    ref = e.cpu().numpy()
+    n0 = float(torch.vdot(e[:, 0], e[:, 0]).real)
+    kp.kpm_evolve(sysg, e, p["dt_fs"], 1, p["n_bessel"])
+    n1 = float(torch.vdot(e[:, 0], e[:, 0]).real)
+    assert abs(n1 - n0) < 1e-10 * n0
+    kp.kpm_evolve(sysg, e, p["dt_fs"], -1, p["n_bessel"])
+    assert np.max(np.abs(e.cpu().numpy() - ref)) < 1e-11

@@ -225,81 +225,6 @@ def test_invalid_calls_raise(small):
         kp.kpm_moments(sysg, bad, bad, 4)           # n_vec not a power of two
 
 
-# ------------------------------------------------------------------ paper-scale sheet
-@pytest.fixture(scope="module")
-def paper():
-    _need_gpu()
-    p = ki.sheet_config("paper")
-    c = recipe("sheet", p["nx"], p["ny"], w=p["w"], vac=p["vac"], e_scale=p["e_scale"])
-    _log("paper-scale lattice (3998792 sites)")
-    sysg = gpu_system(c)
-    # the launch shape bench.py times: autotuned on the same vector
-    _log(f"autotuned shape {kp.kpm_autotune(sysg, sysg.upload(phases(c, 1, 3000)), 50)}")
-    return p, c, oracle_lattice(c), sysg
-
-
-def test_paper_scale_moments_prefix_and_properties(paper):
-    """Full 4M-site sheet in the benchmark's launch configuration: the first
-    64 moments against the oracle; all 3000 checked for properties that hold
-    at any size (C_0 = N_active, real for phi_L = phi_R, |C_m| <= C_0)."""
-    p, c, lat, sysg = paper
-    phi = phases(c, 1, 3000)
-    d = sysg.upload(phi)
-    _log("paper-scale gpu moments 3000")
-    got = kp.kpm_moments(sysg, d, d, p["n_moments"])[0]
-    n_act = int(np.count_nonzero(c["active"]))
-    assert abs(got[0] - n_act) < 1e-6
-    assert np.max(np.abs(got.imag)) < 1e-8 * n_act
-    assert np.all(np.abs(got.real) <= n_act * (1 + 1e-12))
-    _log("paper-scale oracle moments 64")
-    ref = oracle.moments(lat, c["e_scale"], phi[:, 0], phi[:, 0], 64)
-    assert rel_err(got[:64], ref, n_act) < 1e-10
-
-
-def test_paper_scale_doubled_moments(paper):
-    """Doubling form on the full sheet: the first 64 moments against the
-    oracle, all 3000 against the direct form (rounding only)."""
-    p, c, lat, sysg = paper
-    phi = phases(c, 1, 3000)
-    d = sysg.upload(phi)
-    n_act = int(np.count_nonzero(c["active"]))
-    _log("paper-scale gpu doubled moments 3000")
-    got = kp.kpm_moments_doubled(sysg, d, p["n_moments"])[0]
-    direct = kp.kpm_moments(sysg, d, d, p["n_moments"])[0]
-    assert rel_err(got, direct, n_act) < 1e-10
-    _log("paper-scale oracle moments 64")
-    ref = oracle.moments(lat, c["e_scale"], phi[:, 0], phi[:, 0], 64)
-    assert rel_err(got[:64], ref, n_act) < 1e-10
-
-
-def test_paper_scale_vac_msd_one_step(paper):
-    p, c, lat, sysg = paper
-    phi = phases(c, 1, 3000)
-    d = sysg.upload(phi)
-    args = (1, p["dt_fs"], p["n_bessel"], 16)
-    _log("paper-scale gpu vac/msd 1 step")
-    gv = kp.kpm_vac(sysg, d, *args)[0]
-    gm = kp.kpm_msd(sysg, d, *args)[0]
-    _log("paper-scale oracle vac/msd 1 step")
-    rv = oracle.vac(lat, c["e_scale"], phi[:, 0], *args)
-    rm = oracle.msd(lat, c["e_scale"], phi[:, 0], *args)
-    assert rel_err(gv, rv) < 1e-10
-    assert rel_err(gm, rm) < 1e-10
-
-
-def test_paper_scale_evolve_norm(paper):
-    p, c, lat, sysg = paper
-    phi = phases(c, 1, 3005)
-    d = sysg.upload(phi)
-    n0 = float(torch.vdot(d[:, 0], d[:, 0]).real)
-    kp.kpm_evolve(sysg, d, p["dt_fs"], 1, p["n_bessel"])
-    n1 = float(torch.vdot(d[:, 0], d[:, 0]).real)
-    assert abs(n1 - n0) < 1e-10 * n0
-    kp.kpm_evolve(sysg, d, p["dt_fs"], -1, p["n_bessel"])
-    back = d.cpu().numpy()
-    assert np.max(np.abs(back - phi)) < 1e-11
-
-
 # ------------------------------------------------------------------ launch shapes
 @pytest.mark.parametrize("n_vec,precision", [(1, "fp64"), (8, "fp32"), (64, "fp64")])
 def test_launch_shapes(n_vec, precision):

@@ -5,7 +5,7 @@ reports for a launch shape."""
 import csv
 import json
 
-from paper_1307_0288_amd import profile_run as pr
+import profile_run as pr
 
 FIELDS = ["Dispatch_Id", "Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"]
 STRIPS = {"groups_per_cu": 2, "ilp": 1, "streaming": 0, "compact": 1, "tiled": 5, "steps": 8}

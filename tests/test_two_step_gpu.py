@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from cases import gpu_system, oracle_lattice, phases, recipe, rel_err
+from cases import gpu_system, onsite_bytes, oracle_lattice, phases, recipe, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -45,13 +45,20 @@ MULTI = [(2, 0), (2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (4, 2), (2, 3), (3, 4),
          (4, 5), (5, 3), (6, 4), (5, 5), (6, 5), (7, 5), (8, 5), (7, 3), (8, 4)]
 
 
+# on-site terms stored as doubles (the generator's draw) or, for the
+# float-exact variant of a case, as floats
+ONSITE = ["f64", "f32"]
+
+
+@pytest.mark.parametrize("onsite", ONSITE)
 @pytest.mark.parametrize("geometry,nx,ny", SHAPES)
 @pytest.mark.parametrize("nm", [101, 64])
 @pytest.mark.parametrize("steps,tiled", MULTI)
-def test_moments_match_oracle_and_single_step(geometry, nx, ny, nm, steps, tiled):
+def test_moments_match_oracle_and_single_step(geometry, nx, ny, nm, steps, tiled, onsite):
     _need_gpu()
-    c = recipe(geometry, nx, ny, w=1.5, vac=0.02, seed=nx + ny)
-    _log(f"moments {geometry} {nx}x{ny} nm={nm} steps={steps} tiled={tiled}")
+    c = recipe(geometry, nx, ny, w=1.5, vac=0.02, seed=nx + ny, onsite=onsite)
+    ob = onsite_bytes(c)
+    _log(f"moments {geometry} {nx}x{ny} nm={nm} steps={steps} tiled={tiled} onsite={onsite}")
     one, two = _pair(c, tiled=tiled, steps=steps)
     phi = phases(c, 1, 4400)
     d = one.upload(phi)
@@ -65,20 +72,21 @@ def test_moments_match_oracle_and_single_step(geometry, nx, ny, nm, steps, tiled
     assert rel_err(m2, ref, scale) < 1e-10
     assert rel_err(m2, m1, scale) < 1e-13
     n = nx * ny
-    # 5 state accesses of 16 B, pattern byte and float on-site term per row
-    assert st["step_bytes"] == n * (5 * 16 + 1 + 4)
+    # 5 state accesses of 16 B, pattern byte and on-site term per row
+    assert st["step_bytes"] == n * (5 * 16 + 1 + ob)
     # full passes, then one pass of the 2 .. steps - 1 steps left, or one single step
     n2, r = divmod(nm - 2, steps)
     n2, n1 = (n2 + 1, 0) if r >= 2 else (n2, r)
     assert st["step_launches"] == n2 + n1
-    assert st["step_bytes_total"] == n2 * st["step_bytes"] + n1 * n * (4 * 16 + 1 + 4)
+    assert st["step_bytes_total"] == n2 * st["step_bytes"] + n1 * n * (4 * 16 + 1 + ob)
 
 
+@pytest.mark.parametrize("onsite", ONSITE)
 @pytest.mark.parametrize("geometry,nx,ny", SHAPES[:3])
 @pytest.mark.parametrize("steps,tiled", MULTI)
-def test_distinct_left_vector_and_doubling(geometry, nx, ny, steps, tiled):
+def test_distinct_left_vector_and_doubling(geometry, nx, ny, steps, tiled, onsite):
     _need_gpu()
-    c = recipe(geometry, nx, ny, w=0.8, vac=0.01, seed=7 * nx + ny)
+    c = recipe(geometry, nx, ny, w=0.8, vac=0.01, seed=7 * nx + ny, onsite=onsite)
     _log(f"phi_L != phi_R and doubling {geometry} {nx}x{ny} steps={steps} tiled={tiled}")
     one, two = _pair(c, tiled=tiled, steps=steps)
     pl, pr = phases(c, 1, 4500), phases(c, 1, 4501)
@@ -92,14 +100,14 @@ def test_distinct_left_vector_and_doubling(geometry, nx, ny, steps, tiled):
         assert rel_err(dbl, ref, np.vdot(pr, pr).real) < 1e-10, nm
 
 
-@pytest.mark.parametrize("steps,tiled", [(2, 0), (3, 1), (3, 3)])
+@pytest.mark.parametrize("steps,tiled", [(2, 0), (3, 1), (3, 3), (8, 5)])
 def test_double_onsite_form(steps, tiled):
-    """On-site energies that are not floats: the width-3 compact form with
-    double on-site terms."""
+    """On-site energies that differ from floats only below float precision
+    still take the width-3 compact form with double on-site terms."""
     _need_gpu()
-    c = recipe("sheet", 130, 26, w=1.0, vac=0.02, seed=3)
+    c = recipe("sheet", 130, 26, w=1.0, vac=0.02, seed=3, onsite="f32")
     c["onsite"] = c["onsite"] + 1e-9 * np.sin(np.arange(c["onsite"].size))
-    _log("double on-site sheet 130x26")
+    _log(f"double on-site sheet 130x26 steps={steps} tiled={tiled}")
     one, two = _pair(c, tiled=tiled, steps=steps)
     phi = phases(c, 1, 4650)
     d = one.upload(phi)
@@ -129,11 +137,12 @@ def test_fp32_states_equal_single_step(steps, tiled):
     assert rel_err(m2, ref, scale) < 1e-4
 
 
+@pytest.mark.parametrize("onsite", ONSITE)
 @pytest.mark.parametrize("kind", ["vac", "msd", "msd_doubled"])
 @pytest.mark.parametrize("steps,tiled", [(2, 0), (3, 2), (4, 3), (8, 5)])
-def test_time_loops_with_two_step_moments(kind, steps, tiled):
+def test_time_loops_with_two_step_moments(kind, steps, tiled, onsite):
     _need_gpu()
-    c = recipe("sheet", 130, 26, w=1.0, vac=0.02, seed=9)
+    c = recipe("sheet", 130, 26, w=1.0, vac=0.02, seed=9, onsite=onsite)
     _log(f"{kind} sheet 130x26 steps={steps}")
     one, two = _pair(c, tiled=tiled, steps=steps)
     phi = phases(c, 1, 4700)
@@ -168,15 +177,16 @@ def test_resumed_loops_in_strips_equal_one_call(kind):
 EVOLVE = [(2, 5), (3, 5), (5, 5), (6, 5), (8, 5), (7, 3), (8, 4)]
 
 
+@pytest.mark.parametrize("onsite", ONSITE)
 @pytest.mark.parametrize("geometry,nx,ny", SHAPES[:3])
 @pytest.mark.parametrize("steps,tiled", EVOLVE)
-def test_propagator_in_strips_equals_single_steps(geometry, nx, ny, steps, tiled):
+def test_propagator_in_strips_equals_single_steps(geometry, nx, ny, steps, tiled, onsite):
     """U(+-dt) with the recursion in marching strips (Alg. 6 several steps per
     pass): the same states and accumulator as single steps, and the oracle's
     result; Bessel term counts leave full passes, a short last pass, a
     single last step, or no multi-step pass at all."""
     _need_gpu()
-    c = recipe(geometry, nx, ny, w=1.2, vac=0.02, seed=3 * nx + ny)
+    c = recipe(geometry, nx, ny, w=1.2, vac=0.02, seed=3 * nx + ny, onsite=onsite)
     _log(f"propagator {geometry} {nx}x{ny} steps={steps} tiled={tiled}")
     one, two = _pair(c, tiled=tiled, steps=steps)
     lat = oracle_lattice(c)
@@ -191,15 +201,17 @@ def test_propagator_in_strips_equals_single_steps(geometry, nx, ny, steps, tiled
         assert rel_err(g2, ref) < 1e-12, (sign, nb)
 
 
+@pytest.mark.parametrize("onsite", ONSITE)
 @pytest.mark.parametrize("geometry,nx,ny", SHAPES[:3])
 @pytest.mark.parametrize("steps,tiled", [(2, 5), (3, 5), (8, 5), (5, 3), (4, 4)])
-def test_commutator_propagator_in_strips_equals_single_steps(geometry, nx, ny, steps, tiled):
+def test_commutator_propagator_in_strips_equals_single_steps(geometry, nx, ny, steps, tiled,
+                                                            onsite):
     """[X, U(dt)] psi and U(dt) psi (Alg. 7) with up to three coupled steps per
     pass in marching strips: the same results as single steps, and the
     oracle's; term counts leave full passes, a short last pass, a single last
     step, or no multi-step pass."""
     _need_gpu()
-    c = recipe(geometry, nx, ny, w=1.1, vac=0.02, seed=5 * nx + ny)
+    c = recipe(geometry, nx, ny, w=1.1, vac=0.02, seed=5 * nx + ny, onsite=onsite)
     _log(f"commutator propagator {geometry} {nx}x{ny} steps={steps} tiled={tiled}")
     one, two = _pair(c, tiled=tiled, steps=steps)
     lat = oracle_lattice(c)
