@@ -32,6 +32,10 @@
 
 typedef double complex cplx;
 
+/* Row loops shorter than this run on one thread: on small lattices the
+ * thread start-up would cost more than the loop. */
+#define ORC_PAR_MIN 32768
+
 /* With ORC_PROGRESS set in the environment, the time loops report each
  * finished time step on stderr (long runs at paper scale). */
 static void progress(const char *loop, int k, int n)
@@ -146,7 +150,7 @@ typedef struct {
 
 static void apply_h(const orc_ham *h, const cplx *x, cplx *y)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (h->n >= ORC_PAR_MIN)
     for (int64_t n = 0; n < h->n; ++n) {
         cplx s = 0.0;
         if (h->onsite) s = h->onsite[n] * x[n];
@@ -158,7 +162,7 @@ static void apply_h(const orc_ham *h, const cplx *x, cplx *y)
 
 static void apply_d(const orc_ham *h, const cplx *x, cplx *y)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (h->n >= ORC_PAR_MIN)
     for (int64_t n = 0; n < h->n; ++n) {
         cplx s = 0.0;
         for (int64_t e = h->row_ptr[n]; e < h->row_ptr[n + 1]; ++e)
@@ -204,7 +208,7 @@ static int moments(const orc_ham *h, const cplx *phil, const cplx *phir,
     }
     for (int m = 2; m < nm; ++m) {
         apply_h(h, p1, p2);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
         for (int64_t k = 0; k < n; ++k) p2[k] = 2.0 * p2[k] - p0[k];
         mu[m] = dot(n, phil, p2);
         cplx *tmp = p0; p0 = p1; p1 = p2; p2 = tmp;
@@ -285,11 +289,11 @@ static int evolve(const orc_ham *h, double hbar, double dt, int sign, int np,
     if (!rc) {
         memcpy(p0, in, (size_t)n * sizeof(cplx));
         apply_h(h, p0, p1);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
         for (int64_t k = 0; k < n; ++k) out[k] = c[0] * p0[k] + c[1] * p1[k];
         for (int m = 2; m < np; ++m) {
             apply_h(h, p1, p2);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
             for (int64_t k = 0; k < n; ++k) {
                 p2[k] = 2.0 * p2[k] - p0[k];
                 out[k] += c[m] * p2[k];
@@ -332,7 +336,7 @@ static int evolve_x(const orc_ham *h, double hbar, double dt, int np,
         /* q0 = [X,T_0] in = 0 (cvec is zeroed)                              */
         apply_h(h, p0, p1);                                /* T_1 in      */
         apply_d(h, in, q1);                                /* [X,T_1] in  */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
         for (int64_t k = 0; k < n; ++k) {
             outx[k] = c[1] * q1[k];
             if (outu) outu[k] = c[0] * p0[k] + c[1] * p1[k];
@@ -341,7 +345,7 @@ static int evolve_x(const orc_ham *h, double hbar, double dt, int np,
             apply_h(h, p1, p2);                            /* H~ T_{m-1}  */
             apply_d(h, p1, tmpv);                          /* D T_{m-1}   */
             apply_h(h, q1, q2);                            /* H~ [X,T_{m-1}] */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
             for (int64_t k = 0; k < n; ++k) {
                 q2[k] = 2.0 * tmpv[k] + 2.0 * q2[k] - q0[k];
                 p2[k] = 2.0 * p2[k] - p0[k];
@@ -372,7 +376,7 @@ static void apply_v(const orc_ham *h, double hbar, const cplx *x, cplx *y)
 {
     apply_d(h, x, y);
     cplx f = -I * (h->e_scale / hbar);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (h->n >= ORC_PAR_MIN)
     for (int64_t k = 0; k < h->n; ++k) y[k] *= f;
 }
 
@@ -436,7 +440,7 @@ int orc_msd(int64_t n, const int64_t *row_ptr, const int64_t *col,
             rc = evolve(&h, hbar, dt, +1, np, y, ya);           /* U(dt) Y_{k-1}     */
             if (!rc) rc = evolve_x(&h, hbar, dt, np, psi, xu, u); /* [X,U] psi', U psi' */
             if (rc) break;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
             for (int64_t q = 0; q < n; ++q) y[q] = ya[q] + xu[q];
             memcpy(psi, u, (size_t)n * sizeof(cplx));
         }

@@ -461,8 +461,8 @@ def test_threaded_oracle_equals_serial_bit_for_bit():
     """The oracle's row loops may run on several threads; every value is then
     computed by the same operations in the same order and the inner products
     stay serial, so moments, propagators and both time loops are bit-identical
-    for 1 and 4 threads."""
-    nx, ny = 64, 32
+    for 1 and 4 threads (on a lattice long enough for the loops to split)."""
+    nx, ny = 256, 160
     n = nx * ny
     act = ki.vacancy_mask(n, 0.02, 2000)
     lat = oracle.graphene(nx, ny, "sheet", -2.7, ki.anderson_onsite(n, 1.0, 1000), act)
