@@ -178,6 +178,25 @@ kpm_status kpm_moments(kpm_system *sys, int n_vec, const void *phi_l,
                        const void *phi_r, int n_moments, double *mu);
 
 /*
+ * kpm_moments for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same moments from the same kernels and launch shape, with every scratch
+ * buffer (the recursion states, the per-group partial sums and the reduced
+ * moments) taken from a fixed device array of 320 MiB per GPU that the
+ * library holds until the process ends.  It calls no hipMalloc or hipFree
+ * and records no graph or timing event.  Sizes whose scratch exceeds the
+ * array (two states, or four under a multi-step launch shape, of n_sites x
+ * n_vec complex values, plus partials and moments) return KPM_ERR_OOM with
+ * the bytes needed in kpm_last_error; the paper-scale sheet (3,998,792
+ * sites, one FP64 vector) fits.  Every call on a GPU shares that GPU's array
+ * and overwrites it: calls that overlap on one GPU (other streams, threads or
+ * systems) race and must be serialised by the caller.  Arguments, output and
+ * errors otherwise as kpm_moments; synchronises the stream.
+ */
+kpm_status kpm_moments_noalloc(kpm_system *sys, int n_vec, const void *phi_l,
+                               const void *phi_r, int n_moments, double *mu);
+
+/*
  * The moments of kpm_moments for phi_l = phi_r = phi (the DOS of Eq. 29), from
  * half the recursion steps: with phi_n = T_n(H~) phi, the product identities
  * T_{2n} = 2 T_n^2 - T_0 and T_{2n+1} = 2 T_{n+1} T_n - T_1 of the Chebyshev

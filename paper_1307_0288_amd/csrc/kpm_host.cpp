@@ -439,8 +439,10 @@ struct kpm_system {
 
     // The sweep of the moment step (and every other kernel) for n_vec =
     // 2^vshift under launch shape l.  Batches give each sample a contiguous
-    // run of work-groups (a multiple of 8) in proportion to its rows.
-    kpm_status sweep_with(int vshift, const kpm_launch &l, kpm::Sweep *out) {
+    // run of work-groups (a multiple of 8) in proportion to its rows; their
+    // device segment table is built on first use (may_alloc), or must exist.
+    kpm_status sweep_with(int vshift, const kpm_launch &l, kpm::Sweep *out,
+                          bool may_alloc = true) {
         kpm::Sweep sw{};
         sw.total = n << vshift;
         sw.vshift = vshift;
@@ -491,6 +493,8 @@ struct kpm_system {
                 return KPM_OK;
             }
         }
+        if (!may_alloc)
+            return fail(KPM_ERR_UNSUPPORTED, "no segment table for this launch shape");
         const int64_t units = want / kpm::kXcds;
         std::vector<kpm::Seg> seg(nseg);
         int64_t g0 = 0;
@@ -551,6 +555,9 @@ struct kpm_system {
         const double2 v = make_double2(0.0, -es[0] / kHbar);   // V = -i (E_s/hbar) D
         return nseg == 1 ? kpm::coef_val(v) : kpm::coef_tab(d_alpha, 1, 0, v);
     }
+
+    // This device's fixed scratch (kpm_moments_noalloc), looked up at creation.
+    void *static_scratch = nullptr;
 
     // Scratch limit (KPM_SCRATCH_LIMIT_MB at creation; 0 = none): the recursion
     // buffers, partials and moments together may not exceed it.
@@ -731,17 +738,18 @@ void moment_plan(int slots, int ring, bool dbl, int k, F visit, G segment) {
 // each uninterrupted run of recursion steps for kpm_set_timing.  In the
 // doubling form phil is phir, recursion step n fills slots 2n and 2n + 1, and
 // a final kernel turns the doubling sums into moments.  States rotate through
-// a_buf, b_buf (and the system's two extra states for two-step launches);
-// phir is only read.
+// a_buf, b_buf (and x0_buf, x1_buf for multi-step launches); group partials
+// go to `partial`, the reduced moments to `dmom`; phir is only read.
 template <typename V>
 kpm_status enqueue_moments(kpm_system *sys, const kpm::Sweep &sw, int ring, hipStream_t s,
                            bool events, bool dbl, bool re, const V *phil, const V *phir, int nm,
-                           V *a_buf, V *b_buf, int64_t stride_r, int64_t offset) {
+                           V *a_buf, V *b_buf, V *x0_buf, V *x1_buf, double2 *partial,
+                           double2 *dmom, int64_t stride_r, int64_t offset) {
     const kpm_launch &l = sys->shape(sw.vshift, dbl);
     const kpm::Ell h = sys->ell_for(l);
     const int k = sys->multi_steps(sw.vshift, l);
     const kpm::Lat2 lat = sys->lat2(l, k, sw.nwg);
-    V *pool[4] = {a_buf, b_buf, (V *)sys->xbuf[0], (V *)sys->xbuf[1]};
+    V *pool[4] = {a_buf, b_buf, x0_buf, x1_buf};
     const int npool = k > 1 ? 4 : 2;
     // a pool state that is none of x, y, z
     auto free_state = [&](const V *x, const V *y, const V *z) -> V * {
@@ -750,7 +758,7 @@ kpm_status enqueue_moments(kpm_system *sys, const kpm::Sweep &sw, int ring, hipS
         return nullptr;
     };
     // C_0 and C_1 (phi_0 = phi_R, phi_1 = H~ phi_0)
-    kpm::launch_moment_step<V>(h, sw, true, phir, nullptr, a_buf, phil, sys->partial, 0, s);
+    kpm::launch_moment_step<V>(h, sw, true, phir, nullptr, a_buf, phil, partial, 0, s);
     // phi_m = 2 H~ phi_{m-1} - phi_{m-2}; a single step writes over phi_{m-2}
     // (when it is scratch), a two-step launch into two other states
     const V *p0 = phir;
@@ -776,7 +784,7 @@ kpm_status enqueue_moments(kpm_system *sys, const kpm::Sweep &sw, int ring, hipS
                 V *o2 = free_state(p0, p1, o1);
                 if (!kpm::launch_moment_multi<V>(
                         h, sw, kind == k ? lat : sys->lat2(l, kind, sw.nwg), p1, p0, o1, o2,
-                        phil, sys->partial, m - c0, dbl, re, s)) {
+                        phil, partial, m - c0, dbl, re, s)) {
                     st = fail(KPM_ERR_UNSUPPORTED, "no multi-step kernel for %d steps", kind);
                     return;
                 }
@@ -788,10 +796,9 @@ kpm_status enqueue_moments(kpm_system *sys, const kpm::Sweep &sw, int ring, hipS
             for (int q = 0; q < npool; ++q) scratch = scratch || pool[q] == p0;
             V *out = scratch ? const_cast<V *>(p0) : free_state(p0, p1, nullptr);
             if (dbl)
-                kpm::launch_moment_step_doubled<V>(h, sw, p1, p0, out, sys->partial, m - c0, s);
+                kpm::launch_moment_step_doubled<V>(h, sw, p1, p0, out, partial, m - c0, s);
             else
-                kpm::launch_moment_step<V>(h, sw, false, p1, p0, out, phil, sys->partial,
-                                           m - c0, s);
+                kpm::launch_moment_step<V>(h, sw, false, p1, p0, out, phil, partial, m - c0, s);
             p0 = p1;
             p1 = out;
         },
@@ -801,11 +808,10 @@ kpm_status enqueue_moments(kpm_system *sys, const kpm::Sweep &sw, int ring, hipS
                 if (hipEventRecord(e1, s) != hipSuccess) st = fail(KPM_ERR_DEVICE, "event record");
                 open = false;
             }
-            kpm::launch_reduce(sys->partial, sw, std::min(c1, nm) - c0, sys->dmom, stride_r,
-                               offset + c0, s);
+            kpm::launch_reduce(partial, sw, std::min(c1, nm) - c0, dmom, stride_r, offset + c0, s);
         });
     KPM_TRY(st);
-    if (dbl) kpm::launch_undouble(sys->dmom, sw.nseg << sw.vshift, stride_r, offset, nm, s);
+    if (dbl) kpm::launch_undouble(dmom, sw.nseg << sw.vshift, stride_r, offset, nm, s);
     return KPM_OK;
 }
 
@@ -845,7 +851,8 @@ kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir
     }
     if (!sys->graphs)
         return enqueue_moments<V>(sys, sw, ring, sys->stream, sys->timing, dbl, re, phil, phir,
-                                  nm, a_buf, b_buf, stride_r, offset);
+                                  nm, a_buf, b_buf, (V *)sys->xbuf[0], (V *)sys->xbuf[1],
+                                  sys->partial, sys->dmom, stride_r, offset);
     kpm_system::GraphKey key{phil, phir, a_buf, b_buf, sys->partial, sys->dmom, nm, vshift,
                              l.groups_per_cu, l.ilp, l.streaming, l.compact, l.tiled, l.steps,
                              dbl ? 1 : 0, re ? 1 : 0, stride_r, offset};
@@ -854,7 +861,9 @@ kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir
         KPM_TRY(sys->ensure_capture_stream());
         KPM_HIP(hipStreamBeginCapture(sys->cap, hipStreamCaptureModeThreadLocal));
         kpm_status st = enqueue_moments<V>(sys, sw, ring, sys->cap, false, dbl, re, phil, phir,
-                                           nm, a_buf, b_buf, stride_r, offset);
+                                           nm, a_buf, b_buf, (V *)sys->xbuf[0],
+                                           (V *)sys->xbuf[1], sys->partial, sys->dmom, stride_r,
+                                           offset);
         hipGraph_t graph = nullptr;
         const hipError_t ec = hipStreamEndCapture(sys->cap, &graph);
         if (st != KPM_OK) {
@@ -999,9 +1008,10 @@ kpm_status check_common(kpm_system *sys, int n_vec, int *vshift) {
     return KPM_OK;
 }
 
-kpm_status finish_moments(kpm_system *sys, size_t elems, double2 *host) {
-    KPM_HIP(hipMemcpyAsync(host, sys->dmom, elems * sizeof(double2), hipMemcpyDeviceToHost,
-                           sys->stream));
+kpm_status finish_moments(kpm_system *sys, size_t elems, double2 *host,
+                          const double2 *src = nullptr) {
+    KPM_HIP(hipMemcpyAsync(host, src ? src : sys->dmom, elems * sizeof(double2),
+                           hipMemcpyDeviceToHost, sys->stream));
     KPM_HIP(hipStreamSynchronize(sys->stream));
     KPM_HIP(hipGetLastError());
     if (sys->timing) KPM_TRY(sys->harvest_events());
@@ -1020,6 +1030,48 @@ kpm_status moments_impl(kpm_system *sys, int vshift, const void *phil, const voi
     V *a = (V *)sys->vecs[0], *b = (V *)sys->vecs[1];
     KPM_TRY(run_moments<V>(sys, vshift, (const V *)phil, (const V *)phir, nm, a, b, nm, 0, dbl));
     return finish_moments(sys, elems, (double2 *)mu);
+}
+
+// moments_impl (direct form) without allocating: the recursion states (two,
+// or four under a multi-step launch shape), the group partials and the
+// reduced moments are carved from the device's fixed scratch, which each call
+// overwrites; no graph capture and no timing events.
+template <typename V>
+kpm_status moments_noalloc_impl(kpm_system *sys, int vshift, const void *phil, const void *phir,
+                                int nm, double *mu) {
+    if (!sys->static_scratch)
+        return fail(KPM_ERR_DEVICE, "no fixed scratch on device %d", sys->device);
+    const kpm_launch &l = sys->shape(vshift, false);
+    kpm::Sweep sw;
+    KPM_TRY(sys->sweep_with(vshift, l, &sw, false));
+    const int k = sys->multi_steps(vshift, l);
+    const int slots = moment_slots(nm, false);
+    const int ring = std::min(std::max(slots, 2), kPartialRing - kPartialRing % k);
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t nvec = (size_t)1 << vshift;
+    const size_t sb = up(sys->state_bytes(vshift));
+    const size_t nstates = k > 1 ? 4 : 2;
+    const size_t pb = up((size_t)(ring + 2) * sw.nwg * nvec * sizeof(double2));
+    const size_t elems = (size_t)sys->nseg * nvec * nm;
+    const size_t db = up(elems * sizeof(double2));
+    const size_t need = nstates * sb + pb + db;
+    if (need > kpm::kStaticScratchBytes)
+        return fail(KPM_ERR_OOM,
+                    "kpm_moments_noalloc needs %zu bytes of scratch (%zu states of %zu bytes, "
+                    "partials, moments), more than its fixed %zu bytes",
+                    need, nstates, sb, (size_t)kpm::kStaticScratchBytes);
+    char *base = (char *)sys->static_scratch;
+    V *st[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (size_t q = 0; q < nstates; ++q) st[q] = (V *)(base + q * sb);
+    double2 *partial = (double2 *)(base + nstates * sb);
+    double2 *dmom = (double2 *)(base + nstates * sb + pb);
+    sys->stats.step_rows = sw.total;
+    sys->stats.step_bytes = k > 1 ? sys->step2_bytes(false) : sys->step_bytes(vshift, false);
+    sys->stats.site_updates += (int64_t)std::max(nm - 1, 1) * sw.total;
+    KPM_TRY(enqueue_moments<V>(sys, sw, ring, sys->stream, false, false, false, (const V *)phil,
+                               (const V *)phir, nm, st[0], st[1], st[2], st[3], partial, dmom,
+                               nm, 0));
+    return finish_moments(sys, elems, (double2 *)mu, dmom);
 }
 
 template <typename V>
@@ -1508,6 +1560,17 @@ kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int devi
         for (int s = 0; s < nseg; ++s) al[s] = make_double2(0.0, -sys->es[s] / kHbar);
         st = upload((void **)&sys->d_alpha, al.data(), al.size() * sizeof(double2));
     }
+    if (st == KPM_OK) {
+        const hipError_t e = kpm::static_scratch(device, &sys->static_scratch);
+        if (e != hipSuccess)
+            st = fail(KPM_ERR_DEVICE, "fixed scratch address: %s", hipGetErrorString(e));
+    }
+    // segment tables of the starting launch shapes (the allocation-free entry
+    // point only looks them up)
+    for (int v = 0; v < 7 && st == KPM_OK && nseg > 1; ++v) {
+        kpm::Sweep sw;
+        st = sys->sweep_with(v, sys->launch[v], &sw);
+    }
     if (st != KPM_OK) return bail(st);
     *out = sys;
     return KPM_OK;
@@ -1581,6 +1644,18 @@ kpm_status kpm_moments(kpm_system *sys, int n_vec, const void *phil, const void 
     DeviceGuard g(sys->device);
     return sys->prec == KPM_FP64 ? moments_impl<double2>(sys, vs, phil, phir, n_moments, mu, false)
                                  : moments_impl<float2>(sys, vs, phil, phir, n_moments, mu, false);
+}
+
+kpm_status kpm_moments_noalloc(kpm_system *sys, int n_vec, const void *phil, const void *phir,
+                               int n_moments, double *mu) {
+    int vs;
+    KPM_TRY(check_common(sys, n_vec, &vs));
+    if (!phil || !phir || !mu) return fail(KPM_ERR_INVALID, "null buffer");
+    if (n_moments < 1) return fail(KPM_ERR_INVALID, "n_moments must be >= 1");
+    DeviceGuard g(sys->device);
+    return sys->prec == KPM_FP64
+               ? moments_noalloc_impl<double2>(sys, vs, phil, phir, n_moments, mu)
+               : moments_noalloc_impl<float2>(sys, vs, phil, phir, n_moments, mu);
 }
 
 kpm_status kpm_moments_doubled(kpm_system *sys, int n_vec, const void *phi, int n_moments,
@@ -1817,6 +1892,11 @@ kpm_status kpm_set_launch(kpm_system *sys, int n_vec, const kpm_launch *l) {
     if (!l || !valid_launch(*l)) return fail(KPM_ERR_INVALID, "launch shape out of range");
     sys->launch[vs] = *l;
     sys->launch_dbl[vs] = *l;
+    if (sys->nseg > 1) {      // its segment table, for the allocation-free entry point
+        DeviceGuard g(sys->device);
+        kpm::Sweep sw;
+        KPM_TRY(sys->sweep_with(vs, *l, &sw));
+    }
     return KPM_OK;
 }
 

@@ -219,4 +219,11 @@ void launch_kpm_sum(const double *mom, int rows, int nm, const double *w,
                     const double *eps, const double *pref, int ne, double *out,
                     hipStream_t s);
 
+// Fixed device scratch of the entry point that allocates nothing
+// (kpm_moments_noalloc): a file-scope device array of kStaticScratchBytes per
+// GPU.  static_scratch returns its address on `device`, which must be the
+// current device; the address is looked up once per device and kept.
+constexpr size_t kStaticScratchBytes = (size_t)320 << 20;
+hipError_t static_scratch(int device, void **ptr);
+
 }  // namespace kpm

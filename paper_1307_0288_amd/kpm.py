@@ -27,7 +27,7 @@ BOND_NM = 0.142
 ABI_SYMBOLS = ("kpm_build_graphene", "kpm_validate", "kpm_system_create", "kpm_system_destroy",
                "kpm_system_set_stream", "kpm_system_n_sites", "kpm_batch_create",
                "kpm_system_n_samples", "kpm_system_offsets", "kpm_moments",
-               "kpm_moments_doubled", "kpm_evolve", "kpm_evolve_x", "kpm_vac", "kpm_msd",
+               "kpm_moments_noalloc", "kpm_moments_doubled", "kpm_evolve", "kpm_evolve_x", "kpm_vac", "kpm_msd",
                "kpm_msd_doubled", "kpm_fourier_moments", "kpm_ftm_sum",
                "kpm_kpm_sum", "kpm_sigma_gk",
                "kpm_sigma_e1", "kpm_sigma_e2", "kpm_length", "kpm_conductance",
@@ -93,6 +93,7 @@ def _signatures():
         "kpm_system_destroy": [vp],
         "kpm_system_set_stream": [vp, vp],
         "kpm_moments": [vp, C.c_int, vp, vp, C.c_int, dp],
+        "kpm_moments_noalloc": [vp, C.c_int, vp, vp, C.c_int, dp],
         "kpm_moments_doubled": [vp, C.c_int, vp, C.c_int, dp],
         "kpm_evolve": [vp, C.c_int, vp, C.c_double, C.c_int, C.c_int],
         "kpm_evolve_x": [vp, C.c_int, vp, vp, vp, C.c_double, C.c_int],
@@ -477,6 +478,19 @@ def kpm_moments(sys: System, phi_l, phi_r, n_moments: int) -> np.ndarray:
     out = np.empty((sys.n_samples, nv, n_moments, 2))
     sys._sync_stream()
     _check(lib().kpm_moments(sys.handle, nv, pl, pr, n_moments, _dp(out)))
+    return sys._shape(out[..., 0] + 1j * out[..., 1])
+
+
+def kpm_moments_noalloc(sys: System, phi_l, phi_r, n_moments: int) -> np.ndarray:
+    """kpm_moments through the entry point that allocates no device memory
+    (its scratch is the library's fixed per-GPU array)."""
+    pl, nv = sys._state(phi_l, "phi_l")
+    pr, nv2 = sys._state(phi_r, "phi_r")
+    if nv != nv2:
+        raise ValueError("phi_l and phi_r differ in n_vec")
+    out = np.empty((sys.n_samples, nv, n_moments, 2))
+    sys._sync_stream()
+    _check(lib().kpm_moments_noalloc(sys.handle, nv, pl, pr, n_moments, _dp(out)))
     return sys._shape(out[..., 0] + 1j * out[..., 1])
 
 
