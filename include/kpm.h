@@ -481,6 +481,22 @@ kpm_status kpm_xu_state(kpm_system *sys, int n_vec, const void *phi, int n_steps
  * shape changes only the order of the inner-product partial sums (in the
  * doubling form the strips accumulate only the real parts, the moments of
  * phi_L = phi_R being real).
+ *
+ * vectors_per_wave selects, for n_vec > 1 on a one-sample system, how a
+ * wavefront's 64 lanes cover the states: 0 (default) puts the n_vec vectors
+ * of a row in adjacent lanes (64 / n_vec rows per wavefront, one structure
+ * read per row for all vectors); 1 gives every wavefront one vector: the
+ * library then keeps its recursion states vector-major (one plane of
+ * n_sites values per vector, converted from and to the caller's
+ * [n_sites][n_vec] layout at the start and end of each call), every launch
+ * sweeps all planes (the plane is the grid's second dimension), and the
+ * multi-step shapes above apply to each plane as to one vector.
+ * plane_groups (vectors_per_wave = 1 only) is the number of work-groups per
+ * plane, a multiple of 8 up to 65536, or 0 for the grid groups_per_cu gives
+ * one vector; fewer groups per plane make the strips of tiled = 5 longer (up
+ * to the whole sample), so fewer boundary chains are recomputed.  Batches
+ * and n_vec = 1 ignore both fields, and the layout of a call follows the
+ * direct form's shape (kpm_set_launch) also for doubling-form moment sets.
  */
 typedef struct {
     int32_t groups_per_cu;
@@ -489,6 +505,8 @@ typedef struct {
     int32_t compact;
     int32_t tiled;
     int32_t steps;
+    int32_t vectors_per_wave;
+    int32_t plane_groups;
 } kpm_launch;
 
 /* The shape a new system starts with for n_vec vectors per row (both forms):

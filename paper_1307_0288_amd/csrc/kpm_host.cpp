@@ -84,7 +84,13 @@ bool valid_launch(const kpm_launch &l) {
            (l.ilp == 1 || l.ilp == 2 || l.ilp == 4) && (l.streaming == 0 || l.streaming == 1) &&
            (l.compact == 0 || l.compact == 1) && l.tiled >= 0 &&
            l.tiled <= (l.steps > 1 ? 5 : 3) && l.steps >= 1 &&
-           l.steps <= (l.tiled >= 3 ? 8 : 4);
+           l.steps <= (l.tiled >= 3 ? 8 : 4) &&
+           (l.vectors_per_wave == 0 || l.vectors_per_wave == 1) &&
+           (l.plane_groups == 0 ||
+            (l.plane_groups >= kpm::kXcds && l.plane_groups <= 65536 &&
+             l.plane_groups % kpm::kXcds == 0)) &&
+           // vector-major states take several steps per pass only in the strips
+           !(l.vectors_per_wave == 1 && l.steps > 1 && l.tiled < 3);
 }
 
 // Tile width (rows) of the tiled traversal for 2^vshift vectors per row: a
@@ -181,7 +187,7 @@ bool graphene_flags(const std::vector<uint32_t> &code, std::vector<uint32_t> &fl
 
 // Launch shape used until kpm_autotune or kpm_set_launch picks another.
 kpm_launch default_launch(int vshift, kpm_precision prec) {
-    kpm_launch l;
+    kpm_launch l{};
     // measured on MI355X (paper-scale sheet): one vector favours 4 groups per
     // CU, many vectors 8; streaming helps every vector count
     // the compact neighbour form pays off while the per-row structure is a
@@ -214,6 +220,13 @@ kpm_launch default_launch(int vshift, kpm_precision prec) {
 // strips caps the steps at 4, and single steps take a traversal of at most 3
 // (row order when the default was a strip shape).  KPM_ERR_INVALID when the
 // result is still not a valid shape.
+bool launch_env_set() {
+    for (const char *v : {"KPM_GROUPS_PER_CU", "KPM_ILP", "KPM_STREAMING", "KPM_COMPACT_LAUNCH",
+                          "KPM_TILED", "KPM_STEPS"})
+        if (std::getenv(v)) return true;
+    return false;
+}
+
 kpm_status env_launch(int vshift, kpm_precision prec, kpm_launch *out) {
     kpm_launch l = default_launch(vshift, prec);
     if (const char *env = std::getenv("KPM_GROUPS_PER_CU"))
@@ -385,11 +398,14 @@ struct kpm_system {
             // strips sized for the grid: the fewest loop passes of the wavefront
             // with the most strips (passes of kMarchRows rows, tj + 2k rows per
             // strip), then the longest strips (fewer reloaded boundary chains);
-            // 8 .. 64 chains
+            // at least 8 chains
             const int64_t nst = (l2nx + kpm::kWave - 2 * k - 1) / (kpm::kWave - 2 * k);
             const int64_t waves = (int64_t)nwg * (kpm::kBlock / kpm::kWave);
             int64_t best = -1;
-            for (int j = 8; j <= 64; ++j) {
+            // up to the whole sample when the grid has few wavefronts per
+            // sample (vector-major states with few groups per plane)
+            const int jmax = std::max<int>(64, l2ny);
+            for (int j = 8; j <= jmax; ++j) {
                 const int64_t strips = nst * ((l2ny + j - 1) / j);
                 const int64_t passes = (j + 2 * k + kpm::kMarchRows - 1) / kpm::kMarchRows;
                 const int64_t cost = (strips + waves - 1) / waves * passes;
@@ -444,6 +460,8 @@ struct kpm_system {
     kpm_status sweep_with(int vshift, const kpm_launch &l, kpm::Sweep *out,
                           bool may_alloc = true) {
         kpm::Sweep sw{};
+        sw.nplanes = 1;
+        sw.pstride = 0;
         sw.total = n << vshift;
         sw.vshift = vshift;
         sw.ilp = l.ilp;
@@ -528,7 +546,42 @@ struct kpm_system {
         return KPM_OK;
     }
 
-    kpm_status sweep(int vshift, kpm::Sweep *out) { return sweep_with(vshift, launch[vshift], out); }
+    // Whether calls with 2^vshift vectors keep their states vector-major (one
+    // plane per vector; one-sample systems under a shape with one vector per
+    // wavefront).  The direct form's shape decides for both forms.
+    bool planar(int vshift) const {
+        return vshift > 0 && nseg == 1 && launch[vshift].vectors_per_wave == 1;
+    }
+
+    // The sweep of every kernel of a call with 2^vshift vectors under shape l:
+    // sweep_with, or for vector-major states the one-vector sweep of each
+    // plane (plane_groups work-groups, when set) over 2^vshift planes.
+    kpm_status sweep_planes(int vshift, const kpm_launch &l, kpm::Sweep *out,
+                            bool may_alloc = true) {
+        KPM_TRY(sweep_with(0, l, out, may_alloc));
+        if (l.plane_groups > 0) {
+            out->nwg = l.plane_groups;
+            out->one.nwg = l.plane_groups;
+        }
+        out->nplanes = 1 << vshift;
+        out->pstride = n;
+        return KPM_OK;
+    }
+    kpm_status sweep_for(int vshift, const kpm_launch &l, kpm::Sweep *out,
+                         bool may_alloc = true) {
+        return planar(vshift) ? sweep_planes(vshift, l, out, may_alloc)
+                              : sweep_with(vshift, l, out, may_alloc);
+    }
+    kpm_status sweep(int vshift, kpm::Sweep *out) { return sweep_for(vshift, launch[vshift], out); }
+
+    // Algorithmic bytes of one single-step moment launch of sweep sw under
+    // shape l (step_bytes for any layout).
+    int64_t sweep_step_bytes(const kpm::Sweep &sw, const kpm_launch &l, bool dbl) const {
+        const bool compact = d_pid && l.compact;
+        const int64_t per_row = (compact ? 1 : 4 * w) + (d_onsf ? 4 : 8) + (d_hop ? 8 * w : 0);
+        const int64_t acc = dbl ? 3 : 4;
+        return (int64_t)sw.nplanes * (n * ((acc * (int64_t)elem_bytes()) << sw.vshift) + n * per_row);
+    }
 
     // Coefficients c_m of Eq. 36 for every sample: host values for a single
     // sample (kernel arguments), a cached device table [nseg][np] otherwise.
@@ -550,6 +603,9 @@ struct kpm_system {
         *tab = c.d;
         return KPM_OK;
     }
+
+    // Elements one launch of sweep sw updates (rows x vectors).
+    static int64_t sweep_elems(const kpm::Sweep &sw) { return sw.total * sw.nplanes; }
 
     kpm::Coef alpha() const {
         const double2 v = make_double2(0.0, -es[0] / kHbar);   // V = -i (E_s/hbar) D
@@ -733,6 +789,21 @@ void moment_plan(int slots, int ring, bool dbl, int k, F visit, G segment) {
     }
 }
 
+// The sweep that reduces the partials of launches of sw: partials of
+// vector-major launches are [slot][nwg][planes], which is the layout of
+// 2^vshift vectors side by side with vshift = log2(planes).
+kpm::Sweep reduce_sweep(const kpm::Sweep &sw) {
+    kpm::Sweep r = sw;
+    if (sw.nplanes > 1) {
+        int v = 0;
+        while ((1 << v) < sw.nplanes) ++v;
+        r.vshift = v;
+        r.nplanes = 1;
+        r.pstride = 0;
+    }
+    return r;
+}
+
 // Launches of one moment set (Alg. 5) on stream s: the first step, the
 // recursion steps and the ring reductions into sys->dmom.  `events` brackets
 // each uninterrupted run of recursion steps for kpm_set_timing.  In the
@@ -808,10 +879,12 @@ kpm_status enqueue_moments(kpm_system *sys, const kpm::Sweep &sw, int ring, hipS
                 if (hipEventRecord(e1, s) != hipSuccess) st = fail(KPM_ERR_DEVICE, "event record");
                 open = false;
             }
-            kpm::launch_reduce(partial, sw, std::min(c1, nm) - c0, dmom, stride_r, offset + c0, s);
+            kpm::launch_reduce(partial, reduce_sweep(sw), std::min(c1, nm) - c0, dmom, stride_r,
+                               offset + c0, s);
         });
     KPM_TRY(st);
-    if (dbl) kpm::launch_undouble(dmom, sw.nseg << sw.vshift, stride_r, offset, nm, s);
+    const kpm::Sweep rs = reduce_sweep(sw);
+    if (dbl) kpm::launch_undouble(dmom, rs.nseg << rs.vshift, stride_r, offset, nm, s);
     return KPM_OK;
 }
 
@@ -827,8 +900,8 @@ kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir
                        bool re = false) {
     const kpm_launch &l = sys->shape(vshift, dbl);
     kpm::Sweep sw;
-    KPM_TRY(sys->sweep_with(vshift, l, &sw));
-    const int k = sys->multi_steps(vshift, l);
+    KPM_TRY(sys->sweep_for(vshift, l, &sw));
+    const int k = sys->multi_steps(sw.vshift, l);
     if (k > 1) KPM_TRY(sys->ensure_xbuf(vshift));
     // Group partials live in a ring of moment slots that is reduced into
     // sys->dmom whenever it fills, bounding its size at any N_m; the ring is
@@ -840,11 +913,11 @@ kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir
     int64_t n1 = 0, n2 = 0;
     moment_plan(slots, ring, dbl, k, [&](int kind, int, int) { (kind > 1 ? n2 : n1) += 1; },
                 [](int, int, int) {});
-    const int64_t b1 = sys->step_bytes(vshift, dbl), b2 = sys->step2_bytes(dbl);
+    const int64_t b1 = sys->sweep_step_bytes(sw, l, dbl), b2 = sys->step2_bytes(dbl) * sw.nplanes;
     const int steps = dbl ? slots / 2 - 1 : std::max(nm - 2, 0);   // recursion steps
-    sys->stats.step_rows = sw.total;
+    sys->stats.step_rows = kpm_system::sweep_elems(sw);
     sys->stats.step_bytes = n2 > 0 ? b2 : b1;
-    sys->stats.site_updates += (int64_t)(steps + 1) * sw.total;
+    sys->stats.site_updates += (int64_t)(steps + 1) * kpm_system::sweep_elems(sw);
     if (sys->timing) {
         sys->stats.step_launches += n1 + n2;
         sys->stats.step_bytes_total += n1 * b1 + n2 * b2;
@@ -907,7 +980,7 @@ kpm_status run_evolve(kpm_system *sys, int vshift, const V *in, V *acc, const V 
     // states that the pass does not read (never to `in`), and a last pass
     // takes the remaining steps when there are at least two
     const kpm_launch &l = sys->launch[vshift];
-    const int k = sys->multi_steps(vshift, l);
+    const int k = sys->multi_steps(sw.vshift, l);
     if (k > 1 && l.tiled >= 3 && sys->d_flags && !tab && np - m >= 2) {
         KPM_TRY(sys->ensure_xbuf(vshift));
         V *pool[4] = {a_buf, b_buf, (V *)sys->xbuf[0], (V *)sys->xbuf[1]};
@@ -934,7 +1007,7 @@ kpm_status run_evolve(kpm_system *sys, int vshift, const V *in, V *acc, const V 
         p0 = p1;
         p1 = out;
     }
-    sys->stats.site_updates += (int64_t)(np - 1) * sw.total;
+    sys->stats.site_updates += (int64_t)(np - 1) * kpm_system::sweep_elems(sw);
     return KPM_OK;
 }
 
@@ -959,7 +1032,7 @@ kpm_status run_evolve_x(kpm_system *sys, int vshift, const V *in, V *accx, V *ac
     // each recursion's new states go to two of its four scratch states that the
     // pass does not read
     const kpm_launch &l = sys->launch[vshift];
-    const int k = std::min(sys->multi_steps(vshift, l), 3);
+    const int k = std::min(sys->multi_steps(sw.vshift, l), 3);
     if (k > 1 && l.tiled >= 3 && sys->d_flags && sys->d_pxw && !tab && np - m >= 2) {
         KPM_TRY(sys->ensure_xbuf(vshift, 4));
         V *pool_p[4] = {pa, pb, (V *)sys->xbuf[0], (V *)sys->xbuf[1]};
@@ -997,7 +1070,7 @@ kpm_status run_evolve_x(kpm_system *sys, int vshift, const V *in, V *accx, V *ac
         q0 = q1;
         q1 = qout;
     }
-    sys->stats.site_updates += 2 * (int64_t)(np - 1) * sw.total;
+    sys->stats.site_updates += 2 * (int64_t)(np - 1) * kpm_system::sweep_elems(sw);
     return KPM_OK;
 }
 
@@ -1021,14 +1094,44 @@ kpm_status finish_moments(kpm_system *sys, size_t elems, double2 *host,
     return KPM_OK;
 }
 
+// The caller's state src ([n_sites][n_vec]) into the device buffer dst in
+// the layout of the call (vector-major when planar), and back.
+template <typename V>
+kpm_status stage_in(kpm_system *sys, int vshift, const void *src, V *dst) {
+    if (sys->planar(vshift))
+        kpm::launch_planar<V>((const V *)src, dst, sys->n, vshift, true, sys->stream);
+    else
+        KPM_HIP(hipMemcpyAsync(dst, src, sys->state_bytes(vshift), hipMemcpyDeviceToDevice,
+                               sys->stream));
+    return KPM_OK;
+}
+template <typename V>
+kpm_status stage_out(kpm_system *sys, int vshift, const V *src, void *dst) {
+    if (sys->planar(vshift))
+        kpm::launch_planar<V>(src, (V *)dst, sys->n, vshift, false, sys->stream);
+    else
+        KPM_HIP(hipMemcpyAsync(dst, src, sys->state_bytes(vshift), hipMemcpyDeviceToDevice,
+                               sys->stream));
+    return KPM_OK;
+}
+
 template <typename V>
 kpm_status moments_impl(kpm_system *sys, int vshift, const void *phil, const void *phir,
                         int nm, double *mu, bool dbl) {
-    KPM_TRY(sys->ensure_vecs(2, vshift));
+    const bool pl = sys->planar(vshift);
+    KPM_TRY(sys->ensure_vecs(pl ? 4 : 2, vshift));
     const size_t elems = (size_t)sys->nseg * ((size_t)1 << vshift) * nm;
     KPM_TRY(sys->ensure_dmom(elems));
     V *a = (V *)sys->vecs[0], *b = (V *)sys->vecs[1];
-    KPM_TRY(run_moments<V>(sys, vshift, (const V *)phil, (const V *)phir, nm, a, b, nm, 0, dbl));
+    const V *l = (const V *)phil, *r = (const V *)phir;
+    if (pl) {           // vector-major copies of the operands
+        V *sl = (V *)sys->vecs[2], *sr = (V *)sys->vecs[3];
+        KPM_TRY(stage_in<V>(sys, vshift, phil, sl));
+        if (phir != phil) KPM_TRY(stage_in<V>(sys, vshift, phir, sr));
+        l = sl;
+        r = phir != phil ? sr : sl;
+    }
+    KPM_TRY(run_moments<V>(sys, vshift, l, r, nm, a, b, nm, 0, dbl));
     return finish_moments(sys, elems, (double2 *)mu);
 }
 
@@ -1076,11 +1179,16 @@ kpm_status moments_noalloc_impl(kpm_system *sys, int vshift, const void *phil, c
 
 template <typename V>
 kpm_status evolve_impl(kpm_system *sys, int vshift, void *phi, double dt, int sign, int np) {
-    KPM_TRY(sys->ensure_vecs(3, vshift));
+    const bool pl = sys->planar(vshift);
+    KPM_TRY(sys->ensure_vecs(pl ? 4 : 3, vshift));
     V *a = (V *)sys->vecs[0], *b = (V *)sys->vecs[1], *acc = (V *)sys->vecs[2];
-    KPM_TRY(run_evolve<V>(sys, vshift, (const V *)phi, acc, nullptr, dt, sign, np, a, b));
-    KPM_HIP(hipMemcpyAsync(phi, acc, sys->state_bytes(vshift), hipMemcpyDeviceToDevice,
-                           sys->stream));
+    const V *in = (const V *)phi;
+    if (pl) {
+        KPM_TRY(stage_in<V>(sys, vshift, phi, (V *)sys->vecs[3]));
+        in = (const V *)sys->vecs[3];
+    }
+    KPM_TRY(run_evolve<V>(sys, vshift, in, acc, nullptr, dt, sign, np, a, b));
+    KPM_TRY(stage_out<V>(sys, vshift, acc, phi));
     KPM_HIP(hipGetLastError());
     return KPM_OK;
 }
@@ -1088,11 +1196,20 @@ kpm_status evolve_impl(kpm_system *sys, int vshift, void *phi, double dt, int si
 template <typename V>
 kpm_status evolve_x_impl(kpm_system *sys, int vshift, const void *phi, void *outx, void *outu,
                          double dt, int np) {
-    KPM_TRY(sys->ensure_vecs(5, vshift));
+    const bool pl = sys->planar(vshift);
+    KPM_TRY(sys->ensure_vecs(pl ? 7 : 5, vshift));
     V *pa = (V *)sys->vecs[0], *pb = (V *)sys->vecs[1], *qa = (V *)sys->vecs[2],
       *qb = (V *)sys->vecs[3], *u = (V *)sys->vecs[4];
-    KPM_TRY(run_evolve_x<V>(sys, vshift, (const V *)phi, (V *)outx, outu ? (V *)outu : u, dt,
-                            np, pa, pb, qa, qb));
+    if (!pl) {
+        KPM_TRY(run_evolve_x<V>(sys, vshift, (const V *)phi, (V *)outx, outu ? (V *)outu : u,
+                                dt, np, pa, pb, qa, qb));
+    } else {
+        V *in = (V *)sys->vecs[5], *ox = (V *)sys->vecs[6];
+        KPM_TRY(stage_in<V>(sys, vshift, phi, in));
+        KPM_TRY(run_evolve_x<V>(sys, vshift, in, ox, u, dt, np, pa, pb, qa, qb));
+        KPM_TRY(stage_out<V>(sys, vshift, ox, outx));
+        if (outu) KPM_TRY(stage_out<V>(sys, vshift, u, outu));
+    }
     KPM_HIP(hipGetLastError());
     return KPM_OK;
 }
@@ -1148,8 +1265,7 @@ kpm_status vac_impl(kpm_system *sys, int vshift, const void *phi, int nsteps, do
                     int nm, double *out) {
     KPM_TRY(sys->ensure_vecs(9, vshift));
     V *psi = (V *)sys->vecs[7], *rr = (V *)sys->vecs[8];
-    KPM_HIP(hipMemcpyAsync(psi, phi, sys->state_bytes(vshift), hipMemcpyDeviceToDevice,
-                           sys->stream));
+    KPM_TRY(stage_in<V>(sys, vshift, phi, psi));
     return vac_run<V>(sys, vshift, psi, rr, true, nsteps, dt, np, nm, out);
 }
 
@@ -1202,9 +1318,32 @@ kpm_status msd_impl(kpm_system *sys, int vshift, const void *phi, int nsteps, do
                     int nm, double *out, bool dbl) {
     KPM_TRY(sys->ensure_vecs(9, vshift));
     V *psi = (V *)sys->vecs[7], *y = (V *)sys->vecs[8];
-    KPM_HIP(hipMemcpyAsync(psi, phi, sys->state_bytes(vshift), hipMemcpyDeviceToDevice,
-                           sys->stream));
+    KPM_TRY(stage_in<V>(sys, vshift, phi, psi));
     return msd_run<V>(sys, vshift, psi, y, true, nsteps, dt, np, nm, dbl, out);
+}
+
+// The resumable loops on the caller's two state buffers: run in place, or
+// for vector-major states on staged copies converted back at the end (Y_0
+// and R_0 are not read when the loop starts).
+template <typename V>
+kpm_status continue_impl(kpm_system *sys, int vshift, void *a_io, void *b_io, bool start,
+                         int nsteps, double dt, int np, int nm, int kind, double *out) {
+    // kind: 0 VAC, 1 MSD, 2 MSD in the doubling form
+    auto run = [&](V *a, V *b) {
+        return kind == 0 ? vac_run<V>(sys, vshift, a, b, start, nsteps, dt, np, nm, out)
+                         : msd_run<V>(sys, vshift, a, b, start, nsteps, dt, np, nm, kind == 2,
+                                      out);
+    };
+    if (!sys->planar(vshift)) return run((V *)a_io, (V *)b_io);
+    KPM_TRY(sys->ensure_vecs(11, vshift));
+    V *a = (V *)sys->vecs[9], *b = (V *)sys->vecs[10];
+    KPM_TRY(stage_in<V>(sys, vshift, a_io, a));
+    if (!start) KPM_TRY(stage_in<V>(sys, vshift, b_io, b));
+    KPM_TRY(run(a, b));
+    KPM_TRY(stage_out<V>(sys, vshift, a, a_io));
+    KPM_TRY(stage_out<V>(sys, vshift, b, b_io));
+    KPM_HIP(hipStreamSynchronize(sys->stream));
+    return KPM_OK;
 }
 
 // Y_n = [X, U(n dt)] phi by the recursion of Eq. 44, copied to out.
@@ -1217,6 +1356,11 @@ kpm_status xu_state_impl(kpm_system *sys, int vshift, const void *phi_v, int nst
     V *y = (V *)sys->vecs[4], *y2 = (V *)sys->vecs[5], *xu = (V *)sys->vecs[6];
     V *psi = (V *)sys->vecs[7], *psi2 = (V *)sys->vecs[8];
     const V *cur = (const V *)phi_v;
+    if (sys->planar(vshift)) {
+        KPM_TRY(sys->ensure_vecs(10, vshift));
+        KPM_TRY(stage_in<V>(sys, vshift, phi_v, (V *)sys->vecs[9]));
+        cur = (const V *)sys->vecs[9];
+    }
     for (int k = 1; k <= nsteps; ++k) {
         KPM_TRY(run_evolve_x<V>(sys, vshift, cur, xu, psi2, dt, np, pa, pb, qa, qb));
         std::swap(psi, psi2);
@@ -1228,7 +1372,7 @@ kpm_status xu_state_impl(kpm_system *sys, int vshift, const void *phi_v, int nst
             std::swap(y, y2);
         }
     }
-    KPM_HIP(hipMemcpyAsync(out, y, sys->state_bytes(vshift), hipMemcpyDeviceToDevice, sys->stream));
+    KPM_TRY(stage_out<V>(sys, vshift, y, out));
     KPM_HIP(hipGetLastError());
     return KPM_OK;
 }
@@ -1248,10 +1392,21 @@ kpm_status fourier_impl(kpm_system *sys, int vshift, const void *phil_v, const v
     V *a = (V *)sys->vecs[0], *b = (V *)sys->vecs[1], *psi = (V *)sys->vecs[2],
       *psi2 = (V *)sys->vecs[3];
     const V *phil = (const V *)phil_v, *phir = (const V *)phir_v;
+    if (sys->planar(vshift)) {
+        KPM_TRY(sys->ensure_vecs(6, vshift));
+        a = (V *)sys->vecs[0];
+        b = (V *)sys->vecs[1];
+        psi = (V *)sys->vecs[2];
+        psi2 = (V *)sys->vecs[3];
+        KPM_TRY(stage_in<V>(sys, vshift, phil_v, (V *)sys->vecs[4]));
+        KPM_TRY(stage_in<V>(sys, vshift, phir_v, (V *)sys->vecs[5]));
+        phil = (const V *)sys->vecs[4];
+        phir = (const V *)sys->vecs[5];
+    }
     hipStream_t s = sys->stream;
     auto dot_into = [&](const V *x, int64_t idx) {
         kpm::launch_dot<V>(sw, phil, x, sys->partial, 0, s);
-        kpm::launch_reduce(sys->partial, sw, 1, sys->dmom, per_r, idx, s);
+        kpm::launch_reduce(sys->partial, reduce_sweep(sw), 1, sys->dmom, per_r, idx, s);
     };
     dot_into(phir, nm);
     for (int dir = +1; dir >= -1; dir -= 2) {
@@ -1289,8 +1444,10 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
     auto time_shape = [&](const kpm_launch &l, bool dbl, float *out_ms) -> kpm_status {
         const kpm::Ell h = sys->ell_for(l);
         kpm::Sweep sw;
-        KPM_TRY(sys->sweep_with(vs, l, &sw));
-        const int ks = sys->multi_steps(vs, l);
+        KPM_TRY(l.vectors_per_wave == 1 && vs > 0 && sys->nseg == 1
+                    ? sys->sweep_planes(vs, l, &sw)
+                    : sys->sweep_with(vs, l, &sw));
+        const int ks = sys->multi_steps(sw.vshift, l);
         if (ks > 1) KPM_TRY(sys->ensure_xbuf(vs));
         KPM_TRY(sys->ensure_partial(2 * ks, sw.nwg, 1 << vs));
         const kpm::Lat2 lat = sys->lat2(l, ks, sw.nwg);
@@ -1336,7 +1493,7 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
     std::vector<kpm_launch> cand;
     for (int g : groups)
         for (int q = 0; q < 6 * forms * tilings; ++q) {
-            kpm_launch l;
+            kpm_launch l{};
             l.groups_per_cu = g;
             l.ilp = ilps[q % 3];
             l.streaming = (q / 3) % 2;
@@ -1345,6 +1502,14 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
             l.steps = 1;
             cand.push_back(l);
         }
+    // several vectors on a one-sample chain lattice: one vector per wavefront
+    // (vector-major states) in marching strips, the grid per plane from
+    // groups_per_cu or a few groups per plane (longer strips)
+    if (sys->d_flags && vs > 0 && sys->nseg == 1) {
+        for (int ksteps : {4, 6, 8})
+            for (int pg : {0, 16, 32, 64, 128})
+                cand.push_back(kpm_launch{2, 1, 0, 1, 5, ksteps, 1, pg});
+    }
     if (sys->d_code && vs == 0) {
         for (int g : {2, 3, 4, 6})
             for (int nt : {0, 1}) cand.push_back(kpm_launch{g, 1, nt, 1, 0, 2});
@@ -1363,14 +1528,18 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
     // Each form (direct, doubling) keeps its current shape as the incumbent; a
     // candidate replaces it only when more than 2 % faster, so near-ties keep
     // a stable choice.
+    // The direct form's pick fixes the layout of the states (vectors per
+    // wavefront), so the doubling form then only considers shapes of that layout.
     kpm_launch pick = sys->launch[vs], pick_dbl = sys->launch_dbl[vs];
     for (int form = 0; form < 2 && st == KPM_OK; ++form) {
         const bool dbl = form == 1;
         kpm_launch &p = dbl ? pick_dbl : pick;
+        if (dbl && p.vectors_per_wave != pick.vectors_per_wave) p = pick;
         float best_ms = 1e30f;
         st = time_shape(p, dbl, &best_ms);
         for (const kpm_launch &l : cand) {
             if (st != KPM_OK) break;
+            if (dbl && l.vectors_per_wave != pick.vectors_per_wave) continue;
             float ms = 0;
             if ((st = time_shape(l, dbl, &ms)) != KPM_OK) break;
             if (ms < 0.98f * best_ms) {
@@ -1560,6 +1729,17 @@ kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int devi
         for (int s = 0; s < nseg; ++s) al[s] = make_double2(0.0, -sys->es[s] / kHbar);
         st = upload((void **)&sys->d_alpha, al.data(), al.size() * sizeof(double2));
     }
+    // several vectors on a one-sample graphene lattice: one vector per
+    // wavefront in eight-step strips by default (measured fastest on the
+    // paper-scale sheet with 64 vectors, in FP64 and with FP32 states), with
+    // about 1024 work-groups over all planes; not when a KPM_* launch
+    // override is set
+    if (st == KPM_OK && nseg == 1 && sys->d_flags && !launch_env_set()) {
+        for (int v = 1; v < 7; ++v) {
+            const kpm_launch l{2, 1, 0, 1, 5, 8, 1, std::max(16, 1024 >> v)};
+            sys->launch[v] = sys->launch_dbl[v] = l;
+        }
+    }
     if (st == KPM_OK) {
         const hipError_t e = kpm::static_scratch(device, &sys->static_scratch);
         if (e != hipSuccess)
@@ -1744,10 +1924,10 @@ kpm_status kpm_vac_continue(kpm_system *sys, int n_vec, void *psi, void *r, int 
     KPM_TRY(check_continue(sys, n_vec, psi, r, start, n_steps, dt_fs, n_bessel, n_moments, out, &vs));
     DeviceGuard g(sys->device);
     return sys->prec == KPM_FP64
-               ? vac_run<double2>(sys, vs, (double2 *)psi, (double2 *)r, start != 0, n_steps, dt_fs,
-                                  n_bessel, n_moments, out)
-               : vac_run<float2>(sys, vs, (float2 *)psi, (float2 *)r, start != 0, n_steps, dt_fs,
-                                 n_bessel, n_moments, out);
+               ? continue_impl<double2>(sys, vs, psi, r, start != 0, n_steps, dt_fs, n_bessel,
+                                        n_moments, 0, out)
+               : continue_impl<float2>(sys, vs, psi, r, start != 0, n_steps, dt_fs, n_bessel,
+                                       n_moments, 0, out);
 }
 
 kpm_status kpm_msd_continue(kpm_system *sys, int n_vec, void *psi, void *y, int start,
@@ -1758,10 +1938,10 @@ kpm_status kpm_msd_continue(kpm_system *sys, int n_vec, void *psi, void *y, int 
     if (doubled != 0 && doubled != 1) return fail(KPM_ERR_INVALID, "doubled must be 0 or 1");
     DeviceGuard g(sys->device);
     return sys->prec == KPM_FP64
-               ? msd_run<double2>(sys, vs, (double2 *)psi, (double2 *)y, start != 0, n_steps, dt_fs,
-                                  n_bessel, n_moments, doubled != 0, out)
-               : msd_run<float2>(sys, vs, (float2 *)psi, (float2 *)y, start != 0, n_steps, dt_fs,
-                                 n_bessel, n_moments, doubled != 0, out);
+               ? continue_impl<double2>(sys, vs, psi, y, start != 0, n_steps, dt_fs, n_bessel,
+                                        n_moments, doubled ? 2 : 1, out)
+               : continue_impl<float2>(sys, vs, psi, y, start != 0, n_steps, dt_fs, n_bessel,
+                                       n_moments, doubled ? 2 : 1, out);
 }
 
 kpm_status kpm_xu_state(kpm_system *sys, int n_vec, const void *phi, int n_steps, double dt_fs,

@@ -73,6 +73,12 @@ struct Sweep {
     const Seg *seg;       // [nseg] device table, or nullptr for one segment
     const int32_t *wg_seg;// [nwg] device table: segment of each group (with seg)
     Seg one;              // the segment when seg is nullptr
+    // Vector-major states: nplanes planes of pstride elements, one vector
+    // each (then vshift = 0 and total = rows); the grid's second dimension
+    // is the plane, and group partials are [slot][nwg][nplanes].  nplanes = 1
+    // and pstride = 0 for states with every vector of a row side by side.
+    int64_t pstride;
+    int nplanes;
 };
 
 // Chain-lattice geometry of a one-sample system for the multi-step moment
@@ -198,6 +204,12 @@ void launch_evolve_x_step(const Ell &h, const Sweep &sw, bool first, const V *p1
 template <typename V>
 void launch_apply_d(const Ell &h, const Sweep &sw, const V *x, V *y, Coef alpha,
                     hipStream_t s);
+
+// State of R = 2^vshift >= 2 vectors from rows-major [n][R] (vectors of a
+// row side by side, the caller's layout) to vector-major [R][n] (to_planar)
+// or back; src and dst must not overlap.
+template <typename V>
+void launch_planar(const V *src, V *dst, int64_t n, int vshift, bool to_planar, hipStream_t s);
 
 // partial[slot] = <a|b> per work-group and vector.
 template <typename V>

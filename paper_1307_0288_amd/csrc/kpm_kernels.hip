@@ -241,6 +241,20 @@ __device__ __forceinline__ void block_sum(double2 s, int vshift, double2 *dst) {
     }
 }
 
+// Vector-major states: the element offset of this group's plane, a state
+// pointer moved to it (null stays null), and the index of the group's
+// partial of `slot` in [slot][nwg][planes] (times the vectors per row).
+__device__ __forceinline__ int64_t plane_off(const Sweep &sw) {
+    return (int64_t)blockIdx.y * sw.pstride;
+}
+template <typename T>
+__device__ __forceinline__ T *on_plane(T *p, int64_t off) {
+    return p ? p + off : p;
+}
+__device__ __forceinline__ int64_t part_index(const Sweep &sw, int slot) {
+    return ((int64_t)slot * sw.nwg + blockIdx.x) * gridDim.y + blockIdx.y;
+}
+
 __device__ __forceinline__ Walk walk_of(const Sweep &sw) {
     Walk w;
     Seg s;
@@ -300,6 +314,10 @@ __global__ __launch_bounds__(kBlock) void k_moment_first(Ell h, Sweep sw, const 
                                                          const V *__restrict__ phil,
                                                          double2 *__restrict__ partial,
                                                          int slot) {
+    const int64_t po = plane_off(sw);
+    in = on_plane(in, po);
+    out = on_plane(out, po);
+    phil = on_plane(phil, po);
     double2 s0 = make_double2(0.0, 0.0), s1 = make_double2(0.0, 0.0);
     KPM_SWEEP_BEGIN(sw, h)
     const double2 xi = ld(in + e);
@@ -310,8 +328,8 @@ __global__ __launch_bounds__(kBlock) void k_moment_first(Ell h, Sweep sw, const 
     s1 = cdot_acc(s1, l, o);
     KPM_SWEEP_END
     const int64_t r = (int64_t)1 << sw.vshift;
-    block_sum(s0, sw.vshift, partial + ((int64_t)slot * sw.nwg + blockIdx.x) * r);
-    block_sum(s1, sw.vshift, partial + ((int64_t)(slot + 1) * sw.nwg + blockIdx.x) * r);
+    block_sum(s0, sw.vshift, partial + part_index(sw, slot) * r);
+    block_sum(s1, sw.vshift, partial + part_index(sw, slot + 1) * r);
 }
 
 // Structure forms of the moment step.  kFormGeneric reads everything the
@@ -431,6 +449,11 @@ __global__ __launch_bounds__(kBlock) void k_moment_step(Ell h, Sweep sw, const V
                                                         double2 *__restrict__ partial,
                                                         int slot) {
     using F = FormTraits<FORM>;
+    const int64_t po = plane_off(sw);
+    p1 = on_plane(p1, po);
+    p0 = on_plane(p0, po);
+    out = on_plane(out, po);
+    phil = on_plane(phil, po);
     double2 s0 = make_double2(0.0, 0.0), s1 = make_double2(0.0, 0.0);
     __shared__ int32_t lpat[kMaxPatterns * kMaxWidth];
     if (F::compact || (F::generic && h.pid)) {
@@ -521,9 +544,8 @@ __global__ __launch_bounds__(kBlock) void k_moment_step(Ell h, Sweep sw, const V
         }
     }
     const int64_t r = (int64_t)1 << sw.vshift;
-    block_sum(s0, sw.vshift, partial + ((int64_t)slot * sw.nwg + blockIdx.x) * r);
-    if constexpr (DBL)
-        block_sum(s1, sw.vshift, partial + ((int64_t)(slot + 1) * sw.nwg + blockIdx.x) * r);
+    block_sum(s0, sw.vshift, partial + part_index(sw, slot) * r);
+    if constexpr (DBL) block_sum(s1, sw.vshift, partial + part_index(sw, slot + 1) * r);
 }
 
 // Moments from the doubling sums, in place: row t of mom holds
@@ -560,6 +582,12 @@ template <typename V, bool FIRST, int FORM, bool NT>
 __global__ __launch_bounds__(kBlock) void k_evolve_step(Ell h, Sweep sw, const V *p1,
                                                         const V *p0, V *out, V *acc,
                                                         const V *add, Coef c0, Coef c) {
+    const int64_t po = plane_off(sw);
+    p1 = on_plane(p1, po);
+    p0 = on_plane(p0, po);
+    out = on_plane(out, po);
+    acc = on_plane(acc, po);
+    add = on_plane(add, po);
     KPM_SWEEP_BEGIN(sw, h)
     const double2 cm = coef(c, sg);
     const double2 xi = ld(p1 + e);
@@ -584,6 +612,15 @@ __global__ __launch_bounds__(kBlock) void k_evolve_x_step(Ell h, Sweep sw, const
                                                           const V *q1, const V *q0,
                                                           V *qout, V *accx, V *accu,
                                                           Coef c0, Coef c) {
+    const int64_t po = plane_off(sw);
+    p1 = on_plane(p1, po);
+    p0 = on_plane(p0, po);
+    pout = on_plane(pout, po);
+    q1 = on_plane(q1, po);
+    q0 = on_plane(q0, po);
+    qout = on_plane(qout, po);
+    accx = on_plane(accx, po);
+    accu = on_plane(accu, po);
     KPM_SWEEP_BEGIN(sw, h)
     const double2 cm = coef(c, sg);
     const double2 xi = ld(p1 + e);
@@ -614,6 +651,9 @@ __global__ __launch_bounds__(kBlock) void k_evolve_x_step(Ell h, Sweep sw, const
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_apply_d(Ell h, Sweep sw, const V *x, V *y,
                                                     Coef alpha) {
+    const int64_t po = plane_off(sw);
+    x = on_plane(x, po);
+    y = on_plane(y, po);
     KPM_SWEEP_BEGIN(sw, h)
     st(y + e, cmul(coef(alpha, sg), row_d(h, lpat, x, i, v, sw.vshift)));
     KPM_SWEEP_END
@@ -624,6 +664,9 @@ template <typename V>
 __global__ __launch_bounds__(kBlock) void k_dot(Sweep sw, const V *__restrict__ a,
                                                 const V *__restrict__ b,
                                                 double2 *__restrict__ partial, int slot) {
+    const int64_t po = plane_off(sw);
+    a = on_plane(a, po);
+    b = on_plane(b, po);
     double2 s0 = make_double2(0.0, 0.0);
     const Walk wk = walk_of(sw);
     for (int64_t blk = wk.b0 + wk.loc; blk < wk.b1; blk += wk.nloc) {
@@ -632,7 +675,43 @@ __global__ __launch_bounds__(kBlock) void k_dot(Sweep sw, const V *__restrict__ 
             s0 = cdot_acc(s0, ld_nt(a + e), ld_nt(b + e));
     }
     const int64_t r = (int64_t)1 << sw.vshift;
-    block_sum(s0, sw.vshift, partial + ((int64_t)slot * sw.nwg + blockIdx.x) * r);
+    block_sum(s0, sw.vshift, partial + part_index(sw, slot) * r);
+}
+
+// Layout conversion of a state with R = 2^vshift vectors: rows-major [n][R]
+// (to_planar: source) and vector-major [R][n].  A group moves a tile of
+// kPlanarTile / R rows through LDS, so both sides are read and written in
+// contiguous runs; the tile is padded by one element per 32 against bank
+// conflicts.  Values are copied bit for bit.
+constexpr int kPlanarTile = 2048;
+__device__ __forceinline__ int planar_pad(int q) { return q + (q >> 5); }
+
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_planar(const V *__restrict__ src, V *__restrict__ dst,
+                                                   int64_t n, int vshift, int to_planar) {
+    __shared__ V tile[kPlanarTile + kPlanarTile / 32];
+    const int r = 1 << vshift;
+    const int tr = kPlanarTile >> vshift;                 // rows per tile
+    const int64_t row0 = (int64_t)blockIdx.x * tr;
+    const int rows = (int)min((int64_t)tr, n - row0);
+    const int cnt = rows << vshift;
+    if (to_planar) {
+        for (int q = threadIdx.x; q < cnt; q += kBlock)
+            tile[planar_pad((q & (r - 1)) * tr + (q >> vshift))] = src[(row0 << vshift) + q];
+        __syncthreads();
+        for (int q = threadIdx.x; q < cnt; q += kBlock) {
+            const int v = q / rows, i = q - v * rows;
+            dst[(int64_t)v * n + row0 + i] = tile[planar_pad(v * tr + i)];
+        }
+    } else {
+        for (int q = threadIdx.x; q < cnt; q += kBlock) {
+            const int v = q / rows, i = q - v * rows;
+            tile[planar_pad(v * tr + i)] = src[(int64_t)v * n + row0 + i];
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < cnt; q += kBlock)
+            dst[(row0 << vshift) + q] = tile[planar_pad((q & (r - 1)) * tr + (q >> vshift))];
+    }
 }
 
 // One thread per (row, energy): Hanning-windowed Fourier sum (Eq. 22-24),
@@ -1141,6 +1220,12 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
                                             const CoefK &ck) {
     constexpr bool DBL = MODE == kMarchDoubled, BES = MODE == kMarchBessel,
                    RE = MODE == kMarchDirectRe;
+    const int64_t po = plane_off(sw);
+    p1 = on_plane(p1, po);
+    p0 = on_plane(p0, po);
+    out1 = on_plane(out1, po);
+    out2 = on_plane(out2, po);
+    lacc = on_plane(lacc, po);
     constexpr int TC = kWave - 2 * K;                  // columns per strip
     constexpr int P = kRowRing, PS = kStateRing, DS = kDs, DR = kRowRing - 1 - K;
     // phi_L rows are loaded DL ahead and used through K iterations after their
@@ -1331,7 +1416,8 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
     if (BES) return;
     const int nw = sw.nwg;
 #pragma unroll
-    for (int k = 0; k < NA; ++k) block_sum(acc[k], 0, partial + (int64_t)(slot + k) * nw + blockIdx.x);
+    for (int k = 0; k < NA; ++k) block_sum(acc[k], 0, partial + part_index(sw, slot + k));
+    (void)nw;
 }
 
 template <typename V, bool ONSF, bool DBL, int K>
@@ -1378,7 +1464,7 @@ static void launch_step_shape(const Ell &h, const Sweep &sw, const V *p1, const 
     switch (form_of(h)) {
 #define KPM_FORM_CASE(F)                                                                       \
         case F:                                                                                \
-            hipLaunchKernelGGL((k_moment_step<V, ILP, NT, F, DBL>), dim3(sw.nwg), dim3(kBlock), \
+            hipLaunchKernelGGL((k_moment_step<V, ILP, NT, F, DBL>), dim3(sw.nwg, sw.nplanes), dim3(kBlock), \
                                0, s, h, sw, p1, p0, out, phil, partial, slot);                 \
             break;
         KPM_FORM_CASE(kFormC3F)
@@ -1411,7 +1497,7 @@ void launch_moment_step(const Ell &h, const Sweep &sw, bool first, const V *p1,
                         const V *p0, V *out, const V *phil, double2 *partial, int slot,
                         hipStream_t s) {
     if (first) {
-        hipLaunchKernelGGL((k_moment_first<V>), dim3(sw.nwg), dim3(kBlock), 0, s, h, sw, p1,
+        hipLaunchKernelGGL((k_moment_first<V>), dim3(sw.nwg, sw.nplanes), dim3(kBlock), 0, s, h, sw, p1,
                            out, phil, partial, slot);
         return;
     }
@@ -1447,7 +1533,7 @@ void launch_evolve_step(const Ell &h, const Sweep &sw, bool first, const V *p1, 
                         V *out, V *acc, const V *add, Coef c0, Coef c, hipStream_t s) {
 #define KPM_EVOLVE(FIRST_, NT_)                                                               \
     KPM_BY_FORM(form_of(h),                                                                   \
-                hipLaunchKernelGGL((k_evolve_step<V, FIRST_, F, NT_>), dim3(sw.nwg),          \
+                hipLaunchKernelGGL((k_evolve_step<V, FIRST_, F, NT_>), dim3(sw.nwg, sw.nplanes),          \
                                    dim3(kBlock), 0, s, h, sw, p1, p0, out, acc, add, c0, c))
     if (first && sw.nt) { KPM_EVOLVE(true, true) }
     else if (first) { KPM_EVOLVE(true, false) }
@@ -1462,7 +1548,7 @@ void launch_evolve_x_step(const Ell &h, const Sweep &sw, bool first, const V *p1
                           V *accx, V *accu, Coef c0, Coef c, hipStream_t s) {
 #define KPM_EVOLVE_X(FIRST_, NT_)                                                             \
     KPM_BY_FORM(form_of(h),                                                                   \
-                hipLaunchKernelGGL((k_evolve_x_step<V, FIRST_, F, NT_>), dim3(sw.nwg),        \
+                hipLaunchKernelGGL((k_evolve_x_step<V, FIRST_, F, NT_>), dim3(sw.nwg, sw.nplanes),        \
                                    dim3(kBlock), 0, s, h, sw, p1, p0, pout, q1, q0, qout,     \
                                    accx, accu, c0, c))
     // always non-temporal: with ten state streams per step, caching them evicts
@@ -1475,7 +1561,7 @@ void launch_evolve_x_step(const Ell &h, const Sweep &sw, bool first, const V *p1
 template <typename V>
 void launch_apply_d(const Ell &h, const Sweep &sw, const V *x, V *y, Coef alpha,
                     hipStream_t s) {
-    hipLaunchKernelGGL((k_apply_d<V>), dim3(sw.nwg), dim3(kBlock), 0, s, h, sw, x, y, alpha);
+    hipLaunchKernelGGL((k_apply_d<V>), dim3(sw.nwg, sw.nplanes), dim3(kBlock), 0, s, h, sw, x, y, alpha);
 }
 
 void launch_reduce(const double2 *partial, const Sweep &sw, int slots, double2 *dst,
@@ -1487,7 +1573,16 @@ void launch_reduce(const double2 *partial, const Sweep &sw, int slots, double2 *
 template <typename V>
 void launch_dot(const Sweep &sw, const V *a, const V *b, double2 *partial, int slot,
                 hipStream_t s) {
-    hipLaunchKernelGGL((k_dot<V>), dim3(sw.nwg), dim3(kBlock), 0, s, sw, a, b, partial, slot);
+    hipLaunchKernelGGL((k_dot<V>), dim3(sw.nwg, sw.nplanes), dim3(kBlock), 0, s, sw, a, b, partial, slot);
+}
+
+template <typename V>
+void launch_planar(const V *src, V *dst, int64_t n, int vshift, bool to_planar, hipStream_t s) {
+    const int64_t tr = kPlanarTile >> vshift;
+    const int64_t blocks = (n + tr - 1) / tr;
+    if (blocks <= 0) return;
+    hipLaunchKernelGGL((k_planar<V>), dim3((unsigned)blocks), dim3(kBlock), 0, s, src, dst, n,
+                       vshift, to_planar ? 1 : 0);
 }
 
 void launch_ftm_sum(const double2 *f, int rows, int nm, const double *w, const double *theta,
@@ -1515,6 +1610,8 @@ bool launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
     // 2 .. 4, marching strips 2 .. 8
     if (lat.k < 2 || lat.k > (lat.reg == 2 ? kMaxMarchSteps : (lat.reg == 1 ? 4 : 2)))
         return false;
+    // vector-major states run only in the marching strips
+    if (sw.nplanes > 1 && lat.reg != 2) return false;
 #define KPM_LDS2(NT_, ONSF_, DBL_)                                                            \
     hipLaunchKernelGGL((k_moment_step2<V, NT_, ONSF_, DBL_, 16>), dim3(sw.nwg), dim3(kBlock),  \
                        0, s, h, sw, lat, p1, p0, out1, out2, phil, partial, slot)
@@ -1530,10 +1627,10 @@ bool launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
 #define KPM_MARCHK(ONSF_, DBL_, K_)                                                          \
     do {                                                                                      \
         if (!(DBL_) && re)                                                                    \
-            hipLaunchKernelGGL((k_moment_march_re<V, ONSF_, K_>), dim3(sw.nwg), dim3(kBlock),  \
+            hipLaunchKernelGGL((k_moment_march_re<V, ONSF_, K_>), dim3(sw.nwg, sw.nplanes), dim3(kBlock),  \
                                0, s, h, sw, lat, p1, p0, out1, out2, phil, partial, slot);    \
         else                                                                                  \
-            hipLaunchKernelGGL((k_moment_march<V, ONSF_, DBL_, K_>), dim3(sw.nwg),            \
+            hipLaunchKernelGGL((k_moment_march<V, ONSF_, DBL_, K_>), dim3(sw.nwg, sw.nplanes),            \
                                dim3(kBlock), 0, s, h, sw, lat, p1, p0, out1, out2, phil,      \
                                partial, slot);                                                \
     } while (0)
@@ -1577,7 +1674,7 @@ bool launch_evolve_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
                          hipStream_t s) {
     if (lat.reg != 2 || lat.k < 2 || lat.k > kMaxMarchSteps) return false;
 #define KPM_EVK(ONSF_, K_)                                                                    \
-    hipLaunchKernelGGL((k_evolve_march<V, ONSF_, K_>), dim3(sw.nwg), dim3(kBlock), 0, s, h,   \
+    hipLaunchKernelGGL((k_evolve_march<V, ONSF_, K_>), dim3(sw.nwg, sw.nplanes), dim3(kBlock), 0, s, h,   \
                        sw, lat, p1, p0, out1, out2, acc, ck)
 #define KPM_EV(ONSF_)                                                                         \
     switch (lat.k) {                                                                          \
@@ -1613,6 +1710,7 @@ bool launch_evolve_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
                                     hipStream_t);                                           \
     template void launch_dot<V>(const Sweep &, const V *, const V *, double2 *, int,        \
                                 hipStream_t);                                               \
+    template void launch_planar<V>(const V *, V *, int64_t, int, bool, hipStream_t);        \
     template bool launch_moment_multi<V>(const Ell &, const Sweep &, const Lat2 &, const V *, \
                                          const V *, V *, V *, const V *, double2 *, int,    \
                                          bool, bool, hipStream_t);                          \
@@ -1645,6 +1743,17 @@ __global__ __launch_bounds__(kBlock, 2) void k_evolve_x_march(
     static_assert(K >= 2 && K <= 3, "coupled steps per pass");
     static_assert(DR >= 1 && DS + 3 <= PS && P % PS == 0 && PS % 3 == 0 && DL + K < P,
                   "ring sizes");
+    const int64_t po = plane_off(sw);
+    p1 = on_plane(p1, po);
+    p0 = on_plane(p0, po);
+    pout1 = on_plane(pout1, po);
+    pout2 = on_plane(pout2, po);
+    q1 = on_plane(q1, po);
+    q0 = on_plane(q0, po);
+    qout1 = on_plane(qout1, po);
+    qout2 = on_plane(qout2, po);
+    accx = on_plane(accx, po);
+    accu = on_plane(accu, po);
     const double t = sw.one.t, inv_es = sw.one.inv_es;
     // per pattern: hopping (previous column, next column), (next chain, previous
     // chain), then commutator weights in the same order
@@ -1811,8 +1920,9 @@ bool launch_evolve_x_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const
                            hipStream_t s) {
     if (lat.reg != 2 || lat.k < 2 || lat.k > 3) return false;
 #define KPM_EXK(ONSF_, K_)                                                                    \
-    hipLaunchKernelGGL((k_evolve_x_march<V, ONSF_, K_>), dim3(sw.nwg), dim3(kBlock), 0, s, h, \
-                       sw, lat, pxw, p1, p0, pout1, pout2, q1, q0, qout1, qout2, accx, accu, ck)
+    hipLaunchKernelGGL((k_evolve_x_march<V, ONSF_, K_>), dim3(sw.nwg, sw.nplanes),            \
+                       dim3(kBlock), 0, s, h, sw, lat, pxw, p1, p0, pout1, pout2, q1, q0,     \
+                       qout1, qout2, accx, accu, ck)
 #define KPM_EX(ONSF_)                                                                         \
     switch (lat.k) {                                                                          \
         case 3: KPM_EXK(ONSF_, 3); break;                                                     \

@@ -60,11 +60,16 @@ class _Desc(C.Structure):
 
 class Launch(C.Structure):
     _fields_ = [("groups_per_cu", C.c_int32), ("ilp", C.c_int32), ("streaming", C.c_int32),
-                ("compact", C.c_int32), ("tiled", C.c_int32), ("steps", C.c_int32)]
+                ("compact", C.c_int32), ("tiled", C.c_int32), ("steps", C.c_int32),
+                ("vectors_per_wave", C.c_int32), ("plane_groups", C.c_int32)]
 
     def as_dict(self) -> dict:
-        return dict(groups_per_cu=self.groups_per_cu, ilp=self.ilp, streaming=self.streaming,
-                    compact=self.compact, tiled=self.tiled, steps=self.steps)
+        """The shape's fields; the two vector-layout fields only when set."""
+        d = dict(groups_per_cu=self.groups_per_cu, ilp=self.ilp, streaming=self.streaming,
+                 compact=self.compact, tiled=self.tiled, steps=self.steps)
+        if self.vectors_per_wave or self.plane_groups:
+            d.update(vectors_per_wave=self.vectors_per_wave, plane_groups=self.plane_groups)
+        return d
 
 
 class Adam(C.Structure):
@@ -595,11 +600,13 @@ def kpm_msd_continue(sys: System, psi, y, start: bool, n_steps: int, dt_fs: floa
 
 
 def kpm_set_launch(sys: System, n_vec: int, groups_per_cu: int, ilp: int, streaming: int = 0,
-                   compact: int = 1, tiled: int = 0, steps: int = 1):
+                   compact: int = 1, tiled: int = 0, steps: int = 1, vectors_per_wave: int = 0,
+                   plane_groups: int = 0):
     """Launch shape of the moment step for n_vec vectors (see kpm_launch in kpm.h)."""
     _check(lib().kpm_set_launch(sys.handle, n_vec,
                                 C.byref(Launch(groups_per_cu, ilp, int(bool(streaming)),
-                                               int(bool(compact)), int(tiled), int(steps)))))
+                                               int(bool(compact)), int(tiled), int(steps),
+                                               int(vectors_per_wave), int(plane_groups)))))
 
 
 def kpm_default_launch(n_vec: int, precision: str = "fp64") -> dict:
@@ -618,12 +625,14 @@ def kpm_get_launch(sys: System, n_vec: int) -> dict:
 
 
 def kpm_set_launch_doubled(sys: System, n_vec: int, groups_per_cu: int, ilp: int,
-                           streaming: int = 0, compact: int = 1, tiled: int = 0, steps: int = 1):
+                           streaming: int = 0, compact: int = 1, tiled: int = 0, steps: int = 1,
+                           vectors_per_wave: int = 0, plane_groups: int = 0):
     """Launch shape of doubling-form moment sets (kpm_set_launch sets both forms)."""
     _check(lib().kpm_set_launch_doubled(sys.handle, n_vec,
                                         C.byref(Launch(groups_per_cu, ilp, int(bool(streaming)),
                                                        int(bool(compact)), int(tiled),
-                                                       int(steps)))))
+                                                       int(steps), int(vectors_per_wave),
+                                                       int(plane_groups)))))
 
 
 def kpm_get_launch_doubled(sys: System, n_vec: int) -> dict:
