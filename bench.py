@@ -682,13 +682,51 @@ def ftm(args):
     print(json.dumps(out), flush=True)
 
 
-def batched(args):
-    """64 random vectors per Chebyshev step on the paper-scale sheet: FP32 states
-    (FP64 arithmetic, inner products and moments) against FP64 states.
+def _golden_vector0(ons, act, phi0):
+    """The oracle's stored moments of the paper-scale sheet's vector of seed
+    3000 (tests/golden/paper_sheet_oracle.npz, written by a script that calls
+    only the oracle), when they belong to these inputs; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "tests", "golden", "paper_sheet_oracle.npz")
+    if not os.path.exists(path):
+        return None
+    z = np.load(path, allow_pickle=False)
+    meta = json.loads(bytes(z["meta"]).decode())
+    h = hashlib.sha256()
+    for a in (ons, act, phi0):
+        h.update(np.ascontiguousarray(a).tobytes())
+    if meta.get("input_sha256") != h.hexdigest():
+        return None
+    return dict(dos=z["dos_re"], vac=z["vac"], msd=z["msd"])
 
-    Timed: 3000 moments for all 64 vectors (one sparse-matrix x 64-vector product
-    per step).  Error: sigma_GK (from the VAC) and sigma_E1 (from the MSD) at 2048
-    energies and t = dt, 2 dt, averaged over the 64 vectors, FP32 vs FP64.
+
+def _spectra(kp, dos, vac, msd, en, es, area, dt):
+    """DOS (Eq. 29) and sigma_GK / sigma_E1 / sigma_E2 (Eq. 6, 9, 11) at the
+    energies en and every time point, from moments [3000], [21][3000] x 2,
+    through the library's sums."""
+    rho_v = kp.kpm_kpm_sum(vac, en, es, area)
+    rho_m = kp.kpm_kpm_sum(msd, en, es, area)
+    return dict(dos=kp.kpm_kpm_sum(dos[None, :], en, es, area),
+                gk=kp.kpm_sigma_gk(rho_v, dt), e1=kp.kpm_sigma_e1(rho_m, dt),
+                e2=kp.kpm_sigma_e2(rho_m, dt))
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def batched(args):
+    """64 random-phase vectors on the paper-scale sheet, the whole hot path per
+    step (DOS moments, VAC and MSD over 20 time steps, 3000 moments each), with
+    FP32 states (FP64 arithmetic, inner products and moments) and with FP64
+    states, next to plain FP64 with one vector on the same GPU.
+
+    sigma(E) error per result, max over the 2048 energies and 21 times of
+    |d sigma| / max |sigma_ref|: the DOS (Eq. 29), sigma_GK (Eq. 6), sigma_E1
+    (Eq. 9) and sigma_E2 (Eq. 11) of the FP32 run against the FP64 run (both
+    averaged over the 64 vectors), and of vector 0 of each run (seed 3000)
+    against the oracle's stored moments of that vector, all through the same
+    sums (Eq. 29-31, Jackson kernel).
     """
     import torch
     import paper_1307_0288_amd as kp
@@ -699,66 +737,98 @@ def batched(args):
     act = ki.vacancy_mask(n, p["vac"], 2000)
     ons = ki.anderson_onsite(n, p["w"], 1000)
     phi_h = ki.random_phase(n, r, 3000, act)
-    nm, nb, dt = p["n_moments"], p["n_bessel"], p["dt_fs"]
-    res = {}
-    sig = {}
-    en = np.linspace(-0.95 * p["e_scale"], 0.95 * p["e_scale"], 2048)
+    nm, ns, nb, dt, es = p["n_moments"], p["n_steps"], p["n_bessel"], p["dt_fs"], p["e_scale"]
+    gold = _golden_vector0(ons, act, phi_h[:, 0])
+    en = np.linspace(-0.95 * es, 0.95 * es, 2048)
+    steps = max(1, args.steps)
+    res, spec, spec0 = {}, {}, {}
     for prec in ("fp64", "fp32"):
-        sysg = kp.graphene_system(p["nx"], p["ny"], "sheet", p["t"], ons, act, p["e_scale"], prec)
+        sysg = kp.graphene_system(p["nx"], p["ny"], "sheet", p["t"], ons, act, es, prec)
+        area = sysg.area_nm2
         phi = sysg.upload(phi_h)
-        res_launch = kp.kpm_autotune(sysg, phi, 5)
-        log(f"{prec} autotuned launch shape: {res_launch}")
+        launch = kp.kpm_autotune(sysg, phi, 8)
+        log(f"{prec} autotuned launch shape: {launch}")
         kp.kpm_moments(sysg, phi, phi, 64)                      # warm-up
+        kp.kpm_vac(sysg, phi, 1, dt, nb, 64)
         kp.kpm_reset_stats(sysg)
         kp.kpm_set_timing(sysg, True)
         torch.cuda.synchronize()
-        times = []
-        for k in range(max(args.steps, 1)):
-            t0 = time.perf_counter()
-            kp.kpm_moments(sysg, phi, phi, nm)
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - t0)
-            log(f"{prec} moments run {k + 1}: {times[-1]:.3f} s")
+        t0 = time.perf_counter()
+        for k in range(steps):
+            dos = kp.kpm_moments(sysg, phi, phi, nm)
+            vac = kp.kpm_vac(sysg, phi, ns, dt, nb, nm)
+            msd = kp.kpm_msd(sysg, phi, ns, dt, nb, nm)
+            log(f"{prec} step {k + 1}/{steps} done")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
         st = kp.kpm_get_stats(sysg)
         kp.kpm_set_timing(sysg, False)
-        ups = (nm - 1) * n * r
         launch_ms = st["step_ms"] / max(st["step_launches"], 1)
-        res[prec] = dict(seconds=min(times), gsu=ups / min(times) / 1e9,
-                         launch_us=launch_ms * 1e3, launch=res_launch,
-                         bpu=st["step_bytes"] / st["step_rows"])
-        log(f"{prec} sigma runs (VAC + MSD, 2 steps)")
-        vac = kp.kpm_vac(sysg, phi, 2, dt, nb, nm).mean(axis=0)
-        msd = kp.kpm_msd(sysg, phi, 2, dt, nb, nm).mean(axis=0)
-        rho_v = kp.kpm_kpm_sum(vac, en, p["e_scale"], sysg.area_nm2)
-        rho_m = kp.kpm_kpm_sum(msd, en, p["e_scale"], sysg.area_nm2)
-        sig[prec] = (kp.kpm_sigma_gk(rho_v, dt), kp.kpm_sigma_e1(rho_m, dt))
+        res[prec] = dict(gsu=st["site_updates"] / elapsed / 1e9, ms=elapsed / steps * 1e3,
+                         launch=launch, launch_us=launch_ms * 1e3,
+                         bytes_launch=st["step_bytes"], rows=st["step_rows"],
+                         site_updates=st["site_updates"] // steps)
+        log(f"{prec}: {res[prec]['gsu']:.1f} Gsite-updates/s")
+        spec[prec] = _spectra(kp, dos.real.mean(axis=0), vac.mean(axis=0), msd.mean(axis=0),
+                              en, es, area, dt)
+        spec0[prec] = _spectra(kp, dos[0].real, vac[0], msd[0], en, es, area, dt)
         sysg.close()
         del phi
         torch.cuda.empty_cache()
-    err_gk = float(np.max(np.abs(sig["fp32"][0] - sig["fp64"][0])) / np.max(np.abs(sig["fp64"][0])))
-    err_e1 = float(np.max(np.abs(sig["fp32"][1] - sig["fp64"][1])) / np.max(np.abs(sig["fp64"][1])))
-    bpu = {k: v["bpu"] for k, v in res.items()}
+    # plain FP64, one vector, on the same GPU (the default workload's step)
+    sysg = kp.graphene_system(p["nx"], p["ny"], "sheet", p["t"], ons, act, es, "fp64")
+    phi1 = sysg.upload(phi_h[:, :1])
+    kp.kpm_autotune(sysg, phi1, 50)
+    kp.kpm_moments(sysg, phi1, phi1, 64)
+    kp.kpm_reset_stats(sysg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kp.kpm_moments(sysg, phi1, phi1, nm)
+    kp.kpm_vac(sysg, phi1, ns, dt, nb, nm)
+    kp.kpm_msd(sysg, phi1, ns, dt, nb, nm)
+    torch.cuda.synchronize()
+    plain = kp.kpm_get_stats(sysg)["site_updates"] / (time.perf_counter() - t0) / 1e9
+    sysg.close()
+    log(f"plain fp64, one vector: {plain:.1f} Gsite-updates/s")
+
+    err32 = {k: _rel(spec["fp32"][k], spec["fp64"][k]) for k in spec["fp64"]}
+    err_or = None
+    if gold is not None:
+        ref = _spectra(kp, gold["dos"], gold["vac"], gold["msd"], en, es, area, dt)
+        err_or = {prec: {k: _rel(spec0[prec][k], ref[k]) for k in ref} for prec in spec0}
+    worst = max(list(err32.values()) + ([] if err_or is None else list(err_or["fp32"].values())))
+    f32 = res["fp32"]
+    kname = moment_kernel_name("float2", f32["launch"], False, real=True, onsf=False,
+                               n_vec=r)
+    achieved = f32["bytes_launch"] / (f32["launch_us"] * 1e-6) / 1e9
     out = {
-        "metric": "Gsite-updates/s (batched Chebyshev moments, 64 vectors, FP32 states)",
-        "value": round(res["fp32"]["gsu"], 3), "unit": "Gsite-updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": 1, "ms_per_step": round(res["fp32"]["seconds"] * 1e3, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32-states/f64-dots",
-        "data": "synthetic",
-        "config": {"workload": "graphene sheet 2828x1414 sites, 0.5% vacancies, W=0.1 eV, 64 "
-                               "random-phase vectors per step, 3000 moments", "n_sites": n,
-                   "n_vec": r},
+        "metric": "Gsite-updates/s (batched Chebyshev hot path: DOS + VAC + MSD, 64 vectors, "
+                  "FP32 states)",
+        "value": round(f32["gsu"], 3), "unit": "Gsite-updates/s", "n_gpus": 1,
+        "steps": steps, "warmup": 0, "ms_per_step": round(f32["ms"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32-states/f64-arithmetic-and-dots", "data": "synthetic",
+        "config": {"workload": "graphene sheet 2828x1414 sites (3998792), 0.5% vacancies, "
+                               "W=0.1 eV, 64 random-phase vectors (seeds 3000..3063), 3000 "
+                               "moments, VAC+MSD 20 steps x 40 Bessel terms, dt=hbar/|t|",
+                   "n_sites": n, "n_vec": r, "site_updates_per_step": f32["site_updates"]},
         "fp64_batched_gsu": round(res["fp64"]["gsu"], 3),
-        "speedup_fp32_vs_fp64": round(res["fp32"]["gsu"] / res["fp64"]["gsu"], 3),
-        "sigma_rel_err_fp32_vs_fp64": {"gk": err_gk, "e1": err_e1,
-                                       "energies": 2048, "times": "dt, 2dt"},
-        "roofline": {prec: {"bound": "hbm", "bytes_per_site_update": round(bpu[prec], 3),
-                            "avg_launch_us": round(res[prec]["launch_us"], 2),
-                            "launch_shape": res[prec]["launch"],
-                            "achieved": round(bpu[prec] * n * r / (res[prec]["launch_us"] * 1e-6) / 1e9, 1),
-                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": round(bpu[prec] * n * r / (res[prec]["launch_us"] * 1e-6) / 1e9
-                                          / HBM_PEAK_GBS, 4)}
-                     for prec in ("fp64", "fp32")},
+        "plain_fp64_one_vector_gsu": round(plain, 3),
+        "speedup_fp32_batched_vs_plain_fp64": round(f32["gsu"] / plain, 3),
+        "speedup_fp32_vs_fp64_batched": round(f32["gsu"] / res["fp64"]["gsu"], 3),
+        "sigma_rel_err_fp32_vs_fp64": err32,
+        "sigma_rel_err_vs_oracle": err_or,
+        "sigma_error_norm": "max over 2048 energies in [-0.95 E_s, 0.95 E_s] and 21 times of "
+                            "|d sigma| / max |sigma_ref|; vs_oracle: vector 0 (seed 3000) "
+                            "against the oracle's stored moments of that vector",
+        "sigma_bar": 1e-3, "sigma_within_bar": bool(worst <= 1e-3),
+        "roofline": {"kernel": kname, "bound": "hbm",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": f32["bytes_launch"],
+                     "avg_launch_us": round(f32["launch_us"], 2),
+                     "launch_shape": f32["launch"]},
+        "launch_shapes": {k: v["launch"] for k, v in res.items()},
     }
     print(json.dumps(out), flush=True)
 

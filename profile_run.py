@@ -41,8 +41,10 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1307_0288_amd", "csrc", "kpm_kernels.hip"
 
 def multi_step(launch: dict, n_vec: int = 1) -> bool:
     """Whether moment sets take the multi-step sweeps under this launch shape
-    (one vector, compact form; the sample must be a chain lattice)."""
-    return launch.get("steps", 1) >= 2 and n_vec == 1 and bool(launch["compact"])
+    (compact form; one vector, or several kept vector-major, which take the
+    strips; the sample must be a chain lattice)."""
+    planar = n_vec > 1 and launch.get("vectors_per_wave", 0) == 1 and launch.get("tiled", 0) >= 3
+    return launch.get("steps", 1) >= 2 and (n_vec == 1 or planar) and bool(launch["compact"])
 
 
 def float_onsite(onsite) -> bool:

@@ -142,3 +142,51 @@ def test_evolve_norm_and_inverse(paper):
     assert abs(n1 - n0) < 1e-10 * n0
     kp.kpm_evolve(sysg, e, p["dt_fs"], -1, p["n_bessel"])
     assert np.max(np.abs(e.cpu().numpy() - ref)) < 1e-11
+
+
+def _oracle_spectra(dos, vac, msd, en, es, area, dt):
+    rho_v = oracle.kpm_sum(vac, en, es, area)
+    rho_m = oracle.kpm_sum(msd, en, es, area)
+    return dict(dos=oracle.dos(dos, en, es, area), gk=oracle.sigma_gk(rho_v, dt),
+                e1=oracle.sigma_e1(rho_m, dt), e2=oracle.sigma_e2(rho_m, dt))
+
+
+def test_fp32_states_eight_vectors_sigma(paper):
+    """Eight vectors (seeds 3000 .. 3007) with FP32 states (FP64 arithmetic,
+    inner products and moments) through the whole hot path: the DOS (Eq. 29)
+    and sigma_GK / sigma_E1 / sigma_E2 (Eq. 6, 9, 11) at 2048 energies and all
+    21 times are within 1e-3 of the FP64 states' (mean over the vectors), and
+    vector 0's within 1e-3 of the oracle's; the FP64 states' vector 0 matches
+    the oracle to 1e-8."""
+    p, act, phi, gold, sysg, d = paper
+    n = p["nx"] * p["ny"]
+    es, dt, nm = p["e_scale"], p["dt_fs"], p["n_moments"]
+    ons = ki.anderson_onsite(n, p["w"], 1000)
+    phi8 = ki.random_phase(n, 8, 3000, act)
+    assert np.array_equal(phi8[:, 0], phi)
+    args = (p["n_steps"], dt, p["n_bessel"], nm)
+    o_area = (np.sqrt(3.0) * p["nx"] * oracle.BOND_NM / 2.0) * (3.0 * p["ny"] * oracle.BOND_NM / 2.0)
+    en = oracle.energies_grid(2048, es)
+    runs = {}
+    for prec in ("fp32", "fp64"):
+        _log(f"paper-scale, 8 vectors, {prec} states: DOS, VAC, MSD")
+        s8 = kp.graphene_system(p["nx"], p["ny"], "sheet", p["t"], ons, act, es, prec)
+        _log(f"launch shape {kp.kpm_get_launch(s8, 8)}")
+        d8 = s8.upload(phi8)
+        runs[prec] = (kp.kpm_moments(s8, d8, d8, nm).real, kp.kpm_vac(s8, d8, *args),
+                      kp.kpm_msd(s8, d8, *args))
+        s8.close()
+        del d8
+    mean = {k: _oracle_spectra(v[0].mean(axis=0), v[1].mean(axis=0), v[2].mean(axis=0), en, es,
+                               o_area, dt) for k, v in runs.items()}
+    first = {k: _oracle_spectra(v[0][0], v[1][0], v[2][0], en, es, o_area, dt)
+             for k, v in runs.items()}
+    ref = _oracle_spectra(gold["dos"].real, gold["vac"], gold["msd"], en, es, o_area, dt)
+    for key in ("dos", "gk", "e1", "e2"):
+        e32 = rel_err(mean["fp32"][key], mean["fp64"][key])
+        o32 = rel_err(first["fp32"][key], ref[key])
+        o64 = rel_err(first["fp64"][key], ref[key])
+        _log(f"sigma {key}: fp32 vs fp64 {e32:.2e}, fp32 vs oracle {o32:.2e}, "
+             f"fp64 vs oracle {o64:.2e}")
+        assert e32 <= 1e-3 and o32 <= 1e-3, key
+        assert o64 <= 1e-8, key
