@@ -38,6 +38,8 @@ HBM_PEAK_GBS = 8000.0
 # rate is the published 78.6 TFLOP/s)
 VALU_PEAK_GINST = 256 * 4 * 2.4 / 4
 SQ_FILE = os.path.join(ROOT, "profiles", "moment_multistep_fp64_paper_sq.json")
+SQ_FILE_R64 = os.path.join(ROOT, "profiles", "moment_multistep_fp32_r64_paper_sq.json")
+TRAFFIC_FILE_R64 = os.path.join(ROOT, "profiles", "moment_multistep_fp32_r64_paper_traffic.json")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "moment_step_fp64_paper_traffic.json")
 TRAFFIC_FILE_DBL = os.path.join(ROOT, "profiles", "moment_step_doubled_fp64_paper_traffic.json")
 TRAFFIC_FILE2 = os.path.join(ROOT, "profiles", "moment_multistep_fp64_paper_traffic.json")
@@ -801,6 +803,11 @@ def batched(args):
     kname = moment_kernel_name("float2", f32["launch"], False, real=True, onsf=False,
                                n_vec=r)
     achieved = f32["bytes_launch"] / (f32["launch_us"] * 1e-6) / 1e9
+    launch_s = f32["launch_us"] * 1e-6
+    traffic = measured_traffic(TRAFFIC_FILE_R64, f32["rows"], f32["launch"], kname)
+    sq = valu_record(SQ_FILE_R64, f32["rows"], f32["launch"], kname)
+    hbm = (traffic if traffic is not None else f32["bytes_launch"]) / launch_s / 1e9
+    valu = None if sq is None else sq["valu_insts_per_launch"] / launch_s / 1e9
     out = {
         "metric": "Gsite-updates/s (batched Chebyshev hot path: DOS + VAC + MSD, 64 vectors, "
                   "FP32 states)",
@@ -824,7 +831,20 @@ def batched(args):
         "sigma_bar": 1e-3, "sigma_within_bar": bool(worst <= 1e-3),
         "roofline": {"kernel": kname, "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_source": (f"lookup: {os.path.relpath(TRAFFIC_FILE_R64, ROOT)} "
+                                        "(rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated, same "
+                                        "kernel source, size and shape; not measured in this run)")
+                                       if traffic is not None else None,
+                     "bound_by": {"hbm_gbs": round(hbm, 1),
+                                  "hbm_basis": "measured traffic" if traffic is not None
+                                               else "algorithmic bytes",
+                                  "frac_of_peak": {"hbm": round(hbm / HBM_PEAK_GBS, 4),
+                                                   **({} if valu is None else
+                                                      {"alu": round(valu / VALU_PEAK_GINST, 4)})},
+                                  "valu_ginst_per_s": None if valu is None else round(valu, 1),
+                                  "valu_source": (f"lookup: {os.path.relpath(SQ_FILE_R64, ROOT)}"
+                                                  " (rocprofv3 SQ_INSTS_VALU)") if sq else None},
                      "bytes_per_launch": f32["bytes_launch"],
                      "avg_launch_us": round(f32["launch_us"], 2),
                      "launch_shape": f32["launch"]},

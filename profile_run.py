@@ -190,6 +190,43 @@ def summarize(fetch_dir: str, write_dir: str, meta_path: str, out_path: str):
     print(json.dumps(out))
 
 
+SQ_KEYS = ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY",
+           "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_LDS", "SQ_INSTS_VALU",
+           "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR",
+           "SQ_WAIT_INST_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_SCA")
+
+
+def summarize_sq(dirs, meta_path: str, out_path: str):
+    """Per-launch averages of the SQ counters of the kernel named in the meta
+    (one or more --pmc runs, one directory each), as one record: the VALU
+    instructions per launch are what bench.py reads for its VALU roof."""
+    with open(meta_path) as f:
+        meta = json.load(f)
+    prefix = "void kpm::" + meta["kernel"].split("<")[0] + "<"
+    vals = {}
+    for d in dirs:
+        rows = [r for r in _read_counter(d) if r["Kernel_Name"].startswith(prefix)]
+        per = {}
+        for r in rows:
+            key = (r["Counter_Name"], r["Dispatch_Id"])
+            per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+        for name in {k[0] for k in per}:
+            vals[name] = round(_mean(v for (c, _), v in per.items() if c == name), 1)
+    out = {
+        "kernel": meta["kernel"],
+        "kernel_sha": meta["kernel_sha"],
+        "step_rows": meta["step_rows"],
+        "launch_shape": meta["launch_shape"],
+        "counters_per_launch": {k: vals[k] for k in SQ_KEYS if k in vals},
+        "valu_insts_per_launch": vals.get("SQ_INSTS_VALU"),
+        "command": meta["command"].replace("--pmc FETCH_SIZE (then WRITE_SIZE)",
+                                           "--pmc <SQ counter set>"),
+    }
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
 def _short_kernel_name(name: str) -> str:
     name = name.replace("HIP_vector_type<double, 2u>", "double2")
     name = name.replace("HIP_vector_type<float, 2u>", "float2")
@@ -231,6 +268,8 @@ def main():
     ap.add_argument("--meta", default="", help="write the run's launch shape, sizes and "
                                                "algorithmic bytes here")
     ap.add_argument("--summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--summarize-sq", nargs="+", metavar="PMC_DIR",
+                    help="per-launch SQ counter averages of the meta's kernel")
     ap.add_argument("--out", default="")
     ap.add_argument("--trace-table", metavar="KERNEL_STATS_CSV",
                     help="print a markdown table of a --stats kernel summary")
@@ -241,6 +280,8 @@ def main():
         return
     if args.summarize:
         return summarize(args.summarize[0], args.summarize[1], args.meta, args.out)
+    if args.summarize_sq:
+        return summarize_sq(args.summarize_sq, args.meta, args.out)
 
     import torch
     import kpm_inputs as ki
@@ -251,6 +292,7 @@ def main():
     n = p["nx"] * p["ny"]
     act = ki.vacancy_mask(n, p["vac"], 2000)
     ons = ki.anderson_onsite(n, p["w"], 1000)
+    onsf = float_onsite(ons)
     sysg = kp.graphene_system(p["nx"], p["ny"], "sheet", p["t"], ons, act, p["e_scale"],
                               args.precision)
     phi = sysg.upload(ki.random_phase(n, args.n_vec, 3000, act))
@@ -290,7 +332,7 @@ def main():
         if args.autotune:
             cmd.append(f"--autotune {args.autotune}")
         meta = {
-            "kernel": f"{moment_kernel_name(v, launch, args.doubled, args.n_vec, args.real)} "
+            "kernel": f"{moment_kernel_name(v, launch, args.doubled, args.n_vec, args.real, onsf)} "
                       f"({args.precision}, {args.n_vec} vector(s))",
             "kernel_sha": kernel_sha(launch),
             "step_rows": st["step_rows"],
