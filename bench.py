@@ -40,6 +40,8 @@ VALU_PEAK_GINST = 256 * 4 * 2.4 / 4
 SQ_FILE = os.path.join(ROOT, "profiles", "moment_multistep_fp64_paper_sq.json")
 SQ_FILE_R64 = os.path.join(ROOT, "profiles", "moment_multistep_fp32_r64_paper_sq.json")
 TRAFFIC_FILE_R64 = os.path.join(ROOT, "profiles", "moment_multistep_fp32_r64_paper_traffic.json")
+SQ_FILE_R64A = os.path.join(ROOT, "profiles", "moment_multistep_fp32a_r64_paper_sq.json")
+TRAFFIC_FILE_R64A = os.path.join(ROOT, "profiles", "moment_multistep_fp32a_r64_paper_traffic.json")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "moment_step_fp64_paper_traffic.json")
 TRAFFIC_FILE_DBL = os.path.join(ROOT, "profiles", "moment_step_doubled_fp64_paper_traffic.json")
 TRAFFIC_FILE2 = os.path.join(ROOT, "profiles", "moment_multistep_fp64_paper_traffic.json")
@@ -162,6 +164,9 @@ def main():
                          "DOS by KPM vs the Fourier-transform method at equal resolution")
     ap.add_argument("--samples", type=int, default=2000,
                     help="learned workload: generated samples (the last 10 %% are held out)")
+    ap.add_argument("--label-vectors", type=int, default=16,
+                    help="learned workload: random-phase vectors per sample (the labels' "
+                         "stochastic error falls as one over the square root of this)")
     ap.add_argument("--onsite", default="f64", choices=["f64", "f32"],
                     help="paper workload: the generator's disorder draw (f64, default), or the "
                          "same draw rounded to float32 (f32: the library then stores the on-site "
@@ -475,7 +480,8 @@ def learned(args):
     """Learned moment-to-spectrum reconstruction (not the paper's method).
 
     Data: `--samples` periodic sheets of 632 x 316 sites (199,712), vacancy
-    fraction in [0, 2 %), Anderson W in [0, 2) eV, 4 random-phase vectors each,
+    fraction in [0, 2 %), Anderson W in [0, 2) eV, `--label-vectors` random-phase
+    vectors each (16 by default),
     FP32 states, E_s = 1.01 (3|t| + 1 eV) for all; per sample 4000 DOS moments
     and 4000 MSD moments at t* = 10 fs (10 steps of 1 fs, 40 Bessel terms), both
     in the doubling form, in ragged batches of 20 samples.  Targets: Jackson KPM
@@ -483,12 +489,17 @@ def learned(args):
     [-7.5, 7.5] eV); features: the first 256 moments of each.  The network
     (513 -> 1024 -> 1024 -> 2048, tanh) trains with Adam on 90 % of the samples;
     on the held-out 10 % its spectra are compared with plain 4000-moment KPM,
-    and plain KPM is kept wherever the learned error exceeds 1e-3."""
+    and plain KPM is kept wherever the learned error exceeds 1e-3.  Reported
+    side by side, in the same norm against the 4000-moment spectra: the
+    learned error, the error of plain Jackson KPM from the same 256 moments
+    the network reads (Eq. 29-31, 35), and the labels' own stochastic error."""
     import torch
     import paper_1307_0288_amd as kp
     nx, ny = 632, 316
     n = nx * ny
-    r_vec, nm, n_in, nc, dt, nb = 4, 4000, 256, 10, 1.0, 40
+    r_vec, nm, n_in, nc, dt, nb = args.label_vectors, 4000, 256, 10, 1.0, 40
+    if r_vec < 2 or r_vec & (r_vec - 1) or r_vec > 64:
+        raise SystemExit("--label-vectors must be a power of two in 2 .. 64")
     es = 1.01 * (3 * 2.7 + 1.0)
     t_star = nc * dt
     en = np.linspace(-7.5, 7.5, 1024)
@@ -496,15 +507,26 @@ def learned(args):
     specs = ki.learned_sample_specs(args.samples, 100000)
     mus, cs = [], []
     t_gen = 0.0
+
+    def inputs(sp):
+        act = ki.vacancy_mask(n, sp["vac"], sp["vac_seed"])
+        ons = ki.anderson_onsite(n, sp["w"], sp["onsite_seed"])
+        return (dict(nx=nx, ny=ny, geometry="sheet", onsite=ons, active=act, e_scale=es),
+                ki.random_phase(n, r_vec, sp["vec_seed"], act))
+
+    from concurrent.futures import ThreadPoolExecutor
+    pool = ThreadPoolExecutor(max(1, host_cores()))
+
+    def submit(b0):          # the host inputs of one batch, drawn on every core
+        return [pool.submit(inputs, sp) for sp in specs[b0:b0 + per_batch]]
+
+    nxt = submit(0)
     for b0 in range(0, len(specs), per_batch):
-        group = specs[b0:b0 + per_batch]
-        samples, phis = [], []
-        for sp in group:
-            act = ki.vacancy_mask(n, sp["vac"], sp["vac_seed"])
-            ons = ki.anderson_onsite(n, sp["w"], sp["onsite_seed"])
-            samples.append(dict(nx=nx, ny=ny, geometry="sheet", onsite=ons, active=act,
-                                e_scale=es))
-            phis.append(ki.random_phase(n, r_vec, sp["vec_seed"], act))
+        group = [f.result() for f in nxt]
+        nxt = submit(b0 + per_batch)              # one batch ahead, while this one runs
+        samples = [g[0] for g in group]
+        phis = [g[1] for g in group]
+        del group
         sysg = kp.graphene_batch(samples, "fp32")
         d = sysg.upload(np.concatenate(phis))
         del phis
@@ -521,6 +543,7 @@ def learned(args):
         del d, y_state
         log(f"generated {min(b0 + per_batch, len(specs))}/{len(specs)} samples "
             f"({t_gen:.1f} s GPU)")
+    pool.shutdown()
     mu = np.concatenate(mus)
     cm = np.concatenate(cs)
     lx = np.sqrt(3.0) * nx * 0.142 / 2.0
@@ -569,12 +592,22 @@ def learned(args):
     e_sig = np.max(np.abs(pred[:, k:] - yh[:, k:]), axis=1) / np.max(np.abs(yh[:, k:]), axis=1)
     accept = (e_dos <= 1e-3) & (e_sig <= 1e-3)
     # stochastic spread of plain KPM itself on the same samples: the targets of
-    # the two disjoint vector pairs differ by about twice the error of the
-    # four-vector target
-    ya = kp.kpm_learned_targets(mu[n_train:, :2], cm[n_train:, :2], en, es, area, t_star)
-    yb = kp.kpm_learned_targets(mu[n_train:, 2:], cm[n_train:, 2:], en, es, area, t_star)
+    # the two disjoint halves of the vectors differ by about twice the error of
+    # the target from all of them
+    h = r_vec // 2
+    ya = kp.kpm_learned_targets(mu[n_train:, :h], cm[n_train:, :h], en, es, area, t_star)
+    yb = kp.kpm_learned_targets(mu[n_train:, h:], cm[n_train:, h:], en, es, area, t_star)
     s_dos = 0.5 * np.max(np.abs(ya[:, :k] - yb[:, :k]), axis=1) / np.max(np.abs(yh[:, :k]), axis=1)
     s_sig = 0.5 * np.max(np.abs(ya[:, k:] - yb[:, k:]), axis=1) / np.max(np.abs(yh[:, k:]), axis=1)
+    # what the network replaces: plain Jackson KPM from the same 256 moments
+    y256 = kp.kpm_learned_targets(mu[n_train:, :, :n_in], cm[n_train:, :, :n_in], en, es, area,
+                                  t_star)
+    k_dos = np.max(np.abs(y256[:, :k] - yh[:, :k]), axis=1) / np.max(np.abs(yh[:, :k]), axis=1)
+    k_sig = np.max(np.abs(y256[:, k:] - yh[:, k:]), axis=1) / np.max(np.abs(yh[:, k:]), axis=1)
+
+    def stats(e):
+        return {"median": float(np.median(e)), "p90": float(np.quantile(e, 0.9)),
+                "max": float(np.max(e))}
     # cost per sample: the learned path needs the first 256 moments of each set,
     # plain KPM all 4000; both need the [X, U(t*)] state
     flops_step = 6.0 * batch * sum(sizes[l] * sizes[l + 1] for l in range(len(sizes) - 1))
@@ -593,18 +626,26 @@ def learned(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{len(specs)} sheets 632x316 (199712 sites), vacancies 0-2%, "
-                               "W 0-2 eV, 4 vectors, FP32 states; 4000 DOS + 4000 MSD(t*=10 fs) "
+                               f"W 0-2 eV, {r_vec} vectors, FP32 states; 4000 DOS + 4000 MSD(t*=10 fs) "
                                "moments; MLP 513-1024-1024-2048 on 256 moments, 1024 energies",
                    "train": n_train, "held_out": len(specs) - n_train},
         "plain_kpm_samples_per_s": round(1.0 / gen_per_sample, 3),
         "learned_only_samples_per_s": round(1.0 / (gen_per_sample * frac_learned), 3),
-        "learned_error": {"dos_median": float(np.median(e_dos)), "dos_p90": float(np.quantile(e_dos, 0.9)),
-                          "sigma_median": float(np.median(e_sig)),
-                          "sigma_p90": float(np.quantile(e_sig, 0.9))},
-        "kpm_stochastic_error": {"dos_median": float(np.median(s_dos)),
-                                 "sigma_median": float(np.median(s_sig)),
-                                 "estimate": "half the difference of the targets of vectors "
-                                             "{0,1} and {2,3}, same norm"},
+        "error_vs_4000_moment_kpm": {
+            "norm": "per held-out sample max|dy| / max|y| over the 1024 energies",
+            "learned": {"dos": stats(e_dos), "sigma_e2": stats(e_sig)},
+            "plain_kpm_256_moments": {"dos": stats(k_dos), "sigma_e2": stats(k_sig)},
+            "label_noise": {"dos": stats(s_dos), "sigma_e2": stats(s_sig),
+                            "estimate": f"half the difference of the targets of vectors "
+                                        f"0..{h - 1} and {h}..{r_vec - 1}, same norm"}},
+        "learned_beats_kpm_256": {
+            "dos_fraction": float(np.mean(e_dos < k_dos)),
+            "sigma_fraction": float(np.mean(e_sig < k_sig)),
+            "dos_median_ratio": float(np.median(e_dos / k_dos)),
+            "sigma_median_ratio": float(np.median(e_sig / k_sig))},
+        "label_vectors": r_vec,
+        "gate_1e-3_reachable": bool(np.median(s_dos) <= 1e-3),
+        "label_vectors_for_1e-3_dos": int(np.ceil(r_vec * (np.median(s_dos) / 1e-3) ** 2)),
         "accepted_at_1e-3": int(accept.sum()), "fallback_to_kpm": int((~accept).sum()),
         "train_seconds": round(t_train, 2), "train_steps": steps,
         "train_tflops": round(flops_step * steps / t_train / 1e12, 3),
@@ -744,7 +785,7 @@ def batched(args):
     en = np.linspace(-0.95 * es, 0.95 * es, 2048)
     steps = max(1, args.steps)
     res, spec, spec0 = {}, {}, {}
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "fp32_arith"):
         sysg = kp.graphene_system(p["nx"], p["ny"], "sheet", p["t"], ons, act, es, prec)
         area = sysg.area_nm2
         phi = sysg.upload(phi_h)
@@ -793,33 +834,44 @@ def batched(args):
     sysg.close()
     log(f"plain fp64, one vector: {plain:.1f} Gsite-updates/s")
 
-    err32 = {k: _rel(spec["fp32"][k], spec["fp64"][k]) for k in spec["fp64"]}
+    f32s = ("fp32", "fp32_arith")
+    err32 = {q: {k: _rel(spec[q][k], spec["fp64"][k]) for k in spec["fp64"]} for q in f32s}
     err_or = None
     if gold is not None:
         ref = _spectra(kp, gold["dos"], gold["vac"], gold["msd"], en, es, area, dt)
         err_or = {prec: {k: _rel(spec0[prec][k], ref[k]) for k in ref} for prec in spec0}
-    worst = max(list(err32.values()) + ([] if err_or is None else list(err_or["fp32"].values())))
-    f32 = res["fp32"]
+    worst = {q: max(list(err32[q].values()) +
+                    ([] if err_or is None else list(err_or[q].values()))) for q in f32s}
+    # the reported FP32 form: the faster one whose sigma(E) error is within the bar
+    ok = [q for q in f32s if worst[q] <= 1e-3]
+    best = max(ok or list(f32s), key=lambda q: res[q]["gsu"])
+    f32 = res[best]
     kname = moment_kernel_name("float2", f32["launch"], False, real=True, onsf=False,
-                               n_vec=r)
+                               n_vec=r, arith32=best == "fp32_arith")
+    tfile, sfile = ((TRAFFIC_FILE_R64, SQ_FILE_R64) if best == "fp32" else
+                    (TRAFFIC_FILE_R64A, SQ_FILE_R64A))
     achieved = f32["bytes_launch"] / (f32["launch_us"] * 1e-6) / 1e9
     launch_s = f32["launch_us"] * 1e-6
-    traffic = measured_traffic(TRAFFIC_FILE_R64, f32["rows"], f32["launch"], kname)
-    sq = valu_record(SQ_FILE_R64, f32["rows"], f32["launch"], kname)
+    traffic = measured_traffic(tfile, f32["rows"], f32["launch"], kname)
+    sq = valu_record(sfile, f32["rows"], f32["launch"], kname)
     hbm = (traffic if traffic is not None else f32["bytes_launch"]) / launch_s / 1e9
     valu = None if sq is None else sq["valu_insts_per_launch"] / launch_s / 1e9
     out = {
         "metric": "Gsite-updates/s (batched Chebyshev hot path: DOS + VAC + MSD, 64 vectors, "
                   "FP32 states)",
+        "fp32_form": best,
         "value": round(f32["gsu"], 3), "unit": "Gsite-updates/s", "n_gpus": 1,
         "steps": steps, "warmup": 0, "ms_per_step": round(f32["ms"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32-states/f64-arithmetic-and-dots", "data": "synthetic",
+        "dtype": ("f32-states-and-strip-arithmetic/f64-dots" if best == "fp32_arith"
+                  else "f32-states/f64-arithmetic-and-dots"), "data": "synthetic",
         "config": {"workload": "graphene sheet 2828x1414 sites (3998792), 0.5% vacancies, "
                                "W=0.1 eV, 64 random-phase vectors (seeds 3000..3063), 3000 "
                                "moments, VAC+MSD 20 steps x 40 Bessel terms, dt=hbar/|t|",
                    "n_sites": n, "n_vec": r, "site_updates_per_step": f32["site_updates"]},
         "fp64_batched_gsu": round(res["fp64"]["gsu"], 3),
+        "fp32_states_gsu": round(res["fp32"]["gsu"], 3),
+        "fp32_arith_gsu": round(res["fp32_arith"]["gsu"], 3),
         "plain_fp64_one_vector_gsu": round(plain, 3),
         "speedup_fp32_batched_vs_plain_fp64": round(f32["gsu"] / plain, 3),
         "speedup_fp32_vs_fp64_batched": round(f32["gsu"] / res["fp64"]["gsu"], 3),
@@ -828,11 +880,11 @@ def batched(args):
         "sigma_error_norm": "max over 2048 energies in [-0.95 E_s, 0.95 E_s] and 21 times of "
                             "|d sigma| / max |sigma_ref|; vs_oracle: vector 0 (seed 3000) "
                             "against the oracle's stored moments of that vector",
-        "sigma_bar": 1e-3, "sigma_within_bar": bool(worst <= 1e-3),
+        "sigma_bar": 1e-3, "sigma_within_bar": {q: bool(worst[q] <= 1e-3) for q in f32s},
         "roofline": {"kernel": kname, "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "traffic_source": (f"lookup: {os.path.relpath(TRAFFIC_FILE_R64, ROOT)} "
+                     "traffic_source": (f"lookup: {os.path.relpath(tfile, ROOT)} "
                                         "(rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated, same "
                                         "kernel source, size and shape; not measured in this run)")
                                        if traffic is not None else None,
@@ -843,7 +895,7 @@ def batched(args):
                                                    **({} if valu is None else
                                                       {"alu": round(valu / VALU_PEAK_GINST, 4)})},
                                   "valu_ginst_per_s": None if valu is None else round(valu, 1),
-                                  "valu_source": (f"lookup: {os.path.relpath(SQ_FILE_R64, ROOT)}"
+                                  "valu_source": (f"lookup: {os.path.relpath(sfile, ROOT)}"
                                                   " (rocprofv3 SQ_INSTS_VALU)") if sq else None},
                      "bytes_per_launch": f32["bytes_launch"],
                      "avg_launch_us": round(f32["launch_us"], 2),

@@ -20,7 +20,7 @@
  *   checks e_scale >= the Gershgorin bound).  No shift is applied.
  * States: device memory, complex numbers stored as (re, im) pairs,
  *   layout [n_sites][n_vec] with the vector index fastest; element type
- *   double for KPM_FP64 systems and float for KPM_FP32_STATES systems.
+ *   double for KPM_FP64 systems and float for KPM_FP32_STATES and KPM_FP32 systems.
  *   n_vec must be 1, 2, 4, 8, 16, 32 or 64.  States must be zero on removed
  *   (inactive) sites; the library keeps them zero there.
  * Streams: every call enqueues its work on the system's HIP stream.  Calls
@@ -50,8 +50,12 @@ typedef enum {
 
 typedef enum {
     KPM_FP64 = 0,            /* states and arithmetic in double            */
-    KPM_FP32_STATES = 1      /* states stored as float; recursion arithmetic,
+    KPM_FP32_STATES = 1,     /* states stored as float; recursion arithmetic,
                                 inner products and moments in double       */
+    KPM_FP32 = 2             /* states stored as float, the recursion levels
+                                of the multi-step strips computed in float
+                                (other steps as KPM_FP32_STATES); inner
+                                products and moments in double             */
 } kpm_precision;
 
 enum { KPM_MAX_WIDTH = 4 };
@@ -497,6 +501,13 @@ kpm_status kpm_xu_state(kpm_system *sys, int n_vec, const void *phi, int n_steps
  * to the whole sample), so fewer boundary chains are recomputed.  Batches
  * and n_vec = 1 ignore both fields, and the layout of a call follows the
  * direct form's shape (kpm_set_launch) also for doubling-form moment sets.
+ *
+ * group_size: threads per work-group of the marching strips (64, 128, 256 or
+ * 512; 0 = 256).  Each wavefront walks its own strips, so the group size
+ * changes how the grid's wavefronts are grouped (groups_per_cu then counts
+ * groups of that size; 8 x 64, 4 x 128, 2 x 256 and 1 x 512 threads per CU
+ * all give two wavefronts per SIMD); the coupled strips of Alg. 7 and all
+ * other kernels keep 256.
  */
 typedef struct {
     int32_t groups_per_cu;
@@ -507,6 +518,7 @@ typedef struct {
     int32_t steps;
     int32_t vectors_per_wave;
     int32_t plane_groups;
+    int32_t group_size;
 } kpm_launch;
 
 /* The shape a new system starts with for n_vec vectors per row (both forms):
@@ -542,6 +554,12 @@ kpm_status kpm_get_launch_doubled(kpm_system *sys, int n_vec, kpm_launch *out);
  * for this n_vec and returns the direct form's in *best (may be NULL).
  * Synchronises the stream.
  */
+/* The candidate shapes kpm_autotune times for n_vec vectors on this system
+ * (the incumbent shape is timed first as well): *count receives their number
+ * and out[0 .. min(capacity, count) - 1] the shapes (out may be NULL when
+ * capacity is 0).  Host only. */
+kpm_status kpm_autotune_candidates(kpm_system *sys, int n_vec, kpm_launch *out, int32_t capacity,
+                                   int32_t *count);
 kpm_status kpm_autotune(kpm_system *sys, int n_vec, const void *phi, int reps,
                         kpm_launch *best);
 

@@ -10,7 +10,7 @@ is no CPU fallback.
 """
 from .kpm import (ABI_SYMBOLS, HBAR_EV_FS, BOND_NM, KpmError, System, graphene_batch,
                   graphene_system,
-                  kpm_autotune, kpm_build_graphene, kpm_validate, kpm_evolve, kpm_evolve_x, kpm_fourier_moments,
+                  kpm_autotune, kpm_autotune_candidates, kpm_build_graphene, kpm_validate, kpm_evolve, kpm_evolve_x, kpm_fourier_moments,
                   kpm_ftm_sum, kpm_default_launch, kpm_get_launch, kpm_get_launch_doubled, kpm_set_launch_doubled,
                   kpm_get_stats, kpm_kpm_sum, kpm_set_graphs, kpm_set_launch,
                   kpm_moments, kpm_moments_doubled, kpm_moments_noalloc, kpm_msd, kpm_reset_stats, kpm_set_timing, kpm_sigma_e1,
@@ -22,7 +22,7 @@ from .kpm import (ABI_SYMBOLS, HBAR_EV_FS, BOND_NM, KpmError, System, graphene_b
 
 __all__ = ["ABI_SYMBOLS", "HBAR_EV_FS", "BOND_NM", "KpmError", "System", "graphene_batch",
            "graphene_system",
-           "kpm_autotune", "kpm_build_graphene", "kpm_validate", "kpm_evolve", "kpm_fourier_moments", "kpm_ftm_sum",
+           "kpm_autotune", "kpm_autotune_candidates", "kpm_build_graphene", "kpm_validate", "kpm_evolve", "kpm_fourier_moments", "kpm_ftm_sum",
            "kpm_default_launch", "kpm_get_launch", "kpm_get_launch_doubled", "kpm_set_launch_doubled", "kpm_set_launch",
            "kpm_set_graphs", "kpm_evolve_x", "kpm_get_stats",
            "kpm_kpm_sum", "kpm_moments", "kpm_moments_doubled", "kpm_moments_noalloc", "kpm_msd", "kpm_reset_stats", "kpm_set_timing",

@@ -21,7 +21,8 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libkpm.so")
 OBJDIR = os.path.join(PKG, "_build")
 SOURCES = ["kpm_kernels.hip", "kpm_host.cpp", "kpm_error.cpp", "kpm_lattice.cpp",
-           "kpm_transport.cpp", "kpm_learned.cpp", "kpm_mlp.hip", "kpm_noalloc.hip"]
+           "kpm_transport.cpp", "kpm_learned.cpp", "kpm_mlp.hip", "kpm_noalloc.hip",
+           "kpm_march32.hip"]
 ARCH = "gfx950"
 
 

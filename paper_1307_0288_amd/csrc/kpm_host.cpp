@@ -90,7 +90,14 @@ bool valid_launch(const kpm_launch &l) {
             (l.plane_groups >= kpm::kXcds && l.plane_groups <= 65536 &&
              l.plane_groups % kpm::kXcds == 0)) &&
            // vector-major states take several steps per pass only in the strips
-           !(l.vectors_per_wave == 1 && l.steps > 1 && l.tiled < 3);
+           !(l.vectors_per_wave == 1 && l.steps > 1 && l.tiled < 3) &&
+           (l.group_size == 0 || l.group_size == 64 || l.group_size == 128 ||
+            l.group_size == 256 || l.group_size == 512);
+}
+
+// Wavefronts per work-group of the marching strips under shape l.
+int strip_waves(const kpm_launch &l) {
+    return (l.group_size > 0 ? l.group_size : kpm::kBlock) / kpm::kWave;
 }
 
 // Tile width (rows) of the tiled traversal for 2^vshift vectors per row: a
@@ -193,7 +200,7 @@ kpm_launch default_launch(int vshift, kpm_precision prec) {
     // the compact neighbour form pays off while the per-row structure is a
     // noticeable share of the bytes (few vectors per row)
     l.groups_per_cu = vshift == 0 ? 4 : 8;
-    l.ilp = (vshift >= 6 && prec == KPM_FP32_STATES) ? 4 : 1;
+    l.ilp = (vshift >= 6 && prec != KPM_FP64) ? 4 : 1;
     l.streaming = vshift == 0 ? 0 : 1;
     l.compact = vshift <= 3 ? 1 : 0;
     // with 8+ vectors per row a row's vertical neighbour lies megabytes ahead in
@@ -400,7 +407,7 @@ struct kpm_system {
             // strip), then the longest strips (fewer reloaded boundary chains);
             // at least 8 chains
             const int64_t nst = (l2nx + kpm::kWave - 2 * k - 1) / (kpm::kWave - 2 * k);
-            const int64_t waves = (int64_t)nwg * (kpm::kBlock / kpm::kWave);
+            const int64_t waves = (int64_t)nwg * strip_waves(l);
             int64_t best = -1;
             // up to the whole sample when the grid has few wavefronts per
             // sample (vector-major states with few groups per plane)
@@ -416,7 +423,7 @@ struct kpm_system {
             }
         }
         return kpm::Lat2{l2nx, l2ny, k, reg, tj, (l2nx + kpm::kTileCols - 1) / kpm::kTileCols,
-                         (l2ny + tj - 1) / tj, d_code, d_flags};
+                         (l2ny + tj - 1) / tj, d_code, d_flags, prec == KPM_FP32 ? 1 : 0};
     }
 
     kpm::Ell ell() const {
@@ -462,6 +469,7 @@ struct kpm_system {
         kpm::Sweep sw{};
         sw.nplanes = 1;
         sw.pstride = 0;
+        sw.wpg = strip_waves(l);
         sw.total = n << vshift;
         sw.vshift = vshift;
         sw.ilp = l.ilp;
@@ -1031,7 +1039,10 @@ kpm_status run_evolve_x(kpm_system *sys, int vshift, const V *in, V *accx, V *ac
     // sets use strips and the commutator weights follow the neighbour patterns;
     // each recursion's new states go to two of its four scratch states that the
     // pass does not read
-    const kpm_launch &l = sys->launch[vshift];
+    // the coupled strips run in groups of kBlock threads whatever the shape's
+    // group size
+    kpm_launch l = sys->launch[vshift];
+    l.group_size = 0;
     const int k = std::min(sys->multi_steps(sw.vshift, l), 3);
     if (k > 1 && l.tiled >= 3 && sys->d_flags && sys->d_pxw && !tab && np - m >= 2) {
         KPM_TRY(sys->ensure_xbuf(vshift, 4));
@@ -1421,12 +1432,16 @@ kpm_status fourier_impl(kpm_system *sys, int vshift, const void *phil_v, const v
     return finish_moments(sys, elems, (double2 *)f);
 }
 
-template <typename V>
-kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_launch *best) {
-    KPM_TRY(sys->ensure_vecs(2, vs));
-    V *a = (V *)sys->vecs[0], *b = (V *)sys->vecs[1];
-    hipStream_t s = sys->stream;
-    const size_t bytes = sys->state_bytes(vs);
+// The launch shapes kpm_autotune times for 2^vs vectors on this system.
+// Candidates: single steps (grid x ILP x streaming x neighbour form x
+// traversal; all vectors of a row in adjacent lanes); then on chain lattices
+// several recursion steps per pass: for one vector two steps in LDS tiles, 2,
+// 3 or 4 steps in register tiles of 8 or 4 chains and 3 .. 8 steps in
+// marching strips where the slots follow the graphene order, for several
+// vectors one vector per wavefront in 4, 6 or 8-step strips (grid per plane
+// from groups_per_cu or 16 .. 128 groups per plane); strips also in
+// work-groups of 64, 128 and 512 threads.
+std::vector<kpm_launch> autotune_candidates(const kpm_system *sys, int vs) {
     static const int groups[] = {4, 8, 16};
     static const int ilps[] = {1, 2, 4};
     const int forms = sys->d_pid ? 2 : 1;
@@ -1434,6 +1449,58 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
     for (int32_t c : sys->chain) can_tile = can_tile || c >= 2 * tile_rows(vs);
     // row order and the base tile (wider tiles measured slower on every shape tried)
     const int tilings = can_tile ? 2 : 1;
+    std::vector<kpm_launch> cand;
+    for (int g : groups)
+        for (int q = 0; q < 6 * forms * tilings; ++q) {
+            kpm_launch l{};
+            l.groups_per_cu = g;
+            l.ilp = ilps[q % 3];
+            l.streaming = (q / 3) % 2;
+            l.compact = forms == 2 ? (q / 6) % 2 : 0;
+            l.tiled = tilings == 2 ? q / (6 * forms) : 0;
+            l.steps = 1;
+            cand.push_back(l);
+        }
+    // several vectors on a one-sample chain lattice: one vector per wavefront
+    // (vector-major states) in marching strips, the grid per plane from
+    // groups_per_cu or a few groups per plane (longer strips)
+    if (sys->d_flags && vs > 0 && sys->nseg == 1) {
+        for (int ksteps : {4, 6, 8})
+            for (int pg : {0, 16, 32, 64, 128})
+                cand.push_back(kpm_launch{2, 1, 0, 1, 5, ksteps, 1, pg, 0});
+        // work-groups of 64, 128 and 512 threads (the wavefronts per plane of 16
+        // groups of 256)
+        for (int gs : {64, 128, 512})
+            cand.push_back(kpm_launch{2 * 256 / gs, 1, 0, 1, 5, 8, 1, 16 * 256 / gs, gs});
+    }
+    if (sys->d_code && vs == 0) {
+        for (int g : {2, 3, 4, 6})
+            for (int nt : {0, 1}) cand.push_back(kpm_launch{g, 1, nt, 1, 0, 2});
+        if (sys->d_flags) {
+            for (int ksteps : {2, 3, 4})
+                for (int tiled : {1, 2})
+                    for (int g : {1, 2, 3, 4, 6, 8})
+                        cand.push_back(kpm_launch{g, 1, 0, 1, tiled, ksteps});
+            // eight-step strips in work-groups of 64, 128 and 512 threads (two
+            // wavefronts per SIMD)
+            for (int gs : {64, 128, 512})
+                cand.push_back(kpm_launch{2 * 256 / gs, 1, 0, 1, 5, 8, 0, 0, gs});
+            for (int ksteps : {3, 4, 5, 6, 7, 8}) {
+                for (int g : {2, 3, 4}) cand.push_back(kpm_launch{g, 1, 0, 1, 5, ksteps});
+                if (ksteps <= 6)
+                    for (int tiled : {3, 4}) cand.push_back(kpm_launch{2, 1, 0, 1, tiled, ksteps});
+            }
+        }
+    }
+    return cand;
+}
+
+template <typename V>
+kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_launch *best) {
+    KPM_TRY(sys->ensure_vecs(2, vs));
+    V *a = (V *)sys->vecs[0], *b = (V *)sys->vecs[1];
+    hipStream_t s = sys->stream;
+    const size_t bytes = sys->state_bytes(vs);
     hipEvent_t e0, e1;
     KPM_HIP(hipEventCreate(&e0));
     KPM_HIP(hipEventCreate(&e1));
@@ -1485,46 +1552,7 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
         *out_ms = best * (float)reps / (float)steps;     // per reps recursion steps
         return KPM_OK;
     };
-    // Candidates: single steps (grid x ILP x streaming x neighbour form x
-    // traversal), then several recursion steps per pass on chain lattices
-    // with one vector: two steps in LDS tiles, 2, 3 or 4 steps in register
-    // tiles of 8 or 4 chains and 3 .. 8 steps in marching strips where the
-    // slots follow the graphene order.
-    std::vector<kpm_launch> cand;
-    for (int g : groups)
-        for (int q = 0; q < 6 * forms * tilings; ++q) {
-            kpm_launch l{};
-            l.groups_per_cu = g;
-            l.ilp = ilps[q % 3];
-            l.streaming = (q / 3) % 2;
-            l.compact = forms == 2 ? (q / 6) % 2 : 0;
-            l.tiled = tilings == 2 ? q / (6 * forms) : 0;
-            l.steps = 1;
-            cand.push_back(l);
-        }
-    // several vectors on a one-sample chain lattice: one vector per wavefront
-    // (vector-major states) in marching strips, the grid per plane from
-    // groups_per_cu or a few groups per plane (longer strips)
-    if (sys->d_flags && vs > 0 && sys->nseg == 1) {
-        for (int ksteps : {4, 6, 8})
-            for (int pg : {0, 16, 32, 64, 128})
-                cand.push_back(kpm_launch{2, 1, 0, 1, 5, ksteps, 1, pg});
-    }
-    if (sys->d_code && vs == 0) {
-        for (int g : {2, 3, 4, 6})
-            for (int nt : {0, 1}) cand.push_back(kpm_launch{g, 1, nt, 1, 0, 2});
-        if (sys->d_flags) {
-            for (int ksteps : {2, 3, 4})
-                for (int tiled : {1, 2})
-                    for (int g : {1, 2, 3, 4, 6, 8})
-                        cand.push_back(kpm_launch{g, 1, 0, 1, tiled, ksteps});
-            for (int ksteps : {3, 4, 5, 6, 7, 8}) {
-                for (int g : {2, 3, 4}) cand.push_back(kpm_launch{g, 1, 0, 1, 5, ksteps});
-                if (ksteps <= 6)
-                    for (int tiled : {3, 4}) cand.push_back(kpm_launch{2, 1, 0, 1, tiled, ksteps});
-            }
-        }
-    }
+    const std::vector<kpm_launch> cand = autotune_candidates(sys, vs);
     // Each form (direct, doubling) keeps its current shape as the incumbent; a
     // candidate replaces it only when more than 2 % faster, so near-ties keep
     // a stable choice.
@@ -1783,7 +1811,8 @@ kpm_status kpm_batch_create(int n_sys, const kpm_system_desc *descs, kpm_precisi
     if (!descs || !out) return fail(KPM_ERR_INVALID, "null descriptor or output");
     *out = nullptr;
     if (n_sys < 1 || n_sys > 4096) return fail(KPM_ERR_INVALID, "n_sys must be 1..4096");
-    if (prec != KPM_FP64 && prec != KPM_FP32_STATES) return fail(KPM_ERR_INVALID, "precision");
+    if (prec != KPM_FP64 && prec != KPM_FP32_STATES && prec != KPM_FP32)
+        return fail(KPM_ERR_INVALID, "precision");
     std::vector<Packed> parts(n_sys);
     for (int s = 0; s < n_sys; ++s) KPM_TRY(pack_desc(&descs[s], s, parts[s]));
     return build_system(parts, prec, device, hip_stream, out);
@@ -2060,7 +2089,7 @@ kpm_status kpm_kpm_sum(int n_rows, int n_moments, const double *moments, int n_e
 kpm_status kpm_default_launch(int n_vec, kpm_precision precision, kpm_launch *out) {
     const int vs = vshift_of(n_vec);
     if (vs < 0) return fail(KPM_ERR_INVALID, "n_vec must be 1, 2, 4, ..., 64 (got %d)", n_vec);
-    if (precision != KPM_FP64 && precision != KPM_FP32_STATES)
+    if (precision != KPM_FP64 && precision != KPM_FP32_STATES && precision != KPM_FP32)
         return fail(KPM_ERR_INVALID, "precision");
     if (!out) return fail(KPM_ERR_INVALID, "null output");
     return env_launch(vs, precision, out);
@@ -2101,6 +2130,18 @@ kpm_status kpm_get_launch_doubled(kpm_system *sys, int n_vec, kpm_launch *out) {
     KPM_TRY(check_common(sys, n_vec, &vs));
     if (!out) return fail(KPM_ERR_INVALID, "null output");
     *out = sys->launch_dbl[vs];
+    return KPM_OK;
+}
+
+kpm_status kpm_autotune_candidates(kpm_system *sys, int n_vec, kpm_launch *out, int32_t capacity,
+                                   int32_t *count) {
+    int vs;
+    KPM_TRY(check_common(sys, n_vec, &vs));
+    if (!count || (capacity > 0 && !out) || capacity < 0)
+        return fail(KPM_ERR_INVALID, "null output or negative capacity");
+    const std::vector<kpm_launch> cand = autotune_candidates(sys, vs);
+    *count = (int32_t)cand.size();
+    for (int32_t q = 0; q < std::min<int32_t>(capacity, *count); ++q) out[q] = cand[q];
     return KPM_OK;
 }
 

@@ -8,6 +8,7 @@
 namespace kpm {
 
 constexpr int kBlock = 256;       // work-group size of the sweep kernels
+constexpr int kMaxStripBlock = 512;   // largest work-group of the marching strips
 constexpr int kWave = 64;         // CDNA wavefront
 constexpr int kXcds = 8;          // MI355X: 8 accelerator complex dies
 constexpr int kMaxWidth = 4;      // neighbour-list slots per row
@@ -79,6 +80,7 @@ struct Sweep {
     // and pstride = 0 for states with every vector of a row side by side.
     int64_t pstride;
     int nplanes;
+    int wpg;              // wavefronts per work-group of the marching strips (1 .. 8)
 };
 
 // Chain-lattice geometry of a one-sample system for the multi-step moment
@@ -103,6 +105,7 @@ struct Lat2 {
     int32_t nti, ntj;
     const uint32_t *code;    // [npat]
     const uint32_t *flags;   // [npat], or nullptr
+    int32_t arith32;         // FP32 states: strip levels in FP32 arithmetic (KPM_FP32)
 };
 
 // Coefficient of a step: the value for segment s is tab[s * stride + idx]
@@ -177,6 +180,15 @@ bool launch_evolve_x_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const
                            const V *p1, const V *p0, V *pout1, V *pout2, const V *q1,
                            const V *q0, V *qout1, V *qout2, V *accx, V *accu, const CoefK &ck,
                            hipStream_t s);
+
+// The strip launchers above for FP32 states with the recursion levels in FP32
+// registers (lat.arith32; kpm_march32.hip); the same contracts.
+bool launch_moment_multi_f32(const Ell &h, const Sweep &sw, const Lat2 &lat, const float2 *p1,
+                             const float2 *p0, float2 *out1, float2 *out2, const float2 *phil,
+                             double2 *partial, int slot, bool dbl, bool re, hipStream_t s);
+bool launch_evolve_multi_f32(const Ell &h, const Sweep &sw, const Lat2 &lat, const float2 *p1,
+                             const float2 *p0, float2 *out1, float2 *out2, float2 *acc,
+                             const CoefK &ck, hipStream_t s);
 
 // mom[t * stride + offset + j] = 2 mom[...j] - mom[...j % 2] for 2 <= j < nm,
 // t < rows: moments from the doubling sums.

@@ -16,6 +16,9 @@
 // every work-group belongs to exactly one segment (see Seg in
 // kpm_internal.h), so per-sample inner products need no atomics.
 #include "kpm_internal.h"
+#include "kpm_device.h"
+
+#include <type_traits>
 
 namespace kpm {
 
@@ -32,8 +35,6 @@ __device__ __forceinline__ void st(float2 *p, double2 v) {
 
 // Streaming (non-temporal) accesses for operands read or written once per
 // step, so that L2 keeps the gathered vector for the neighbour reads.
-typedef double d2v __attribute__((ext_vector_type(2)));
-typedef float f2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ double2 ld_nt(const double2 *p) {
     d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(p));
     return make_double2(v.x, v.y);
@@ -62,31 +63,6 @@ template <> __device__ __forceinline__ double2 rounded<float2>(double2 v) {
     return make_double2((double)(float)v.x, (double)(float)v.y);
 }
 
-// The library is compiled with -ffp-contract=off: every fused multiply-add
-// below is written out, so all launch shapes round identically.
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) {
-    return make_double2(a.x + b.x, a.y + b.y);
-}
-// s + a * b
-__device__ __forceinline__ double2 cmla(double2 s, double2 a, double2 b) {
-    return make_double2(fma(a.x, b.x, fma(-a.y, b.y, s.x)), fma(a.x, b.y, fma(a.y, b.x, s.y)));
-}
-// a * b
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-    return cmla(make_double2(0.0, 0.0), a, b);
-}
-// s + conj(a) * b
-__device__ __forceinline__ double2 cdot_acc(double2 s, double2 a, double2 b) {
-    return make_double2(fma(a.x, b.x, fma(a.y, b.y, s.x)), fma(a.x, b.y, fma(-a.y, b.x, s.y)));
-}
-// s + h * x  (real h)
-__device__ __forceinline__ double2 raxpy(double2 s, double h, double2 x) {
-    return make_double2(fma(h, x.x, s.x), fma(h, x.y, s.y));
-}
-// 2 a - b
-__device__ __forceinline__ double2 two_minus(double2 a, double2 b) {
-    return make_double2(fma(2.0, a.x, -b.x), fma(2.0, a.y, -b.y));
-}
 
 __device__ __forceinline__ double2 coef(const Coef &c, int sg) {
     return c.tab ? c.tab[sg * c.stride + c.idx] : c.val;
@@ -219,41 +195,7 @@ __device__ __forceinline__ double2 row_d(const Ell &h, const int32_t *lpat, cons
     return dx;
 }
 
-// Block-wide segmented sum: lane l holds a value for vector l % R; the R
-// sums of the work-group go to dst[0 .. R-1].  Fixed order.
-__device__ __forceinline__ void block_sum(double2 s, int vshift, double2 *dst) {
-    __shared__ double2 red[kBlock / kWave][kWave];
-    const int r = 1 << vshift;
-    for (int off = kWave / 2; off >= r; off >>= 1) {
-        s.x += __shfl_down(s.x, off, kWave);
-        s.y += __shfl_down(s.y, off, kWave);
-    }
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
-    __syncthreads();                        // red may still be read by a previous call
-    if (lane < r) red[wv][lane] = s;
-    __syncthreads();
-    if ((int)threadIdx.x < r) {
-        double2 t = red[0][threadIdx.x];
-#pragma unroll
-        for (int q = 1; q < kBlock / kWave; ++q) t = cadd(t, red[q][threadIdx.x]);
-        dst[threadIdx.x] = t;
-    }
-}
 
-// Vector-major states: the element offset of this group's plane, a state
-// pointer moved to it (null stays null), and the index of the group's
-// partial of `slot` in [slot][nwg][planes] (times the vectors per row).
-__device__ __forceinline__ int64_t plane_off(const Sweep &sw) {
-    return (int64_t)blockIdx.y * sw.pstride;
-}
-template <typename T>
-__device__ __forceinline__ T *on_plane(T *p, int64_t off) {
-    return p ? p + off : p;
-}
-__device__ __forceinline__ int64_t part_index(const Sweep &sw, int slot) {
-    return ((int64_t)slot * sw.nwg + blockIdx.x) * gridDim.y + blockIdx.y;
-}
 
 __device__ __forceinline__ Walk walk_of(const Sweep &sw) {
     Walk w;
@@ -802,9 +744,6 @@ __global__ __launch_bounds__(kBlock) void k_kpm_sum(const double *__restrict__ m
 // Non-DBL: partial[slot] = <L|phi_{n+1}>, partial[slot+1] = <L|phi_{n+2}>.
 // DBL (phi_L = phi_R): slots slot .. slot+3 get <phi_n|phi_n>,
 // <phi_n|phi_{n+1}>, <phi_{n+1}|phi_{n+1}>, <phi_{n+1}|phi_{n+2}>.
-__device__ __forceinline__ int wrap_index(int x, int n) {
-    return x < 0 ? x + n : (x >= n ? x - n : x);
-}
 
 // Row offset in a window of row width WW for slot code c (0xFF = empty: 0).
 template <int WW>
@@ -992,25 +931,6 @@ __global__ __launch_bounds__(kBlock) void k_moment_step2(Ell h, Sweep sw, Lat2 l
 // k_moment_step, in its slot order.
 // Partials: non-DBL slot + s - 1 = <L|phi_{n+s}>, s = 1 .. K; DBL slots
 // slot + 2 (s - 1) and + 1 = <phi_{n+s-1}|phi_{n+s-1}>, <phi_{n+s-1}|phi_{n+s}>.
-// Cross-lane moves by one lane as DPP wavefront shifts (one VALU move per
-// 32-bit half, no LDS): wave_shr:1 gives lane l the value of lane l - 1,
-// wave_shl:1 that of lane l + 1; the end lane, which has no source, reads 0
-// (bound_ctrl), so the move needs no copy of its old value.  End lanes are
-// halo lanes of every tile: their values are never used.
-constexpr int kDppWaveShl1 = 0x130;
-constexpr int kDppWaveShr1 = 0x138;
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, true),
-                            __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, true));
-}
-__device__ __forceinline__ double2 lane_prev(double2 v) {     // value of lane l - 1
-    return make_double2(dpp_move<kDppWaveShr1>(v.x), dpp_move<kDppWaveShr1>(v.y));
-}
-__device__ __forceinline__ double2 lane_next(double2 v) {     // value of lane l + 1
-    return make_double2(dpp_move<kDppWaveShl1>(v.x), dpp_move<kDppWaveShl1>(v.y));
-}
 
 // 2 H~ x - q at a row with flags f: own value x, horizontal neighbours from
 // the adjacent lanes, vertical from xup (next chain) or xdn (previous chain).
@@ -1023,40 +943,6 @@ __device__ __forceinline__ double2 reg_row_step(double o, double t, uint32_t f, 
     acc = raxpy(acc, (f & 2u) ? t : 0.0, xr);
     acc = raxpy(acc, (f & 4u) ? t : 0.0, xv);
     return two_minus(acc, q);
-}
-
-// Row accesses of the register tiles: one buffer resource per row (a
-// wave-uniform base and the row's byte size, so out-of-row offsets read 0 and
-// drop stores) and the lane's byte offset in the row, shared by all rows.
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-constexpr int kBufWord3 = 0x00020000;     // raw 32-bit access, gfx9 buffer resource
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *base, uint32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, kBufWord3);
-}
-__device__ __forceinline__ double2 buf_ld(const double2 *row, uint32_t bytes, uint32_t off) {
-    const d2v v = __builtin_bit_cast(
-        d2v, __builtin_amdgcn_raw_buffer_load_b128(row_rsrc(row, bytes), (int)off, 0, 0));
-    return make_double2(v.x, v.y);
-}
-__device__ __forceinline__ double2 buf_ld(const float2 *row, uint32_t bytes, uint32_t off) {
-    const f2v v = __builtin_bit_cast(
-        f2v, __builtin_amdgcn_raw_buffer_load_b64(row_rsrc(row, bytes), (int)off, 0, 0));
-    return make_double2((double)v.x, (double)v.y);
-}
-__device__ __forceinline__ void buf_st(double2 *row, uint32_t bytes, uint32_t off, double2 x) {
-    d2v v;
-    v.x = x.x;
-    v.y = x.y;
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), row_rsrc(row, bytes),
-                                           (int)off, 0, 0);
-}
-__device__ __forceinline__ void buf_st(float2 *row, uint32_t bytes, uint32_t off, double2 x) {
-    f2v v;
-    v.x = (float)x.x;
-    v.y = (float)x.y;
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), row_rsrc(row, bytes),
-                                          (int)off, 0, 0);
 }
 
 template <typename V, bool ONSF, bool DBL, int TJ, int K>
@@ -1199,18 +1085,7 @@ __global__ __launch_bounds__(kBlock) void k_moment_stepk(Ell h, Sweep sw, Lat2 l
 // the wait before each use leaves the later rows' loads in flight.  A zero
 // weight adds an exact zero, so each state value is the one k_moment_step
 // computes.
-constexpr int kStateRing = 6;
-constexpr int kRowRing = kMarchRows;
-constexpr int kDs = 3;
-constexpr uint32_t kOffNone = 0x80000000u;   // past the end of every row
 
-// MODE: kMarchDirect (moments <phi_L|phi_{n+s}>), kMarchDirectRe (their real
-// parts only, for callers that use no more: the same real parts, bit for
-// bit), kMarchDoubled (the two doubling sums per level, phi_L unused) or
-// kMarchBessel (the propagator's accumulator: lacc holds acc, updated acc +=
-// c_{n+s} phi_{n+s} at each level in step order and stored after level K; no
-// inner products).
-constexpr int kMarchDirect = 0, kMarchDoubled = 1, kMarchBessel = 2, kMarchDirectRe = 3;
 
 template <typename V, bool ONSF, int MODE, int K>
 __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const Lat2 &lat,
@@ -1241,7 +1116,7 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
     const double t = sw.one.t, inv_es = sw.one.inv_es;
     // per pattern: (previous column, next column), (next chain, previous chain)
     __shared__ double2 lwt[2 * kMaxPatterns];
-    for (int j = threadIdx.x; j < h.npat; j += kBlock) {
+    for (int j = threadIdx.x; j < h.npat; j += (int)blockDim.x) {
         const uint32_t f = lat.flags[j];
         const double tv = (f & 4u) ? t : 0.0;
         lwt[2 * j] = make_double2((f & 1u) ? t : 0.0, (f & 2u) ? t : 0.0);
@@ -1255,10 +1130,10 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
     const int lb = blockIdx.x;
     const int per = (ntile + kXcds - 1) / kXcds;
     const int b0 = (lb % kXcds) * per, b1 = min(b0 + per, ntile);
-    constexpr int kWaves = kBlock / kWave;
+    const int nwv = (int)blockDim.x / kWave;          // wavefronts per group
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    const int wloc = (lb / kXcds) * kWaves + wv;
-    const int wn = (sw.nwg / kXcds) * kWaves;
+    const int wloc = (lb / kXcds) * nwv + wv;
+    const int wn = (sw.nwg / kXcds) * nwv;
     double2 acc[NA];
 #pragma unroll
     for (int k = 0; k < NA; ++k) acc[k] = make_double2(0.0, 0.0);
@@ -1416,12 +1291,12 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
     if (BES) return;
     const int nw = sw.nwg;
 #pragma unroll
-    for (int k = 0; k < NA; ++k) block_sum(acc[k], 0, partial + part_index(sw, slot + k));
+    for (int k = 0; k < NA; ++k) block_sum_waves(acc[k], partial + part_index(sw, slot + k));
     (void)nw;
 }
 
 template <typename V, bool ONSF, bool DBL, int K>
-__global__ __launch_bounds__(kBlock, 2) void k_moment_march(Ell h, Sweep sw, Lat2 lat,
+__global__ __launch_bounds__(kMaxStripBlock, 1) void k_moment_march(Ell h, Sweep sw, Lat2 lat,
                                                          const V *p1, const V *p0,
                                                          V *__restrict__ out1,
                                                          V *__restrict__ out2,
@@ -1434,7 +1309,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_moment_march(Ell h, Sweep sw, Lat
 
 // k_moment_march's direct form accumulating only Re <phi_L|phi_{n+s}>.
 template <typename V, bool ONSF, int K>
-__global__ __launch_bounds__(kBlock, 2) void k_moment_march_re(Ell h, Sweep sw, Lat2 lat,
+__global__ __launch_bounds__(kMaxStripBlock, 1) void k_moment_march_re(Ell h, Sweep sw, Lat2 lat,
                                                             const V *p1, const V *p0,
                                                             V *__restrict__ out1,
                                                             V *__restrict__ out2,
@@ -1448,7 +1323,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_moment_march_re(Ell h, Sweep sw, 
 // K steps of the Chebyshev-Bessel propagator (Alg. 6) per pass: the states as
 // in k_moment_march, and acc += c_m phi_m for the K new states, c_m = ck.c[m - n - 1].
 template <typename V, bool ONSF, int K>
-__global__ __launch_bounds__(kBlock, 2) void k_evolve_march(Ell h, Sweep sw, Lat2 lat,
+__global__ __launch_bounds__(kMaxStripBlock, 1) void k_evolve_march(Ell h, Sweep sw, Lat2 lat,
                                                          const V *p1, const V *p0,
                                                          V *__restrict__ out1,
                                                          V *__restrict__ out2,
@@ -1612,6 +1487,10 @@ bool launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
         return false;
     // vector-major states run only in the marching strips
     if (sw.nplanes > 1 && lat.reg != 2) return false;
+    if constexpr (std::is_same<V, float2>::value)
+        if (lat.arith32 && lat.reg == 2)
+            return launch_moment_multi_f32(h, sw, lat, p1, p0, out1, out2, phil, partial, slot,
+                                           dbl, re, s);
 #define KPM_LDS2(NT_, ONSF_, DBL_)                                                            \
     hipLaunchKernelGGL((k_moment_step2<V, NT_, ONSF_, DBL_, 16>), dim3(sw.nwg), dim3(kBlock),  \
                        0, s, h, sw, lat, p1, p0, out1, out2, phil, partial, slot)
@@ -1627,11 +1506,11 @@ bool launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
 #define KPM_MARCHK(ONSF_, DBL_, K_)                                                          \
     do {                                                                                      \
         if (!(DBL_) && re)                                                                    \
-            hipLaunchKernelGGL((k_moment_march_re<V, ONSF_, K_>), dim3(sw.nwg, sw.nplanes), dim3(kBlock),  \
+            hipLaunchKernelGGL((k_moment_march_re<V, ONSF_, K_>), dim3(sw.nwg, sw.nplanes), dim3(sw.wpg * kWave),  \
                                0, s, h, sw, lat, p1, p0, out1, out2, phil, partial, slot);    \
         else                                                                                  \
             hipLaunchKernelGGL((k_moment_march<V, ONSF_, DBL_, K_>), dim3(sw.nwg, sw.nplanes),            \
-                               dim3(kBlock), 0, s, h, sw, lat, p1, p0, out1, out2, phil,      \
+                               dim3(sw.wpg * kWave), 0, s, h, sw, lat, p1, p0, out1, out2, phil,      \
                                partial, slot);                                                \
     } while (0)
 #define KPM_REG(ONSF_, DBL_)                                                                  \
@@ -1673,8 +1552,10 @@ bool launch_evolve_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
                          const V *p0, V *out1, V *out2, V *acc, const CoefK &ck,
                          hipStream_t s) {
     if (lat.reg != 2 || lat.k < 2 || lat.k > kMaxMarchSteps) return false;
+    if constexpr (std::is_same<V, float2>::value)
+        if (lat.arith32) return launch_evolve_multi_f32(h, sw, lat, p1, p0, out1, out2, acc, ck, s);
 #define KPM_EVK(ONSF_, K_)                                                                    \
-    hipLaunchKernelGGL((k_evolve_march<V, ONSF_, K_>), dim3(sw.nwg, sw.nplanes), dim3(kBlock), 0, s, h,   \
+    hipLaunchKernelGGL((k_evolve_march<V, ONSF_, K_>), dim3(sw.nwg, sw.nplanes), dim3(sw.wpg * kWave), 0, s, h,   \
                        sw, lat, p1, p0, out1, out2, acc, ck)
 #define KPM_EV(ONSF_)                                                                         \
     switch (lat.k) {                                                                          \
@@ -1774,10 +1655,12 @@ __global__ __launch_bounds__(kBlock, 2) void k_evolve_x_march(
     const int lb = blockIdx.x;
     const int per = (ntile + kXcds - 1) / kXcds;
     const int b0 = (lb % kXcds) * per, b1 = min(b0 + per, ntile);
-    constexpr int kWaves = kBlock / kWave;
+    // work-groups of kBlock threads (a run-time group size costs this kernel,
+    // at the edge of its registers, spills)
+    constexpr int nwv = kBlock / kWave;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    const int wloc = (lb / kXcds) * kWaves + wv;
-    const int wn = (sw.nwg / kXcds) * kWaves;
+    const int wloc = (lb / kXcds) * nwv + wv;
+    const int wn = (sw.nwg / kXcds) * nwv;
     for (int b = b0 + wloc; b < b1; b += wn) {
         const int strip = b % nst;
         const int j0 = (b / nst) * J, c0 = strip * TC;

@@ -4,7 +4,7 @@ Every computation runs in libkpm.so.  PyTorch provides device memory (state
 tensors) and the stream: each call runs on torch's current HIP stream.
 
 States are torch tensors on the GPU of shape [n_sites, n_vec] and dtype
-complex128 (KPM_FP64 systems) or complex64 (KPM_FP32_STATES systems), or the
+complex128 (KPM_FP64 systems) or complex64 (KPM_FP32_STATES and KPM_FP32 systems), or the
 equivalent real view [n_sites, n_vec, 2]; n_vec is a power of two <= 64.
 """
 from __future__ import annotations
@@ -18,7 +18,10 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libkpm.so")
 
 KPM_OK, KPM_ERR_INVALID, KPM_ERR_OOM, KPM_ERR_DEVICE, KPM_ERR_UNSUPPORTED, KPM_ERR_NUMERIC = range(6)
-KPM_FP64, KPM_FP32_STATES = 0, 1
+KPM_FP64, KPM_FP32_STATES, KPM_FP32 = 0, 1, 2
+# precision names of the binding: FP64 states; FP32 states (FP64 arithmetic);
+# FP32 states with the strips' recursion arithmetic in FP32
+PRECISIONS = {"fp64": KPM_FP64, "fp32": KPM_FP32_STATES, "fp32_arith": KPM_FP32}
 GEOMETRIES = {"sheet": 0, "zgnr": 1, "agnr": 2}
 HBAR_EV_FS = 0.6582119569
 BOND_NM = 0.142
@@ -39,7 +42,7 @@ ABI_SYMBOLS = ("kpm_build_graphene", "kpm_validate", "kpm_system_create", "kpm_s
                "kpm_xu_state", "kpm_vac_continue", "kpm_msd_continue",
                "kpm_default_launch", "kpm_set_launch", "kpm_get_launch", "kpm_set_launch_doubled",
                "kpm_get_launch_doubled",
-               "kpm_autotune", "kpm_set_graphs", "kpm_set_timing", "kpm_get_stats",
+               "kpm_autotune", "kpm_autotune_candidates", "kpm_set_graphs", "kpm_set_timing", "kpm_get_stats",
                "kpm_reset_stats",
                "kpm_last_error", "kpm_version")
 
@@ -61,7 +64,8 @@ class _Desc(C.Structure):
 class Launch(C.Structure):
     _fields_ = [("groups_per_cu", C.c_int32), ("ilp", C.c_int32), ("streaming", C.c_int32),
                 ("compact", C.c_int32), ("tiled", C.c_int32), ("steps", C.c_int32),
-                ("vectors_per_wave", C.c_int32), ("plane_groups", C.c_int32)]
+                ("vectors_per_wave", C.c_int32), ("plane_groups", C.c_int32),
+                ("group_size", C.c_int32)]
 
     def as_dict(self) -> dict:
         """The shape's fields; the two vector-layout fields only when set."""
@@ -69,6 +73,8 @@ class Launch(C.Structure):
                  compact=self.compact, tiled=self.tiled, steps=self.steps)
         if self.vectors_per_wave or self.plane_groups:
             d.update(vectors_per_wave=self.vectors_per_wave, plane_groups=self.plane_groups)
+        if self.group_size:
+            d.update(group_size=self.group_size)
         return d
 
 
@@ -143,6 +149,8 @@ def _signatures():
         "kpm_set_launch_doubled": [vp, C.c_int, C.POINTER(Launch)],
         "kpm_get_launch_doubled": [vp, C.c_int, C.POINTER(Launch)],
         "kpm_autotune": [vp, C.c_int, vp, C.c_int, C.POINTER(Launch)],
+        "kpm_autotune_candidates": [vp, C.c_int, C.POINTER(Launch), C.c_int32,
+                                    C.POINTER(C.c_int32)],
         "kpm_set_graphs": [vp, C.c_int],
         "kpm_set_timing": [vp, C.c_int],
         "kpm_get_stats": [vp, C.POINTER(Stats)],
@@ -405,7 +413,9 @@ class System:
         self.e_scale = float(descs[0].e_scale)
         self.device = torch.cuda.current_device() if device is None else int(device)
         self._h = C.c_void_p()
-        prec = KPM_FP64 if precision == "fp64" else KPM_FP32_STATES
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        prec = PRECISIONS[precision]
         arr = (_Desc * len(descs))(*descs)
         with torch.cuda.device(self.device):
             _check(lib().kpm_batch_create(len(descs), arr, prec, self.device, _stream(),
@@ -601,20 +611,20 @@ def kpm_msd_continue(sys: System, psi, y, start: bool, n_steps: int, dt_fs: floa
 
 def kpm_set_launch(sys: System, n_vec: int, groups_per_cu: int, ilp: int, streaming: int = 0,
                    compact: int = 1, tiled: int = 0, steps: int = 1, vectors_per_wave: int = 0,
-                   plane_groups: int = 0):
+                   plane_groups: int = 0, group_size: int = 0):
     """Launch shape of the moment step for n_vec vectors (see kpm_launch in kpm.h)."""
     _check(lib().kpm_set_launch(sys.handle, n_vec,
                                 C.byref(Launch(groups_per_cu, ilp, int(bool(streaming)),
                                                int(bool(compact)), int(tiled), int(steps),
-                                               int(vectors_per_wave), int(plane_groups)))))
+                                               int(vectors_per_wave), int(plane_groups),
+                                               int(group_size)))))
 
 
 def kpm_default_launch(n_vec: int, precision: str = "fp64") -> dict:
     """Launch shape a new system starts with (environment overrides applied);
     host only."""
     out = Launch()
-    prec = KPM_FP64 if precision == "fp64" else KPM_FP32_STATES
-    _check(lib().kpm_default_launch(n_vec, prec, C.byref(out)))
+    _check(lib().kpm_default_launch(n_vec, PRECISIONS[precision], C.byref(out)))
     return out.as_dict()
 
 
@@ -626,13 +636,13 @@ def kpm_get_launch(sys: System, n_vec: int) -> dict:
 
 def kpm_set_launch_doubled(sys: System, n_vec: int, groups_per_cu: int, ilp: int,
                            streaming: int = 0, compact: int = 1, tiled: int = 0, steps: int = 1,
-                           vectors_per_wave: int = 0, plane_groups: int = 0):
+                           vectors_per_wave: int = 0, plane_groups: int = 0, group_size: int = 0):
     """Launch shape of doubling-form moment sets (kpm_set_launch sets both forms)."""
     _check(lib().kpm_set_launch_doubled(sys.handle, n_vec,
                                         C.byref(Launch(groups_per_cu, ilp, int(bool(streaming)),
                                                        int(bool(compact)), int(tiled),
                                                        int(steps), int(vectors_per_wave),
-                                                       int(plane_groups)))))
+                                                       int(plane_groups), int(group_size)))))
 
 
 def kpm_get_launch_doubled(sys: System, n_vec: int) -> dict:
@@ -648,6 +658,15 @@ def kpm_autotune(sys: System, phi, reps: int = 10) -> dict:
     sys._sync_stream()
     _check(lib().kpm_autotune(sys.handle, nv, p, reps, C.byref(out)))
     return out.as_dict()
+
+
+def kpm_autotune_candidates(sys: System, n_vec: int) -> list:
+    """The launch shapes kpm_autotune times for n_vec vectors on this system."""
+    cnt = C.c_int32()
+    _check(lib().kpm_autotune_candidates(sys.handle, n_vec, None, 0, C.byref(cnt)))
+    arr = (Launch * max(cnt.value, 1))()
+    _check(lib().kpm_autotune_candidates(sys.handle, n_vec, arr, cnt.value, C.byref(cnt)))
+    return [arr[q].as_dict() for q in range(cnt.value)]
 
 
 def kpm_set_graphs(sys: System, enable: bool = True):

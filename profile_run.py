@@ -37,6 +37,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 KERNEL_SRC = os.path.join(ROOT, "paper_1307_0288_amd", "csrc", "kpm_kernels.hip")
+DEVICE_SRC = os.path.join(ROOT, "paper_1307_0288_amd", "csrc", "kpm_device.h")
+MARCH32_SRC = os.path.join(ROOT, "paper_1307_0288_amd", "csrc", "kpm_march32.hip")
+
+
+def _read(path: str) -> str:
+    with open(path) as f:
+        return f.read()
 
 
 def multi_step(launch: dict, n_vec: int = 1) -> bool:
@@ -58,7 +65,7 @@ def float_onsite(onsite) -> bool:
 
 
 def moment_kernel_name(v: str, launch: dict, dbl: bool, n_vec: int = 1,
-                       real: bool = False, onsf: bool = True) -> str:
+                       real: bool = False, onsf: bool = True, arith32: bool = False) -> str:
     """Instantiation of the moment step for a graphene system from the builder
     (width 3, uniform hopping, at least 24 chains) under a launch shape; onsf:
     on-site terms stored as floats (float_onsite) or doubles; real: the moment
@@ -68,6 +75,10 @@ def moment_kernel_name(v: str, launch: dict, dbl: bool, n_vec: int = 1,
     of = "true" if onsf else "false"
     if multi_step(launch, n_vec):
         k, tiled = launch["steps"], launch["tiled"]
+        if arith32 and tiled >= 3:          # FP32 recursion arithmetic in the strips
+            if real and not dbl:
+                return f"k_moment_march_re_f32<{of},{k}>"
+            return f"k_moment_march_f32<{of},{db},{k}>"
         if k == 2 and tiled == 0:
             return f"k_moment_step2<{v},{nt},{of},{db},16>"
         if tiled >= 3 and real and not dbl:
@@ -87,6 +98,8 @@ def kernel_sha(launch: dict | None = None) -> str:
     plus the launchers (edits elsewhere in the file change neither)."""
     with open(KERNEL_SRC) as f:
         t = f.read()
+    with open(DEVICE_SRC) as f:          # the helpers every kernel file shares
+        t = f.read() + t
     head = t[:t.index("// Loads and stores of the propagator kernels")]
     if launch is not None and multi_step(launch):
         # LDS tiles | register tiles (and the helpers the marching form uses) |
@@ -99,7 +112,7 @@ def kernel_sha(launch: dict | None = None) -> str:
         d = t.index("#define KPM_INSTANTIATE(V)")
         k, tiled = launch["steps"], launch["tiled"]
         body = (t[lds:reg] if (k == 2 and tiled == 0) else
-                t[reg:end] if tiled >= 3 else t[reg:march])
+                t[reg:end] + _read(MARCH32_SRC) if tiled >= 3 else t[reg:march])
         return hashlib.sha256((head + body + t[c:d]).encode()).hexdigest()[:16]
     a = t.index("template <typename V, int ILP, bool NT, bool DBL>\nstatic void launch_step_shape(")
     b = t.index("template <typename V>\nvoid launch_evolve_step(")
@@ -253,7 +266,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--moments", type=int, default=40)
     ap.add_argument("--n-vec", type=int, default=1)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp32_arith"])
     ap.add_argument("--doubled", action="store_true", help="doubling form (kpm_moments_doubled)")
     ap.add_argument("--real", action="store_true",
                     help="a real-part moment set as the VAC takes them (kpm_vac, no time steps: "
@@ -261,7 +274,8 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=512)
     ap.add_argument("--copies", type=int, default=3)
     ap.add_argument("--launch", default="",
-                    help="groups_per_cu,ilp,streaming,compact[,tiled] (default: the library's)")
+                    help="groups_per_cu,ilp,streaming,compact[,tiled[,steps[,vectors_per_wave"
+                         "[,plane_groups]]]] (default: the library's)")
     ap.add_argument("--autotune", type=int, default=0,
                     help="run kpm_autotune with this many repetitions first (the benchmark's "
                          "choice of shape)")
@@ -332,7 +346,7 @@ def main():
         if args.autotune:
             cmd.append(f"--autotune {args.autotune}")
         meta = {
-            "kernel": f"{moment_kernel_name(v, launch, args.doubled, args.n_vec, args.real, onsf)} "
+            "kernel": f"{moment_kernel_name(v, launch, args.doubled, args.n_vec, args.real, onsf, args.precision == 'fp32_arith')} "
                       f"({args.precision}, {args.n_vec} vector(s))",
             "kernel_sha": kernel_sha(launch),
             "step_rows": st["step_rows"],

@@ -253,3 +253,99 @@ def test_default_shape_for_several_vectors():
     for n_vec in (2, 8, 64):
         assert kp.kpm_get_launch(sysg, n_vec) == planar(8, max(16, 1024 // n_vec))
     sysg.close()
+
+
+@pytest.mark.parametrize("n_vec", [1, 8])
+def test_fp32_arithmetic_strips(n_vec):
+    """Precision fp32_arith (KPM_FP32): FP32 states with the strips' recursion
+    levels in FP32 registers.  Moments, the propagator and the VAC / MSD loops
+    agree with the FP32-states path (FP64 arithmetic) and with the oracle to
+    single-precision rounding."""
+    _need_gpu()
+    c = recipe("sheet", 200, 38, w=1.0, vac=0.02, seed=79)
+    s64 = gpu_system(c, "fp32")
+    s32 = gpu_system(c, "fp32_arith")
+    if n_vec > 1:
+        for s in (s64, s32):
+            kp.kpm_set_launch(s, n_vec, **planar(8, 0))
+    phi = phases(c, n_vec, 7100)
+    lat = oracle_lattice(c)
+    scale = float(np.max(np.sum(np.abs(phi) ** 2, axis=0)))
+    d = s32.upload(phi)
+    got = kp.kpm_moments(s32, d, d, 150)
+    assert rel_err(got, kp.kpm_moments(s64, d, d, 150), scale) < 1e-5
+    ref = oracle.moments(lat, c["e_scale"], phi[:, 0], phi[:, 0], 150)
+    assert rel_err(got[0], ref, scale) < 1e-4
+    dbl = kp.kpm_moments_doubled(s32, d, 150)
+    assert rel_err(dbl[0], ref, scale) < 1e-4
+    e = s32.upload(phi)
+    kp.kpm_evolve(s32, e, 1.0, 1, 40)
+    ru = oracle.evolve(lat, c["e_scale"], phi[:, 0], 1.0, 1, 40)
+    assert rel_err(e.cpu().numpy()[:, 0], ru) < 1e-5
+    for fn, ofn in ((kp.kpm_vac, oracle.vac), (kp.kpm_msd, oracle.msd)):
+        g = fn(s32, d, 2, 0.5, 20, 61)
+        r = ofn(lat, c["e_scale"], phi[:, 0], 2, 0.5, 20, 61)
+        assert rel_err(g[0], r) < 1e-4
+    s32.close()
+    s64.close()
+
+
+@pytest.mark.parametrize("n_vec,precision", [(1, "fp64"), (8, "fp64"), (8, "fp32_arith")])
+@pytest.mark.parametrize("group_size", [64, 128, 512])
+def test_strip_group_sizes(n_vec, precision, group_size):
+    """Strips in work-groups of 64, 128 and 512 threads: each wavefront walks
+    its own strips, so propagated states equal the 256-thread groups' bit for
+    bit and moments differ only in the order of the group partial sums."""
+    _need_gpu()
+    c = recipe("zgnr", 200, 30, w=1.0, vac=0.02, seed=83)
+    base, other = gpu_system(c, precision), gpu_system(c, precision)
+    g = 2 * 256 // group_size
+    if n_vec == 1:
+        kp.kpm_set_launch(base, 1, 2, 1, 0, 1, 5, 8)
+        kp.kpm_set_launch(other, 1, g, 1, 0, 1, 5, 8, 0, 0, group_size)
+    else:
+        kp.kpm_set_launch(base, n_vec, **planar(8, 16))
+        kp.kpm_set_launch(other, n_vec, **dict(planar(8, 16 * 256 // group_size), groups_per_cu=g,
+                                               group_size=group_size))
+    _log(f"group size {group_size}, n_vec={n_vec}, {precision}: {kp.kpm_get_launch(other, n_vec)}")
+    phi = phases(c, n_vec, 7200)
+    d = base.upload(phi)
+    scale = float(np.max(np.sum(np.abs(phi) ** 2, axis=0)))
+    m1, m2 = kp.kpm_moments(base, d, d, 130), kp.kpm_moments(other, d, d, 130)
+    assert rel_err(m2, m1, scale) < 1e-13
+    if precision == "fp64":
+        ref = oracle.moments(oracle_lattice(c), c["e_scale"], phi[:, 0], phi[:, 0], 130)
+        assert rel_err(m2[0], ref, scale) < 1e-10
+    e1, e2 = base.upload(phi), other.upload(phi)
+    kp.kpm_evolve(base, e1, 1.0, -1, 40)
+    kp.kpm_evolve(other, e2, 1.0, -1, 40)
+    assert np.array_equal(e2.cpu().numpy(), e1.cpu().numpy())
+    v1 = kp.kpm_vac(base, d, 2, 0.5, 20, 41)
+    v2 = kp.kpm_vac(other, d, 2, 0.5, 20, 41)
+    assert rel_err(v2, v1) < 1e-12
+    base.close()
+    other.close()
+
+
+@pytest.mark.parametrize("n_vec", [1, 8])
+def test_autotuner_axes(n_vec):
+    """The autotuner's candidates cover work-group sizes 64 .. 512 and, for
+    several vectors, both lane layouts (every vector of a row in adjacent lanes,
+    one vector per wavefront); the shape it keeps gives the oracle's moments."""
+    _need_gpu()
+    c = recipe("sheet", 400, 96, w=1.0, vac=0.02, seed=89)
+    sysg = gpu_system(c)
+    cand = kp.kpm_autotune_candidates(sysg, n_vec)
+    sizes = {cd.get("group_size", 0) or 256 for cd in cand}
+    assert {64, 128, 256, 512} <= sizes
+    layouts = {cd.get("vectors_per_wave", 0) for cd in cand}
+    assert layouts == ({0, 1} if n_vec > 1 else {0})
+    phi = phases(c, n_vec, 7300)
+    d = sysg.upload(phi)
+    best = kp.kpm_autotune(sysg, d, 16)
+    _log(f"autotuned {n_vec} vector(s): {best}")
+    assert best in cand or best == kp.kpm_get_launch(sysg, n_vec)
+    got = kp.kpm_moments(sysg, d, d, 90)
+    ref = oracle.moments(oracle_lattice(c), c["e_scale"], phi[:, -1], phi[:, -1], 90)
+    assert rel_err(got[-1], ref, np.vdot(phi[:, -1], phi[:, -1]).real) < 1e-10
+    sysg.close()
