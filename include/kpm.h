@@ -258,6 +258,19 @@ kpm_status kpm_msd(kpm_system *sys, int n_vec, const void *phi, int n_steps,
                    double dt_fs, int n_bessel, int n_moments, double *out);
 
 /*
+ * kpm_vac and kpm_msd of the same phi in one call (Alg. 2 and 3): vac_out and
+ * msd_out as the two calls give them, up to the order of the inner-product
+ * sums.  With one vector on a one-sample lattice whose moment sets take the
+ * marching strips, both loops advance together and at every t_k > 0 the two
+ * moment sets run as two vector planes of one launch sequence (half the
+ * one-vector grid per plane: longer strips, half the launches); otherwise the
+ * loops run one after the other.  Host outputs [n_vec][n_steps+1][n_moments]
+ * each.  Synchronises the stream.
+ */
+kpm_status kpm_vac_msd(kpm_system *sys, int n_vec, const void *phi, int n_steps, double dt_fs,
+                       int n_bessel, int n_moments, double *vac_out, double *msd_out);
+
+/*
  * kpm_msd with the moments of each [X, U(t_k)] phi taken in the doubling form
  * of kpm_moments_doubled (the bra and ket of Eq. 44 are the same state).  Same
  * arguments and output.

@@ -335,14 +335,16 @@ struct kpm_system {
     hipStream_t cap = nullptr;
     struct GraphKey {
         const void *phil, *phir, *a, *b, *partial, *dmom;
-        int nm, vshift, groups, ilp, streaming, compact, tiled, steps, dbl, re;
+        // planes and groups of the sweep as run (layout and plane grid), strip group size
+        int nm, vshift, groups, ilp, streaming, compact, tiled, steps, dbl, re, planes, nwg, gs;
         int64_t stride_r, offset;
         bool operator==(const GraphKey &o) const {
             return phil == o.phil && phir == o.phir && a == o.a && b == o.b &&
                    partial == o.partial && dmom == o.dmom && nm == o.nm && vshift == o.vshift &&
                    groups == o.groups && ilp == o.ilp && streaming == o.streaming &&
                    compact == o.compact && tiled == o.tiled && steps == o.steps &&
-                   dbl == o.dbl && re == o.re &&
+                   dbl == o.dbl && re == o.re && planes == o.planes && nwg == o.nwg &&
+                   gs == o.gs &&
                    stride_r == o.stride_r &&
                    offset == o.offset;
         }
@@ -820,11 +822,10 @@ kpm::Sweep reduce_sweep(const kpm::Sweep &sw) {
 // a_buf, b_buf (and x0_buf, x1_buf for multi-step launches); group partials
 // go to `partial`, the reduced moments to `dmom`; phir is only read.
 template <typename V>
-kpm_status enqueue_moments(kpm_system *sys, const kpm::Sweep &sw, int ring, hipStream_t s,
-                           bool events, bool dbl, bool re, const V *phil, const V *phir, int nm,
-                           V *a_buf, V *b_buf, V *x0_buf, V *x1_buf, double2 *partial,
-                           double2 *dmom, int64_t stride_r, int64_t offset) {
-    const kpm_launch &l = sys->shape(sw.vshift, dbl);
+kpm_status enqueue_moments(kpm_system *sys, const kpm_launch &l, const kpm::Sweep &sw, int ring,
+                           hipStream_t s, bool events, bool dbl, bool re, const V *phil,
+                           const V *phir, int nm, V *a_buf, V *b_buf, V *x0_buf, V *x1_buf,
+                           double2 *partial, double2 *dmom, int64_t stride_r, int64_t offset) {
     const kpm::Ell h = sys->ell_for(l);
     const int k = sys->multi_steps(sw.vshift, l);
     const kpm::Lat2 lat = sys->lat2(l, k, sw.nwg);
@@ -905,10 +906,11 @@ kpm_status enqueue_moments(kpm_system *sys, const kpm::Sweep &sw, int ring, hipS
 template <typename V>
 kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir, int nm,
                        V *a_buf, V *b_buf, int64_t stride_r, int64_t offset, bool dbl = false,
-                       bool re = false) {
-    const kpm_launch &l = sys->shape(vshift, dbl);
+                       bool re = false, const kpm_launch *planes = nullptr) {
+    // planes: run the 2^vshift vectors as vector-major planes under this shape
+    const kpm_launch &l = planes ? *planes : sys->shape(vshift, dbl);
     kpm::Sweep sw;
-    KPM_TRY(sys->sweep_for(vshift, l, &sw));
+    KPM_TRY(planes ? sys->sweep_planes(vshift, l, &sw) : sys->sweep_for(vshift, l, &sw));
     const int k = sys->multi_steps(sw.vshift, l);
     if (k > 1) KPM_TRY(sys->ensure_xbuf(vshift));
     // Group partials live in a ring of moment slots that is reduced into
@@ -931,17 +933,18 @@ kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir
         sys->stats.step_bytes_total += n1 * b1 + n2 * b2;
     }
     if (!sys->graphs)
-        return enqueue_moments<V>(sys, sw, ring, sys->stream, sys->timing, dbl, re, phil, phir,
+        return enqueue_moments<V>(sys, l, sw, ring, sys->stream, sys->timing, dbl, re, phil, phir,
                                   nm, a_buf, b_buf, (V *)sys->xbuf[0], (V *)sys->xbuf[1],
                                   sys->partial, sys->dmom, stride_r, offset);
     kpm_system::GraphKey key{phil, phir, a_buf, b_buf, sys->partial, sys->dmom, nm, vshift,
                              l.groups_per_cu, l.ilp, l.streaming, l.compact, l.tiled, l.steps,
-                             dbl ? 1 : 0, re ? 1 : 0, stride_r, offset};
+                             dbl ? 1 : 0, re ? 1 : 0, sw.nplanes, sw.nwg, l.group_size,
+                             stride_r, offset};
     hipGraphExec_t exec = sys->find_graph(key);
     if (!exec) {
         KPM_TRY(sys->ensure_capture_stream());
         KPM_HIP(hipStreamBeginCapture(sys->cap, hipStreamCaptureModeThreadLocal));
-        kpm_status st = enqueue_moments<V>(sys, sw, ring, sys->cap, false, dbl, re, phil, phir,
+        kpm_status st = enqueue_moments<V>(sys, l, sw, ring, sys->cap, false, dbl, re, phil, phir,
                                            nm, a_buf, b_buf, (V *)sys->xbuf[0],
                                            (V *)sys->xbuf[1], sys->partial, sys->dmom, stride_r,
                                            offset);
@@ -1182,7 +1185,7 @@ kpm_status moments_noalloc_impl(kpm_system *sys, int vshift, const void *phil, c
     sys->stats.step_rows = sw.total;
     sys->stats.step_bytes = k > 1 ? sys->step2_bytes(false) : sys->step_bytes(vshift, false);
     sys->stats.site_updates += (int64_t)std::max(nm - 1, 1) * sw.total;
-    KPM_TRY(enqueue_moments<V>(sys, sw, ring, sys->stream, false, false, false, (const V *)phil,
+    KPM_TRY(enqueue_moments<V>(sys, l, sw, ring, sys->stream, false, false, false, (const V *)phil,
                                (const V *)phir, nm, st[0], st[1], st[2], st[3], partial, dmom,
                                nm, 0));
     return finish_moments(sys, elems, (double2 *)mu, dmom);
@@ -1331,6 +1334,80 @@ kpm_status msd_impl(kpm_system *sys, int vshift, const void *phi, int nsteps, do
     V *psi = (V *)sys->vecs[7], *y = (V *)sys->vecs[8];
     KPM_TRY(stage_in<V>(sys, vshift, phi, psi));
     return msd_run<V>(sys, vshift, psi, y, true, nsteps, dt, np, nm, dbl, out);
+}
+
+// VAC (Alg. 2) and MSD (Alg. 3) of the same phi in one pass over the time
+// steps: both loops advance together and, at every t_k > 0, the VAC moment set
+// <L_k|T_m|R_k> and the MSD set <Y_k|T_m|Y_k> run as the two vector planes of
+// one launch sequence, with half the one-vector grid per plane (so each strip
+// is about twice as long and half as many launches run).  The recursion states
+// are those of vac_run and msd_run, the moments theirs up to the order of the
+// inner-product sums.  One vector on a one-sample lattice whose moment sets take
+// the marching strips; otherwise the two loops run one after the other.
+template <typename V>
+kpm_status vac_msd_impl(kpm_system *sys, int vshift, const void *phi, int nsteps, double dt,
+                        int np, int nm, double *vac_out, double *msd_out) {
+    const kpm_launch &l0 = sys->launch[0];
+    const bool joint = vshift == 0 && sys->nseg == 1 && sys->d_flags && l0.tiled >= 3 &&
+                       sys->multi_steps(0, l0) > 1;
+    if (!joint) {
+        KPM_TRY(vac_impl<V>(sys, vshift, phi, nsteps, dt, np, nm, vac_out));
+        return msd_impl<V>(sys, vshift, phi, nsteps, dt, np, nm, msd_out, false);
+    }
+    kpm::Sweep sw0;
+    KPM_TRY(sys->sweep_with(0, l0, &sw0));
+    // the one-vector shape on two planes, half its work-groups on each
+    kpm_launch l2 = l0;
+    l2.vectors_per_wave = 1;
+    l2.plane_groups = std::max(kpm::kXcds, sw0.nwg / 2 / kpm::kXcds * kpm::kXcds);
+    KPM_TRY(sys->ensure_vecs(19, 1));                 // every scratch state holds two planes
+    auto vec = [&](int i) { return (V *)sys->vecs[i]; };
+    const size_t sb = sys->state_bytes(0);           // one plane
+    V *ma = vec(0), *mb = vec(1), *pl = vec(2), *pr = vec(3);
+    V *a = vec(4), *b = vec(5), *pa = vec(6), *pb = vec(7), *qa = vec(8), *qb = vec(9);
+    V *psi = vec(10), *psi2 = vec(11), *rr = vec(12), *rr2 = vec(13);
+    V *ps = vec(14), *ps2 = vec(15), *y = vec(16), *y2 = vec(17), *xu = vec(18);
+    V *pl1 = (V *)((char *)pl + sb), *pr1 = (V *)((char *)pr + sb);
+    const int64_t per = (int64_t)(nsteps + 1) * nm;
+    const size_t elems = 2 * (size_t)per;            // [VAC, MSD][t_k][m]
+    KPM_TRY(sys->ensure_dmom(elems));
+    hipStream_t s = sys->stream;
+    KPM_HIP(hipMemsetAsync(sys->dmom, 0, elems * sizeof(double2), s));    // MSD(0) = 0
+    const kpm::Ell h = sys->ell_for(l0);
+    const kpm::Coef alpha = sys->alpha();
+    KPM_HIP(hipMemcpyAsync(psi, phi, sb, hipMemcpyDeviceToDevice, s));
+    KPM_HIP(hipMemcpyAsync(ps, phi, sb, hipMemcpyDeviceToDevice, s));
+    // t_0: R_0 = L_0 = V phi, the VAC set alone (Y_0 = 0)
+    kpm::launch_apply_d<V>(h, sw0, psi, rr, alpha, s);
+    KPM_TRY(run_moments<V>(sys, 0, rr, rr, nm, ma, mb, per, 0, false, true));
+    for (int k = 1; k <= nsteps; ++k) {
+        // VAC: psi_k = U(-dt) psi_{k-1}, R_k = U(-dt) R_{k-1}, L_k = V psi_k
+        KPM_TRY(run_evolve<V>(sys, 0, psi, psi2, nullptr, dt, -1, np, a, b));
+        std::swap(psi, psi2);
+        KPM_TRY(run_evolve<V>(sys, 0, rr, rr2, nullptr, dt, -1, np, a, b));
+        std::swap(rr, rr2);
+        kpm::launch_apply_d<V>(h, sw0, psi, pl, alpha, s);
+        KPM_HIP(hipMemcpyAsync(pr, rr, sb, hipMemcpyDeviceToDevice, s));
+        // MSD: [X, U(dt)] psi'_{k-1}, psi'_k = U(dt) psi'_{k-1}, Y_k = U(dt) Y_{k-1} + [X, U(dt)] psi'_{k-1}
+        KPM_TRY(run_evolve_x<V>(sys, 0, ps, xu, ps2, dt, np, pa, pb, qa, qb));
+        std::swap(ps, ps2);
+        if (k == 1) {
+            std::swap(y, xu);
+        } else {
+            KPM_TRY(run_evolve<V>(sys, 0, y, y2, xu, dt, +1, np, pa, pb));
+            std::swap(y, y2);
+        }
+        KPM_HIP(hipMemcpyAsync(pl1, y, sb, hipMemcpyDeviceToDevice, s));
+        KPM_HIP(hipMemcpyAsync(pr1, y, sb, hipMemcpyDeviceToDevice, s));
+        KPM_TRY(run_moments<V>(sys, 1, pl, pr, nm, ma, mb, per, (int64_t)k * nm, false, true, &l2));
+    }
+    std::vector<double2> host(elems);
+    KPM_TRY(finish_moments(sys, host.size(), host.data()));
+    for (int64_t q = 0; q < per; ++q) {
+        vac_out[q] = host[q].x;
+        msd_out[q] = host[per + q].x;
+    }
+    return KPM_OK;
 }
 
 // The resumable loops on the caller's two state buffers: run in place, or
@@ -1925,6 +2002,19 @@ kpm_status kpm_msd(kpm_system *sys, int n_vec, const void *phi, int n_steps, dou
     return sys->prec == KPM_FP64
                ? msd_impl<double2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, out, false)
                : msd_impl<float2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, out, false);
+}
+
+kpm_status kpm_vac_msd(kpm_system *sys, int n_vec, const void *phi, int n_steps, double dt_fs,
+                       int n_bessel, int n_moments, double *vac_out, double *msd_out) {
+    int vs;
+    KPM_TRY(check_loop(sys, n_vec, phi, n_steps, dt_fs, n_bessel, n_moments, vac_out, &vs));
+    if (!msd_out) return fail(KPM_ERR_INVALID, "null buffer");
+    DeviceGuard g(sys->device);
+    return sys->prec == KPM_FP64
+               ? vac_msd_impl<double2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, vac_out,
+                                       msd_out)
+               : vac_msd_impl<float2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, vac_out,
+                                      msd_out);
 }
 
 kpm_status kpm_msd_doubled(kpm_system *sys, int n_vec, const void *phi, int n_steps,

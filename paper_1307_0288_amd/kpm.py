@@ -31,7 +31,7 @@ ABI_SYMBOLS = ("kpm_build_graphene", "kpm_validate", "kpm_system_create", "kpm_s
                "kpm_system_set_stream", "kpm_system_n_sites", "kpm_batch_create",
                "kpm_system_n_samples", "kpm_system_offsets", "kpm_moments",
                "kpm_moments_noalloc", "kpm_moments_doubled", "kpm_evolve", "kpm_evolve_x", "kpm_vac", "kpm_msd",
-               "kpm_msd_doubled", "kpm_fourier_moments", "kpm_ftm_sum",
+               "kpm_msd_doubled", "kpm_vac_msd", "kpm_fourier_moments", "kpm_ftm_sum",
                "kpm_kpm_sum", "kpm_sigma_gk",
                "kpm_sigma_e1", "kpm_sigma_e2", "kpm_length", "kpm_conductance",
                "kpm_ballistic_conductance", "kpm_sigma_sc_max", "kpm_sigma_sc_average",
@@ -111,6 +111,7 @@ def _signatures():
         "kpm_vac": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, C.c_int, dp],
         "kpm_msd": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, C.c_int, dp],
         "kpm_msd_doubled": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, C.c_int, dp],
+        "kpm_vac_msd": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, C.c_int, dp, dp],
         "kpm_kpm_sum": [C.c_int, C.c_int, dp, C.c_int, dp, C.c_double, C.c_double,
                         C.c_int, vp, dp],
         "kpm_fourier_moments": [vp, C.c_int, vp, vp, C.c_int, C.c_double, C.c_int, dp],
@@ -563,6 +564,18 @@ def _loop(fn, sys, phi, n_steps, dt_fs, n_bessel, n_moments):
     sys._sync_stream()
     _check(fn(sys.handle, nv, p, n_steps, dt_fs, n_bessel, n_moments, _dp(out)))
     return sys._shape(out)
+
+
+def kpm_vac_msd(sys: System, phi, n_steps: int, dt_fs: float, n_bessel: int, n_moments: int):
+    """(VAC, MSD) moments of kpm_vac and kpm_msd from one call, each
+    [n_vec, n_steps+1, n_moments]; leading sample axis for a batch."""
+    p, nv = sys._state(phi, "phi")
+    vac = np.empty((sys.n_samples, nv, n_steps + 1, n_moments))
+    msd = np.empty_like(vac)
+    sys._sync_stream()
+    _check(lib().kpm_vac_msd(sys.handle, nv, p, n_steps, dt_fs, n_bessel, n_moments, _dp(vac),
+                             _dp(msd)))
+    return sys._shape(vac), sys._shape(msd)
 
 
 def kpm_vac(sys: System, phi, n_steps: int, dt_fs: float, n_bessel: int, n_moments: int):

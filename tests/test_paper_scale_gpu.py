@@ -100,6 +100,16 @@ def test_msd_all_time_points(paper, loops):
         assert rel_err(gm[k], gold["msd"][k]) < 1e-10, k
 
 
+def test_joint_vac_msd_all_time_points(paper):
+    """kpm_vac_msd (both loops, their moment sets as two planes of one launch
+    sequence) against the stored oracle values."""
+    p, act, phi, gold, sysg, d = paper
+    _log("paper-scale VAC and MSD in one call")
+    gv, gm = kp.kpm_vac_msd(sysg, d, p["n_steps"], p["dt_fs"], p["n_bessel"], p["n_moments"])
+    assert rel_err(gv[0], gold["vac"]) < 1e-10
+    assert rel_err(gm[0], gold["msd"]) < 1e-10
+
+
 def test_msd_doubled_all_time_points(paper):
     p, act, phi, gold, sysg, d = paper
     _log("paper-scale MSD, doubling form")

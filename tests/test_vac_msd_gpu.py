@@ -1,0 +1,72 @@
+"""kpm_vac_msd: the VAC and MSD loops of one state in one call, their moment
+sets at every t_k > 0 run as two vector planes of one launch sequence.  The
+recursion states are those of kpm_vac and kpm_msd, so the moments equal theirs
+up to the order of the inner-product sums, and the oracle's to the parity bar;
+where the joint form does not apply (several vectors, batches, single-step
+shapes) the call runs the two loops one after the other, with identical
+results."""
+import numpy as np
+import pytest
+
+import oracle
+from cases import gpu_system, oracle_lattice, phases, recipe, rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+kp = pytest.importorskip("paper_1307_0288_amd")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_arith"])
+@pytest.mark.parametrize("geometry,nx,ny", [("sheet", 200, 38), ("zgnr", 130, 38)])
+def test_joint_loops_equal_separate_calls_and_oracle(precision, geometry, nx, ny):
+    _need_gpu()
+    c = recipe(geometry, nx, ny, w=1.0, vac=0.02, seed=nx + ny)
+    sysg = gpu_system(c, precision)
+    phi = phases(c, 1, 7500)
+    d = sysg.upload(phi)
+    print(f"[vac_msd] {geometry} {nx}x{ny} {precision} {kp.kpm_get_launch(sysg, 1)}", flush=True)
+    args = (3, 0.5, 20, 97)
+    v2, m2 = kp.kpm_vac_msd(sysg, d, *args)
+    v1, m1 = kp.kpm_vac(sysg, d, *args), kp.kpm_msd(sysg, d, *args)
+    assert v2.shape == m2.shape == (1, 4, 97)
+    assert np.all(m2[0, 0] == 0)
+    assert rel_err(v2, v1) < 1e-12 and rel_err(m2, m1) < 1e-12
+    assert np.array_equal(d.cpu().numpy(), phi.astype(d.cpu().numpy().dtype))
+    if precision == "fp64":
+        lat = oracle_lattice(c)
+        assert rel_err(v2[0], oracle.vac(lat, c["e_scale"], phi[:, 0], *args)) < 1e-10
+        assert rel_err(m2[0], oracle.msd(lat, c["e_scale"], phi[:, 0], *args)) < 1e-10
+    sysg.close()
+
+
+@pytest.mark.parametrize("case", ["two_vectors", "single_steps", "batch"])
+def test_other_shapes_run_the_loops_in_turn(case):
+    _need_gpu()
+    args = (2, 0.5, 20, 61)
+    if case == "batch":
+        import kpm_inputs as ki
+        cases = [recipe("sheet", 96, 30, w=1.0, vac=0.02, seed=60),
+                 recipe("zgnr", 100, 26, w=0.5, seed=61)]
+        sysg = kp.graphene_batch([dict(nx=c["nx"], ny=c["ny"], geometry=c["geometry"],
+                                       onsite=c["onsite"], active=c["active"],
+                                       e_scale=c["e_scale"]) for c in cases], "fp64")
+        phi = np.concatenate([ki.random_phase(c["nx"] * c["ny"], 1, 3000 + 100 * s, c["active"])
+                              for s, c in enumerate(cases)])
+    else:
+        c = recipe("sheet", 200, 38, w=1.0, vac=0.02, seed=63)
+        sysg = gpu_system(c)
+        n_vec = 2 if case == "two_vectors" else 1
+        if case == "single_steps":
+            kp.kpm_set_launch(sysg, 1, 4, 1, 0, 1, 0, 1)
+        phi = phases(c, n_vec, 7600)
+    d = sysg.upload(phi)
+    v2, m2 = kp.kpm_vac_msd(sysg, d, *args)
+    assert np.array_equal(v2, kp.kpm_vac(sysg, d, *args))
+    assert np.array_equal(m2, kp.kpm_msd(sysg, d, *args))
+    sysg.close()
