@@ -481,7 +481,11 @@ kpm_status kpm_xu_state(kpm_system *sys, int n_vec, const void *phi, int n_steps
  * pass instead of once per step.  It applies to one vector per row on a
  * single-sample lattice in the compact width-3 form whose every bond joins
  * rows at most one column and one chain apart (chains of at least 68 rows, at
- * least 24 chains); other calls take single steps.  Two steps run in tiles of
+ * least 24 chains); other calls take single steps.  A batch whose every
+ * sample is such a lattice (with uniform hopping and the builder's slot
+ * order) runs its moment sets in the strips below (tiled >= 3; each
+ * work-group walks strips of its own sample, with that sample's chain length,
+ * strip height and scale); its propagators take single steps.  Two steps run in tiles of
  * 16 chains x 64 columns staged in LDS (tiled = 0) or, where the slots follow
  * the order of kpm_build_graphene, in register tiles of one wavefront each, 8
  * chains (tiled = 1) or 4 (tiled = 2) by 64 - 2 steps columns, or in strips
@@ -499,7 +503,8 @@ kpm_status kpm_xu_state(kpm_system *sys, int n_vec, const void *phi, int n_steps
  * doubling form the strips accumulate only the real parts, the moments of
  * phi_L = phi_R being real).
  *
- * vectors_per_wave selects, for n_vec > 1 on a one-sample system, how a
+ * vectors_per_wave selects, for n_vec > 1 on a one-sample system (or a
+ * batch whose moment sets take the strips), how a
  * wavefront's 64 lanes cover the states: 0 (default) puts the n_vec vectors
  * of a row in adjacent lanes (64 / n_vec rows per wavefront, one structure
  * read per row for all vectors); 1 gives every wavefront one vector: the
@@ -511,9 +516,11 @@ kpm_status kpm_xu_state(kpm_system *sys, int n_vec, const void *phi, int n_steps
  * plane_groups (vectors_per_wave = 1 only) is the number of work-groups per
  * plane, a multiple of 8 up to 65536, or 0 for the grid groups_per_cu gives
  * one vector; fewer groups per plane make the strips of tiled = 5 longer (up
- * to the whole sample), so fewer boundary chains are recomputed.  Batches
- * and n_vec = 1 ignore both fields, and the layout of a call follows the
- * direct form's shape (kpm_set_launch) also for doubling-form moment sets.
+ * to the whole sample), so fewer boundary chains are recomputed.  A batch
+ * shares a plane's groups out among its samples in proportion to their rows
+ * (at least 8 each).  Other batches and n_vec = 1 ignore both fields, and the
+ * layout of a call follows the direct form's shape (kpm_set_launch) also for
+ * doubling-form moment sets.
  *
  * group_size: threads per work-group of the marching strips (64, 128, 256 or
  * 512; 0 = 256).  Each wavefront walks its own strips, so the group size

@@ -48,13 +48,19 @@ def build(verbose: bool = False) -> str:
     def compile_one(src):
         obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [hipcc] + flags() + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        # device code: the compiler's per-kernel resource report (registers,
+        # spills, LDS) goes to _build/<source>.resources
+        report = ["-Rpass-analysis=kernel-resource-usage"] if src.endswith(".hip") else []
+        cmd = [hipcc] + flags() + lang + report + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
-        if verbose and r.stderr.strip():
+        if report:
+            with open(os.path.join(OBJDIR, src + ".resources"), "w") as f:
+                f.write(r.stderr)
+        elif verbose and r.stderr.strip():
             print(r.stderr, flush=True)
         return obj
 
@@ -69,6 +75,30 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
     return LIB
+
+
+def resources(src: str) -> dict:
+    """Per-kernel resources of a device source from the last build: mangled
+    name -> {"VGPRs", "AGPRs", "VGPRs Spill", "ScratchSize", "Occupancy",
+    "LDS"}; empty when the source has not been built here."""
+    import re
+    path = os.path.join(OBJDIR, src + ".resources")
+    if not os.path.exists(path):
+        return {}
+    keys = {"VGPRs": "VGPRs", "AGPRs": "AGPRs", "VGPRs Spill": "VGPRs Spill",
+            "ScratchSize [bytes/lane]": "ScratchSize", "Occupancy [waves/SIMD]": "Occupancy",
+            "LDS Size [bytes/block]": "LDS"}
+    out, cur = {}, None
+    with open(path) as f:
+        for line in f:
+            m = re.search(r"Function Name: (\S+)", line)
+            if m:
+                cur = out.setdefault(m.group(1), {})
+                continue
+            m = re.search(r"remark:\s+([A-Za-z][A-Za-z /\[\]]*?): (\d+)", line)
+            if m and cur is not None and m.group(1) in keys:
+                cur[keys[m.group(1)]] = int(m.group(2))
+    return out
 
 
 if __name__ == "__main__":

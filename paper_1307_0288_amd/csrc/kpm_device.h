@@ -165,4 +165,23 @@ constexpr uint32_t kOffNone = 0x80000000u;   // past the end of every row
 // inner products).
 constexpr int kMarchDirect = 0, kMarchDoubled = 1, kMarchBessel = 2, kMarchDirectRe = 3;
 
+// The sample a work-group of the marching strips sweeps: its first row, chain
+// length nx, chains ny, chains per strip J, the group's index among the
+// sample's nwg groups, and the sample's t / E_s and 1 / E_s (one-sample
+// systems: the lattice geometry and the sweep's single segment; batches: the
+// group's segment, whose strips take one vector per row).
+struct StripGeo {
+    int64_t e0;
+    int nx, ny, J, lb, nwg;
+    double t, inv_es;
+};
+__device__ __forceinline__ StripGeo strip_geo(const Sweep &sw, const Lat2 &lat) {
+    if (!sw.seg)
+        return StripGeo{0, lat.nx, lat.ny, lat.tj, (int)blockIdx.x, sw.nwg, sw.one.t,
+                        sw.one.inv_es};
+    const Seg g = sw.seg[sw.wg_seg[blockIdx.x]];
+    return StripGeo{g.e0, g.snx, (int)((g.e1 - g.e0) / g.snx), g.sj, (int)blockIdx.x - g.g0,
+                    g.nwg, g.t, g.inv_es};
+}
+
 }  // namespace kpm

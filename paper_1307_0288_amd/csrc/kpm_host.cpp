@@ -138,22 +138,29 @@ int32_t chain_length(const std::vector<int32_t> &nbr, int w, int64_t n) {
     return (int32_t)best;
 }
 
-// (chain, column) step codes of the two-step sweep (see kpm::Lat2) for a
-// one-sample system with nx-row chains: for every row, the chain and column
-// distance to each neighbour, -1, 0 or 1 under periodic wrap, must be the same
-// for every row of its pattern.  False when some row breaks this.
-bool lattice_codes(const std::vector<int32_t> &nbr, int w, int64_t n, int64_t nx,
-                   const std::vector<uint8_t> &pid, int npat, std::vector<uint32_t> &code) {
-    if (nx < kpm::kTileCols + 4 || n % nx != 0 || n / nx < 4 || w > 4) return false;
-    const int64_t ny = n / nx;
-    code.assign(npat, 0u);
-    std::vector<uint8_t> seen(npat, 0);
-    for (int64_t r = 0; r < n; ++r) {
+// (chain, column) step codes of the two-step sweep (see kpm::Lat2) for the
+// sample in rows [r0, r1) of a system of n rows, with nx-row chains: for every
+// row, the chain and column distance to each neighbour, -1, 0 or 1 under
+// periodic wrap, must be the same for every row of its pattern, here and in
+// the samples already seen (code and seen carry over from call to call; empty
+// vectors start them).  False when some row breaks this or has a neighbour
+// outside its sample.
+bool lattice_codes(const std::vector<int32_t> &nbr, int w, int64_t n, int64_t r0, int64_t r1,
+                   int64_t nx, const std::vector<uint8_t> &pid, int npat,
+                   std::vector<uint32_t> &code, std::vector<uint8_t> &seen) {
+    const int64_t ns = r1 - r0;
+    if (nx < kpm::kTileCols + 4 || ns % nx != 0 || ns / nx < 4 || w > 4) return false;
+    const int64_t ny = ns / nx;
+    if (code.empty()) code.assign(npat, 0u);
+    if (seen.empty()) seen.assign(npat, 0);
+    for (int64_t r = 0; r < ns; ++r) {
         const int64_t j = r / nx, i = r % nx;
         uint32_t c = 0xFFFFFFFFu;
         for (int k = 0; k < w; ++k) {
-            const int32_t m = nbr[(size_t)k * n + r];
-            if (m < 0) continue;
+            const int32_t mg = nbr[(size_t)k * n + r0 + r];
+            if (mg < 0) continue;
+            if (mg < r0 || mg >= r1) return false;
+            const int64_t m = mg - r0;
             int64_t di = m % nx - i, dj = m / nx - j;
             if (di == nx - 1) di = -1;
             if (di == 1 - nx) di = 1;
@@ -163,13 +170,44 @@ bool lattice_codes(const std::vector<int32_t> &nbr, int w, int64_t n, int64_t nx
             const uint32_t b = (uint32_t)((dj + 1) * 3 + (di + 1));
             c = (c & ~(0xFFu << (8 * k))) | (b << (8 * k));
         }
-        const int p = pid[r];
+        const int p = pid[r0 + r];
         if (!seen[p]) {
             seen[p] = 1;
             code[p] = c;
         } else if (code[p] != c) {
             return false;
         }
+    }
+    return true;
+}
+
+// (chain, column) step codes (as in lattice_codes) of every row of the sample
+// in rows [r0, r1) of a system of n rows with nx-row chains, appended to rc.
+// False when a row has a neighbour outside its sample or more than one chain
+// or column away.
+bool row_codes(const std::vector<int32_t> &nbr, int w, int64_t n, int64_t r0, int64_t r1,
+               int64_t nx, std::vector<uint32_t> &rc) {
+    const int64_t ns = r1 - r0;
+    if (nx < kpm::kTileCols + 4 || ns % nx != 0 || ns / nx < 4 || w > 4) return false;
+    const int64_t ny = ns / nx;
+    for (int64_t r = 0; r < ns; ++r) {
+        const int64_t j = r / nx, i = r % nx;
+        uint32_t c = 0xFFFFFFFFu;
+        for (int k = 0; k < w; ++k) {
+            const int32_t mg = nbr[(size_t)k * n + r0 + r];
+            if (mg < 0) continue;
+            if (mg < r0 || mg >= r1) return false;
+            const int64_t m = mg - r0;
+            int64_t di = m % nx - i, dj = m / nx - j;
+            if (di == nx - 1) di = -1;
+            if (di == 1 - nx) di = 1;
+            if (dj == ny - 1) dj = -1;
+            if (dj == 1 - ny) dj = 1;
+            if (di < -1 || di > 1 || dj < -1 || dj > 1) return false;
+            const uint32_t b = (uint32_t)((dj + 1) * 3 + (di + 1));
+            c = (c & ~(0xFFu << (8 * k))) | (b << (8 * k));
+        }
+        rc.push_back(c);
     }
     return true;
 }
@@ -287,6 +325,12 @@ struct kpm_system {
     int32_t l2nx = 0, l2ny = 0;
     uint32_t *d_code = nullptr;
     uint32_t *d_flags = nullptr;   // graphene slot flags (register tiles), or none
+    // a batch of chain lattices whose moment sets take the marching strips:
+    // per-row strip pattern ids d_sid (nsp distinct (chain, column) step
+    // codes over all samples), d_flags per id; d_code stays unset
+    bool bstrips = false;
+    uint8_t *d_sid = nullptr;
+    int nsp = 0;
     void *xbuf[4] = {nullptr, nullptr, nullptr, nullptr};
     int xbuf_count = 0;
     size_t xbuf_bytes = 0;
@@ -304,7 +348,9 @@ struct kpm_system {
     double2 *d_alpha = nullptr;  // [nseg] velocity prefactor -i E_s / hbar (batches)
     // segment tables per (vshift, requested groups); batches only
     struct SegTab {
-        int vshift, groups, tiled;
+        int vshift;
+        int64_t want;          // groups asked for (all samples)
+        int tiled, ksteps, wpg;// single-step traversal; strip steps and group size
         int nwg;
         kpm::Seg *seg;
         int32_t *wg;
@@ -387,12 +433,41 @@ struct kpm_system {
     // chain lattice, compact form; 3 and 4 steps need the graphene slot order,
     // else 2), 1 otherwise.
     int multi_steps(int vshift, const kpm_launch &l) const {
+        // batches: the marching strips only (their moment sets; the propagators
+        // of a batch take single steps)
+        if (nseg > 1)
+            return bstrips && vshift == 0 && l.steps >= 2 && l.tiled >= 3 ? l.steps : 1;
         // the tiles address a row through a buffer resource of 32-bit byte size,
         // with offsets from 2^31 up as the "no access" offset
         if (!d_code || vshift != 0 || l.steps < 2 || !l.compact || l2ny < kpm::kMinChains ||
             (int64_t)l2nx * (int64_t)sizeof(double2) >= ((int64_t)1 << 31))
             return 1;
         return d_flags ? l.steps : 2;
+    }
+
+    // Chains per marching strip of k steps on an nx x ny chain lattice swept
+    // by `waves` wavefronts: 16 or 32 (tiled = 3, 4), or sized for the grid
+    // (tiled = 5): the fewest loop passes of the wavefront with the most
+    // strips (passes of kMarchRows rows, tj + 2k rows per strip), then the
+    // longest strips (fewer reloaded boundary chains); at least 8 chains, up
+    // to the whole sample when there are few wavefronts per sample
+    // (vector-major states with few groups per plane).
+    static int strip_chains(const kpm_launch &l, int k, int64_t nx, int64_t ny, int64_t waves) {
+        if (l.tiled < 5) return 16 << (l.tiled - 3);
+        const int64_t nst = (nx + kpm::kWave - 2 * k - 1) / (kpm::kWave - 2 * k);
+        int64_t best = -1;
+        int tj = 8;
+        const int jmax = (int)std::max<int64_t>(64, ny);
+        for (int j = 8; j <= jmax; ++j) {
+            const int64_t strips = nst * ((ny + j - 1) / j);
+            const int64_t passes = (j + 2 * k + kpm::kMarchRows - 1) / kpm::kMarchRows;
+            const int64_t cost = (strips + waves - 1) / waves * passes;
+            if (best < 0 || cost <= best) {
+                best = cost;
+                tj = j;
+            }
+        }
+        return tj;
     }
 
     // Multi-step tiles: two steps in LDS tiles of 16 chains x kTileCols
@@ -403,29 +478,12 @@ struct kpm_system {
     kpm::Lat2 lat2(const kpm_launch &l, int k, int nwg) const {
         const int reg = !d_flags ? 0 : (l.tiled >= 3 ? 2 : ((l.tiled >= 1 || k > 2) ? 1 : 0));
         int tj = reg == 2 ? 16 << (l.tiled - 3) : (reg == 1 ? (l.tiled == 2 ? 4 : 8) : 16);
-        if (reg == 2 && l.tiled == 5) {
-            // strips sized for the grid: the fewest loop passes of the wavefront
-            // with the most strips (passes of kMarchRows rows, tj + 2k rows per
-            // strip), then the longest strips (fewer reloaded boundary chains);
-            // at least 8 chains
-            const int64_t nst = (l2nx + kpm::kWave - 2 * k - 1) / (kpm::kWave - 2 * k);
-            const int64_t waves = (int64_t)nwg * strip_waves(l);
-            int64_t best = -1;
-            // up to the whole sample when the grid has few wavefronts per
-            // sample (vector-major states with few groups per plane)
-            const int jmax = std::max<int>(64, l2ny);
-            for (int j = 8; j <= jmax; ++j) {
-                const int64_t strips = nst * ((l2ny + j - 1) / j);
-                const int64_t passes = (j + 2 * k + kpm::kMarchRows - 1) / kpm::kMarchRows;
-                const int64_t cost = (strips + waves - 1) / waves * passes;
-                if (best < 0 || cost <= best) {
-                    best = cost;
-                    tj = j;
-                }
-            }
-        }
+        if (reg == 2 && nseg == 1)
+            tj = strip_chains(l, k, l2nx, l2ny, (int64_t)nwg * strip_waves(l));
+        // (a batch's strips take their geometry from its segment table)
         return kpm::Lat2{l2nx, l2ny, k, reg, tj, (l2nx + kpm::kTileCols - 1) / kpm::kTileCols,
-                         (l2ny + tj - 1) / tj, d_code, d_flags, prec == KPM_FP32 ? 1 : 0};
+                         (l2ny + tj - 1) / tj, d_code, d_flags, prec == KPM_FP32 ? 1 : 0,
+                         d_sid, nsp};
     }
 
     kpm::Ell ell() const {
@@ -467,7 +525,7 @@ struct kpm_system {
     // run of work-groups (a multiple of 8) in proportion to its rows; their
     // device segment table is built on first use (may_alloc), or must exist.
     kpm_status sweep_with(int vshift, const kpm_launch &l, kpm::Sweep *out,
-                          bool may_alloc = true) {
+                          bool may_alloc = true, int64_t want_groups = 0) {
         kpm::Sweep sw{};
         sw.nplanes = 1;
         sw.pstride = 0;
@@ -476,7 +534,9 @@ struct kpm_system {
         sw.vshift = vshift;
         sw.ilp = l.ilp;
         sw.nt = l.streaming;
-        const int64_t want = std::max<int64_t>(kpm::kXcds, ((int64_t)cus * l.groups_per_cu) / kpm::kXcds * kpm::kXcds);
+        const int64_t want = want_groups > 0 ? want_groups
+                             : std::max<int64_t>(kpm::kXcds, ((int64_t)cus * l.groups_per_cu) /
+                                                                 kpm::kXcds * kpm::kXcds);
         // the single-step traversal; under a multi-step shape, tiled selects
         // the multi-step tiles and single steps keep row order
         const int tiled = l.steps == 1 ? l.tiled : 0;
@@ -511,8 +571,12 @@ struct kpm_system {
             *out = sw;
             return KPM_OK;
         }
+        // marching strips of a batch: each sample's chain length and strip
+        // chains for its wavefronts
+        const int ksteps = multi_steps(vshift, l) > 1 ? l.steps : 0;
         for (const SegTab &t : segtabs) {
-            if (t.vshift == vshift && t.groups == l.groups_per_cu && t.tiled == tiled) {
+            if (t.vshift == vshift && t.want == want && t.tiled == tiled && t.ksteps == ksteps &&
+                t.wpg == (ksteps ? sw.wpg : 0)) {
                 sw.nwg = t.nwg;
                 sw.nseg = nseg;
                 sw.seg = t.seg;
@@ -536,13 +600,18 @@ struct kpm_system {
             seg[s] = kpm::Seg{off[s] << vshift, off[s + 1] << vshift, (int32_t)g0,
                               (int32_t)(u * kpm::kXcds), seg_t[s], 1.0 / es[s], tnx, tw, 0, 0};
             divider(s, tnx, seg[s]);
+            if (ksteps) {
+                seg[s].snx = chain[s];
+                seg[s].sj = strip_chains(l, ksteps, chain[s], rows / chain[s],
+                                         u * kpm::kXcds * sw.wpg);
+            }
             g0 += u * kpm::kXcds;
         }
         if (g0 > (1 << 30)) return fail(KPM_ERR_INVALID, "batch needs too many work-groups");
         std::vector<int32_t> wg(g0);
         for (int s = 0; s < nseg; ++s)
             for (int g = 0; g < seg[s].nwg; ++g) wg[seg[s].g0 + g] = s;
-        SegTab t{vshift, l.groups_per_cu, tiled, (int)g0, nullptr, nullptr};
+        SegTab t{vshift, want, tiled, ksteps, ksteps ? sw.wpg : 0, (int)g0, nullptr, nullptr};
         KPM_HIP(hipMalloc(&t.seg, seg.size() * sizeof(kpm::Seg)));
         KPM_HIP(hipMalloc(&t.wg, wg.size() * sizeof(int32_t)));
         KPM_HIP(hipMemcpy(t.seg, seg.data(), seg.size() * sizeof(kpm::Seg), hipMemcpyHostToDevice));
@@ -557,10 +626,11 @@ struct kpm_system {
     }
 
     // Whether calls with 2^vshift vectors keep their states vector-major (one
-    // plane per vector; one-sample systems under a shape with one vector per
-    // wavefront).  The direct form's shape decides for both forms.
+    // plane per vector; one-sample systems, or batches whose moment sets take
+    // the marching strips, under a shape with one vector per wavefront).  The
+    // direct form's shape decides for both forms.
     bool planar(int vshift) const {
-        return vshift > 0 && nseg == 1 && launch[vshift].vectors_per_wave == 1;
+        return vshift > 0 && (nseg == 1 || bstrips) && launch[vshift].vectors_per_wave == 1;
     }
 
     // The sweep of every kernel of a call with 2^vshift vectors under shape l:
@@ -568,8 +638,9 @@ struct kpm_system {
     // plane (plane_groups work-groups, when set) over 2^vshift planes.
     kpm_status sweep_planes(int vshift, const kpm_launch &l, kpm::Sweep *out,
                             bool may_alloc = true) {
-        KPM_TRY(sweep_with(0, l, out, may_alloc));
-        if (l.plane_groups > 0) {
+        // a batch shares plane_groups out among its samples
+        KPM_TRY(sweep_with(0, l, out, may_alloc, nseg > 1 ? l.plane_groups : 0));
+        if (l.plane_groups > 0 && nseg == 1) {
             out->nwg = l.plane_groups;
             out->one.nwg = l.plane_groups;
         }
@@ -743,6 +814,7 @@ struct kpm_system {
         for (void *p : xbuf)
             if (p) (void)hipFree(p);
         if (d_code) (void)hipFree(d_code);
+        if (d_sid) (void)hipFree(d_sid);
         if (d_flags) (void)hipFree(d_flags);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         for (SegTab &t : segtabs) {
@@ -1517,7 +1589,8 @@ kpm_status fourier_impl(kpm_system *sys, int vshift, const void *phil_v, const v
 // marching strips where the slots follow the graphene order, for several
 // vectors one vector per wavefront in 4, 6 or 8-step strips (grid per plane
 // from groups_per_cu or 16 .. 128 groups per plane); strips also in
-// work-groups of 64, 128 and 512 threads.
+// work-groups of 64, 128 and 512 threads.  Batches of chain lattices: strips
+// per sample (one vector per wavefront for several vectors).
 std::vector<kpm_launch> autotune_candidates(const kpm_system *sys, int vs) {
     static const int groups[] = {4, 8, 16};
     static const int ilps[] = {1, 2, 4};
@@ -1549,6 +1622,26 @@ std::vector<kpm_launch> autotune_candidates(const kpm_system *sys, int vs) {
         // groups of 256)
         for (int gs : {64, 128, 512})
             cand.push_back(kpm_launch{2 * 256 / gs, 1, 0, 1, 5, 8, 1, 16 * 256 / gs, gs});
+    }
+    // a batch of chain lattices: 4, 6 or 8-step strips in groups of one or four
+    // wavefronts, one vector per wavefront for several vectors (about 2048
+    // wavefronts over all planes, or twice that, shared out among the samples
+    // in proportion to their rows; at least 8 groups per sample)
+    if (sys->bstrips) {
+        const int64_t minpg = 8 * (int64_t)sys->nseg;
+        for (int ksteps : {4, 6, 8})
+            for (int gs : {64, 256}) {
+                const int wpg = gs / kpm::kWave;
+                if (vs == 0) {
+                    cand.push_back(kpm_launch{8 / wpg, 1, 0, 1, 5, ksteps, 0, 0, gs});
+                    continue;
+                }
+                for (int mult : {1, 2}) {
+                    const int64_t per = ((int64_t)sys->cus * 8 * mult / wpg) >> vs;
+                    const int64_t pg = std::max(minpg, std::min<int64_t>(65536, per / 8 * 8));
+                    cand.push_back(kpm_launch{2, 1, 0, 1, 5, ksteps, 1, (int)pg, gs});
+                }
+            }
     }
     if (sys->d_code && vs == 0) {
         for (int g : {2, 3, 4, 6})
@@ -1588,7 +1681,7 @@ kpm_status autotune_impl(kpm_system *sys, int vs, const V *phi, int reps, kpm_la
     auto time_shape = [&](const kpm_launch &l, bool dbl, float *out_ms) -> kpm_status {
         const kpm::Ell h = sys->ell_for(l);
         kpm::Sweep sw;
-        KPM_TRY(l.vectors_per_wave == 1 && vs > 0 && sys->nseg == 1
+        KPM_TRY(l.vectors_per_wave == 1 && vs > 0 && (sys->nseg == 1 || sys->bstrips)
                     ? sys->sweep_planes(vs, l, &sw)
                     : sys->sweep_with(vs, l, &sw));
         const int ks = sys->multi_steps(sw.vshift, l);
@@ -1769,8 +1862,37 @@ kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int devi
     // Chain-lattice codes of the two-step sweep (one sample, compact width-3
     // form with uniform hopping).
     std::vector<uint32_t> code;
+    std::vector<uint8_t> seen;
     const bool lat2 = nseg == 1 && !pid.empty() && w == 3 && !any_hop && sys->chain[0] > 0 &&
-                      lattice_codes(nbr, w, n, sys->chain[0], pid, sys->npat, code);
+                      lattice_codes(nbr, w, n, 0, n, sys->chain[0], pid, sys->npat, code, seen);
+    // a batch whose every sample is such a lattice of at least kMinChains
+    // chains (and no wider than the strips' 32-bit row offsets allow): its
+    // moment sets can take the marching strips, one vector per row, with
+    // per-row ids of the distinct step codes of all samples (whatever the
+    // compact form, whose patterns hold sample-specific row offsets)
+    bool bstrips = nseg > 1 && w == 3 && !any_hop;
+    std::vector<uint32_t> rcode, bcode, bflags;
+    std::vector<uint8_t> sid;
+    for (int s = 0; s < nseg && bstrips; ++s) {
+        const int64_t nx = sys->chain[s], rows = sys->off[s + 1] - sys->off[s];
+        bstrips = nx > 0 && rows / nx >= kpm::kMinChains &&
+                  nx * (int64_t)sizeof(double2) < ((int64_t)1 << 31) &&
+                  row_codes(nbr, w, n, sys->off[s], sys->off[s + 1], nx, rcode);
+    }
+    if (bstrips) {
+        sid.resize(n);
+        for (int64_t r = 0; r < n && bstrips; ++r) {
+            size_t id = 0;
+            while (id < bcode.size() && bcode[id] != rcode[r]) ++id;
+            if (id == bcode.size()) {
+                if (bcode.size() >= (size_t)kpm::kMaxPatterns) bstrips = false;
+                bcode.push_back(rcode[r]);
+            }
+            sid[r] = (uint8_t)id;
+        }
+        rcode.clear();
+        bstrips = bstrips && graphene_flags(bcode, bflags);
+    }
     if (!ons_float) {
         for (int s = 0; s < nseg; ++s)
             for (int64_t r = sys->off[s]; r < sys->off[s + 1]; ++r) ons[r] /= parts[s].e_scale;
@@ -1820,6 +1942,12 @@ kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int devi
                     st = upload((void **)&sys->d_pxw, pxw.data(), pxw.size() * sizeof(double));
             }
         }
+    }
+    if (st == KPM_OK && bstrips) {
+        st = upload((void **)&sys->d_flags, bflags.data(), bflags.size() * sizeof(uint32_t));
+        if (st == KPM_OK) st = upload((void **)&sys->d_sid, sid.data(), sid.size());
+        sys->nsp = (int)bcode.size();
+        sys->bstrips = st == KPM_OK;
     }
     if (st == KPM_OK && ons_float) {
         std::vector<float> of(ons.begin(), ons.end());

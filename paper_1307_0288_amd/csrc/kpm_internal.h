@@ -57,6 +57,9 @@ struct Seg {
     // for t < 2^32, and t * div_m fits 64 bits for the tile indices t < 2^31 used
     uint64_t div_m;
     int32_t div_l;
+    // marching strips of a batch (one vector per row): the sample's chain
+    // length and the chains per strip
+    int32_t snx, sj;
 };
 
 // Persistent, XCD-aware sweep.  Work-groups are dispatched round-robin over
@@ -106,6 +109,11 @@ struct Lat2 {
     const uint32_t *code;    // [npat]
     const uint32_t *flags;   // [npat], or nullptr
     int32_t arith32;         // FP32 states: strip levels in FP32 arithmetic (KPM_FP32)
+    // batches: the strips' own per-row pattern ids (the distinct (chain,
+    // column) step codes of all samples, nsp of them, flags per id); null:
+    // the compact form's ids
+    const uint8_t *sid;
+    int32_t nsp;
 };
 
 // Coefficient of a step: the value for segment s is tab[s * stride + idx]

@@ -1095,12 +1095,20 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
                                             const CoefK &ck) {
     constexpr bool DBL = MODE == kMarchDoubled, BES = MODE == kMarchBessel,
                    RE = MODE == kMarchDirectRe;
-    const int64_t po = plane_off(sw);
+    // the group's sample (the whole system, or its segment of a batch); row
+    // pointers start at the sample's first row of this group's plane
+    const StripGeo geo = strip_geo(sw, lat);
+    const int64_t po = plane_off(sw) + geo.e0;
     p1 = on_plane(p1, po);
     p0 = on_plane(p0, po);
     out1 = on_plane(out1, po);
     out2 = on_plane(out2, po);
     lacc = on_plane(lacc, po);
+    // pattern ids: the strips' own (batches) or the compact form's
+    const uint8_t *pid = (lat.sid ? lat.sid : h.pid) + geo.e0;
+    const int npat = lat.sid ? lat.nsp : h.npat;
+    const float *onsf = on_plane(h.onsf, geo.e0);
+    const double *ons = on_plane(h.ons, geo.e0);
     constexpr int TC = kWave - 2 * K;                  // columns per strip
     constexpr int P = kRowRing, PS = kStateRing, DS = kDs, DR = kRowRing - 1 - K;
     // phi_L rows are loaded DL ahead and used through K iterations after their
@@ -1113,41 +1121,54 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
     // use; with more levels their registers are needed for the level rings
     static_assert(K >= 2 && K <= 8, "steps per pass");
     constexpr bool kAhead = K <= 5;
-    const double t = sw.one.t, inv_es = sw.one.inv_es;
-    // per pattern: (previous column, next column), (next chain, previous chain)
-    __shared__ double2 lwt[2 * kMaxPatterns];
-    for (int j = threadIdx.x; j < h.npat; j += (int)blockDim.x) {
+    const double t = geo.t, inv_es = geo.inv_es;
+    // per pattern and marching direction d: (previous column, next column),
+    // then the weights of the rows after and before in marching order: (next
+    // chain, previous chain) marching down the chains (d = 0), swapped
+    // marching up (d = 1)
+    __shared__ double2 lwt[4 * kMaxPatterns];
+    for (int j = threadIdx.x; j < npat; j += (int)blockDim.x) {
         const uint32_t f = lat.flags[j];
         const double tv = (f & 4u) ? t : 0.0;
-        lwt[2 * j] = make_double2((f & 1u) ? t : 0.0, (f & 2u) ? t : 0.0);
-        lwt[2 * j + 1] = make_double2((f & 8u) ? tv : 0.0, (f & 8u) ? 0.0 : tv);
+        const double wn = (f & 8u) ? tv : 0.0, wp = (f & 8u) ? 0.0 : tv;
+        const double2 wh = make_double2((f & 1u) ? t : 0.0, (f & 2u) ? t : 0.0);
+        lwt[4 * j] = lwt[4 * j + 2] = wh;
+        lwt[4 * j + 1] = make_double2(wn, wp);
+        lwt[4 * j + 3] = make_double2(wp, wn);
     }
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
-    const int nx = lat.nx, ny = lat.ny, J = lat.tj;
+    const int nx = geo.nx, ny = geo.ny, J = geo.J;
     const int nst = (nx + TC - 1) / TC, nsg = (ny + J - 1) / J;
     const int ntile = nst * nsg;
-    const int lb = blockIdx.x;
+    const int lb = geo.lb;
     const int per = (ntile + kXcds - 1) / kXcds;
     const int b0 = (lb % kXcds) * per, b1 = min(b0 + per, ntile);
     const int nwv = (int)blockDim.x / kWave;          // wavefronts per group
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     const int wloc = (lb / kXcds) * nwv + wv;
-    const int wn = (sw.nwg / kXcds) * nwv;
+    const int wn = (geo.nwg / kXcds) * nwv;
     double2 acc[NA];
 #pragma unroll
     for (int k = 0; k < NA; ++k) acc[k] = make_double2(0.0, 0.0);
     for (int b = b0 + wloc; b < b1; b += wn) {
         const int strip = b % nst;                     // across the strips first
         const int j0 = (b / nst) * J, c0 = strip * TC;
+        // odd bands of strips march up the chains: two neighbouring bands then
+        // reach their shared boundary chains at the same time (both first or
+        // both last), and the second reads of those rows hit the cache
+        const int dir = (b / nst) & 1;
         const int gi = wrap_index(c0 - K + lane, nx);
         const bool colok = lane >= K && lane < K + TC && c0 - K + lane < nx;
         const int Jt = min(J, ny - j0), T = Jt + 2 * K;
         const uint32_t ov = (uint32_t)gi * sizeof(V), rb = (uint32_t)nx * sizeof(V);
         const uint32_t ovo = colok ? ov : kOffNone;   // offset of the strip's own columns
         const double mcol = colok ? 1.0 : 0.0;
-        auto base = [&](int rho) { return (int64_t)wrap_index(j0 - K + rho, ny) * nx; };
+        // chain of walked row rho (rows K .. K + Jt - 1 are the band's own)
+        const int cst = dir ? j0 + Jt + K - 1 : j0 - K, sgn = dir ? -1 : 1;
+        auto base = [&](int rho) { return (int64_t)wrap_index(cst + sgn * rho, ny) * nx; };
         auto owned = [&](int rho) { return rho >= K && rho < K + Jt; };
+        const int wo = 2 * dir;                        // this direction's weights
         double2 X0[PS], Xm[PS], LL[P];                 // phi_n, phi_{n-1}, phi_L rings
         int PI[P];                                     // pattern ids
         float OF[P];
@@ -1176,8 +1197,8 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
         }
         auto row_terms = [&](int q) {
             if (!kAhead) return;
-            WH[q] = lwt[2 * PI[q]];
-            WV[q] = lwt[2 * PI[q] + 1];
+            WH[q] = lwt[4 * PI[q] + wo];
+            WV[q] = lwt[4 * PI[q] + wo + 1];
             OO[q] = ONSF ? (double)OF[q] * inv_es : OD[q];
         };
         auto load_state = [&](int rho, int q) {
@@ -1194,16 +1215,16 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
             const int64_t rbase = base(rho);
             const bool in = rho < T;
             PI[q] = __builtin_amdgcn_raw_buffer_load_b8(
-                row_rsrc(h.pid + rbase, in ? (uint32_t)nx : 0u), gi, 0, 0);
+                row_rsrc(pid + rbase, in ? (uint32_t)nx : 0u), gi, 0, 0);
             if (ONSF)
                 OF[q] = __builtin_bit_cast(
                     float, __builtin_amdgcn_raw_buffer_load_b32(
-                               row_rsrc(h.onsf + rbase, in ? (uint32_t)nx * 4u : 0u), gi * 4, 0,
+                               row_rsrc(onsf + rbase, in ? (uint32_t)nx * 4u : 0u), gi * 4, 0,
                                0));
             else
                 OD[q] = __builtin_bit_cast(
                     double, __builtin_amdgcn_raw_buffer_load_b64(
-                                row_rsrc(h.ons + rbase, in ? (uint32_t)nx * 8u : 0u), gi * 8, 0,
+                                row_rsrc(ons + rbase, in ? (uint32_t)nx * 8u : 0u), gi * 8, 0,
                                 0));
         };
 #pragma unroll
@@ -1242,11 +1263,11 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
                         old = s == 2 ? X0[qs] : LV[s - 3 < 0 ? 0 : s - 3][q3];
                     }
                     // 2 H~ x - q in the slot order of k_moment_step (of the two
-                    // vertical terms one has weight 0; the previous chain's comes
-                    // first, as the next chain's value is the one computed last)
+                    // vertical terms one has weight 0, so their order, the row
+                    // before in marching order first, leaves the sum unchanged)
                     if (!kAhead) {                 // the row's terms, read at each level
-                        WH[qp] = lwt[2 * PI[qp]];
-                        WV[qp] = lwt[2 * PI[qp] + 1];
+                        WH[qp] = lwt[4 * PI[qp] + wo];
+                        WV[qp] = lwt[4 * PI[qp] + wo + 1];
                         OO[qp] = ONSF ? (double)OF[qp] * inv_es : OD[qp];
                     }
                     double2 a = make_double2(OO[qp] * x0.x, OO[qp] * x0.y);
@@ -1260,7 +1281,7 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
                         LL[qp] = rounded<V>(cmla(LL[qp], ck.c[s - 1], c));
                         if (s == K) {
                             const bool own = owned(rho);
-                            const int64_t row = (int64_t)(own ? j0 + rho - K : 0) * nx;
+                            const int64_t row = (int64_t)(own ? cst + sgn * rho : 0) * nx;
                             buf_st(lacc + row, own ? rb : 0u, ovo, LL[qp]);
                         }
                     } else if (DBL) {
@@ -1278,7 +1299,7 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
                     }
                     if (s >= K - 1) {
                         const bool own = owned(rho);
-                        const int64_t row = (int64_t)(own ? j0 + rho - K : 0) * nx;
+                        const int64_t row = (int64_t)(own ? cst + sgn * rho : 0) * nx;
                         buf_st((s == K ? out2 : out1) + row, own ? rb : 0u, ovo, c);
                     }
                 }
@@ -1485,8 +1506,8 @@ bool launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
     // 2 .. 4, marching strips 2 .. 8
     if (lat.k < 2 || lat.k > (lat.reg == 2 ? kMaxMarchSteps : (lat.reg == 1 ? 4 : 2)))
         return false;
-    // vector-major states run only in the marching strips
-    if (sw.nplanes > 1 && lat.reg != 2) return false;
+    // vector-major states and batches run only in the marching strips
+    if ((sw.nplanes > 1 || sw.seg) && lat.reg != 2) return false;
     if constexpr (std::is_same<V, float2>::value)
         if (lat.arith32 && lat.reg == 2)
             return launch_moment_multi_f32(h, sw, lat, p1, p0, out1, out2, phil, partial, slot,
