@@ -922,8 +922,9 @@ def batched(args):
 def ragged(args):
     """32 independent samples (AGNR, ZGNR, sheets of 1e4..1e6 sites, Anderson W in
     {0.5, 1, 2} eV), 8 random vectors each, 1000 moments per sample, all samples
-    advanced by one launch per Chebyshev step; direct launches vs hipGraph replay,
-    FP64 and FP32 states."""
+    advanced together by every launch (eight recursion steps per launch in the
+    marching strips when the autotuner keeps them); direct launches vs hipGraph
+    replay, FP64 states, FP32 states and FP32 strip arithmetic."""
     import torch
     import paper_1307_0288_amd as kp
     cfg = ki.sheet_config("ragged")
@@ -940,12 +941,24 @@ def ragged(args):
     phi_h = np.concatenate(phis)
     total = phi_h.shape[0]
     log(f"ragged inputs: {len(specs)} samples, {total} sites, {r} vectors")
-    res = {}
-    for prec in ("fp64", "fp32"):
+    res, rates = {}, {}
+    for prec in ("fp64", "fp32", "fp32_arith"):
         sysg = kp.graphene_batch(samples, prec)
         phi = sysg.upload(phi_h)
         launch = kp.kpm_autotune(sysg, phi, 20)
         log(f"{prec} autotuned launch shape: {launch}")
+        # per-launch rate of the moment passes (HIP events, direct launches)
+        kp.kpm_moments(sysg, phi, phi, nm)
+        kp.kpm_reset_stats(sysg)
+        kp.kpm_set_timing(sysg, True)
+        kp.kpm_moments(sysg, phi, phi, nm)
+        st = kp.kpm_get_stats(sysg)
+        kp.kpm_set_timing(sysg, False)
+        us = st["step_ms"] / max(st["step_launches"], 1) * 1e3
+        rates[prec] = {"avg_launch_us": round(us, 3), "launches": st["step_launches"],
+                       "bytes_per_launch": st["step_bytes"],
+                       "algorithmic_gbs": round(achieved_gbs(st), 1),
+                       "frac_of_8tbs": round(achieved_gbs(st) / HBM_PEAK_GBS, 4)}
         for graphs in (False, True):
             kp.kpm_set_graphs(sysg, graphs)
             kp.kpm_moments(sysg, phi, phi, nm)                # warm-up (and capture)
@@ -976,6 +989,8 @@ def ragged(args):
                    "n_sites": int(total), "n_vec": r, "samples": len(specs)},
         "runs": {k: {"ms": round(v["seconds"] * 1e3, 3), "gsu": round(v["gsu"], 3),
                      "launch_shape": v["launch"]} for k, v in res.items()},
+        "moment_launches": rates,
+        "fp32_arith_over_fp64": round(res["fp32_arith_graph"]["gsu"] / best["gsu"], 3),
     }
     print(json.dumps(out), flush=True)
 

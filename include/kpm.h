@@ -496,7 +496,9 @@ kpm_status kpm_xu_state(kpm_system *sys, int n_vec, const void *phi, int n_steps
  * 3 and 4 steps need the register forms (else 2 steps apply), 5 .. 8 steps
  * the strips.  Under steps > 1 any single steps keep row order.  Default for
  * one vector: groups_per_cu 2, steps 8, tiled 5; for more vectors single
- * steps.  At a fixed grid size, traversal and step count the moments are
+ * steps, except on one-sample graphene lattices and batches that take the
+ * strips: eight-step strips with one vector per wavefront (below), about
+ * 1024 work-groups over all planes (at least 8 per sample of a batch).  At a fixed grid size, traversal and step count the moments are
  * bit-identical for every ilp, streaming and compact choice; the recursion
  * states are bit-identical for every shape (up to the sign of zero), and the
  * shape changes only the order of the inner-product partial sums (in the

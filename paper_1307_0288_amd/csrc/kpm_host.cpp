@@ -1973,6 +1973,19 @@ kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int devi
             sys->launch[v] = sys->launch_dbl[v] = l;
         }
     }
+    // a batch whose moment sets can take the strips: eight-step strips, one
+    // vector per wavefront for several vectors with about 1024 groups over all
+    // planes and at least 8 per sample (the autotuner's pick for the 32-sample
+    // batch of 8 vectors)
+    if (st == KPM_OK && sys->bstrips && !launch_env_set()) {
+        sys->launch[0] = sys->launch_dbl[0] = kpm_launch{2, 1, 0, 1, 5, 8, 0, 0, 0};
+        for (int v = 1; v < 7; ++v) {
+            const int pg = std::max(8 * nseg, 1024 >> v);
+            if (pg > 65536) break;
+            const kpm_launch l{2, 1, 0, 1, 5, 8, 1, pg, 0};
+            sys->launch[v] = sys->launch_dbl[v] = l;
+        }
+    }
     if (st == KPM_OK) {
         const hipError_t e = kpm::static_scratch(device, &sys->static_scratch);
         if (e != hipSuccess)
