@@ -242,14 +242,19 @@ def main():
     kp.kpm_set_timing(sysg, False)
 
     value = st["site_updates"] / elapsed / 1e9
-    launch_ms = st["step_ms"] / max(st["step_launches"], 1)
+    # the dominant kernel: the VAC and MSD moment sets of every time step after
+    # the first run as two vector planes of one launch sequence (the library's
+    # joint VAC / MSD call), with half the one-vector grid per plane; they are
+    # the widest launches of the step, timed on their own (HIP events around
+    # their runs); the DOS set and the first VAC set are one-plane launches
+    wide = st["wide_rows"] == st["step_rows"] and st["wide_launches"] > 0
+    launch_ms = (st["wide_ms"] / st["wide_launches"] if wide
+                 else st["step_ms"] / max(st["step_launches"], 1))
     bytes_launch = st["step_bytes"]
     two = multi_step(launch)
     bpu = bytes_launch / st["step_rows"] / (launch["steps"] if two else 1)
-    achieved = achieved_gbs(st)
-    # the VAC and MSD moment sets (all but the DOS set) keep only real parts;
-    # at every time step after the first they run as two vector planes, with half
-    # the one-vector grid per plane (the library's joint VAC / MSD call)
+    achieved = bytes_launch / (launch_ms * 1e-3) / 1e9 if wide else achieved_gbs(st)
+    # the VAC and MSD moment sets keep only real parts
     kname = moment_kernel_name("double2", launch, False, real=True, onsf=onsf)
     tfile = TRAFFIC_FILE2 if two else TRAFFIC_FILE
     shape2 = dict(launch, vectors_per_wave=1, plane_groups=joint_plane_groups(launch))
@@ -317,8 +322,14 @@ def main():
                      "bytes_per_site_update": round(bpu, 3),
                      "avg_launch_us": round(launch_ms * 1e3, 3),
                      "timing": "HIP events around each run of launches on the library's stream "
-                               "(mean over the timed steps; direct launches, no graph replay)",
-                     "launches": st["step_launches"], "launch_shape": launch,
+                               "(mean over the two-plane launches of the timed steps; direct "
+                               "launches, no graph replay)",
+                     "launches": st["wide_launches"] if wide else st["step_launches"],
+                     "all_moment_launches": {"launches": st["step_launches"],
+                                             "avg_launch_us": round(st["step_ms"] * 1e3 / max(
+                                                 st["step_launches"], 1), 3),
+                                             "algorithmic_gbs": round(achieved_gbs(st), 1)},
+                     "launch_shape": launch,
                      "two_plane_shape": shape2},
         "cpu_baseline": cpu,
     }
@@ -739,18 +750,22 @@ def ftm(args):
     print(json.dumps(out), flush=True)
 
 
-def _golden_vector0(ons, act, phi0):
-    """The oracle's stored moments of the paper-scale sheet's vector of seed
-    3000 (tests/golden/paper_sheet_oracle.npz, written by a script that calls
-    only the oracle), when they belong to these inputs; else None."""
+def _golden_vector(seed, ons, act, phi):
+    """The oracle's stored moments of the paper-scale sheet's vector of this
+    seed (tests/golden/paper_sheet_oracle.npz for seed 3000,
+    paper_sheet_oracle_seed<S>.npz for others; written by a script that calls
+    only the oracle), when they are stored for these inputs; else None."""
     import hashlib
-    path = os.path.join(ROOT, "tests", "golden", "paper_sheet_oracle.npz")
+    name = "paper_sheet_oracle.npz" if seed == 3000 else f"paper_sheet_oracle_seed{seed}.npz"
+    path = os.path.join(ROOT, "tests", "golden", name)
     if not os.path.exists(path):
         return None
     z = np.load(path, allow_pickle=False)
+    if not {"dos_re", "vac", "msd"} <= set(z.files):
+        return None
     meta = json.loads(bytes(z["meta"]).decode())
     h = hashlib.sha256()
-    for a in (ons, act, phi0):
+    for a in (ons, act, phi):
         h.update(np.ascontiguousarray(a).tobytes())
     if meta.get("input_sha256") != h.hexdigest():
         return None
@@ -795,7 +810,9 @@ def batched(args):
     ons = ki.anderson_onsite(n, p["w"], 1000)
     phi_h = ki.random_phase(n, r, 3000, act)
     nm, ns, nb, dt, es = p["n_moments"], p["n_steps"], p["n_bessel"], p["dt_fs"], p["e_scale"]
-    gold = _golden_vector0(ons, act, phi_h[:, 0])
+    # vectors 0 .. 3 whose oracle moments are stored
+    golds = {q: g for q in range(4)
+             if (g := _golden_vector(3000 + q, ons, act, phi_h[:, q])) is not None}
     en = np.linspace(-0.95 * es, 0.95 * es, 2048)
     steps = max(1, args.steps)
     res, spec, spec0 = {}, {}, {}
@@ -828,7 +845,8 @@ def batched(args):
         log(f"{prec}: {res[prec]['gsu']:.1f} Gsite-updates/s")
         spec[prec] = _spectra(kp, dos.real.mean(axis=0), vac.mean(axis=0), msd.mean(axis=0),
                               en, es, area, dt)
-        spec0[prec] = _spectra(kp, dos[0].real, vac[0], msd[0], en, es, area, dt)
+        spec0[prec] = {q: _spectra(kp, dos[q].real, vac[q], msd[q], en, es, area, dt)
+                       for q in golds}
         sysg.close()
         del phi
         torch.cuda.empty_cache()
@@ -841,8 +859,7 @@ def batched(args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     kp.kpm_moments(sysg, phi1, phi1, nm)
-    kp.kpm_vac(sysg, phi1, ns, dt, nb, nm)
-    kp.kpm_msd(sysg, phi1, ns, dt, nb, nm)
+    kp.kpm_vac_msd(sysg, phi1, ns, dt, nb, nm)
     torch.cuda.synchronize()
     plain = kp.kpm_get_stats(sysg)["site_updates"] / (time.perf_counter() - t0) / 1e9
     sysg.close()
@@ -851,9 +868,12 @@ def batched(args):
     f32s = ("fp32", "fp32_arith")
     err32 = {q: {k: _rel(spec[q][k], spec["fp64"][k]) for k in spec["fp64"]} for q in f32s}
     err_or = None
-    if gold is not None:
-        ref = _spectra(kp, gold["dos"], gold["vac"], gold["msd"], en, es, area, dt)
-        err_or = {prec: {k: _rel(spec0[prec][k], ref[k]) for k in ref} for prec in spec0}
+    if golds:
+        refs = {q: _spectra(kp, g["dos"], g["vac"], g["msd"], en, es, area, dt)
+                for q, g in golds.items()}
+        # per result, the worst of the checked vectors
+        err_or = {prec: {k: max(_rel(spec0[prec][q][k], refs[q][k]) for q in refs)
+                         for k in next(iter(refs.values()))} for prec in spec0}
     worst = {q: max(list(err32[q].values()) +
                     ([] if err_or is None else list(err_or[q].values()))) for q in f32s}
     # the reported FP32 form: the faster one whose sigma(E) error is within the bar
@@ -870,6 +890,8 @@ def batched(args):
     sq = valu_record(sfile, f32["rows"], f32["launch"], kname)
     hbm = (traffic if traffic is not None else f32["bytes_launch"]) / launch_s / 1e9
     valu = None if sq is None else sq["valu_insts_per_launch"] / launch_s / 1e9
+    # the roof closer to its peak: HBM (measured traffic when known) or VALU issue
+    bound = "alu" if valu is not None and valu / VALU_PEAK_GINST > hbm / HBM_PEAK_GBS else "hbm"
     out = {
         "metric": "Gsite-updates/s (batched Chebyshev hot path: DOS + VAC + MSD, 64 vectors, "
                   "FP32 states)",
@@ -892,12 +914,19 @@ def batched(args):
         "sigma_rel_err_fp32_vs_fp64": err32,
         "sigma_rel_err_vs_oracle": err_or,
         "sigma_error_norm": "max over 2048 energies in [-0.95 E_s, 0.95 E_s] and 21 times of "
-                            "|d sigma| / max |sigma_ref|; vs_oracle: vector 0 (seed 3000) "
-                            "against the oracle's stored moments of that vector",
+                            "|d sigma| / max |sigma_ref|; vs_oracle: each of the vectors in "
+                            "oracle_vectors against the oracle's stored moments of that vector "
+                            "(the worst of them)",
+        "oracle_vectors": sorted(golds),
         "sigma_bar": 1e-3, "sigma_within_bar": {q: bool(worst[q] <= 1e-3) for q in f32s},
-        "roofline": {"kernel": kname, "bound": "hbm",
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+        "roofline": {"kernel": kname, "bound": bound,
+                     **({"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4)} if bound == "hbm" else
+                        {"achieved": round(valu, 1), "peak": VALU_PEAK_GINST,
+                         "unit": "G VALU wave-instructions/s",
+                         "frac": round(valu / VALU_PEAK_GINST, 4),
+                         "hbm_algorithmic_gbs": round(achieved, 1)}),
+                     "traffic": traffic,
                      "traffic_source": (f"lookup: {os.path.relpath(tfile, ROOT)} "
                                         "(rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated, same "
                                         "kernel source, size and shape; not measured in this run)")

@@ -615,6 +615,10 @@ typedef struct {
                                  4 in the doubling form)                     */
     int64_t step_bytes_total; /* algorithmic bytes of all launches in the
                                  timed moment-step runs                     */
+    double wide_ms;           /* event time of the timed runs whose launches
+                                 cover the most rows x vectors (wide_rows)  */
+    int64_t wide_launches;    /* moment-step launches in those runs         */
+    int64_t wide_rows;        /* rows x vectors per launch of those runs    */
 } kpm_stats;
 
 kpm_status kpm_set_timing(kpm_system *sys, int enable);

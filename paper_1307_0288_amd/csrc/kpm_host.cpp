@@ -374,6 +374,7 @@ struct kpm_system {
     bool timing = false;
     std::vector<hipEvent_t> events;
     size_t events_used = 0;
+    std::vector<std::pair<int64_t, int64_t>> ev_runs;   // (rows x vectors, launches) per pair
     kpm_stats stats{};
     // captured moment sets (kpm_set_graphs): one executable graph per set of
     // buffers, sizes and launch shape; dropped whenever scratch is reallocated
@@ -483,7 +484,7 @@ struct kpm_system {
         // (a batch's strips take their geometry from its segment table)
         return kpm::Lat2{l2nx, l2ny, k, reg, tj, (l2nx + kpm::kTileCols - 1) / kpm::kTileCols,
                          (l2ny + tj - 1) / tj, d_code, d_flags, prec == KPM_FP32 ? 1 : 0,
-                         d_sid, nsp};
+                         nseg == 1 ? d_pid : d_sid, nseg == 1 ? npat : nsp};
     }
 
     kpm::Ell ell() const {
@@ -782,7 +783,9 @@ struct kpm_system {
         return KPM_OK;
     }
 
-    kpm_status event_pair(hipEvent_t *a, hipEvent_t *b) {
+    // An event pair for a run of `launches` moment-step launches of `rows`
+    // rows x vectors each (the count may be set once the run is closed).
+    kpm_status event_pair(hipEvent_t *a, hipEvent_t *b, int64_t rows, int64_t launches = 0) {
         while (events.size() < events_used + 2) {
             hipEvent_t e;
             KPM_HIP(hipEventCreate(&e));
@@ -791,18 +794,32 @@ struct kpm_system {
         *a = events[events_used];
         *b = events[events_used + 1];
         events_used += 2;
+        ev_runs.resize(events_used / 2);
+        ev_runs.back() = {rows, launches};
         return KPM_OK;
     }
+    void close_run(int64_t launches) { ev_runs.back().second = launches; }
 
-    // Adds the elapsed time of every recorded event pair to the stats.
-    // The stream must have been synchronised.
+    // Adds the elapsed time of every recorded event pair to the stats (and to
+    // the widest runs' figures).  The stream must have been synchronised.
     kpm_status harvest_events() {
         for (size_t k = 0; k + 1 < events_used; k += 2) {
             float ms = 0;
             KPM_HIP(hipEventElapsedTime(&ms, events[k], events[k + 1]));
             stats.step_ms += ms;
+            const auto &run = ev_runs[k / 2];
+            if (run.first > stats.wide_rows) {
+                stats.wide_rows = run.first;
+                stats.wide_ms = 0;
+                stats.wide_launches = 0;
+            }
+            if (run.first == stats.wide_rows) {
+                stats.wide_ms += ms;
+                stats.wide_launches += run.second;
+            }
         }
         events_used = 0;
+        ev_runs.clear();
         return KPM_OK;
     }
 
@@ -918,19 +935,23 @@ kpm_status enqueue_moments(kpm_system *sys, const kpm_launch &l, const kpm::Swee
     const int slots = moment_slots(nm, dbl);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     bool open = false;
+    int64_t in_run = 0;                       // launches in the open timed run
     kpm_status st = KPM_OK;
     moment_plan(
         slots, ring, dbl, k,
         [&](int kind, int m, int c0) {
             if (st != KPM_OK) return;
             if (events && !open) {
-                if ((st = sys->event_pair(&e0, &e1)) != KPM_OK) return;
+                if ((st = sys->event_pair(&e0, &e1, kpm_system::sweep_elems(sw))) != KPM_OK)
+                    return;
                 if (hipEventRecord(e0, s) != hipSuccess) {
                     st = fail(KPM_ERR_DEVICE, "event record");
                     return;
                 }
                 open = true;
+                in_run = 0;
             }
+            ++in_run;
             if (kind > 1) {
                 V *o1 = free_state(p0, p1, nullptr);
                 V *o2 = free_state(p0, p1, o1);
@@ -958,6 +979,7 @@ kpm_status enqueue_moments(kpm_system *sys, const kpm_launch &l, const kpm::Swee
             if (st != KPM_OK) return;
             if (open) {
                 if (hipEventRecord(e1, s) != hipSuccess) st = fail(KPM_ERR_DEVICE, "event record");
+                sys->close_run(in_run);
                 open = false;
             }
             kpm::launch_reduce(partial, reduce_sweep(sw), std::min(c1, nm) - c0, dmom, stride_r,
@@ -1034,7 +1056,7 @@ kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (sys->timing) {
-        KPM_TRY(sys->event_pair(&e0, &e1));
+        KPM_TRY(sys->event_pair(&e0, &e1, kpm_system::sweep_elems(sw), n1 + n2));
         KPM_HIP(hipEventRecord(e0, sys->stream));
     }
     KPM_HIP(hipGraphLaunch(exec, sys->stream));

@@ -109,9 +109,9 @@ struct Lat2 {
     const uint32_t *code;    // [npat]
     const uint32_t *flags;   // [npat], or nullptr
     int32_t arith32;         // FP32 states: strip levels in FP32 arithmetic (KPM_FP32)
-    // batches: the strips' own per-row pattern ids (the distinct (chain,
-    // column) step codes of all samples, nsp of them, flags per id); null:
-    // the compact form's ids
+    // per-row pattern ids of the strips and their number (flags per id):
+    // the compact form's on one sample, on a batch the distinct (chain,
+    // column) step codes of all its samples
     const uint8_t *sid;
     int32_t nsp;
 };

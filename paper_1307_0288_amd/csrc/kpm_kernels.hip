@@ -1104,11 +1104,10 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
     out1 = on_plane(out1, po);
     out2 = on_plane(out2, po);
     lacc = on_plane(lacc, po);
-    // pattern ids: the strips' own (batches) or the compact form's
-    const uint8_t *pid = (lat.sid ? lat.sid : h.pid) + geo.e0;
-    const int npat = lat.sid ? lat.nsp : h.npat;
-    const float *onsf = on_plane(h.onsf, geo.e0);
-    const double *ons = on_plane(h.ons, geo.e0);
+    // the per-row structure (the strips' pattern ids, on-site terms) is
+    // addressed from the kernel arguments plus the sample's first row, which
+    // keeps no further pointers live in scalar registers
+    const int64_t e0 = geo.e0;
     constexpr int TC = kWave - 2 * K;                  // columns per strip
     constexpr int P = kRowRing, PS = kStateRing, DS = kDs, DR = kRowRing - 1 - K;
     // phi_L rows are loaded DL ahead and used through K iterations after their
@@ -1127,7 +1126,7 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
     // chain, previous chain) marching down the chains (d = 0), swapped
     // marching up (d = 1)
     __shared__ double2 lwt[4 * kMaxPatterns];
-    for (int j = threadIdx.x; j < npat; j += (int)blockDim.x) {
+    for (int j = threadIdx.x; j < lat.nsp; j += (int)blockDim.x) {
         const uint32_t f = lat.flags[j];
         const double tv = (f & 4u) ? t : 0.0;
         const double wn = (f & 8u) ? tv : 0.0, wp = (f & 8u) ? 0.0 : tv;
@@ -1156,8 +1155,10 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
         const int j0 = (b / nst) * J, c0 = strip * TC;
         // odd bands of strips march up the chains: two neighbouring bands then
         // reach their shared boundary chains at the same time (both first or
-        // both last), and the second reads of those rows hit the cache
-        const int dir = (b / nst) & 1;
+        // both last), and the second reads of those rows hit the cache.  FP64
+        // states only: with FP32 states (converted at every load and store)
+        // the direction's scalar registers cost the pass its load pipelining
+        const int dir = std::is_same<V, double2>::value ? (b / nst) & 1 : 0;
         const int gi = wrap_index(c0 - K + lane, nx);
         const bool colok = lane >= K && lane < K + TC && c0 - K + lane < nx;
         const int Jt = min(J, ny - j0), T = Jt + 2 * K;
@@ -1212,19 +1213,19 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
         };
 
         auto load_row = [&](int rho, int q) {
-            const int64_t rbase = base(rho);
+            const int64_t rbase = base(rho) + e0;
             const bool in = rho < T;
             PI[q] = __builtin_amdgcn_raw_buffer_load_b8(
-                row_rsrc(pid + rbase, in ? (uint32_t)nx : 0u), gi, 0, 0);
+                row_rsrc(lat.sid + rbase, in ? (uint32_t)nx : 0u), gi, 0, 0);
             if (ONSF)
                 OF[q] = __builtin_bit_cast(
                     float, __builtin_amdgcn_raw_buffer_load_b32(
-                               row_rsrc(onsf + rbase, in ? (uint32_t)nx * 4u : 0u), gi * 4, 0,
+                               row_rsrc(h.onsf + rbase, in ? (uint32_t)nx * 4u : 0u), gi * 4, 0,
                                0));
             else
                 OD[q] = __builtin_bit_cast(
                     double, __builtin_amdgcn_raw_buffer_load_b64(
-                                row_rsrc(ons + rbase, in ? (uint32_t)nx * 8u : 0u), gi * 8, 0,
+                                row_rsrc(h.ons + rbase, in ? (uint32_t)nx * 8u : 0u), gi * 8, 0,
                                 0));
         };
 #pragma unroll

@@ -82,11 +82,10 @@ __device__ __forceinline__ void march_sweep_f32(const Ell &h, const Sweep &sw, c
     out1 = on_plane(out1, po);
     out2 = on_plane(out2, po);
     lacc = on_plane(lacc, po);
-    // pattern ids: the strips' own (batches) or the compact form's
-    const uint8_t *pid = (lat.sid ? lat.sid : h.pid) + geo.e0;
-    const int npat = lat.sid ? lat.nsp : h.npat;
-    const float *onsf = on_plane(h.onsf, geo.e0);
-    const double *ons = on_plane(h.ons, geo.e0);
+    // the per-row structure (the strips' pattern ids, on-site terms) is
+    // addressed from the kernel arguments plus the sample's first row, which
+    // keeps no further pointers live in scalar registers
+    const int64_t e0 = geo.e0;
     constexpr int TC = kWave - 2 * K;                  // columns per strip
     // states are prefetched 6 rows ahead (a ring of 12 rows: two 32-bit
     // registers per row, where the FP64 form affords 3 ahead in 6)
@@ -97,18 +96,13 @@ __device__ __forceinline__ void march_sweep_f32(const Ell &h, const Sweep &sw, c
                   "ring sizes");
     static_assert(K >= 2 && K <= 8, "steps per pass");
     const float tf = (float)geo.t, inv_esf = (float)geo.inv_es;
-    // per pattern and marching direction d: (previous column, next column,
-    // row after, row before in marching order), the rows after and before
-    // being the next and previous chains marching down (d = 0), swapped
-    // marching up (d = 1)
-    __shared__ float4 lwt[2 * kMaxPatterns];
-    for (int j = threadIdx.x; j < npat; j += (int)blockDim.x) {
+    // per pattern: (previous column, next column, next chain, previous chain)
+    __shared__ float4 lwt[kMaxPatterns];
+    for (int j = threadIdx.x; j < lat.nsp; j += (int)blockDim.x) {
         const uint32_t f = lat.flags[j];
         const float tv = (f & 4u) ? tf : 0.0f;
-        const float wn = (f & 8u) ? tv : 0.0f, wp = (f & 8u) ? 0.0f : tv;
-        const float hp = (f & 1u) ? tf : 0.0f, hn = (f & 2u) ? tf : 0.0f;
-        lwt[2 * j] = make_float4(hp, hn, wn, wp);
-        lwt[2 * j + 1] = make_float4(hp, hn, wp, wn);
+        lwt[j] = make_float4((f & 1u) ? tf : 0.0f, (f & 2u) ? tf : 0.0f, (f & 8u) ? tv : 0.0f,
+                             (f & 8u) ? 0.0f : tv);
     }
     __syncthreads();
     // the K coefficients of a propagator pass in single precision
@@ -132,18 +126,15 @@ __device__ __forceinline__ void march_sweep_f32(const Ell &h, const Sweep &sw, c
     for (int b = b0 + wloc; b < b1; b += wn) {
         const int strip = b % nst;                     // across the strips first
         const int j0 = (b / nst) * J, c0 = strip * TC;
-        // odd bands of strips march up the chains, so that two neighbouring
-        // bands read the rows about their shared boundary at the same time
-        const int dir = (b / nst) & 1;
         const int gi = wrap_index(c0 - K + lane, nx);
         const bool colok = lane >= K && lane < K + TC && c0 - K + lane < nx;
         const int Jt = min(J, ny - j0), T = Jt + 2 * K;
         const uint32_t ov = (uint32_t)gi * sizeof(float2), rb = (uint32_t)nx * sizeof(float2);
         const uint32_t ovo = colok ? ov : kOffNone;   // offset of the strip's own columns
         const double mcol = colok ? 1.0 : 0.0;
-        // chain of walked row rho (rows K .. K + Jt - 1 are the band's own)
-        const int cst = dir ? j0 + Jt + K - 1 : j0 - K, sgn = dir ? -1 : 1;
-        auto base = [&](int rho) { return (int64_t)wrap_index(cst + sgn * rho, ny) * nx; };
+        // every band walks down the chains (alternating directions, as the
+        // FP64 strips take them, cost these kernels their scalar registers)
+        auto base = [&](int rho) { return (int64_t)wrap_index(j0 - K + rho, ny) * nx; };
         auto owned = [&](int rho) { return rho >= K && rho < K + Jt; };
         float2 X0[PS], Xm[PS];                         // phi_n, phi_{n-1} rings
         float2 LL[P];                                  // phi_L (or the accumulator) ring
@@ -171,20 +162,20 @@ __device__ __forceinline__ void march_sweep_f32(const Ell &h, const Sweep &sw, c
             LL[q] = buf_ldf(lacc + base(rho), owned(rho) ? rb : 0u, ovo);
         };
         auto load_row = [&](int rho, int q) {
-            const int64_t rbase = base(rho);
+            const int64_t rbase = base(rho) + e0;
             const bool in = rho < T;
             PI[q] = __builtin_amdgcn_raw_buffer_load_b8(
-                row_rsrc(pid + rbase, in ? (uint32_t)nx : 0u), gi, 0, 0);
+                row_rsrc(lat.sid + rbase, in ? (uint32_t)nx : 0u), gi, 0, 0);
             if (ONSF)
                 OO[q] = __builtin_bit_cast(
                             float, __builtin_amdgcn_raw_buffer_load_b32(
-                                       row_rsrc(onsf + rbase, in ? (uint32_t)nx * 4u : 0u),
+                                       row_rsrc(h.onsf + rbase, in ? (uint32_t)nx * 4u : 0u),
                                        gi * 4, 0, 0)) *
                         inv_esf;
             else
                 OO[q] = (float)__builtin_bit_cast(
                     double, __builtin_amdgcn_raw_buffer_load_b64(
-                                row_rsrc(ons + rbase, in ? (uint32_t)nx * 8u : 0u), gi * 8, 0,
+                                row_rsrc(h.ons + rbase, in ? (uint32_t)nx * 8u : 0u), gi * 8, 0,
                                 0));
         };
 #pragma unroll
@@ -220,7 +211,7 @@ __device__ __forceinline__ void march_sweep_f32(const Ell &h, const Sweep &sw, c
                         xp1 = LV[s - 2][q3p];
                         old = s == 2 ? X0[qs] : LV[s - 3 < 0 ? 0 : s - 3][q3];
                     }
-                    const float4 w = lwt[2 * PI[qp] + dir];
+                    const float4 w = lwt[PI[qp]];
                     const float o = OO[qp];
                     float2 a = make_float2(o * x0.x, o * x0.y);
                     a = fraxpy_shifted(a, lane_prevf(x0), w.x);
@@ -233,7 +224,7 @@ __device__ __forceinline__ void march_sweep_f32(const Ell &h, const Sweep &sw, c
                         LL[qp] = fcmla(LL[qp], cf[s - 1], c);
                         if (s == K) {
                             const bool own = owned(rho);
-                            const int64_t row = (int64_t)(own ? cst + sgn * rho : 0) * nx;
+                            const int64_t row = (int64_t)(own ? j0 + rho - K : 0) * nx;
                             buf_stf(lacc + row, own ? rb : 0u, ovo, LL[qp]);
                         }
                     } else if constexpr (DBL) {
@@ -254,7 +245,7 @@ __device__ __forceinline__ void march_sweep_f32(const Ell &h, const Sweep &sw, c
                     }
                     if (s >= K - 1) {
                         const bool own = owned(rho);
-                        const int64_t row = (int64_t)(own ? cst + sgn * rho : 0) * nx;
+                        const int64_t row = (int64_t)(own ? j0 + rho - K : 0) * nx;
                         buf_stf((s == K ? out2 : out1) + row, own ? rb : 0u, ovo, c);
                     }
                 }

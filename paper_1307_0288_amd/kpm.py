@@ -85,7 +85,8 @@ class Adam(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("step_ms", C.c_double), ("step_launches", C.c_int64),
                 ("step_rows", C.c_int64), ("site_updates", C.c_int64),
-                ("step_bytes", C.c_int64), ("step_bytes_total", C.c_int64)]
+                ("step_bytes", C.c_int64), ("step_bytes_total", C.c_int64),
+                ("wide_ms", C.c_double), ("wide_launches", C.c_int64), ("wide_rows", C.c_int64)]
 
 
 _lib = None
@@ -696,7 +697,8 @@ def kpm_get_stats(sys: System) -> dict:
     _check(lib().kpm_get_stats(sys.handle, C.byref(s)))
     return dict(step_ms=s.step_ms, step_launches=s.step_launches, step_rows=s.step_rows,
                 site_updates=s.site_updates, step_bytes=s.step_bytes,
-                step_bytes_total=s.step_bytes_total)
+                step_bytes_total=s.step_bytes_total, wide_ms=s.wide_ms,
+                wide_launches=s.wide_launches, wide_rows=s.wide_rows)
 
 
 def kpm_reset_stats(sys: System):

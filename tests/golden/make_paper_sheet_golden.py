@@ -1,11 +1,13 @@
 """Oracle values for the paper-scale sheet, written once and stored.
 
-    python tests/golden/make_paper_sheet_golden.py [--threads T] [--out PATH]
+    python tests/golden/make_paper_sheet_golden.py [--threads T] [--vector-seed S] [--out PATH]
 
 The sample is the plain-method workload at paper scale: a periodic graphene
 sheet of 2828 x 1414 sites (1414 x 1414 two-atom cells, 3,998,792 sites),
 t = -2.7 eV, 0.5 % vacancies (seed 2000), Anderson disorder W = 0.1 eV (seed
-1000), E_s = 1.01 (3 |t| + W/2), and the random-phase vector of seed 3000.
+1000), E_s = 1.01 (3 |t| + W/2), and the random-phase vector of seed 3000
+(paper_sheet_oracle.npz) or of another seed S (paper_sheet_oracle_seedS.npz;
+seeds 3001 .. 3003 are vectors 1 .. 3 of the 64-vector workload).
 Stored (float64, numpy .npz without pickled objects):
 
   * dos_re, dos_im  [3000]     C_m = <phi|T_m(H~)|phi> (Eq. 46, Alg. 5)
@@ -37,18 +39,26 @@ sys.path.insert(0, ROOT)
 import kpm_inputs as ki  # noqa: E402
 import oracle  # noqa: E402
 
-OUT = os.path.join(HERE, "paper_sheet_oracle.npz")
 VECTOR_SEED = 3000
 
 
-def inputs():
-    """The paper-scale sheet's inputs (lattice arguments, vector) from the
-    shared generator, and the parameters of the run."""
+def golden_path(seed: int = VECTOR_SEED) -> str:
+    """Where the values for the vector of this seed are stored."""
+    name = "paper_sheet_oracle.npz" if seed == VECTOR_SEED else f"paper_sheet_oracle_seed{seed}.npz"
+    return os.path.join(HERE, name)
+
+
+OUT = golden_path()
+
+
+def inputs(seed: int = VECTOR_SEED):
+    """The paper-scale sheet's inputs (lattice arguments, vector of the given
+    seed) from the shared generator, and the parameters of the run."""
     p = ki.sheet_config("paper")
     n = p["nx"] * p["ny"]
     act = ki.vacancy_mask(n, p["vac"], 2000)
     ons = ki.anderson_onsite(n, p["w"], 1000)
-    phi = ki.random_phase(n, 1, VECTOR_SEED, act)[:, 0]
+    phi = ki.random_phase(n, 1, seed, act)[:, 0]
     return p, ons, act, phi
 
 
@@ -75,13 +85,15 @@ def _load_parts(path, digest):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=0, help="oracle threads (0: its default)")
-    ap.add_argument("--out", default=OUT)
+    ap.add_argument("--vector-seed", type=int, default=VECTOR_SEED)
+    ap.add_argument("--out", default="", help="default: the seed's file beside this script")
     ap.add_argument("--parts", default="dos,vac,msd",
                     help="parts to compute now (the others are kept from an earlier run)")
     args = ap.parse_args()
     os.environ["ORC_PROGRESS"] = "1"
     th = oracle.set_threads(args.threads)
-    p, ons, act, phi = inputs()
+    args.out = args.out or golden_path(args.vector_seed)
+    p, ons, act, phi = inputs(args.vector_seed)
     digest = input_digest(ons, act, phi)
     parts = _load_parts(args.out, digest)
     lat = oracle.graphene(p["nx"], p["ny"], "sheet", p["t"], ons, act)
@@ -89,7 +101,7 @@ def main():
     print(f"[golden] {lat.n} sites, {th} oracle threads, stored parts {sorted(parts)}", flush=True)
     meta = dict(nx=p["nx"], ny=p["ny"], t_ev=p["t"], w_ev=p["w"], vacancies=p["vac"],
                 e_scale=es, n_moments=nm, n_steps=ns, n_bessel=nb, dt_fs=dt,
-                onsite_seed=1000, vacancy_seed=2000, vector_seed=VECTOR_SEED,
+                onsite_seed=1000, vacancy_seed=2000, vector_seed=args.vector_seed,
                 input_sha256=digest)
 
     def save():

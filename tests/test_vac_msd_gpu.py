@@ -70,3 +70,25 @@ def test_other_shapes_run_the_loops_in_turn(case):
     assert np.array_equal(v2, kp.kpm_vac(sysg, d, *args))
     assert np.array_equal(m2, kp.kpm_msd(sysg, d, *args))
     sysg.close()
+
+
+def test_widest_launches_are_timed_on_their_own():
+    """kpm_get_stats splits out the runs of the widest launches: in the joint
+    loops these are the two-plane moment sets of t_1 .. t_n (2 N rows per
+    launch), the t_0 VAC set being a one-plane set."""
+    _need_gpu()
+    c = recipe("sheet", 200, 38, w=1.0, seed=7)
+    sysg = gpu_system(c)
+    d = sysg.upload(phases(c, 1, 7600))
+    n = c["nx"] * c["ny"]
+    kp.kpm_reset_stats(sysg)
+    kp.kpm_set_timing(sysg, True)
+    kp.kpm_vac_msd(sysg, d, 3, 0.5, 20, 97)
+    st = kp.kpm_get_stats(sysg)
+    kp.kpm_set_timing(sysg, False)
+    assert st["wide_rows"] == st["step_rows"] == 2 * n
+    # 97 moments: 11 eight-step passes and one of 7 steps per set
+    assert st["wide_launches"] == 3 * 12
+    assert st["step_launches"] == 4 * 12
+    assert 0 < st["wide_ms"] < st["step_ms"]
+    sysg.close()

@@ -77,6 +77,33 @@ def test_ragged_batch():
     sysg.close()
 
 
+def test_batch_in_the_strips():
+    """A batch whose samples are chain lattices: one vector takes the batch's
+    eight-step strips on the fixed scratch array too (bit-equal to
+    kpm_moments); two vectors run rows-major single steps there while
+    kpm_moments keeps them vector-major in the strips."""
+    _need_gpu()
+    import kpm_inputs as ki
+    cases = [recipe("sheet", 130, 26, w=1.0, vac=0.01, seed=22),
+             recipe("agnr", 90, 40, w=2.0, seed=23)]
+    sysg = kp.graphene_batch([dict(nx=c["nx"], ny=c["ny"], geometry=c["geometry"],
+                                   onsite=c["onsite"], active=c["active"],
+                                   e_scale=c["e_scale"]) for c in cases], "fp64")
+    for n_vec in (1, 2):
+        phi_h = np.concatenate([ki.random_phase(c["nx"] * c["ny"], n_vec, 3000 + 100 * s,
+                                                c["active"]) for s, c in enumerate(cases)])
+        d = sysg.upload(phi_h)
+        got = kp.kpm_moments_noalloc(sysg, d, d, 150)
+        ref = kp.kpm_moments(sysg, d, d, 150)
+        assert got.shape == ref.shape == (2, n_vec, 150)
+        if n_vec == 1:
+            assert kp.kpm_get_launch(sysg, 1)["steps"] == 8
+            assert rel_err(got, ref, float(np.abs(ref[..., 0]).max())) <= 1e-15
+        else:
+            assert rel_err(got, ref, float(np.abs(ref[..., 0]).max())) < 1e-13
+    sysg.close()
+
+
 def test_too_large_is_refused():
     _need_gpu()
     # 64 FP64 vectors on a 65536-site sheet need 2 x 64 MiB of states plus
