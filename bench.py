@@ -909,6 +909,7 @@ def batched(args):
         "fp32_states_gsu": round(res["fp32"]["gsu"], 3),
         "fp32_arith_gsu": round(res["fp32_arith"]["gsu"], 3),
         "plain_fp64_one_vector_gsu": round(plain, 3),
+        "moment_launch_us": {q: round(v["launch_us"], 2) for q, v in res.items()},
         "speedup_fp32_batched_vs_plain_fp64": round(f32["gsu"] / plain, 3),
         "speedup_fp32_vs_fp64_batched": round(f32["gsu"] / res["fp64"]["gsu"], 3),
         "sigma_rel_err_fp32_vs_fp64": err32,
