@@ -176,6 +176,9 @@ def main():
     ap.add_argument("--label-vectors", type=int, default=16,
                     help="learned workload: random-phase vectors per sample (the labels' "
                          "stochastic error falls as one over the square root of this)")
+    ap.add_argument("--graph-steps", type=int, default=3,
+                    help="paper workload: further steps with every moment set replayed from a "
+                         "captured hipGraph, reported as their median step time (0 skips them)")
     ap.add_argument("--onsite", default="f64", choices=["f64", "f32"],
                     help="paper workload: the generator's disorder draw (f64, default), or the "
                          "same draw rounded to float32 (f32: the library then stores the on-site "
@@ -271,6 +274,25 @@ def main():
     log("copy ceiling")
     ceiling = copy_ceiling_gbs()
 
+    # the same step with every moment set replayed from its captured graph
+    # (captured in the first, untimed step); median step time
+    graph = None
+    if args.graph_steps > 0:
+        kp.kpm_set_graphs(sysg, True)
+        step()
+        times = []
+        for k in range(args.graph_steps):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            step()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t1)
+            log(f"graph-replay step {k + 1}/{args.graph_steps} done")
+        kp.kpm_set_graphs(sysg, False)
+        med = float(np.median(times))
+        graph = {"steps": args.graph_steps, "median_ms_per_step": round(med * 1e3, 3),
+                 "gsu": round(st["site_updates"] / args.steps / med / 1e9, 4)}
+
     cpu = None
     if args.cpu_moments > 0:
         log(f"cpu baseline: oracle, {args.cpu_moments} moments, 1 core and all cores")
@@ -331,6 +353,7 @@ def main():
                                              "algorithmic_gbs": round(achieved_gbs(st), 1)},
                      "launch_shape": launch,
                      "two_plane_shape": shape2},
+        "graph_replay": graph,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

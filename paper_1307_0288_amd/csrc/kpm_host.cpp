@@ -1645,20 +1645,21 @@ std::vector<kpm_launch> autotune_candidates(const kpm_system *sys, int vs) {
         for (int gs : {64, 128, 512})
             cand.push_back(kpm_launch{2 * 256 / gs, 1, 0, 1, 5, 8, 1, 16 * 256 / gs, gs});
     }
-    // a batch of chain lattices: 4, 6 or 8-step strips in groups of one or four
-    // wavefronts, one vector per wavefront for several vectors (about 2048
-    // wavefronts over all planes, or twice that, shared out among the samples
-    // in proportion to their rows; at least 8 groups per sample)
+    // a batch of chain lattices: 4, 6 or 8-step strips in groups of one, two or
+    // four wavefronts, one vector per wavefront for several vectors (about
+    // 2048 wavefronts over all planes, or two or four times that, shared out
+    // among the samples in proportion to their rows; at least 8 groups per
+    // sample)
     if (sys->bstrips) {
         const int64_t minpg = 8 * (int64_t)sys->nseg;
         for (int ksteps : {4, 6, 8})
-            for (int gs : {64, 256}) {
+            for (int gs : {64, 128, 256}) {
                 const int wpg = gs / kpm::kWave;
                 if (vs == 0) {
                     cand.push_back(kpm_launch{8 / wpg, 1, 0, 1, 5, ksteps, 0, 0, gs});
                     continue;
                 }
-                for (int mult : {1, 2}) {
+                for (int mult : {1, 2, 4}) {
                     const int64_t per = ((int64_t)sys->cus * 8 * mult / wpg) >> vs;
                     const int64_t pg = std::max(minpg, std::min<int64_t>(65536, per / 8 * 8));
                     cand.push_back(kpm_launch{2, 1, 0, 1, 5, ksteps, 1, (int)pg, gs});
@@ -1684,7 +1685,15 @@ std::vector<kpm_launch> autotune_candidates(const kpm_system *sys, int vs) {
             }
         }
     }
-    return cand;
+    // each shape once (the grid formulas above can meet)
+    std::vector<kpm_launch> uniq;
+    for (const kpm_launch &l : cand) {
+        bool seen = false;
+        for (const kpm_launch &u : uniq)
+            seen = seen || std::memcmp(&u, &l, sizeof(kpm_launch)) == 0;
+        if (!seen) uniq.push_back(l);
+    }
+    return uniq;
 }
 
 template <typename V>

@@ -92,3 +92,24 @@ def test_widest_launches_are_timed_on_their_own():
     assert st["step_launches"] == 4 * 12
     assert 0 < st["wide_ms"] < st["step_ms"]
     sysg.close()
+
+
+def test_joint_loops_replayed_from_graphs():
+    """With hipGraph capture on, the joint call's moment sets (the one-plane
+    t_0 set and the two-plane sets, one graph each, reused at every time step)
+    replay bit-identical to direct launches, call after call."""
+    _need_gpu()
+    c = recipe("sheet", 200, 38, w=1.0, vac=0.02, seed=9)
+    sysg = gpu_system(c)
+    d = sysg.upload(phases(c, 1, 7700))
+    args = (3, 0.5, 20, 97)
+    ref = kp.kpm_vac_msd(sysg, d, *args)
+    kp.kpm_set_graphs(sysg, True)
+    for rep in range(3):
+        got = kp.kpm_vac_msd(sysg, d, *args)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), rep
+        e = d.clone()
+        kp.kpm_evolve(sysg, e, 0.2, 1, 12)                 # eager work in between
+        torch.cuda.synchronize()
+    kp.kpm_set_graphs(sysg, False)
+    sysg.close()
