@@ -89,6 +89,11 @@ typedef struct kpm_system kpm_system;
  *   active     [N] 0 marks a removed site (vacancy, Sec. 2), or NULL.
  *              Removed sites get no bonds and zero on-site energy.
  *   e_scale    E_s in eV (see Conventions).
+ * There is no spectral shift field: the graphene spectra this library targets
+ * are symmetric about zero, so H~ = H / e_scale (shift b = 0); a caller with
+ * a shifted spectrum subtracts b from the on-site energies.  There is no area
+ * field either: the area Omega enters only the sums (kpm_kpm_sum,
+ * kpm_ftm_sum, the learned targets), which take it as an argument.
  * Validation: indices in range, H real symmetric (each bond listed from both
  * ends with equal hopping), dx antisymmetric, e_scale >= Gershgorin bound.
  * Device form (chosen at creation, results agree to rounding): when the rows
