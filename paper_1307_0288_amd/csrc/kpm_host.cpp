@@ -1993,12 +1993,13 @@ kpm_status build_system(std::vector<Packed> &parts, kpm_precision prec, int devi
         for (int s = 0; s < nseg; ++s) al[s] = make_double2(0.0, -sys->es[s] / kHbar);
         st = upload((void **)&sys->d_alpha, al.data(), al.size() * sizeof(double2));
     }
-    // several vectors on a one-sample graphene lattice: one vector per
-    // wavefront in eight-step strips by default (measured fastest on the
+    // several vectors on a one-sample graphene lattice that takes the strips:
+    // one vector per wavefront in eight-step strips by default (measured fastest on the
     // paper-scale sheet with 64 vectors, in FP64 and with FP32 states), with
     // about 1024 work-groups over all planes; not when a KPM_* launch
     // override is set
-    if (st == KPM_OK && nseg == 1 && sys->d_flags && !launch_env_set()) {
+    if (st == KPM_OK && nseg == 1 && sys->d_flags && sys->multi_steps(0, sys->launch[0]) > 1 &&
+        !launch_env_set()) {
         for (int v = 1; v < 7; ++v) {
             const kpm_launch l{2, 1, 0, 1, 5, 8, 1, std::max(16, 1024 >> v)};
             sys->launch[v] = sys->launch_dbl[v] = l;

@@ -264,6 +264,11 @@ def test_default_shape_for_several_vectors():
     for n_vec in (2, 8, 64):
         assert kp.kpm_get_launch(sysg, n_vec) == planar(8, max(16, 1024 // n_vec))
     sysg.close()
+    # a ribbon of 16 chains takes no strips: several vectors stay side by side
+    r = recipe("zgnr", 200, 16, w=1.0, seed=74)
+    rib = gpu_system(r)
+    assert kp.kpm_get_launch(rib, 8).get("vectors_per_wave", 0) == 0
+    rib.close()
 
 
 @pytest.mark.parametrize("n_vec", [1, 8])
