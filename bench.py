@@ -220,7 +220,9 @@ def main():
     sysg = kp.graphene_system(p["nx"], p["ny"], "sheet", p["t"], ons, act, p["e_scale"], "fp64")
     phi = sysg.upload(phi_h)
     nm, ns, nb, dt = p["n_moments"], p["n_steps"], p["n_bessel"], p["dt_fs"]
-    launch = kp.kpm_autotune(sysg, phi, 50)
+    # 200 recursion steps per candidate and round (25 eight-step passes): shapes
+    # of the same wavefront count differ by about 2 %, within shorter rounds' noise
+    launch = kp.kpm_autotune(sysg, phi, 200)
     log(f"autotuned launch shape: {launch}")
 
     def step():
