@@ -104,13 +104,17 @@ def cpu_baseline(p, lat_args, n_moments: int):
             "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
-def joint_plane_groups(launch: dict) -> int:
-    """Work-groups per plane of the joint VAC / MSD moment sets: half the
-    one-vector grid (groups per CU times CUs, a multiple of the 8 XCDs)."""
+def joint_shape(launch: dict) -> dict:
+    """Launch shape of the joint VAC / MSD moment sets (two vector planes):
+    the one-vector grid's wavefronts (groups per CU times CUs, a multiple of
+    the 8 XCDs, times the wavefronts per group) shared between the two planes
+    in groups of 256 threads."""
     import torch
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     nwg = max(8, cus * launch["groups_per_cu"] // 8 * 8)
-    return max(8, nwg // 2 // 8 * 8)
+    waves = nwg * launch.get("group_size", 256) // 64
+    shape = {k: v for k, v in launch.items() if k != "group_size"}
+    return dict(shape, vectors_per_wave=1, plane_groups=max(8, waves // 4 // 2 // 8 * 8))
 
 
 def copy_ceiling_gbs(gib: float = 1.0, reps: int = 10) -> float:
@@ -262,7 +266,7 @@ def main():
     # the VAC and MSD moment sets keep only real parts
     kname = moment_kernel_name("double2", launch, False, real=True, onsf=onsf)
     tfile = TRAFFIC_FILE2 if two else TRAFFIC_FILE
-    shape2 = dict(launch, vectors_per_wave=1, plane_groups=joint_plane_groups(launch))
+    shape2 = joint_shape(launch)
     traffic = measured_traffic(tfile, st["step_rows"], shape2, kname if two else "")
     sq = valu_record(SQ_FILE, st["step_rows"], shape2, kname)
     launch_s = launch_ms * 1e-3

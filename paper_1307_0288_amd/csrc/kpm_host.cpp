@@ -1450,10 +1450,16 @@ kpm_status vac_msd_impl(kpm_system *sys, int vshift, const void *phi, int nsteps
     }
     kpm::Sweep sw0;
     KPM_TRY(sys->sweep_with(0, l0, &sw0));
-    // the one-vector shape on two planes, half its work-groups on each
+    // the one-vector shape on two planes: its wavefronts shared between the
+    // planes, in groups of kBlock threads whatever the one-vector group size
+    // (two-plane passes in groups of 64 threads measured 2.5 % slower on the
+    // paper-scale sheet than in groups of 256)
     kpm_launch l2 = l0;
     l2.vectors_per_wave = 1;
-    l2.plane_groups = std::max(kpm::kXcds, sw0.nwg / 2 / kpm::kXcds * kpm::kXcds);
+    l2.group_size = 0;
+    const int waves = sw0.nwg * strip_waves(l0);
+    l2.plane_groups = std::max(kpm::kXcds, waves / (kpm::kBlock / kpm::kWave) / 2 / kpm::kXcds *
+                                               kpm::kXcds);
     KPM_TRY(sys->ensure_vecs(19, 1));                 // every scratch state holds two planes
     auto vec = [&](int i) { return (V *)sys->vecs[i]; };
     const size_t sb = sys->state_bytes(0);           // one plane
