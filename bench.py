@@ -29,7 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 import kpm_inputs as ki  # noqa: E402
-from profile_run import (float_onsite, measured_traffic, moment_kernel_name,  # noqa: E402
+from profile_run import (float_onsite, joint_shape, measured_traffic, moment_kernel_name,  # noqa: E402
                          multi_step)
 
 HBM_PEAK_GBS = 8000.0
@@ -102,19 +102,6 @@ def cpu_baseline(p, lat_args, n_moments: int):
             "one_core": {"value": round(rates[1][0], 5), "cores": 1,
                          "seconds": round(rates[1][1], 1)},
             "nproc": os.cpu_count(), "cpu_model": cpu_model()}
-
-
-def joint_shape(launch: dict) -> dict:
-    """Launch shape of the joint VAC / MSD moment sets (two vector planes):
-    the one-vector grid's wavefronts (groups per CU times CUs, a multiple of
-    the 8 XCDs, times the wavefronts per group) shared between the two planes
-    in groups of 256 threads."""
-    import torch
-    cus = torch.cuda.get_device_properties(0).multi_processor_count
-    nwg = max(8, cus * launch["groups_per_cu"] // 8 * 8)
-    waves = nwg * launch.get("group_size", 256) // 64
-    shape = {k: v for k, v in launch.items() if k != "group_size"}
-    return dict(shape, vectors_per_wave=1, plane_groups=max(8, waves // 4 // 2 // 8 * 8))
 
 
 def copy_ceiling_gbs(gib: float = 1.0, reps: int = 10) -> float:
@@ -261,12 +248,15 @@ def main():
                  else st["step_ms"] / max(st["step_launches"], 1))
     bytes_launch = st["step_bytes"]
     two = multi_step(launch)
-    bpu = bytes_launch / st["step_rows"] / (launch["steps"] if two else 1)
+    # the two-plane passes' shape (nine steps per pass where the one-vector
+    # shape takes eight)
+    shape2 = joint_shape(launch, torch.cuda.get_device_properties(0).multi_processor_count)
+    bpu = bytes_launch / st["step_rows"] / ((shape2 if wide else launch)["steps"] if two else 1)
     achieved = bytes_launch / (launch_ms * 1e-3) / 1e9 if wide else achieved_gbs(st)
     # the VAC and MSD moment sets keep only real parts
-    kname = moment_kernel_name("double2", launch, False, real=True, onsf=onsf)
+    kname = moment_kernel_name("double2", shape2 if wide else launch, False, real=True,
+                               onsf=onsf)
     tfile = TRAFFIC_FILE2 if two else TRAFFIC_FILE
-    shape2 = joint_shape(launch)
     traffic = measured_traffic(tfile, st["step_rows"], shape2, kname if two else "")
     sq = valu_record(SQ_FILE, st["step_rows"], shape2, kname)
     launch_s = launch_ms * 1e-3

@@ -1457,6 +1457,10 @@ kpm_status vac_msd_impl(kpm_system *sys, int vshift, const void *phi, int nsteps
     kpm_launch l2 = l0;
     l2.vectors_per_wave = 1;
     l2.group_size = 0;
+    // both sets keep only real parts: with FP64 states the eight-step strips
+    // take nine steps per pass
+    if (std::is_same<V, double2>::value && l0.steps == kpm::kMaxMarchSteps && l0.tiled >= 3)
+        l2.steps = kpm::kReMarchSteps;
     const int waves = sw0.nwg * strip_waves(l0);
     l2.plane_groups = std::max(kpm::kXcds, waves / (kpm::kBlock / kpm::kWave) / 2 / kpm::kXcds *
                                                kpm::kXcds);

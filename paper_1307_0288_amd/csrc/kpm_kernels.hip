@@ -1109,16 +1109,24 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
     // keeps no further pointers live in scalar registers
     const int64_t e0 = geo.e0;
     constexpr int TC = kWave - 2 * K;                  // columns per strip
-    constexpr int P = kRowRing, PS = kStateRing, DS = kDs, DR = kRowRing - 1 - K;
+    // the states are prefetched DS rows ahead (two at nine steps, which frees
+    // the registers of the ninth level ring)
+    constexpr int P = kRowRing, PS = kStateRing, DS = K >= 9 ? 2 : kDs,
+                  DR = kRowRing - 1 - K;
     // phi_L rows are loaded DL ahead and used through K iterations after their
-    // own (fewer rows ahead at K = 8 keep that kernel within its registers)
-    constexpr int DL = K >= 8 ? (sizeof(V) == sizeof(double2) ? 2 : 1) : (DS < DR ? DS : DR);
+    // own (fewer rows ahead from K = 8 on keep those kernels within their
+    // registers)
+    constexpr int DL = K >= 9 ? 1
+                              : (K >= 8 ? (sizeof(V) == sizeof(double2) ? 2 : 1) : (DS < DR ? DS : DR));
     constexpr int NA = BES ? 1 : (DBL ? 2 * K : K);
     static_assert(DR >= 1 && DS + 3 <= PS && P % PS == 0 && PS % 3 == 0 && DL + K < P,
                   "ring sizes");
     // up to 5 steps the row terms are formed once per row, ahead of their first
     // use; with more levels their registers are needed for the level rings
-    static_assert(K >= 2 && K <= 8, "steps per pass");
+    // (nine steps: the real-part pass with FP64 states only)
+    static_assert(K >= 2 && (K <= kMaxMarchSteps || (K == kReMarchSteps && RE &&
+                                                      std::is_same<V, double2>::value)),
+                  "steps per pass");
     constexpr bool kAhead = K <= 5;
     const double t = geo.t, inv_es = geo.inv_es;
     // per pattern and marching direction d: (previous column, next column),
@@ -1505,8 +1513,11 @@ bool launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
     const bool onsf = h.onsf != nullptr;
     // the step counts each form is built for: LDS tiles 2, register tiles
     // 2 .. 4, marching strips 2 .. 8
-    if (lat.k < 2 || lat.k > (lat.reg == 2 ? kMaxMarchSteps : (lat.reg == 1 ? 4 : 2)))
-        return false;
+    // (the real-part strips with FP64 states also nine)
+    const int kmax = lat.reg == 2 ? (re && !dbl && std::is_same<V, double2>::value ? kReMarchSteps
+                                                                                 : kMaxMarchSteps)
+                                  : (lat.reg == 1 ? 4 : 2);
+    if (lat.k < 2 || lat.k > kmax) return false;
     // vector-major states and batches run only in the marching strips
     if ((sw.nplanes > 1 || sw.seg) && lat.reg != 2) return false;
     if constexpr (std::is_same<V, float2>::value)
@@ -1538,7 +1549,12 @@ bool launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
 #define KPM_REG(ONSF_, DBL_)                                                                  \
     do {                                                                                      \
         if (lat.reg == 2) {                                                                   \
-            if (lat.k == 8) KPM_MARCHK(ONSF_, DBL_, 8);                                       \
+            if (lat.k == kReMarchSteps) {                                                     \
+                if constexpr (std::is_same<V, double2>::value && !(DBL_))                     \
+                    hipLaunchKernelGGL((k_moment_march_re<V, ONSF_, kReMarchSteps>),          \
+                                       dim3(sw.nwg, sw.nplanes), dim3(sw.wpg * kWave), 0, s,  \
+                                       h, sw, lat, p1, p0, out1, out2, phil, partial, slot);  \
+            } else if (lat.k == 8) KPM_MARCHK(ONSF_, DBL_, 8);                                \
             else if (lat.k == 7) KPM_MARCHK(ONSF_, DBL_, 7);                                  \
             else if (lat.k == 6) KPM_MARCHK(ONSF_, DBL_, 6);                                  \
             else if (lat.k == 5) KPM_MARCHK(ONSF_, DBL_, 5);                                  \

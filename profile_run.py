@@ -64,6 +64,21 @@ def float_onsite(onsite) -> bool:
     return bool(np.array_equal(a.astype(np.float32).astype(np.float64), a))
 
 
+def joint_shape(launch: dict, cus: int, fp64: bool = True) -> dict:
+    """Launch shape of the joint VAC / MSD moment sets (two vector planes)
+    under the one-vector shape `launch` on a GPU of `cus` compute units: the
+    one-vector grid's wavefronts (groups per CU times CUs, a multiple of the 8
+    XCDs, times the wavefronts per group) shared between the two planes in
+    groups of 256 threads; with FP64 states the eight-step strips take nine
+    steps per pass (both sets keep only real parts)."""
+    nwg = max(8, cus * launch["groups_per_cu"] // 8 * 8)
+    waves = nwg * launch.get("group_size", 256) // 64
+    shape = {k: v for k, v in launch.items() if k != "group_size"}
+    if fp64 and shape.get("steps") == 8 and shape.get("tiled", 0) >= 3:
+        shape["steps"] = 9
+    return dict(shape, vectors_per_wave=1, plane_groups=max(8, waves // 4 // 2 // 8 * 8))
+
+
 def moment_kernel_name(v: str, launch: dict, dbl: bool, n_vec: int = 1,
                        real: bool = False, onsf: bool = True, arith32: bool = False) -> str:
     """Instantiation of the moment step for a graphene system from the builder
@@ -169,8 +184,8 @@ def _mean(vals):
 def summarize(fetch_dir: str, write_dir: str, meta_path: str, out_path: str):
     with open(meta_path) as f:
         meta = json.load(f)
-    # dispatches of the kernel named in the meta (any instantiation of it)
-    step_prefix = "void kpm::" + meta["kernel"].split("<")[0] + "<"
+    # dispatches of the kernel instantiation named in the meta
+    want = meta["kernel"].split(" ")[0]
     res = {}
     for key, d in (("fetch", fetch_dir), ("write", write_dir)):
         rows = _read_counter(d)
@@ -179,8 +194,7 @@ def summarize(fetch_dir: str, write_dir: str, meta_path: str, out_path: str):
         copies = _dispatch_sums(r for r in rows if r["Kernel_Name"] == "__amd_rocclr_copyBuffer")
         big = max(copies.values())
         copy_kib = _mean(v for v in copies.values() if v >= 0.5 * big)
-        step = _mean(float(r["Counter_Value"]) for r in rows
-                     if r["Kernel_Name"].startswith(step_prefix))
+        step = _mean(float(r["Counter_Value"]) for r in rows if _is_kernel(r["Kernel_Name"], want))
         res[key] = (step, meta["copy_mib"] * 1024.0 / copy_kib)
     fetch_kib, fs = res["fetch"]
     write_kib, ws = res["write"]
@@ -215,10 +229,10 @@ def summarize_sq(dirs, meta_path: str, out_path: str):
     instructions per launch are what bench.py reads for its VALU roof."""
     with open(meta_path) as f:
         meta = json.load(f)
-    prefix = "void kpm::" + meta["kernel"].split("<")[0] + "<"
+    want = meta["kernel"].split(" ")[0]
     vals = {}
     for d in dirs:
-        rows = [r for r in _read_counter(d) if r["Kernel_Name"].startswith(prefix)]
+        rows = [r for r in _read_counter(d) if _is_kernel(r["Kernel_Name"], want)]
         per = {}
         for r in rows:
             key = (r["Counter_Name"], r["Dispatch_Id"])
@@ -248,10 +262,20 @@ def _short_kernel_name(name: str) -> str:
     return name.split("(")[0] if "(" in name else name
 
 
-def trace_table(stats_csv: str, top: int) -> str:
-    """Markdown table of the `top` kernels of a rocprofv3 --stats kernel summary."""
+def _is_kernel(name: str, want: str) -> bool:
+    """Whether a profiler's kernel name is the instantiation `want` (written
+    as moment_kernel_name writes it: no namespace, no spaces)."""
+    return _short_kernel_name(name).removeprefix("kpm::").replace(" ", "") == want
+
+
+def trace_table(stats_csv: str, top: int, only: str = "") -> str:
+    """Markdown table of the `top` kernels of a rocprofv3 --stats kernel summary
+    (only those whose short name matches the regular expression `only`, if given)."""
+    import re
     with open(stats_csv) as f:
         rows = list(csv.DictReader(f))
+    if only:
+        rows = [r for r in rows if re.search(only, _short_kernel_name(r["Name"]))]
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     out = ["| kernel | calls | avg (us) | min (us) | max (us) | share of GPU time |",
            "|---|---|---|---|---|---|"]
@@ -271,6 +295,10 @@ def main():
     ap.add_argument("--real", action="store_true",
                     help="a real-part moment set as the VAC takes them (kpm_vac, no time steps: "
                          "the moments of V phi)")
+    ap.add_argument("--joint", type=int, default=0, metavar="STEPS",
+                    help="the joint VAC / MSD call (kpm_vac_msd) over this many time steps: "
+                         "its moment sets of t_1 .. t_STEPS run as two vector planes, the "
+                         "kernel summarised (one vector; --launch gives the one-vector shape)")
     ap.add_argument("--copy-mib", type=int, default=512)
     ap.add_argument("--copies", type=int, default=3)
     ap.add_argument("--launch", default="",
@@ -288,9 +316,11 @@ def main():
     ap.add_argument("--trace-table", metavar="KERNEL_STATS_CSV",
                     help="print a markdown table of a --stats kernel summary")
     ap.add_argument("--top", type=int, default=12)
+    ap.add_argument("--only", default="", help="--trace-table: kernels whose name matches this "
+                                               "regular expression")
     args = ap.parse_args()
     if args.trace_table:
-        print(trace_table(args.trace_table, args.top))
+        print(trace_table(args.trace_table, args.top, args.only))
         return
     if args.summarize:
         return summarize(args.summarize[0], args.summarize[1], args.meta, args.out)
@@ -317,7 +347,12 @@ def main():
     launch = kp.kpm_get_launch(sysg, args.n_vec)
     print(f"launch shape: {launch}", flush=True)
     kp.kpm_reset_stats(sysg)
-    if args.doubled:
+    if args.joint:
+        if args.n_vec != 1:
+            raise SystemExit("--joint runs one vector")
+        vac, _ = kp.kpm_vac_msd(sysg, phi, args.joint, p["dt_fs"], p["n_bessel"], args.moments)
+        mu = vac[:, 0, :]
+    elif args.doubled:
         mu = kp.kpm_moments_doubled(sysg, phi, args.moments)
     elif args.real:
         mu = kp.kpm_vac(sysg, phi, 0, p["dt_fs"], p["n_bessel"], args.moments)[:, 0, :]
@@ -341,13 +376,21 @@ def main():
             cmd.append("--doubled")
         if args.real:
             cmd.append("--real")
+        if args.joint:
+            cmd.append(f"--joint {args.joint}")
         if args.launch:
             cmd.append(f"--launch {args.launch}")
         if args.autotune:
             cmd.append(f"--autotune {args.autotune}")
+        if args.joint:          # the two-plane passes: real parts, two vectors
+            launch = joint_shape(launch, torch.cuda.get_device_properties(0).multi_processor_count,
+                                 args.precision == "fp64")
+            kname = moment_kernel_name(v, launch, False, 2, True, onsf)
+        else:
+            kname = moment_kernel_name(v, launch, args.doubled, args.n_vec, args.real, onsf,
+                                       args.precision == "fp32_arith")
         meta = {
-            "kernel": f"{moment_kernel_name(v, launch, args.doubled, args.n_vec, args.real, onsf, args.precision == 'fp32_arith')} "
-                      f"({args.precision}, {args.n_vec} vector(s))",
+            "kernel": f"{kname} ({args.precision}, {2 if args.joint else args.n_vec} vector(s))",
             "kernel_sha": kernel_sha(launch),
             "step_rows": st["step_rows"],
             "step_bytes": st["step_bytes"],

@@ -28,8 +28,11 @@ def test_summary_calibrates_on_the_large_copies_only(tmp_path):
     other = "void kpm::k_moment_march<HIP_vector_type<double, 2u>, true, false, 8>(kpm::Ell)"
     copy = "__amd_rocclr_copyBuffer"
     # counters read half the true KiB for copies (a factor 2 to recover)
+    tail = "void kpm::k_moment_march_re<HIP_vector_type<double, 2u>, true, 5>(kpm::Ell)"
+    # another kernel and a shorter pass of the same kernel (a moment set's
+    # tail) stay out of the launch's average
     fetch = [(copy, 512, 32768.0), (kern, 1024, 1000.0), (kern, 1024, 1200.0),
-             (other, 1024, 9999.0)] + [(copy, 512, 262144.0)] * 3
+             (other, 1024, 9999.0), (tail, 1024, 7777.0)] + [(copy, 512, 262144.0)] * 3
     write = [(copy, 512, 65536.0), (kern, 1024, 500.0), (kern, 1024, 500.0)] + \
             [(copy, 512, 524288.0)] * 3
     _counters(tmp_path / "f", fetch)
@@ -76,3 +79,18 @@ def test_reported_kernel_names():
     tiles = dict(STRIPS, tiled=2, steps=4)
     assert pr.moment_kernel_name("double2", tiles, False, real=True) == \
         "k_moment_stepk<double2,true,false,4,4>"
+
+
+def test_joint_shape():
+    """The two-plane shape of the joint VAC / MSD call: the one-vector grid's
+    wavefronts over both planes in groups of 256 threads, nine steps per pass
+    where the one-vector FP64 strips take eight."""
+    j = pr.joint_shape(STRIPS, 256)
+    assert j == dict(STRIPS, steps=9, vectors_per_wave=1, plane_groups=256)
+    small = dict(STRIPS, groups_per_cu=8, group_size=64)
+    assert pr.joint_shape(small, 256) == dict(STRIPS, groups_per_cu=8, steps=9,
+                                              vectors_per_wave=1, plane_groups=256)
+    assert pr.joint_shape(STRIPS, 256, fp64=False)["steps"] == 8
+    assert pr.joint_shape(dict(STRIPS, steps=6), 256)["steps"] == 6
+    assert pr.moment_kernel_name("double2", j, False, 2, real=True, onsf=False) == \
+        "k_moment_march_re<double2,false,9>"
