@@ -248,7 +248,7 @@ def main():
                  else st["step_ms"] / max(st["step_launches"], 1))
     bytes_launch = st["step_bytes"]
     two = multi_step(launch)
-    # the two-plane passes' shape (nine steps per pass where the one-vector
+    # the two-plane passes' shape (ten steps per pass where the one-vector
     # shape takes eight)
     shape2 = joint_shape(launch, torch.cuda.get_device_properties(0).multi_processor_count)
     bpu = bytes_launch / st["step_rows"] / ((shape2 if wide else launch)["steps"] if two else 1)

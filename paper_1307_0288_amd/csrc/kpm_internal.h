@@ -165,9 +165,9 @@ bool launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
 
 // Coefficients of the K steps of one multi-step propagator pass.
 constexpr int kMaxMarchSteps = 8;
-// Steps per pass of the real-part strips with FP64 states (the VAC and MSD
-// moment sets), one more than the other strips take
-constexpr int kReMarchSteps = 9;
+// Most steps per pass of the real-part strips with FP64 states (the VAC and
+// MSD moment sets): two more than the other strips take
+constexpr int kReMarchSteps = 10;
 struct CoefK {
     double2 c[kMaxMarchSteps];
 };

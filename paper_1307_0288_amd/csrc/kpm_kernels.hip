@@ -1123,10 +1123,15 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
                   "ring sizes");
     // up to 5 steps the row terms are formed once per row, ahead of their first
     // use; with more levels their registers are needed for the level rings
-    // (nine steps: the real-part pass with FP64 states only)
-    static_assert(K >= 2 && (K <= kMaxMarchSteps || (K == kReMarchSteps && RE &&
+    // (nine and ten steps: the real-part pass with FP64 states only)
+    static_assert(K >= 2 && (K <= kMaxMarchSteps || (K <= kReMarchSteps && RE &&
                                                       std::is_same<V, double2>::value)),
                   "steps per pass");
+    // from ten steps on, each lane's real-part sums live in LDS (one slot per
+    // level and thread, updated with the same fused multiply-adds), which
+    // frees their registers for the level rings
+    constexpr bool kAccLds = RE && K >= 10;
+    __shared__ double lsum[kAccLds ? K : 1][kAccLds ? kMaxStripBlock : 1];
     constexpr bool kAhead = K <= 5;
     const double t = geo.t, inv_es = geo.inv_es;
     // per pattern and marching direction d: (previous column, next column),
@@ -1158,6 +1163,9 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
     double2 acc[NA];
 #pragma unroll
     for (int k = 0; k < NA; ++k) acc[k] = make_double2(0.0, 0.0);
+    if constexpr (kAccLds)
+#pragma unroll
+        for (int k = 0; k < K; ++k) lsum[k][threadIdx.x] = 0.0;
     for (int b = b0 + wloc; b < b1; b += wn) {
         const int strip = b % nst;                     // across the strips first
         const int j0 = (b / nst) * J, c0 = strip * TC;
@@ -1302,7 +1310,11 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
                         acc[2 * (s - 1) + 1].x =
                             fma(xw.x, c.x, fma(xw.y, c.y, acc[2 * (s - 1) + 1].x));
                     } else if (RE) {
-                        acc[s - 1].x = fma(LL[qp].x, c.x, fma(LL[qp].y, c.y, acc[s - 1].x));
+                        if constexpr (kAccLds)
+                            lsum[s - 1][threadIdx.x] = fma(
+                                LL[qp].x, c.x, fma(LL[qp].y, c.y, lsum[s - 1][threadIdx.x]));
+                        else
+                            acc[s - 1].x = fma(LL[qp].x, c.x, fma(LL[qp].y, c.y, acc[s - 1].x));
                     } else {
                         acc[s - 1] = cdot_acc(acc[s - 1], LL[qp], c);
                     }
@@ -1319,6 +1331,9 @@ __device__ __forceinline__ void march_sweep(const Ell &h, const Sweep &sw, const
         }
     }
     if (BES) return;
+    if constexpr (kAccLds)
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k].x = lsum[k][threadIdx.x];
     const int nw = sw.nwg;
 #pragma unroll
     for (int k = 0; k < NA; ++k) block_sum_waves(acc[k], partial + part_index(sw, slot + k));
@@ -1549,11 +1564,19 @@ bool launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
 #define KPM_REG(ONSF_, DBL_)                                                                  \
     do {                                                                                      \
         if (lat.reg == 2) {                                                                   \
-            if (lat.k == kReMarchSteps) {                                                     \
-                if constexpr (std::is_same<V, double2>::value && !(DBL_))                     \
-                    hipLaunchKernelGGL((k_moment_march_re<V, ONSF_, kReMarchSteps>),          \
-                                       dim3(sw.nwg, sw.nplanes), dim3(sw.wpg * kWave), 0, s,  \
-                                       h, sw, lat, p1, p0, out1, out2, phil, partial, slot);  \
+            if (lat.k > kMaxMarchSteps) {                                                     \
+                if constexpr (std::is_same<V, double2>::value && !(DBL_)) {                   \
+                    if (lat.k == 10)                                                          \
+                        hipLaunchKernelGGL((k_moment_march_re<V, ONSF_, 10>),                 \
+                                           dim3(sw.nwg, sw.nplanes), dim3(sw.wpg * kWave), 0, \
+                                           s, h, sw, lat, p1, p0, out1, out2, phil, partial,  \
+                                           slot);                                             \
+                    else                                                                      \
+                        hipLaunchKernelGGL((k_moment_march_re<V, ONSF_, 9>),                  \
+                                           dim3(sw.nwg, sw.nplanes), dim3(sw.wpg * kWave), 0, \
+                                           s, h, sw, lat, p1, p0, out1, out2, phil, partial,  \
+                                           slot);                                             \
+                }                                                                             \
             } else if (lat.k == 8) KPM_MARCHK(ONSF_, DBL_, 8);                                \
             else if (lat.k == 7) KPM_MARCHK(ONSF_, DBL_, 7);                                  \
             else if (lat.k == 6) KPM_MARCHK(ONSF_, DBL_, 6);                                  \

@@ -69,13 +69,13 @@ def joint_shape(launch: dict, cus: int, fp64: bool = True) -> dict:
     under the one-vector shape `launch` on a GPU of `cus` compute units: the
     one-vector grid's wavefronts (groups per CU times CUs, a multiple of the 8
     XCDs, times the wavefronts per group) shared between the two planes in
-    groups of 256 threads; with FP64 states the eight-step strips take nine
+    groups of 256 threads; with FP64 states the eight-step strips take ten
     steps per pass (both sets keep only real parts)."""
     nwg = max(8, cus * launch["groups_per_cu"] // 8 * 8)
     waves = nwg * launch.get("group_size", 256) // 64
     shape = {k: v for k, v in launch.items() if k != "group_size"}
     if fp64 and shape.get("steps") == 8 and shape.get("tiled", 0) >= 3:
-        shape["steps"] = 9
+        shape["steps"] = 10
     return dict(shape, vectors_per_wave=1, plane_groups=max(8, waves // 4 // 2 // 8 * 8))
 
 

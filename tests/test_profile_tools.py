@@ -83,14 +83,14 @@ def test_reported_kernel_names():
 
 def test_joint_shape():
     """The two-plane shape of the joint VAC / MSD call: the one-vector grid's
-    wavefronts over both planes in groups of 256 threads, nine steps per pass
+    wavefronts over both planes in groups of 256 threads, ten steps per pass
     where the one-vector FP64 strips take eight."""
     j = pr.joint_shape(STRIPS, 256)
-    assert j == dict(STRIPS, steps=9, vectors_per_wave=1, plane_groups=256)
+    assert j == dict(STRIPS, steps=10, vectors_per_wave=1, plane_groups=256)
     small = dict(STRIPS, groups_per_cu=8, group_size=64)
-    assert pr.joint_shape(small, 256) == dict(STRIPS, groups_per_cu=8, steps=9,
+    assert pr.joint_shape(small, 256) == dict(STRIPS, groups_per_cu=8, steps=10,
                                               vectors_per_wave=1, plane_groups=256)
     assert pr.joint_shape(STRIPS, 256, fp64=False)["steps"] == 8
     assert pr.joint_shape(dict(STRIPS, steps=6), 256)["steps"] == 6
     assert pr.moment_kernel_name("double2", j, False, 2, real=True, onsf=False) == \
-        "k_moment_march_re<double2,false,9>"
+        "k_moment_march_re<double2,false,10>"

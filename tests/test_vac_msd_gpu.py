@@ -88,10 +88,10 @@ def test_widest_launches_are_timed_on_their_own():
     kp.kpm_set_timing(sysg, False)
     assert st["wide_rows"] == st["step_rows"] == 2 * n
     # 97 moments (95 recursion steps after C_0, C_1): the one-plane t_0 set in
-    # 11 eight-step passes and one of 7 steps, the two-plane sets in 10
-    # nine-step passes and one of 5 steps
-    assert st["wide_launches"] == 3 * 11
-    assert st["step_launches"] == 12 + 3 * 11
+    # 11 eight-step passes and one of 7 steps, the two-plane sets in 9 ten-step
+    # passes and one of 5 steps
+    assert st["wide_launches"] == 3 * 10
+    assert st["step_launches"] == 12 + 3 * 10
     assert 0 < st["wide_ms"] < st["step_ms"]
     sysg.close()
 
