@@ -1576,6 +1576,8 @@ bool launch_moment_multi(const Ell &h, const Sweep &sw, const Lat2 &lat, const V
                                            dim3(sw.nwg, sw.nplanes), dim3(sw.wpg * kWave), 0, \
                                            s, h, sw, lat, p1, p0, out1, out2, phil, partial,  \
                                            slot);                                             \
+                } else {                                                                      \
+                    return false;           /* no such pass (excluded by kmax above) */       \
                 }                                                                             \
             } else if (lat.k == 8) KPM_MARCHK(ONSF_, DBL_, 8);                                \
             else if (lat.k == 7) KPM_MARCHK(ONSF_, DBL_, 7);                                  \
