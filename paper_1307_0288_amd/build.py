@@ -22,7 +22,9 @@ LIB = os.path.join(PKG, "libkpm.so")
 OBJDIR = os.path.join(PKG, "_build")
 SOURCES = ["kpm_kernels.hip", "kpm_host.cpp", "kpm_error.cpp", "kpm_lattice.cpp",
            "kpm_transport.cpp", "kpm_learned.cpp", "kpm_mlp.hip", "kpm_noalloc.hip",
-           "kpm_march32.hip"]
+           "kpm_march32.hip", "kpm_march_long.hip"]
+# per-file device flags: the long real-part strips take the max-ILP schedule
+EXTRA = {"kpm_march_long.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
 ARCH = "gfx950"
 
 
@@ -51,7 +53,8 @@ def build(verbose: bool = False) -> str:
         # device code: the compiler's per-kernel resource report (registers,
         # spills, LDS) goes to _build/<source>.resources
         report = ["-Rpass-analysis=kernel-resource-usage"] if src.endswith(".hip") else []
-        cmd = [hipcc] + flags() + lang + report + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc] + flags() + EXTRA.get(src, []) + lang + report + \
+            ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

@@ -168,6 +168,12 @@ constexpr int kMaxMarchSteps = 8;
 // Most steps per pass of the real-part strips with FP64 states (the VAC and
 // MSD moment sets): two more than the other strips take
 constexpr int kReMarchSteps = 10;
+// Launch of those real-part strips of 9 or 10 steps (kpm_march_long.hip);
+// false for any other step count or a lattice that does not take the strips.
+bool launch_moment_march_re_long(const Ell &h, const Sweep &sw, const Lat2 &lat,
+                                 const double2 *p1, const double2 *p0, double2 *out1,
+                                 double2 *out2, const double2 *phil, double2 *partial, int slot,
+                                 hipStream_t s);
 struct CoefK {
     double2 c[kMaxMarchSteps];
 };

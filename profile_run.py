@@ -39,6 +39,8 @@ if ROOT not in sys.path:
 KERNEL_SRC = os.path.join(ROOT, "paper_1307_0288_amd", "csrc", "kpm_kernels.hip")
 DEVICE_SRC = os.path.join(ROOT, "paper_1307_0288_amd", "csrc", "kpm_device.h")
 MARCH32_SRC = os.path.join(ROOT, "paper_1307_0288_amd", "csrc", "kpm_march32.hip")
+MARCH_H = os.path.join(ROOT, "paper_1307_0288_amd", "csrc", "kpm_march.h")
+MARCH_LONG_SRC = os.path.join(ROOT, "paper_1307_0288_amd", "csrc", "kpm_march_long.hip")
 
 
 def _read(path: str) -> str:
@@ -110,7 +112,9 @@ def kernel_sha(launch: dict | None = None) -> str:
     """Hash of the source the moment step under `launch` is compiled from (the
     single-step kernel by default): the kernel file up to the first kernel
     after the moment step, plus the multi-step kernels for a multi-step shape,
-    plus the launchers (edits elsewhere in the file change neither)."""
+    plus the launchers (edits elsewhere in the file change neither); the
+    marching strips live in kpm_march.h, kpm_march_long.hip and
+    kpm_march32.hip."""
     with open(KERNEL_SRC) as f:
         t = f.read()
     with open(DEVICE_SRC) as f:          # the helpers every kernel file shares
@@ -126,8 +130,9 @@ def kernel_sha(launch: dict | None = None) -> str:
         c = t.index("template <typename V>\nbool launch_moment_multi(")
         d = t.index("#define KPM_INSTANTIATE(V)")
         k, tiled = launch["steps"], launch["tiled"]
+        strips = _read(MARCH_H) + _read(MARCH_LONG_SRC) + _read(MARCH32_SRC)
         body = (t[lds:reg] if (k == 2 and tiled == 0) else
-                t[reg:end] + _read(MARCH32_SRC) if tiled >= 3 else t[reg:march])
+                t[reg:end] + strips if tiled >= 3 else t[reg:march])
         return hashlib.sha256((head + body + t[c:d]).encode()).hexdigest()[:16]
     a = t.index("template <typename V, int ILP, bool NT, bool DBL>\nstatic void launch_step_shape(")
     b = t.index("template <typename V>\nvoid launch_evolve_step(")

@@ -10,7 +10,7 @@ from paper_1307_0288_amd import build as bld
 MAX_SPILL = 8          # VGPRs spilled by any strip kernel
 
 
-@pytest.mark.parametrize("src", ["kpm_kernels.hip", "kpm_march32.hip"])
+@pytest.mark.parametrize("src", ["kpm_kernels.hip", "kpm_march32.hip", "kpm_march_long.hip"])
 def test_strip_kernels_keep_their_registers(src):
     res = bld.resources(src)
     if not res:
