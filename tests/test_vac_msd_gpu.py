@@ -45,6 +45,25 @@ def test_joint_loops_equal_separate_calls_and_oracle(precision, geometry, nx, ny
     sysg.close()
 
 
+def test_joint_loops_float_onsite_and_long_tail():
+    """The ten-step two-plane passes with 4-byte on-site terms (the float-exact
+    draw), on a sheet whose chains end in a partial strip and whose moment
+    count leaves a tail of nine steps in the last ring segment."""
+    _need_gpu()
+    c = recipe("sheet", 150, 30, w=1.0, vac=0.02, seed=71, onsite="f32")
+    sysg = gpu_system(c)
+    phi = phases(c, 1, 7100)
+    d = sysg.upload(phi)
+    args = (2, 0.5, 20, 101)             # 99 recursion steps: 9 ten-step passes and one of 9
+    v2, m2 = kp.kpm_vac_msd(sysg, d, *args)
+    v1, m1 = kp.kpm_vac(sysg, d, *args), kp.kpm_msd(sysg, d, *args)
+    assert rel_err(v2, v1) < 1e-12 and rel_err(m2, m1) < 1e-12
+    lat = oracle_lattice(c)
+    assert rel_err(v2[0], oracle.vac(lat, c["e_scale"], phi[:, 0], *args)) < 1e-10
+    assert rel_err(m2[0], oracle.msd(lat, c["e_scale"], phi[:, 0], *args)) < 1e-10
+    sysg.close()
+
+
 @pytest.mark.parametrize("case", ["two_vectors", "single_steps", "batch"])
 def test_other_shapes_run_the_loops_in_turn(case):
     _need_gpu()
