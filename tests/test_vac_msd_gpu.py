@@ -23,8 +23,11 @@ def _need_gpu():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_arith"])
-@pytest.mark.parametrize("geometry,nx,ny", [("sheet", 200, 38), ("zgnr", 130, 38)])
+@pytest.mark.parametrize("geometry,nx,ny", [("sheet", 200, 38), ("zgnr", 130, 38),
+                                             ("sheet", 68, 24)])
 def test_joint_loops_equal_separate_calls_and_oracle(precision, geometry, nx, ny):
+    """(68 x 24: the smallest lattice the strips take, whose ten-step windows
+    of up to 44 chains wrap around the 24 chains of the periodic sheet.)"""
     _need_gpu()
     c = recipe(geometry, nx, ny, w=1.0, vac=0.02, seed=nx + ny)
     sysg = gpu_system(c, precision)
