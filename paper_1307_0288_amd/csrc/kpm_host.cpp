@@ -1002,7 +1002,19 @@ kpm_status run_moments(kpm_system *sys, int vshift, const V *phil, const V *phir
                        V *a_buf, V *b_buf, int64_t stride_r, int64_t offset, bool dbl = false,
                        bool re = false, const kpm_launch *planes = nullptr) {
     // planes: run the 2^vshift vectors as vector-major planes under this shape
-    const kpm_launch &l = planes ? *planes : sys->shape(vshift, dbl);
+    const kpm_launch *lp = planes ? planes : &sys->shape(vshift, dbl);
+    // real parts of FP64 states in vector-major planes: the eight-step strips
+    // take ten steps per pass (in groups of at least kBlock threads, whose LDS
+    // holds the ten-step pass's per-thread sums with two groups per CU)
+    kpm_launch lre;
+    if (re && !dbl && std::is_same<V, double2>::value && vshift > 0 &&
+        lp->vectors_per_wave == 1 && lp->tiled >= 3 && lp->steps == kpm::kMaxMarchSteps &&
+        (lp->group_size == 0 || lp->group_size >= kpm::kBlock)) {
+        lre = *lp;
+        lre.steps = kpm::kReMarchSteps;
+        lp = &lre;
+    }
+    const kpm_launch &l = *lp;
     kpm::Sweep sw;
     KPM_TRY(planes ? sys->sweep_planes(vshift, l, &sw) : sys->sweep_for(vshift, l, &sw));
     const int k = sys->multi_steps(sw.vshift, l);
