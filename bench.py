@@ -167,7 +167,7 @@ def main():
     ap.add_argument("--label-vectors", type=int, default=16,
                     help="learned workload: random-phase vectors per sample (the labels' "
                          "stochastic error falls as one over the square root of this)")
-    ap.add_argument("--graph-steps", type=int, default=3,
+    ap.add_argument("--graph-steps", type=int, default=5,
                     help="paper workload: further steps with every moment set replayed from a "
                          "captured hipGraph, reported as their median step time (0 skips them)")
     ap.add_argument("--onsite", default="f64", choices=["f64", "f32"],
