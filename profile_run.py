@@ -81,6 +81,18 @@ def joint_shape(launch: dict, cus: int, fp64: bool = True) -> dict:
     return dict(shape, vectors_per_wave=1, plane_groups=max(8, waves // 4 // 2 // 8 * 8))
 
 
+def re_launch(launch: dict, precision: str, n_vec: int) -> dict:
+    """The shape the library's real-part moment sets (VAC, MSD) of n_vec
+    vectors kept vector-major actually run under `launch`: with FP64 states the
+    eight-step strips take ten steps per pass (in groups of 256 threads or
+    more); the FP32 forms keep eight."""
+    if (n_vec > 1 and precision == "fp64" and launch.get("steps") == 8
+            and launch.get("tiled", 0) >= 3 and launch.get("vectors_per_wave", 0) == 1
+            and launch.get("group_size", 0) in (0, 256, 512)):
+        return dict(launch, steps=10)
+    return launch
+
+
 def moment_kernel_name(v: str, launch: dict, dbl: bool, n_vec: int = 1,
                        real: bool = False, onsf: bool = True, arith32: bool = False) -> str:
     """Instantiation of the moment step for a graphene system from the builder
@@ -392,7 +404,8 @@ def main():
                                  args.precision == "fp64")
             kname = moment_kernel_name(v, launch, False, 2, True, onsf)
         else:
-            kname = moment_kernel_name(v, launch, args.doubled, args.n_vec, args.real, onsf,
+            kl = re_launch(launch, args.precision, args.n_vec) if args.real else launch
+            kname = moment_kernel_name(v, kl, args.doubled, args.n_vec, args.real, onsf,
                                        args.precision == "fp32_arith")
         meta = {
             "kernel": f"{kname} ({args.precision}, {2 if args.joint else args.n_vec} vector(s))",

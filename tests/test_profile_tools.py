@@ -94,3 +94,16 @@ def test_joint_shape():
     assert pr.joint_shape(dict(STRIPS, steps=6), 256)["steps"] == 6
     assert pr.moment_kernel_name("double2", j, False, 2, real=True, onsf=False) == \
         "k_moment_march_re<double2,false,10>"
+
+
+def test_real_part_sets_of_several_vectors():
+    """Real-part sets of several vectors kept vector-major run ten steps per
+    pass with FP64 states, eight in the FP32 forms."""
+    planar = dict(STRIPS, vectors_per_wave=1, plane_groups=16)
+    assert pr.re_launch(planar, "fp64", 64)["steps"] == 10
+    assert pr.re_launch(planar, "fp32_arith", 64)["steps"] == 8
+    assert pr.re_launch(planar, "fp32", 64)["steps"] == 8
+    assert pr.re_launch(planar, "fp64", 1)["steps"] == 8
+    assert pr.re_launch(dict(planar, group_size=64), "fp64", 64)["steps"] == 8
+    assert pr.moment_kernel_name("double2", pr.re_launch(planar, "fp64", 64), False, 64,
+                                 real=True, onsf=False) == "k_moment_march_re<double2,false,10>"
