@@ -217,10 +217,10 @@ def main():
     log(f"autotuned launch shape: {launch}")
 
     def step():
-        kp.kpm_moments(sysg, phi, phi, nm)
-        # the VAC and MSD loops together: their moment sets at each time step
-        # run as two vector planes of one launch sequence
-        kp.kpm_vac_msd(sysg, phi, ns, dt, nb, nm)
+        # DOS, VAC and MSD in one call: the DOS set beside the VAC set of t_0,
+        # the VAC and MSD sets of each later time step together, every set as
+        # two vector planes of one launch sequence
+        kp.kpm_dos_vac_msd(sysg, phi, ns, dt, nb, nm)
 
     for w in range(args.warmup):
         step()
@@ -238,11 +238,11 @@ def main():
     kp.kpm_set_timing(sysg, False)
 
     value = st["site_updates"] / elapsed / 1e9
-    # the dominant kernel: the VAC and MSD moment sets of every time step after
-    # the first run as two vector planes of one launch sequence (the library's
-    # joint VAC / MSD call), with half the one-vector grid per plane; they are
-    # the widest launches of the step, timed on their own (HIP events around
-    # their runs); the DOS set and the first VAC set are one-plane launches
+    # the dominant kernel: the moment sets run as two vector planes of one
+    # launch sequence (the DOS set with the VAC set of t_0, the VAC and MSD
+    # sets of each later time step), with half the one-vector grid per plane;
+    # they are the widest launches of the step, timed on their own (HIP
+    # events around their runs)
     wide = st["wide_rows"] == st["step_rows"] and st["wide_launches"] > 0
     launch_ms = (st["wide_ms"] / st["wide_launches"] if wide
                  else st["step_ms"] / max(st["step_launches"], 1))
@@ -877,8 +877,7 @@ def batched(args):
     kp.kpm_reset_stats(sysg)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    kp.kpm_moments(sysg, phi1, phi1, nm)
-    kp.kpm_vac_msd(sysg, phi1, ns, dt, nb, nm)
+    kp.kpm_dos_vac_msd(sysg, phi1, ns, dt, nb, nm)
     torch.cuda.synchronize()
     plain = kp.kpm_get_stats(sysg)["site_updates"] / (time.perf_counter() - t0) / 1e9
     sysg.close()

@@ -276,6 +276,22 @@ kpm_status kpm_vac_msd(kpm_system *sys, int n_vec, const void *phi, int n_steps,
                        int n_bessel, int n_moments, double *vac_out, double *msd_out);
 
 /*
+ * The whole Kubo-Greenwood hot path of one set of random vectors in one call
+ * (Alg. 1 with Alg. 2, 3 and 5): dos_out[r][m] = <phi_r|T_m(H~)|phi_r> (real,
+ * H~ Hermitian; the real parts of kpm_moments(phi, phi)), and vac_out and
+ * msd_out as kpm_vac_msd gives them.  Where kpm_vac_msd runs its loops jointly,
+ * the DOS set runs as the second vector plane of the VAC set of t_0 (whose
+ * MSD set is zero), so every moment set of the call is a two-plane launch
+ * sequence; otherwise the DOS set runs first, on its own.  phi: device states
+ * (unchanged).  Host outputs [n_vec][n_moments] and [n_vec][n_steps+1]
+ * [n_moments] (a leading sample axis for a batch).  KPM_ERR_INVALID for a
+ * null output.  Synchronises the stream.
+ */
+kpm_status kpm_dos_vac_msd(kpm_system *sys, int n_vec, const void *phi, int n_steps,
+                           double dt_fs, int n_bessel, int n_moments, double *dos_out,
+                           double *vac_out, double *msd_out);
+
+/*
  * kpm_msd with the moments of each [X, U(t_k)] phi taken in the doubling form
  * of kpm_moments_doubled (the bra and ket of Eq. 44 are the same state).  Same
  * arguments and output.

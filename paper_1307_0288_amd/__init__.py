@@ -14,7 +14,8 @@ from .kpm import (ABI_SYMBOLS, HBAR_EV_FS, BOND_NM, KpmError, System, graphene_b
                   kpm_ftm_sum, kpm_default_launch, kpm_get_launch, kpm_get_launch_doubled, kpm_set_launch_doubled,
                   kpm_get_stats, kpm_kpm_sum, kpm_set_graphs, kpm_set_launch,
                   kpm_moments, kpm_moments_doubled, kpm_moments_noalloc, kpm_msd, kpm_reset_stats, kpm_set_timing, kpm_sigma_e1,
-                  kpm_sigma_e2, kpm_sigma_gk, kpm_vac, kpm_vac_msd, kpm_length, kpm_conductance,
+                  kpm_sigma_e2, kpm_sigma_gk, kpm_vac, kpm_vac_msd, kpm_dos_vac_msd, kpm_length,
+                  kpm_conductance,
                   kpm_ballistic_conductance, kpm_sigma_sc_max, kpm_sigma_sc_average,
                   kpm_pade_fit, kpm_pade_eval, kpm_typical_conductance, kpm_msd_doubled,
                   MLP, kpm_learned_features, kpm_learned_targets, kpm_xu_state,
@@ -26,7 +27,8 @@ __all__ = ["ABI_SYMBOLS", "HBAR_EV_FS", "BOND_NM", "KpmError", "System", "graphe
            "kpm_default_launch", "kpm_get_launch", "kpm_get_launch_doubled", "kpm_set_launch_doubled", "kpm_set_launch",
            "kpm_set_graphs", "kpm_evolve_x", "kpm_get_stats",
            "kpm_kpm_sum", "kpm_moments", "kpm_moments_doubled", "kpm_moments_noalloc", "kpm_msd", "kpm_reset_stats", "kpm_set_timing",
-           "kpm_sigma_e1", "kpm_sigma_e2", "kpm_sigma_gk", "kpm_vac", "kpm_vac_msd", "kpm_length",
+           "kpm_sigma_e1", "kpm_sigma_e2", "kpm_sigma_gk", "kpm_vac", "kpm_vac_msd",
+           "kpm_dos_vac_msd", "kpm_length",
            "kpm_conductance", "kpm_ballistic_conductance", "kpm_sigma_sc_max",
            "kpm_sigma_sc_average", "kpm_pade_fit", "kpm_pade_eval", "kpm_typical_conductance",
            "kpm_msd_doubled", "MLP", "kpm_learned_features", "kpm_learned_targets",

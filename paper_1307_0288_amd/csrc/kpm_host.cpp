@@ -1449,14 +1449,25 @@ kpm_status msd_impl(kpm_system *sys, int vshift, const void *phi, int nsteps, do
 // is about twice as long and half as many launches run).  The recursion states
 // are those of vac_run and msd_run, the moments theirs up to the order of the
 // inner-product sums.  One vector on a one-sample lattice whose moment sets take
-// the marching strips; otherwise the two loops run one after the other.
+// the marching strips; otherwise the two loops run one after the other.  With
+// dos_out the DOS moments <phi|T_m|phi> (real: H~ is Hermitian) come along: in
+// the joint form they are the second plane of the t_0 set, beside the VAC set
+// of t_0 (whose MSD set is zero), so every moment set of the call runs on two
+// planes; otherwise they are the real parts of kpm_moments.
 template <typename V>
 kpm_status vac_msd_impl(kpm_system *sys, int vshift, const void *phi, int nsteps, double dt,
-                        int np, int nm, double *vac_out, double *msd_out) {
+                        int np, int nm, double *vac_out, double *msd_out,
+                        double *dos_out = nullptr) {
     const kpm_launch &l0 = sys->launch[0];
     const bool joint = vshift == 0 && sys->nseg == 1 && sys->d_flags && l0.tiled >= 3 &&
                        sys->multi_steps(0, l0) > 1;
     if (!joint) {
+        if (dos_out) {
+            const size_t nmu = (size_t)sys->nseg * ((size_t)1 << vshift) * nm;
+            std::vector<double> mu(2 * nmu);
+            KPM_TRY(moments_impl<V>(sys, vshift, phi, phi, nm, mu.data(), false));
+            for (size_t q = 0; q < nmu; ++q) dos_out[q] = mu[2 * q];
+        }
         KPM_TRY(vac_impl<V>(sys, vshift, phi, nsteps, dt, np, nm, vac_out));
         return msd_impl<V>(sys, vshift, phi, nsteps, dt, np, nm, msd_out, false);
     }
@@ -1494,9 +1505,18 @@ kpm_status vac_msd_impl(kpm_system *sys, int vshift, const void *phi, int nsteps
     const kpm::Coef alpha = sys->alpha();
     KPM_HIP(hipMemcpyAsync(psi, phi, sb, hipMemcpyDeviceToDevice, s));
     KPM_HIP(hipMemcpyAsync(ps, phi, sb, hipMemcpyDeviceToDevice, s));
-    // t_0: R_0 = L_0 = V phi, the VAC set alone (Y_0 = 0)
+    // t_0: R_0 = L_0 = V phi, the VAC set alone (Y_0 = 0), or beside the DOS set
+    // of phi, whose moments fill the MSD set's slots of t_0 until read out
     kpm::launch_apply_d<V>(h, sw0, psi, rr, alpha, s);
-    KPM_TRY(run_moments<V>(sys, 0, rr, rr, nm, ma, mb, per, 0, false, true));
+    if (dos_out) {
+        KPM_HIP(hipMemcpyAsync(pl, rr, sb, hipMemcpyDeviceToDevice, s));
+        KPM_HIP(hipMemcpyAsync(pr, rr, sb, hipMemcpyDeviceToDevice, s));
+        KPM_HIP(hipMemcpyAsync(pl1, phi, sb, hipMemcpyDeviceToDevice, s));
+        KPM_HIP(hipMemcpyAsync(pr1, phi, sb, hipMemcpyDeviceToDevice, s));
+        KPM_TRY(run_moments<V>(sys, 1, pl, pr, nm, ma, mb, per, 0, false, true, &l2));
+    } else {
+        KPM_TRY(run_moments<V>(sys, 0, rr, rr, nm, ma, mb, per, 0, false, true));
+    }
     for (int k = 1; k <= nsteps; ++k) {
         // VAC: psi_k = U(-dt) psi_{k-1}, R_k = U(-dt) R_{k-1}, L_k = V psi_k
         KPM_TRY(run_evolve<V>(sys, 0, psi, psi2, nullptr, dt, -1, np, a, b));
@@ -1524,6 +1544,11 @@ kpm_status vac_msd_impl(kpm_system *sys, int vshift, const void *phi, int nsteps
         vac_out[q] = host[q].x;
         msd_out[q] = host[per + q].x;
     }
+    if (dos_out)
+        for (int m = 0; m < nm; ++m) {
+            dos_out[m] = msd_out[m];
+            msd_out[m] = 0.0;                          // [X, U(0)] = 0
+        }
     return KPM_OK;
 }
 
@@ -2211,6 +2236,20 @@ kpm_status kpm_vac_msd(kpm_system *sys, int n_vec, const void *phi, int n_steps,
                                        msd_out)
                : vac_msd_impl<float2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, vac_out,
                                       msd_out);
+}
+
+kpm_status kpm_dos_vac_msd(kpm_system *sys, int n_vec, const void *phi, int n_steps,
+                           double dt_fs, int n_bessel, int n_moments, double *dos_out,
+                           double *vac_out, double *msd_out) {
+    int vs;
+    KPM_TRY(check_loop(sys, n_vec, phi, n_steps, dt_fs, n_bessel, n_moments, vac_out, &vs));
+    if (!msd_out || !dos_out) return fail(KPM_ERR_INVALID, "null buffer");
+    DeviceGuard g(sys->device);
+    return sys->prec == KPM_FP64
+               ? vac_msd_impl<double2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, vac_out,
+                                       msd_out, dos_out)
+               : vac_msd_impl<float2>(sys, vs, phi, n_steps, dt_fs, n_bessel, n_moments, vac_out,
+                                      msd_out, dos_out);
 }
 
 kpm_status kpm_msd_doubled(kpm_system *sys, int n_vec, const void *phi, int n_steps,

@@ -31,7 +31,8 @@ ABI_SYMBOLS = ("kpm_build_graphene", "kpm_validate", "kpm_system_create", "kpm_s
                "kpm_system_set_stream", "kpm_system_n_sites", "kpm_batch_create",
                "kpm_system_n_samples", "kpm_system_offsets", "kpm_moments",
                "kpm_moments_noalloc", "kpm_moments_doubled", "kpm_evolve", "kpm_evolve_x", "kpm_vac", "kpm_msd",
-               "kpm_msd_doubled", "kpm_vac_msd", "kpm_fourier_moments", "kpm_ftm_sum",
+               "kpm_msd_doubled", "kpm_vac_msd", "kpm_dos_vac_msd", "kpm_fourier_moments",
+               "kpm_ftm_sum",
                "kpm_kpm_sum", "kpm_sigma_gk",
                "kpm_sigma_e1", "kpm_sigma_e2", "kpm_length", "kpm_conductance",
                "kpm_ballistic_conductance", "kpm_sigma_sc_max", "kpm_sigma_sc_average",
@@ -113,6 +114,7 @@ def _signatures():
         "kpm_msd": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, C.c_int, dp],
         "kpm_msd_doubled": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, C.c_int, dp],
         "kpm_vac_msd": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, C.c_int, dp, dp],
+        "kpm_dos_vac_msd": [vp, C.c_int, vp, C.c_int, C.c_double, C.c_int, C.c_int, dp, dp, dp],
         "kpm_kpm_sum": [C.c_int, C.c_int, dp, C.c_int, dp, C.c_double, C.c_double,
                         C.c_int, vp, dp],
         "kpm_fourier_moments": [vp, C.c_int, vp, vp, C.c_int, C.c_double, C.c_int, dp],
@@ -577,6 +579,21 @@ def kpm_vac_msd(sys: System, phi, n_steps: int, dt_fs: float, n_bessel: int, n_m
     _check(lib().kpm_vac_msd(sys.handle, nv, p, n_steps, dt_fs, n_bessel, n_moments, _dp(vac),
                              _dp(msd)))
     return sys._shape(vac), sys._shape(msd)
+
+
+def kpm_dos_vac_msd(sys: System, phi, n_steps: int, dt_fs: float, n_bessel: int,
+                    n_moments: int):
+    """(DOS, VAC, MSD) moments of one call: the DOS moments <phi|T_m|phi> (real)
+    [n_vec, n_moments] and kpm_vac_msd's two arrays; leading sample axis for a
+    batch."""
+    p, nv = sys._state(phi, "phi")
+    dos = np.empty((sys.n_samples, nv, n_moments))
+    vac = np.empty((sys.n_samples, nv, n_steps + 1, n_moments))
+    msd = np.empty_like(vac)
+    sys._sync_stream()
+    _check(lib().kpm_dos_vac_msd(sys.handle, nv, p, n_steps, dt_fs, n_bessel, n_moments,
+                                 _dp(dos), _dp(vac), _dp(msd)))
+    return sys._shape(dos), sys._shape(vac), sys._shape(msd)
 
 
 def kpm_vac(sys: System, phi, n_steps: int, dt_fs: float, n_bessel: int, n_moments: int):

@@ -131,6 +131,22 @@ def test_joint_vac_msd_all_time_points(paper):
     assert rel_err(gm[0], gold["msd"]) < 1e-10
 
 
+def test_dos_vac_msd_all_moments(paper):
+    """kpm_dos_vac_msd (the DOS set as the second plane of the VAC set of t_0,
+    every set a two-plane launch sequence) against the stored oracle values:
+    all 3000 DOS moments and the 21 x 3000 VAC and MSD moments."""
+    p, act, phi, gold, sysg, d = paper
+    _log("paper-scale DOS, VAC and MSD in one call")
+    gd, gv, gm = kp.kpm_dos_vac_msd(sysg, d, p["n_steps"], p["dt_fs"], p["n_bessel"],
+                                    p["n_moments"])
+    n_act = float(np.count_nonzero(act))
+    assert abs(gd[0][0] - n_act) < 1e-6
+    assert rel_err(gd[0], gold["dos"].real, n_act) < 1e-10
+    assert rel_err(gv[0], gold["vac"]) < 1e-10
+    assert rel_err(gm[0], gold["msd"]) < 1e-10
+    assert np.all(gm[0][0] == 0)
+
+
 def test_msd_doubled_all_time_points(paper):
     p, act, phi, gold, sysg, d = paper
     _log("paper-scale MSD, doubling form")

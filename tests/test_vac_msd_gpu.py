@@ -48,6 +48,42 @@ def test_joint_loops_equal_separate_calls_and_oracle(precision, geometry, nx, ny
     sysg.close()
 
 
+@pytest.mark.parametrize("case", ["joint", "two_vectors", "batch"])
+def test_dos_vac_msd(case):
+    """kpm_dos_vac_msd: the DOS moments <phi|T_m|phi> (real parts of
+    kpm_moments) with kpm_vac_msd's VAC and MSD, in the joint form (DOS beside
+    the VAC set of t_0) and where the sets run one after the other."""
+    _need_gpu()
+    args = (2, 0.5, 20, 93)
+    if case == "batch":
+        import kpm_inputs as ki
+        cases = [recipe("sheet", 96, 30, w=1.0, vac=0.02, seed=80),
+                 recipe("zgnr", 100, 26, w=0.5, seed=81)]
+        sysg = kp.graphene_batch([dict(nx=c["nx"], ny=c["ny"], geometry=c["geometry"],
+                                       onsite=c["onsite"], active=c["active"],
+                                       e_scale=c["e_scale"]) for c in cases], "fp64")
+        phi = np.concatenate([ki.random_phase(c["nx"] * c["ny"], 1, 3100 + 100 * s, c["active"])
+                              for s, c in enumerate(cases)])
+    else:
+        c = recipe("sheet", 200, 38, w=1.0, vac=0.02, seed=82)
+        sysg = gpu_system(c)
+        phi = phases(c, 2 if case == "two_vectors" else 1, 8200)
+    d = sysg.upload(phi)
+    dos, vac, msd = kp.kpm_dos_vac_msd(sysg, d, *args)
+    v2, m2 = kp.kpm_vac_msd(sysg, d, *args)
+    mu = kp.kpm_moments(sysg, d, d, args[-1])
+    assert dos.shape == mu.shape and vac.shape == v2.shape
+    assert rel_err(vac, v2) < 1e-12 and rel_err(msd, m2) < 1e-12
+    assert rel_err(dos, mu.real) < 1e-12
+    assert np.array_equal(d.cpu().numpy(), phi.astype(d.cpu().numpy().dtype))
+    if case == "joint":
+        lat = oracle_lattice(c)
+        ref = oracle.moments(lat, c["e_scale"], phi[:, 0], phi[:, 0], args[-1])
+        assert rel_err(dos[0], ref.real, np.vdot(phi, phi).real) < 1e-10
+        assert np.all(msd[0, 0] == 0)
+    sysg.close()
+
+
 def test_joint_loops_float_onsite_and_long_tail():
     """The ten-step two-plane passes with 4-byte on-site terms (the float-exact
     draw), on a sheet whose chains end in a partial strip and whose moment
